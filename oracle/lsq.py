@@ -1,0 +1,100 @@
+"""Core re-estimation by randomized least squares (oracle, test infrastructure).
+
+Sec. 5 rewrites eq. (1) as u~(y) = sum_j alpha_j w_j(y) with w_j = prod_k w^(k)_{j_k} and
+R = r1 r2 r3, and re-estimates the core from the original scattered data by the regression
+eq. (6): alpha^ = argmin ||u - W alpha||^2, W[q, j] = w_j(y^q).  Algorithm 2 solves it on a
+sketch: rows of W and u are sign-flipped (D), mixed (FFT) and S > R of them are sampled
+uniformly, and step 5 solves the sampled problem exactly.
+
+Readings taken here:
+* the core is vectorised in C order, j = (j1 r2 + j2) r3 + j3;
+* the hot path samples M rows of W directly (no mixing).  D alone changes nothing, since
+  (DW)^T (DW) = W^T W; the mixed variant is a separate, later row;
+* step 5 is read as min_alpha ||S W alpha - S u||^2 (the printed formula drops alpha) and is
+  solved through the normal equations G alpha = h, G = A^T A, h = A^T v, by a Cholesky
+  factorisation; numpy's lstsq (SVD based) serves as an independent truth check.
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.linalg
+
+from .basis import legendre_orthonormal, to_reference
+from .model import Model
+from .sampler import STREAM_LS, sample_without_replacement
+
+
+def factor_values(model: Model, pts: np.ndarray):
+    """[U_k (m, r_k)]: U_k[q, j] = w^(k)_j(y^q_k) = sum_i C_k[i, j] phi_i(xi^q_k)  (eq. (2))."""
+    pts = np.asarray(pts, dtype=np.float64)
+    out = []
+    for k in range(3):
+        xi = to_reference(pts[:, k], model.lo[k], model.hi[k])
+        out.append(legendre_orthonormal(xi, model.degree[k]) @ model.coefs[k])
+    return out
+
+
+def design_rows(U) -> np.ndarray:
+    """A[q, (j1 r2 + j2) r3 + j3] = U1[q, j1] U2[q, j2] U3[q, j3]  (rows of W in eq. (6))."""
+    U1, U2, U3 = U
+    m = U1.shape[0]
+    return np.einsum("qa,qb,qc->qabc", U1, U2, U3).reshape(m, -1)
+
+
+def normal_equations(model: Model, pts: np.ndarray, v: np.ndarray, chunk: int = 4096):
+    """G = A^T A and h = A^T v over the given rows, accumulated over point batches."""
+    R = model.R
+    G = np.zeros((R, R), dtype=np.float64)
+    h = np.zeros(R, dtype=np.float64)
+    v = np.asarray(v, dtype=np.float64)
+    for s in range(0, pts.shape[0], chunk):
+        A = design_rows(factor_values(model, pts[s:s + chunk]))
+        G += A.T @ A
+        h += A.T @ v[s:s + chunk]
+    return G, h
+
+
+def solve_cholesky(G: np.ndarray, h: np.ndarray) -> np.ndarray:
+    """alpha = G^-1 h by Cholesky (LAPACK potrf/potrs through scipy)."""
+    c, low = scipy.linalg.cho_factor(G, lower=True, check_finite=True)
+    return scipy.linalg.cho_solve((c, low), h)
+
+
+def solve_lstsq(A: np.ndarray, v: np.ndarray) -> np.ndarray:
+    """Least-squares solution by numpy's SVD-based lstsq (truth check for the normal equations)."""
+    return np.linalg.lstsq(A, v, rcond=None)[0]
+
+
+def sample_rows(seed: int, n: int, m: int) -> np.ndarray:
+    """The M least-squares rows: uniform, without replacement, sorted (stream 2)."""
+    if not (0 < m <= n):
+        raise ValueError("need 0 < M <= N")
+    return sample_without_replacement(seed, STREAM_LS, n, m)
+
+
+def refit_core(model: Model, pts: np.ndarray, vals: np.ndarray, n_samples: int, seed: int,
+               chunk: int = 4096):
+    """Algorithm 2 with uniform row sampling: returns (alpha (r1, r2, r3), rows, G, h)."""
+    if n_samples <= model.R:
+        raise ValueError("Algorithm 2 needs more sampled rows than core entries (S > R)")
+    idx = sample_rows(seed, pts.shape[0], n_samples)
+    G, h = normal_equations(model, pts[idx], np.asarray(vals, np.float64)[idx], chunk)
+    alpha = solve_cholesky(G, h)
+    return alpha.reshape(model.rank), idx, G, h
+
+
+def residual_normal(model: Model, pts: np.ndarray, v: np.ndarray, alpha: np.ndarray,
+                    chunk: int = 4096) -> np.ndarray:
+    """A^T (v - A alpha): the normal-equations residual used by iterative refinement."""
+    r = np.zeros(model.R, dtype=np.float64)
+    a = np.asarray(alpha, np.float64).reshape(-1)
+    for s in range(0, pts.shape[0], chunk):
+        A = design_rows(factor_values(model, pts[s:s + chunk]))
+        r += A.T @ (np.asarray(v[s:s + chunk], np.float64) - A @ a)
+    return r
+
+
+def leverage_scores(A: np.ndarray) -> np.ndarray:
+    """Squared row norms of the thin left singular factor of A (Sec. 5)."""
+    U, _, _ = np.linalg.svd(A, full_matrices=False)
+    return (U * U).sum(axis=1)

@@ -1,0 +1,61 @@
+"""Evaluation of the functional sparse Tucker model (oracle, test infrastructure).
+
+Sec. 6: reconstruction needs only the evaluation of the basis functions at the points of
+interest, followed by eq. (1).  Two independent forms are provided so that each pins the
+other: the Tucker form of eq. (1) and the full tensor-product expansion of Sec. 2 with
+beta = alpha x_1 C_1 x_2 C_2 x_3 C_3.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from .basis import legendre_orthonormal, to_reference
+from .interp import grid_nodes
+from .lsq import factor_values
+from .model import Model
+from .sthosvd import mode_product
+
+
+def evaluate(model: Model, pts: np.ndarray, chunk: int = 8192) -> np.ndarray:
+    """u~(y^q) = sum_{j1 j2 j3} alpha_{j1 j2 j3} U1[q,j1] U2[q,j2] U3[q,j3]  (eq. (1))."""
+    pts = np.asarray(pts, dtype=np.float64)
+    out = np.empty(pts.shape[0], dtype=np.float64)
+    core = np.asarray(model.core, np.float64)
+    for s in range(0, pts.shape[0], chunk):
+        U1, U2, U3 = factor_values(model, pts[s:s + chunk])
+        out[s:s + chunk] = np.einsum("qa,qb,qc,abc->q", U1, U2, U3, core, optimize=True)
+    return out
+
+
+def full_expansion_coefficients(model: Model) -> np.ndarray:
+    """beta (n1, n2, n3) of the tensor-product expansion equal to the Tucker model."""
+    beta = np.asarray(model.core, np.float64)
+    for k in range(3):
+        beta = mode_product(beta, model.coefs[k], k)
+    return beta
+
+
+def evaluate_full_expansion(model: Model, pts: np.ndarray) -> np.ndarray:
+    """u(y) = sum_{i1 i2 i3} beta_{i1 i2 i3} phi_i1(y1) phi_i2(y2) phi_i3(y3)  (Sec. 2)."""
+    beta = full_expansion_coefficients(model)
+    pts = np.asarray(pts, dtype=np.float64)
+    P = [legendre_orthonormal(to_reference(pts[:, k], model.lo[k], model.hi[k]), model.degree[k])
+         for k in range(3)]
+    return np.einsum("qa,qb,qc,abc->q", P[0], P[1], P[2], beta, optimize=True)
+
+
+def evaluate_on_grid(model: Model, grid) -> np.ndarray:
+    """Reconstruction on an equispaced reference grid by mode products (preview form):
+    alpha x_1 (Phi_1 C_1) x_2 (Phi_2 C_2) x_3 (Phi_3 C_3)."""
+    Y = np.asarray(model.core, np.float64)
+    for k in range(3):
+        F = legendre_orthonormal(grid_nodes(grid[k]), model.degree[k]) @ model.coefs[k]
+        Y = mode_product(Y, F, k)
+    return Y
+
+
+def rel_l2(x, ref) -> float:
+    """||x - ref||_2 / ||ref||_2."""
+    x = np.asarray(x, np.float64).reshape(-1)
+    ref = np.asarray(ref, np.float64).reshape(-1)
+    return float(np.linalg.norm(x - ref) / np.linalg.norm(ref))

@@ -1,0 +1,83 @@
+"""Sparse Legendre fit of each singular vector (oracle, test infrastructure).
+
+Sec. 4.2 represents column j of W^(k), sampled at the grid nodes, as a function
+w_j(y) = sum_i c_i phi_i(y) with few non-zero c_i, found by sparsity-regularised least
+squares (Sec. 3, eq. (3)-(5)) with the regularisation chosen by leave-one-out error.  The
+paper uses Lasso-LARS; this build uses orthogonal matching pursuit, a greedy solver of the
+l0-constrained problem (3), and keeps the leave-one-out model selection:
+
+1. start from the residual r = z and an empty support S;
+2. repeatedly add the column m not in S with the largest normalised correlation
+   |Phi_m^T r| / ||Phi_m|| (lowest m on ties), refit c_S by least squares (Householder QR)
+   and update r = z - Phi_S c_S;
+3. after every step record the leave-one-out (PRESS) error (1/I) sum_i (r_i / (1 - h_ii))^2,
+   where h_ii is the leverage of node i, the i-th diagonal entry of the hat matrix
+   Phi_S (Phi_S^T Phi_S)^-1 Phi_S^T;
+4. stop when |S| reaches min(n, I - 2) or ||r|| <= 1e-14 ||z||;
+5. keep the support size with the smallest PRESS (the smaller size on ties).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from .basis import legendre_orthonormal
+
+
+def ls_qr(Phi: np.ndarray, z: np.ndarray):
+    """Least-squares coefficients by Householder QR, and the thin Q factor."""
+    Q, R = np.linalg.qr(Phi, mode="reduced")
+    c = np.linalg.solve(R, Q.T @ z)  # R is upper triangular and non-singular here
+    return c, Q
+
+
+def omp_loo(Phi: np.ndarray, z: np.ndarray, tol: float = 1e-14):
+    """Returns (support: int array in selection order, coefficients, press list)."""
+    Phi = np.asarray(Phi, dtype=np.float64)
+    z = np.asarray(z, dtype=np.float64)
+    I, n = Phi.shape
+    znorm = np.linalg.norm(z)
+    if znorm == 0.0:
+        return np.zeros(0, dtype=np.int64), np.zeros(0), []
+    colnorm = np.linalg.norm(Phi, axis=0)
+    support = []
+    coefs = []
+    press = []
+    r = z.copy()
+    tmax = min(n, I - 2)
+    for _ in range(tmax):
+        score = np.abs(Phi.T @ r) / colnorm
+        score[support] = -1.0
+        m = int(np.argmax(score))
+        support.append(m)
+        c, Q = ls_qr(Phi[:, support], z)
+        r = z - Phi[:, support] @ c
+        h = (Q * Q).sum(axis=1)
+        with np.errstate(divide="ignore"):
+            loo = r / (1.0 - h)
+        press.append(float(np.mean(loo * loo)))
+        coefs.append(c)
+        if np.linalg.norm(r) <= tol * znorm:
+            break
+    best = int(np.argmin(press))          # first minimum = smaller support on ties
+    return np.asarray(support[: best + 1], dtype=np.int64), coefs[best], press
+
+
+def fit_factor(W: np.ndarray, nodes: np.ndarray, p: int) -> np.ndarray:
+    """Sparse coefficient matrix C (p+1, r) with W[:, j] ~ Phi(nodes) @ C[:, j]."""
+    Phi = legendre_orthonormal(nodes, p)
+    C = np.zeros((p + 1, W.shape[1]), dtype=np.float64)
+    for j in range(W.shape[1]):
+        S, c, _ = omp_loo(Phi, W[:, j])
+        C[S, j] = c
+    return C
+
+
+def press_bruteforce(Phi_S: np.ndarray, z: np.ndarray) -> float:
+    """Leave-one-out error by refitting without each node in turn (for pinning PRESS)."""
+    I = Phi_S.shape[0]
+    errs = np.empty(I)
+    for i in range(I):
+        keep = np.arange(I) != i
+        c, *_ = np.linalg.lstsq(Phi_S[keep], z[keep], rcond=None)
+        errs[i] = z[i] - Phi_S[i] @ c
+    return float(np.mean(errs * errs))
