@@ -1,0 +1,233 @@
+/*
+ * fst.h — C ABI of the MI355X (gfx950) randomized functional sparse Tucker library.
+ *
+ * Method: Rai, Kolla, Cannada, Gorodetsky, "Randomized functional sparse Tucker tensor for
+ * compression and fast visualization of scientific data" (arXiv 1907.05884).
+ *
+ *   model   u~(y) = sum_{j1,j2,j3} alpha_{j1 j2 j3} w1_{j1}(y1) w2_{j2}(y2) w3_{j3}(y3)   eq. (1)
+ *   factors w^(k)_j(y) = sum_i C_k[i, j] phi_i(xi_k(y)),  few non-zero C_k[i, j]          eq. (2)
+ *   basis   phi_i(t) = sqrt(2i+1) P_i(t), i = 0..p_k (orthonormal Legendre, Sec. 4.2)
+ *   coords  xi_k = 2 (y_k - lo_k) / (hi_k - lo_k) - 1
+ *   core    flattened in C order: j = (j1 r2 + j2) r3 + j3 (the paper only says "reshaped")
+ *   refit   alpha^ = argmin ||v_S - A alpha||^2 over M uniformly sampled rows S, eq. (6) and
+ *           Algorithm 2; A[q, j] = prod_k w^(k)_{j_k}(y^q_k); solved through the normal
+ *           equations G = A^T A, h = A^T v_S with an FP64 Cholesky factorisation.
+ *
+ * Conventions for every call:
+ *  - Return value: FST_OK (0) or a negative status; the message of the last failure on the
+ *    calling thread is returned by fst_last_error().  No C++ exception crosses the ABI.
+ *  - Points are structure-of-arrays: three arrays x, y, z of n coordinates plus n values.
+ *    "device" arrays live in memory of the current HIP device (hipMalloc or torch tensors);
+ *    "host" arrays are ordinary CPU memory.  Every pointer argument says which it is.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).  Calls marked
+ *    "asynchronous" only enqueue work on it; the others synchronise it before returning.
+ *  - The caller owns every buffer it passes.  The library owns fst_model objects (freed by
+ *    fst_model_free) and the small device copy of a model that it uploads on first use.
+ *  - Output is bitwise reproducible for identical inputs on the same device: reductions run
+ *    in a fixed order and use no floating-point atomics.
+ *  - Limits of this version: d = 3, 1 <= r_k <= 32, 0 <= p_k <= 31, n < 2^31 points.
+ */
+#ifndef FST_H
+#define FST_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t fst_status;
+#define FST_OK             0
+#define FST_E_INVAL       (-1)   /* bad argument: shape, range, NaN/Inf input, null pointer */
+#define FST_E_NOMEM       (-2)   /* host or device allocation failed, or workspace too small */
+#define FST_E_DEVICE      (-3)   /* a HIP runtime call or kernel launch failed */
+#define FST_E_NOT_SPD     (-4)   /* Cholesky breakdown: the sampled Gram is not positive definite */
+#define FST_E_UNSUPPORTED (-5)   /* outside the limits of this version */
+#define FST_E_FORMAT      (-6)   /* malformed or truncated serialised model */
+
+/* element type of points, values and evaluation arithmetic */
+#define FST_F64 0
+#define FST_F32 1
+
+/* precision of the Gram contraction A^T A (the Cholesky and its solves are always FP64) */
+#define FST_GRAM_F64  0   /* FP64 rows, FP64 MFMA */
+#define FST_GRAM_F32  1   /* FP32 rows, FP32 MFMA, FP32 partial sums folded into FP64 */
+#define FST_GRAM_BF16 2   /* BF16 rows, BF16 MFMA, FP32 accumulation folded into FP64 */
+#define FST_GRAM_F16  3   /* FP16 rows (scaled), FP16 MFMA, FP32 accumulation folded into FP64 */
+
+/* random streams: state = seed * 256 + stream (SplitMix64) */
+#define FST_STREAM_INTERP 1
+#define FST_STREAM_LS     2
+
+typedef struct fst_model fst_model;   /* opaque; library-owned */
+
+/* Parameters of Algorithm 1 + Algorithm 2.  Set struct_size = sizeof(fst_fit_params). */
+typedef struct {
+  uint32_t struct_size;
+  int32_t  dtype;            /* FST_F64 | FST_F32: type of the point/value arrays */
+  double   lo[3], hi[3];     /* box mapped onto [-1,1]^3 */
+  int32_t  grid[3];          /* I_k: equispaced interpolation grid incl. end points (Sec. 4.1) */
+  int32_t  rank[3];          /* r_k: fixed Tucker ranks, r_k <= I_k and r_k <= r_l r_m */
+  int32_t  degree[3];        /* p_k: Legendre degree per mode, p_k < I_k - 1 */
+  double   interp_fraction;  /* share of the points interpolated onto the grid (paper: ~10%) */
+  int32_t  idw_k;            /* neighbours of the inverse-distance interpolation (8) */
+  double   idw_power;        /* distance power (2) */
+  int64_t  n_samples;        /* M rows of Algorithm 2; r1 r2 r3 < M <= n */
+  uint64_t seed;             /* method randomness (interpolation subset, sampled rows) */
+  int32_t  gram_prec;        /* FST_GRAM_* */
+  int32_t  refine_steps;     /* FP64-residual iterative-refinement steps after the solve */
+  int32_t  n_threads;        /* host threads for the host steps; 0 = all hardware threads */
+} fst_fit_params;
+
+/* ------------------------------------------------------------------ library */
+
+/* Message of the last failed call on this thread ("" if none).  Valid until the next call. */
+const char* fst_last_error(void);
+/* Version string of the library. */
+const char* fst_version(void);
+/* Fills defaults (idw_k 8, power 2, fraction 0.1, grid 32^3, ranks 8^3, degree 15, ...). */
+void fst_fit_params_default(fst_fit_params* p);
+
+/* ------------------------------------------------------------------ whole method */
+
+/* Device workspace (bytes) that fst_fit / fst_refit_core need for n points. */
+size_t fst_fit_workspace_bytes(const fst_fit_params* p, int64_t n);
+
+/* Algorithm 1 then Algorithm 2 (Sec. 4-5).  x, y, z, v: device arrays of n elements of
+ * p->dtype.  Host steps (subset draw, inverse-distance interpolation, ST-HOSVD, sparse
+ * Legendre fit by OMP + leave-one-out) run on host threads; the refit (factor evaluation at
+ * the sampled rows, Gram, Cholesky, solve, refinement) runs on the GPU.  ws: device
+ * workspace of ws_bytes >= fst_fit_workspace_bytes(p, n), or NULL to let the library
+ * allocate and free it.  Synchronises `stream`.  *out receives a new model. */
+fst_status fst_fit(const fst_fit_params* p, int64_t n, const void* x, const void* y,
+                   const void* z, const void* v, void* ws, size_t ws_bytes, void* stream,
+                   fst_model** out);
+
+/* Algorithm 1 only (Sec. 4): host arrays x, y, z, v (p->dtype, n elements).  The model's
+ * core is the ST-HOSVD core of the interpolated grid tensor.  Host only, no GPU use. */
+fst_status fst_compress_host(const fst_fit_params* p, int64_t n, const void* x, const void* y,
+                             const void* z, const void* v, fst_model** out);
+
+/* Device workspace (bytes) of fst_refit_core for a model, point dtype, M and refinement. */
+size_t fst_refit_workspace_bytes(const fst_model* m, int32_t dtype, int64_t n_samples,
+                                 int32_t refine_steps);
+
+/* Algorithm 2 (Sec. 5) for a given model's factor functions: re-estimates the core from
+ * M = n_samples uniformly sampled rows (stream FST_STREAM_LS of `seed`).  x, y, z, v:
+ * device arrays of `dtype`.  ws: device workspace >= fst_refit_workspace_bytes(...), or
+ * NULL to let the library allocate it.  Writes the new core into *out (a new model with
+ * m's factors).  Synchronises `stream`. */
+fst_status fst_refit_core(const fst_model* m, int32_t dtype, int64_t n, const void* x,
+                          const void* y, const void* z, const void* v, int64_t n_samples,
+                          uint64_t seed, int32_t gram_prec, int32_t refine_steps, void* ws,
+                          size_t ws_bytes, void* stream, fst_model** out);
+
+/* Reconstruction at points of interest (eq. (1), Sec. 6): out[i] = u~(x[i], y[i], z[i]).
+ * x, y, z, out: device arrays of n elements of `dtype`.  Asynchronous on `stream`. */
+fst_status fst_eval(const fst_model* m, int32_t dtype, int64_t n, const void* x,
+                    const void* y, const void* z, void* out, void* stream);
+
+/* ------------------------------------------------------------------ per-step GPU calls */
+
+/* Rows of Algorithm 2 step 1 at sampled points, eq. (2): for q < m and i = idx[q] (or i = q
+ * if idx is NULL), U[(o_k + j) * m + q] = w^(k)_j(point i), o_1 = 0, o_2 = r1, o_3 = r1 + r2
+ * (feature-major, points contiguous), and vs[q] = v[i] (vs, v may be NULL).  x, y, z, v, idx,
+ * U, vs: device arrays; idx int32.  Asynchronous. */
+fst_status fst_factor_eval(const fst_model* m, int32_t dtype, int64_t n, const void* x,
+                           const void* y, const void* z, const void* v, const int32_t* idx,
+                           int64_t mrows, void* U, void* vs, void* stream);
+
+/* Normal equations of the sampled problem (Algorithm 2 step 5, eq. (6)):
+ * G = A^T A (lower triangle incl. diagonal written; strictly upper part untouched) and
+ * h = A^T vs, with A[q, j] = U1[q, j1] U2[q, j2] U3[q, j3] formed on the fly from U as
+ * written by fst_factor_eval (never stored).  U, vs: device, `dtype` (FST_F64 needs
+ * gram_prec FST_GRAM_F64; FST_F32 takes F32, BF16 or F16).  G: device FP64 R x R
+ * row-major, h: device FP64 R; either may be NULL to skip that product (not both).  ws: device workspace >= fst_gram_workspace_bytes.
+ * Asynchronous. */
+size_t fst_gram_workspace_bytes(const fst_model* m, int64_t mrows);
+fst_status fst_gram(const fst_model* m, int32_t dtype, int64_t mrows, const void* U,
+                    const void* vs, int32_t gram_prec, double* G, double* h, void* ws,
+                    size_t ws_bytes, void* stream);
+
+/* In-place FP64 Cholesky G = L L^T of a device R x R row-major matrix (lower triangle read,
+ * L written there).  Synchronises `stream`; returns FST_E_NOT_SPD if a pivot is not above
+ * R * 2^-52 times its diagonal entry before the factorisation (numerically rank-deficient
+ * system), with its index in *info (1-based; 0 on success; info may be NULL).
+ * ws: device workspace >= fst_cholesky_workspace_bytes(R). */
+size_t fst_cholesky_workspace_bytes(int64_t R);
+fst_status fst_cholesky(int64_t R, double* G, int64_t* info, void* ws, size_t ws_bytes,
+                        void* stream);
+
+/* Solves L L^T x = b with L from fst_cholesky (device FP64); b and x may alias.
+ * Asynchronous. */
+fst_status fst_cholesky_solve(int64_t R, const double* L, const double* b, double* x,
+                              void* stream);
+
+/* FP64 normal-equations residual r = A^T (v_S - A alpha) at the sampled rows idx (device
+ * int32, mrows), with rows regenerated in FP64 from the points (x, y, z, v: device, dtype).
+ * alpha: device FP64 R; r: device FP64 R.  ws >= fst_residual_workspace_bytes.
+ * Asynchronous. */
+size_t fst_residual_workspace_bytes(const fst_model* m, int64_t mrows);
+fst_status fst_residual(const fst_model* m, int32_t dtype, int64_t n, const void* x,
+                        const void* y, const void* z, const void* v, const int32_t* idx,
+                        int64_t mrows, const double* alpha, double* r, void* ws,
+                        size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------ host steps */
+
+/* M distinct indices of [0, n), sorted ascending, from a partial Fisher-Yates shuffle driven
+ * by SplitMix64 with state seed * 256 + stream.  out: host int64[m].  0 <= m <= n < 2^32. */
+fst_status fst_sample_indices(uint64_t seed, int32_t stream, int64_t n, int64_t m,
+                              int64_t* out);
+
+/* Inverse-distance interpolation onto the equispaced grid of Sec. 4.1: for every node
+ * (C order, last mode fastest) the k nearest points in reference coordinates, weights d^-power;
+ * a node that coincides with a point takes its value.  xi: host FP64 (K, 3) row-major
+ * reference coordinates; v: host FP64 K; out: host FP64 I1*I2*I3.  n_threads 0 = all. */
+fst_status fst_idw_grid(const double* xi, const double* v, int64_t K, const int32_t grid[3],
+                        int32_t k, double power, int32_t n_threads, double* out);
+
+/* ST-HOSVD at fixed ranks (Sec. 4.1): modes in the order 1, 2, 3; each factor's columns are
+ * the leading left singular vectors of the current unfolding, signed so that the entry of
+ * largest magnitude is positive.  T: host FP64 I1 x I2 x I3 (C order); core: host FP64
+ * r1 r2 r3 (C order); W[k]: host FP64 I_k x r_k row-major; sigma[k] (may be NULL): host
+ * FP64 I_k singular values of the unfolding seen at step k (zero-padded). */
+fst_status fst_sthosvd(const double* T, const int32_t dims[3], const int32_t rank[3],
+                       int32_t n_threads, double* core, double* const W[3],
+                       double* const sigma[3]);
+
+/* Sparse Legendre fit of the columns of W (Sec. 4.2): orthogonal matching pursuit with
+ * normalised correlations, support size chosen by the smallest leave-one-out (PRESS) error.
+ * W: host FP64 I x r row-major, sampled at the equispaced nodes; C: host FP64 (p+1) x r
+ * row-major (zeros off the support). */
+fst_status fst_sparse_fit(const double* W, int32_t I, int32_t r, int32_t p, double* C);
+
+/* ------------------------------------------------------------------ model */
+
+/* Builds a model from its parts.  lo, hi: host double[3]; rank, degree: host int32[3];
+ * core: host FP64 r1 r2 r3 (C order); coefs[k]: host FP64 (p_k + 1) x r_k row-major. */
+fst_status fst_model_from_parts(const double lo[3], const double hi[3], const int32_t rank[3],
+                                const int32_t degree[3], const double* core,
+                                const double* const coefs[3], fst_model** out);
+void fst_model_free(fst_model* m);
+/* lo, hi (double[3]), rank, degree (int32[3]), nnz: non-zero coefficients; any may be NULL */
+fst_status fst_model_info(const fst_model* m, double* lo, double* hi, int32_t* rank,
+                          int32_t* degree, int64_t* nnz);
+/* core_out: host FP64 r1 r2 r3 */
+fst_status fst_model_core(const fst_model* m, double* core_out);
+/* C_out: host FP64 (p_k + 1) x r_k row-major, zeros off the support */
+fst_status fst_model_coefs(const fst_model* m, int32_t k, double* C_out);
+/* Storage in the paper's convention (Sec. 2): 8 bytes per stored value, core entries plus
+ * non-zero coefficients, locations not counted. */
+int64_t fst_model_paper_bytes(const fst_model* m);
+/* Versioned little-endian serialisation.  buf == NULL queries the size into *nbytes; else
+ * *nbytes is the capacity on input and the bytes written on output. */
+fst_status fst_model_save(const fst_model* m, void* buf, size_t* nbytes);
+fst_status fst_model_load(const void* buf, size_t nbytes, fst_model** out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FST_H */

@@ -1,0 +1,431 @@
+"""Python binding of libfst (randomized functional sparse Tucker on MI355X / gfx950).
+
+Argument marshalling only: every step runs in the C-ABI library (host C++ for the host
+steps of Algorithm 1, HIP kernels for the GPU path).  Functions carry the names of the C
+entry points declared in include/fst.h.  Device arrays are torch tensors on a ROCm device;
+torch provides memory and the current stream, nothing else.  Host arrays are numpy arrays.
+
+The library must be built first (``python -m paper_1907_05884_amd.build``); importing this
+module without it raises immediately.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libfst.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1907_05884_amd.build`")
+_lib = C.CDLL(LIB_PATH)
+
+FST_OK = 0
+FST_E_INVAL, FST_E_NOMEM, FST_E_DEVICE, FST_E_NOT_SPD, FST_E_UNSUPPORTED, FST_E_FORMAT = -1, -2, -3, -4, -5, -6
+FST_F64, FST_F32 = 0, 1
+FST_GRAM_F64, FST_GRAM_F32, FST_GRAM_BF16, FST_GRAM_F16 = 0, 1, 2, 3
+FST_STREAM_INTERP, FST_STREAM_LS = 1, 2
+
+_STATUS_NAMES = {-1: "FST_E_INVAL", -2: "FST_E_NOMEM", -3: "FST_E_DEVICE", -4: "FST_E_NOT_SPD",
+                 -5: "FST_E_UNSUPPORTED", -6: "FST_E_FORMAT"}
+
+
+class FstError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class fst_fit_params(C.Structure):
+    _fields_ = [("struct_size", C.c_uint32), ("dtype", C.c_int32),
+                ("lo", C.c_double * 3), ("hi", C.c_double * 3),
+                ("grid", C.c_int32 * 3), ("rank", C.c_int32 * 3), ("degree", C.c_int32 * 3),
+                ("interp_fraction", C.c_double), ("idw_k", C.c_int32), ("idw_power", C.c_double),
+                ("n_samples", C.c_int64), ("seed", C.c_uint64), ("gram_prec", C.c_int32),
+                ("refine_steps", C.c_int32), ("n_threads", C.c_int32)]
+
+
+_vp, _i64, _i32, _dp = C.c_void_p, C.c_int64, C.c_int32, C.POINTER(C.c_double)
+
+
+def _proto(name, res, *args):
+    f = getattr(_lib, name)
+    f.restype = res
+    f.argtypes = list(args)
+    return f
+
+
+_P = C.POINTER(fst_fit_params)
+_lib_fns = dict(
+    fst_last_error=(C.c_char_p,),
+    fst_version=(C.c_char_p,),
+    fst_fit_params_default=(None, _P),
+    fst_fit_workspace_bytes=(C.c_size_t, _P, _i64),
+    fst_fit=(_i32, _P, _i64, _vp, _vp, _vp, _vp, _vp, C.c_size_t, _vp, C.POINTER(_vp)),
+    fst_compress_host=(_i32, _P, _i64, _vp, _vp, _vp, _vp, C.POINTER(_vp)),
+    fst_refit_workspace_bytes=(C.c_size_t, _vp, _i32, _i64, _i32),
+    fst_refit_core=(_i32, _vp, _i32, _i64, _vp, _vp, _vp, _vp, _i64, C.c_uint64, _i32, _i32, _vp,
+                    C.c_size_t, _vp, C.POINTER(_vp)),
+    fst_eval=(_i32, _vp, _i32, _i64, _vp, _vp, _vp, _vp, _vp),
+    fst_factor_eval=(_i32, _vp, _i32, _i64, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp),
+    fst_gram_workspace_bytes=(C.c_size_t, _vp, _i64),
+    fst_gram=(_i32, _vp, _i32, _i64, _vp, _vp, _i32, _vp, _vp, _vp, C.c_size_t, _vp),
+    fst_cholesky_workspace_bytes=(C.c_size_t, _i64),
+    fst_cholesky=(_i32, _i64, _vp, C.POINTER(_i64), _vp, C.c_size_t, _vp),
+    fst_cholesky_solve=(_i32, _i64, _vp, _vp, _vp, _vp),
+    fst_residual_workspace_bytes=(C.c_size_t, _vp, _i64),
+    fst_residual=(_i32, _vp, _i32, _i64, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp, C.c_size_t, _vp),
+    fst_sample_indices=(_i32, C.c_uint64, _i32, _i64, _i64, _vp),
+    fst_idw_grid=(_i32, _vp, _vp, _i64, _vp, _i32, C.c_double, _i32, _vp),
+    fst_sthosvd=(_i32, _vp, _vp, _vp, _i32, _vp, _vp, _vp),
+    fst_sparse_fit=(_i32, _vp, _i32, _i32, _i32, _vp),
+    fst_model_from_parts=(_i32, _vp, _vp, _vp, _vp, _vp, _vp, C.POINTER(_vp)),
+    fst_model_free=(None, _vp),
+    fst_model_info=(_i32, _vp, _vp, _vp, _vp, _vp, _vp),
+    fst_model_core=(_i32, _vp, _vp),
+    fst_model_coefs=(_i32, _vp, _i32, _vp),
+    fst_model_paper_bytes=(_i64, _vp),
+    fst_model_save=(_i32, _vp, _vp, C.POINTER(C.c_size_t)),
+    fst_model_load=(_i32, _vp, C.c_size_t, C.POINTER(_vp)),
+)
+_fn = {name: _proto(name, spec[0], *spec[1:]) for name, spec in _lib_fns.items()}
+EXPORTED_SYMBOLS = tuple(_lib_fns)
+
+
+def _check(status: int):
+    if status != FST_OK:
+        raise FstError(status, _fn["fst_last_error"]().decode(errors="replace"))
+
+
+def fst_version() -> str:
+    return _fn["fst_version"]().decode()
+
+
+def fst_last_error() -> str:
+    return _fn["fst_last_error"]().decode(errors="replace")
+
+
+# ------------------------------------------------------------------------------ helpers
+def _host(a, dtype):
+    a = np.ascontiguousarray(a, dtype=dtype)
+    return a, a.ctypes.data_as(C.c_void_p)
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dev_ptr(t):
+    if t is None:
+        return None
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("expected a torch tensor on a GPU device")
+    if not t.is_contiguous():
+        raise ValueError("device arrays must be contiguous")
+    return C.c_void_p(t.data_ptr())
+
+
+def _dtype_code(t) -> int:
+    torch = _torch()
+    if t.dtype == torch.float64:
+        return FST_F64
+    if t.dtype == torch.float32:
+        return FST_F32
+    raise TypeError("points and values must be float32 or float64")
+
+
+def _stream(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _workspace(nbytes: int, device):
+    torch = _torch()
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+def make_params(dtype=FST_F64, lo=(-1.0,) * 3, hi=(1.0,) * 3, grid=(32,) * 3, rank=(8,) * 3,
+                degree=(15,) * 3, interp_fraction=0.10, idw_k=8, idw_power=2.0, n_samples=2000,
+                seed=1, gram_prec=None, refine_steps=0, n_threads=0) -> fst_fit_params:
+    p = fst_fit_params()
+    _fn["fst_fit_params_default"](C.byref(p))
+    p.dtype = dtype
+    for k in range(3):
+        p.lo[k], p.hi[k] = float(lo[k]), float(hi[k])
+        p.grid[k], p.rank[k], p.degree[k] = int(grid[k]), int(rank[k]), int(degree[k])
+    p.interp_fraction = float(interp_fraction)
+    p.idw_k = int(idw_k)
+    p.idw_power = float(idw_power)
+    p.n_samples = int(n_samples)
+    p.seed = int(seed)
+    if gram_prec is None:
+        gram_prec = FST_GRAM_F64 if dtype == FST_F64 else FST_GRAM_F32
+    p.gram_prec = int(gram_prec)
+    p.refine_steps = int(refine_steps)
+    p.n_threads = int(n_threads)
+    return p
+
+
+# ------------------------------------------------------------------------------ model
+class Model:
+    """Owns an fst_model handle."""
+
+    def __init__(self, handle: C.c_void_p):
+        self._h = handle
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h and _fn is not None:
+            _fn["fst_model_free"](h)
+            self._h = None
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self):
+        lo, hi = (C.c_double * 3)(), (C.c_double * 3)()
+        rank, degree = (C.c_int32 * 3)(), (C.c_int32 * 3)()
+        nnz = C.c_int64()
+        _check(_fn["fst_model_info"](self._h, lo, hi, rank, degree, C.byref(nnz)))
+        return dict(lo=tuple(lo), hi=tuple(hi), rank=tuple(rank), degree=tuple(degree), nnz=nnz.value)
+
+    @property
+    def rank(self):
+        return self.info()["rank"]
+
+    @property
+    def degree(self):
+        return self.info()["degree"]
+
+    @property
+    def R(self) -> int:
+        r = self.rank
+        return r[0] * r[1] * r[2]
+
+    @property
+    def core(self) -> np.ndarray:
+        out = np.empty(self.rank, dtype=np.float64)
+        _check(_fn["fst_model_core"](self._h, out.ctypes.data_as(C.c_void_p)))
+        return out
+
+    def coefs(self, k: int) -> np.ndarray:
+        inf = self.info()
+        out = np.empty((inf["degree"][k] + 1, inf["rank"][k]), dtype=np.float64)
+        _check(_fn["fst_model_coefs"](self._h, int(k), out.ctypes.data_as(C.c_void_p)))
+        return out
+
+    def paper_bytes(self) -> int:
+        return int(_fn["fst_model_paper_bytes"](self._h))
+
+
+def fst_model_from_parts(lo, hi, rank, degree, core, coefs) -> Model:
+    lo_a, lo_p = _host(lo, np.float64)
+    hi_a, hi_p = _host(hi, np.float64)
+    r_a, r_p = _host(rank, np.int32)
+    d_a, d_p = _host(degree, np.int32)
+    c_a, c_p = _host(core, np.float64)
+    cs = [np.ascontiguousarray(c, dtype=np.float64) for c in coefs]
+    for k in range(3):
+        if cs[k].shape != (int(degree[k]) + 1, int(rank[k])):
+            raise ValueError("coefficient matrix k must have shape (degree[k] + 1, rank[k])")
+    if c_a.size != int(np.prod(rank)):
+        raise ValueError("core must have r1 r2 r3 entries")
+    arr = (C.c_void_p * 3)(*[c.ctypes.data_as(C.c_void_p) for c in cs])
+    h = C.c_void_p()
+    _check(_fn["fst_model_from_parts"](lo_p, hi_p, r_p, d_p, c_p, arr, C.byref(h)))
+    return Model(h)
+
+
+def fst_model_save(m: Model) -> bytes:
+    n = C.c_size_t(0)
+    _check(_fn["fst_model_save"](m.handle, None, C.byref(n)))
+    buf = (C.c_ubyte * n.value)()
+    _check(_fn["fst_model_save"](m.handle, buf, C.byref(n)))
+    return bytes(buf[: n.value])
+
+
+def fst_model_load(data: bytes) -> Model:
+    buf = (C.c_ubyte * len(data)).from_buffer_copy(data)
+    h = C.c_void_p()
+    _check(_fn["fst_model_load"](buf, len(data), C.byref(h)))
+    return Model(h)
+
+
+# ------------------------------------------------------------------------------ whole method
+def fst_fit_workspace_bytes(p: fst_fit_params, n: int) -> int:
+    b = _fn["fst_fit_workspace_bytes"](C.byref(p), int(n))
+    if b == 0:
+        raise FstError(FST_E_INVAL, fst_last_error())
+    return int(b)
+
+
+def fst_fit(p: fst_fit_params, x, y, z, v, stream=None) -> Model:
+    """Algorithm 1 + Algorithm 2 on device arrays x, y, z, v (torch, same dtype)."""
+    n = x.numel()
+    ws = _workspace(fst_fit_workspace_bytes(p, n), x.device)
+    h = C.c_void_p()
+    _check(_fn["fst_fit"](C.byref(p), n, _dev_ptr(x), _dev_ptr(y), _dev_ptr(z), _dev_ptr(v),
+                          _dev_ptr(ws), ws.numel(), _stream(stream), C.byref(h)))
+    return Model(h)
+
+
+def fst_compress_host(p: fst_fit_params, x, y, z, v) -> Model:
+    """Algorithm 1 on host numpy arrays (dtype given by p.dtype)."""
+    dt = np.float64 if p.dtype == FST_F64 else np.float32
+    xs = [_host(a, dt) for a in (x, y, z, v)]
+    h = C.c_void_p()
+    _check(_fn["fst_compress_host"](C.byref(p), xs[0][0].size, *[t[1] for t in xs], C.byref(h)))
+    return Model(h)
+
+
+def fst_refit_workspace_bytes(m: Model, dtype: int, n_samples: int, refine_steps: int = 0) -> int:
+    b = _fn["fst_refit_workspace_bytes"](m.handle, int(dtype), int(n_samples), int(refine_steps))
+    if b == 0:
+        raise FstError(FST_E_INVAL, fst_last_error())
+    return int(b)
+
+
+def fst_refit_core(m: Model, x, y, z, v, n_samples: int, seed: int, gram_prec=None,
+                   refine_steps: int = 0, ws=None, stream=None) -> Model:
+    """Algorithm 2: re-estimates the core of m from n_samples uniformly sampled rows."""
+    dt = _dtype_code(x)
+    if gram_prec is None:
+        gram_prec = FST_GRAM_F64 if dt == FST_F64 else FST_GRAM_F32
+    n = x.numel()
+    if ws is None:
+        ws = _workspace(fst_refit_workspace_bytes(m, dt, n_samples, refine_steps), x.device)
+    h = C.c_void_p()
+    _check(_fn["fst_refit_core"](m.handle, dt, n, _dev_ptr(x), _dev_ptr(y), _dev_ptr(z), _dev_ptr(v),
+                                 int(n_samples), int(seed), int(gram_prec), int(refine_steps),
+                                 _dev_ptr(ws), ws.numel(), _stream(stream), C.byref(h)))
+    return Model(h)
+
+
+def fst_eval(m: Model, x, y, z, out=None, stream=None):
+    """Reconstruction u~ at device points; returns `out` (allocated if None)."""
+    torch = _torch()
+    if out is None:
+        out = torch.empty_like(x)
+    _check(_fn["fst_eval"](m.handle, _dtype_code(x), x.numel(), _dev_ptr(x), _dev_ptr(y), _dev_ptr(z),
+                           _dev_ptr(out), _stream(stream)))
+    return out
+
+
+# ------------------------------------------------------------------------------ per-step GPU
+def fst_factor_eval(m: Model, x, y, z, v=None, idx=None, mrows=None, U=None, vs=None, stream=None):
+    """Factor values at rows idx (int32 device tensor or None): returns (U [sum r, m], vs)."""
+    torch = _torch()
+    n = x.numel()
+    if mrows is None:
+        mrows = idx.numel() if idx is not None else n
+    sr = sum(m.rank)
+    if U is None:
+        U = torch.empty((sr, mrows), dtype=x.dtype, device=x.device)
+    if vs is None and v is not None:
+        vs = torch.empty(mrows, dtype=x.dtype, device=x.device)
+    _check(_fn["fst_factor_eval"](m.handle, _dtype_code(x), n, _dev_ptr(x), _dev_ptr(y), _dev_ptr(z),
+                                  _dev_ptr(v), _dev_ptr(idx), int(mrows), _dev_ptr(U), _dev_ptr(vs),
+                                  _stream(stream)))
+    return U, vs
+
+
+def fst_gram_workspace_bytes(m: Model, mrows: int) -> int:
+    return int(_fn["fst_gram_workspace_bytes"](m.handle, int(mrows)))
+
+
+def fst_gram(m: Model, U, vs=None, gram_prec=None, G=None, h=None, ws=None, stream=None, want_G=True):
+    """G = A^T A (lower triangle) and h = A^T vs, FP64 device tensors (want_G=False: h only)."""
+    torch = _torch()
+    dt = _dtype_code(U)
+    if gram_prec is None:
+        gram_prec = FST_GRAM_F64 if dt == FST_F64 else FST_GRAM_F32
+    R = m.R
+    mrows = U.shape[1]
+    if G is None and want_G:
+        G = torch.zeros((R, R), dtype=torch.float64, device=U.device)
+    if h is None and vs is not None:
+        h = torch.empty(R, dtype=torch.float64, device=U.device)
+    if ws is None:
+        ws = _workspace(fst_gram_workspace_bytes(m, mrows), U.device)
+    _check(_fn["fst_gram"](m.handle, dt, int(mrows), _dev_ptr(U), _dev_ptr(vs), int(gram_prec),
+                           _dev_ptr(G) if want_G else None, _dev_ptr(h), _dev_ptr(ws), ws.numel(),
+                           _stream(stream)))
+    return G, h
+
+
+def fst_cholesky(G, stream=None) -> int:
+    """In-place FP64 Cholesky of a device (R, R) tensor; raises FstError(FST_E_NOT_SPD)."""
+    R = G.shape[0]
+    ws = _workspace(int(_fn["fst_cholesky_workspace_bytes"](R)), G.device)
+    info = C.c_int64(0)
+    st = _fn["fst_cholesky"](R, _dev_ptr(G), C.byref(info), _dev_ptr(ws), ws.numel(), _stream(stream))
+    if st != FST_OK:
+        raise FstError(st, fst_last_error() + f" (info={info.value})")
+    return info.value
+
+
+def fst_cholesky_solve(L, b, x=None, stream=None):
+    torch = _torch()
+    if x is None:
+        x = torch.empty_like(b)
+    _check(_fn["fst_cholesky_solve"](L.shape[0], _dev_ptr(L), _dev_ptr(b), _dev_ptr(x), _stream(stream)))
+    return x
+
+
+def fst_residual(m: Model, x, y, z, v, idx, alpha, r=None, stream=None):
+    """FP64 A^T (v_S - A alpha) at rows idx, rows regenerated in FP64 from the points."""
+    torch = _torch()
+    mrows = idx.numel()
+    if r is None:
+        r = torch.empty(m.R, dtype=torch.float64, device=x.device)
+    ws = _workspace(int(_fn["fst_residual_workspace_bytes"](m.handle, mrows)), x.device)
+    _check(_fn["fst_residual"](m.handle, _dtype_code(x), x.numel(), _dev_ptr(x), _dev_ptr(y), _dev_ptr(z),
+                               _dev_ptr(v), _dev_ptr(idx), mrows, _dev_ptr(alpha), _dev_ptr(r),
+                               _dev_ptr(ws), ws.numel(), _stream(stream)))
+    return r
+
+
+# ------------------------------------------------------------------------------ host steps
+def fst_sample_indices(seed: int, stream: int, n: int, m: int) -> np.ndarray:
+    out = np.empty(int(m), dtype=np.int64)
+    _check(_fn["fst_sample_indices"](int(seed), int(stream), int(n), int(m), out.ctypes.data_as(C.c_void_p)))
+    return out
+
+
+def fst_idw_grid(xi, v, grid, k=8, power=2.0, n_threads=0) -> np.ndarray:
+    xi_a, xi_p = _host(xi, np.float64)
+    v_a, v_p = _host(v, np.float64)
+    g_a, g_p = _host(grid, np.int32)
+    out = np.empty(tuple(int(g) for g in grid), dtype=np.float64)
+    _check(_fn["fst_idw_grid"](xi_p, v_p, v_a.size, g_p, int(k), float(power), int(n_threads),
+                               out.ctypes.data_as(C.c_void_p)))
+    return out
+
+
+def fst_sthosvd(T, rank, n_threads=0):
+    """Returns (core, [W1, W2, W3], [sigma1, sigma2, sigma3])."""
+    T_a, T_p = _host(T, np.float64)
+    dims = np.asarray(T_a.shape, dtype=np.int32)
+    r_a, r_p = _host(rank, np.int32)
+    core = np.empty(tuple(int(r) for r in rank), dtype=np.float64)
+    W = [np.empty((int(dims[k]), int(rank[k])), dtype=np.float64) for k in range(3)]
+    S = [np.empty(int(dims[k]), dtype=np.float64) for k in range(3)]
+    Wp = (C.c_void_p * 3)(*[w.ctypes.data_as(C.c_void_p) for w in W])
+    Sp = (C.c_void_p * 3)(*[s.ctypes.data_as(C.c_void_p) for s in S])
+    _check(_fn["fst_sthosvd"](T_p, dims.ctypes.data_as(C.c_void_p), r_p, int(n_threads),
+                              core.ctypes.data_as(C.c_void_p), Wp, Sp))
+    return core, W, S
+
+
+def fst_sparse_fit(W, p: int) -> np.ndarray:
+    W_a, W_p = _host(W, np.float64)
+    I, r = W_a.shape
+    out = np.empty((int(p) + 1, r), dtype=np.float64)
+    _check(_fn["fst_sparse_fit"](W_p, int(I), int(r), int(p), out.ctypes.data_as(C.c_void_p)))
+    return out

@@ -1,0 +1,551 @@
+// C ABI entry points: argument validation, error reporting, and the orchestration of
+// Algorithm 1 (host steps) and Algorithm 2 (GPU refit of the core).
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "fst_internal.h"
+
+namespace fst {
+
+static thread_local std::string g_last_error;
+void set_last_error(const std::string& msg) { g_last_error = msg; }
+[[noreturn]] void fail(fst_status code, const std::string& msg) { throw Error(code, msg); }
+
+// Owns a device workspace when the caller passes none.
+struct Workspace {
+  void* p = nullptr;
+  size_t bytes = 0;
+  bool owned = false;
+  Workspace(void* user, size_t user_bytes, size_t need) {
+    if (user) {
+      if (user_bytes < need)
+        fail(FST_E_NOMEM, "workspace too small: " + std::to_string(user_bytes) + " < " + std::to_string(need));
+      p = user;
+      bytes = user_bytes;
+    } else {
+      p = device_alloc(need);
+      bytes = need;
+      owned = true;
+    }
+  }
+  ~Workspace() {
+    if (owned) device_free(p);
+  }
+};
+
+static void check_dtype(int dtype) {
+  if (dtype != FST_F64 && dtype != FST_F32) fail(FST_E_INVAL, "dtype must be FST_F64 or FST_F32");
+}
+static void check_prec(int dtype, int gram_prec) {
+  if (dtype == FST_F64 && gram_prec != FST_GRAM_F64) fail(FST_E_INVAL, "FP64 points need gram_prec FST_GRAM_F64");
+  if (dtype == FST_F32 && gram_prec != FST_GRAM_F32 && gram_prec != FST_GRAM_BF16 && gram_prec != FST_GRAM_F16)
+    fail(FST_E_INVAL, "FP32 points need gram_prec FST_GRAM_F32, FST_GRAM_BF16 or FST_GRAM_F16");
+}
+static size_t dsize(int dtype) { return dtype == FST_F64 ? sizeof(double) : sizeof(float); }
+
+static void validate_params(const fst_fit_params* p, int64_t n) {
+  if (!p) fail(FST_E_INVAL, "null parameters");
+  if (p->struct_size != sizeof(fst_fit_params)) fail(FST_E_INVAL, "fst_fit_params.struct_size mismatch");
+  check_dtype(p->dtype);
+  check_prec(p->dtype, p->gram_prec);
+  if (n < 1 || n >= (int64_t(1) << 31)) fail(FST_E_INVAL, "need 1 <= n < 2^31 points");
+  for (int k = 0; k < 3; ++k) {
+    if (!(std::isfinite(p->lo[k]) && std::isfinite(p->hi[k]) && p->hi[k] > p->lo[k]))
+      fail(FST_E_INVAL, "need finite lo < hi in every mode");
+    if (p->grid[k] < 3 || p->grid[k] > 4096) fail(FST_E_INVAL, "grid sizes must be in [3, 4096]");
+    if (p->rank[k] < 1 || p->rank[k] > p->grid[k]) fail(FST_E_INVAL, "need 1 <= rank <= grid size");
+    if (p->rank[k] > kMaxRank) fail(FST_E_UNSUPPORTED, "rank above 32 is not supported");
+    if (p->degree[k] < 0) fail(FST_E_INVAL, "degree must be >= 0");
+    if (p->degree[k] + 1 > kMaxBasis) fail(FST_E_UNSUPPORTED, "degree above 31 is not supported");
+  }
+  for (int k = 0; k < 3; ++k)
+    if ((int64_t)p->rank[k] > (int64_t)p->rank[(k + 1) % 3] * p->rank[(k + 2) % 3])
+      fail(FST_E_INVAL, "each rank must not exceed the product of the other two");
+  if ((int64_t)p->grid[0] * p->grid[1] * p->grid[2] > (int64_t(1) << 28)) fail(FST_E_INVAL, "grid too large");
+  if (!(p->interp_fraction > 0.0 && p->interp_fraction <= 1.0)) fail(FST_E_INVAL, "interp_fraction must be in (0, 1]");
+  if (p->idw_k < 1 || p->idw_k > 64) fail(FST_E_INVAL, "idw_k must be in [1, 64]");
+  if (!(p->idw_power > 0.0 && std::isfinite(p->idw_power))) fail(FST_E_INVAL, "idw_power must be positive");
+  const int64_t R = (int64_t)p->rank[0] * p->rank[1] * p->rank[2];
+  if (p->n_samples <= R || p->n_samples > n)
+    fail(FST_E_INVAL, "Algorithm 2 needs r1 r2 r3 < n_samples <= n (more sampled rows than core entries)");
+  if (llround(p->interp_fraction * (double)n) < 1) fail(FST_E_INVAL, "interpolation subset is empty");
+  if (p->refine_steps < 0 || p->refine_steps > 100) fail(FST_E_INVAL, "refine_steps must be in [0, 100]");
+}
+
+// --------------------------------------------------------------------------- refit layout
+struct RefitLayout {
+  size_t idx, U, vs, G, h, alpha, r, scratch, total;
+};
+static RefitLayout refit_layout(int64_t R, int sr, int64_t M, int dtype, int refine, size_t scratch_need) {
+  RefitLayout L;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off += align_up(bytes);
+    return o;
+  };
+  L.idx = take(sizeof(int32_t) * (size_t)M);
+  L.U = take(dsize(dtype) * (size_t)sr * (size_t)M);
+  L.vs = take(dsize(dtype) * (size_t)M);
+  L.G = take(sizeof(double) * (size_t)R * (size_t)R);
+  L.h = take(sizeof(double) * (size_t)R);
+  L.alpha = take(sizeof(double) * (size_t)R);
+  L.r = take(refine > 0 ? sizeof(double) * (size_t)R : 0);
+  L.scratch = take(scratch_need);
+  L.total = off;
+  return L;
+}
+static size_t refit_scratch(const fst_model* m, int64_t M, int refine) {
+  size_t s = std::max(gram_workspace_bytes(m, M), cholesky_workspace_bytes(m->R()));
+  if (refine > 0) s = std::max(s, residual_workspace_bytes(m, M));
+  return s;
+}
+// the same bound without a model object (for fst_fit_workspace_bytes)
+static size_t refit_bytes_for(const int32_t rank[3], const int32_t degree[3], int64_t M, int dtype, int refine) {
+  double lo[3] = {-1, -1, -1}, hi[3] = {1, 1, 1};
+  std::unique_ptr<fst_model> tmp(model_new(lo, hi, rank, degree));
+  return refit_layout(tmp->R(), tmp->sum_r(), M, dtype, refine, refit_scratch(tmp.get(), M, refine)).total;
+}
+
+static fst_model* copy_with_core(const fst_model* m, const std::vector<double>& core) {
+  fst_model* out = model_new(m->lo, m->hi, m->rank, m->degree);
+  for (int k = 0; k < 3; ++k) out->coef[k] = m->coef[k];
+  out->core = core;
+  return out;
+}
+
+static fst_model* refit_impl(const fst_model* m, int dtype, int64_t n, const void* x, const void* y,
+                             const void* z, const void* v, int64_t M, uint64_t seed, int gram_prec,
+                             int refine, void* ws_user, size_t ws_bytes, void* stream) {
+  check_model(m);
+  check_dtype(dtype);
+  check_prec(dtype, gram_prec);
+  const int64_t R = m->R();
+  if (n < 1 || n >= (int64_t(1) << 31)) fail(FST_E_INVAL, "need 1 <= n < 2^31 points");
+  if (M <= R || M > n) fail(FST_E_INVAL, "Algorithm 2 needs r1 r2 r3 < n_samples <= n");
+  if (!x || !y || !z || !v) fail(FST_E_INVAL, "null point or value array");
+  if (refine < 0 || refine > 100) fail(FST_E_INVAL, "refine_steps must be in [0, 100]");
+  const RefitLayout L = refit_layout(R, m->sum_r(), M, dtype, refine, refit_scratch(m, M, refine));
+  Workspace ws(ws_user, ws_bytes, L.total);
+  char* base = (char*)ws.p;
+  int32_t* d_idx = (int32_t*)(base + L.idx);
+  void* d_U = base + L.U;
+  void* d_vs = base + L.vs;
+  double* d_G = (double*)(base + L.G);
+  double* d_h = (double*)(base + L.h);
+  double* d_alpha = (double*)(base + L.alpha);
+  double* d_r = (double*)(base + L.r);
+  void* d_scr = base + L.scratch;
+  const size_t scr_bytes = ws.bytes - L.scratch;
+
+  // Algorithm 2 step 4: M rows drawn uniformly without replacement (stream 2), sorted
+  std::vector<int64_t> idx((size_t)M);
+  sample_indices(seed, FST_STREAM_LS, n, M, idx.data());
+  std::vector<int32_t> idx32((size_t)M);
+  for (int64_t i = 0; i < M; ++i) idx32[(size_t)i] = (int32_t)idx[(size_t)i];
+  copy_h2d(d_idx, idx32.data(), sizeof(int32_t) * (size_t)M, stream);
+
+  // step 1 at the sampled rows (factor functions), then the normal equations of step 5
+  const DeviceModel& dm = device_model(m, dtype);
+  launch_factor_eval(m, dm, dtype, n, x, y, z, v, d_idx, M, d_U, d_vs, stream);
+  launch_gram(m, dtype, M, d_U, d_vs, gram_prec, d_G, d_h, d_scr, scr_bytes, stream);
+  std::vector<double> h((size_t)R);
+  copy_d2h(h.data(), d_h, sizeof(double) * (size_t)R, stream);
+  for (double t : h)
+    if (!std::isfinite(t)) fail(FST_E_INVAL, "non-finite coordinates or values among the sampled rows");
+  int64_t info = cholesky(R, d_G, d_scr, scr_bytes, stream);
+  if (info != 0)
+    fail(FST_E_NOT_SPD, "Cholesky breakdown at pivot " + std::to_string(info) +
+                            ": the sampled Gram matrix is not positive definite (too few distinct rows?)");
+  cholesky_solve(R, d_G, d_h, d_alpha, stream);
+  for (int s = 0; s < refine; ++s) {
+    residual(m, dtype, n, x, y, z, v, d_idx, M, d_alpha, d_r, d_scr, scr_bytes, stream);
+    cholesky_solve(R, d_G, d_r, d_r, stream);
+    device_axpy(R, 1.0, d_r, d_alpha, stream);
+  }
+  std::vector<double> alpha((size_t)R);
+  copy_d2h(alpha.data(), d_alpha, sizeof(double) * (size_t)R, stream);
+  for (double t : alpha)
+    if (!std::isfinite(t)) fail(FST_E_NOT_SPD, "solve produced non-finite core values");
+  return copy_with_core(m, alpha);
+}
+
+// Algorithm 1 from the gathered interpolation subset (host FP64, K x 4: x, y, z, v).
+static fst_model* compress_from_subset(const fst_fit_params* p, const std::vector<double>& sub, int64_t K) {
+  std::vector<double> xi((size_t)K * 3), v((size_t)K);
+  for (int64_t i = 0; i < K; ++i) {
+    for (int k = 0; k < 3; ++k) {
+      double c = sub[(size_t)(4 * i + k)];
+      if (!std::isfinite(c)) fail(FST_E_INVAL, "non-finite coordinate in the interpolation subset");
+      xi[(size_t)(3 * i + k)] = 2.0 * (c - p->lo[k]) / (p->hi[k] - p->lo[k]) - 1.0;
+    }
+    v[(size_t)i] = sub[(size_t)(4 * i + 3)];
+    if (!std::isfinite(v[(size_t)i])) fail(FST_E_INVAL, "non-finite value in the interpolation subset");
+  }
+  const int64_t nodes = (int64_t)p->grid[0] * p->grid[1] * p->grid[2];
+  std::vector<double> T((size_t)nodes);
+  idw_grid(xi.data(), v.data(), K, p->grid, p->idw_k, p->idw_power, p->n_threads, T.data());
+  std::unique_ptr<fst_model> m(model_new(p->lo, p->hi, p->rank, p->degree));
+  std::vector<double> W[3];
+  double* Wp[3];
+  for (int k = 0; k < 3; ++k) {
+    W[k].assign((size_t)p->grid[k] * p->rank[k], 0.0);
+    Wp[k] = W[k].data();
+  }
+  sthosvd(T.data(), p->grid, p->rank, p->n_threads, m->core.data(), Wp, nullptr);
+  for (int k = 0; k < 3; ++k) sparse_fit(W[k].data(), p->grid[k], p->rank[k], p->degree[k], m->coef[k].data());
+  return m.release();
+}
+
+}  // namespace fst
+
+using namespace fst;
+
+#define FST_TRY try {
+#define FST_CATCH                                   \
+  }                                                 \
+  catch (const fst::Error& e) {                     \
+    fst::set_last_error(e.what());                  \
+    return e.code;                                  \
+  }                                                 \
+  catch (const std::bad_alloc&) {                   \
+    fst::set_last_error("host allocation failed");  \
+    return FST_E_NOMEM;                             \
+  }                                                 \
+  catch (const std::exception& e) {                 \
+    fst::set_last_error(e.what());                  \
+    return FST_E_INVAL;                             \
+  }
+
+extern "C" {
+
+const char* fst_last_error(void) { return fst::g_last_error.c_str(); }
+const char* fst_version(void) { return "fst-mi355x 0.1.0 (gfx950)"; }
+
+void fst_fit_params_default(fst_fit_params* p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof(*p));
+  p->struct_size = sizeof(fst_fit_params);
+  p->dtype = FST_F64;
+  for (int k = 0; k < 3; ++k) {
+    p->lo[k] = -1.0;
+    p->hi[k] = 1.0;
+    p->grid[k] = 32;
+    p->rank[k] = 8;
+    p->degree[k] = 15;
+  }
+  p->interp_fraction = 0.10;
+  p->idw_k = 8;
+  p->idw_power = 2.0;
+  p->n_samples = 2000;
+  p->seed = 1;
+  p->gram_prec = FST_GRAM_F64;
+  p->refine_steps = 0;
+  p->n_threads = 0;
+}
+
+size_t fst_fit_workspace_bytes(const fst_fit_params* p, int64_t n) {
+  try {
+    validate_params(p, n);
+    int64_t K = llround(p->interp_fraction * (double)n);
+    size_t gather = align_up(sizeof(int32_t) * (size_t)K) + sizeof(double) * 4 * (size_t)K;
+    size_t refit = refit_bytes_for(p->rank, p->degree, p->n_samples, p->dtype, p->refine_steps);
+    return std::max(gather, refit);
+  } catch (const fst::Error& e) {
+    fst::set_last_error(e.what());
+    return 0;
+  }
+}
+
+fst_status fst_compress_host(const fst_fit_params* p, int64_t n, const void* x, const void* y,
+                             const void* z, const void* v, fst_model** out) {
+  FST_TRY
+  set_last_error("");
+  validate_params(p, n);
+  if (!x || !y || !z || !v || !out) fail(FST_E_INVAL, "null argument");
+  const int64_t K = llround(p->interp_fraction * (double)n);
+  std::vector<int64_t> sub((size_t)K);
+  sample_indices(p->seed, FST_STREAM_INTERP, n, K, sub.data());
+  std::vector<double> xyzv((size_t)K * 4);
+  for (int64_t t = 0; t < K; ++t) {
+    int64_t i = sub[(size_t)t];
+    if (p->dtype == FST_F64) {
+      xyzv[(size_t)(4 * t + 0)] = ((const double*)x)[i];
+      xyzv[(size_t)(4 * t + 1)] = ((const double*)y)[i];
+      xyzv[(size_t)(4 * t + 2)] = ((const double*)z)[i];
+      xyzv[(size_t)(4 * t + 3)] = ((const double*)v)[i];
+    } else {
+      xyzv[(size_t)(4 * t + 0)] = ((const float*)x)[i];
+      xyzv[(size_t)(4 * t + 1)] = ((const float*)y)[i];
+      xyzv[(size_t)(4 * t + 2)] = ((const float*)z)[i];
+      xyzv[(size_t)(4 * t + 3)] = ((const float*)v)[i];
+    }
+  }
+  *out = compress_from_subset(p, xyzv, K);
+  return FST_OK;
+  FST_CATCH
+}
+
+fst_status fst_fit(const fst_fit_params* p, int64_t n, const void* x, const void* y, const void* z,
+                   const void* v, void* ws, size_t ws_bytes, void* stream, fst_model** out) {
+  FST_TRY
+  set_last_error("");
+  validate_params(p, n);
+  if (!x || !y || !z || !v || !out) fail(FST_E_INVAL, "null argument");
+  const int64_t K = llround(p->interp_fraction * (double)n);
+  const size_t need = fst_fit_workspace_bytes(p, n);
+  Workspace w(ws, ws_bytes, need);
+  // Algorithm 1 step 1: a random subset (stream 1) is gathered on the device and copied out
+  std::vector<int64_t> sub((size_t)K);
+  sample_indices(p->seed, FST_STREAM_INTERP, n, K, sub.data());
+  std::vector<double> xyzv((size_t)K * 4);
+  gather_points(p->dtype, K, sub.data(), x, y, z, v, xyzv.data(), w.p, w.bytes, stream);
+  std::unique_ptr<fst_model> m0(compress_from_subset(p, xyzv, K));
+  // Algorithm 2 on the device
+  *out = refit_impl(m0.get(), p->dtype, n, x, y, z, v, p->n_samples, p->seed, p->gram_prec,
+                    p->refine_steps, w.p, w.bytes, stream);
+  return FST_OK;
+  FST_CATCH
+}
+
+size_t fst_refit_workspace_bytes(const fst_model* m, int32_t dtype, int64_t n_samples,
+                                 int32_t refine_steps) {
+  try {
+    check_model(m);
+    check_dtype(dtype);
+    if (n_samples < 1 || refine_steps < 0) fail(FST_E_INVAL, "bad sizes");
+    return refit_layout(m->R(), m->sum_r(), n_samples, dtype, refine_steps,
+                        refit_scratch(m, n_samples, refine_steps)).total;
+  } catch (const fst::Error& e) {
+    fst::set_last_error(e.what());
+    return 0;
+  }
+}
+
+fst_status fst_refit_core(const fst_model* m, int32_t dtype, int64_t n, const void* x, const void* y,
+                          const void* z, const void* v, int64_t n_samples, uint64_t seed,
+                          int32_t gram_prec, int32_t refine_steps, void* ws, size_t ws_bytes,
+                          void* stream, fst_model** out) {
+  FST_TRY
+  set_last_error("");
+  if (!out) fail(FST_E_INVAL, "null output");
+  *out = refit_impl(m, dtype, n, x, y, z, v, n_samples, seed, gram_prec, refine_steps, ws, ws_bytes, stream);
+  return FST_OK;
+  FST_CATCH
+}
+
+fst_status fst_eval(const fst_model* m, int32_t dtype, int64_t n, const void* x, const void* y,
+                    const void* z, void* out, void* stream) {
+  FST_TRY
+  set_last_error("");
+  check_model(m);
+  check_dtype(dtype);
+  if (n < 0 || n >= (int64_t(1) << 31)) fail(FST_E_INVAL, "need 0 <= n < 2^31 points");
+  if (n == 0) return FST_OK;
+  if (!x || !y || !z || !out) fail(FST_E_INVAL, "null point or output array");
+  const DeviceModel& dm = device_model(m, dtype);
+  launch_eval(m, dm, dtype, n, x, y, z, nullptr, nullptr, out, stream);
+  return FST_OK;
+  FST_CATCH
+}
+
+fst_status fst_factor_eval(const fst_model* m, int32_t dtype, int64_t n, const void* x, const void* y,
+                           const void* z, const void* v, const int32_t* idx, int64_t mrows, void* U,
+                           void* vs, void* stream) {
+  FST_TRY
+  set_last_error("");
+  check_model(m);
+  check_dtype(dtype);
+  if (n < 0 || mrows < 0 || n >= (int64_t(1) << 31)) fail(FST_E_INVAL, "bad sizes");
+  if (!idx && mrows > n) fail(FST_E_INVAL, "mrows > n without an index array");
+  if (mrows == 0) return FST_OK;
+  if (!x || !y || !z || !U) fail(FST_E_INVAL, "null argument");
+  if (vs && !v) fail(FST_E_INVAL, "vs requested without values");
+  const DeviceModel& dm = device_model(m, dtype);
+  launch_factor_eval(m, dm, dtype, n, x, y, z, v, idx, mrows, U, vs, stream);
+  return FST_OK;
+  FST_CATCH
+}
+
+size_t fst_gram_workspace_bytes(const fst_model* m, int64_t mrows) {
+  if (!m || mrows < 0) return 0;
+  return gram_workspace_bytes(m, mrows);
+}
+
+fst_status fst_gram(const fst_model* m, int32_t dtype, int64_t mrows, const void* U, const void* vs,
+                    int32_t gram_prec, double* G, double* h, void* ws, size_t ws_bytes, void* stream) {
+  FST_TRY
+  set_last_error("");
+  check_model(m);
+  check_dtype(dtype);
+  check_prec(dtype, gram_prec);
+  if (mrows < 1) fail(FST_E_INVAL, "need mrows >= 1");
+  if (!U || (!G && !h)) fail(FST_E_INVAL, "null argument");
+  if (h && !vs) fail(FST_E_INVAL, "h requested without vs");
+  if (h && !ws) fail(FST_E_INVAL, "h needs a workspace");
+  launch_gram(m, dtype, mrows, U, vs, gram_prec, G, h, ws, ws ? ws_bytes : 0, stream);
+  return FST_OK;
+  FST_CATCH
+}
+
+size_t fst_cholesky_workspace_bytes(int64_t R) { return cholesky_workspace_bytes(R); }
+
+fst_status fst_cholesky(int64_t R, double* G, int64_t* info, void* ws, size_t ws_bytes, void* stream) {
+  FST_TRY
+  set_last_error("");
+  if (info) *info = 0;
+  if (R < 1 || !G || !ws) fail(FST_E_INVAL, "bad arguments");
+  int64_t piv = cholesky(R, G, ws, ws_bytes, stream);
+  if (info) *info = piv;
+  if (piv != 0) fail(FST_E_NOT_SPD, "Cholesky breakdown at pivot " + std::to_string(piv));
+  return FST_OK;
+  FST_CATCH
+}
+
+fst_status fst_cholesky_solve(int64_t R, const double* L, const double* b, double* x, void* stream) {
+  FST_TRY
+  set_last_error("");
+  if (R < 1 || !L || !b || !x) fail(FST_E_INVAL, "bad arguments");
+  cholesky_solve(R, L, b, x, stream);
+  return FST_OK;
+  FST_CATCH
+}
+
+size_t fst_residual_workspace_bytes(const fst_model* m, int64_t mrows) {
+  if (!m || mrows < 0) return 0;
+  return residual_workspace_bytes(m, mrows);
+}
+
+fst_status fst_residual(const fst_model* m, int32_t dtype, int64_t n, const void* x, const void* y,
+                        const void* z, const void* v, const int32_t* idx, int64_t mrows,
+                        const double* alpha, double* r, void* ws, size_t ws_bytes, void* stream) {
+  FST_TRY
+  set_last_error("");
+  check_model(m);
+  check_dtype(dtype);
+  if (mrows < 1 || n < 1) fail(FST_E_INVAL, "bad sizes");
+  if (!x || !y || !z || !v || !idx || !alpha || !r || !ws) fail(FST_E_INVAL, "null argument");
+  residual(m, dtype, n, x, y, z, v, idx, mrows, alpha, r, ws, ws_bytes, stream);
+  return FST_OK;
+  FST_CATCH
+}
+
+fst_status fst_sample_indices(uint64_t seed, int32_t stream, int64_t n, int64_t m, int64_t* out) {
+  FST_TRY
+  set_last_error("");
+  if (!out && m > 0) fail(FST_E_INVAL, "null output");
+  sample_indices(seed, stream, n, m, out);
+  return FST_OK;
+  FST_CATCH
+}
+
+fst_status fst_idw_grid(const double* xi, const double* v, int64_t K, const int32_t grid[3], int32_t k,
+                        double power, int32_t n_threads, double* out) {
+  FST_TRY
+  set_last_error("");
+  if (!xi || !v || !grid || !out) fail(FST_E_INVAL, "null argument");
+  if (!(power > 0.0)) fail(FST_E_INVAL, "power must be positive");
+  for (int64_t i = 0; i < 3 * K; ++i)
+    if (!std::isfinite(xi[i])) fail(FST_E_INVAL, "non-finite coordinate");
+  for (int64_t i = 0; i < K; ++i)
+    if (!std::isfinite(v[i])) fail(FST_E_INVAL, "non-finite value");
+  idw_grid(xi, v, K, grid, k, power, n_threads, out);
+  return FST_OK;
+  FST_CATCH
+}
+
+fst_status fst_sthosvd(const double* T, const int32_t dims[3], const int32_t rank[3], int32_t n_threads,
+                       double* core, double* const W[3], double* const sigma[3]) {
+  FST_TRY
+  set_last_error("");
+  if (!T || !dims || !rank || !core || !W || !W[0] || !W[1] || !W[2]) fail(FST_E_INVAL, "null argument");
+  sthosvd(T, dims, rank, n_threads, core, W, sigma);
+  return FST_OK;
+  FST_CATCH
+}
+
+fst_status fst_sparse_fit(const double* W, int32_t I, int32_t r, int32_t p, double* C) {
+  FST_TRY
+  set_last_error("");
+  if (!W || !C) fail(FST_E_INVAL, "null argument");
+  sparse_fit(W, I, r, p, C);
+  return FST_OK;
+  FST_CATCH
+}
+
+fst_status fst_model_from_parts(const double lo[3], const double hi[3], const int32_t rank[3],
+                                const int32_t degree[3], const double* core, const double* const coefs[3],
+                                fst_model** out) {
+  FST_TRY
+  set_last_error("");
+  if (!lo || !hi || !rank || !degree || !core || !coefs || !out) fail(FST_E_INVAL, "null argument");
+  std::unique_ptr<fst_model> m(model_new(lo, hi, rank, degree));
+  for (size_t i = 0; i < m->core.size(); ++i) {
+    if (!std::isfinite(core[i])) fail(FST_E_INVAL, "non-finite core entry");
+    m->core[i] = core[i];
+  }
+  for (int k = 0; k < 3; ++k) {
+    if (!coefs[k]) fail(FST_E_INVAL, "null coefficient matrix");
+    for (size_t i = 0; i < m->coef[k].size(); ++i) {
+      if (!std::isfinite(coefs[k][i])) fail(FST_E_INVAL, "non-finite coefficient");
+      m->coef[k][i] = coefs[k][i];
+    }
+  }
+  *out = m.release();
+  return FST_OK;
+  FST_CATCH
+}
+
+void fst_model_free(fst_model* m) { delete m; }
+
+fst_status fst_model_info(const fst_model* m, double* lo, double* hi, int32_t* rank, int32_t* degree,
+                          int64_t* nnz) {
+  FST_TRY
+  set_last_error("");
+  check_model(m);
+  for (int k = 0; k < 3; ++k) {
+    if (lo) lo[k] = m->lo[k];
+    if (hi) hi[k] = m->hi[k];
+    if (rank) rank[k] = m->rank[k];
+    if (degree) degree[k] = m->degree[k];
+  }
+  if (nnz) {
+    int64_t c = 0;
+    for (int k = 0; k < 3; ++k)
+      for (double t : m->coef[k]) c += t != 0.0;
+    *nnz = c;
+  }
+  return FST_OK;
+  FST_CATCH
+}
+
+fst_status fst_model_core(const fst_model* m, double* core_out) {
+  FST_TRY
+  set_last_error("");
+  check_model(m);
+  if (!core_out) fail(FST_E_INVAL, "null output");
+  std::memcpy(core_out, m->core.data(), sizeof(double) * m->core.size());
+  return FST_OK;
+  FST_CATCH
+}
+
+fst_status fst_model_coefs(const fst_model* m, int32_t k, double* C_out) {
+  FST_TRY
+  set_last_error("");
+  check_model(m);
+  if (k < 0 || k > 2 || !C_out) fail(FST_E_INVAL, "bad mode or null output");
+  std::memcpy(C_out, m->coef[k].data(), sizeof(double) * m->coef[k].size());
+  return FST_OK;
+  FST_CATCH
+}
+
+int64_t fst_model_paper_bytes(const fst_model* m) {
+  if (!m) return -1;
+  int64_t nnz = 0;
+  for (int k = 0; k < 3; ++k)
+    for (double t : m->coef[k]) nnz += t != 0.0;
+  return 8 * (m->R() + nnz);
+}
+
+}  // extern "C"

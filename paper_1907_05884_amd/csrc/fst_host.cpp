@@ -1,0 +1,537 @@
+// Host steps of Algorithm 1 (Sec. 4): random subset draw, interpolation onto the equispaced
+// grid, ST-HOSVD at fixed ranks, sparse Legendre fit of each singular vector.  These steps
+// work on small objects (a grid of at most a few million nodes, factor vectors of a few
+// hundred entries) and stay on host threads.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <limits>
+#include <numeric>
+#include <thread>
+
+#include "fst_internal.h"
+
+namespace fst {
+
+int hardware_threads(int requested) {
+  if (requested > 0) return requested;
+  unsigned h = std::thread::hardware_concurrency();
+  return h == 0 ? 1 : (int)std::min(h, 64u);
+}
+
+template <class F>
+static void parallel_for(int64_t n, int n_threads, F&& body) {
+  n_threads = (int)std::max<int64_t>(1, std::min<int64_t>(n_threads, n));
+  if (n_threads <= 1) {
+    body(0, n);
+    return;
+  }
+  std::vector<std::thread> th;
+  int64_t chunk = (n + n_threads - 1) / n_threads;
+  for (int t = 0; t < n_threads; ++t) {
+    int64_t a = t * chunk, b = std::min(n, a + chunk);
+    if (a >= b) break;
+    th.emplace_back([&body, a, b] { body(a, b); });
+  }
+  for (auto& t : th) t.join();
+}
+
+// ------------------------------------------------------------------------------ sampler
+// SplitMix64 (Steele, Lea, Flood 2014): golden-ratio increment, then the 64-bit finaliser
+// with constants 0xBF58476D1CE4E5B9 / 0x94D049BB133111EB and shifts 30, 27, 31.
+uint64_t splitmix64_next(uint64_t& state) {
+  state += 0x9E3779B97F4A7C15ull;
+  uint64_t z = state;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// Algorithm 2 samples rows uniformly; draws are without replacement, sorted, from a partial
+// Fisher-Yates shuffle whose bounded draw in [0, k) is the high half of r * k.
+void sample_indices(uint64_t seed, int stream, int64_t n, int64_t m, int64_t* out) {
+  if (n < 0 || m < 0 || m > n) fail(FST_E_INVAL, "sample_indices: need 0 <= m <= n");
+  if (n >= (int64_t(1) << 32)) fail(FST_E_UNSUPPORTED, "sample_indices: n must be < 2^32");
+  uint64_t state = seed * 256ull + (uint64_t)stream;
+  std::vector<int64_t> a((size_t)n);
+  std::iota(a.begin(), a.end(), int64_t(0));
+  for (int64_t i = 0; i < m; ++i) {
+    uint64_t r = splitmix64_next(state);
+    uint64_t span = (uint64_t)(n - i);
+    int64_t j = i + (int64_t)(((unsigned __int128)r * span) >> 64);
+    std::swap(a[(size_t)i], a[(size_t)j]);
+  }
+  std::sort(a.begin(), a.begin() + m);
+  std::memcpy(out, a.data(), sizeof(int64_t) * (size_t)m);
+}
+
+// ------------------------------------------------------------------------------ IDW
+// Exact k-nearest neighbours through a uniform bin grid over [-1,1]^3, searched in growing
+// cubic shells until the k-th best distance is below the distance to any unsearched cell.
+// Candidates are ordered by (squared distance, index): equal distances go to the lower index.
+namespace {
+struct Cand {
+  double d2;
+  int64_t idx;
+  bool operator<(const Cand& o) const { return d2 < o.d2 || (d2 == o.d2 && idx < o.idx); }
+};
+
+struct BinGrid {
+  int B = 1;
+  double h = 2.0;
+  std::vector<int64_t> start;   // B^3 + 1
+  std::vector<int64_t> order;   // point indices sorted by cell (stable, so ascending in a cell)
+  int cell_of(double t) const {
+    int c = (int)std::floor((t + 1.0) / h);
+    return std::min(std::max(c, 0), B - 1);
+  }
+};
+}  // namespace
+
+void idw_grid(const double* xi, const double* v, int64_t K, const int32_t grid[3], int k,
+              double power, int n_threads, double* out) {
+  if (K <= 0) fail(FST_E_INVAL, "idw_grid: no points");
+  for (int d = 0; d < 3; ++d)
+    if (grid[d] < 2) fail(FST_E_INVAL, "idw_grid: grid sizes must be >= 2");
+  if (k < 1) fail(FST_E_INVAL, "idw_grid: k must be >= 1");
+  k = (int)std::min<int64_t>(k, K);
+  BinGrid bg;
+  bg.B = std::max(1, (int)std::cbrt((double)K / 2.0));
+  bg.B = std::min(bg.B, 256);
+  bg.h = 2.0 / bg.B;
+  const int B = bg.B;
+  const int64_t ncell = (int64_t)B * B * B;
+  std::vector<int64_t> cell((size_t)K);
+  bg.start.assign((size_t)ncell + 1, 0);
+  for (int64_t i = 0; i < K; ++i) {
+    int64_t c = ((int64_t)bg.cell_of(xi[3 * i]) * B + bg.cell_of(xi[3 * i + 1])) * B +
+                bg.cell_of(xi[3 * i + 2]);
+    cell[(size_t)i] = c;
+    bg.start[(size_t)c + 1]++;
+  }
+  for (int64_t c = 0; c < ncell; ++c) bg.start[(size_t)c + 1] += bg.start[(size_t)c];
+  bg.order.resize((size_t)K);
+  {
+    std::vector<int64_t> fill(bg.start.begin(), bg.start.end() - 1);
+    for (int64_t i = 0; i < K; ++i) bg.order[(size_t)fill[(size_t)cell[(size_t)i]]++] = i;
+  }
+  const int64_t I0 = grid[0], I1 = grid[1], I2 = grid[2];
+  const int64_t nodes = I0 * I1 * I2;
+  parallel_for(nodes, hardware_threads(n_threads), [&](int64_t a, int64_t b) {
+    std::vector<Cand> best;
+    best.reserve((size_t)k + 1);
+    for (int64_t node = a; node < b; ++node) {
+      int64_t i0 = node / (I1 * I2), i1 = (node / I2) % I1, i2 = node % I2;
+      double q[3] = {-1.0 + 2.0 * i0 / (I0 - 1), -1.0 + 2.0 * i1 / (I1 - 1),
+                     -1.0 + 2.0 * i2 / (I2 - 1)};
+      int c[3] = {bg.cell_of(q[0]), bg.cell_of(q[1]), bg.cell_of(q[2])};
+      best.clear();
+      for (int rho = 0;; ++rho) {
+        int lo[3], hi[3];
+        for (int d = 0; d < 3; ++d) {
+          lo[d] = std::max(0, c[d] - rho);
+          hi[d] = std::min(B - 1, c[d] + rho);
+        }
+        for (int x = lo[0]; x <= hi[0]; ++x)
+          for (int y = lo[1]; y <= hi[1]; ++y)
+            for (int z = lo[2]; z <= hi[2]; ++z) {
+              // only the shell at Chebyshev distance rho (inner cells were done before)
+              int cheb = std::max({std::abs(x - c[0]), std::abs(y - c[1]), std::abs(z - c[2])});
+              if (cheb != rho) continue;
+              int64_t cc = ((int64_t)x * B + y) * B + z;
+              for (int64_t s = bg.start[(size_t)cc]; s < bg.start[(size_t)cc + 1]; ++s) {
+                int64_t i = bg.order[(size_t)s];
+                double dx = xi[3 * i] - q[0], dy = xi[3 * i + 1] - q[1], dz = xi[3 * i + 2] - q[2];
+                Cand cd{dx * dx + dy * dy + dz * dz, i};
+                if ((int)best.size() < k) {
+                  best.insert(std::upper_bound(best.begin(), best.end(), cd), cd);
+                } else if (cd < best.back()) {
+                  best.pop_back();
+                  best.insert(std::upper_bound(best.begin(), best.end(), cd), cd);
+                }
+              }
+            }
+        bool covers_all = true;
+        double bound = std::numeric_limits<double>::infinity();
+        for (int d = 0; d < 3; ++d) {
+          if (c[d] - rho > 0) {
+            covers_all = false;
+            bound = std::min(bound, q[d] - (-1.0 + (c[d] - rho) * bg.h));
+          }
+          if (c[d] + rho < B - 1) {
+            covers_all = false;
+            bound = std::min(bound, (-1.0 + (c[d] + rho + 1) * bg.h) - q[d]);
+          }
+        }
+        if (covers_all) break;
+        // Points in unsearched cells lie at least `bound` away (cells are clamped at the
+        // domain edge, so points slightly outside [-1,1] sit in edge cells already searched).
+        if ((int)best.size() == k && best.back().d2 < bound * bound) break;
+      }
+      if (best.front().d2 == 0.0) {
+        out[node] = v[best.front().idx];
+        continue;
+      }
+      double num = 0.0, den = 0.0;
+      for (const Cand& cd : best) {
+        double w = 1.0 / std::pow(std::sqrt(cd.d2), power);
+        num += w * v[cd.idx];
+        den += w;
+      }
+      out[node] = num / den;
+    }
+  });
+}
+
+// ------------------------------------------------------------------------------ ST-HOSVD
+namespace {
+
+// Householder QR of a column-major m x n matrix (m >= n); returns R (n x n, column-major,
+// upper triangular) and keeps the reflectors in A so that Q can be applied afterwards.
+struct HouseholderQR {
+  int64_t m, n;
+  std::vector<double> A;      // column-major m x n; reflectors below the diagonal
+  std::vector<double> beta;   // 2 / (v^T v) per reflector, v = (1, A[j+1.., j])
+  std::vector<double> diag;   // R diagonal
+  void factor() {
+    beta.assign((size_t)n, 0.0);
+    diag.assign((size_t)n, 0.0);
+    for (int64_t j = 0; j < n; ++j) {
+      double* col = &A[(size_t)(j * m)];
+      double norm2 = 0.0;
+      for (int64_t i = j; i < m; ++i) norm2 += col[i] * col[i];
+      double norm = std::sqrt(norm2);
+      if (norm == 0.0) {
+        beta[(size_t)j] = 0.0;
+        diag[(size_t)j] = 0.0;
+        continue;
+      }
+      double alpha = col[j] > 0 ? -norm : norm;   // R_jj
+      double v0 = col[j] - alpha;
+      // v = (v0, col[j+1..]) scaled so that v[0] = 1
+      for (int64_t i = j + 1; i < m; ++i) col[i] /= v0;
+      double vtv = 1.0;
+      for (int64_t i = j + 1; i < m; ++i) vtv += col[i] * col[i];
+      beta[(size_t)j] = 2.0 / vtv;
+      diag[(size_t)j] = alpha;
+      col[j] = alpha;
+      for (int64_t c = j + 1; c < n; ++c) {
+        double* cc = &A[(size_t)(c * m)];
+        double s = cc[j];
+        for (int64_t i = j + 1; i < m; ++i) s += col[i] * cc[i];
+        s *= beta[(size_t)j];
+        cc[j] -= s;
+        for (int64_t i = j + 1; i < m; ++i) cc[i] -= s * col[i];
+      }
+    }
+  }
+  std::vector<double> R() const {
+    std::vector<double> r((size_t)(n * n), 0.0);
+    for (int64_t c = 0; c < n; ++c)
+      for (int64_t i = 0; i <= c; ++i) r[(size_t)(c * n + i)] = A[(size_t)(c * m + i)];
+    for (int64_t j = 0; j < n; ++j) r[(size_t)(j * n + j)] = diag[(size_t)j];
+    return r;
+  }
+  // y (length m) <- Q y, where y holds an n-vector padded with zeros below
+  void apply_Q(double* y) const {
+    for (int64_t j = n - 1; j >= 0; --j) {
+      if (beta[(size_t)j] == 0.0) continue;
+      const double* col = &A[(size_t)(j * m)];
+      double s = y[j];
+      for (int64_t i = j + 1; i < m; ++i) s += col[i] * y[i];
+      s *= beta[(size_t)j];
+      y[j] -= s;
+      for (int64_t i = j + 1; i < m; ++i) y[i] -= s * col[i];
+    }
+  }
+};
+
+// One-sided (Hestenes) Jacobi on a column-major n x n matrix B: rotates columns until they
+// are mutually orthogonal, B V = W.  Returns V (column-major) and the column norms of W.
+void hestenes(std::vector<double>& B, int64_t n, std::vector<double>& V, std::vector<double>& sig) {
+  V.assign((size_t)(n * n), 0.0);
+  for (int64_t i = 0; i < n; ++i) V[(size_t)(i * n + i)] = 1.0;
+  const double tol = 1e-15;
+  for (int sweep = 0; sweep < 80; ++sweep) {
+    bool rotated = false;
+    for (int64_t i = 0; i < n - 1; ++i) {
+      for (int64_t j = i + 1; j < n; ++j) {
+        double* bi = &B[(size_t)(i * n)];
+        double* bj = &B[(size_t)(j * n)];
+        double a = 0, b = 0, g = 0;
+        for (int64_t t = 0; t < n; ++t) {
+          a += bi[t] * bi[t];
+          b += bj[t] * bj[t];
+          g += bi[t] * bj[t];
+        }
+        if (g == 0.0 || std::fabs(g) <= tol * std::sqrt(a * b)) continue;
+        rotated = true;
+        double zeta = (b - a) / (2.0 * g);
+        double t = (zeta >= 0 ? 1.0 : -1.0) / (std::fabs(zeta) + std::sqrt(1.0 + zeta * zeta));
+        double c = 1.0 / std::sqrt(1.0 + t * t), s = c * t;
+        for (int64_t r = 0; r < n; ++r) {
+          double x = bi[r], y = bj[r];
+          bi[r] = c * x - s * y;
+          bj[r] = s * x + c * y;
+        }
+        double* vi = &V[(size_t)(i * n)];
+        double* vj = &V[(size_t)(j * n)];
+        for (int64_t r = 0; r < n; ++r) {
+          double x = vi[r], y = vj[r];
+          vi[r] = c * x - s * y;
+          vj[r] = s * x + c * y;
+        }
+      }
+    }
+    if (!rotated) break;
+  }
+  sig.assign((size_t)n, 0.0);
+  for (int64_t i = 0; i < n; ++i) {
+    double s = 0;
+    for (int64_t t = 0; t < n; ++t) s += B[(size_t)(i * n + t)] * B[(size_t)(i * n + t)];
+    sig[(size_t)i] = std::sqrt(s);
+  }
+}
+
+// Leading r left singular vectors (I x r, row-major, signs fixed) of the mode-k unfolding
+// of Y with dims d; all singular values into sig_out (length min(I, L)).
+void leading_left_singular(const std::vector<double>& Y, const int64_t d[3], int k, int r,
+                           std::vector<double>& Wout, std::vector<double>& sig_out) {
+  const int64_t I = d[k];
+  const int64_t A = (k == 0) ? 1 : (k == 1 ? d[0] : d[0] * d[1]);
+  const int64_t Bs = (k == 2) ? 1 : (k == 1 ? d[2] : d[1] * d[2]);
+  const int64_t L = A * Bs;
+  // element (i, l) of the unfolding with l = a * Bs + b
+  auto at = [&](int64_t i, int64_t l) {
+    int64_t a = l / Bs, b = l % Bs;
+    return Y[(size_t)((a * I + i) * Bs + b)];
+  };
+  std::vector<double> U((size_t)(I * I), 0.0);   // left singular vectors, column-major I x nsv
+  std::vector<double> sig;
+  int64_t nsv;
+  if (L >= I) {
+    // B = Y_(k)^T (L x I, column-major: column i is row i of the unfolding); B = QR;
+    // Hestenes on R gives V = left singular vectors of Y_(k).
+    HouseholderQR qr;
+    qr.m = L;
+    qr.n = I;
+    qr.A.resize((size_t)(L * I));
+    for (int64_t i = 0; i < I; ++i)
+      for (int64_t l = 0; l < L; ++l) qr.A[(size_t)(i * L + l)] = at(i, l);
+    qr.factor();
+    std::vector<double> R = qr.R();
+    std::vector<double> V;
+    hestenes(R, I, V, sig);
+    nsv = I;
+    U = V;
+  } else {
+    // B = Y_(k) (I x L, column-major: column l is column l of the unfolding); B = QR;
+    // Hestenes on R: R V = W, left singular vectors of Y_(k) are Q W / sigma.
+    HouseholderQR qr;
+    qr.m = I;
+    qr.n = L;
+    qr.A.resize((size_t)(I * L));
+    for (int64_t l = 0; l < L; ++l)
+      for (int64_t i = 0; i < I; ++i) qr.A[(size_t)(l * I + i)] = at(i, l);
+    qr.factor();
+    std::vector<double> R = qr.R();
+    std::vector<double> V;
+    hestenes(R, L, V, sig);   // R now holds W (columns)
+    nsv = L;
+    for (int64_t c = 0; c < L; ++c) {
+      std::vector<double> y((size_t)I, 0.0);
+      for (int64_t t = 0; t < L; ++t) y[(size_t)t] = sig[(size_t)c] > 0 ? R[(size_t)(c * L + t)] / sig[(size_t)c] : 0.0;
+      qr.apply_Q(y.data());
+      for (int64_t i = 0; i < I; ++i) U[(size_t)(c * I + i)] = y[(size_t)i];
+    }
+  }
+  std::vector<int64_t> ord((size_t)nsv);
+  std::iota(ord.begin(), ord.end(), int64_t(0));
+  std::stable_sort(ord.begin(), ord.end(),
+                   [&](int64_t a, int64_t b) { return sig[(size_t)a] > sig[(size_t)b]; });
+  sig_out.assign((size_t)nsv, 0.0);
+  for (int64_t i = 0; i < nsv; ++i) sig_out[(size_t)i] = sig[(size_t)ord[(size_t)i]];
+  Wout.assign((size_t)(I * r), 0.0);
+  for (int j = 0; j < r; ++j) {
+    const double* col = &U[(size_t)(ord[(size_t)j] * I)];
+    int64_t imax = 0;
+    for (int64_t i = 1; i < I; ++i)
+      if (std::fabs(col[i]) > std::fabs(col[imax])) imax = i;
+    double sgn = col[imax] < 0 ? -1.0 : 1.0;
+    for (int64_t i = 0; i < I; ++i) Wout[(size_t)(i * r + j)] = sgn * col[i];
+  }
+}
+
+// Y (dims d) <- Y x_k W^T with W (I_k x r) row-major; d[k] becomes r.
+void mode_product_transposed(std::vector<double>& Y, int64_t d[3], int k, const std::vector<double>& W, int r) {
+  const int64_t I = d[k];
+  const int64_t A = (k == 0) ? 1 : (k == 1 ? d[0] : d[0] * d[1]);
+  const int64_t Bs = (k == 2) ? 1 : (k == 1 ? d[2] : d[1] * d[2]);
+  std::vector<double> out((size_t)(A * r * Bs), 0.0);
+  for (int64_t a = 0; a < A; ++a)
+    for (int j = 0; j < r; ++j) {
+      double* o = &out[(size_t)((a * r + j) * Bs)];
+      for (int64_t i = 0; i < I; ++i) {
+        double w = W[(size_t)(i * r + j)];
+        const double* y = &Y[(size_t)((a * I + i) * Bs)];
+        for (int64_t b = 0; b < Bs; ++b) o[b] += w * y[b];
+      }
+    }
+  Y.swap(out);
+  d[k] = r;
+}
+
+}  // namespace
+
+void sthosvd(const double* T, const int32_t dims[3], const int32_t rank[3], int n_threads,
+             double* core, double* const W[3], double* const sigma[3]) {
+  (void)n_threads;
+  int64_t d[3] = {dims[0], dims[1], dims[2]};
+  for (int k = 0; k < 3; ++k) {
+    if (d[k] < 1 || rank[k] < 1 || rank[k] > d[k])
+      fail(FST_E_INVAL, "sthosvd: need 1 <= r_k <= I_k");
+  }
+  std::vector<double> Y(T, T + d[0] * d[1] * d[2]);
+  for (int k = 0; k < 3; ++k) {
+    int64_t L = 1;
+    for (int l = 0; l < 3; ++l)
+      if (l != k) L *= d[l];
+    if (rank[k] > L) fail(FST_E_INVAL, "sthosvd: r_k exceeds the product of the other sizes");
+    std::vector<double> Wk, sig;
+    leading_left_singular(Y, d, k, rank[k], Wk, sig);
+    std::memcpy(W[k], Wk.data(), sizeof(double) * Wk.size());
+    if (sigma && sigma[k]) {
+      for (int64_t i = 0; i < dims[k]; ++i) sigma[k][i] = i < (int64_t)sig.size() ? sig[(size_t)i] : 0.0;
+    }
+    mode_product_transposed(Y, d, k, Wk, rank[k]);
+  }
+  std::memcpy(core, Y.data(), sizeof(double) * Y.size());
+}
+
+// ------------------------------------------------------------------------------ sparse fit
+void legendre_orthonormal_host(double t, int p, double* phi) {
+  // Bonnet recurrence (m+1) P_{m+1} = (2m+1) t P_m - m P_{m-1}, then phi_m = sqrt(2m+1) P_m
+  double pm1 = 1.0, pm = t;
+  phi[0] = 1.0;
+  if (p >= 1) phi[1] = std::sqrt(3.0) * t;
+  for (int m = 1; m < p; ++m) {
+    double pn = ((2.0 * m + 1.0) * t * pm - m * pm1) / (m + 1.0);
+    pm1 = pm;
+    pm = pn;
+    phi[m + 1] = std::sqrt(2.0 * (m + 1) + 1.0) * pn;
+  }
+}
+
+namespace {
+// Least squares on the selected columns by Householder QR; returns coefficients, residual
+// and leverages h_ii (squared row norms of Phi_S R^-1).
+void ls_select(const std::vector<double>& Phi, int I, int n, const std::vector<int>& S,
+               const double* z, std::vector<double>& c, std::vector<double>& res,
+               std::vector<double>& lev) {
+  const int t = (int)S.size();
+  HouseholderQR qr;
+  qr.m = I;
+  qr.n = t;
+  qr.A.resize((size_t)I * t);
+  for (int j = 0; j < t; ++j)
+    for (int i = 0; i < I; ++i) qr.A[(size_t)j * I + i] = Phi[(size_t)i * n + S[(size_t)j]];
+  qr.factor();
+  std::vector<double> R = qr.R();   // column-major t x t
+  // Q^T z: apply reflectors in forward order
+  std::vector<double> y(z, z + I);
+  for (int j = 0; j < t; ++j) {
+    if (qr.beta[(size_t)j] == 0.0) continue;
+    const double* col = &qr.A[(size_t)j * I];
+    double s = y[(size_t)j];
+    for (int i = j + 1; i < I; ++i) s += col[i] * y[(size_t)i];
+    s *= qr.beta[(size_t)j];
+    y[(size_t)j] -= s;
+    for (int i = j + 1; i < I; ++i) y[(size_t)i] -= s * col[i];
+  }
+  c.assign((size_t)t, 0.0);
+  for (int j = t - 1; j >= 0; --j) {
+    double s = y[(size_t)j];
+    for (int l = j + 1; l < t; ++l) s -= R[(size_t)l * t + j] * c[(size_t)l];
+    c[(size_t)j] = s / R[(size_t)j * t + j];
+  }
+  res.assign((size_t)I, 0.0);
+  lev.assign((size_t)I, 0.0);
+  std::vector<double> w((size_t)t);
+  for (int i = 0; i < I; ++i) {
+    double f = 0.0;
+    for (int j = 0; j < t; ++j) f += Phi[(size_t)i * n + S[(size_t)j]] * c[(size_t)j];
+    res[(size_t)i] = z[i] - f;
+    // solve R^T w = Phi_S[i, :]^T
+    double h = 0.0;
+    for (int j = 0; j < t; ++j) {
+      double s = Phi[(size_t)i * n + S[(size_t)j]];
+      for (int l = 0; l < j; ++l) s -= R[(size_t)j * t + l] * w[(size_t)l];
+      w[(size_t)j] = s / R[(size_t)j * t + j];
+      h += w[(size_t)j] * w[(size_t)j];
+    }
+    lev[(size_t)i] = h;
+  }
+}
+}  // namespace
+
+void sparse_fit(const double* W, int I, int r, int p, double* C) {
+  if (I < 3 || r < 1 || p < 0) fail(FST_E_INVAL, "sparse_fit: need I >= 3, r >= 1, p >= 0");
+  const int n = p + 1;
+  std::vector<double> Phi((size_t)I * n);
+  for (int i = 0; i < I; ++i) legendre_orthonormal_host(-1.0 + 2.0 * i / (I - 1), p, &Phi[(size_t)i * n]);
+  std::vector<double> colnorm((size_t)n, 0.0);
+  for (int m = 0; m < n; ++m) {
+    double s = 0;
+    for (int i = 0; i < I; ++i) s += Phi[(size_t)i * n + m] * Phi[(size_t)i * n + m];
+    colnorm[(size_t)m] = std::sqrt(s);
+  }
+  std::fill(C, C + (size_t)n * r, 0.0);
+  std::vector<double> z((size_t)I), res, lev, c;
+  for (int j = 0; j < r; ++j) {
+    for (int i = 0; i < I; ++i) z[(size_t)i] = W[(size_t)i * r + j];
+    double zn = 0;
+    for (double t : z) zn += t * t;
+    zn = std::sqrt(zn);
+    if (zn == 0.0) continue;
+    std::vector<int> S;
+    std::vector<std::vector<double>> coefs;
+    std::vector<double> press;
+    std::vector<double> rcur = z;
+    const int tmax = std::min(n, I - 2);
+    for (int t = 0; t < tmax; ++t) {
+      int best = -1;
+      double bscore = -1.0;
+      for (int m = 0; m < n; ++m) {
+        if (std::find(S.begin(), S.end(), m) != S.end()) continue;
+        double s = 0;
+        for (int i = 0; i < I; ++i) s += Phi[(size_t)i * n + m] * rcur[(size_t)i];
+        double score = std::fabs(s) / colnorm[(size_t)m];
+        if (score > bscore) {
+          bscore = score;
+          best = m;
+        }
+      }
+      S.push_back(best);
+      ls_select(Phi, I, n, S, z.data(), c, res, lev);
+      double pr = 0.0;
+      for (int i = 0; i < I; ++i) {
+        double e = res[(size_t)i] / (1.0 - lev[(size_t)i]);
+        pr += e * e;
+      }
+      pr /= I;
+      if (!(pr == pr)) pr = std::numeric_limits<double>::infinity();
+      press.push_back(pr);
+      coefs.push_back(c);
+      rcur = res;
+      double rn = 0;
+      for (double t2 : res) rn += t2 * t2;
+      if (std::sqrt(rn) <= 1e-14 * zn) break;
+    }
+    size_t tb = 0;
+    for (size_t t = 1; t < press.size(); ++t)
+      if (press[t] < press[tb]) tb = t;
+    for (size_t l = 0; l <= tb; ++l) C[(size_t)S[l] * r + j] = coefs[tb][l];
+  }
+}
+
+}  // namespace fst

@@ -1,0 +1,238 @@
+// The functional sparse Tucker model object (eq. (1)-(2)): validation, device copies and a
+// versioned binary serialisation.
+#include <cmath>
+#include <cstring>
+
+#include "fst_internal.h"
+
+fst_model::~fst_model() {
+  for (auto& kv : dev) {
+    fst::device_free(kv.second.coefs);
+    fst::device_free(kv.second.core);
+    fst::device_free(kv.second.core64);
+  }
+}
+
+namespace fst {
+
+fst_model* model_new(const double lo[3], const double hi[3], const int32_t rank[3],
+                     const int32_t degree[3]) {
+  for (int k = 0; k < 3; ++k) {
+    if (!(std::isfinite(lo[k]) && std::isfinite(hi[k]) && hi[k] > lo[k]))
+      fail(FST_E_INVAL, "model: need finite lo < hi in every mode");
+    if (rank[k] < 1) fail(FST_E_INVAL, "model: ranks must be >= 1");
+    if (degree[k] < 0) fail(FST_E_INVAL, "model: degrees must be >= 0");
+    if (rank[k] > kMaxRank) fail(FST_E_UNSUPPORTED, "model: rank above 32 is not supported");
+    if (degree[k] + 1 > kMaxBasis) fail(FST_E_UNSUPPORTED, "model: degree above 31 is not supported");
+  }
+  fst_model* m = new fst_model();
+  for (int k = 0; k < 3; ++k) {
+    m->lo[k] = lo[k];
+    m->hi[k] = hi[k];
+    m->rank[k] = rank[k];
+    m->degree[k] = degree[k];
+    m->coef[k].assign((size_t)(degree[k] + 1) * rank[k], 0.0);
+  }
+  m->core.assign((size_t)m->R(), 0.0);
+  return m;
+}
+
+void check_model(const fst_model* m) {
+  if (!m) fail(FST_E_INVAL, "null model");
+}
+
+template <class T>
+static void pack_model(const fst_model* m, std::vector<T>& coefs, std::vector<T>& core) {
+  coefs.assign((size_t)3 * kMaxBasis * kMaxRank, T(0));
+  for (int k = 0; k < 3; ++k) {
+    const int n = m->degree[k] + 1, r = m->rank[k];
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < r; ++j)
+        coefs[(size_t)(k * kMaxBasis + i) * kMaxRank + j] = (T)m->coef[k][(size_t)i * r + j];
+  }
+  core.resize(m->core.size());
+  for (size_t i = 0; i < core.size(); ++i) core[i] = (T)m->core[i];
+}
+
+const DeviceModel& device_model(const fst_model* m, int dtype) {
+  int dev = current_device();
+  std::lock_guard<std::mutex> lk(m->mu);
+  auto key = std::make_pair(dev, dtype);
+  auto it = m->dev.find(key);
+  if (it != m->dev.end()) return it->second;
+  DeviceModel dm;
+  if (dtype == FST_F64) {
+    std::vector<double> c, a;
+    pack_model(m, c, a);
+    dm.coefs = device_alloc(c.size() * sizeof(double));
+    dm.core = device_alloc(a.size() * sizeof(double));
+    copy_h2d(dm.coefs, c.data(), c.size() * sizeof(double), nullptr);
+    copy_h2d(dm.core, a.data(), a.size() * sizeof(double), nullptr);
+  } else {
+    std::vector<float> c, a;
+    pack_model(m, c, a);
+    dm.coefs = device_alloc(c.size() * sizeof(float));
+    dm.core = device_alloc(a.size() * sizeof(float));
+    copy_h2d(dm.coefs, c.data(), c.size() * sizeof(float), nullptr);
+    copy_h2d(dm.core, a.data(), a.size() * sizeof(float), nullptr);
+  }
+  stream_sync(nullptr);
+  return m->dev.emplace(key, dm).first->second;
+}
+
+}  // namespace fst
+
+// ------------------------------------------------------------------------------ serialisation
+// Layout (little endian):
+//   "FSTM" | u32 version=1 | u32 d=3 | f64 lo[3] | f64 hi[3] | i32 rank[3] | i32 degree[3]
+//   | f64 core[R] | per mode: i32 nnz, i32 colptr[r+1], u8 row[nnz], f64 val[nnz]
+//   | u64 FNV-1a checksum of all preceding bytes
+namespace {
+struct Writer {
+  std::vector<unsigned char> b;
+  template <class T> void put(const T& v) {
+    const unsigned char* p = reinterpret_cast<const unsigned char*>(&v);
+    b.insert(b.end(), p, p + sizeof(T));
+  }
+};
+struct Reader {
+  const unsigned char* p;
+  size_t n, off = 0;
+  template <class T> T get() {
+    if (off + sizeof(T) > n) fst::fail(FST_E_FORMAT, "model buffer is truncated");
+    T v;
+    std::memcpy(&v, p + off, sizeof(T));
+    off += sizeof(T);
+    return v;
+  }
+};
+uint64_t fnv1a(const unsigned char* p, size_t n) {
+  uint64_t h = 1469598103934665603ull;
+  for (size_t i = 0; i < n; ++i) {
+    h ^= p[i];
+    h *= 1099511628211ull;
+  }
+  return h;
+}
+std::vector<unsigned char> serialise(const fst_model* m) {
+  Writer w;
+  w.b.insert(w.b.end(), {'F', 'S', 'T', 'M'});
+  w.put<uint32_t>(1);
+  w.put<uint32_t>(3);
+  for (int k = 0; k < 3; ++k) w.put<double>(m->lo[k]);
+  for (int k = 0; k < 3; ++k) w.put<double>(m->hi[k]);
+  for (int k = 0; k < 3; ++k) w.put<int32_t>(m->rank[k]);
+  for (int k = 0; k < 3; ++k) w.put<int32_t>(m->degree[k]);
+  for (double c : m->core) w.put<double>(c);
+  for (int k = 0; k < 3; ++k) {
+    const int n = m->degree[k] + 1, r = m->rank[k];
+    std::vector<int32_t> colptr(1, 0);
+    std::vector<uint8_t> rows;
+    std::vector<double> vals;
+    for (int j = 0; j < r; ++j) {
+      for (int i = 0; i < n; ++i) {
+        double v = m->coef[k][(size_t)i * r + j];
+        if (v != 0.0) {
+          rows.push_back((uint8_t)i);
+          vals.push_back(v);
+        }
+      }
+      colptr.push_back((int32_t)rows.size());
+    }
+    w.put<int32_t>((int32_t)rows.size());
+    for (int32_t c : colptr) w.put<int32_t>(c);
+    for (uint8_t rr : rows) w.put<uint8_t>(rr);
+    for (double v : vals) w.put<double>(v);
+  }
+  w.put<uint64_t>(fnv1a(w.b.data(), w.b.size()));
+  return w.b;
+}
+}  // namespace
+
+extern "C" {
+
+fst_status fst_model_save(const fst_model* m, void* buf, size_t* nbytes) {
+  try {
+    fst::check_model(m);
+    if (!nbytes) fst::fail(FST_E_INVAL, "nbytes is null");
+    std::vector<unsigned char> b = serialise(m);
+    if (!buf) {
+      *nbytes = b.size();
+      return FST_OK;
+    }
+    if (*nbytes < b.size()) fst::fail(FST_E_INVAL, "buffer too small for the model");
+    std::memcpy(buf, b.data(), b.size());
+    *nbytes = b.size();
+    return FST_OK;
+  } catch (const fst::Error& e) {
+    fst::set_last_error(e.what());
+    return e.code;
+  } catch (const std::exception& e) {
+    fst::set_last_error(e.what());
+    return FST_E_NOMEM;
+  }
+}
+
+fst_status fst_model_load(const void* buf, size_t nbytes, fst_model** out) {
+  fst_model* m = nullptr;
+  try {
+    if (!buf || !out) fst::fail(FST_E_INVAL, "null argument");
+    const unsigned char* p = static_cast<const unsigned char*>(buf);
+    if (nbytes < 4 + 8 || std::memcmp(p, "FSTM", 4) != 0) fst::fail(FST_E_FORMAT, "not a model buffer");
+    if (nbytes < 8 + 4) fst::fail(FST_E_FORMAT, "model buffer is truncated");
+    uint64_t stored;
+    Reader r{p, nbytes, 4};
+    uint32_t version = r.get<uint32_t>();
+    uint32_t d = r.get<uint32_t>();
+    if (version != 1) fst::fail(FST_E_FORMAT, "unknown model version");
+    if (d != 3) fst::fail(FST_E_UNSUPPORTED, "only d = 3 models are supported");
+    double lo[3], hi[3];
+    int32_t rank[3], degree[3];
+    for (int k = 0; k < 3; ++k) lo[k] = r.get<double>();
+    for (int k = 0; k < 3; ++k) hi[k] = r.get<double>();
+    for (int k = 0; k < 3; ++k) rank[k] = r.get<int32_t>();
+    for (int k = 0; k < 3; ++k) degree[k] = r.get<int32_t>();
+    for (int k = 0; k < 3; ++k)
+      if (rank[k] < 1 || rank[k] > fst::kMaxRank || degree[k] < 0 || degree[k] + 1 > fst::kMaxBasis)
+        fst::fail(FST_E_FORMAT, "model header out of range");
+    m = fst::model_new(lo, hi, rank, degree);
+    for (auto& c : m->core) c = r.get<double>();
+    for (int k = 0; k < 3; ++k) {
+      const int n = degree[k] + 1, rk = rank[k];
+      int32_t nnz = r.get<int32_t>();
+      if (nnz < 0 || nnz > n * rk) fst::fail(FST_E_FORMAT, "bad coefficient count");
+      std::vector<int32_t> colptr((size_t)rk + 1);
+      for (auto& c : colptr) c = r.get<int32_t>();
+      if (colptr[0] != 0 || colptr[(size_t)rk] != nnz) fst::fail(FST_E_FORMAT, "bad column pointers");
+      for (int j = 0; j < rk; ++j)
+        if (colptr[(size_t)j + 1] < colptr[(size_t)j]) fst::fail(FST_E_FORMAT, "bad column pointers");
+      std::vector<uint8_t> rows((size_t)nnz);
+      for (auto& x : rows) x = r.get<uint8_t>();
+      for (int j = 0; j < rk; ++j)
+        for (int32_t s = colptr[(size_t)j]; s < colptr[(size_t)j + 1]; ++s) {
+          if (rows[(size_t)s] >= n) fst::fail(FST_E_FORMAT, "coefficient row out of range");
+          m->coef[k][(size_t)rows[(size_t)s] * rk + j] = 0.0;  // placeholder, value below
+        }
+      std::vector<double> vals((size_t)nnz);
+      for (auto& x : vals) x = r.get<double>();
+      for (int j = 0; j < rk; ++j)
+        for (int32_t s = colptr[(size_t)j]; s < colptr[(size_t)j + 1]; ++s)
+          m->coef[k][(size_t)rows[(size_t)s] * rk + j] = vals[(size_t)s];
+    }
+    size_t body = r.off;
+    stored = r.get<uint64_t>();
+    if (stored != fnv1a(p, body)) fst::fail(FST_E_FORMAT, "model checksum mismatch");
+    *out = m;
+    return FST_OK;
+  } catch (const fst::Error& e) {
+    delete m;
+    fst::set_last_error(e.what());
+    return e.code;
+  } catch (const std::exception& e) {
+    delete m;
+    fst::set_last_error(e.what());
+    return FST_E_NOMEM;
+  }
+}
+
+}  // extern "C"

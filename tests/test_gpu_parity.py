@@ -1,0 +1,260 @@
+"""GPU parity of every hot-path step against the FP64 oracle, through the C ABI.
+
+Tolerances (relative L2 over the compared vector): FP64 paths 1e-10; FP32 paths 1e-5 for
+factor values, Gram entries and reconstructed values.  The FP32 core is compared with a
+bound that scales with the conditioning of the sampled Gram (perturbation bound
+||d alpha|| / ||alpha|| <= kappa(G) ||dG|| / ||G||, with ||dG|| / ||G|| ~ 1e-7 for FP32 rows).
+FP32 inputs are compared against the oracle evaluated at the same float32 numbers up-cast
+exactly to float64, so the comparison measures kernel arithmetic only.
+"""
+import numpy as np
+import pytest
+
+import datagen
+from oracle import lsq, pipeline, reconstruct
+from oracle.model import Model as OModel
+from oracle.reconstruct import rel_l2
+from oracle.sampler import STREAM_LS, sample_without_replacement
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+fst = pytest.importorskip("paper_1907_05884_amd.binding")
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def D(a, dev):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+
+def H(t):
+    return t.detach().cpu().numpy()
+
+
+def _pts(seed, n, lo=(-1, -1, -1), hi=(1, 1, 1), dtype=np.float64):
+    rng = np.random.default_rng(seed)
+    lo, hi = np.asarray(lo, float), np.asarray(hi, float)
+    return (lo + (hi - lo) * rng.random((n, 3))).astype(dtype)
+
+
+def _models(seed, rank, degree, lo=(-1, -1, -1), hi=(1, 1, 1)):
+    core, coefs = datagen.random_model_parts(seed, rank, degree)
+    om = OModel(tuple(lo), tuple(hi), tuple(rank), tuple(degree), core, coefs)
+    gm = fst.fst_model_from_parts(lo, hi, rank, degree, core, coefs)
+    return om, gm
+
+
+def _soa(p, dev):
+    return [D(np.ascontiguousarray(p[:, k]), dev) for k in range(3)]
+
+
+# ------------------------------------------------------------------------------ factor values
+@pytest.mark.parametrize("dtype,rank,degree,n,m,tol", [
+    (np.float64, (5, 7, 3), (9, 12, 6), 3001, 1337, 1e-10),
+    (np.float64, (8, 8, 8), (15, 15, 15), 20000, 2000, 1e-10),
+    (np.float32, (24, 24, 24), (31, 31, 31), 50001, 20011, 1e-5),
+    (np.float32, (32, 4, 17), (31, 15, 20), 9000, 9000, 1e-5),
+])
+def test_factor_eval_parity(dev, dtype, rank, degree, n, m, tol):
+    om, gm = _models(1, rank, degree, lo=(0, 0, 0), hi=(4, 1, 1))
+    pts = _pts(2, n, (0, 0, 0), (4, 1, 1), dtype)
+    v = np.random.default_rng(3).standard_normal(n).astype(dtype)
+    idx = np.sort(np.random.default_rng(4).choice(n, m, replace=False)).astype(np.int32)
+    x, y, z = _soa(pts, dev)
+    U, vs = fst.fst_factor_eval(gm, x, y, z, D(v, dev), D(idx, dev))
+    ref = lsq.factor_values(om, pts[idx].astype(np.float64))
+    Uh = H(U)
+    off = 0
+    for k in range(3):
+        assert rel_l2(Uh[off:off + rank[k]].T, ref[k]) <= tol
+        off += rank[k]
+    np.testing.assert_array_equal(H(vs), v[idx])
+
+
+# ------------------------------------------------------------------------------ Gram and A^T v
+def _gram_case(dev, dtype, rank, degree, m, seed=5):
+    om, gm = _models(seed, rank, degree)
+    pts = _pts(seed + 1, m, dtype=dtype)
+    v = np.random.default_rng(seed + 2).standard_normal(m).astype(dtype)
+    x, y, z = _soa(pts, dev)
+    U, vs = fst.fst_factor_eval(gm, x, y, z, D(v, dev))
+    G, h = fst.fst_gram(gm, U, vs)
+    Gr, hr = lsq.normal_equations(om, pts.astype(np.float64), v.astype(np.float64))
+    return H(G), H(h), Gr, hr
+
+
+@pytest.mark.parametrize("rank,degree,m", [((5, 7, 3), (9, 12, 6), 777), ((8, 8, 8), (15, 15, 15), 2037),
+                                           ((9, 10, 11), (13, 9, 11), 3001), ((1, 1, 1), (0, 3, 2), 50)])
+def test_gram_fp64_parity(dev, rank, degree, m):
+    G, h, Gr, hr = _gram_case(dev, np.float64, rank, degree, m)
+    low = np.tril_indices(Gr.shape[0])
+    assert rel_l2(G[low], Gr[low]) <= 1e-10
+    assert rel_l2(h, hr) <= 1e-10
+
+
+@pytest.mark.parametrize("rank,degree,m", [((12, 11, 10), (20, 20, 20), 20013), ((6, 6, 6), (31, 31, 31), 4099)])
+def test_gram_fp32_parity(dev, rank, degree, m):
+    G, h, Gr, hr = _gram_case(dev, np.float32, rank, degree, m)
+    low = np.tril_indices(Gr.shape[0])
+    assert rel_l2(G[low], Gr[low]) <= 1e-5
+    assert rel_l2(h, hr) <= 1e-5
+
+
+def test_gram_kronecker_closed_form(dev):
+    from oracle.interp import grid_nodes, grid_points
+    from oracle.basis import legendre_orthonormal
+    rank, degree, grid = (3, 4, 2), (6, 5, 7), (5, 6, 7)
+    om, gm = _models(8, rank, degree)
+    pts = grid_points(grid)
+    x, y, z = _soa(pts, dev)
+    U, _ = fst.fst_factor_eval(gm, x, y, z)
+    G, _ = fst.fst_gram(gm, U)
+    Uk = [legendre_orthonormal(grid_nodes(I), degree[k]) @ om.coefs[k] for k, I in enumerate(grid)]
+    K = np.kron(np.kron(Uk[0].T @ Uk[0], Uk[1].T @ Uk[1]), Uk[2].T @ Uk[2])
+    low = np.tril_indices(K.shape[0])
+    assert rel_l2(H(G)[low], K[low]) <= 1e-12
+
+
+def test_gram_is_deterministic(dev):
+    om, gm = _models(9, (10, 9, 8), (15, 15, 15))
+    pts = _pts(10, 30000, dtype=np.float32)
+    x, y, z = _soa(pts, dev)
+    U, _ = fst.fst_factor_eval(gm, x, y, z)
+    G1, _ = fst.fst_gram(gm, U)
+    G2, _ = fst.fst_gram(gm, U)
+    assert torch.equal(G1, G2)
+
+
+# ------------------------------------------------------------------------------ Cholesky + solve
+@pytest.mark.parametrize("R", [1, 64, 333, 1000])
+def test_cholesky_and_solve(dev, R):
+    rng = np.random.default_rng(R)
+    B = rng.standard_normal((R, R))
+    A = B @ B.T / R + np.eye(R)
+    b = rng.standard_normal(R)
+    G = D(A.copy(), dev)
+    assert fst.fst_cholesky(G) == 0
+    L = np.tril(H(G))
+    assert rel_l2(L, np.linalg.cholesky(A)) <= 1e-12
+    x = fst.fst_cholesky_solve(G, D(b, dev))
+    assert rel_l2(H(x), np.linalg.solve(A, b)) <= 1e-10
+
+
+def test_cholesky_reports_non_spd_pivot(dev):
+    R = 200
+    A = np.eye(R)
+    A[137, 137] = -1.0
+    with pytest.raises(fst.FstError) as e:
+        fst.fst_cholesky(D(A, dev))
+    assert e.value.status == fst.FST_E_NOT_SPD
+    assert "info=138" in str(e.value)
+
+
+# ------------------------------------------------------------------------------ reconstruction
+@pytest.mark.parametrize("dtype,rank,degree,n,tol", [
+    (np.float64, (8, 8, 8), (15, 15, 15), 20001, 1e-10),
+    (np.float64, (5, 7, 3), (9, 12, 6), 4097, 1e-10),
+    (np.float64, (24, 24, 24), (31, 31, 31), 3000, 1e-10),
+    (np.float32, (24, 24, 24), (31, 31, 31), 100003, 1e-5),
+    (np.float32, (32, 32, 32), (31, 31, 31), 5000, 1e-5),
+    (np.float32, (4, 20, 9), (15, 31, 22), 777, 1e-5),
+    (np.float32, (1, 1, 1), (0, 0, 0), 1, 1e-6),
+])
+def test_eval_parity(dev, dtype, rank, degree, n, tol):
+    om, gm = _models(11, rank, degree, lo=(0, 0, 0), hi=(4, 1, 1))
+    pts = _pts(12, n, (0, 0, 0), (4, 1, 1), dtype)
+    x, y, z = _soa(pts, dev)
+    f = fst.fst_eval(gm, x, y, z)
+    ref = reconstruct.evaluate(om, pts.astype(np.float64))
+    assert rel_l2(H(f), ref) <= tol
+
+
+def test_eval_empty(dev):
+    _, gm = _models(1, (2, 2, 2), (3, 3, 3))
+    e = torch.empty(0, dtype=torch.float32, device=dev)
+    assert fst.fst_eval(gm, e, e, e).numel() == 0
+
+
+# ------------------------------------------------------------------------------ FP64 residual
+def test_residual_fp64_parity(dev):
+    om, gm = _models(13, (6, 5, 4), (10, 10, 10))
+    n, m = 5000, 1200
+    pts = _pts(14, n, dtype=np.float32)
+    v = np.random.default_rng(15).standard_normal(n).astype(np.float32)
+    idx = np.sort(np.random.default_rng(16).choice(n, m, replace=False)).astype(np.int32)
+    alpha = np.random.default_rng(17).standard_normal(om.R)
+    x, y, z = _soa(pts, dev)
+    r = fst.fst_residual(gm, x, y, z, D(v, dev), D(idx, dev), D(alpha, dev))
+    ref = lsq.residual_normal(om, pts[idx].astype(np.float64), v[idx].astype(np.float64), alpha)
+    assert rel_l2(H(r), ref) <= 1e-10
+
+
+# ------------------------------------------------------------------------------ Algorithm 2 end to end
+def _small_workload_model():
+    w = datagen.small_f64()
+    m0 = pipeline.compress(w.pts, w.vals, w.lo, w.hi, w.grid, w.rank, w.degree, w.interp_fraction, w.seed)
+    return w, m0
+
+
+def test_refit_core_fp64_matches_oracle(dev):
+    w, m0 = _small_workload_model()
+    alpha_o, idx, G, h = lsq.refit_core(m0, w.pts, w.vals, w.n_samples, w.seed)
+    gm = fst.fst_model_from_parts(w.lo, w.hi, w.rank, w.degree, m0.core, m0.coefs)
+    x, y, z, v = [D(a, dev) for a in w.soa()]
+    out = fst.fst_refit_core(gm, x, y, z, v, w.n_samples, w.seed)
+    assert rel_l2(out.core, alpha_o) <= 1e-10
+    f = fst.fst_eval(out, x, y, z)
+    ref = reconstruct.evaluate(m0.with_core(alpha_o), w.pts)
+    assert rel_l2(H(f), ref) <= 1e-10
+
+
+def test_fit_end_to_end_fp64(dev):
+    w = datagen.small_f64()
+    mo = pipeline.fit(w.pts, w.vals, w.lo, w.hi, w.grid, w.rank, w.degree, w.interp_fraction,
+                      w.n_samples, w.seed)
+    p = fst.make_params(dtype=fst.FST_F64, lo=w.lo, hi=w.hi, grid=w.grid, rank=w.rank, degree=w.degree,
+                        interp_fraction=w.interp_fraction, n_samples=w.n_samples, seed=w.seed)
+    x, y, z, v = [D(a, dev) for a in w.soa()]
+    gm = fst.fst_fit(p, x, y, z, v)
+    for k in range(3):
+        np.testing.assert_array_equal(gm.coefs(k) != 0, mo.coefs[k] != 0)
+        assert rel_l2(gm.coefs(k), mo.coefs[k]) <= 1e-7
+    assert rel_l2(gm.core, mo.core) <= 1e-6
+    f = H(fst.fst_eval(gm, x, y, z))
+    err_gpu, err_ref = rel_l2(f, w.vals), rel_l2(reconstruct.evaluate(mo, w.pts), w.vals)
+    assert abs(err_gpu - err_ref) <= 1e-8 * err_ref + 1e-12
+
+
+def test_refit_rejects_too_few_samples_and_duplicates(dev):
+    om, gm = _models(20, (4, 4, 4), (6, 6, 6))
+    pts = _pts(21, 500)
+    x, y, z = _soa(pts, dev)
+    v = D(np.zeros(500), dev)
+    with pytest.raises(fst.FstError) as e:
+        fst.fst_refit_core(gm, x, y, z, v, 64, 1)
+    assert e.value.status == fst.FST_E_INVAL
+    # every point identical: the sampled design has rank one, Cholesky must break down
+    same = [D(np.full(500, 0.3), dev) for _ in range(3)]
+    with pytest.raises(fst.FstError) as e:
+        fst.fst_refit_core(gm, *same, v, 200, 1)
+    assert e.value.status == fst.FST_E_NOT_SPD
+
+
+def test_refit_exact_recovery_fp32(dev):
+    # a field that lies in the model span: the sampled LS must return the planted core
+    om, gm = _models(22, (10, 9, 8), (15, 15, 15))
+    n, M = 60000, 6000
+    pts = _pts(23, n, dtype=np.float32)
+    idx = sample_without_replacement(7, STREAM_LS, n, M)
+    v = np.zeros(n, dtype=np.float64)
+    v[idx] = reconstruct.evaluate(om, pts[idx].astype(np.float64))
+    x, y, z = _soa(pts, dev)
+    out = fst.fst_refit_core(gm, x, y, z, D(v.astype(np.float32), dev), M, 7)
+    G, _ = lsq.normal_equations(om, pts[idx].astype(np.float64), v[idx])
+    kappa = np.linalg.cond(G)
+    assert rel_l2(out.core, om.core) <= max(1e-5, 1e-6 * kappa)

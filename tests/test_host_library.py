@@ -1,0 +1,178 @@
+"""CPU tests of the C-ABI library: every declared symbol is exported, the host steps of
+Algorithm 1 match the oracle, models round-trip through serialisation, and bad arguments
+are rejected with the documented status codes.  No GPU is touched."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import datagen
+from oracle import interp, pipeline, sampler, sparsefit, sthosvd
+from oracle.basis import legendre_orthonormal
+from oracle.model import Model as OModel
+
+fst = pytest.importorskip("paper_1907_05884_amd.binding")
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_symbols():
+    src = open(os.path.join(ROOT, "include", "fst.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(fst_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_every_declared_symbol_is_exported_and_bound():
+    lib = ctypes.CDLL(fst.LIB_PATH)
+    declared = _declared_symbols()
+    assert len(declared) >= 25
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert set(declared) == set(fst.EXPORTED_SYMBOLS)
+
+
+def test_params_struct_layout_matches():
+    p = fst.make_params()
+    assert p.struct_size == ctypes.sizeof(fst.fst_fit_params)
+    assert fst.fst_version().startswith("fst-mi355x")
+
+
+@pytest.mark.parametrize("seed,stream,n,m", [(1, 2, 2000, 500), (7, 1, 100000, 5000), (3, 2, 17, 17), (3, 2, 5, 0)])
+def test_sampler_bit_exact_with_oracle(seed, stream, n, m):
+    np.testing.assert_array_equal(fst.fst_sample_indices(seed, stream, n, m),
+                                  sampler.sample_without_replacement(seed, stream, n, m))
+
+
+def test_idw_matches_oracle():
+    rng = np.random.default_rng(0)
+    xi = rng.uniform(-1, 1, (3000, 3))
+    v = rng.standard_normal(3000)
+    grid = (9, 12, 7)
+    ref = interp.idw_to_grid(xi, v, grid)
+    got = fst.fst_idw_grid(xi, v, grid, k=8, power=2.0)
+    np.testing.assert_allclose(got, ref, rtol=1e-12, atol=1e-13)
+    # exact hit on a grid node takes the point's value
+    xi2 = np.vstack([xi, interp.grid_points(grid)[[5]]])
+    v2 = np.concatenate([v, [42.0]])
+    assert fst.fst_idw_grid(xi2, v2, grid).reshape(-1)[5] == 42.0
+    # fewer points than neighbours, and a different power
+    np.testing.assert_allclose(fst.fst_idw_grid(xi[:5], v[:5], (4, 4, 4), k=8, power=3.0),
+                               interp.idw_to_grid(xi[:5], v[:5], (4, 4, 4), k=8, power=3.0),
+                               rtol=1e-12, atol=1e-13)
+
+
+@pytest.mark.parametrize("dims,rank", [((12, 10, 9), (4, 3, 2)), ((20, 6, 7), (5, 6, 7)), ((16, 16, 16), (3, 3, 3))])
+def test_sthosvd_matches_oracle(dims, rank):
+    rng = np.random.default_rng(sum(dims))
+    T = rng.standard_normal(dims)
+    core_o, W_o, s_o = sthosvd.st_hosvd(T, rank)
+    core, W, S = fst.fst_sthosvd(T, rank)
+    for k in range(3):
+        np.testing.assert_allclose(W[k], W_o[k], atol=1e-10)
+        np.testing.assert_allclose(S[k][: len(s_o[k])], s_o[k], rtol=1e-11, atol=1e-12)
+    np.testing.assert_allclose(core, core_o, atol=1e-10)
+
+
+def test_sthosvd_exact_low_rank_recovery():
+    rng = np.random.default_rng(9)
+    r = (3, 4, 2)
+    G = rng.standard_normal(r)
+    Q = [np.linalg.qr(rng.standard_normal((n, k)))[0] for n, k in zip((14, 11, 10), r)]
+    X = sthosvd.tucker_full(G, Q)
+    core, W, _ = fst.fst_sthosvd(X, r)
+    assert np.linalg.norm(sthosvd.tucker_full(core, W) - X) / np.linalg.norm(X) < 1e-13
+
+
+def test_sparse_fit_matches_oracle():
+    nodes = interp.grid_nodes(32)
+    rng = np.random.default_rng(1)
+    Phi = legendre_orthonormal(nodes, 15)
+    c = np.zeros((16, 4))
+    c[[0, 3, 7], 0] = [1.0, -0.5, 0.25]
+    c[[2], 1] = [2.0]
+    W = Phi @ c
+    W[:, 2] = np.sin(3 * nodes)
+    W[:, 3] = np.exp(-nodes ** 2) + 1e-3 * rng.standard_normal(32)
+    ref = sparsefit.fit_factor(W, nodes, 15)
+    got = fst.fst_sparse_fit(W, 15)
+    np.testing.assert_array_equal(got != 0, ref != 0)      # identical supports
+    np.testing.assert_allclose(got, ref, rtol=1e-9, atol=1e-12)
+    np.testing.assert_allclose(got[:, :2], c[:, :2], atol=1e-12)
+
+
+def test_compress_host_matches_oracle_small():
+    w = datagen.small_f64(n=6000, n_samples=1500)
+    p = fst.make_params(dtype=fst.FST_F64, lo=w.lo, hi=w.hi, grid=(16, 16, 16), rank=(5, 4, 3),
+                        degree=(9, 9, 9), interp_fraction=0.2, n_samples=1500, seed=w.seed)
+    x, y, z, v = w.soa()
+    m = fst.fst_compress_host(p, x, y, z, v)
+    mo = pipeline.compress(w.pts, w.vals, w.lo, w.hi, (16, 16, 16), (5, 4, 3), (9, 9, 9), 0.2, w.seed)
+    np.testing.assert_allclose(m.core, mo.core, rtol=1e-8, atol=1e-9)
+    for k in range(3):
+        Ck, Co = m.coefs(k), mo.coefs[k]
+        np.testing.assert_array_equal(Ck != 0, Co != 0)
+        np.testing.assert_allclose(Ck, Co, rtol=1e-7, atol=1e-9)
+
+
+def test_model_parts_roundtrip_and_serialisation():
+    core, coefs = datagen.random_model_parts(3, (4, 3, 5), (6, 7, 5))
+    m = fst.fst_model_from_parts((0, 0, 0), (4, 1, 1), (4, 3, 5), (6, 7, 5), core, coefs)
+    np.testing.assert_array_equal(m.core, core)
+    for k in range(3):
+        np.testing.assert_array_equal(m.coefs(k), coefs[k])
+    inf = m.info()
+    assert inf["rank"] == (4, 3, 5) and inf["degree"] == (6, 7, 5) and inf["hi"] == (4.0, 1.0, 1.0)
+    om = OModel((0, 0, 0), (4, 1, 1), (4, 3, 5), (6, 7, 5), core, coefs)
+    assert m.paper_bytes() == om.paper_bytes()
+    blob = fst.fst_model_save(m)
+    m2 = fst.fst_model_load(blob)
+    np.testing.assert_array_equal(m2.core, core)
+    for k in range(3):
+        np.testing.assert_array_equal(m2.coefs(k), coefs[k])
+    assert fst.fst_model_save(m2) == blob
+    # truncated, corrupted and foreign buffers are rejected
+    for bad in (blob[:-3], blob[:20], b"XXXX" + blob[4:], blob[:40] + bytes([blob[40] ^ 1]) + blob[41:]):
+        with pytest.raises(fst.FstError) as e:
+            fst.fst_model_load(bad)
+        assert e.value.status == fst.FST_E_FORMAT
+
+
+def test_invalid_arguments_are_rejected():
+    core, coefs = datagen.random_model_parts(1, (2, 2, 2), (3, 3, 3))
+    with pytest.raises(fst.FstError) as e:
+        fst.fst_model_from_parts((0, 0, 0), (0, 1, 1), (2, 2, 2), (3, 3, 3), core, coefs)
+    assert e.value.status == fst.FST_E_INVAL
+    with pytest.raises(fst.FstError) as e:
+        fst.fst_model_from_parts((0, 0, 0), (1, 1, 1), (40, 2, 2), (3, 3, 3), np.zeros(160),
+                                 [np.zeros((4, 40)), coefs[1], coefs[2]])
+    assert e.value.status == fst.FST_E_UNSUPPORTED
+    bad = coefs[0].copy()
+    bad[0, 0] = np.nan
+    with pytest.raises(fst.FstError):
+        fst.fst_model_from_parts((0, 0, 0), (1, 1, 1), (2, 2, 2), (3, 3, 3), core, [bad, coefs[1], coefs[2]])
+    x = np.zeros(100)
+    # M <= R (Algorithm 2 needs S > R)
+    p = fst.make_params(rank=(4, 4, 4), grid=(8, 8, 8), degree=(3, 3, 3), n_samples=64)
+    with pytest.raises(fst.FstError) as e:
+        fst.fst_fit_workspace_bytes(p, 100)
+    assert e.value.status == fst.FST_E_INVAL
+    # rank larger than the grid, rank larger than the product of the others
+    for kw in (dict(rank=(9, 8, 8), grid=(8, 8, 8)), dict(rank=(2, 2, 5), grid=(8, 8, 8))):
+        p = fst.make_params(degree=(3, 3, 3), n_samples=90, **kw)
+        with pytest.raises(fst.FstError):
+            fst.fst_compress_host(p, x, x, x, x)
+    # non-finite data in the interpolation subset
+    p = fst.make_params(rank=(2, 2, 2), grid=(6, 6, 6), degree=(3, 3, 3), n_samples=50, interp_fraction=1.0)
+    xb = np.random.default_rng(0).uniform(-1, 1, 100)
+    vb = xb.copy()
+    vb[10] = np.inf
+    with pytest.raises(fst.FstError) as e:
+        fst.fst_compress_host(p, xb, xb, xb, vb)
+    assert e.value.status == fst.FST_E_INVAL
+    with pytest.raises(fst.FstError):
+        fst.fst_sample_indices(1, 2, 10, 11)
+    p.struct_size = 8
+    with pytest.raises(fst.FstError):
+        fst.fst_fit_workspace_bytes(p, 100)
