@@ -27,7 +27,8 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_FP32_MFMA = 157.3e12
+PEAK = {"f32": 157.3e12, "bf16": 2.5e15, "f16": 2.5e15}
+GOLDEN = os.path.join(ROOT, "tests", "golden", "large_f32_reference.npz")
 METRIC = "LS design rows/s + reconstructed points/s at stated rel-L2 vs FP64 oracle"
 
 
@@ -94,6 +95,9 @@ def main():
     ap.add_argument("--cpu-sample-rows", type=int, default=4096)
     ap.add_argument("--n", type=int, default=2_000_000)
     ap.add_argument("--samples", type=int, default=200_000)
+    ap.add_argument("--precision", choices=("f32", "bf16", "f16"), default="f32",
+                    help="Gram precision: f32 (FP32 MFMA) or the 16-bit form with FP64 refinement")
+    ap.add_argument("--refine", type=int, default=None, help="refinement steps (default 0 for f32, 3 otherwise)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -117,6 +121,18 @@ def main():
     m0 = fst.fst_compress_host(p, x_h, y_h, z_h, v_h)
     t_host = time.perf_counter() - t
     log(f"[bench] host steps (IDW {w.grid}, ST-HOSVD, OMP): {t_host:.2f} s, nnz={m0.info()['nnz']}")
+    ref = None
+    model_src = "library host steps"
+    if os.path.exists(GOLDEN) and args.n == 2_000_000 and args.samples == 200_000:
+        # run the GPU path on the oracle's model, so that the core can be compared with the
+        # oracle's FP64 core of the same sampled problem
+        ref = np.load(GOLDEN)
+        rc = [ref[f"coefs{k}"] for k in range(3)]
+        host_vs_oracle = max(float(np.abs(m0.coefs(k) - rc[k]).max()) for k in range(3))
+        m0 = fst.fst_model_from_parts(w.lo, w.hi, w.rank, w.degree, ref["core0"], rc)
+        model_src = f"oracle host steps (library host steps agree to {host_vs_oracle:.1e} max abs)"
+    refine = args.refine if args.refine is not None else (0 if args.precision == "f32" else 3)
+    gram_prec = {"f32": fst.FST_GRAM_F32, "bf16": fst.FST_GRAM_BF16, "f16": fst.FST_GRAM_F16}[args.precision]
     t = time.perf_counter()
     idx_host = fst.fst_sample_indices(w.seed, fst.FST_STREAM_LS, w.n, w.n_samples)
     t_sample = time.perf_counter() - t
@@ -132,11 +148,13 @@ def main():
     alpha = torch.empty(R, dtype=torch.float64, device=dev)
     out = torch.empty(N, dtype=torch.float32, device=dev)
     gws = torch.empty(max(fst.fst_gram_workspace_bytes(m0, M), 256), dtype=torch.uint8, device=dev)
+    rws = torch.empty(max(fst.fst_refine_workspace_bytes(m0, M), 256), dtype=torch.uint8, device=dev)
+    alpha_steps = []
     coefs = [m0.coefs(k) for k in range(3)]
     lo, hi = m0.info()["lo"], m0.info()["hi"]
     stream = torch.cuda.current_stream()
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
-    times = {"k1": [], "gram": [], "atv": [], "solve": [], "eval": []}
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(7)]
+    times = {"k1": [], "gram": [], "atv": [], "solve": [], "refine": [], "eval": []}
     gm_fit = None
 
     def step(record):
@@ -144,13 +162,19 @@ def main():
         ev[0].record(stream)
         fst.fst_factor_eval(m0, x, y, z, v, idx, U=U, vs=vs)
         ev[1].record(stream)
-        fst.fst_gram(m0, U, G=G, ws=gws)                    # the Gram kernel alone
+        fst.fst_gram(m0, U, G=G, ws=gws, gram_prec=gram_prec)   # the Gram kernel alone
         ev[2].record(stream)
-        fst.fst_gram(m0, U, vs, h=h, ws=gws, want_G=False)  # A^T v
+        fst.fst_gram(m0, U, vs, h=h, ws=gws, want_G=False)      # A^T v
         ev[3].record(stream)
         fst.fst_cholesky(G)
         fst.fst_cholesky_solve(G, h, alpha)
         ev[4].record(stream)
+        snaps = [alpha.clone()] if record else []
+        for _ in range(refine):
+            fst.fst_refine_step(m0, x, y, z, v, idx, G, alpha, ws=rws)
+            if record:
+                snaps.append(alpha.clone())
+        ev[6].record(stream)
         core = alpha.cpu().numpy()
         gm_fit = fst.fst_model_from_parts(lo, hi, m0.rank, m0.degree, core, coefs)
         t_ev = torch.cuda.Event(enable_timing=True)
@@ -163,6 +187,8 @@ def main():
             times["gram"].append(ev[1].elapsed_time(ev[2]) / 1e3)
             times["atv"].append(ev[2].elapsed_time(ev[3]) / 1e3)
             times["solve"].append(ev[3].elapsed_time(ev[4]) / 1e3)
+            times["refine"].append(ev[4].elapsed_time(ev[6]) / 1e3)
+            alpha_steps[:] = [a_.cpu().numpy() for a_ in snaps]
             times["eval"].append(t_ev.elapsed_time(ev[5]) / 1e3)
 
     for i in range(args.warmup):
@@ -181,30 +207,39 @@ def main():
     t_rows = avg["k1"] + avg["gram"] + avg["atv"]
     design_rows_per_s = M / t_rows
     points_per_s = N / avg["eval"]
-    fitcore_rows_per_s = M / (t_rows + avg["solve"])
+    fitcore_rows_per_s = M / (t_rows + avg["solve"] + avg["refine"])
     gram_flops = float(M) * R * (R + 1)
     achieved = gram_flops / avg["gram"]
+    peak = PEAK[args.precision]
     f_all = out.cpu().numpy()
     eps_data = float(np.linalg.norm(f_all - w.vals.astype(np.float64)) / np.linalg.norm(w.vals.astype(np.float64)))
 
     result = {
         "metric": METRIC, "value": design_rows_per_s, "unit": "rows/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": args.precision,
         "data": "synthetic",
         "config": {"workload": f"large_f32: N={N} FP32 points uniform in [-1,1]^3, 40 Gaussians + sinusoid + "
                                f"N(0,1e-3) noise; 5% interpolated (IDW-8) to a 128^3 grid; ranks 24^3 "
                                f"(R={R}); Legendre degree 31; M={M} sampled LS rows; reconstruct all N",
-                   "gram": "FP32 MFMA, FP64 fold", "solve": "FP64 Cholesky"},
+                   "gram": {"f32": "FP32 MFMA", "bf16": "BF16 MFMA", "f16": "FP16 MFMA (scaled)"}[args.precision]
+                           + ", FP32 accumulation folded into FP64", "solve": "FP64 Cholesky",
+                   "refine_steps": refine, "model": model_src},
         "reconstructed_points_per_s": points_per_s,
         "fitcore_rows_per_s": fitcore_rows_per_s,
         "breakdown_ms": {k: vv * 1e3 for k, vv in avg.items()},
         "host_steps_s": t_host, "host_sample_draw_s": t_sample,
         "data_rel_l2": eps_data,
-        "roofline": {"kernel": "k_gram<float>", "bound": "mfma", "achieved": achieved / 1e12,
-                     "peak": PEAK_FP32_MFMA / 1e12, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_MFMA,
+        "roofline": {"kernel": "k_gram<float>" if args.precision == "f32" else f"k_gram_lp<{args.precision}>",
+                     "bound": "mfma", "achieved": achieved / 1e12,
+                     "peak": peak / 1e12, "unit": "TFLOP/s", "frac": achieved / peak,
                      "traffic": None, "flops_per_launch": gram_flops},
     }
+    if ref is not None:
+        a_ref = ref["alpha"]
+        result["core_rel_l2_vs_oracle_per_refine_step"] = [
+            float(np.linalg.norm(a - a_ref) / np.linalg.norm(a_ref)) for a in alpha_steps]
+        result["gram_kappa_oracle"] = float(ref["eig_max"] / ref["eig_min"])
 
     if not args.no_cpu_baseline:
         # GPU results on the oracle's sample, computed outside the timed region

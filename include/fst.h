@@ -174,6 +174,16 @@ fst_status fst_residual(const fst_model* m, int32_t dtype, int64_t n, const void
                         int64_t mrows, const double* alpha, double* r, void* ws,
                         size_t ws_bytes, void* stream);
 
+/* One step of iterative refinement of the sampled least-squares core: r = A^T (v_S - A alpha)
+ * with FP64 rows (as fst_residual), delta = (L L^T)^-1 r with L from fst_cholesky (device
+ * FP64 R x R), alpha += delta.  alpha: device FP64 R, updated in place; r_out (may be NULL):
+ * device FP64 R receiving delta.  ws >= fst_refine_workspace_bytes.  Asynchronous. */
+size_t fst_refine_workspace_bytes(const fst_model* m, int64_t mrows);
+fst_status fst_refine_step(const fst_model* m, int32_t dtype, int64_t n, const void* x,
+                           const void* y, const void* z, const void* v, const int32_t* idx,
+                           int64_t mrows, const double* L, double* alpha, double* r_out,
+                           void* ws, size_t ws_bytes, void* stream);
+
 /* ------------------------------------------------------------------ host steps */
 
 /* M distinct indices of [0, n), sorted ascending, from a partial Fisher-Yates shuffle driven

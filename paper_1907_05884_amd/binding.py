@@ -77,6 +77,8 @@ _lib_fns = dict(
     fst_cholesky_solve=(_i32, _i64, _vp, _vp, _vp, _vp),
     fst_residual_workspace_bytes=(C.c_size_t, _vp, _i64),
     fst_residual=(_i32, _vp, _i32, _i64, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp, C.c_size_t, _vp),
+    fst_refine_workspace_bytes=(C.c_size_t, _vp, _i64),
+    fst_refine_step=(_i32, _vp, _i32, _i64, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp, _vp, C.c_size_t, _vp),
     fst_sample_indices=(_i32, C.c_uint64, _i32, _i64, _i64, _vp),
     fst_idw_grid=(_i32, _vp, _vp, _i64, _vp, _i32, C.c_double, _i32, _vp),
     fst_sthosvd=(_i32, _vp, _vp, _vp, _i32, _vp, _vp, _vp),
@@ -389,6 +391,21 @@ def fst_residual(m: Model, x, y, z, v, idx, alpha, r=None, stream=None):
                                _dev_ptr(v), _dev_ptr(idx), mrows, _dev_ptr(alpha), _dev_ptr(r),
                                _dev_ptr(ws), ws.numel(), _stream(stream)))
     return r
+
+
+def fst_refine_step(m: Model, x, y, z, v, idx, L, alpha, r_out=None, ws=None, stream=None):
+    """One FP64-residual refinement step of the core (alpha updated in place)."""
+    mrows = idx.numel()
+    if ws is None:
+        ws = _workspace(int(_fn["fst_refine_workspace_bytes"](m.handle, mrows)), x.device)
+    _check(_fn["fst_refine_step"](m.handle, _dtype_code(x), x.numel(), _dev_ptr(x), _dev_ptr(y), _dev_ptr(z),
+                                  _dev_ptr(v), _dev_ptr(idx), mrows, _dev_ptr(L), _dev_ptr(alpha),
+                                  _dev_ptr(r_out), _dev_ptr(ws), ws.numel(), _stream(stream)))
+    return alpha
+
+
+def fst_refine_workspace_bytes(m: Model, mrows: int) -> int:
+    return int(_fn["fst_refine_workspace_bytes"](m.handle, int(mrows)))
 
 
 # ------------------------------------------------------------------------------ host steps

@@ -383,7 +383,7 @@ fst_status fst_gram(const fst_model* m, int32_t dtype, int64_t mrows, const void
   if (mrows < 1) fail(FST_E_INVAL, "need mrows >= 1");
   if (!U || (!G && !h)) fail(FST_E_INVAL, "null argument");
   if (h && !vs) fail(FST_E_INVAL, "h requested without vs");
-  if (h && !ws) fail(FST_E_INVAL, "h needs a workspace");
+  if ((h || gram_prec == FST_GRAM_F16) && !ws) fail(FST_E_INVAL, "h and FP16 rows need a workspace");
   launch_gram(m, dtype, mrows, U, vs, gram_prec, G, h, ws, ws ? ws_bytes : 0, stream);
   return FST_OK;
   FST_CATCH
@@ -427,6 +427,31 @@ fst_status fst_residual(const fst_model* m, int32_t dtype, int64_t n, const void
   if (mrows < 1 || n < 1) fail(FST_E_INVAL, "bad sizes");
   if (!x || !y || !z || !v || !idx || !alpha || !r || !ws) fail(FST_E_INVAL, "null argument");
   residual(m, dtype, n, x, y, z, v, idx, mrows, alpha, r, ws, ws_bytes, stream);
+  return FST_OK;
+  FST_CATCH
+}
+
+size_t fst_refine_workspace_bytes(const fst_model* m, int64_t mrows) {
+  if (!m || mrows < 0) return 0;
+  return align_up(sizeof(double) * (size_t)m->R()) + residual_workspace_bytes(m, mrows);
+}
+
+fst_status fst_refine_step(const fst_model* m, int32_t dtype, int64_t n, const void* x, const void* y,
+                           const void* z, const void* v, const int32_t* idx, int64_t mrows, const double* L,
+                           double* alpha, double* r_out, void* ws, size_t ws_bytes, void* stream) {
+  FST_TRY
+  set_last_error("");
+  check_model(m);
+  check_dtype(dtype);
+  if (mrows < 1 || n < 1) fail(FST_E_INVAL, "bad sizes");
+  if (!x || !y || !z || !v || !idx || !L || !alpha || !ws) fail(FST_E_INVAL, "null argument");
+  if (ws_bytes < fst_refine_workspace_bytes(m, mrows)) fail(FST_E_NOMEM, "refine: workspace too small");
+  double* d_r = (double*)ws;
+  char* rest = (char*)ws + align_up(sizeof(double) * (size_t)m->R());
+  residual(m, dtype, n, x, y, z, v, idx, mrows, alpha, d_r, rest, ws_bytes - (size_t)(rest - (char*)ws), stream);
+  cholesky_solve(m->R(), L, d_r, d_r, stream);
+  device_axpy(m->R(), 1.0, d_r, alpha, stream);
+  if (r_out) copy_d2d(r_out, d_r, sizeof(double) * (size_t)m->R(), stream);
   return FST_OK;
   FST_CATCH
 }

@@ -97,6 +97,7 @@ void* device_alloc(size_t bytes);
 void device_free(void* p);
 void copy_h2d(void* dst, const void* src, size_t bytes, void* stream);
 void copy_d2h(void* dst, const void* src, size_t bytes, void* stream);
+void copy_d2d(void* dst, const void* src, size_t bytes, void* stream);
 
 inline size_t align_up(size_t v, size_t a = 256) { return (v + a - 1) / a * a; }
 

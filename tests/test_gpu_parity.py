@@ -258,3 +258,41 @@ def test_refit_exact_recovery_fp32(dev):
     G, _ = lsq.normal_equations(om, pts[idx].astype(np.float64), v[idx])
     kappa = np.linalg.cond(G)
     assert rel_l2(out.core, om.core) <= max(1e-5, 1e-6 * kappa)
+
+
+# ------------------------------------------------------------------------------ precision form
+@pytest.mark.parametrize("prec,u", [("bf16", 2.0 ** -8), ("f16", 2.0 ** -11)])
+def test_gram_16bit_within_rounding_bound(dev, prec, u):
+    # each design-row entry is rounded once to the 16-bit format, so every Gram entry is within
+    # ~2u * sum_q |A[q,j] A[q,j']| of the exact value (plus FP32 accumulation, far smaller)
+    code = fst.FST_GRAM_BF16 if prec == "bf16" else fst.FST_GRAM_F16
+    om, gm = _models(30, (9, 8, 7), (15, 15, 15))
+    m = 6007
+    pts = _pts(31, m, dtype=np.float32)
+    x, y, z = _soa(pts, dev)
+    U, _ = fst.fst_factor_eval(gm, x, y, z)
+    G, _ = fst.fst_gram(gm, U, gram_prec=code)
+    A = lsq.design_rows(lsq.factor_values(om, pts.astype(np.float64)))
+    Gr = A.T @ A
+    bound = np.abs(A).T @ np.abs(A)
+    low = np.tril_indices(om.R)
+    err = np.abs(H(G)[low] - Gr[low])
+    assert np.all(err <= 2.2 * u * bound[low] + 1e-12 * np.abs(Gr).max())
+    assert rel_l2(H(G)[low], Gr[low]) <= 4 * u
+
+
+@pytest.mark.parametrize("prec", [fst.FST_GRAM_BF16, fst.FST_GRAM_F16])
+def test_refit_16bit_gram_with_refinement_matches_fp64(dev, prec):
+    w, m0 = _small_workload_model()
+    n = 40000
+    wl = datagen.make_workload("lp", seed=3, n=n, n_gauss=6, grid=(32, 32, 32), rank=(8, 8, 8),
+                               degree=(15, 15, 15), interp_fraction=0.1, n_samples=4000, dtype=np.float32)
+    alpha_o, idx, G, h = lsq.refit_core(m0, wl.pts.astype(np.float64), wl.vals.astype(np.float64), 4000, 9)
+    gm = fst.fst_model_from_parts(w.lo, w.hi, w.rank, w.degree, m0.core, m0.coefs)
+    x, y, z, v = [D(a, dev) for a in wl.soa()]
+    errs = []
+    for steps in (0, 1, 3):
+        out = fst.fst_refit_core(gm, x, y, z, v, 4000, 9, gram_prec=prec, refine_steps=steps)
+        errs.append(rel_l2(out.core, alpha_o))
+    assert errs[2] <= 1e-6, errs
+    assert errs[2] < errs[0], errs
