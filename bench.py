@@ -37,7 +37,7 @@ def log(*a):
 
 
 def cpu_baseline_leg(w, lo, hi, rank, degree, core_gpu, coefs, idx_host, gpu_sample, sample_rows,
-                     budget_s=20.0):
+                     budget_s=20.0, core_oracle=None):
     """Times the FP64 oracle on a bounded sample of the workload and states the rel-L2 of
     the GPU results on that same sample."""
     from threadpoolctl import threadpool_info
@@ -75,6 +75,10 @@ def cpu_baseline_leg(w, lo, hi, rank, degree, core_gpu, coefs, idx_host, gpu_sam
         out["gram_sample"] = float(np.linalg.norm(gpu_sample["G"][low] - G[low]) / np.linalg.norm(G[low]))
         out["h_sample"] = float(np.linalg.norm(gpu_sample["h"] - h) / np.linalg.norm(h))
     out["field_sample"] = float(np.linalg.norm(gpu_sample["f"][:npts] - f_ref) / np.linalg.norm(f_ref))
+    if core_oracle is not None:
+        # the field of the oracle's own FP64 core: end-to-end rel-L2 of the GPU reconstruction
+        f_or = reconstruct.evaluate(om.with_core(core_oracle), pts64[:npts])
+        out["field_vs_oracle_core"] = float(np.linalg.norm(gpu_sample["f"][:npts] - f_or) / np.linalg.norm(f_or))
     cores = 0
     for info in threadpool_info():
         if info.get("user_api") == "blas":
@@ -251,7 +255,8 @@ def main():
         torch.cuda.synchronize()
         gpu_sample = {"G": G.cpu().numpy(), "h": h.cpu().numpy(), "f": f_all[:20000].astype(np.float64)}
         log(f"[bench] oracle leg on {S} rows ...")
-        cpu, rel = cpu_baseline_leg(w, lo, hi, m0.rank, m0.degree, gm_fit.core, coefs, idx_host, gpu_sample, S)
+        cpu, rel = cpu_baseline_leg(w, lo, hi, m0.rank, m0.degree, gm_fit.core, coefs, idx_host, gpu_sample, S,
+                                    core_oracle=None if ref is None else ref["alpha"].reshape(m0.rank))
         result["cpu_baseline"] = cpu
         result["rel_l2_vs_oracle"] = rel
     print(json.dumps(result), flush=True)

@@ -151,7 +151,9 @@ fst_status fst_gram(const fst_model* m, int32_t dtype, int64_t mrows, const void
                     size_t ws_bytes, void* stream);
 
 /* In-place FP64 Cholesky G = L L^T of a device R x R row-major matrix (lower triangle read,
- * L written there).  Synchronises `stream`; returns FST_E_NOT_SPD if a pivot is not above
+ * L written there; the strictly upper triangle of each 64 x 64 diagonal block receives the
+ * transposed strictly lower triangle of that block's inverse, used by fst_cholesky_solve;
+ * the rest of the strictly upper triangle is untouched).  Synchronises `stream`; returns FST_E_NOT_SPD if a pivot is not above
  * R * 2^-52 times its diagonal entry before the factorisation (numerically rank-deficient
  * system), with its index in *info (1-based; 0 on success; info may be NULL).
  * ws: device workspace >= fst_cholesky_workspace_bytes(R). */
@@ -159,7 +161,8 @@ size_t fst_cholesky_workspace_bytes(int64_t R);
 fst_status fst_cholesky(int64_t R, double* G, int64_t* info, void* ws, size_t ws_bytes,
                         void* stream);
 
-/* Solves L L^T x = b with L from fst_cholesky (device FP64); b and x may alias.
+/* Solves L L^T x = b with L from fst_cholesky (device FP64, including its stored
+ * diagonal-block inverses); b and x may alias.
  * Asynchronous. */
 fst_status fst_cholesky_solve(int64_t R, const double* L, const double* b, double* x,
                               void* stream);
