@@ -296,3 +296,39 @@ def test_refit_16bit_gram_with_refinement_matches_fp64(dev, prec):
         errs.append(rel_l2(out.core, alpha_o))
     assert errs[2] <= 1e-6, errs
     assert errs[2] < errs[0], errs
+
+
+# ------------------------------------------------------------------------------ full size
+GOLDEN = __import__("os").path.join(__import__("os").path.dirname(__file__), "golden", "large_f32_reference.npz")
+
+
+@pytest.mark.skipif(not __import__("os").path.exists(GOLDEN), reason="oracle reference not generated")
+def test_full_size_against_oracle_reference(dev):
+    # 2M FP32 points, ranks 24^3 (R = 13824), degree 31, M = 200,000 sampled rows: the launch
+    # configuration of the benchmark.  The reference holds the oracle's model and its FP64
+    # core of the sampled problem (tests/golden/make_large_golden.py, oracle only).
+    ref = np.load(GOLDEN)
+    w = datagen.large_f32()
+    coefs = [ref[f"coefs{k}"] for k in range(3)]
+    gm = fst.fst_model_from_parts(w.lo, w.hi, w.rank, w.degree, ref["core0"], coefs)
+    x, y, z, v = [D(a, dev) for a in w.soa()]
+    idx = D(sample_without_replacement(w.seed, STREAM_LS, w.n, w.n_samples).astype(np.int32), dev)
+    U, vs = fst.fst_factor_eval(gm, x, y, z, v, idx)
+    G, h = fst.fst_gram(gm, U, vs)
+    assert rel_l2(H(h), ref["h"]) <= 1e-5
+    assert rel_l2(np.diag(H(G)), ref["gram_diag"]) <= 1e-5
+    del G
+    torch.cuda.empty_cache()
+    alpha = ref["alpha"]
+    # FP32 rows: kappa(G) ~ 6e7 amplifies FP32 rounding in the core; three FP64-residual
+    # refinement steps bring it to the oracle's core
+    out32 = fst.fst_refit_core(gm, x, y, z, v, w.n_samples, w.seed, refine_steps=3)
+    assert rel_l2(out32.core, alpha) <= 1e-6
+    out16 = fst.fst_refit_core(gm, x, y, z, v, w.n_samples, w.seed, gram_prec=fst.FST_GRAM_F16, refine_steps=9)
+    assert rel_l2(out16.core, alpha) <= 1e-6
+    # reconstruction at sampled output points, against the oracle's field of its own core
+    om = OModel(w.lo, w.hi, w.rank, w.degree, alpha.reshape(w.rank), coefs)
+    f = H(fst.fst_eval(out32, x, y, z))
+    pick = np.random.default_rng(0).choice(w.n, 20000, replace=False)
+    fr = reconstruct.evaluate(om, w.pts[pick].astype(np.float64))
+    assert rel_l2(f[pick], fr) <= 1e-5
