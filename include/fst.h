@@ -239,6 +239,58 @@ int64_t fst_model_paper_bytes(const fst_model* m);
 fst_status fst_model_save(const fst_model* m, void* buf, size_t* nbytes);
 fst_status fst_model_load(const void* buf, size_t nbytes, fst_model** out);
 
+/* ------------------------------------------------------------------ learned residual corrector */
+/* A small network g(xi) = W3 s(W2 s(W1 xi + b1) + b2) + b3, s(z) = z / (1 + e^-z), layers
+ * 3 -> 64 -> 64 -> 1 on the reference coordinates xi of the model's box, trained by Adam on the
+ * mean squared error against the model's residual divided by its standard deviation; the
+ * corrected reconstruction is u~(x) + sd * g(xi(x)).  Not part of the paper: an optional
+ * addition judged against the plain model (which is also the fallback).  BF16 weights and
+ * activations on MFMA for the 64 x 64 layer with FP32 accumulation, FP32 master weights.
+ * Flat parameter order (4481 values): W1 (64 x 3) | b1 (64) | W2 (64 x 64, [out][in]) | b2 (64)
+ * | W3 (64) | b3 (1).  Initial weights: Xavier-uniform from SplitMix64 (state seed*256 + 4),
+ * zero biases; minibatch rows: SplitMix64 output number step*batch + i of state seed*256 + 3,
+ * bounded to [0, n) (with replacement). */
+typedef struct fst_corrector fst_corrector;   /* opaque; library-owned */
+typedef struct {
+  uint32_t struct_size;      /* sizeof(fst_train_params) */
+  int32_t  steps;            /* Adam steps (2000) */
+  int32_t  batch;            /* minibatch size (8192) */
+  double   lr, beta1, beta2, eps;   /* 1e-3, 0.9, 0.999, 1e-8 */
+  uint64_t seed;
+} fst_train_params;
+
+void fst_train_params_default(fst_train_params* tp);
+/* device workspace of fst_corrector_train for n training points */
+size_t fst_corrector_workspace_bytes(const fst_train_params* tp, int64_t n);
+/* Trains a corrector on the residual of model m at the n training points (device arrays x, y,
+ * z, v of dtype).  Synchronises `stream`. */
+fst_status fst_corrector_train(const fst_model* m, int32_t dtype, int64_t n, const void* x, const void* y,
+                               const void* z, const void* v, const fst_train_params* tp, void* ws,
+                               size_t ws_bytes, void* stream, fst_corrector** out);
+/* Builds a corrector from host FP32 parameters (4481) and output scale; lo, hi: box. */
+fst_status fst_corrector_from_params(const double lo[3], const double hi[3], const float* params,
+                                     float out_scale, fst_corrector** out);
+/* params_out: host float[4481] (stored values, BF16-rounded after training); either may be NULL */
+fst_status fst_corrector_params(const fst_corrector* c, float* params_out, float* out_scale);
+/* training loss every 50 steps: *count in = capacity of out, out = entries available */
+fst_status fst_corrector_losses(const fst_corrector* c, float* out, int32_t* count);
+void fst_corrector_free(fst_corrector* c);
+/* stored size: BF16 weights (2 bytes each) plus the FP32 output scale */
+int64_t fst_corrector_stored_bytes(const fst_corrector* c);
+/* out[i] += sd * g(xi(x[i], y[i], z[i])) for device arrays of dtype.  Asynchronous. */
+fst_status fst_corrector_apply(const fst_corrector* c, int32_t dtype, int64_t n, const void* x, const void* y,
+                               const void* z, void* out, void* stream);
+/* fst_eval followed by fst_corrector_apply (c may be NULL: plain reconstruction). */
+fst_status fst_eval_corrected(const fst_model* m, const fst_corrector* c, int32_t dtype, int64_t n,
+                              const void* x, const void* y, const void* z, void* out, void* stream);
+/* Gradient of mean((g(xi_b) - target_b)^2) over the batch rows idx (device int32[batch]) at the
+ * corrector's stored parameters: grad_out device float[4482] (4481 gradients, then the sum of
+ * squared errors).  target: device float[n].  Synchronises `stream`. */
+size_t fst_mlp_grad_workspace_bytes(int32_t batch);
+fst_status fst_mlp_grad(const fst_corrector* c, int32_t dtype, int64_t n, const void* x, const void* y,
+                        const void* z, const float* target, const int32_t* idx, int32_t batch,
+                        float* grad_out, void* ws, size_t ws_bytes, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

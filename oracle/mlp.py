@@ -86,3 +86,36 @@ class Adam:
 
 def n_params(layers=LAYERS) -> int:
     return sum(layers[l] * layers[l + 1] + layers[l + 1] for l in range(len(layers) - 1))
+
+
+PARAM_ORDER = ("W1", "b1", "W2", "b2", "W3", "b3")
+
+
+def flatten(params) -> np.ndarray:
+    """Parameters in the library's flat order: W1 (64x3), b1, W2 (64x64), b2, W3 (1x64), b3."""
+    return np.concatenate([np.asarray(params[k], np.float64).reshape(-1) for k in PARAM_ORDER])
+
+
+def unflatten(flat) -> dict:
+    flat = np.asarray(flat, np.float64)
+    shapes = {"W1": (64, 3), "b1": (64,), "W2": (64, 64), "b2": (64,), "W3": (1, 64), "b3": (1,)}
+    out, o = {}, 0
+    for k in PARAM_ORDER:
+        size = int(np.prod(shapes[k]))
+        out[k] = flat[o:o + size].reshape(shapes[k]).copy()
+        o += size
+    return out
+
+
+def train(params, xi, target, steps, batch, seed, lr=1e-3):
+    """Adam on mean squared error with minibatches drawn by sampler.batch_indices."""
+    from .sampler import batch_indices
+    params = {k: v.copy() for k, v in params.items()}
+    opt = Adam(params, lr=lr)
+    losses = []
+    for s in range(steps):
+        idx = batch_indices(seed, s, batch, xi.shape[0])
+        loss, g = loss_and_grads(params, xi[idx], target[idx])
+        params = opt.step(params, g)
+        losses.append(loss)
+    return params, losses

@@ -70,3 +70,21 @@ def sample_without_replacement(seed: int, stream: int, n: int, m: int) -> np.nda
         jt = j[t]
         a[t], a[jt] = a[jt], a[t]
     return np.sort(a[:m])
+
+
+STREAM_BATCH = 3
+
+
+def batch_indices(seed: int, step: int, batch: int, n: int) -> np.ndarray:
+    """Minibatch of the corrector's training step `step` (0-based): `batch` indices of [0, n)
+    drawn with replacement.  Index i is the bounded draw of SplitMix64 output number
+    step * batch + i of the stream seed * 256 + 3 (counter form, so any step can be drawn
+    without the previous ones)."""
+    state = stream_state(seed, STREAM_BATCH)
+    k = np.arange(step * batch, (step + 1) * batch, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        z = np.uint64(state) + (k + np.uint64(1)) * np.uint64(GAMMA)
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(M1)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(M2)
+        z = z ^ (z >> np.uint64(31))
+    return bounded(z, np.uint64(n)).astype(np.int64)

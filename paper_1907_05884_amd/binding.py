@@ -57,7 +57,14 @@ def _proto(name, res, *args):
     return f
 
 
+class fst_train_params(C.Structure):
+    _fields_ = [("struct_size", C.c_uint32), ("steps", C.c_int32), ("batch", C.c_int32),
+                ("lr", C.c_double), ("beta1", C.c_double), ("beta2", C.c_double), ("eps", C.c_double),
+                ("seed", C.c_uint64)]
+
+
 _P = C.POINTER(fst_fit_params)
+_TP = C.POINTER(fst_train_params)
 _lib_fns = dict(
     fst_last_error=(C.c_char_p,),
     fst_version=(C.c_char_p,),
@@ -91,6 +98,18 @@ _lib_fns = dict(
     fst_model_paper_bytes=(_i64, _vp),
     fst_model_save=(_i32, _vp, _vp, C.POINTER(C.c_size_t)),
     fst_model_load=(_i32, _vp, C.c_size_t, C.POINTER(_vp)),
+    fst_train_params_default=(None, _TP),
+    fst_corrector_workspace_bytes=(C.c_size_t, _TP, _i64),
+    fst_corrector_train=(_i32, _vp, _i32, _i64, _vp, _vp, _vp, _vp, _TP, _vp, C.c_size_t, _vp, C.POINTER(_vp)),
+    fst_corrector_from_params=(_i32, _vp, _vp, _vp, C.c_float, C.POINTER(_vp)),
+    fst_corrector_params=(_i32, _vp, _vp, _vp),
+    fst_corrector_losses=(_i32, _vp, _vp, C.POINTER(_i32)),
+    fst_corrector_free=(None, _vp),
+    fst_corrector_stored_bytes=(_i64, _vp),
+    fst_corrector_apply=(_i32, _vp, _i32, _i64, _vp, _vp, _vp, _vp, _vp),
+    fst_eval_corrected=(_i32, _vp, _vp, _i32, _i64, _vp, _vp, _vp, _vp, _vp),
+    fst_mlp_grad_workspace_bytes=(C.c_size_t, _i32),
+    fst_mlp_grad=(_i32, _vp, _i32, _i64, _vp, _vp, _vp, _vp, _vp, _i32, _vp, _vp, C.c_size_t, _vp),
 )
 _fn = {name: _proto(name, spec[0], *spec[1:]) for name, spec in _lib_fns.items()}
 EXPORTED_SYMBOLS = tuple(_lib_fns)
@@ -446,3 +465,101 @@ def fst_sparse_fit(W, p: int) -> np.ndarray:
     out = np.empty((int(p) + 1, r), dtype=np.float64)
     _check(_fn["fst_sparse_fit"](W_p, int(I), int(r), int(p), out.ctypes.data_as(C.c_void_p)))
     return out
+
+
+# ------------------------------------------------------------------------------ corrector
+MLP_PARAMS = 4481
+
+
+class Corrector:
+    """Owns an fst_corrector handle."""
+
+    def __init__(self, handle):
+        self._h = handle
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h and _fn is not None:
+            _fn["fst_corrector_free"](h)
+            self._h = None
+
+    @property
+    def handle(self):
+        return self._h
+
+    def params(self):
+        p = np.empty(MLP_PARAMS, dtype=np.float32)
+        sc = C.c_float()
+        _check(_fn["fst_corrector_params"](self._h, p.ctypes.data_as(C.c_void_p), C.byref(sc)))
+        return p, sc.value
+
+    def losses(self):
+        cnt = C.c_int32(0)
+        _check(_fn["fst_corrector_losses"](self._h, None, C.byref(cnt)))
+        out = np.empty(max(cnt.value, 1), dtype=np.float32)
+        _check(_fn["fst_corrector_losses"](self._h, out.ctypes.data_as(C.c_void_p), C.byref(cnt)))
+        return out[: cnt.value]
+
+    def stored_bytes(self) -> int:
+        return int(_fn["fst_corrector_stored_bytes"](self._h))
+
+
+def make_train_params(steps=2000, batch=8192, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, seed=1):
+    tp = fst_train_params()
+    _fn["fst_train_params_default"](C.byref(tp))
+    tp.steps, tp.batch, tp.lr, tp.beta1, tp.beta2, tp.eps, tp.seed = int(steps), int(batch), float(lr), \
+        float(beta1), float(beta2), float(eps), int(seed)
+    return tp
+
+
+def fst_corrector_train(m: Model, x, y, z, v, tp=None, stream=None) -> Corrector:
+    if tp is None:
+        tp = make_train_params()
+    n = x.numel()
+    nb = int(_fn["fst_corrector_workspace_bytes"](C.byref(tp), n))
+    if nb == 0:
+        raise FstError(FST_E_INVAL, fst_last_error())
+    ws = _workspace(nb, x.device)
+    h = C.c_void_p()
+    _check(_fn["fst_corrector_train"](m.handle, _dtype_code(x), n, _dev_ptr(x), _dev_ptr(y), _dev_ptr(z),
+                                      _dev_ptr(v), C.byref(tp), _dev_ptr(ws), ws.numel(), _stream(stream),
+                                      C.byref(h)))
+    return Corrector(h)
+
+
+def fst_corrector_from_params(lo, hi, params, out_scale=1.0) -> Corrector:
+    lo_a, lo_p = _host(lo, np.float64)
+    hi_a, hi_p = _host(hi, np.float64)
+    p_a, p_p = _host(params, np.float32)
+    if p_a.size != MLP_PARAMS:
+        raise ValueError("need 4481 parameters")
+    h = C.c_void_p()
+    _check(_fn["fst_corrector_from_params"](lo_p, hi_p, p_p, float(out_scale), C.byref(h)))
+    return Corrector(h)
+
+
+def fst_corrector_apply(c: Corrector, x, y, z, out, stream=None):
+    _check(_fn["fst_corrector_apply"](c.handle, _dtype_code(x), x.numel(), _dev_ptr(x), _dev_ptr(y), _dev_ptr(z),
+                                      _dev_ptr(out), _stream(stream)))
+    return out
+
+
+def fst_eval_corrected(m: Model, c, x, y, z, out=None, stream=None):
+    torch = _torch()
+    if out is None:
+        out = torch.empty_like(x)
+    _check(_fn["fst_eval_corrected"](m.handle, None if c is None else c.handle, _dtype_code(x), x.numel(),
+                                     _dev_ptr(x), _dev_ptr(y), _dev_ptr(z), _dev_ptr(out), _stream(stream)))
+    return out
+
+
+def fst_mlp_grad(c: Corrector, x, y, z, target, idx, stream=None):
+    """Gradients (4481) and the batch's sum of squared errors, as a device float tensor."""
+    torch = _torch()
+    batch = idx.numel()
+    ws = _workspace(int(_fn["fst_mlp_grad_workspace_bytes"](batch)), x.device)
+    g = torch.empty(MLP_PARAMS + 1, dtype=torch.float32, device=x.device)
+    _check(_fn["fst_mlp_grad"](c.handle, _dtype_code(x), x.numel(), _dev_ptr(x), _dev_ptr(y), _dev_ptr(z),
+                               _dev_ptr(target), _dev_ptr(idx), batch, _dev_ptr(g), _dev_ptr(ws), ws.numel(),
+                               _stream(stream)))
+    return g

@@ -89,3 +89,23 @@ def test_adam_first_step_closed_form():
 
 def test_param_count():
     assert mlp.n_params() == 3 * 64 + 64 + 64 * 64 + 64 + 64 + 1 == 4481
+
+
+def test_batch_indices_counter_form_and_range():
+    from oracle.sampler import batch_indices, splitmix64, bounded, stream_state
+    b0 = batch_indices(5, 0, 16, 1000)
+    b3 = batch_indices(5, 3, 16, 1000)
+    z = splitmix64(stream_state(5, 3), 64)
+    np.testing.assert_array_equal(b0, bounded(z[:16], np.uint64(1000)).astype(np.int64))
+    np.testing.assert_array_equal(b3, bounded(z[48:64], np.uint64(1000)).astype(np.int64))
+    assert b0.min() >= 0 and b0.max() < 1000
+
+
+def test_oracle_training_reduces_loss_on_a_ridge():
+    rng = np.random.default_rng(4)
+    xi = rng.uniform(-1, 1, (4000, 3))
+    t = np.tanh((xi @ np.array([0.6, 0.8, 0.0]) - 0.1) / 0.1)
+    p0 = mlp.init_params(2)
+    p1, losses = mlp.train(p0, xi, t, steps=600, batch=256, seed=1, lr=3e-3)
+    assert np.mean(losses[-20:]) < 0.2 * np.mean(losses[:5])
+    np.testing.assert_array_equal(mlp.flatten(mlp.unflatten(mlp.flatten(p1))), mlp.flatten(p1))
