@@ -257,6 +257,7 @@ typedef struct {
   int32_t  batch;            /* minibatch size (8192) */
   double   lr, beta1, beta2, eps;   /* 1e-3, 0.9, 0.999, 1e-8 */
   uint64_t seed;
+  const float* init_params;  /* host float[4481] initial parameters, or NULL (Xavier-uniform) */
 } fst_train_params;
 
 void fst_train_params_default(fst_train_params* tp);

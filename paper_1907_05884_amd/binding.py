@@ -60,7 +60,7 @@ def _proto(name, res, *args):
 class fst_train_params(C.Structure):
     _fields_ = [("struct_size", C.c_uint32), ("steps", C.c_int32), ("batch", C.c_int32),
                 ("lr", C.c_double), ("beta1", C.c_double), ("beta2", C.c_double), ("eps", C.c_double),
-                ("seed", C.c_uint64)]
+                ("seed", C.c_uint64), ("init_params", C.c_void_p)]
 
 
 _P = C.POINTER(fst_fit_params)
@@ -504,11 +504,18 @@ class Corrector:
         return int(_fn["fst_corrector_stored_bytes"](self._h))
 
 
-def make_train_params(steps=2000, batch=8192, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, seed=1):
+def make_train_params(steps=2000, batch=8192, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, seed=1,
+                      init_params=None):
     tp = fst_train_params()
     _fn["fst_train_params_default"](C.byref(tp))
     tp.steps, tp.batch, tp.lr, tp.beta1, tp.beta2, tp.eps, tp.seed = int(steps), int(batch), float(lr), \
         float(beta1), float(beta2), float(eps), int(seed)
+    if init_params is not None:
+        arr = np.ascontiguousarray(init_params, dtype=np.float32)
+        if arr.size != MLP_PARAMS:
+            raise ValueError("need 4481 initial parameters")
+        tp._init_keepalive = arr
+        tp.init_params = arr.ctypes.data_as(C.c_void_p)
     return tp
 
 

@@ -74,6 +74,7 @@ void fst_train_params_default(fst_train_params* tp) {
   tp->beta2 = 0.999;
   tp->eps = 1e-8;
   tp->seed = 1;
+  tp->init_params = nullptr;
 }
 
 size_t fst_corrector_workspace_bytes(const fst_train_params* tp, int64_t n) {
@@ -123,6 +124,9 @@ fst_status fst_corrector_train(const fst_model* m, int32_t dtype, int64_t n, con
   if (!(sd > 0)) sd = 1.0;
   std::vector<float> target((size_t)n);
   for (int64_t i = 0; i < n; ++i) target[(size_t)i] = (float)(e[(size_t)i] / sd);
+  if (tp->init_params)
+    for (int j = 0; j < fst::kMlpParams; ++j)
+      if (!std::isfinite(tp->init_params[j])) fst::fail(FST_E_INVAL, "non-finite initial parameter");
   fst::copy_h2d(d_target, target.data(), sizeof(float) * (size_t)n, stream);
   std::unique_ptr<fst_corrector> c(new fst_corrector());
   for (int k = 0; k < 3; ++k) {
@@ -130,7 +134,8 @@ fst_status fst_corrector_train(const fst_model* m, int32_t dtype, int64_t n, con
     c->hi[k] = m->hi[k];
   }
   c->out_scale = (float)sd;
-  std::vector<float> P = fst::mlp_init_params(tp->seed);
+  std::vector<float> P = tp->init_params ? std::vector<float>(tp->init_params, tp->init_params + fst::kMlpParams)
+                                         : fst::mlp_init_params(tp->seed);
   fst::mlp_train(dtype, m->lo, m->hi, n, x, y, z, d_target, nullptr, tp->batch, 0, tp->steps, tp->seed,
                  adam_of(tp), P, nullptr, &c->losses, d_train, ws_bytes - (size_t)((char*)d_train - base), stream);
   c->P.resize(P.size());

@@ -106,3 +106,38 @@ def test_training_reduces_loss_and_held_out_error(dev):
     e_plain = rel_l2(plain, v[ntr:])
     e_corr = rel_l2(corr, v[ntr:])
     assert e_corr < 0.5 * e_plain, (e_plain, e_corr)
+
+
+def test_adam_steps_match_oracle(dev):
+    # three Adam steps from the same parameters on the same counter-drawn minibatches
+    from oracle.sampler import batch_indices
+    flat = bf16_round(_params(11))
+    rank, degree = (3, 3, 3), (5, 5, 5)
+    core, coefs = datagen.random_model_parts(12, rank, degree)
+    gm = fst.fst_model_from_parts((-1,) * 3, (1,) * 3, rank, degree, core, coefs)
+    n = 4000
+    pts = np.random.default_rng(13).uniform(-1, 1, (n, 3)).astype(np.float32)
+    x, y, z = [D(pts[:, k], dev) for k in range(3)]
+    f = fst.fst_eval(gm, x, y, z).cpu().numpy().astype(np.float64)
+    v = (f + np.sin(4 * pts[:, 0]) * pts[:, 1]).astype(np.float32)
+    lr = 1e-3
+    tp = fst.make_train_params(steps=3, batch=512, lr=lr, seed=7, init_params=flat)
+    c = fst.fst_corrector_train(gm, x, y, z, D(v, dev), tp)
+    gpu_after, sd = c.params()
+    # oracle: the same scaled residual target, the same batches, FP64 Adam
+    e = v.astype(np.float64) - f
+    t = e / e.std()
+    params = mlp.unflatten(flat.astype(np.float64))
+    opt = mlp.Adam(params, lr=lr)
+    for s in range(3):
+        idx = batch_indices(7, s, 512, n)
+        _, g = mlp.loss_and_grads(params, pts[idx].astype(np.float64), t[idx])
+        params = opt.step(params, g)
+    ref_after = mlp.flatten(params)
+    d_gpu = gpu_after.astype(np.float64) - flat
+    d_ref = ref_after - flat
+    # the stored parameters are BF16-rounded after training: compare updates above that rounding
+    big = np.abs(d_ref) > 4 * np.abs(flat) * 2.0 ** -8
+    assert big.sum() > 100
+    assert rel_l2(d_gpu[big], d_ref[big]) <= 0.1
+    assert sd == pytest.approx(e.std(), rel=1e-4)
