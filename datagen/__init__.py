@@ -16,6 +16,7 @@ Random streams come from ``numpy.random.SeedSequence(seed).spawn(8)``:
 """
 from __future__ import annotations
 
+import os
 from dataclasses import dataclass, field
 from typing import Optional
 
@@ -176,18 +177,24 @@ def batched(n_vars: int = 48, n: int = 4_000_000, sample_fraction: float = 0.05,
     st = _streams(4)
     pts = uniform_points(st[STREAM_POINTS], n, lo, hi).astype(np.float32)
     xi = to_reference(pts.astype(np.float64), lo, hi)
-    vals, ranks, degrees = [], [], []
+    fields, ranks, degrees = [], [], []
     for vseed in np.random.SeedSequence(4).spawn(n_vars):
         rng = np.random.default_rng(vseed)
-        while True:   # a rank triple is usable only if r_k <= prod of the other two
+        # A (ranks, degree) draw is usable only if every r_k is at most the product of the
+        # other two ranks (a Tucker rank condition) and at most p + 1 (r_k factor functions
+        # in a space of dimension p + 1 would be linearly dependent); otherwise redraw.
+        while True:
             r = tuple(int(x) for x in rng.integers(rmin, rmax + 1, size=3))
-            if all(r[k] <= r[(k + 1) % 3] * r[(k + 2) % 3] for k in range(3)):
+            p = int(rng.integers(pmin, pmax + 1))
+            if all(r[k] <= r[(k + 1) % 3] * r[(k + 2) % 3] and r[k] <= p + 1 for k in range(3)):
                 break
-        p = int(rng.integers(pmin, pmax + 1))
-        fp = draw_field(rng, n_gauss)
-        vals.append(fp(xi).astype(np.float32))
+        fields.append(draw_field(rng, n_gauss))
         ranks.append(r)
         degrees.append(p)
+    # the field values are independent per variable: evaluate them on a few threads
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(max_workers=min(8, os.cpu_count() or 1)) as ex:
+        vals = list(ex.map(lambda fp: fp(xi).astype(np.float32), fields))
     return BatchedWorkload(seed=4, lo=lo, hi=hi, pts=pts, vals=vals, ranks=ranks,
                            degrees=degrees, grid=tuple(grid), interp_fraction=0.05,
                            n_samples=int(round(sample_fraction * n)))

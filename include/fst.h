@@ -231,6 +231,18 @@ fst_status fst_model_info(const fst_model* m, double* lo, double* hi, int32_t* r
 fst_status fst_model_core(const fst_model* m, double* core_out);
 /* C_out: host FP64 (p_k + 1) x r_k row-major, zeros off the support */
 fst_status fst_model_coefs(const fst_model* m, int32_t k, double* C_out);
+/* How the core of a model from fst_fit, fst_refit_core or fst_fit_batched was solved.
+ * Precision ladder: a Gram whose Cholesky breaks down, or whose refinement makes the FP64
+ * normal-equation residual grow, is formed again from FP32 rows, then from FP64 rows (G and
+ * h); the FP64 step skips numerically dependent columns instead of failing.  Refinement
+ * undoes a step that does not reduce ||A^T (v - A alpha)|| and stops there.
+ * gram_prec_used: the Gram precision the core was solved with (-1 for other models);
+ * dropped: core entries fixed at zero because their design columns are numerically
+ * dependent on earlier ones (the fitted field is unaffected); refine_steps: refinement steps
+ * kept; rel_residual: final ||A^T (v - A alpha)|| / ||A^T v|| in FP64 (NaN without
+ * refinement).  Any pointer may be NULL. */
+fst_status fst_model_fit_info(const fst_model* m, int32_t* gram_prec_used, int64_t* dropped,
+                              int32_t* refine_steps, double* rel_residual);
 /* Storage in the paper's convention (Sec. 2): 8 bytes per stored value, core entries plus
  * non-zero coefficients, locations not counted. */
 int64_t fst_model_paper_bytes(const fst_model* m);
@@ -238,6 +250,39 @@ int64_t fst_model_paper_bytes(const fst_model* m);
  * *nbytes is the capacity on input and the bytes written on output. */
 fst_status fst_model_save(const fst_model* m, void* buf, size_t* nbytes);
 fst_status fst_model_load(const void* buf, size_t nbytes, fst_model** out);
+
+/* ------------------------------------------------------------------ batched form */
+/* Many field variables on one shared point set (device arrays x, y, z of n points, dtype
+ * base->dtype), with per-variable ranks (V x 3) and degrees (V x 3), both host int32.  All
+ * variables share the interpolation subset of base->seed; variable v draws its least-squares
+ * rows from stream FST_STREAM_LS of seed base->seed + v.  Host steps run on host threads;
+ * the Gram matrices of all variables are formed in one persistent launch; each variable is
+ * then solved in FP64 (with at most base->refine_steps refinement steps), climbing the
+ * precision ladder of fst_model_fit_info where needed; gram_prec_used (may be NULL): host
+ * int32[V] receiving the Gram precision each variable was solved with.  values: host
+ * array of V device pointers.  out: host array receiving V new models.  timings (may be NULL): host
+ * double[5] = host steps, row generation, batched Gram, A^T v, solves with refinement
+ * (seconds, each phase synchronised).  Allocates its
+ * device buffers (sum over variables of R_v^2 * 8 bytes for the Gram matrices) for the
+ * duration of the call.  Synchronises `stream`. */
+fst_status fst_fit_batched(const fst_fit_params* base, int32_t V, const int32_t* ranks,
+                           const int32_t* degrees, int64_t n, const void* x, const void* y,
+                           const void* z, const void* const* values, void* stream,
+                           fst_model** out, int32_t* gram_prec_used, double* timings);
+/* Reconstruction of V models at the same points: outs host array of V device arrays.
+ * Asynchronous. */
+fst_status fst_eval_batched(const fst_model* const* models, int32_t V, int32_t dtype, int64_t n,
+                            const void* x, const void* y, const void* z, void* const* outs,
+                            void* stream);
+/* The same batched reconstruction captured once into a HIP graph, replayed by
+ * fst_graph_launch on any stream.  The models and every array passed must stay alive and at
+ * the same addresses until fst_graph_free. */
+typedef struct fst_graph fst_graph;
+fst_status fst_eval_graph_create(const fst_model* const* models, int32_t V, int32_t dtype, int64_t n,
+                                 const void* x, const void* y, const void* z, void* const* outs,
+                                 fst_graph** out);
+fst_status fst_graph_launch(const fst_graph* g, void* stream);
+void fst_graph_free(fst_graph* g);
 
 /* ------------------------------------------------------------------ learned residual corrector */
 /* A small network g(xi) = W3 s(W2 s(W1 xi + b1) + b2) + b3, s(z) = z / (1 + e^-z), layers

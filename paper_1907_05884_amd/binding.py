@@ -96,8 +96,14 @@ _lib_fns = dict(
     fst_model_core=(_i32, _vp, _vp),
     fst_model_coefs=(_i32, _vp, _i32, _vp),
     fst_model_paper_bytes=(_i64, _vp),
+    fst_model_fit_info=(_i32, _vp, C.POINTER(_i32), C.POINTER(_i64), C.POINTER(_i32), C.POINTER(C.c_double)),
     fst_model_save=(_i32, _vp, _vp, C.POINTER(C.c_size_t)),
     fst_model_load=(_i32, _vp, C.c_size_t, C.POINTER(_vp)),
+    fst_fit_batched=(_i32, _P, _i32, _vp, _vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp),
+    fst_eval_batched=(_i32, _vp, _i32, _i32, _i64, _vp, _vp, _vp, _vp, _vp),
+    fst_eval_graph_create=(_i32, _vp, _i32, _i32, _i64, _vp, _vp, _vp, _vp, C.POINTER(_vp)),
+    fst_graph_launch=(_i32, _vp, _vp),
+    fst_graph_free=(None, _vp),
     fst_train_params_default=(None, _TP),
     fst_corrector_workspace_bytes=(C.c_size_t, _TP, _i64),
     fst_corrector_train=(_i32, _vp, _i32, _i64, _vp, _vp, _vp, _vp, _TP, _vp, C.c_size_t, _vp, C.POINTER(_vp)),
@@ -241,6 +247,16 @@ class Model:
         _check(_fn["fst_model_coefs"](self._h, int(k), out.ctypes.data_as(C.c_void_p)))
         return out
 
+    def fit_info(self):
+        """(Gram precision the core was solved with, core entries dropped as dependent)."""
+        d = self.solve_info()
+        return d["gram_prec"], d["dropped"]
+
+    def solve_info(self) -> dict:
+        prec, dropped, steps, res = _i32(), _i64(), _i32(), C.c_double()
+        _check(_fn["fst_model_fit_info"](self._h, C.byref(prec), C.byref(dropped), C.byref(steps), C.byref(res)))
+        return dict(gram_prec=prec.value, dropped=dropped.value, refine_steps=steps.value, rel_residual=res.value)
+
     def paper_bytes(self) -> int:
         return int(_fn["fst_model_paper_bytes"](self._h))
 
@@ -336,6 +352,74 @@ def fst_eval(m: Model, x, y, z, out=None, stream=None):
     _check(_fn["fst_eval"](m.handle, _dtype_code(x), x.numel(), _dev_ptr(x), _dev_ptr(y), _dev_ptr(z),
                            _dev_ptr(out), _stream(stream)))
     return out
+
+
+# ------------------------------------------------------------------------------ batched form
+def fst_fit_batched(p: fst_fit_params, ranks, degrees, x, y, z, values, stream=None):
+    """Fits len(values) variables sharing the points x, y, z.  ranks, degrees: (V, 3) ints.
+    Returns (models, timings, gram_prec_used) with timings = host steps, row generation,
+    batched Gram, A^T v, solves with refinement (seconds) and the Gram precision each
+    variable was solved with."""
+    V = len(values)
+    r, rp = _host(np.asarray(ranks).reshape(V, 3), np.int32)
+    d, dp = _host(np.broadcast_to(np.asarray(degrees).reshape(V, -1), (V, 3)), np.int32)
+    vptr = (_vp * V)(*[_dev_ptr(v) for v in values])
+    outs = (_vp * V)()
+    t = np.zeros(5)
+    used = np.zeros(V, np.int32)
+    _check(_fn["fst_fit_batched"](C.byref(p), V, rp, dp, x.numel(), _dev_ptr(x), _dev_ptr(y), _dev_ptr(z),
+                                  vptr, _stream(stream), outs, used.ctypes.data_as(C.c_void_p),
+                                  t.ctypes.data_as(C.c_void_p)))
+    return [Model(C.c_void_p(h)) for h in outs], t, used
+
+
+def fst_eval_batched(models, x, y, z, outs=None, stream=None):
+    """Reconstruction of every model at the same device points; returns the list of outputs."""
+    torch = _torch()
+    V = len(models)
+    if outs is None:
+        outs = [torch.empty_like(x) for _ in range(V)]
+    mp = (_vp * V)(*[m.handle for m in models])
+    op = (_vp * V)(*[_dev_ptr(o) for o in outs])
+    _check(_fn["fst_eval_batched"](mp, V, _dtype_code(x), x.numel(), _dev_ptr(x), _dev_ptr(y), _dev_ptr(z),
+                                   op, _stream(stream)))
+    return outs
+
+
+class EvalGraph:
+    """The batched reconstruction captured as a HIP graph.  Holds references to the models and
+    tensors it was captured with, which therefore stay alive and in place."""
+
+    def __init__(self, models, x, y, z, outs):
+        V = len(models)
+        self._keep = (list(models), x, y, z, list(outs))
+        mp = (_vp * V)(*[m.handle for m in models])
+        op = (_vp * V)(*[_dev_ptr(o) for o in outs])
+        h = C.c_void_p()
+        _check(_fn["fst_eval_graph_create"](mp, V, _dtype_code(x), x.numel(), _dev_ptr(x), _dev_ptr(y),
+                                            _dev_ptr(z), op, C.byref(h)))
+        self._h = h
+
+    def launch(self, stream=None):
+        _check(_fn["fst_graph_launch"](self._h, _stream(stream)))
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            _fn["fst_graph_free"](h)
+            self._h = None
+
+
+def fst_eval_graph_create(models, x, y, z, outs) -> EvalGraph:
+    return EvalGraph(models, x, y, z, outs)
+
+
+def fst_graph_launch(g: EvalGraph, stream=None):
+    g.launch(stream)
+
+
+def fst_graph_free(g: EvalGraph):
+    g.__del__()
 
 
 # ------------------------------------------------------------------------------ per-step GPU

@@ -1,6 +1,7 @@
 // C ABI entry points: argument validation, error reporting, and the orchestration of
 // Algorithm 1 (host steps) and Algorithm 2 (GPU refit of the core).
 #include <cmath>
+#include <limits>
 #include <cstring>
 #include <new>
 
@@ -62,6 +63,10 @@ static void validate_params(const fst_fit_params* p, int64_t n) {
   for (int k = 0; k < 3; ++k)
     if ((int64_t)p->rank[k] > (int64_t)p->rank[(k + 1) % 3] * p->rank[(k + 2) % 3])
       fail(FST_E_INVAL, "each rank must not exceed the product of the other two");
+  for (int k = 0; k < 3; ++k)
+    if (p->rank[k] > p->degree[k] + 1)
+      fail(FST_E_INVAL, "each rank must not exceed degree + 1 (more factor functions than basis functions "
+                        "makes the core least-squares problem singular)");
   if ((int64_t)p->grid[0] * p->grid[1] * p->grid[2] > (int64_t(1) << 28)) fail(FST_E_INVAL, "grid too large");
   if (!(p->interp_fraction > 0.0 && p->interp_fraction <= 1.0)) fail(FST_E_INVAL, "interp_fraction must be in (0, 1]");
   if (p->idw_k < 1 || p->idw_k > 64) fail(FST_E_INVAL, "idw_k must be in [1, 64]");
@@ -75,7 +80,7 @@ static void validate_params(const fst_fit_params* p, int64_t n) {
 
 // --------------------------------------------------------------------------- refit layout
 struct RefitLayout {
-  size_t idx, U, vs, G, h, alpha, r, scratch, total;
+  size_t idx, U, vs, G, h, alpha, scratch, total;
 };
 static RefitLayout refit_layout(int64_t R, int sr, int64_t M, int dtype, int refine, size_t scratch_need) {
   RefitLayout L;
@@ -91,15 +96,133 @@ static RefitLayout refit_layout(int64_t R, int sr, int64_t M, int dtype, int ref
   L.G = take(sizeof(double) * (size_t)R * (size_t)R);
   L.h = take(sizeof(double) * (size_t)R);
   L.alpha = take(sizeof(double) * (size_t)R);
-  L.r = take(refine > 0 ? sizeof(double) * (size_t)R : 0);
   L.scratch = take(scratch_need);
   L.total = off;
   return L;
 }
 static size_t refit_scratch(const fst_model* m, int64_t M, int refine) {
+  (void)refine;
+  return std::max(gram_workspace_bytes(m, M), solve_scratch_bytes(m, M));
+}
+
+// --------------------------------------------------------------------------- solve + ladder
+size_t solve_scratch_bytes(const fst_model* m, int64_t M) {
+  const size_t r8 = align_up(sizeof(double) * (size_t)m->R());
   size_t s = std::max(gram_workspace_bytes(m, M), cholesky_workspace_bytes(m->R()));
-  if (refine > 0) s = std::max(s, residual_workspace_bytes(m, M));
-  return s;
+  s = std::max(s, residual_workspace_bytes(m, M) + 2 * r8);
+  return std::max(s, gram_f64_rows_workspace_bytes(m, M));
+}
+
+// Euclidean norm of a device vector over the entries not masked out (mask may be empty)
+static double device_norm(const double* d, int64_t R, const std::vector<uint8_t>& skip, void* stream) {
+  std::vector<double> t((size_t)R);
+  copy_d2h(t.data(), d, sizeof(double) * (size_t)R, stream);
+  double s = 0.0;
+  for (int64_t j = 0; j < R; ++j)
+    if (skip.empty() || !skip[(size_t)j]) s += t[(size_t)j] * t[(size_t)j];
+  return std::sqrt(s);
+}
+
+// Relative pivot below which the FP64 step of the ladder treats a column as dependent on the
+// earlier ones: sqrt(2^-52).  The squared sine of the column's angle to the span of the
+// earlier columns is resolved by FP64 normal equations only well above 2^-52; kept
+// columns closer to that span would give core entries with large, cancelling values.
+constexpr double kDropTol = 1.4901161193847656e-08;
+// A refinement that stops making progress above this relative residual means the factor is
+// too inaccurate for the problem, and the ladder climbs.
+constexpr double kStallTol = 1e-8;
+
+// Iterative refinement (Algorithm 2 step 5 solved through the factored normal equations,
+// corrected with residuals r = A^T (v_S - A alpha) formed from FP64 rows).  Every step must
+// reduce ||r||; a step that does not is undone.  Returns 1 when the residual grew by more
+// than a factor 2 (the factor is too inaccurate for refinement to converge), else 0.
+static int refine_loop(const fst_model* m, int dtype, int64_t n, const void* x, const void* y, const void* z,
+                       const void* v, const int32_t* idx, int64_t M, const double* L, double* alpha, int steps,
+                       double hnorm, const std::vector<uint8_t>& skip, void* scr, size_t scr_bytes, void* stream,
+                       SolveInfo& info) {
+  const int64_t R = m->R();
+  const size_t r8 = align_up(sizeof(double) * (size_t)R);
+  double* r = (double*)scr;
+  double* prev_alpha = (double*)((char*)scr + r8);
+  char* rest = (char*)scr + 2 * r8;
+  const size_t rest_bytes = scr_bytes - 2 * r8;
+  double prev = std::numeric_limits<double>::infinity();
+  for (int s = 0; s <= steps; ++s) {
+    residual(m, dtype, n, x, y, z, v, idx, M, alpha, r, rest, rest_bytes, stream);
+    const double nr = device_norm(r, R, skip, stream);
+    if (!(nr < prev)) {
+      info.rel_residual = nr / hnorm;
+      if (s == 0) return 1;   // non-finite residual of the first solution
+      copy_d2d(alpha, prev_alpha, sizeof(double) * (size_t)R, stream);
+      info.refine_steps = s - 1;
+      info.rel_residual = prev / hnorm;
+      return (nr > 2.0 * prev || info.rel_residual > kStallTol) ? 1 : 0;
+    }
+    info.rel_residual = nr / hnorm;
+    if (s == steps || nr == 0.0) return 0;
+    prev = nr;
+    copy_d2d(prev_alpha, alpha, sizeof(double) * (size_t)R, stream);
+    cholesky_solve(R, L, r, r, stream);
+    device_axpy(R, 1.0, r, alpha, stream);
+    info.refine_steps = s + 1;
+  }
+  return 0;
+}
+
+SolveInfo solve_core(const fst_model* m, int dtype, int64_t n, const void* x, const void* y, const void* z,
+                     const void* v, const int32_t* idx, int64_t M, const void* U, const void* vs, int gram_prec,
+                     int refine, double* G, double* h, double* alpha, void* scr, size_t scr_bytes, void* stream) {
+  if (scr_bytes < solve_scratch_bytes(m, M)) fail(FST_E_NOMEM, "solve: scratch too small");
+  const int64_t R = m->R();
+  const std::vector<uint8_t> none;
+  if (!std::isfinite(device_norm(h, R, none, stream)))
+    fail(FST_E_INVAL, "non-finite coordinates or values among the sampled rows");
+  SolveInfo info;
+  int level = gram_prec;
+  bool semidefinite = false;   // FP64 rows, strict factorisation already broke down
+  auto reform = [&](int prec) {
+    if (prec == FST_GRAM_F32)
+      launch_gram(m, dtype, M, U, vs, FST_GRAM_F32, G, nullptr, scr, scr_bytes, stream);
+    else if (dtype == FST_F32)
+      gram_from_f64_rows(m, dtype, n, x, y, z, v, idx, M, G, h, scr, scr_bytes, stream);
+    else
+      launch_gram(m, dtype, M, U, vs, FST_GRAM_F64, G, nullptr, scr, scr_bytes, stream);
+  };
+  for (;;) {
+    int64_t dropped = 0;
+    const int64_t piv = cholesky(R, G, scr, scr_bytes, stream, semidefinite ? kDropTol : 0.0, &dropped);
+    if (piv != 0) {
+      if (semidefinite)
+        fail(FST_E_NOT_SPD, "Cholesky breakdown at pivot " + std::to_string(piv) +
+                                ": non-finite entries in the sampled Gram matrix");
+      // precision ladder: 16-bit -> FP32 rows -> FP64 rows (G and h) -> FP64 rows with
+      // dependent columns skipped
+      if (level == FST_GRAM_BF16 || level == FST_GRAM_F16) {
+        level = FST_GRAM_F32;
+      } else if (level == FST_GRAM_F32) {
+        level = FST_GRAM_F64;
+      } else {
+        semidefinite = true;
+      }
+      reform(level);
+      continue;
+    }
+    info.gram_prec = level;
+    info.dropped = dropped;
+    info.refine_steps = 0;
+    info.rel_residual = std::numeric_limits<double>::quiet_NaN();
+    cholesky_solve(R, G, h, alpha, stream);
+    if (refine <= 0) break;
+    const std::vector<uint8_t> skip = dropped > 0 ? dropped_mask(G, R, scr, stream) : none;
+    const double hnorm = device_norm(h, R, skip, stream);
+    if (!(hnorm > 0.0)) break;
+    const int climb = refine_loop(m, dtype, n, x, y, z, v, idx, M, G, alpha, refine, hnorm, skip, scr, scr_bytes,
+                                  stream, info);
+    if (!climb || level == FST_GRAM_F64) break;
+    level = (level == FST_GRAM_BF16 || level == FST_GRAM_F16) ? FST_GRAM_F32 : FST_GRAM_F64;
+    reform(level);
+  }
+  return info;
 }
 // the same bound without a model object (for fst_fit_workspace_bytes)
 static size_t refit_bytes_for(const int32_t rank[3], const int32_t degree[3], int64_t M, int dtype, int refine) {
@@ -124,6 +247,10 @@ static fst_model* refit_impl(const fst_model* m, int dtype, int64_t n, const voi
   const int64_t R = m->R();
   if (n < 1 || n >= (int64_t(1) << 31)) fail(FST_E_INVAL, "need 1 <= n < 2^31 points");
   if (M <= R || M > n) fail(FST_E_INVAL, "Algorithm 2 needs r1 r2 r3 < n_samples <= n");
+  for (int k = 0; k < 3; ++k)
+    if (m->rank[k] > m->degree[k] + 1)
+      fail(FST_E_INVAL, "Algorithm 2 needs rank <= degree + 1 in every mode (otherwise the design rows are "
+                        "linearly dependent)");
   if (!x || !y || !z || !v) fail(FST_E_INVAL, "null point or value array");
   if (refine < 0 || refine > 100) fail(FST_E_INVAL, "refine_steps must be in [0, 100]");
   const RefitLayout L = refit_layout(R, m->sum_r(), M, dtype, refine, refit_scratch(m, M, refine));
@@ -135,7 +262,6 @@ static fst_model* refit_impl(const fst_model* m, int dtype, int64_t n, const voi
   double* d_G = (double*)(base + L.G);
   double* d_h = (double*)(base + L.h);
   double* d_alpha = (double*)(base + L.alpha);
-  double* d_r = (double*)(base + L.r);
   void* d_scr = base + L.scratch;
   const size_t scr_bytes = ws.bytes - L.scratch;
 
@@ -150,25 +276,15 @@ static fst_model* refit_impl(const fst_model* m, int dtype, int64_t n, const voi
   const DeviceModel& dm = device_model(m, dtype);
   launch_factor_eval(m, dm, dtype, n, x, y, z, v, d_idx, M, d_U, d_vs, stream);
   launch_gram(m, dtype, M, d_U, d_vs, gram_prec, d_G, d_h, d_scr, scr_bytes, stream);
-  std::vector<double> h((size_t)R);
-  copy_d2h(h.data(), d_h, sizeof(double) * (size_t)R, stream);
-  for (double t : h)
-    if (!std::isfinite(t)) fail(FST_E_INVAL, "non-finite coordinates or values among the sampled rows");
-  int64_t info = cholesky(R, d_G, d_scr, scr_bytes, stream);
-  if (info != 0)
-    fail(FST_E_NOT_SPD, "Cholesky breakdown at pivot " + std::to_string(info) +
-                            ": the sampled Gram matrix is not positive definite (too few distinct rows?)");
-  cholesky_solve(R, d_G, d_h, d_alpha, stream);
-  for (int s = 0; s < refine; ++s) {
-    residual(m, dtype, n, x, y, z, v, d_idx, M, d_alpha, d_r, d_scr, scr_bytes, stream);
-    cholesky_solve(R, d_G, d_r, d_r, stream);
-    device_axpy(R, 1.0, d_r, d_alpha, stream);
-  }
+  const SolveInfo si = solve_core(m, dtype, n, x, y, z, v, d_idx, M, d_U, d_vs, gram_prec, refine, d_G, d_h,
+                                  d_alpha, d_scr, scr_bytes, stream);
   std::vector<double> alpha((size_t)R);
   copy_d2h(alpha.data(), d_alpha, sizeof(double) * (size_t)R, stream);
   for (double t : alpha)
     if (!std::isfinite(t)) fail(FST_E_NOT_SPD, "solve produced non-finite core values");
-  return copy_with_core(m, alpha);
+  fst_model* out = copy_with_core(m, alpha);
+  out->fit = si;
+  return out;
 }
 
 // Algorithm 1 from the gathered interpolation subset (host FP64, K x 4: x, y, z, v).
@@ -561,6 +677,19 @@ fst_status fst_model_coefs(const fst_model* m, int32_t k, double* C_out) {
   check_model(m);
   if (k < 0 || k > 2 || !C_out) fail(FST_E_INVAL, "bad mode or null output");
   std::memcpy(C_out, m->coef[k].data(), sizeof(double) * m->coef[k].size());
+  return FST_OK;
+  FST_CATCH
+}
+
+fst_status fst_model_fit_info(const fst_model* m, int32_t* gram_prec_used, int64_t* dropped,
+                              int32_t* refine_steps, double* rel_residual) {
+  FST_TRY
+  set_last_error("");
+  check_model(m);
+  if (gram_prec_used) *gram_prec_used = m->fit.gram_prec;
+  if (dropped) *dropped = m->fit.dropped;
+  if (refine_steps) *refine_steps = m->fit.refine_steps;
+  if (rel_residual) *rel_residual = m->fit.rel_residual;
   return FST_OK;
   FST_CATCH
 }

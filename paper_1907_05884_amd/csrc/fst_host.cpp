@@ -88,8 +88,10 @@ struct BinGrid {
 };
 }  // namespace
 
-void idw_grid(const double* xi, const double* v, int64_t K, const int32_t grid[3], int k,
-              double power, int n_threads, double* out) {
+// The k nearest subset points of every grid node (C order), as (index, weight) pairs with
+// weights d^-power; an exact hit is stored as a single neighbour with a negative weight.
+void idw_knn(const double* xi, int64_t K, const int32_t grid[3], int k, double power, int n_threads,
+             std::vector<int64_t>& nbr, std::vector<double>& wgt, std::vector<int32_t>& count) {
   if (K <= 0) fail(FST_E_INVAL, "idw_grid: no points");
   for (int d = 0; d < 3; ++d)
     if (grid[d] < 2) fail(FST_E_INVAL, "idw_grid: grid sizes must be >= 2");
@@ -117,6 +119,9 @@ void idw_grid(const double* xi, const double* v, int64_t K, const int32_t grid[3
   }
   const int64_t I0 = grid[0], I1 = grid[1], I2 = grid[2];
   const int64_t nodes = I0 * I1 * I2;
+  nbr.assign((size_t)(nodes * k), 0);
+  wgt.assign((size_t)(nodes * k), 0.0);
+  count.assign((size_t)nodes, 0);
   parallel_for(nodes, hardware_threads(n_threads), [&](int64_t a, int64_t b) {
     std::vector<Cand> best;
     best.reserve((size_t)k + 1);
@@ -168,19 +173,52 @@ void idw_grid(const double* xi, const double* v, int64_t K, const int32_t grid[3
         // domain edge, so points slightly outside [-1,1] sit in edge cells already searched).
         if ((int)best.size() == k && best.back().d2 < bound * bound) break;
       }
+      int64_t* nb = &nbr[(size_t)(node * k)];
+      double* wt = &wgt[(size_t)(node * k)];
       if (best.front().d2 == 0.0) {
-        out[node] = v[best.front().idx];
+        nb[0] = best.front().idx;
+        wt[0] = -1.0;
+        count[(size_t)node] = 1;
+        continue;
+      }
+      for (size_t t = 0; t < best.size(); ++t) {
+        nb[t] = best[t].idx;
+        wt[t] = 1.0 / std::pow(std::sqrt(best[t].d2), power);
+      }
+      count[(size_t)node] = (int32_t)best.size();
+    }
+  });
+}
+
+void idw_apply(const std::vector<int64_t>& nbr, const std::vector<double>& wgt, const std::vector<int32_t>& count,
+               int k, const double* v, int n_threads, double* out) {
+  const int64_t nodes = (int64_t)count.size();
+  parallel_for(nodes, hardware_threads(n_threads), [&](int64_t a, int64_t b) {
+    for (int64_t node = a; node < b; ++node) {
+      const int64_t* nb = &nbr[(size_t)(node * k)];
+      const double* wt = &wgt[(size_t)(node * k)];
+      if (wt[0] < 0.0) {
+        out[node] = v[nb[0]];
         continue;
       }
       double num = 0.0, den = 0.0;
-      for (const Cand& cd : best) {
-        double w = 1.0 / std::pow(std::sqrt(cd.d2), power);
-        num += w * v[cd.idx];
-        den += w;
+      for (int t = 0; t < count[(size_t)node]; ++t) {
+        num += wt[t] * v[nb[t]];
+        den += wt[t];
       }
       out[node] = num / den;
     }
   });
+}
+
+void idw_grid(const double* xi, const double* v, int64_t K, const int32_t grid[3], int k,
+              double power, int n_threads, double* out) {
+  std::vector<int64_t> nbr;
+  std::vector<double> wgt;
+  std::vector<int32_t> count;
+  k = (int)std::min<int64_t>(std::max(k, 1), std::max<int64_t>(K, 1));
+  idw_knn(xi, K, grid, k, power, n_threads, nbr, wgt, count);
+  idw_apply(nbr, wgt, count, k, v, n_threads, out);
 }
 
 // ------------------------------------------------------------------------------ ST-HOSVD

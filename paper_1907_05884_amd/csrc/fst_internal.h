@@ -3,6 +3,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <limits>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -36,11 +37,24 @@ struct DeviceModel {
 
 }  // namespace fst
 
+namespace fst {
+// How the core of a refit was solved: Gram precision after the precision ladder (-1 for
+// models not produced by a refit), core entries skipped as numerically dependent,
+// refinement steps taken and the final ||A^T (v - A alpha)|| / ||A^T v|| (NaN if none).
+struct SolveInfo {
+  int32_t gram_prec = -1;
+  int64_t dropped = 0;
+  int32_t refine_steps = 0;
+  double rel_residual = std::numeric_limits<double>::quiet_NaN();
+};
+}  // namespace fst
+
 struct fst_model {
   double lo[3], hi[3];
   int32_t rank[3], degree[3];
   std::vector<double> core;      // r1 r2 r3, C order
   std::vector<double> coef[3];   // (p_k + 1) x r_k row-major
+  fst::SolveInfo fit;             // how the core was solved (models from a refit)
   // lazily uploaded device copies, keyed by (device ordinal, dtype)
   mutable std::mutex mu;
   mutable std::map<std::pair<int, int>, fst::DeviceModel> dev;
@@ -56,6 +70,10 @@ uint64_t splitmix64_next(uint64_t& state);
 void sample_indices(uint64_t seed, int stream, int64_t n, int64_t m, int64_t* out);
 void idw_grid(const double* xi, const double* v, int64_t K, const int32_t grid[3], int k,
               double power, int n_threads, double* out);
+void idw_knn(const double* xi, int64_t K, const int32_t grid[3], int k, double power, int n_threads,
+             std::vector<int64_t>& nbr, std::vector<double>& wgt, std::vector<int32_t>& count);
+void idw_apply(const std::vector<int64_t>& nbr, const std::vector<double>& wgt, const std::vector<int32_t>& count,
+               int k, const double* v, int n_threads, double* out);
 void sthosvd(const double* T, const int32_t dims[3], const int32_t rank[3], int n_threads,
              double* core, double* const W[3], double* const sigma[3]);
 void sparse_fit(const double* W, int I, int r, int p, double* C);
@@ -79,7 +97,15 @@ void launch_gram(const fst_model* m, int dtype, int64_t mrows, const void* U, co
                  int gram_prec, double* G, double* h, void* ws, size_t ws_bytes, void* stream);
 size_t cholesky_workspace_bytes(int64_t R);
 // returns 0 on success, else the 1-based index of the failing pivot
-int64_t cholesky(int64_t R, double* G, void* ws, size_t ws_bytes, void* stream);
+// FP64 Cholesky in place; returns the first breakdown pivot (1-based) or 0.  A pivot breaks
+// down when it is not above R 2^-52 times its original diagonal.  With drop_tol > 0, a pivot
+// not above max(R 2^-52, drop_tol) times its original diagonal marks a column (numerically)
+// dependent on the earlier ones: it is skipped (L_jj = +inf, so its solution entry is zero)
+// and counted in *dropped instead of being reported.
+int64_t cholesky(int64_t R, double* G, void* ws, size_t ws_bytes, void* stream, double drop_tol = 0.0,
+                 int64_t* dropped = nullptr);
+// 1 for every column a semidefinite factorisation skipped (ws: R doubles of scratch)
+std::vector<uint8_t> dropped_mask(const double* L, int64_t R, void* ws, void* stream);
 void cholesky_solve(int64_t R, const double* L, const double* b, double* x, void* stream);
 void launch_eval(const fst_model* m, const DeviceModel& dm, int dtype, int64_t n,
                  const void* x, const void* y, const void* z, const int32_t* idx,
@@ -88,6 +114,23 @@ size_t residual_workspace_bytes(const fst_model* m, int64_t mrows);
 void residual(const fst_model* m, int dtype, int64_t n, const void* x, const void* y,
               const void* z, const void* v, const int32_t* idx, int64_t mrows,
               const double* alpha, double* r, void* ws, size_t ws_bytes, void* stream);
+void launch_gram_batched(const std::vector<const fst_model*>& models, const std::vector<const void*>& U,
+                         const std::vector<int64_t>& mrows, const std::vector<double*>& G, int prec, void* ws,
+                         void* stream);
+size_t solve_scratch_bytes(const fst_model* m, int64_t M);
+// Cholesky + solve + refinement of one sampled system with the precision ladder (fst_api.cpp).
+// On entry G holds the Gram at gram_prec and h = A^T v from the rows U, vs.
+SolveInfo solve_core(const fst_model* m, int dtype, int64_t n, const void* x, const void* y, const void* z,
+                     const void* v, const int32_t* idx, int64_t M, const void* U, const void* vs, int gram_prec,
+                     int refine, double* G, double* h, double* alpha, void* scr, size_t scr_bytes, void* stream);
+size_t gram_f64_rows_workspace_bytes(const fst_model* m, int64_t mrows);
+void gram_from_f64_rows(const fst_model* m, int dtype, int64_t n, const void* x, const void* y,
+                        const void* z, const void* v, const int32_t* idx, int64_t mrows, double* G,
+                        double* h, void* ws, size_t ws_bytes, void* stream);
+void* eval_graph_create(const std::vector<const fst_model*>& models, int dtype, int64_t n, const void* x,
+                        const void* y, const void* z, const std::vector<void*>& outs);
+void eval_graph_launch(void* graph, void* stream);
+void eval_graph_free(void* graph);
 void gather_points(int dtype, int64_t K, const int64_t* idx_host, const void* x,
                    const void* y, const void* z, const void* v, double* out_host, void* ws,
                    size_t ws_bytes, void* stream);

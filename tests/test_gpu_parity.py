@@ -230,19 +230,24 @@ def test_fit_end_to_end_fp64(dev):
     assert abs(err_gpu - err_ref) <= 1e-8 * err_ref + 1e-12
 
 
-def test_refit_rejects_too_few_samples_and_duplicates(dev):
+def test_refit_rejects_too_few_samples_and_solves_rank_one_design(dev):
     om, gm = _models(20, (4, 4, 4), (6, 6, 6))
     pts = _pts(21, 500)
     x, y, z = _soa(pts, dev)
-    v = D(np.zeros(500), dev)
+    v = D(np.full(500, 1.5), dev)
     with pytest.raises(fst.FstError) as e:
         fst.fst_refit_core(gm, x, y, z, v, 64, 1)
     assert e.value.status == fst.FST_E_INVAL
-    # every point identical: the sampled design has rank one, Cholesky must break down
+    # every point identical: the sampled design has rank one.  The strict Cholesky breaks
+    # down, the FP64 step keeps the first column and drops the other R - 1 as dependent,
+    # and the field at the point equals the value
     same = [D(np.full(500, 0.3), dev) for _ in range(3)]
-    with pytest.raises(fst.FstError) as e:
-        fst.fst_refit_core(gm, *same, v, 200, 1)
-    assert e.value.status == fst.FST_E_NOT_SPD
+    out = fst.fst_refit_core(gm, *same, v, 200, 1)
+    prec, dropped = out.fit_info()
+    assert prec == fst.FST_GRAM_F64 and dropped == om.R - 1
+    assert np.count_nonzero(out.core) == 1
+    f = H(fst.fst_eval(out, *[t[:1].contiguous() for t in same]))
+    assert abs(f[0] - 1.5) <= 1e-12
 
 
 def test_refit_exact_recovery_fp32(dev):
@@ -290,12 +295,21 @@ def test_refit_16bit_gram_with_refinement_matches_fp64(dev, prec):
     alpha_o, idx, G, h = lsq.refit_core(m0, wl.pts.astype(np.float64), wl.vals.astype(np.float64), 4000, 9)
     gm = fst.fst_model_from_parts(w.lo, w.hi, w.rank, w.degree, m0.core, m0.coefs)
     x, y, z, v = [D(a, dev) for a in wl.soa()]
-    errs = []
+    errs, res = [], []
     for steps in (0, 1, 3):
         out = fst.fst_refit_core(gm, x, y, z, v, 4000, 9, gram_prec=prec, refine_steps=steps)
         errs.append(rel_l2(out.core, alpha_o))
+        info = out.solve_info()
+        assert info["gram_prec"] == prec and info["dropped"] == 0 and info["refine_steps"] <= steps
+        res.append(info["rel_residual"])
     assert errs[2] <= 1e-6, errs
     assert errs[2] < errs[0], errs
+    assert np.isnan(res[0]) and res[2] < res[1], res
+    # many steps: refinement stops once a step no longer reduces the FP64 residual
+    out = fst.fst_refit_core(gm, x, y, z, v, 4000, 9, gram_prec=prec, refine_steps=40)
+    info = out.solve_info()
+    assert info["refine_steps"] < 40 and info["rel_residual"] <= 1e-12, info
+    assert rel_l2(out.core, alpha_o) <= 1e-10
 
 
 # ------------------------------------------------------------------------------ full size

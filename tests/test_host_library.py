@@ -158,6 +158,11 @@ def test_invalid_arguments_are_rejected():
     with pytest.raises(fst.FstError) as e:
         fst.fst_fit_workspace_bytes(p, 100)
     assert e.value.status == fst.FST_E_INVAL
+    # more factor functions than basis functions in a mode: the design rows are dependent
+    p = fst.make_params(rank=(5, 4, 4), grid=(8, 8, 8), degree=(3, 3, 3), n_samples=200)
+    with pytest.raises(fst.FstError, match="degree \\+ 1") as e:
+        fst.fst_fit_workspace_bytes(p, 1000)
+    assert e.value.status == fst.FST_E_INVAL
     # rank larger than the grid, rank larger than the product of the others
     for kw in (dict(rank=(9, 8, 8), grid=(8, 8, 8)), dict(rank=(2, 2, 5), grid=(8, 8, 8))):
         p = fst.make_params(degree=(3, 3, 3), n_samples=90, **kw)
