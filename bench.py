@@ -29,6 +29,25 @@ sys.path.insert(0, ROOT)
 
 PEAK = {"f32": 157.3e12, "bf16": 2.5e15, "f16": 2.5e15}
 GOLDEN = os.path.join(ROOT, "tests", "golden", "large_f32_reference.npz")
+TRAFFIC = os.path.join(ROOT, "profiles", "traffic_large.json")
+KERNELS_SRC = os.path.join(ROOT, "paper_1907_05884_amd", "csrc", "fst_kernels.hip")
+
+
+def measured_traffic(precision: str):
+    """HBM bytes per launch of the Gram kernel from the committed FETCH_SIZE / WRITE_SIZE
+    counters (calibrated against a copy of known size), or None when there are none for this
+    precision or the kernel source has changed since they were taken."""
+    import hashlib
+    import json as _json
+    try:
+        t = _json.load(open(TRAFFIC))
+        h = hashlib.sha256(open(KERNELS_SRC, "rb").read()).hexdigest()[:16]
+    except OSError:
+        return None
+    name = t.get("gram_kernel", {}).get(precision)
+    if h != t.get("source_sha256_prefix") or name not in t.get("kernels", {}):
+        return None
+    return float(t["kernels"][name]["bytes"])
 METRIC = "LS design rows/s + reconstructed points/s at stated rel-L2 vs FP64 oracle"
 
 
@@ -278,6 +297,32 @@ def run_batched(args):
     print(json.dumps(result), flush=True)
 
 
+def run_copy(args):
+    """Calibration of the HBM traffic counters: a plain device-to-device copy of a known
+    size (1 GiB read, 1 GiB written per launch).  FETCH_SIZE and WRITE_SIZE of this launch
+    divided by 1 GiB give the factors that turn the counters of the hot-path kernels into
+    bytes."""
+    import torch
+
+    n = (1 << 30) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    times = []
+    for i in range(args.warmup + args.steps):
+        e0.record(stream)
+        dst.copy_(src)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        if i >= args.warmup:
+            times.append(e0.elapsed_time(e1) / 1e3)
+    t = float(np.mean(times))
+    print(json.dumps({"metric": "device copy bandwidth (counter calibration)", "value": 2 * n * 4 / t / 1e9,
+                      "unit": "GB/s", "bytes_read_per_launch": n * 4, "bytes_written_per_launch": n * 4,
+                      "steps": args.steps, "warmup": args.warmup}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -290,7 +335,7 @@ def main():
     ap.add_argument("--precision", choices=("f32", "bf16", "f16"), default="f32",
                     help="Gram precision: f32 (FP32 MFMA) or the 16-bit form with FP64 refinement")
     ap.add_argument("--refine", type=int, default=None, help="refinement steps (default 0 for f32, 3 otherwise)")
-    ap.add_argument("--workload", choices=("large_f32", "corrector", "batched"), default="large_f32")
+    ap.add_argument("--workload", choices=("large_f32", "corrector", "batched", "copy"), default="large_f32")
     ap.add_argument("--lr", type=float, default=1e-3, help="corrector: Adam learning rate")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -301,6 +346,8 @@ def main():
         return run_corrector(args)
     if args.workload == "batched":
         return run_batched(args)
+    if args.workload == "copy":
+        return run_copy(args)
 
     import torch
 
@@ -431,7 +478,8 @@ def main():
         "roofline": {"kernel": "k_gram<float>" if args.precision == "f32" else f"k_gram_lp<{args.precision}>",
                      "bound": "mfma", "achieved": achieved / 1e12,
                      "peak": peak / 1e12, "unit": "TFLOP/s", "frac": achieved / peak,
-                     "traffic": None, "flops_per_launch": gram_flops},
+                     "traffic": measured_traffic(args.precision), "flops_per_launch": gram_flops,
+                     "algorithmic_bytes_per_launch": float(SR * M * 4 + R * (R + 1) // 2 * 8)},
     }
     if ref is not None:
         a_ref = ref["alpha"]

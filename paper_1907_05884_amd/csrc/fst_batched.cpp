@@ -139,7 +139,29 @@ fst_status fst_fit_batched(const fst_fit_params* base, int32_t V, const int32_t*
   const int dtype = base->dtype;
   const size_t es = dtype == FST_F64 ? sizeof(double) : sizeof(float);
   const int64_t M = base->n_samples;
-  std::vector<std::unique_ptr<DeviceBuffer>> bU, bvs, bidx, bG, bh, ba, bscr;
+  // the sampled rows of every variable (seed + v, stream 2), drawn on host threads
+  std::vector<std::vector<int32_t>> rows((size_t)V);
+  {
+    std::atomic<int> next(0);
+    std::vector<std::thread> th;
+    const int nth = std::min(fst::hardware_threads(base->n_threads), V);
+    for (int t = 0; t < nth; ++t)
+      th.emplace_back([&] {
+        try {
+          std::vector<int64_t> idx((size_t)M);
+          for (int v = next++; v < V; v = next++) {
+            fst::sample_indices(base->seed + (uint64_t)v, FST_STREAM_LS, n, M, idx.data());
+            rows[(size_t)v].assign(idx.begin(), idx.end());
+          }
+        } catch (...) {
+          next = V;   // the missing rows are reported below
+        }
+      });
+    for (auto& t : th) t.join();
+    for (int v = 0; v < V; ++v)
+      if ((int64_t)rows[(size_t)v].size() != M) fst::fail(FST_E_NOMEM, "sampling the least-squares rows failed");
+  }
+  std::vector<std::unique_ptr<DeviceBuffer>> bU, bvs, bidx, bG, bh, ba;
   std::vector<const fst_model*> mods;
   std::vector<const void*> Up;
   std::vector<int64_t> Ms;
@@ -155,10 +177,7 @@ fst_status fst_fit_batched(const fst_fit_params* base, int32_t V, const int32_t*
     bh.emplace_back(new DeviceBuffer(sizeof(double) * (size_t)R));
     ba.emplace_back(new DeviceBuffer(sizeof(double) * (size_t)R));
     scr_need = std::max(scr_need, fst::solve_scratch_bytes(m, M));
-    std::vector<int64_t> idx((size_t)M);
-    fst::sample_indices(base->seed + (uint64_t)v, FST_STREAM_LS, n, M, idx.data());
-    std::vector<int32_t> idx32(idx.begin(), idx.end());
-    fst::copy_h2d(bidx.back()->p, idx32.data(), sizeof(int32_t) * (size_t)M, stream);
+    fst::copy_h2d(bidx.back()->p, rows[(size_t)v].data(), sizeof(int32_t) * (size_t)M, stream);
     const fst::DeviceModel& dm = fst::device_model(m, dtype);
     fst::launch_factor_eval(m, dm, dtype, n, x, y, z, values[v], (const int32_t*)bidx.back()->p, M, bU.back()->p,
                             bvs.back()->p, stream);
