@@ -80,7 +80,8 @@ _lib_fns = dict(
     fst_gram_workspace_bytes=(C.c_size_t, _vp, _i64),
     fst_gram=(_i32, _vp, _i32, _i64, _vp, _vp, _i32, _vp, _vp, _vp, C.c_size_t, _vp),
     fst_cholesky_workspace_bytes=(C.c_size_t, _i64),
-    fst_cholesky=(_i32, _i64, _vp, C.POINTER(_i64), _vp, C.c_size_t, _vp),
+    fst_cholesky=(_i32, _i64, _vp, C.c_double, C.POINTER(_i64), _vp, C.c_size_t, _vp),
+    fst_gram_shift=(C.c_double, _i32, _i64),
     fst_cholesky_solve=(_i32, _i64, _vp, _vp, _vp, _vp),
     fst_residual_workspace_bytes=(C.c_size_t, _vp, _i64),
     fst_residual=(_i32, _vp, _i32, _i64, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp, C.c_size_t, _vp),
@@ -464,12 +465,18 @@ def fst_gram(m: Model, U, vs=None, gram_prec=None, G=None, h=None, ws=None, stre
     return G, h
 
 
-def fst_cholesky(G, stream=None) -> int:
-    """In-place FP64 Cholesky of a device (R, R) tensor; raises FstError(FST_E_NOT_SPD)."""
+def fst_gram_shift(gram_prec: int, mrows: int) -> float:
+    return float(_fn["fst_gram_shift"](int(gram_prec), int(mrows)))
+
+
+def fst_cholesky(G, stream=None, shift: float = 0.0) -> int:
+    """In-place FP64 Cholesky of G + shift diag(G) (device (R, R) tensor); raises
+    FstError(FST_E_NOT_SPD)."""
     R = G.shape[0]
     ws = _workspace(int(_fn["fst_cholesky_workspace_bytes"](R)), G.device)
     info = C.c_int64(0)
-    st = _fn["fst_cholesky"](R, _dev_ptr(G), C.byref(info), _dev_ptr(ws), ws.numel(), _stream(stream))
+    st = _fn["fst_cholesky"](R, _dev_ptr(G), float(shift), C.byref(info), _dev_ptr(ws), ws.numel(),
+                             _stream(stream))
     if st != FST_OK:
         raise FstError(st, fst_last_error() + f" (info={info.value})")
     return info.value

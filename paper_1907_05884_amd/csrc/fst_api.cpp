@@ -106,6 +106,11 @@ static size_t refit_scratch(const fst_model* m, int64_t M, int refine) {
 }
 
 // --------------------------------------------------------------------------- solve + ladder
+double gram_shift(int gram_prec, int64_t mrows) {
+  if (gram_prec != FST_GRAM_BF16 && gram_prec != FST_GRAM_F16) return 0.0;
+  return 4.0 * std::sqrt((double)((mrows + 31) / 32)) * 5.9604644775390625e-08;
+}
+
 size_t solve_scratch_bytes(const fst_model* m, int64_t M) {
   const size_t r8 = align_up(sizeof(double) * (size_t)m->R());
   size_t s = std::max(gram_workspace_bytes(m, M), cholesky_workspace_bytes(m->R()));
@@ -190,7 +195,8 @@ SolveInfo solve_core(const fst_model* m, int dtype, int64_t n, const void* x, co
   };
   for (;;) {
     int64_t dropped = 0;
-    const int64_t piv = cholesky(R, G, scr, scr_bytes, stream, semidefinite ? kDropTol : 0.0, &dropped);
+    const int64_t piv = cholesky(R, G, scr, scr_bytes, stream, semidefinite ? kDropTol : 0.0, &dropped,
+                                 gram_shift(level, M));
     if (piv != 0) {
       if (semidefinite)
         fail(FST_E_NOT_SPD, "Cholesky breakdown at pivot " + std::to_string(piv) +
@@ -507,12 +513,16 @@ fst_status fst_gram(const fst_model* m, int32_t dtype, int64_t mrows, const void
 
 size_t fst_cholesky_workspace_bytes(int64_t R) { return cholesky_workspace_bytes(R); }
 
-fst_status fst_cholesky(int64_t R, double* G, int64_t* info, void* ws, size_t ws_bytes, void* stream) {
+double fst_gram_shift(int32_t gram_prec, int64_t mrows) { return gram_shift(gram_prec, mrows); }
+
+fst_status fst_cholesky(int64_t R, double* G, double shift, int64_t* info, void* ws, size_t ws_bytes,
+                        void* stream) {
   FST_TRY
   set_last_error("");
   if (info) *info = 0;
   if (R < 1 || !G || !ws) fail(FST_E_INVAL, "bad arguments");
-  int64_t piv = cholesky(R, G, ws, ws_bytes, stream);
+  if (!(shift >= 0.0 && shift < 1.0)) fail(FST_E_INVAL, "shift must be in [0, 1)");
+  int64_t piv = cholesky(R, G, ws, ws_bytes, stream, 0.0, nullptr, shift);
   if (info) *info = piv;
   if (piv != 0) fail(FST_E_NOT_SPD, "Cholesky breakdown at pivot " + std::to_string(piv));
   return FST_OK;

@@ -145,6 +145,24 @@ def test_cholesky_and_solve(dev, R):
     assert rel_l2(H(x), np.linalg.solve(A, b)) <= 1e-10
 
 
+def test_cholesky_with_diagonal_shift(dev):
+    # G + s diag(G) = L L^T; the shift the fits use for 16-bit Grams follows its formula
+    R = 300
+    rng = np.random.default_rng(5)
+    B = rng.standard_normal((R, R))
+    A = B @ B.T / R + 0.1 * np.eye(R)
+    s = 1e-3
+    G = D(A.copy(), dev)
+    assert fst.fst_cholesky(G, shift=s) == 0
+    As = A + s * np.diag(np.diag(A))
+    assert rel_l2(np.tril(H(G)), np.linalg.cholesky(As)) <= 1e-12
+    assert fst.fst_gram_shift(fst.FST_GRAM_F16, 200000) == 4 * np.sqrt(6250) * 2.0 ** -24
+    assert fst.fst_gram_shift(fst.FST_GRAM_BF16, 33) == 4 * np.sqrt(2) * 2.0 ** -24
+    assert fst.fst_gram_shift(fst.FST_GRAM_F32, 200000) == 0.0
+    with pytest.raises(fst.FstError):
+        fst.fst_cholesky(D(A.copy(), dev), shift=-1.0)
+
+
 def test_cholesky_reports_non_spd_pivot(dev):
     R = 200
     A = np.eye(R)
@@ -266,12 +284,15 @@ def test_refit_exact_recovery_fp32(dev):
 
 
 # ------------------------------------------------------------------------------ precision form
+@pytest.mark.parametrize("rank", [(9, 8, 7), (12, 10, 9)])
 @pytest.mark.parametrize("prec,u", [("bf16", 2.0 ** -8), ("f16", 2.0 ** -11)])
-def test_gram_16bit_within_rounding_bound(dev, prec, u):
+def test_gram_16bit_within_rounding_bound(dev, prec, u, rank):
     # each design-row entry is rounded once to the 16-bit format, so every Gram entry is within
-    # ~2u * sum_q |A[q,j] A[q,j']| of the exact value (plus FP32 accumulation, far smaller)
+    # ~2u * sum_q |A[q,j] A[q,j']| of the exact value (plus FP32 accumulation, far smaller).
+    # r3 = 7 forms entries from three factors, r3 = 9 from (j1, j2) pair tables; R = 1080
+    # spans five 256-wide tiles with a ragged edge.
     code = fst.FST_GRAM_BF16 if prec == "bf16" else fst.FST_GRAM_F16
-    om, gm = _models(30, (9, 8, 7), (15, 15, 15))
+    om, gm = _models(30, rank, (15, 15, 15))
     m = 6007
     pts = _pts(31, m, dtype=np.float32)
     x, y, z = _soa(pts, dev)
