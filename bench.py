@@ -411,7 +411,7 @@ def main():
         ev[2].record(stream)
         fst.fst_gram(m0, U, vs, h=h, ws=gws, want_G=False)      # A^T v
         ev[3].record(stream)
-        fst.fst_cholesky(G, shift=fst.fst_gram_shift(gram_prec, M))
+        fst.fst_cholesky(G)
         fst.fst_cholesky_solve(G, h, alpha)
         ev[4].record(stream)
         snaps = [alpha.clone()] if record else []

@@ -154,7 +154,7 @@ fst_status fst_gram(const fst_model* m, int32_t dtype, int64_t mrows, const void
  * (lower triangle read, L written there; the strictly upper triangle of each 64 x 64
  * diagonal block receives the transposed strictly lower triangle of that block's inverse,
  * used by fst_cholesky_solve; the rest of the strictly upper triangle is untouched).
- * shift in [0, 1): relative diagonal shift, 0 for none; fits use fst_gram_shift.
+ * shift in [0, 1): relative diagonal shift, 0 for none (the fits use none).
  * Synchronises `stream`; returns FST_E_NOT_SPD if a pivot is not above R * 2^-52 times its
  * diagonal entry before the factorisation (numerically rank-deficient system), with its
  * index in *info (1-based; 0 on success; info may be NULL).
@@ -162,11 +162,6 @@ fst_status fst_gram(const fst_model* m, int32_t dtype, int64_t mrows, const void
 size_t fst_cholesky_workspace_bytes(int64_t R);
 fst_status fst_cholesky(int64_t R, double* G, double shift, int64_t* info, void* ws,
                         size_t ws_bytes, void* stream);
-/* The relative diagonal shift the fits apply before factoring a Gram of precision gram_prec
- * over mrows rows: 4 sqrt(ceil(mrows / 32)) 2^-24 for the 16-bit forms (FP32 accumulation,
- * whose rounding would otherwise break the definiteness of ill-conditioned systems; the
- * refinement removes the shift's effect), 0 otherwise. */
-double fst_gram_shift(int32_t gram_prec, int64_t mrows);
 
 /* Solves L L^T x = b with L from fst_cholesky (device FP64, including its stored
  * diagonal-block inverses); b and x may alias.

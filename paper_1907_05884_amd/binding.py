@@ -81,7 +81,6 @@ _lib_fns = dict(
     fst_gram=(_i32, _vp, _i32, _i64, _vp, _vp, _i32, _vp, _vp, _vp, C.c_size_t, _vp),
     fst_cholesky_workspace_bytes=(C.c_size_t, _i64),
     fst_cholesky=(_i32, _i64, _vp, C.c_double, C.POINTER(_i64), _vp, C.c_size_t, _vp),
-    fst_gram_shift=(C.c_double, _i32, _i64),
     fst_cholesky_solve=(_i32, _i64, _vp, _vp, _vp, _vp),
     fst_residual_workspace_bytes=(C.c_size_t, _vp, _i64),
     fst_residual=(_i32, _vp, _i32, _i64, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp, C.c_size_t, _vp),
@@ -463,10 +462,6 @@ def fst_gram(m: Model, U, vs=None, gram_prec=None, G=None, h=None, ws=None, stre
                            _dev_ptr(G) if want_G else None, _dev_ptr(h), _dev_ptr(ws), ws.numel(),
                            _stream(stream)))
     return G, h
-
-
-def fst_gram_shift(gram_prec: int, mrows: int) -> float:
-    return float(_fn["fst_gram_shift"](int(gram_prec), int(mrows)))
 
 
 def fst_cholesky(G, stream=None, shift: float = 0.0) -> int:

@@ -106,10 +106,6 @@ static size_t refit_scratch(const fst_model* m, int64_t M, int refine) {
 }
 
 // --------------------------------------------------------------------------- solve + ladder
-double gram_shift(int gram_prec, int64_t mrows) {
-  if (gram_prec != FST_GRAM_BF16 && gram_prec != FST_GRAM_F16) return 0.0;
-  return 4.0 * std::sqrt((double)((mrows + 31) / 32)) * 5.9604644775390625e-08;
-}
 
 size_t solve_scratch_bytes(const fst_model* m, int64_t M) {
   const size_t r8 = align_up(sizeof(double) * (size_t)m->R());
@@ -195,8 +191,7 @@ SolveInfo solve_core(const fst_model* m, int dtype, int64_t n, const void* x, co
   };
   for (;;) {
     int64_t dropped = 0;
-    const int64_t piv = cholesky(R, G, scr, scr_bytes, stream, semidefinite ? kDropTol : 0.0, &dropped,
-                                 gram_shift(level, M));
+    const int64_t piv = cholesky(R, G, scr, scr_bytes, stream, semidefinite ? kDropTol : 0.0, &dropped);
     if (piv != 0) {
       if (semidefinite)
         fail(FST_E_NOT_SPD, "Cholesky breakdown at pivot " + std::to_string(piv) +
@@ -512,8 +507,6 @@ fst_status fst_gram(const fst_model* m, int32_t dtype, int64_t mrows, const void
 }
 
 size_t fst_cholesky_workspace_bytes(int64_t R) { return cholesky_workspace_bytes(R); }
-
-double fst_gram_shift(int32_t gram_prec, int64_t mrows) { return gram_shift(gram_prec, mrows); }
 
 fst_status fst_cholesky(int64_t R, double* G, double shift, int64_t* info, void* ws, size_t ws_bytes,
                         void* stream) {

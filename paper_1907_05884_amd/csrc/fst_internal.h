@@ -105,11 +105,7 @@ size_t cholesky_workspace_bytes(int64_t R);
 // (thresholds stay relative to the unshifted diagonal).
 int64_t cholesky(int64_t R, double* G, void* ws, size_t ws_bytes, void* stream, double drop_tol = 0.0,
                  int64_t* dropped = nullptr, double shift = 0.0);
-// Relative diagonal shift for a Gram accumulated in FP32 without periodic FP64 folding
-// (the 16-bit forms): 4 sqrt(ceil(M / 32)) 2^-24, four times the typical accumulated
-// rounding of M / 32 MFMA steps, which would otherwise destroy the definiteness of
-// ill-conditioned systems.  Refinement removes its effect on the solution.
-double gram_shift(int gram_prec, int64_t mrows);
+
 // 1 for every column a semidefinite factorisation skipped (ws: R doubles of scratch)
 std::vector<uint8_t> dropped_mask(const double* L, int64_t R, void* ws, void* stream);
 void cholesky_solve(int64_t R, const double* L, const double* b, double* x, void* stream);
