@@ -448,6 +448,24 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
 
+    # factor evaluation at all N points (no gather): the HBM-bound kernel of the path,
+    # measured once outside the timed steps; bytes per point = 3 coordinates in + sum r out
+    U_all = torch.empty((SR, N), dtype=torch.float32, device=dev)
+    k1_ms = []
+    for i in range(4):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        fst.fst_factor_eval(m0, x, y, z, U=U_all)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        if i:
+            k1_ms.append(e0.elapsed_time(e1))
+    t_k1_all = float(np.median(k1_ms)) / 1e3
+    del U_all
+    k1_bytes = float(N) * (3 + SR) * 4
+    # data error of the reconstruction, FP64 sums on the device
+    s_err, s_v = fst.fst_eval_error(gm_fit, x, y, z, v)
+
     avg = {k: float(np.mean(vv)) for k, vv in times.items()}
     t_rows = avg["k1"] + avg["gram"] + avg["atv"]
     design_rows_per_s = M / t_rows
@@ -457,7 +475,11 @@ def main():
     achieved = gram_flops / avg["gram"]
     peak = PEAK[args.precision]
     f_all = out.cpu().numpy()
-    eps_data = float(np.linalg.norm(f_all - w.vals.astype(np.float64)) / np.linalg.norm(w.vals.astype(np.float64)))
+    eps_data = float(np.sqrt(s_err / s_v))
+    # algorithmic flops per point: core contraction 2R + 2 r1 r2 + 2 r1, sparse factor
+    # contractions 2 nnz, Legendre recurrences about 4 flop per term and mode
+    eval_flops = float(N) * (2 * R + 2 * m0.rank[0] * m0.rank[1] + 2 * m0.rank[0] + 2 * m0.info()["nnz"]
+                             + 4 * sum(d + 1 for d in m0.degree))
 
     result = {
         "metric": METRIC, "value": design_rows_per_s, "unit": "rows/s", "n_gpus": 1,
@@ -475,6 +497,16 @@ def main():
         "breakdown_ms": {k: vv * 1e3 for k, vv in avg.items()},
         "host_steps_s": t_host, "host_sample_draw_s": t_sample,
         "data_rel_l2": eps_data,
+        "other_kernels": {
+            "k_factor_eval (all N points, no gather)": {
+                "bound": "hbm", "achieved": k1_bytes / t_k1_all / 1e9, "peak": 8000.0, "unit": "GB/s",
+                "frac": k1_bytes / t_k1_all / 8e12, "ms": t_k1_all * 1e3,
+                "bytes_per_launch": k1_bytes},
+            "k_eval (reconstruction)": {
+                "bound": "alu", "achieved": eval_flops / avg["eval"] / 1e12, "peak": 157.3, "unit": "TFLOP/s",
+                "frac": eval_flops / avg["eval"] / 157.3e12, "flops_per_launch": eval_flops,
+                "note": "FP32 vector peak; packed FP32 is disabled by the build rules, so 78.6 TFLOP/s is the "
+                        "attainable scalar-FMA ceiling"}},
         "roofline": {"kernel": "k_gram<float>" if args.precision == "f32" else f"k_gram_lp<{args.precision}>",
                      "bound": "mfma", "achieved": achieved / 1e12,
                      "peak": peak / 1e12, "unit": "TFLOP/s", "frac": achieved / peak,

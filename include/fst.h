@@ -128,6 +128,16 @@ fst_status fst_refit_core(const fst_model* m, int32_t dtype, int64_t n, const vo
 fst_status fst_eval(const fst_model* m, int32_t dtype, int64_t n, const void* x,
                     const void* y, const void* z, void* out, void* stream);
 
+/* Data error of the reconstruction (the scattered analogue of the precision of Sec. 4.1):
+ * sums_out (host double[2]) receives sum_i (v_i - f(x_i))^2 and sum_i v_i^2, accumulated in
+ * FP64 in a fixed order, so ||v - f|| / ||v|| = sqrt(sums_out[0] / sums_out[1]).  v: device
+ * values of the points' dtype.  ws: device workspace >= fst_eval_error_workspace_bytes
+ * (NULL: the library allocates).  Synchronises `stream`. */
+size_t fst_eval_error_workspace_bytes(int32_t dtype, int64_t n);
+fst_status fst_eval_error(const fst_model* m, int32_t dtype, int64_t n, const void* x,
+                          const void* y, const void* z, const void* v, void* ws,
+                          size_t ws_bytes, void* stream, double* sums_out);
+
 /* ------------------------------------------------------------------ per-step GPU calls */
 
 /* Rows of Algorithm 2 step 1 at sampled points, eq. (2): for q < m and i = idx[q] (or i = q

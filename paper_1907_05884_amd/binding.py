@@ -77,6 +77,8 @@ _lib_fns = dict(
                     C.c_size_t, _vp, C.POINTER(_vp)),
     fst_eval=(_i32, _vp, _i32, _i64, _vp, _vp, _vp, _vp, _vp),
     fst_factor_eval=(_i32, _vp, _i32, _i64, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp),
+    fst_eval_error_workspace_bytes=(C.c_size_t, _i32, _i64),
+    fst_eval_error=(_i32, _vp, _i32, _i64, _vp, _vp, _vp, _vp, _vp, C.c_size_t, _vp, _vp),
     fst_gram_workspace_bytes=(C.c_size_t, _vp, _i64),
     fst_gram=(_i32, _vp, _i32, _i64, _vp, _vp, _i32, _vp, _vp, _vp, C.c_size_t, _vp),
     fst_cholesky_workspace_bytes=(C.c_size_t, _i64),
@@ -420,6 +422,18 @@ def fst_graph_launch(g: EvalGraph, stream=None):
 
 def fst_graph_free(g: EvalGraph):
     g.__del__()
+
+
+def fst_eval_error(m: Model, x, y, z, v, ws=None, stream=None):
+    """(sum (v - f)^2, sum v^2) of the reconstruction at device points, FP64."""
+    dt = _dtype_code(x)
+    n = x.numel()
+    if ws is None:
+        ws = _workspace(int(_fn["fst_eval_error_workspace_bytes"](dt, n)), x.device)
+    out = np.zeros(2)
+    _check(_fn["fst_eval_error"](m.handle, dt, n, _dev_ptr(x), _dev_ptr(y), _dev_ptr(z), _dev_ptr(v),
+                                 _dev_ptr(ws), ws.numel(), _stream(stream), out.ctypes.data_as(C.c_void_p)))
+    return float(out[0]), float(out[1])
 
 
 # ------------------------------------------------------------------------------ per-step GPU

@@ -467,6 +467,26 @@ fst_status fst_eval(const fst_model* m, int32_t dtype, int64_t n, const void* x,
   FST_CATCH
 }
 
+size_t fst_eval_error_workspace_bytes(int32_t dtype, int64_t n) {
+  if ((dtype != FST_F64 && dtype != FST_F32) || n < 0) return 0;
+  return eval_error_workspace_bytes(dtype, n);
+}
+
+fst_status fst_eval_error(const fst_model* m, int32_t dtype, int64_t n, const void* x, const void* y,
+                          const void* z, const void* v, void* ws, size_t ws_bytes, void* stream,
+                          double* sums_out) {
+  FST_TRY
+  set_last_error("");
+  check_model(m);
+  check_dtype(dtype);
+  if (n < 1 || n >= (int64_t(1) << 31)) fail(FST_E_INVAL, "need 1 <= n < 2^31 points");
+  if (!x || !y || !z || !v || !sums_out) fail(FST_E_INVAL, "null argument");
+  Workspace w(ws, ws_bytes, eval_error_workspace_bytes(dtype, n));
+  eval_error(m, dtype, n, x, y, z, v, w.p, w.bytes, stream, sums_out);
+  return FST_OK;
+  FST_CATCH
+}
+
 fst_status fst_factor_eval(const fst_model* m, int32_t dtype, int64_t n, const void* x, const void* y,
                            const void* z, const void* v, const int32_t* idx, int64_t mrows, void* U,
                            void* vs, void* stream) {

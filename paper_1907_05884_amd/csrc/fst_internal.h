@@ -119,6 +119,9 @@ void residual(const fst_model* m, int dtype, int64_t n, const void* x, const voi
 void launch_gram_batched(const std::vector<const fst_model*>& models, const std::vector<const void*>& U,
                          const std::vector<int64_t>& mrows, const std::vector<double*>& G, int prec, void* ws,
                          void* stream);
+size_t eval_error_workspace_bytes(int dtype, int64_t n);
+void eval_error(const fst_model* m, int dtype, int64_t n, const void* x, const void* y, const void* z,
+                const void* v, void* ws, size_t ws_bytes, void* stream, double out[2]);
 size_t solve_scratch_bytes(const fst_model* m, int64_t M);
 // Cholesky + solve + refinement of one sampled system with the precision ladder (fst_api.cpp).
 // On entry G holds the Gram at gram_prec and h = A^T v from the rows U, vs.

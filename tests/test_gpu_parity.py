@@ -195,6 +195,27 @@ def test_eval_empty(dev):
     assert fst.fst_eval(gm, e, e, e).numel() == 0
 
 
+@pytest.mark.parametrize("dtype,n,tol", [(np.float64, 20001, 1e-10), (np.float32, 300007, 1e-5)])
+def test_eval_error_parity(dev, dtype, n, tol):
+    # sums of (v - f)^2 and v^2 against the oracle's reconstruction of the same points; the
+    # values are the field plus noise, so the data error is neither 0 nor 1
+    om, gm = _models(17, (7, 6, 5), (12, 12, 12))
+    pts = _pts(18, n, dtype=dtype)
+    p64 = pts.astype(np.float64)
+    f = reconstruct.evaluate(om, p64)
+    v = (f + 0.05 * np.std(f) * np.random.default_rng(19).standard_normal(n)).astype(dtype)
+    x, y, z = _soa(pts, dev)
+    s_err, s_v = fst.fst_eval_error(gm, x, y, z, D(v, dev))
+    v64 = v.astype(np.float64)
+    ref_err, ref_v = float(np.sum((v64 - f) ** 2)), float(np.sum(v64 ** 2))
+    assert abs(s_v - ref_v) <= 1e-12 * ref_v
+    # FP32 reconstruction errors (~1e-7 of |f|) against a residual of 5%: rel 1e-5 on the sum
+    assert abs(s_err - ref_err) <= tol * ref_err
+    assert np.sqrt(s_err / s_v) == pytest.approx(np.linalg.norm(v64 - f) / np.linalg.norm(v64), rel=tol)
+    # deterministic: the same bits twice
+    assert fst.fst_eval_error(gm, x, y, z, D(v, dev)) == (s_err, s_v)
+
+
 # ------------------------------------------------------------------------------ FP64 residual
 def test_residual_fp64_parity(dev):
     om, gm = _models(13, (6, 5, 4), (10, 10, 10))
