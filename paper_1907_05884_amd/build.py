@@ -18,13 +18,16 @@ LIB = os.path.join(PKG, "libfst.so")
 ARCH = os.environ.get("FST_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["fst_api.cpp", "fst_model.cpp", "fst_host.cpp", "fst_corrector.cpp", "fst_batched.cpp",
-           "fst_kernels.hip", "fst_mlp.hip"]
+           "fst_kernels.hip", "fst_linalg.hip", "fst_mlp.hip"]
 
 COMMON = ["-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-function",
           "-I" + os.path.join(ROOT, "include")]
 # Device code: gfx950 only; packed FP32 instructions are disabled on purpose (the compiler
 # would otherwise form v_pk_* FP32 ops from scalar code).
 HIPFLAGS = ["--offload-arch=" + ARCH, "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+# The one-wave diagonal-block factorisation keeps a 64-entry row in registers, which needs
+# its doubly nested 64-step loops unrolled completely (beyond the default pragma limit).
+FILE_FLAGS = {"fst_linalg.hip": ["-mllvm", "-pragma-unroll-threshold=1000000"]}
 
 
 def _hipcc() -> str:
@@ -39,7 +42,7 @@ def _compile(src: str, verbose: bool) -> str:
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
     path = os.path.join(CSRC, src)
     if src.endswith(".hip"):
-        cmd = [_hipcc(), "-x", "hip", *HIPFLAGS, *COMMON, "-c", path, "-o", obj]
+        cmd = [_hipcc(), "-x", "hip", *HIPFLAGS, *FILE_FLAGS.get(src, []), *COMMON, "-c", path, "-o", obj]
     else:
         cmd = [_hipcc(), *COMMON, "-D__HIP_PLATFORM_AMD__", "-c", path, "-o", obj]
     if verbose:

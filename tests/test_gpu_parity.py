@@ -131,7 +131,9 @@ def test_gram_is_deterministic(dev):
 
 
 # ------------------------------------------------------------------------------ Cholesky + solve
-@pytest.mark.parametrize("R", [1, 64, 333, 1000])
+# sizes cover one block, a ragged last block, trailing updates whose last row block is
+# shorter than a tile (R - base not a multiple of 256) and several 256-column panels
+@pytest.mark.parametrize("R", [1, 64, 65, 257, 300, 333, 1000, 4097])
 def test_cholesky_and_solve(dev, R):
     rng = np.random.default_rng(R)
     B = rng.standard_normal((R, R))
@@ -139,8 +141,15 @@ def test_cholesky_and_solve(dev, R):
     b = rng.standard_normal(R)
     G = D(A.copy(), dev)
     assert fst.fst_cholesky(G) == 0
-    L = np.tril(H(G))
-    assert rel_l2(L, np.linalg.cholesky(A)) <= 1e-12
+    Gh = H(G)
+    Lref = np.linalg.cholesky(A)
+    assert rel_l2(np.tril(Gh), Lref) <= 1e-12
+    # strict upper triangle of every 64 x 64 diagonal block: its inverse, transposed
+    for k0 in range(0, R, 64):
+        nb = min(64, R - k0)
+        inv = np.linalg.inv(Lref[k0:k0 + nb, k0:k0 + nb])
+        got = np.triu(Gh[k0:k0 + nb, k0:k0 + nb], 1).T
+        assert np.abs(got - np.tril(inv, -1)).max() <= 1e-12 * np.abs(inv).max()
     x = fst.fst_cholesky_solve(G, D(b, dev))
     assert rel_l2(H(x), np.linalg.solve(A, b)) <= 1e-10
 
