@@ -37,24 +37,25 @@ __device__ inline double readlane_f64(double v, int lane) {
   return __hiloint2double(hi, lo);
 }
 
-// Diagonal block, one wave.  A pivot counts as a breakdown when it is not above
+// Diagonal block, four waves.  A pivot counts as a breakdown when it is not above
 // tol * (its diagonal entry before the factorisation), tol = R * 2^-52: at that size the
 // Schur complement is rounding noise and the sampled system is numerically rank deficient.
 // With drop_tol > 0 such a column is dropped instead (semidefinite factorisation): L_jj = +inf
 // makes its column of L, its solution entry and its row and column of the block inverse
 // exactly zero in every later step.
 //
-// Lane i holds row i of the block in registers.  Column j: the pivot comes from lane j, the
-// lanes below scale their entry, the column goes through LDS and is applied as a rank-1
-// update to the entries right of it (entries right of a lane's diagonal are never read).
-// 1 / L_jj comes from the hardware reciprocal square root refined by two Newton steps, and
-// L_jj = d / sqrt(d) from it with one more Newton correction.
+// Lane i of wave w holds row i, columns 16 w .. 16 w + 15, in registers.  Column j: the wave
+// that owns it reads the pivot from lane j, scales the entries below and publishes the
+// column through LDS (two alternating buffers, one barrier per column); every wave then
+// applies the rank-1 update to its columns right of j.  1 / L_jj comes from the hardware
+// reciprocal square root refined by two Newton steps, and L_jj = d / sqrt(d) from it with
+// one more Newton correction.
 //
-// inv(L11) is then formed in 16 x 16 blocks X_ij: the diagonal blocks by forward
-// substitution (lane 16 b + c forms column c of X_bb), the others level by level (i - j =
-// 1, 2, 3) as X_ij = -X_ii sum_{j <= k < i} L_ik X_kj on FP64 MFMA.  The accumulator of a
-// 16 x 16 x 4 product holds in lane l the rows l / 16 + 4 v of column l % 16, which is the
-// B operand of the next product's k-step v, so the second product reads no LDS for it.
+// inv(L11) is then formed by the first wave in 16 x 16 blocks X_ij: the diagonal blocks by
+// forward substitution (lane 16 b + c forms column c of X_bb), the others level by level
+// (i - j = 1, 2, 3) as X_ij = -X_ii sum_{j <= k < i} L_ik X_kj on FP64 MFMA.  The accumulator
+// of a 16 x 16 x 4 product holds in lane l the rows l / 16 + 4 v of column l % 16, which is
+// the B operand of the next product's k-step v, so the second product reads no LDS for it.
 // The block goes back to G with coalesced row writes.  A short last block (nb < 64) is
 // padded with the identity.
 __device__ inline double rsqrt_f64(double d) {
@@ -67,105 +68,133 @@ __device__ inline double rsqrt_f64(double d) {
   return y;
 }
 
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_potrf_diag(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_potrf_diag(
     double* G, int64_t R, int64_t k0, int nb, int64_t* info, const double* diag0, double tol, double drop_tol) {
   __shared__ double sA[CH_NB][CH_NB + 1];
   __shared__ double sX[CH_NB][CH_NB + 1];
-  __shared__ double scol[CH_NB];
+  __shared__ double scol[2][CH_NB];
   __shared__ double srd[CH_NB];
-  const int l = threadIdx.x;
+  __shared__ int64_t sinfo[4][2];
+  const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
   {
-    // all 64 row loads in flight (clamped rows and columns), the padding selected afterwards
-    double v[CH_NB];
+    // 16 rows per wave, all loads in flight (clamped rows and columns), padding selected after
+    double v[16];
 #pragma unroll
-    for (int r = 0; r < CH_NB; ++r) v[r] = G[(k0 + (r < nb ? r : 0)) * R + k0 + (l < nb ? l : 0)];
+    for (int u = 0; u < 16; ++u) {
+      const int r = 16 * w + u;
+      v[u] = G[(k0 + (r < nb ? r : 0)) * R + k0 + (l < nb ? l : 0)];
+    }
 #pragma unroll
-    for (int r = 0; r < CH_NB; ++r) sA[r][l] = (r < nb && l <= r) ? v[r] : (r == l ? 1.0 : 0.0);
+    for (int u = 0; u < 16; ++u) {
+      const int r = 16 * w + u;
+      sA[r][l] = (r < nb && l <= r) ? v[u] : (r == l ? 1.0 : 0.0);
+    }
   }
   const double thr = (tol > drop_tol ? tol : drop_tol) * diag0[k0 + (l < nb ? l : 0)];
   __syncthreads();
-  double a[CH_NB];
+  double a[16];
 #pragma unroll
-  for (int c = 0; c < CH_NB; ++c) a[c] = sA[l][c];
+  for (int c = 0; c < 16; ++c) a[c] = sA[l][16 * w + c];
   int64_t brk = 0, ndrop = 0;
 #pragma unroll
   for (int j = 0; j < CH_NB; ++j) {
-    // pivot logic without branches (uniform values), so a step stays one basic block
-    const double d = readlane_f64(a[j], j);
-    const double t = readlane_f64(thr, j);
-    const bool fin = isfinite(d);
-    const bool ok = j >= nb || (d > t && fin);
-    const bool drop = !ok && drop_tol > 0.0 && fin;
-    const double y = rsqrt_f64(ok ? d : 1.0);
-    double sq = (ok ? d : 1.0) * y;
-    sq = fma(0.5 * y, fma(-sq, sq, ok ? d : 1.0), sq);
-    const double ljj = ok ? sq : (drop ? INFINITY : 1.0);
-    const double inv = ok ? y : (drop ? 0.0 : 1.0);
-    ndrop += drop ? 1 : 0;
-    brk = (!ok && !drop && brk == 0) ? k0 + j + 1 : brk;
-    const double lij = l > j ? a[j] * inv : (l == j ? ljj : a[j]);
-    a[j] = lij;
-    scol[l] = lij;
-    if (l == 0) srd[j] = inv;
-    __syncthreads();
-#pragma unroll
-    for (int c = 0; c < CH_NB; ++c)   // fixed trip count: both loops unroll fully
-      if (c > j) a[c] -= lij * scol[c];
-    // apply the update now: deferring it would keep every broadcast column alive
-#pragma unroll
-    for (int c = 0; c < CH_NB; ++c)
-      if (c > j) asm volatile("" : "+v"(a[c]));
-    __syncthreads();
-  }
-#pragma unroll
-  for (int c = 0; c < CH_NB; ++c)
-    if (c <= l) sA[l][c] = a[c];
-  __syncthreads();
-  {
-    // diagonal 16 x 16 blocks of the inverse: lane 16 b + c forms column c of X_bb
-    const int b = l >> 4, c = l & 15, o = 16 * b;
-    double x[16];
-#pragma unroll
-    for (int r = 0; r < 16; ++r) x[r] = 0.0;
-#pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      const double xi = (i == c ? 1.0 : x[i]) * srd[o + i];
-      x[i] = i < c ? 0.0 : xi;
-#pragma unroll
-      for (int r = 0; r < 16; ++r)
-        if (r > i) x[r] -= sA[o + r][o + i] * x[i];
-    }
-#pragma unroll
-    for (int r = 0; r < 16; ++r) sX[o + r][o + c] = x[r];
-  }
-  __syncthreads();
-  const int li = l & 15, g = l >> 4;
-#pragma unroll
-  for (int dd = 1; dd < 4; ++dd) {
-#pragma unroll
-    for (int j = 0; j + dd < 4; ++j) {
-      const int i = j + dd;
-      doublex4 t = doublex4{0, 0, 0, 0};
-#pragma unroll
-      for (int k = j; k < i; ++k)
-#pragma unroll
-        for (int s4 = 0; s4 < 4; ++s4)
-          t = MfmaAcc<double>::mfma(sA[16 * i + li][16 * k + 4 * s4 + g], sX[16 * k + 4 * s4 + g][16 * j + li], t);
-      doublex4 xij = doublex4{0, 0, 0, 0};
-#pragma unroll
-      for (int s4 = 0; s4 < 4; ++s4) xij = MfmaAcc<double>::mfma(sX[16 * i + li][16 * i + 4 * s4 + g], t[s4], xij);
-#pragma unroll
-      for (int v = 0; v < 4; ++v) sX[16 * i + MfmaAcc<double>::row(g, v)][16 * j + li] = -xij[v];
+    const int jb = j >> 4, jc = j & 15, buf = j & 1;
+    if (w == jb) {
+      // pivot logic without branches (uniform values)
+      const double d = readlane_f64(a[jc], j);
+      const double t = readlane_f64(thr, j);
+      const bool fin = isfinite(d);
+      const bool ok = j >= nb || (d > t && fin);
+      const bool drop = !ok && drop_tol > 0.0 && fin;
+      const double dd = ok ? d : 1.0;
+      const double y = rsqrt_f64(dd);
+      double sq = dd * y;
+      sq = fma(0.5 * y, fma(-sq, sq, dd), sq);
+      const double ljj = ok ? sq : (drop ? INFINITY : 1.0);
+      const double inv = ok ? y : (drop ? 0.0 : 1.0);
+      ndrop += drop ? 1 : 0;
+      brk = (!ok && !drop && brk == 0) ? k0 + j + 1 : brk;
+      const double lij = l > j ? a[jc] * inv : (l == j ? ljj : a[jc]);
+      a[jc] = lij;
+      scol[buf][l] = lij;
+      if (l == 0) srd[j] = inv;
     }
     __syncthreads();
+    if (w >= jb) {
+      const double lj = scol[buf][l];
+#pragma unroll
+      for (int c = 0; c < 16; ++c)
+        if (w > jb || c > jc) a[c] -= lj * scol[buf][16 * w + c];
+    }
   }
-  // row r of the block: L[r][0..r] below and on the diagonal, inv(L11)[c][r] right of it
-#pragma unroll 16
-  for (int r = 0; r < CH_NB; ++r)
-    if (r < nb && l < nb) G[(k0 + r) * R + k0 + l] = l <= r ? sA[r][l] : sX[l][r];
   if (l == 0) {
-    if (brk != 0 && info[0] == 0) info[0] = brk;
-    info[1] += ndrop;
+    sinfo[w][0] = brk;
+    sinfo[w][1] = ndrop;
+  }
+#pragma unroll
+  for (int c = 0; c < 16; ++c)
+    if (16 * w + c <= l) sA[l][16 * w + c] = a[c];
+  __syncthreads();
+  if (w == 0) {
+    {
+      // diagonal 16 x 16 blocks of the inverse: lane 16 b + c forms column c of X_bb
+      const int b = l >> 4, c = l & 15, o = 16 * b;
+      double x[16];
+#pragma unroll
+      for (int r = 0; r < 16; ++r) x[r] = 0.0;
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        const double xi = (i == c ? 1.0 : x[i]) * srd[o + i];
+        x[i] = i < c ? 0.0 : xi;
+#pragma unroll
+        for (int r = 0; r < 16; ++r)
+          if (r > i) x[r] -= sA[o + r][o + i] * x[i];
+      }
+#pragma unroll
+      for (int r = 0; r < 16; ++r) sX[o + r][o + c] = x[r];
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    const int li = l & 15, g = l >> 4;
+#pragma unroll
+    for (int dd = 1; dd < 4; ++dd) {
+#pragma unroll
+      for (int j = 0; j + dd < 4; ++j) {
+        const int i = j + dd;
+        doublex4 t = doublex4{0, 0, 0, 0};
+#pragma unroll
+        for (int k = j; k < i; ++k)
+#pragma unroll
+          for (int s4 = 0; s4 < 4; ++s4)
+            t = MfmaAcc<double>::mfma(sA[16 * i + li][16 * k + 4 * s4 + g], sX[16 * k + 4 * s4 + g][16 * j + li], t);
+        doublex4 xij = doublex4{0, 0, 0, 0};
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) xij = MfmaAcc<double>::mfma(sX[16 * i + li][16 * i + 4 * s4 + g], t[s4], xij);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) sX[16 * i + MfmaAcc<double>::row(g, v)][16 * j + li] = -xij[v];
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    }
+  }
+  __syncthreads();
+  // row r of the block: L[r][0..r] below and on the diagonal, inv(L11)[c][r] right of it
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    const int r = 16 * w + u;
+    if (r < nb && l < nb) G[(k0 + r) * R + k0 + l] = l <= r ? sA[r][l] : sX[l][r];
+  }
+  if (threadIdx.x == 0) {
+    int64_t b0 = 0, nd = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (b0 == 0) b0 = sinfo[q][0];
+      nd += sinfo[q][1];
+    }
+    if (b0 != 0 && info[0] == 0) info[0] = b0;
+    info[1] += nd;
   }
 }
 
@@ -366,7 +395,7 @@ int64_t cholesky(int64_t R, double* G, void* ws, size_t ws_bytes, void* stream, 
     const int64_t panel_end = K0 + P;
     for (int64_t k0 = K0; k0 < panel_end; k0 += CH_NB) {
       int nb = (int)std::min<int64_t>(CH_NB, R - k0);
-      hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(64), 0, S(stream), G, R, k0, nb, d_info, d_diag, tol,
+      hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(256), 0, S(stream), G, R, k0, nb, d_info, d_diag, tol,
                          drop_tol);
       check_launch("k_potrf_diag");
       const int64_t rest = R - k0 - nb;
