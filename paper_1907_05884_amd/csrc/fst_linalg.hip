@@ -244,16 +244,18 @@ __global__ __launch_bounds__(256) void k_trsm_panel(double* G, int64_t R, int64_
 }
 
 // Trailing update G[i, j] -= sum_{c < K} L[i, kL + c] L[j, kL + c] for base <= j <= i < R,
-// j < col_end, on FP64 MFMA.  Workgroup tile 256 rows x 128 columns: sixteen waves, each
-// 64 x 32 (4 x 2 blocks of 16 x 16), one workgroup per CU (four waves per SIMD hide the LDS
-// and global latency better than two waves of 64 x 64).  K is staged 16 columns at a time through
-// double-buffered LDS with a register prefetch of the next slice; the loads go through buffer
-// resources whose extent ends at the last row of the matrix, so rows past R read as zero.  In
-// a 16 x 16 x 4 step the contraction index is only summed over, so lane group g = lane / 16
-// takes the four consecutive columns 4 g .. 4 g + 3 of each staged row (16-byte LDS reads).
-// Tiles: the lower triangle of 256-row x 128-column blocks (nbc == 0), or an nbc x nblk
-// rectangle of column x row blocks whose tiles above the diagonal exit at once.
-constexpr int SY_WM = 4, SY_WN = 4, SY_BM = 4, SY_BN = 2, SY_KC = 16;
+// j < col_end, on FP64 MFMA.  Workgroup tile 128 x 128: sixteen waves, each 32 x 32 (2 x 2
+// blocks of 16 x 16), K staged 8 columns at a time through double-buffered LDS with a
+// register prefetch of the next slice; two workgroups fit on a CU, so eight waves per SIMD
+// hide the LDS, barrier and global latency (measured faster than fewer, larger wave tiles).
+// The loads go through buffer resources whose extent ends at the last row of the matrix, so
+// rows past R read as zero.  In a 16 x 16 x 4 step the contraction index is only summed
+// over, so lane group g = lane / 16 takes the consecutive columns KS g .. KS g + KS - 1 of
+// each staged row (16-byte LDS reads).  Tiles: the lower triangle of row/column blocks
+// (nbc == 0), numbered so that each XCD (workgroups are dealt to the eight XCDs in turn)
+// gets a contiguous run of tiles that share row blocks in its L2; or an nbc x nblk rectangle
+// of column x row blocks whose tiles above the diagonal exit at once.
+constexpr int SY_WM = 4, SY_WN = 4, SY_BM = 2, SY_BN = 2, SY_KC = 8;
 constexpr int SY_THREADS = 64 * SY_WM * SY_WN, SY_TM = SY_WM * SY_BM * 16, SY_TN = SY_WN * SY_BN * 16;
 constexpr int SY_Q = SY_TM / SY_TN, SY_KCP = SY_KC + 2, SY_RPP = SY_THREADS / SY_KC;
 constexpr int SY_PA = SY_TM / SY_RPP, SY_PB = SY_TN / SY_RPP, SY_KS = SY_KC / 4;
@@ -272,9 +274,10 @@ __device__ inline void syrk_tile_of(int64_t t, int64_t& bi, int64_t& bj) {
   bi = b;
   bj = t - SY_Q * b * (b + 1) / 2;
 }
-static inline int64_t syrk_tiles(int64_t nbr) { return SY_Q * nbr * (nbr + 1) / 2; }
+__host__ __device__ inline int64_t syrk_tiles(int64_t nbr) { return SY_Q * nbr * (nbr + 1) / 2; }
+constexpr int kXcds = 8;
 
-__global__ __launch_bounds__(SY_THREADS, 1) void k_syrk_tile(SyrkArgs a) {
+__global__ __launch_bounds__(SY_THREADS) void k_syrk_tile(SyrkArgs a) {
   __shared__ double sA[2][SY_TM][SY_KCP];
   __shared__ double sB[2][SY_TN][SY_KCP];
   int64_t bi, bj;
@@ -282,7 +285,11 @@ __global__ __launch_bounds__(SY_THREADS, 1) void k_syrk_tile(SyrkArgs a) {
     bj = blockIdx.x % a.nbc;
     bi = blockIdx.x / a.nbc;
   } else {
-    syrk_tile_of(blockIdx.x, bi, bj);
+    // the grid is the tile count rounded up to a multiple of kXcds
+    const int64_t per = gridDim.x / kXcds, t = (blockIdx.x % kXcds) * per + blockIdx.x / kXcds;
+    const int64_t nbr = (a.R - a.base + SY_TM - 1) / SY_TM;
+    if (t >= syrk_tiles(nbr)) return;
+    syrk_tile_of(t, bi, bj);
   }
   const int64_t r0 = a.base + bi * SY_TM, c0 = a.base + bj * SY_TN;
   // nothing to do above the diagonal or right of the last column; a column block starting at
@@ -427,7 +434,8 @@ int64_t cholesky(int64_t R, double* G, void* ws, size_t ws_bytes, void* stream, 
       sa.col_end = R;
       sa.nbc = 0;
       const int64_t nbr = (R - panel_end + SY_TM - 1) / SY_TM;
-      hipLaunchKernelGGL(k_syrk_tile, dim3((unsigned)syrk_tiles(nbr)), dim3(SY_THREADS), 0, S(stream), sa);
+      const int64_t grid = (syrk_tiles(nbr) + kXcds - 1) / kXcds * kXcds;
+      hipLaunchKernelGGL(k_syrk_tile, dim3((unsigned)grid), dim3(SY_THREADS), 0, S(stream), sa);
       check_launch("k_syrk_tile(trailing)");
     }
   }
