@@ -465,6 +465,25 @@ def main():
     k1_bytes = float(N) * (3 + SR) * 4
     # data error of the reconstruction, FP64 sums on the device
     s_err, s_v = fst.fst_eval_error(gm_fit, x, y, z, v)
+    # preview of the fitted model on a 512^3 FP32 grid (Sec. 6): mode products, bound by
+    # writing the grid; algorithmic bytes = the grid out + the r1 x n2 n3 intermediate in and out
+    NG = 512
+    gaxes = [torch.linspace(-1.0, 1.0, NG, dtype=torch.float32, device=dev) for _ in range(3)]
+    grid_out = torch.empty((NG, NG, NG), dtype=torch.float32, device=dev)
+    grid_ws = torch.empty(max(int(fst._fn["fst_eval_grid_workspace_bytes"](gm_fit.handle, fst.FST_F32, NG, NG, NG)), 256),
+                          dtype=torch.uint8, device=dev)
+    grid_ms = []
+    for i in range(4):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        fst.fst_eval_grid(gm_fit, *gaxes, out=grid_out, ws=grid_ws)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        if i:
+            grid_ms.append(e0.elapsed_time(e1))
+    t_grid = float(np.median(grid_ms)) / 1e3
+    grid_bytes = float(NG) ** 3 * 4 + 2.0 * m0.rank[0] * NG * NG * 4
+    del grid_out, grid_ws
 
     avg = {k: float(np.mean(vv)) for k, vv in times.items()}
     t_rows = avg["k1"] + avg["gram"] + avg["atv"]
@@ -506,7 +525,11 @@ def main():
                 "bound": "alu", "achieved": eval_flops / avg["eval"] / 1e12, "peak": 157.3, "unit": "TFLOP/s",
                 "frac": eval_flops / avg["eval"] / 157.3e12, "flops_per_launch": eval_flops,
                 "note": "FP32 vector peak; packed FP32 is disabled by the build rules, so 78.6 TFLOP/s is the "
-                        "attainable scalar-FMA ceiling"}},
+                        "attainable scalar-FMA ceiling"},
+            "grid preview 512^3 FP32 (fst_eval_grid: k_factor_eval + 3 x k_mode_product)": {
+                "bound": "hbm", "achieved": grid_bytes / t_grid / 1e9, "peak": 8000.0, "unit": "GB/s",
+                "frac": grid_bytes / t_grid / 8e12, "ms": t_grid * 1e3, "bytes_per_launch": grid_bytes,
+                "grid_points_per_s": float(NG) ** 3 / t_grid}},
         "roofline": {"kernel": "k_gram<float>" if args.precision == "f32" else f"k_gram_lp<{args.precision}>",
                      "bound": "mfma", "achieved": achieved / 1e12,
                      "peak": peak / 1e12, "unit": "TFLOP/s", "frac": achieved / peak,

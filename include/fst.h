@@ -128,6 +128,23 @@ fst_status fst_refit_core(const fst_model* m, int32_t dtype, int64_t n, const vo
 fst_status fst_eval(const fst_model* m, int32_t dtype, int64_t n, const void* x,
                     const void* y, const void* z, void* out, void* stream);
 
+/* Preview on a tensor grid (Sec. 6, fast visualisation): out[(i1 n2 + i2) n3 + i3] =
+ * f(gx[i1], gy[i2], gz[i3]) with f the model of eq. (1), formed as the mode products
+ * alpha x_1 U1 x_2 U2 x_3 U3 of the core with the factor functions (eq. (2)) evaluated once
+ * per grid line, at 2 r1 flop per grid point instead of 2 R.  A 2-D slice is a grid with one
+ * count equal to 1.  gx, gy, gz: device coordinate arrays of `dtype` (FST_F32 or FST_F64) of
+ * lengths n1, n2, n3 >= 1 (any order, any spacing); out: device array of `dtype` with
+ * n1 n2 n3 entries, C order (i3 fastest), owned by the caller.  Intermediates and output
+ * are computed in `dtype`.  ws: device workspace >= fst_eval_grid_workspace_bytes (NULL: the
+ * library allocates and synchronises `stream` before freeing it); otherwise asynchronous.
+ * FST_E_INVAL for a count below 1 or above 2^31 - 1; FST_E_UNSUPPORTED for more than
+ * 65535 x 32 grid lines along one axis. */
+size_t fst_eval_grid_workspace_bytes(const fst_model* m, int32_t dtype, int64_t n1, int64_t n2,
+                                     int64_t n3);
+fst_status fst_eval_grid(const fst_model* m, int32_t dtype, const void* gx, int64_t n1,
+                         const void* gy, int64_t n2, const void* gz, int64_t n3, void* out,
+                         void* ws, size_t ws_bytes, void* stream);
+
 /* Data error of the reconstruction (the scattered analogue of the precision of Sec. 4.1):
  * sums_out (host double[2]) receives sum_i (v_i - f(x_i))^2 and sum_i v_i^2, accumulated in
  * FP64 in a fixed order, so ||v - f|| / ||v|| = sqrt(sums_out[0] / sums_out[1]).  v: device

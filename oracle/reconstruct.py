@@ -54,6 +54,17 @@ def evaluate_on_grid(model: Model, grid) -> np.ndarray:
     return Y
 
 
+def evaluate_tensor_grid(model: Model, gx, gy, gz) -> np.ndarray:
+    """Reconstruction on the tensor grid gx x gy x gz of physical coordinates (Sec. 6 preview
+    form): alpha x_1 U1 x_2 U2 x_3 U3 with U_k = Phi_k(xi_k(g_k)) C_k, the factor functions of
+    eq. (2) at the grid lines of mode k.  Returns an (n1, n2, n3) array."""
+    Y = np.asarray(model.core, np.float64)
+    for k, g in enumerate((gx, gy, gz)):
+        t = to_reference(np.asarray(g, np.float64), model.lo[k], model.hi[k])
+        Y = mode_product(Y, legendre_orthonormal(t, model.degree[k]) @ model.coefs[k], k)
+    return Y
+
+
 def rel_l2(x, ref) -> float:
     """||x - ref||_2 / ||ref||_2."""
     x = np.asarray(x, np.float64).reshape(-1)

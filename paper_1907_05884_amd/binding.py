@@ -78,6 +78,8 @@ _lib_fns = dict(
     fst_eval=(_i32, _vp, _i32, _i64, _vp, _vp, _vp, _vp, _vp),
     fst_factor_eval=(_i32, _vp, _i32, _i64, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp),
     fst_eval_error_workspace_bytes=(C.c_size_t, _i32, _i64),
+    fst_eval_grid_workspace_bytes=(C.c_size_t, _vp, _i32, _i64, _i64, _i64),
+    fst_eval_grid=(_i32, _vp, _i32, _vp, _i64, _vp, _i64, _vp, _i64, _vp, _vp, C.c_size_t, _vp),
     fst_eval_error=(_i32, _vp, _i32, _i64, _vp, _vp, _vp, _vp, _vp, C.c_size_t, _vp, _vp),
     fst_gram_workspace_bytes=(C.c_size_t, _vp, _i64),
     fst_gram=(_i32, _vp, _i32, _i64, _vp, _vp, _i32, _vp, _vp, _vp, C.c_size_t, _vp),
@@ -434,6 +436,21 @@ def fst_eval_error(m: Model, x, y, z, v, ws=None, stream=None):
     _check(_fn["fst_eval_error"](m.handle, dt, n, _dev_ptr(x), _dev_ptr(y), _dev_ptr(z), _dev_ptr(v),
                                  _dev_ptr(ws), ws.numel(), _stream(stream), out.ctypes.data_as(C.c_void_p)))
     return float(out[0]), float(out[1])
+
+
+def fst_eval_grid(m: Model, gx, gy, gz, out=None, ws=None, stream=None):
+    """Model on the tensor grid gx x gy x gz (device coordinate tensors of one dtype):
+    returns out (n1, n2, n3), C order."""
+    torch = _torch()
+    dt = _dtype_code(gx)
+    n1, n2, n3 = gx.numel(), gy.numel(), gz.numel()
+    if out is None:
+        out = torch.empty((n1, n2, n3), dtype=gx.dtype, device=gx.device)
+    if ws is None:
+        ws = _workspace(int(_fn["fst_eval_grid_workspace_bytes"](m.handle, dt, n1, n2, n3)), gx.device)
+    _check(_fn["fst_eval_grid"](m.handle, dt, _dev_ptr(gx), n1, _dev_ptr(gy), n2, _dev_ptr(gz), n3,
+                                _dev_ptr(out), _dev_ptr(ws), ws.numel(), _stream(stream)))
+    return out
 
 
 # ------------------------------------------------------------------------------ per-step GPU

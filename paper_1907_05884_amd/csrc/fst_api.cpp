@@ -467,6 +467,46 @@ fst_status fst_eval(const fst_model* m, int32_t dtype, int64_t n, const void* x,
   FST_CATCH
 }
 
+static void check_grid_counts(int64_t n1, int64_t n2, int64_t n3) {
+  const int64_t lim = (int64_t(1) << 31) - 1;
+  if (n1 < 1 || n2 < 1 || n3 < 1 || n1 > lim || n2 > lim || n3 > lim)
+    fail(FST_E_INVAL, "grid counts must be in [1, 2^31 - 1]");
+  if (n1 > 65535LL * 32 || n2 > 65535LL * 32) fail(FST_E_UNSUPPORTED, "more than 65535 x 32 lines along one axis");
+}
+
+size_t fst_eval_grid_workspace_bytes(const fst_model* m, int32_t dtype, int64_t n1, int64_t n2, int64_t n3) {
+  if (!m || (dtype != FST_F64 && dtype != FST_F32) || n1 < 1 || n2 < 1 || n3 < 1) return 0;
+  return eval_grid_workspace_bytes(m, dtype, n1, n2, n3);
+}
+
+fst_status fst_eval_grid(const fst_model* m, int32_t dtype, const void* gx, int64_t n1, const void* gy, int64_t n2,
+                         const void* gz, int64_t n3, void* out, void* ws, size_t ws_bytes, void* stream) {
+  FST_TRY
+  set_last_error("");
+  check_model(m);
+  check_dtype(dtype);
+  check_grid_counts(n1, n2, n3);
+  if (!gx || !gy || !gz || !out) fail(FST_E_INVAL, "null coordinate or output array");
+  const size_t need = eval_grid_workspace_bytes(m, dtype, n1, n2, n3);
+  const DeviceModel& dm = device_model(m, dtype);
+  if (ws) {
+    if (ws_bytes < need) fail(FST_E_NOMEM, "eval_grid: workspace too small");
+    eval_grid(m, dm, dtype, gx, n1, gy, n2, gz, n3, out, ws, stream);
+  } else {
+    void* own = device_alloc(need);
+    try {
+      eval_grid(m, dm, dtype, gx, n1, gy, n2, gz, n3, out, own, stream);
+      stream_sync(stream);
+    } catch (...) {
+      device_free(own);
+      throw;
+    }
+    device_free(own);
+  }
+  return FST_OK;
+  FST_CATCH
+}
+
 size_t fst_eval_error_workspace_bytes(int32_t dtype, int64_t n) {
   if ((dtype != FST_F64 && dtype != FST_F32) || n < 0) return 0;
   return eval_error_workspace_bytes(dtype, n);

@@ -120,6 +120,9 @@ void launch_gram_batched(const std::vector<const fst_model*>& models, const std:
                          const std::vector<int64_t>& mrows, const std::vector<double*>& G, int prec, void* ws,
                          void* stream);
 size_t eval_error_workspace_bytes(int dtype, int64_t n);
+size_t eval_grid_workspace_bytes(const fst_model* m, int dtype, int64_t n1, int64_t n2, int64_t n3);
+void eval_grid(const fst_model* m, const DeviceModel& dm, int dtype, const void* gx, int64_t n1, const void* gy,
+               int64_t n2, const void* gz, int64_t n3, void* out, void* ws, void* stream);
 void eval_error(const fst_model* m, int dtype, int64_t n, const void* x, const void* y, const void* z,
                 const void* v, void* ws, size_t ws_bytes, void* stream, double out[2]);
 size_t solve_scratch_bytes(const fst_model* m, int64_t M);

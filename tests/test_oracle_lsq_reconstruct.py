@@ -11,7 +11,7 @@ from oracle.lsq import (design_rows, factor_values, normal_equations, refit_core
                         residual_normal, sample_rows, solve_cholesky, solve_lstsq)
 from oracle.model import Model, to_csc
 from oracle.reconstruct import (evaluate, evaluate_full_expansion, evaluate_on_grid,
-                                full_expansion_coefficients, rel_l2)
+                                evaluate_tensor_grid, full_expansion_coefficients, rel_l2)
 from oracle.sthosvd import tucker_full
 
 
@@ -161,6 +161,23 @@ def test_grid_evaluation_matches_pointwise():
     np.testing.assert_allclose(Y.reshape(-1), f, rtol=1e-12, atol=1e-13)
     F = [legendre_orthonormal(grid_nodes(I), m.degree[k]) @ m.coefs[k] for k, I in enumerate(grid)]
     np.testing.assert_allclose(Y, tucker_full(m.core, F), atol=1e-13)
+
+
+def test_tensor_grid_matches_pointwise_and_expansion():
+    # arbitrary (unsorted, uneven) axes on a non-unit box, including a 1-point axis (a slice):
+    # the mode-product form against eq. (1) point by point and against the full expansion
+    m = _model(seed=3, rank=(3, 4, 2), degree=(5, 4, 6), lo=(0, -2, 1), hi=(4, 1, 3))
+    rng = np.random.default_rng(7)
+    gx, gy, gz = rng.uniform(0, 4, 5), rng.uniform(-2, 1, 1), rng.uniform(1, 3, 4)
+    Y = evaluate_tensor_grid(m, gx, gy, gz)
+    assert Y.shape == (5, 1, 4)
+    P = np.stack(np.meshgrid(gx, gy, gz, indexing="ij"), axis=-1).reshape(-1, 3)
+    np.testing.assert_allclose(Y.reshape(-1), evaluate(m, P), rtol=1e-12, atol=1e-13)
+    np.testing.assert_allclose(Y.reshape(-1), evaluate_full_expansion(m, P), rtol=1e-11, atol=1e-12)
+    # on the reference grid nodes it is the equispaced preview form
+    grid = (4, 3, 5)
+    g = [m.lo[k] + (grid_nodes(grid[k]) + 1) * (m.hi[k] - m.lo[k]) / 2 for k in range(3)]
+    np.testing.assert_allclose(evaluate_tensor_grid(m, *g), evaluate_on_grid(m, grid), atol=1e-12)
 
 
 def test_storage_accounting_and_csc():
