@@ -78,6 +78,9 @@ typedef struct {
   int32_t  gram_prec;        /* FST_GRAM_* */
   int32_t  refine_steps;     /* FP64-residual iterative-refinement steps after the solve */
   int32_t  n_threads;        /* host threads for the host steps; 0 = all hardware threads */
+  double   eps;              /* > 0: ST-HOSVD ranks chosen from this compression precision
+                                (Sec. 4.1, Table 1; fst_sthosvd_eps), with rank[] as caps;
+                                0: the fixed ranks rank[] */
 } fst_fit_params;
 
 /* ------------------------------------------------------------------ library */
@@ -238,6 +241,17 @@ fst_status fst_idw_grid(const double* xi, const double* v, int64_t K, const int3
 fst_status fst_sthosvd(const double* T, const int32_t dims[3], const int32_t rank[3],
                        int32_t n_threads, double* core, double* const W[3],
                        double* const sigma[3]);
+
+/* ST-HOSVD with ranks chosen from a compression precision eps (Sec. 4.1, Table 1): in mode
+ * order 1, 2, 3, r_k is the smallest r with sum_{i > r} sigma_i^2 <= eps^2 ||T||_F^2 / 3 over
+ * the singular values of the current (already truncated) unfolding, which guarantees
+ * ||T - T~||_F <= eps ||T||_F; r_k is capped at max_rank[k] (the guarantee then need not
+ * hold).  0 < eps < 1.  rank_out: host int32[3], the chosen ranks; core: host FP64 of at least
+ * max_rank[0] max_rank[1] max_rank[2] entries, receives r1 r2 r3 (C order); W[k]: host FP64 of
+ * at least I_k max_rank[k] entries, receives I_k x r_k row-major; sigma as fst_sthosvd. */
+fst_status fst_sthosvd_eps(const double* T, const int32_t dims[3], double eps,
+                           const int32_t max_rank[3], int32_t n_threads, int32_t rank_out[3],
+                           double* core, double* const W[3], double* const sigma[3]);
 
 /* Sparse Legendre fit of the columns of W (Sec. 4.2): orthogonal matching pursuit with
  * normalised correlations, support size chosen by the smallest leave-one-out (PRESS) error.

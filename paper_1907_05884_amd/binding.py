@@ -44,7 +44,7 @@ class fst_fit_params(C.Structure):
                 ("grid", C.c_int32 * 3), ("rank", C.c_int32 * 3), ("degree", C.c_int32 * 3),
                 ("interp_fraction", C.c_double), ("idw_k", C.c_int32), ("idw_power", C.c_double),
                 ("n_samples", C.c_int64), ("seed", C.c_uint64), ("gram_prec", C.c_int32),
-                ("refine_steps", C.c_int32), ("n_threads", C.c_int32)]
+                ("refine_steps", C.c_int32), ("n_threads", C.c_int32), ("eps", C.c_double)]
 
 
 _vp, _i64, _i32, _dp = C.c_void_p, C.c_int64, C.c_int32, C.POINTER(C.c_double)
@@ -93,6 +93,7 @@ _lib_fns = dict(
     fst_sample_indices=(_i32, C.c_uint64, _i32, _i64, _i64, _vp),
     fst_idw_grid=(_i32, _vp, _vp, _i64, _vp, _i32, C.c_double, _i32, _vp),
     fst_sthosvd=(_i32, _vp, _vp, _vp, _i32, _vp, _vp, _vp),
+    fst_sthosvd_eps=(_i32, _vp, _vp, C.c_double, _vp, _i32, _vp, _vp, _vp, _vp),
     fst_sparse_fit=(_i32, _vp, _i32, _i32, _i32, _vp),
     fst_model_from_parts=(_i32, _vp, _vp, _vp, _vp, _vp, _vp, C.POINTER(_vp)),
     fst_model_free=(None, _vp),
@@ -182,7 +183,7 @@ def _workspace(nbytes: int, device):
 
 def make_params(dtype=FST_F64, lo=(-1.0,) * 3, hi=(1.0,) * 3, grid=(32,) * 3, rank=(8,) * 3,
                 degree=(15,) * 3, interp_fraction=0.10, idw_k=8, idw_power=2.0, n_samples=2000,
-                seed=1, gram_prec=None, refine_steps=0, n_threads=0) -> fst_fit_params:
+                seed=1, gram_prec=None, refine_steps=0, n_threads=0, eps=0.0) -> fst_fit_params:
     p = fst_fit_params()
     _fn["fst_fit_params_default"](C.byref(p))
     p.dtype = dtype
@@ -199,6 +200,7 @@ def make_params(dtype=FST_F64, lo=(-1.0,) * 3, hi=(1.0,) * 3, grid=(32,) * 3, ra
     p.gram_prec = int(gram_prec)
     p.refine_steps = int(refine_steps)
     p.n_threads = int(n_threads)
+    p.eps = float(eps)
     return p
 
 
@@ -574,6 +576,27 @@ def fst_sthosvd(T, rank, n_threads=0):
     _check(_fn["fst_sthosvd"](T_p, dims.ctypes.data_as(C.c_void_p), r_p, int(n_threads),
                               core.ctypes.data_as(C.c_void_p), Wp, Sp))
     return core, W, S
+
+
+def fst_sthosvd_eps(T, eps: float, max_rank, n_threads=0):
+    """ST-HOSVD with ranks from the precision eps (capped at max_rank): returns
+    (ranks, core, [W1, W2, W3], [sigma1, sigma2, sigma3])."""
+    T_a, T_p = _host(T, np.float64)
+    dims = np.asarray(T_a.shape, dtype=np.int32)
+    mr = np.asarray(max_rank, dtype=np.int32)
+    core = np.empty(int(np.prod(mr)), dtype=np.float64)
+    W = [np.empty(int(dims[k]) * int(mr[k]), dtype=np.float64) for k in range(3)]
+    S = [np.empty(int(dims[k]), dtype=np.float64) for k in range(3)]
+    ranks = np.zeros(3, dtype=np.int32)
+    Wp = (C.c_void_p * 3)(*[w.ctypes.data_as(C.c_void_p) for w in W])
+    Sp = (C.c_void_p * 3)(*[s.ctypes.data_as(C.c_void_p) for s in S])
+    _check(_fn["fst_sthosvd_eps"](T_p, dims.ctypes.data_as(C.c_void_p), float(eps), mr.ctypes.data_as(C.c_void_p),
+                                  int(n_threads), ranks.ctypes.data_as(C.c_void_p),
+                                  core.ctypes.data_as(C.c_void_p), Wp, Sp))
+    r = tuple(int(v) for v in ranks)
+    core = core[:r[0] * r[1] * r[2]].reshape(r)
+    W = [W[k][:int(dims[k]) * r[k]].reshape(int(dims[k]), r[k]) for k in range(3)]
+    return r, core, W, S
 
 
 def fst_sparse_fit(W, p: int) -> np.ndarray:

@@ -76,6 +76,7 @@ static void validate_params(const fst_fit_params* p, int64_t n) {
     fail(FST_E_INVAL, "Algorithm 2 needs r1 r2 r3 < n_samples <= n (more sampled rows than core entries)");
   if (llround(p->interp_fraction * (double)n) < 1) fail(FST_E_INVAL, "interpolation subset is empty");
   if (p->refine_steps < 0 || p->refine_steps > 100) fail(FST_E_INVAL, "refine_steps must be in [0, 100]");
+  if (!(p->eps >= 0.0 && p->eps < 1.0)) fail(FST_E_INVAL, "eps must be in [0, 1)");
 }
 
 // --------------------------------------------------------------------------- refit layout
@@ -303,15 +304,37 @@ static fst_model* compress_from_subset(const fst_fit_params* p, const std::vecto
   const int64_t nodes = (int64_t)p->grid[0] * p->grid[1] * p->grid[2];
   std::vector<double> T((size_t)nodes);
   idw_grid(xi.data(), v.data(), K, p->grid, p->idw_k, p->idw_power, p->n_threads, T.data());
-  std::unique_ptr<fst_model> m(model_new(p->lo, p->hi, p->rank, p->degree));
+  int32_t rank[3] = {p->rank[0], p->rank[1], p->rank[2]};
   std::vector<double> W[3];
   double* Wp[3];
   for (int k = 0; k < 3; ++k) {
     W[k].assign((size_t)p->grid[k] * p->rank[k], 0.0);
     Wp[k] = W[k].data();
   }
-  sthosvd(T.data(), p->grid, p->rank, p->n_threads, m->core.data(), Wp, nullptr);
-  for (int k = 0; k < 3; ++k) sparse_fit(W[k].data(), p->grid[k], p->rank[k], p->degree[k], m->coef[k].data());
+  std::vector<double> core((size_t)rank[0] * rank[1] * rank[2]);
+  if (p->eps > 0.0) {
+    // ranks from the precision, capped by rank[] (valid ranks by validation); a rank above
+    // the product of the other two would only add dependent design columns, so such ranks
+    // are lowered and the decomposition is taken again at the final ranks
+    int32_t r[3];
+    sthosvd_eps(T.data(), p->grid, p->eps, p->rank, p->n_threads, r, core.data(), Wp, nullptr);
+    bool lowered = false;
+    for (int pass = 0; pass < 3; ++pass)
+      for (int k = 0; k < 3; ++k) {
+        const int32_t lim = r[(k + 1) % 3] * r[(k + 2) % 3];
+        if (r[k] > lim) {
+          r[k] = lim;
+          lowered = true;
+        }
+      }
+    for (int k = 0; k < 3; ++k) rank[k] = r[k];
+    if (lowered) sthosvd(T.data(), p->grid, rank, p->n_threads, core.data(), Wp, nullptr);
+  } else {
+    sthosvd(T.data(), p->grid, rank, p->n_threads, core.data(), Wp, nullptr);
+  }
+  std::unique_ptr<fst_model> m(model_new(p->lo, p->hi, rank, p->degree));
+  std::copy(core.begin(), core.begin() + (size_t)rank[0] * rank[1] * rank[2], m->core.begin());
+  for (int k = 0; k < 3; ++k) sparse_fit(W[k].data(), p->grid[k], rank[k], p->degree[k], m->coef[k].data());
   return m.release();
 }
 
@@ -358,6 +381,7 @@ void fst_fit_params_default(fst_fit_params* p) {
   p->n_samples = 2000;
   p->seed = 1;
   p->gram_prec = FST_GRAM_F64;
+  p->eps = 0.0;
   p->refine_steps = 0;
   p->n_threads = 0;
 }
@@ -655,6 +679,17 @@ fst_status fst_idw_grid(const double* xi, const double* v, int64_t K, const int3
   for (int64_t i = 0; i < K; ++i)
     if (!std::isfinite(v[i])) fail(FST_E_INVAL, "non-finite value");
   idw_grid(xi, v, K, grid, k, power, n_threads, out);
+  return FST_OK;
+  FST_CATCH
+}
+
+fst_status fst_sthosvd_eps(const double* T, const int32_t dims[3], double eps, const int32_t max_rank[3],
+                           int32_t n_threads, int32_t rank_out[3], double* core, double* const W[3],
+                           double* const sigma[3]) {
+  FST_TRY
+  set_last_error("");
+  if (!T || !dims || !max_rank || !rank_out || !core || !W || !W[0] || !W[1] || !W[2]) fail(FST_E_INVAL, "null argument");
+  sthosvd_eps(T, dims, eps, max_rank, n_threads, rank_out, core, W, sigma);
   return FST_OK;
   FST_CATCH
 }

@@ -446,6 +446,50 @@ void sthosvd(const double* T, const int32_t dims[3], const int32_t rank[3], int 
   std::memcpy(core, Y.data(), sizeof(double) * Y.size());
 }
 
+// Ranks from a precision (Sec. 4.1, Table 1): the ST-HOSVD truncation rule that bounds the
+// error, ||T - T~||_F^2 <= sum_k sum_{i > r_k} sigma_i^(k)2 <= eps^2 ||T||_F^2, spread evenly
+// over the three modes: at step k, r_k is the smallest r with
+// sum_{i > r} sigma_i^2 <= eps^2 ||T||_F^2 / 3 over the singular values of the current
+// (already truncated) unfolding.  Ranks are capped at max_rank[k] (the bound then need not
+// hold).  W[k] receives I_k x r_k row-major, core r1 r2 r3.
+void sthosvd_eps(const double* T, const int32_t dims[3], double eps, const int32_t max_rank[3], int n_threads,
+                 int32_t rank_out[3], double* core, double* const W[3], double* const sigma[3]) {
+  (void)n_threads;
+  if (!(eps > 0.0 && eps < 1.0)) fail(FST_E_INVAL, "sthosvd_eps: need 0 < eps < 1");
+  int64_t d[3] = {dims[0], dims[1], dims[2]};
+  for (int k = 0; k < 3; ++k)
+    if (d[k] < 1 || max_rank[k] < 1) fail(FST_E_INVAL, "sthosvd_eps: need I_k >= 1 and max_rank_k >= 1");
+  const int64_t total = d[0] * d[1] * d[2];
+  std::vector<double> Y(T, T + total);
+  double norm2 = 0.0;
+  for (int64_t i = 0; i < total; ++i) norm2 += T[i] * T[i];
+  const double thr = eps * eps * norm2 / 3.0;
+  for (int k = 0; k < 3; ++k) {
+    int64_t L = 1;
+    for (int l = 0; l < 3; ++l)
+      if (l != k) L *= d[l];
+    const int cap = (int)std::min<int64_t>({(int64_t)max_rank[k], d[k], L});
+    std::vector<double> Wk, sig;
+    leading_left_singular(Y, d, k, cap, Wk, sig);
+    // tail[r] = sum_{i >= r} sigma_i^2 (0-based), summed from the smallest value up
+    const int ns = (int)sig.size();
+    std::vector<double> tail((size_t)ns + 1, 0.0);
+    for (int i = ns - 1; i >= 0; --i) tail[(size_t)i] = tail[(size_t)i + 1] + sig[(size_t)i] * sig[(size_t)i];
+    int r = 1;
+    while (r < ns && tail[(size_t)r] > thr) ++r;
+    r = std::min(r, cap);
+    rank_out[k] = r;
+    // the leading r of the cap columns (row-major I_k x cap -> I_k x r)
+    for (int64_t i = 0; i < d[k]; ++i)
+      for (int j = 0; j < r; ++j) W[k][(size_t)(i * r + j)] = Wk[(size_t)(i * cap + j)];
+    if (sigma && sigma[k])
+      for (int64_t i = 0; i < dims[k]; ++i) sigma[k][i] = i < (int64_t)sig.size() ? sig[(size_t)i] : 0.0;
+    std::vector<double> Wr(W[k], W[k] + d[k] * r);
+    mode_product_transposed(Y, d, k, Wr, r);
+  }
+  std::memcpy(core, Y.data(), sizeof(double) * Y.size());
+}
+
 // ------------------------------------------------------------------------------ sparse fit
 void legendre_orthonormal_host(double t, int p, double* phi) {
   // Bonnet recurrence (m+1) P_{m+1} = (2m+1) t P_m - m P_{m-1}, then phi_m = sqrt(2m+1) P_m

@@ -76,6 +76,8 @@ void idw_apply(const std::vector<int64_t>& nbr, const std::vector<double>& wgt, 
                int k, const double* v, int n_threads, double* out);
 void sthosvd(const double* T, const int32_t dims[3], const int32_t rank[3], int n_threads,
              double* core, double* const W[3], double* const sigma[3]);
+void sthosvd_eps(const double* T, const int32_t dims[3], double eps, const int32_t max_rank[3], int n_threads,
+                 int32_t rank_out[3], double* core, double* const W[3], double* const sigma[3]);
 void sparse_fit(const double* W, int I, int r, int p, double* C);
 void legendre_orthonormal_host(double t, int p, double* phi);
 int hardware_threads(int requested);

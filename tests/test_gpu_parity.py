@@ -275,6 +275,24 @@ def test_fit_end_to_end_fp64(dev):
     assert abs(err_gpu - err_ref) <= 1e-8 * err_ref + 1e-12
 
 
+def test_fit_with_ranks_from_precision(dev):
+    # Algorithm 1 with ranks chosen from eps (Sec. 4.1, Table 1), then Algorithm 2: the ranks
+    # the oracle's rule picks on its interpolated grid, and the oracle's fit at those ranks
+    from oracle.sthosvd import ranks_for_precision
+    w = datagen.small_f64()
+    eps, caps = 0.1, (10, 10, 10)
+    T = pipeline.compress(w.pts, w.vals, w.lo, w.hi, w.grid, (1, 1, 1), w.degree, w.interp_fraction,
+                          w.seed).info["grid_tensor"]
+    r = tuple(min(a, c) for a, c in zip(ranks_for_precision(T, eps), caps))
+    p = fst.make_params(dtype=fst.FST_F64, lo=w.lo, hi=w.hi, grid=w.grid, rank=caps, degree=w.degree,
+                        interp_fraction=w.interp_fraction, n_samples=w.n_samples, seed=w.seed, eps=eps)
+    x, y, z, v = [D(a, dev) for a in w.soa()]
+    gm = fst.fst_fit(p, x, y, z, v)
+    assert gm.info()["rank"] == r
+    mo = pipeline.fit(w.pts, w.vals, w.lo, w.hi, w.grid, r, w.degree, w.interp_fraction, w.n_samples, w.seed)
+    assert rel_l2(gm.core, mo.core) <= 1e-6
+
+
 def test_refit_rejects_too_few_samples_and_solves_rank_one_design(dev):
     om, gm = _models(20, (4, 4, 4), (6, 6, 6))
     pts = _pts(21, 500)

@@ -12,6 +12,7 @@ import datagen
 from oracle import interp, pipeline, sampler, sparsefit, sthosvd
 from oracle.basis import legendre_orthonormal
 from oracle.model import Model as OModel
+from oracle.sthosvd import ranks_for_precision, st_hosvd, tucker_full
 
 fst = pytest.importorskip("paper_1907_05884_amd.binding")
 
@@ -114,6 +115,57 @@ def test_compress_host_matches_oracle_small():
         Ck, Co = m.coefs(k), mo.coefs[k]
         np.testing.assert_array_equal(Ck != 0, Co != 0)
         np.testing.assert_allclose(Ck, Co, rtol=1e-7, atol=1e-9)
+
+
+def _decaying_tensor(seed, dims, core_dims):
+    # full multilinear rank core_dims with entries decaying like 10^(-(a+b+c)/3), rotated by
+    # random orthonormal factors: the singular values of every unfolding decay steadily
+    rng = np.random.default_rng(seed)
+    a, b, c = np.meshgrid(*[np.arange(n) for n in core_dims], indexing="ij")
+    G = rng.standard_normal(core_dims) * 10.0 ** (-(a + b + c) / 3.0)
+    Q = [np.linalg.qr(rng.standard_normal((n, n)))[0][:, :m] for n, m in zip(dims, core_dims)]
+    return tucker_full(G, Q)
+
+
+@pytest.mark.parametrize("eps", [1e-1, 1e-2, 3e-3, 1e-6])
+def test_sthosvd_eps_matches_oracle_and_meets_precision(eps):
+    # ranks from the precision (Sec. 4.1, Table 1): the library's rule against the oracle's,
+    # the decomposition at those ranks against the oracle's, and ||T - T~|| <= eps ||T||
+    T = _decaying_tensor(0, (20, 18, 16), (10, 9, 7))
+    r, core, W, _ = fst.fst_sthosvd_eps(T, eps, (20, 18, 16))
+    assert r == ranks_for_precision(T, eps)
+    c_o, W_o, _ = st_hosvd(T, r)
+    np.testing.assert_allclose(core, c_o, atol=1e-10)
+    for k in range(3):
+        np.testing.assert_allclose(W[k], W_o[k], atol=1e-10)
+    assert np.linalg.norm(T - tucker_full(core, W)) <= eps * np.linalg.norm(T) * (1 + 1e-12)
+
+
+def test_sthosvd_eps_caps_and_errors():
+    T = _decaying_tensor(1, (12, 11, 10), (8, 8, 8))
+    r, core, W, _ = fst.fst_sthosvd_eps(T, 1e-8, (4, 5, 3))
+    assert r == (4, 5, 3)
+    c_o, _, _ = st_hosvd(T, r)
+    np.testing.assert_allclose(core, c_o, atol=1e-10)
+    for bad in (0.0, 1.0, -1e-3):
+        with pytest.raises(fst.FstError):
+            fst.fst_sthosvd_eps(T, bad, (4, 4, 4))
+
+
+def test_compress_host_with_eps_ranks_matches_oracle():
+    # Algorithm 1 with ranks from the precision: the ranks the oracle's rule picks on the
+    # oracle's interpolated grid (identical to the library's grid), capped by rank[]
+    w = datagen.small_f64(n=6000, n_samples=1500)
+    grid, degree, caps, eps = (16, 16, 16), (11, 11, 11), (10, 10, 10), 0.1
+    p = fst.make_params(dtype=fst.FST_F64, lo=w.lo, hi=w.hi, grid=grid, rank=caps, degree=degree,
+                        interp_fraction=0.2, n_samples=1500, seed=w.seed, eps=eps)
+    m = fst.fst_compress_host(p, *w.soa())
+    T = pipeline.compress(w.pts, w.vals, w.lo, w.hi, grid, (1, 1, 1), degree, 0.2, w.seed).info["grid_tensor"]
+    r = ranks_for_precision(T, eps)
+    assert all(1 <= r[k] <= caps[k] for k in range(3)) and all(r[k] <= r[(k + 1) % 3] * r[(k + 2) % 3] for k in range(3))
+    assert m.info()["rank"] == r
+    mo = pipeline.compress(w.pts, w.vals, w.lo, w.hi, grid, r, degree, 0.2, w.seed)
+    np.testing.assert_allclose(m.core, mo.core, rtol=1e-8, atol=1e-9)
 
 
 def test_model_parts_roundtrip_and_serialisation():
