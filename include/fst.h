@@ -112,6 +112,25 @@ fst_status fst_fit(const fst_fit_params* p, int64_t n, const void* x, const void
 fst_status fst_compress_host(const fst_fit_params* p, int64_t n, const void* x, const void* y,
                              const void* z, const void* v, fst_model** out);
 
+/* Algorithm 2 with its randomised mixing (steps 2-4): the design matrix W of all n points
+ * and the values u are multiplied by random signs D (SplitMix64 stream 5 of `seed`: row i is
+ * negated when the top bit of output i is set) and mixed by the normalised Walsh-Hadamard
+ * transform F = H_N / sqrt(N) (Sylvester order; the real orthogonal stand-in for the FFT of
+ * the paper), N the smallest power of two >= max(n, 4096), rows n .. N-1 zero; n_samples rows
+ * of [0, N) are drawn uniformly without replacement (stream FST_STREAM_LS) and the core solves
+ * the normal equations of those rows of F D W, F D u by an FP64 Cholesky factorisation.  Rows
+ * and Gram are formed in the point dtype (FP32: FP32 MFMA with FP64 folding; FP64: FP64
+ * MFMA); no refinement (the mixed rows are not regenerated in FP64).  x, y, z, v: device
+ * arrays of n <= 2^23 points.  ws: device workspace >= fst_refit_core_mixed_workspace_bytes,
+ * or NULL.  Synchronises `stream`; *out receives a new model (FST_E_NOT_SPD if the sampled
+ * Gram is not positive definite). */
+size_t fst_refit_core_mixed_workspace_bytes(const fst_model* m, int32_t dtype, int64_t n,
+                                            int64_t n_samples);
+fst_status fst_refit_core_mixed(const fst_model* m, int32_t dtype, int64_t n, const void* x,
+                                const void* y, const void* z, const void* v, int64_t n_samples,
+                                uint64_t seed, void* ws, size_t ws_bytes, void* stream,
+                                fst_model** out);
+
 /* Device workspace (bytes) of fst_refit_core for a model, point dtype, M and refinement. */
 size_t fst_refit_workspace_bytes(const fst_model* m, int32_t dtype, int64_t n_samples,
                                  int32_t refine_steps);

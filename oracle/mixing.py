@@ -10,7 +10,9 @@ Readings taken (the paper fixes none of them):
 * F is the normalised Walsh-Hadamard transform H_N / sqrt(N) in Sylvester order,
   H[i][k] = (-1)^popcount(i & k), the real orthogonal fast transform with the same mixing
   property as the FFT the paper names (the subsampled randomized Hadamard transform).  N is
-  the smallest power of two >= n; rows n .. N-1 of W and u are zero before mixing.
+  the smallest power of two >= max(n, 4096) (``mixed_length``; a floor of 4096 rows keeps
+  the transform in whole blocks and changes nothing but the count of zero rows); rows
+  n .. N-1 of W and u are zero before mixing.
 * D: sign of row i is -1 when the top bit of output i of SplitMix64 stream 5 is set
   (stream_state(seed, 5); outputs numbered from 0 as in ``sampler``), +1 otherwise.
 * S: S distinct rows of [0, N), uniformly without replacement and sorted (stream 2, as the
@@ -34,6 +36,10 @@ def next_pow2(n: int) -> int:
     while N < n:
         N *= 2
     return N
+
+
+def mixed_length(n: int) -> int:
+    return max(4096, next_pow2(n))
 
 
 def signs(seed: int, N: int) -> np.ndarray:
@@ -64,7 +70,7 @@ def mixed_problem(model: Model, pts: np.ndarray, vals: np.ndarray, n_samples: in
     pts = np.asarray(pts, np.float64)
     vals = np.asarray(vals, np.float64)
     n = pts.shape[0]
-    N = next_pow2(n)
+    N = mixed_length(n)
     W = design_rows(factor_values(model, pts))
     Wp = np.zeros((N, W.shape[1]))
     Wp[:n] = W

@@ -79,6 +79,9 @@ _lib_fns = dict(
     fst_factor_eval=(_i32, _vp, _i32, _i64, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp),
     fst_eval_error_workspace_bytes=(C.c_size_t, _i32, _i64),
     fst_eval_grid_workspace_bytes=(C.c_size_t, _vp, _i32, _i64, _i64, _i64),
+    fst_refit_core_mixed_workspace_bytes=(C.c_size_t, _vp, _i32, _i64, _i64),
+    fst_refit_core_mixed=(_i32, _vp, _i32, _i64, _vp, _vp, _vp, _vp, _i64, C.c_uint64, _vp, C.c_size_t, _vp,
+                          C.POINTER(_vp)),
     fst_eval_grid=(_i32, _vp, _i32, _vp, _i64, _vp, _i64, _vp, _i64, _vp, _vp, C.c_size_t, _vp),
     fst_eval_error=(_i32, _vp, _i32, _i64, _vp, _vp, _vp, _vp, _vp, C.c_size_t, _vp, _vp),
     fst_gram_workspace_bytes=(C.c_size_t, _vp, _i64),
@@ -347,6 +350,20 @@ def fst_refit_core(m: Model, x, y, z, v, n_samples: int, seed: int, gram_prec=No
     _check(_fn["fst_refit_core"](m.handle, dt, n, _dev_ptr(x), _dev_ptr(y), _dev_ptr(z), _dev_ptr(v),
                                  int(n_samples), int(seed), int(gram_prec), int(refine_steps),
                                  _dev_ptr(ws), ws.numel(), _stream(stream), C.byref(h)))
+    return Model(h)
+
+
+def fst_refit_core_mixed(m: Model, x, y, z, v, n_samples: int, seed: int, ws=None, stream=None) -> Model:
+    """Algorithm 2 with its randomised mixing (sign flips, Walsh-Hadamard transform, uniform
+    row sampling): re-estimates the core of m from n_samples mixed rows."""
+    dt = _dtype_code(x)
+    n = x.numel()
+    if ws is None:
+        ws = _workspace(int(_fn["fst_refit_core_mixed_workspace_bytes"](m.handle, dt, n, int(n_samples))), x.device)
+    h = C.c_void_p()
+    _check(_fn["fst_refit_core_mixed"](m.handle, dt, n, _dev_ptr(x), _dev_ptr(y), _dev_ptr(z), _dev_ptr(v),
+                                       int(n_samples), int(seed), _dev_ptr(ws), ws.numel(), _stream(stream),
+                                       C.byref(h)))
     return Model(h)
 
 

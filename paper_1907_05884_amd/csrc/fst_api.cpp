@@ -240,6 +240,61 @@ static fst_model* copy_with_core(const fst_model* m, const std::vector<double>& 
   return out;
 }
 
+// Algorithm 2 with mixing: workspace = G, h, alpha, Cholesky scratch, then the mixed rows
+struct MixedRefitLayout {
+  size_t G, h, alpha, chol, mix, total;
+};
+static MixedRefitLayout mixed_refit_layout(const fst_model* m, int dtype, int64_t n, int64_t M) {
+  const int64_t R = m->R();
+  MixedRefitLayout L;
+  size_t off = 0;
+  L.G = off;
+  off += align_up(sizeof(double) * (size_t)R * (size_t)R);
+  L.h = off;
+  off += align_up(sizeof(double) * (size_t)R);
+  L.alpha = off;
+  off += align_up(sizeof(double) * (size_t)R);
+  L.chol = off;
+  off += align_up(cholesky_workspace_bytes(R));
+  L.mix = off;
+  off += mixed_workspace_bytes(m, dtype, n, M);
+  L.total = off;
+  return L;
+}
+
+static fst_model* refit_mixed_impl(const fst_model* m, int dtype, int64_t n, const void* x, const void* y,
+                                   const void* z, const void* v, int64_t M, uint64_t seed, void* ws_user,
+                                   size_t ws_bytes, void* stream) {
+  check_model(m);
+  check_dtype(dtype);
+  const int64_t R = m->R();
+  if (n < 1 || n > (int64_t(1) << 23)) fail(FST_E_INVAL, "the mixed refit needs 1 <= n <= 2^23 points");
+  if (M <= R || M > mixed_length(n)) fail(FST_E_INVAL, "the mixed refit needs r1 r2 r3 < n_samples <= N");
+  for (int k = 0; k < 3; ++k)
+    if (m->rank[k] > m->degree[k] + 1) fail(FST_E_INVAL, "Algorithm 2 needs rank <= degree + 1 in every mode");
+  if (!x || !y || !z || !v) fail(FST_E_INVAL, "null point or value array");
+  const MixedRefitLayout L = mixed_refit_layout(m, dtype, n, M);
+  Workspace ws(ws_user, ws_bytes, L.total);
+  char* base = (char*)ws.p;
+  double* d_G = (double*)(base + L.G);
+  double* d_h = (double*)(base + L.h);
+  double* d_alpha = (double*)(base + L.alpha);
+  mixed_normal_equations(m, dtype, n, x, y, z, v, M, seed, base + L.mix, ws.bytes - L.mix, d_G, d_h, stream);
+  const int64_t piv = cholesky(R, d_G, base + L.chol, cholesky_workspace_bytes(R), stream);
+  if (piv != 0)
+    fail(FST_E_NOT_SPD, "mixed refit: Cholesky breakdown at pivot " + std::to_string(piv) +
+                            " (numerically rank-deficient sampled rows)");
+  cholesky_solve(R, d_G, d_h, d_alpha, stream);
+  std::vector<double> alpha((size_t)R);
+  copy_d2h(alpha.data(), d_alpha, sizeof(double) * (size_t)R, stream);
+  for (double t : alpha)
+    if (!std::isfinite(t)) fail(FST_E_NOT_SPD, "mixed refit produced non-finite core values");
+  fst_model* out = copy_with_core(m, alpha);
+  out->fit.gram_prec = dtype == FST_F64 ? FST_GRAM_F64 : FST_GRAM_F32;
+  out->fit.refine_steps = 0;
+  return out;
+}
+
 static fst_model* refit_impl(const fst_model* m, int dtype, int64_t n, const void* x, const void* y,
                              const void* z, const void* v, int64_t M, uint64_t seed, int gram_prec,
                              int refine, void* ws_user, size_t ws_bytes, void* stream) {
@@ -527,6 +582,22 @@ fst_status fst_eval_grid(const fst_model* m, int32_t dtype, const void* gx, int6
     }
     device_free(own);
   }
+  return FST_OK;
+  FST_CATCH
+}
+
+size_t fst_refit_core_mixed_workspace_bytes(const fst_model* m, int32_t dtype, int64_t n, int64_t n_samples) {
+  if (!m || (dtype != FST_F64 && dtype != FST_F32) || n < 1 || n > (int64_t(1) << 23) || n_samples < 1) return 0;
+  return mixed_refit_layout(m, dtype, n, n_samples).total;
+}
+
+fst_status fst_refit_core_mixed(const fst_model* m, int32_t dtype, int64_t n, const void* x, const void* y,
+                                const void* z, const void* v, int64_t n_samples, uint64_t seed, void* ws,
+                                size_t ws_bytes, void* stream, fst_model** out) {
+  FST_TRY
+  set_last_error("");
+  if (!out) fail(FST_E_INVAL, "null output");
+  *out = refit_mixed_impl(m, dtype, n, x, y, z, v, n_samples, seed, ws, ws_bytes, stream);
   return FST_OK;
   FST_CATCH
 }

@@ -122,6 +122,13 @@ void launch_gram_batched(const std::vector<const fst_model*>& models, const std:
                          const std::vector<int64_t>& mrows, const std::vector<double*>& G, int prec, void* ws,
                          void* stream);
 size_t eval_error_workspace_bytes(int dtype, int64_t n);
+// mixed least-squares rows (Algorithm 2 steps 2-4): normal equations of S sampled rows of
+// F D W and F D u into G (lower triangle) and h
+int64_t mixed_length(int64_t n);
+size_t mixed_workspace_bytes(const fst_model* m, int dtype, int64_t n, int64_t nsamp);
+void mixed_normal_equations(const fst_model* m, int dtype, int64_t n, const void* x, const void* y, const void* z,
+                            const void* v, int64_t nsamp, uint64_t seed, void* ws, size_t ws_bytes, double* G,
+                            double* h, void* stream);
 size_t eval_grid_workspace_bytes(const fst_model* m, int dtype, int64_t n1, int64_t n2, int64_t n3);
 void eval_grid(const fst_model* m, const DeviceModel& dm, int dtype, const void* gx, int64_t n1, const void* gy,
                int64_t n2, const void* gz, int64_t n3, void* out, void* ws, void* stream);

@@ -1,0 +1,414 @@
+// Mixed least-squares rows of Algorithm 2 (steps 1-5 with the randomised transform) for
+// gfx950: the design matrix W (N x R, rows past n zero) and the values u are multiplied by
+// random signs D and mixed by the normalised Walsh-Hadamard transform F = H_N / sqrt(N) (the
+// real orthogonal stand-in for the FFT), S rows of F D W and F D u are kept, and the normal
+// equations of that sampled problem are formed.
+//
+//   k_mix_lo     a design column (Khatri-Rao product of three factor rows, times the sign
+//                of each row) in blocks of 4096 rows: the 12 butterfly stages inside a block,
+//                4 of them in registers and 8 through LDS
+//   k_mix_hi     the remaining stages across blocks (strides 4096 .. N/2) through LDS, the
+//                1/sqrt(N) scale, and a scatter of the sampled rows into A^T
+//   k_gram_dense G = A^T A (lower triangle) from the materialised sampled rows, MFMA
+//   k_atv_dense  h = A^T b
+//
+// N is the smallest power of two >= max(n, 4096).  The transform of a column touches every
+// one of its N entries twice (one read and one write per pass), so the mixing is bound by
+// HBM; the Gram of the S x R sampled rows is the same MFMA work as the unmixed one, read from
+// a dense A^T instead of being formed from factor values.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <string>
+#include <vector>
+
+#include "fst_device.h"
+#include "fst_internal.h"
+
+namespace fst {
+
+constexpr int MX_B1 = 4096;        // rows of one block of the first pass
+constexpr int MX_THREADS = 256;
+constexpr int MX_MAX_LOG2N = 23;   // N <= 2^23 (the second pass holds 2^(log2 N - 12) rows per offset)
+constexpr int64_t kSignsStream = 5;
+
+// Output i (from 0) of the SplitMix64 stream started at `state`: mix(state + (i + 1) gamma);
+// the row sign is -1 when its top bit is set.
+__device__ inline int row_sign_negative(uint64_t state, int64_t i) {
+  uint64_t z = state + (uint64_t)(i + 1) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  z ^= z >> 31;
+  return (int)(z >> 63);
+}
+
+template <typename T>
+struct MixArgs {
+  const T* U;           // [SR][n] factor values at all points
+  const T* v;           // values (column R)
+  int64_t n, N, R;
+  int32_t r1, r2, r3, L, H;
+  int64_t c0;           // first design column of this chunk (column R is the values)
+  uint64_t sign_state;
+  T* buf;               // [ncols][N]
+  const int32_t* pos;   // [N]: position of row i among the samples, or -1
+  T* At;                // [R][Sp]
+  T* b;                 // [Sp]
+  int64_t Sp;
+  T scale;
+};
+
+template <typename T>
+__global__ __launch_bounds__(MX_THREADS) void k_mix_lo(MixArgs<T> a) {
+  __shared__ T s[MX_B1];
+  const int c = blockIdx.y, t = threadIdx.x;
+  const int64_t j = a.c0 + c, base = (int64_t)blockIdx.x * MX_B1;
+  const bool values = j >= a.R;
+  const T *p1 = a.U, *p2 = a.U, *p3 = a.U;
+  if (!values) {
+    const int64_t j3 = j % a.r3, j12 = j / a.r3;
+    p1 = a.U + (j12 / a.r2) * a.n;
+    p2 = a.U + (a.r1 + j12 % a.r2) * a.n;
+    p3 = a.U + (a.r1 + a.r2 + j3) * a.n;
+  }
+  T w[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    const int64_t i = base + t + 256 * k;
+    T x = T(0);
+    if (i < a.n) {
+      x = values ? a.v[i] : p1[i] * p2[i] * p3[i];
+      if (row_sign_negative(a.sign_state, i)) x = -x;
+    }
+    w[k] = x;
+  }
+  // strides 256 .. 2048 (bits 8 .. 11 of the row): partners among this thread's elements
+#pragma unroll
+  for (int sb = 0; sb < 4; ++sb)
+#pragma unroll
+    for (int k = 0; k < 16; ++k)
+      if (!(k & (1 << sb))) {
+        const T x = w[k], y = w[k | (1 << sb)];
+        w[k] = x + y;
+        w[k | (1 << sb)] = x - y;
+      }
+#pragma unroll
+  for (int k = 0; k < 16; ++k) s[t + 256 * k] = w[k];
+  __syncthreads();
+  // strides 1 .. 128 (bits 0 .. 7): 2048 disjoint pairs per stage, 8 per thread
+  for (int h = 1; h < 256; h <<= 1) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int p = t + 256 * q;
+      const int i0 = (p / h) * 2 * h + (p % h), i1 = i0 + h;
+      const T x = s[i0], y = s[i1];
+      s[i0] = x + y;
+      s[i1] = x - y;
+    }
+    __syncthreads();
+  }
+  T* out = a.buf + (int64_t)c * a.N + base;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) out[t + 256 * k] = s[t + 256 * k];
+}
+
+// Workgroup (x, c): offsets l0 .. l0 + L - 1 inside the 4096-row blocks, all K = 2^H blocks.
+template <typename T>
+__global__ __launch_bounds__(MX_THREADS) void k_mix_hi(MixArgs<T> a) {
+  extern __shared__ __align__(16) unsigned char mx_smem[];
+  T* s = reinterpret_cast<T*>(mx_smem);   // [K][L]
+  const int c = blockIdx.y;
+  const int64_t j = a.c0 + c;
+  const int L = a.L, K = 1 << a.H, E = K * L;
+  const int l0 = blockIdx.x * L;
+  const T* col = a.buf + (int64_t)c * a.N;
+  for (int e = threadIdx.x; e < E; e += MX_THREADS) {
+    const int k = e / L, l = e % L;
+    s[e] = col[(int64_t)k * MX_B1 + l0 + l];
+  }
+  __syncthreads();
+  for (int h = 1; h < K; h <<= 1) {
+    for (int p = threadIdx.x; p < E / 2; p += MX_THREADS) {
+      const int pk = p / L, l = p % L;
+      const int k0 = (pk / h) * 2 * h + (pk % h), k1 = k0 + h;
+      const T x = s[k0 * L + l], y = s[k1 * L + l];
+      s[k0 * L + l] = x + y;
+      s[k1 * L + l] = x - y;
+    }
+    __syncthreads();
+  }
+  for (int e = threadIdx.x; e < E; e += MX_THREADS) {
+    const int k = e / L, l = e % L;
+    const int p = a.pos[(int64_t)k * MX_B1 + l0 + l];
+    if (p >= 0) {
+      const T val = s[e] * a.scale;
+      if (j < a.R)
+        a.At[j * a.Sp + p] = val;
+      else
+        a.b[p] = val;
+    }
+  }
+}
+
+// zero entries [S, Sp) of every row of A^T and of b (the padding of the last K chunk)
+template <typename T>
+__global__ void k_zero_tail(T* At, T* b, int64_t R, int64_t S, int64_t Sp) {
+  const int64_t w = Sp - S;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (R + 1) * w) return;
+  const int64_t r = e / w, q = S + e % w;
+  if (r < R)
+    At[r * Sp + q] = T(0);
+  else
+    b[q] = T(0);
+}
+
+// G = A^T A for the lower triangle of 128 x 128 tiles: sixteen waves of 32 x 32 (2 x 2
+// MFMA blocks), KC points of the tile's 128 row-block and 128 column-block rows of A^T staged
+// through double-buffered LDS with 16-byte loads (rows of A^T are Sp long, Sp a multiple of
+// KC, so every chunk is whole).  As in the Khatri-Rao Gram, lane group g takes the points
+// g KC/4 + s, and FP32 accumulation is folded into FP64 registers every chunk.
+template <typename T> struct DenseKC;
+template <> struct DenseKC<float> { static constexpr int KC = 64; };
+template <> struct DenseKC<double> { static constexpr int KC = 32; };
+constexpr int GD_TILE = 128, GD_THREADS = 1024;
+
+template <typename T>
+__global__ __launch_bounds__(GD_THREADS) void k_gram_dense(const T* At, int64_t R, int64_t Sp, double* G) {
+  constexpr int KC = DenseKC<T>::KC, KCP = KC + 16 / (int)sizeof(T), VW = 16 / (int)sizeof(T);
+  constexpr int PIECES = 2 * GD_TILE * KC / VW / GD_THREADS;   // 16-byte pieces per thread per chunk
+  typedef T T4 __attribute__((ext_vector_type(4)));
+  typedef T TV __attribute__((ext_vector_type(16 / sizeof(T))));
+  typedef typename MfmaAcc<T>::V V;
+  constexpr bool kFold = sizeof(T) == 4;
+  __shared__ __align__(16) T sA[2][2 * GD_TILE][KCP];
+  int64_t bi, bj;
+  tri_tile(blockIdx.x, bi, bj);
+  const int64_t r0 = bi * GD_TILE, c0 = bj * GD_TILE;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wr = wave >> 2, wc = wave & 3, li = lane & 15, g = lane >> 4;
+  const int row0 = wr * 32, col0 = wc * 32;
+  const bool active = c0 + col0 <= r0 + row0 + 31;
+  TV pf[PIECES];
+  auto fetch = [&](int64_t k0) {
+#pragma unroll
+    for (int u = 0; u < PIECES; ++u) {
+      const int e = threadIdx.x + GD_THREADS * u;
+      const int r = e / (KC / VW), pc = e % (KC / VW);
+      const int64_t gr = r < GD_TILE ? r0 + r : c0 + (r - GD_TILE);
+      TV val = TV{};
+      if (gr < R) val = *reinterpret_cast<const TV*>(&At[gr * Sp + k0 + pc * VW]);
+      pf[u] = val;
+    }
+  };
+  auto stash = [&](int b) {
+#pragma unroll
+    for (int u = 0; u < PIECES; ++u) {
+      const int e = threadIdx.x + GD_THREADS * u;
+      const int r = e / (KC / VW), pc = e % (KC / VW);
+      *reinterpret_cast<TV*>(&sA[b][r][pc * VW]) = pf[u];
+    }
+  };
+  V acc[2][2];
+  double dacc[kFold ? 2 : 1][kFold ? 2 : 1][4];
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y) acc[x][y] = V{0, 0, 0, 0};
+  if (kFold) {
+#pragma unroll
+    for (int x = 0; x < (kFold ? 2 : 1); ++x)
+#pragma unroll
+      for (int y = 0; y < (kFold ? 2 : 1); ++y)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) dacc[x][y][v] = 0.0;
+  }
+  const int64_t nch = Sp / KC;
+  fetch(0);
+  stash(0);
+  __syncthreads();
+  for (int64_t ch = 0; ch < nch; ++ch) {
+    const int b = (int)(ch & 1);
+    if (ch + 1 < nch) fetch((ch + 1) * KC);
+    if (active) {
+#pragma unroll
+      for (int s0 = 0; s0 < KC / 4; s0 += 4) {
+        const int p = g * (KC / 4) + s0;
+        T4 av[2], bv[2];
+#pragma unroll
+        for (int x = 0; x < 2; ++x) av[x] = *reinterpret_cast<const T4*>(&sA[b][row0 + x * 16 + li][p]);
+#pragma unroll
+        for (int y = 0; y < 2; ++y) bv[y] = *reinterpret_cast<const T4*>(&sA[b][GD_TILE + col0 + y * 16 + li][p]);
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+          for (int x = 0; x < 2; ++x)
+#pragma unroll
+            for (int y = 0; y < 2; ++y) acc[x][y] = MfmaAcc<T>::mfma(av[x][s], bv[y][s], acc[x][y]);
+      }
+      if (kFold) {
+#pragma unroll
+        for (int x = 0; x < 2; ++x)
+#pragma unroll
+          for (int y = 0; y < 2; ++y) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) dacc[kFold ? x : 0][kFold ? y : 0][v] += (double)acc[x][y][v];
+            acc[x][y] = V{0, 0, 0, 0};
+          }
+      }
+    }
+    if (ch + 1 < nch) stash(b ^ 1);
+    __syncthreads();
+  }
+  if (!active) return;
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t row = r0 + row0 + x * 16 + MfmaAcc<T>::row(g, v);
+        const int64_t col = c0 + col0 + y * 16 + li;
+        const double val = kFold ? dacc[kFold ? x : 0][kFold ? y : 0][v] : (double)acc[x][y][v];
+        if (row < R && col <= row) G[row * R + col] = val;
+      }
+}
+
+// h[j] = sum_q A^T[j][q] b[q] in FP64, one wave per row, lanes striding over q in a fixed order
+template <typename T>
+__global__ __launch_bounds__(256) void k_atv_dense(const T* At, const T* b, int64_t R, int64_t Sp, double* h) {
+  const int lane = threadIdx.x & 63;
+  const int64_t j = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (j >= R) return;
+  const T* row = At + j * Sp;
+  double s = 0.0;
+  for (int64_t q = lane; q < Sp; q += 64) s += (double)row[q] * (double)b[q];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+  if (lane == 0) h[j] = s;
+}
+
+// ------------------------------------------------------------------------------ host side
+int64_t mixed_length(int64_t n) {
+  int64_t N = MX_B1;
+  while (N < n) N *= 2;
+  return N;
+}
+
+struct MixLayout {
+  int64_t N, Sp, C;
+  size_t U, buf, pos, At, b, total;
+};
+static MixLayout mix_layout(const fst_model* m, int dtype, int64_t n, int64_t nsamp) {
+  const size_t es = dtype == FST_F64 ? 8 : 4;
+  MixLayout L;
+  L.N = mixed_length(n);
+  L.Sp = (nsamp + 63) / 64 * 64;
+  L.C = std::max<int64_t>(1, std::min<int64_t>(256, (int64_t(1) << 30) / (L.N * (int64_t)es)));
+  size_t off = 0;
+  L.U = off;
+  off += align_up(es * (size_t)m->sum_r() * (size_t)n);
+  L.buf = off;
+  off += align_up(es * (size_t)L.C * (size_t)L.N);
+  L.pos = off;
+  off += align_up(4 * (size_t)L.N);
+  L.At = off;
+  off += align_up(es * (size_t)m->R() * (size_t)L.Sp);
+  L.b = off;
+  off += align_up(es * (size_t)L.Sp);
+  L.total = off;
+  return L;
+}
+
+size_t mixed_workspace_bytes(const fst_model* m, int dtype, int64_t n, int64_t nsamp) {
+  return mix_layout(m, dtype, n, nsamp).total;
+}
+
+template <typename T>
+static void mixed_normal_equations_t(const fst_model* m, const DeviceModel& dm, int64_t n, const void* x,
+                                     const void* y, const void* z, const void* v, int64_t nsamp, uint64_t seed,
+                                     void* ws, double* G, double* h, void* stream) {
+  const int dtype = sizeof(T) == 8 ? FST_F64 : FST_F32;
+  const MixLayout L = mix_layout(m, dtype, n, nsamp);
+  char* w = (char*)ws;
+  T* U = (T*)(w + L.U);
+  T* buf = (T*)(w + L.buf);
+  int32_t* pos = (int32_t*)(w + L.pos);
+  T* At = (T*)(w + L.At);
+  T* b = (T*)(w + L.b);
+  const int64_t R = m->R(), N = L.N;
+  int H = 0;
+  while ((int64_t(MX_B1) << H) < N) ++H;
+
+  // Algorithm 2 step 4 over the N mixed rows: S rows uniformly without replacement (stream 2)
+  {
+    std::vector<int64_t> idx((size_t)nsamp);
+    sample_indices(seed, FST_STREAM_LS, N, nsamp, idx.data());
+    std::vector<int32_t> p((size_t)N, -1);
+    for (int64_t q = 0; q < nsamp; ++q) p[(size_t)idx[(size_t)q]] = (int32_t)q;
+    copy_h2d(pos, p.data(), sizeof(int32_t) * (size_t)N, stream);
+  }
+  // step 1: factor functions at every point
+  launch_factor_eval(m, dm, dtype, n, x, y, z, nullptr, nullptr, n, U, nullptr, stream);
+  // steps 2-4: signs, transform, sampled rows, one chunk of columns (and finally the values) at a time
+  MixArgs<T> a;
+  a.U = U;
+  a.v = (const T*)v;
+  a.n = n;
+  a.N = N;
+  a.R = R;
+  a.r1 = m->rank[0];
+  a.r2 = m->rank[1];
+  a.r3 = m->rank[2];
+  a.H = H;
+  const int64_t elems = (sizeof(T) == 4 ? 8192 : 4096);   // 32 KB of LDS in the second pass
+  a.L = (int32_t)std::min<int64_t>(MX_B1, elems >> H);
+  a.sign_state = seed * 256u + (uint64_t)kSignsStream;
+  a.buf = buf;
+  a.pos = pos;
+  a.At = At;
+  a.b = b;
+  a.Sp = L.Sp;
+  a.scale = (T)(1.0 / std::sqrt((double)N));
+  const size_t lds_hi = sizeof(T) * (size_t)((int64_t)a.L << H);
+  for (int64_t c0 = 0; c0 <= R; c0 += L.C) {
+    const int64_t nc = std::min<int64_t>(L.C, R + 1 - c0);
+    a.c0 = c0;
+    hipLaunchKernelGGL(k_mix_lo<T>, dim3((unsigned)(N / MX_B1), (unsigned)nc), dim3(MX_THREADS), 0, S(stream), a);
+    check_launch("k_mix_lo");
+    hipLaunchKernelGGL(k_mix_hi<T>, dim3((unsigned)(MX_B1 / a.L), (unsigned)nc), dim3(MX_THREADS), lds_hi,
+                       S(stream), a);
+    check_launch("k_mix_hi");
+  }
+  if (L.Sp > nsamp) {
+    const int64_t cnt = (R + 1) * (L.Sp - nsamp);
+    hipLaunchKernelGGL(k_zero_tail<T>, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, S(stream), At, b, R, nsamp,
+                       L.Sp);
+    check_launch("k_zero_tail");
+  }
+  // step 5: normal equations of the sampled mixed rows
+  const int64_t nt = (R + GD_TILE - 1) / GD_TILE;
+  hipLaunchKernelGGL(k_gram_dense<T>, dim3((unsigned)(nt * (nt + 1) / 2)), dim3(GD_THREADS), 0, S(stream),
+                     (const T*)At, R, L.Sp, G);
+  check_launch("k_gram_dense");
+  hipLaunchKernelGGL(k_atv_dense<T>, dim3((unsigned)((R + 3) / 4)), dim3(256), 0, S(stream), (const T*)At,
+                     (const T*)b, R, L.Sp, h);
+  check_launch("k_atv_dense");
+}
+
+void mixed_normal_equations(const fst_model* m, int dtype, int64_t n, const void* x, const void* y, const void* z,
+                            const void* v, int64_t nsamp, uint64_t seed, void* ws, size_t ws_bytes, double* G,
+                            double* h, void* stream) {
+  const MixLayout L = mix_layout(m, dtype, n, nsamp);
+  if (ws_bytes < L.total) fail(FST_E_NOMEM, "mixed rows: workspace too small");
+  if (L.N > (int64_t(1) << MX_MAX_LOG2N)) fail(FST_E_UNSUPPORTED, "mixed rows: more than 2^23 points");
+  if ((int64_t)m->R() * L.Sp >= (int64_t(1) << 40)) fail(FST_E_UNSUPPORTED, "mixed rows: A^T too large");
+  const DeviceModel& dm = device_model(m, dtype);
+  if (dtype == FST_F64)
+    mixed_normal_equations_t<double>(m, dm, n, x, y, z, v, nsamp, seed, ws, G, h, stream);
+  else
+    mixed_normal_equations_t<float>(m, dm, n, x, y, z, v, nsamp, seed, ws, G, h, stream);
+}
+
+}  // namespace fst

@@ -34,6 +34,7 @@ def test_fwht_orthogonal_and_involution():
 
 def test_next_pow2_and_signs():
     assert [mixing.next_pow2(n) for n in (1, 2, 3, 4, 5, 4096, 4097)] == [1, 2, 4, 4, 8, 4096, 8192]
+    assert [mixing.mixed_length(n) for n in (1, 4096, 4097, 70000)] == [4096, 4096, 8192, 131072]
     d = mixing.signs(7, 1 << 16)
     assert set(np.unique(d)) == {-1.0, 1.0}
     z = splitmix64(stream_state(7, 5), 5)
@@ -49,7 +50,7 @@ def test_all_rows_kept_recovers_full_least_squares():
     n = 300
     pts = rng.uniform(-1, 1, (n, 3))
     vals = rng.standard_normal(n)
-    N = mixing.next_pow2(n)
+    N = mixing.mixed_length(n)
     alpha, G, h = mixing.refit_core_mixed(m, pts, vals, N, seed=11)
     W = design_rows(factor_values(m, pts))
     np.testing.assert_allclose(alpha, solve_lstsq(W, vals), rtol=1e-9, atol=1e-10)
