@@ -484,6 +484,23 @@ def main():
     t_grid = float(np.median(grid_ms)) / 1e3
     grid_bytes = float(NG) ** 3 * 4 + 2.0 * m0.rank[0] * NG * NG * 4
     del grid_out, grid_ws
+    # Algorithm 2 with its randomised mixing (sign flips, Walsh-Hadamard transform of every
+    # design column over all N rows, M rows sampled from the mixed rows), once: one warm-up
+    # call, one timed call; the data error of its model beside the unmixed one
+    mix_ws = torch.empty(max(int(fst._fn["fst_refit_core_mixed_workspace_bytes"](m0.handle, fst.FST_F32, N, M)), 256),
+                         dtype=torch.uint8, device=dev)
+    fst.fst_refit_core_mixed(m0, x, y, z, v, M, w.seed, ws=mix_ws)
+    torch.cuda.synchronize()
+    t0m = time.perf_counter()
+    gm_mix = fst.fst_refit_core_mixed(m0, x, y, z, v, M, w.seed, ws=mix_ws)
+    torch.cuda.synchronize()
+    t_mix = time.perf_counter() - t0m
+    del mix_ws
+    sm_err, sm_v = fst.fst_eval_error(gm_mix, x, y, z, v)
+    n_pad = 4096
+    while n_pad < N:
+        n_pad *= 2
+    log(f"[bench] mixed refit: {t_mix * 1e3:.1f} ms, data rel-L2 {np.sqrt(sm_err / sm_v):.4e}")
 
     avg = {k: float(np.mean(vv)) for k, vv in times.items()}
     t_rows = avg["k1"] + avg["gram"] + avg["atv"]
@@ -530,6 +547,12 @@ def main():
                 "bound": "hbm", "achieved": grid_bytes / t_grid / 1e9, "peak": 8000.0, "unit": "GB/s",
                 "frac": grid_bytes / t_grid / 8e12, "ms": t_grid * 1e3, "bytes_per_launch": grid_bytes,
                 "grid_points_per_s": float(NG) ** 3 / t_grid}},
+        "mixed_refit": {
+            "what": "Algorithm 2 with sign flips + normalised Walsh-Hadamard mixing over all N rows "
+                    "(fst_refit_core_mixed, FP32 rows and Gram, FP64 Cholesky, no refinement)",
+            "ms": t_mix * 1e3, "mixed_rows_per_s": M / t_mix, "rows_transformed": n_pad,
+            "transform_bytes": float(R + 1) * 2 * n_pad * 4,
+            "data_rel_l2": float(np.sqrt(sm_err / sm_v)), "data_rel_l2_unmixed": eps_data},
         "roofline": {"kernel": "k_gram<float>" if args.precision == "f32" else f"k_gram_lp<{args.precision}>",
                      "bound": "mfma", "achieved": achieved / 1e12,
                      "peak": peak / 1e12, "unit": "TFLOP/s", "frac": achieved / peak,

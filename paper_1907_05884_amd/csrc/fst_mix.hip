@@ -4,11 +4,13 @@
 // real orthogonal stand-in for the FFT), S rows of F D W and F D u are kept, and the normal
 // equations of that sampled problem are formed.
 //
-//   k_mix_lo     a design column (Khatri-Rao product of three factor rows, times the sign
-//                of each row) in blocks of 4096 rows: the 12 butterfly stages inside a block,
-//                4 of them in registers and 8 through LDS
+//   k_mix_lo     the r3 design columns of one (j1, j2) pair (Khatri-Rao products of three
+//                factor rows, times the sign of each row) in blocks of 4096 rows: the signed
+//                product u1 u2 is formed once per row and each column multiplies it by its u3;
+//                the 12 butterfly stages inside a block, 4 in registers and 8 through LDS
 //   k_mix_hi     the remaining stages across blocks (strides 4096 .. N/2) through LDS, the
-//                1/sqrt(N) scale, and a scatter of the sampled rows into A^T
+//                1/sqrt(N) scale, and a scatter of the sampled rows into A^T from a list of
+//                the samples that fall into the workgroup's rows
 //   k_gram_dense G = A^T A (lower triangle) from the materialised sampled rows, MFMA
 //   k_atv_dense  h = A^T b
 //
@@ -45,109 +47,126 @@ __device__ inline int row_sign_negative(uint64_t state, int64_t i) {
 
 template <typename T>
 struct MixArgs {
-  const T* U;           // [SR][n] factor values at all points
-  const T* v;           // values (column R)
+  const T* U;            // [SR][n] factor values at all points
+  const T* v;            // values (with `values` set)
   int64_t n, N, R;
-  int32_t r1, r2, r3, L, H;
-  int64_t c0;           // first design column of this chunk (column R is the values)
+  int32_t r1, r2, r3, L, lgL, H, values;
+  int64_t c0;            // first design column of this launch (a multiple of r3)
   uint64_t sign_state;
-  T* buf;               // [ncols][N]
-  const int32_t* pos;   // [N]: position of row i among the samples, or -1
-  T* At;                // [R][Sp]
-  T* b;                 // [Sp]
+  T* buf;                // [columns of the launch][N]
+  const int32_t* sel;    // per second-pass workgroup: (LDS element, sample position) pairs
+  const int32_t* sel_off;
+  T* At;                 // [R][Sp]
+  T* b;                  // [Sp]
   int64_t Sp;
   T scale;
 };
 
+// Workgroup (x, y): rows x 4096 .. x 4096 + 4095 of the r3 columns of pair y of the launch
+// (or of the value column).
 template <typename T>
 __global__ __launch_bounds__(MX_THREADS) void k_mix_lo(MixArgs<T> a) {
   __shared__ T s[MX_B1];
-  const int c = blockIdx.y, t = threadIdx.x;
-  const int64_t j = a.c0 + c, base = (int64_t)blockIdx.x * MX_B1;
-  const bool values = j >= a.R;
-  const T *p1 = a.U, *p2 = a.U, *p3 = a.U;
-  if (!values) {
-    const int64_t j3 = j % a.r3, j12 = j / a.r3;
-    p1 = a.U + (j12 / a.r2) * a.n;
-    p2 = a.U + (a.r1 + j12 % a.r2) * a.n;
-    p3 = a.U + (a.r1 + a.r2 + j3) * a.n;
-  }
-  T w[16];
+  const int t = threadIdx.x;
+  const int64_t base = (int64_t)blockIdx.x * MX_B1;
+  const int64_t j0 = a.c0 + (int64_t)blockIdx.y * a.r3;   // column of j3 = 0
+  const int64_t j12 = j0 / a.r3;
+  const T* p1 = a.U + (j12 / a.r2) * a.n;
+  const T* p2 = a.U + (a.r1 + j12 % a.r2) * a.n;
+  const T* p3 = a.U + (int64_t)(a.r1 + a.r2) * a.n;
+  T pr[16];   // sign x u1 u2 (or sign x value) of the thread's rows
 #pragma unroll
   for (int k = 0; k < 16; ++k) {
     const int64_t i = base + t + 256 * k;
     T x = T(0);
     if (i < a.n) {
-      x = values ? a.v[i] : p1[i] * p2[i] * p3[i];
+      x = a.values ? a.v[i] : p1[i] * p2[i];
       if (row_sign_negative(a.sign_state, i)) x = -x;
     }
-    w[k] = x;
+    pr[k] = x;
   }
-  // strides 256 .. 2048 (bits 8 .. 11 of the row): partners among this thread's elements
+  const int ncol = a.values ? 1 : a.r3;
+  // u3 of the next column is loaded while the current one goes through the LDS stages
+  T u3[16];
+  auto load_u3 = [&](int jj) {
 #pragma unroll
-  for (int sb = 0; sb < 4; ++sb)
-#pragma unroll
-    for (int k = 0; k < 16; ++k)
-      if (!(k & (1 << sb))) {
-        const T x = w[k], y = w[k | (1 << sb)];
-        w[k] = x + y;
-        w[k | (1 << sb)] = x - y;
-      }
-#pragma unroll
-  for (int k = 0; k < 16; ++k) s[t + 256 * k] = w[k];
-  __syncthreads();
-  // strides 1 .. 128 (bits 0 .. 7): 2048 disjoint pairs per stage, 8 per thread
-  for (int h = 1; h < 256; h <<= 1) {
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int p = t + 256 * q;
-      const int i0 = (p / h) * 2 * h + (p % h), i1 = i0 + h;
-      const T x = s[i0], y = s[i1];
-      s[i0] = x + y;
-      s[i1] = x - y;
+    for (int k = 0; k < 16; ++k) {
+      const int64_t i = base + t + 256 * k;
+      u3[k] = (!a.values && i < a.n) ? p3[(int64_t)jj * a.n + i] : T(1);
     }
-    __syncthreads();
-  }
-  T* out = a.buf + (int64_t)c * a.N + base;
+  };
+  load_u3(0);
+  for (int jj = 0; jj < ncol; ++jj) {
+    T w[16];
 #pragma unroll
-  for (int k = 0; k < 16; ++k) out[t + 256 * k] = s[t + 256 * k];
+    for (int k = 0; k < 16; ++k) w[k] = pr[k] * u3[k];
+    if (jj + 1 < ncol) load_u3(jj + 1);
+    // strides 256 .. 2048 (bits 8 .. 11 of the row): partners among this thread's elements
+#pragma unroll
+    for (int sb = 0; sb < 4; ++sb)
+#pragma unroll
+      for (int k = 0; k < 16; ++k)
+        if (!(k & (1 << sb))) {
+          const T x = w[k], y = w[k | (1 << sb)];
+          w[k] = x + y;
+          w[k | (1 << sb)] = x - y;
+        }
+#pragma unroll
+    for (int k = 0; k < 16; ++k) s[t + 256 * k] = w[k];
+    __syncthreads();
+    // strides 1 .. 128 (bits 0 .. 7): 2048 disjoint pairs per stage, 8 per thread
+#pragma unroll
+    for (int lh = 0; lh < 8; ++lh) {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int p = t + 256 * q;
+        const int i0 = ((p >> lh) << (lh + 1)) | (p & ((1 << lh) - 1)), i1 = i0 + (1 << lh);
+        const T x = s[i0], y = s[i1];
+        s[i0] = x + y;
+        s[i1] = x - y;
+      }
+      __syncthreads();
+    }
+    T* out = a.buf + ((int64_t)blockIdx.y * ncol + jj) * a.N + base;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) out[t + 256 * k] = s[t + 256 * k];
+    __syncthreads();   // s is rewritten by the next column
+  }
 }
 
-// Workgroup (x, c): offsets l0 .. l0 + L - 1 inside the 4096-row blocks, all K = 2^H blocks.
+// Workgroup (x, c): offsets x L .. x L + L - 1 inside the 4096-row blocks of column c of the
+// launch, all K = 2^H blocks (LDS element k L + l is row k 4096 + x L + l).
 template <typename T>
 __global__ __launch_bounds__(MX_THREADS) void k_mix_hi(MixArgs<T> a) {
   extern __shared__ __align__(16) unsigned char mx_smem[];
   T* s = reinterpret_cast<T*>(mx_smem);   // [K][L]
   const int c = blockIdx.y;
-  const int64_t j = a.c0 + c;
-  const int L = a.L, K = 1 << a.H, E = K * L;
+  const int64_t j = a.values ? a.R : a.c0 + c;
+  const int L = a.L, lgL = a.lgL, E = L << a.H;
   const int l0 = blockIdx.x * L;
   const T* col = a.buf + (int64_t)c * a.N;
-  for (int e = threadIdx.x; e < E; e += MX_THREADS) {
-    const int k = e / L, l = e % L;
-    s[e] = col[(int64_t)k * MX_B1 + l0 + l];
-  }
+  // L and 2^H are powers of two: every index below is shifts and masks
+  for (int e = threadIdx.x; e < E; e += MX_THREADS) s[e] = col[(int64_t)(e >> lgL) * MX_B1 + l0 + (e & (L - 1))];
   __syncthreads();
-  for (int h = 1; h < K; h <<= 1) {
+  for (int lh = 0; lh < a.H; ++lh) {
+    const int h = 1 << lh;
     for (int p = threadIdx.x; p < E / 2; p += MX_THREADS) {
-      const int pk = p / L, l = p % L;
-      const int k0 = (pk / h) * 2 * h + (pk % h), k1 = k0 + h;
+      const int pk = p >> lgL, l = p & (L - 1);
+      const int k0 = ((pk >> lh) << (lh + 1)) | (pk & (h - 1)), k1 = k0 + h;
       const T x = s[k0 * L + l], y = s[k1 * L + l];
       s[k0 * L + l] = x + y;
       s[k1 * L + l] = x - y;
     }
     __syncthreads();
   }
-  for (int e = threadIdx.x; e < E; e += MX_THREADS) {
-    const int k = e / L, l = e % L;
-    const int p = a.pos[(int64_t)k * MX_B1 + l0 + l];
-    if (p >= 0) {
-      const T val = s[e] * a.scale;
-      if (j < a.R)
-        a.At[j * a.Sp + p] = val;
-      else
-        a.b[p] = val;
-    }
+  const int beg = a.sel_off[blockIdx.x], end = a.sel_off[blockIdx.x + 1];
+  for (int q = beg + threadIdx.x; q < end; q += MX_THREADS) {
+    const int e = a.sel[2 * q], p = a.sel[2 * q + 1];
+    const T val = s[e] * a.scale;
+    if (j < a.R)
+      a.At[j * a.Sp + p] = val;
+    else
+      a.b[p] = val;
   }
 }
 
@@ -296,23 +315,42 @@ int64_t mixed_length(int64_t n) {
   return N;
 }
 
+// Second-pass geometry: offsets per workgroup L (32 KB of LDS hold L 2^H values)
+static int mix_H(int64_t N) {
+  int H = 0;
+  while ((int64_t(MX_B1) << H) < N) ++H;
+  return H;
+}
+static int mix_L(int dtype, int H) {
+  const int64_t elems = dtype == FST_F64 ? 4096 : 8192;   // 32 KB of LDS
+  return (int)std::min<int64_t>(MX_B1, elems >> H);
+}
+
 struct MixLayout {
   int64_t N, Sp, C;
-  size_t U, buf, pos, At, b, total;
+  int H, L;
+  size_t U, buf, sel, sel_off, At, b, total;
 };
 static MixLayout mix_layout(const fst_model* m, int dtype, int64_t n, int64_t nsamp) {
   const size_t es = dtype == FST_F64 ? 8 : 4;
   MixLayout L;
   L.N = mixed_length(n);
   L.Sp = (nsamp + 63) / 64 * 64;
-  L.C = std::max<int64_t>(1, std::min<int64_t>(256, (int64_t(1) << 30) / (L.N * (int64_t)es)));
+  L.H = mix_H(L.N);
+  L.L = mix_L(dtype, L.H);
+  // columns per launch: whole (j1, j2) pairs, about 1 GB of transform buffer
+  const int64_t r3 = m->rank[2];
+  const int64_t cmax = std::max<int64_t>(1, std::min<int64_t>(256, (int64_t(1) << 30) / (L.N * (int64_t)es)));
+  L.C = std::max<int64_t>(1, cmax / r3) * r3;
   size_t off = 0;
   L.U = off;
   off += align_up(es * (size_t)m->sum_r() * (size_t)n);
   L.buf = off;
   off += align_up(es * (size_t)L.C * (size_t)L.N);
-  L.pos = off;
-  off += align_up(4 * (size_t)L.N);
+  L.sel = off;
+  off += align_up(8 * (size_t)nsamp);
+  L.sel_off = off;
+  off += align_up(4 * (size_t)(MX_B1 / L.L + 1));
   L.At = off;
   off += align_up(es * (size_t)m->R() * (size_t)L.Sp);
   L.b = off;
@@ -334,24 +372,35 @@ static void mixed_normal_equations_t(const fst_model* m, const DeviceModel& dm, 
   char* w = (char*)ws;
   T* U = (T*)(w + L.U);
   T* buf = (T*)(w + L.buf);
-  int32_t* pos = (int32_t*)(w + L.pos);
+  int32_t* sel = (int32_t*)(w + L.sel);
+  int32_t* sel_off = (int32_t*)(w + L.sel_off);
   T* At = (T*)(w + L.At);
   T* b = (T*)(w + L.b);
   const int64_t R = m->R(), N = L.N;
-  int H = 0;
-  while ((int64_t(MX_B1) << H) < N) ++H;
 
-  // Algorithm 2 step 4 over the N mixed rows: S rows uniformly without replacement (stream 2)
+  // Algorithm 2 step 4 over the N mixed rows: S rows uniformly without replacement (stream
+  // 2), listed per second-pass workgroup as (LDS element, sample position)
   {
     std::vector<int64_t> idx((size_t)nsamp);
     sample_indices(seed, FST_STREAM_LS, N, nsamp, idx.data());
-    std::vector<int32_t> p((size_t)N, -1);
-    for (int64_t q = 0; q < nsamp; ++q) p[(size_t)idx[(size_t)q]] = (int32_t)q;
-    copy_h2d(pos, p.data(), sizeof(int32_t) * (size_t)N, stream);
+    const int nblk = MX_B1 / L.L;
+    std::vector<int32_t> off((size_t)nblk + 1, 0), fill((size_t)nblk, 0), list((size_t)(2 * nsamp));
+    for (int64_t q = 0; q < nsamp; ++q) ++off[(size_t)((idx[(size_t)q] % MX_B1) / L.L) + 1];
+    for (int bk = 0; bk < nblk; ++bk) off[(size_t)bk + 1] += off[(size_t)bk];
+    for (int64_t q = 0; q < nsamp; ++q) {
+      const int64_t i = idx[(size_t)q];
+      const int bk = (int)((i % MX_B1) / L.L);
+      const int64_t e = (i / MX_B1) * L.L + (i % MX_B1 - (int64_t)bk * L.L);
+      const int32_t t = off[(size_t)bk] + fill[(size_t)bk]++;
+      list[(size_t)(2 * t)] = (int32_t)e;
+      list[(size_t)(2 * t + 1)] = (int32_t)q;
+    }
+    copy_h2d(sel, list.data(), sizeof(int32_t) * list.size(), stream);
+    copy_h2d(sel_off, off.data(), sizeof(int32_t) * off.size(), stream);
   }
   // step 1: factor functions at every point
   launch_factor_eval(m, dm, dtype, n, x, y, z, nullptr, nullptr, n, U, nullptr, stream);
-  // steps 2-4: signs, transform, sampled rows, one chunk of columns (and finally the values) at a time
+  // steps 2-4: signs, transform, sampled rows; whole (j1, j2) pairs per launch, then the values
   MixArgs<T> a;
   a.U = U;
   a.v = (const T*)v;
@@ -361,25 +410,31 @@ static void mixed_normal_equations_t(const fst_model* m, const DeviceModel& dm, 
   a.r1 = m->rank[0];
   a.r2 = m->rank[1];
   a.r3 = m->rank[2];
-  a.H = H;
-  const int64_t elems = (sizeof(T) == 4 ? 8192 : 4096);   // 32 KB of LDS in the second pass
-  a.L = (int32_t)std::min<int64_t>(MX_B1, elems >> H);
+  a.H = L.H;
+  a.L = L.L;
+  a.lgL = 0;
+  while ((1 << a.lgL) < L.L) ++a.lgL;
   a.sign_state = seed * 256u + (uint64_t)kSignsStream;
   a.buf = buf;
-  a.pos = pos;
+  a.sel = sel;
+  a.sel_off = sel_off;
   a.At = At;
   a.b = b;
   a.Sp = L.Sp;
   a.scale = (T)(1.0 / std::sqrt((double)N));
-  const size_t lds_hi = sizeof(T) * (size_t)((int64_t)a.L << H);
+  const size_t lds_hi = sizeof(T) * (size_t)((int64_t)L.L << L.H);
+  const unsigned lo_blocks = (unsigned)(N / MX_B1), hi_blocks = (unsigned)(MX_B1 / L.L);
   for (int64_t c0 = 0; c0 <= R; c0 += L.C) {
-    const int64_t nc = std::min<int64_t>(L.C, R + 1 - c0);
+    const bool vals = c0 == R;
+    const int64_t nc = vals ? 1 : std::min<int64_t>(L.C, R - c0);
     a.c0 = c0;
-    hipLaunchKernelGGL(k_mix_lo<T>, dim3((unsigned)(N / MX_B1), (unsigned)nc), dim3(MX_THREADS), 0, S(stream), a);
-    check_launch("k_mix_lo");
-    hipLaunchKernelGGL(k_mix_hi<T>, dim3((unsigned)(MX_B1 / a.L), (unsigned)nc), dim3(MX_THREADS), lds_hi,
+    a.values = vals ? 1 : 0;
+    hipLaunchKernelGGL(k_mix_lo<T>, dim3(lo_blocks, (unsigned)(vals ? 1 : nc / a.r3)), dim3(MX_THREADS), 0,
                        S(stream), a);
+    check_launch("k_mix_lo");
+    hipLaunchKernelGGL(k_mix_hi<T>, dim3(hi_blocks, (unsigned)nc), dim3(MX_THREADS), lds_hi, S(stream), a);
     check_launch("k_mix_hi");
+    if (!vals && c0 + L.C > R) c0 = R - L.C;   // next: the value column
   }
   if (L.Sp > nsamp) {
     const int64_t cnt = (R + 1) * (L.Sp - nsamp);
