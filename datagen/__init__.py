@@ -32,7 +32,7 @@ def _streams(seed: int):
 @dataclass
 class FieldParams:
     """Parameters of one synthetic field, defined on reference coordinates in [-1,1]^3."""
-    centers: np.ndarray          # (G, 3) in [-0.8, 0.8]
+    centers: np.ndarray          # (G, d) in [-0.8, 0.8]
     widths: np.ndarray           # (G,)  in (0.1, 0.4)
     amps: np.ndarray             # (G,)  N(0, 1)
     sin_amp: float = 0.3
@@ -41,9 +41,12 @@ class FieldParams:
     front_width: float = 0.02
 
     def __call__(self, xi: np.ndarray) -> np.ndarray:
-        """Field value at reference coordinates ``xi`` of shape (n, 3), in float64."""
+        """Field value at reference coordinates ``xi`` of shape (n, d), d = 3 or 4 (the centres
+        have d columns), in float64."""
         xi = np.asarray(xi, dtype=np.float64)
         out = self.sin_amp * np.sin(3.0 * xi[:, 0]) * np.cos(2.0 * xi[:, 1]) * np.sin(xi[:, 2])
+        if xi.shape[1] == 4:
+            out = out * np.cos(1.5 * xi[:, 3])
         for c, w, a in zip(self.centers, self.widths, self.amps):
             d2 = ((xi - c) ** 2).sum(axis=1)
             out += a * np.exp(-d2 / (2.0 * w * w))
@@ -53,8 +56,8 @@ class FieldParams:
 
 
 def draw_field(rng: np.random.Generator, n_gauss: int, front: bool = False,
-               front_rng: Optional[np.random.Generator] = None) -> FieldParams:
-    centers = rng.uniform(-0.8, 0.8, size=(n_gauss, 3))
+               front_rng: Optional[np.random.Generator] = None, d: int = 3) -> FieldParams:
+    centers = rng.uniform(-0.8, 0.8, size=(n_gauss, d))
     widths = rng.uniform(0.1, 0.4, size=n_gauss)
     amps = rng.standard_normal(n_gauss)
     fp = FieldParams(centers=centers, widths=widths, amps=amps)
@@ -67,14 +70,14 @@ def draw_field(rng: np.random.Generator, n_gauss: int, front: bool = False,
 
 
 def uniform_points(rng: np.random.Generator, n: int, lo, hi) -> np.ndarray:
-    """(n, 3) float64 points, i.i.d. uniform in the box [lo, hi]."""
+    """(n, d) float64 points, d = len(lo), i.i.d. uniform in the box [lo, hi]."""
     lo = np.asarray(lo, dtype=np.float64)
     hi = np.asarray(hi, dtype=np.float64)
-    return lo + (hi - lo) * rng.random((n, 3))
+    return lo + (hi - lo) * rng.random((n, lo.shape[0]))
 
 
 def to_reference(pts: np.ndarray, lo, hi) -> np.ndarray:
-    """Affine map of box coordinates onto [-1,1]^3 (used only to evaluate the synthetic field)."""
+    """Affine map of box coordinates onto [-1,1]^d (used only to evaluate the synthetic field)."""
     lo = np.asarray(lo, dtype=np.float64)
     hi = np.asarray(hi, dtype=np.float64)
     return 2.0 * (np.asarray(pts, np.float64) - lo) / (hi - lo) - 1.0
@@ -87,7 +90,7 @@ class Workload:
     seed: int
     lo: tuple
     hi: tuple
-    pts: np.ndarray               # (N, 3), dtype = dtype
+    pts: np.ndarray               # (N, d), dtype = dtype
     vals: np.ndarray              # (N,),   dtype = dtype
     grid: tuple
     rank: tuple
@@ -103,10 +106,10 @@ class Workload:
         return int(self.pts.shape[0])
 
     def soa(self):
-        """Contiguous x, y, z, v arrays (structure of arrays)."""
+        """Contiguous coordinate arrays, one per mode, then the values (structure of arrays)."""
         p = self.pts
-        return (np.ascontiguousarray(p[:, 0]), np.ascontiguousarray(p[:, 1]),
-                np.ascontiguousarray(p[:, 2]), np.ascontiguousarray(self.vals))
+        return tuple(np.ascontiguousarray(p[:, k]) for k in range(p.shape[1])) + (
+            np.ascontiguousarray(self.vals),)
 
 
 def make_workload(name: str, seed: int, n: int, n_gauss: int, grid, rank, degree,
@@ -115,7 +118,7 @@ def make_workload(name: str, seed: int, n: int, n_gauss: int, grid, rank, degree
                   lo=(-1.0, -1.0, -1.0), hi=(1.0, 1.0, 1.0)) -> Workload:
     st = _streams(seed)
     pts = uniform_points(st[STREAM_POINTS], n, lo, hi)
-    fp = draw_field(st[STREAM_FIELD], n_gauss, front=front, front_rng=st[STREAM_FRONT])
+    fp = draw_field(st[STREAM_FIELD], n_gauss, front=front, front_rng=st[STREAM_FRONT], d=len(lo))
     # Values are computed from the points as they will be stored (rounded to dtype first),
     # so that a float32 workload's values are the field at its float32 points.
     pts = pts.astype(dtype)
@@ -146,6 +149,17 @@ def large_f32(n: int = 2_000_000, n_samples: int = 200_000, grid=(128, 128, 128)
     return make_workload("large_f32", seed=2, n=n, n_gauss=40, grid=grid, rank=rank,
                          degree=degree, interp_fraction=0.05, n_samples=n_samples,
                          dtype=np.float32, noise_std=1e-3)
+
+
+def spacetime_f32(n: int = 2_000_000, n_samples: int = 52_000, rank=(12, 12, 12, 12),
+                  degree=(31, 31, 31, 31), grid=(32, 32, 32, 32)) -> Workload:
+    """A 4-way (space plus time) field standing in for the paper's space-time data (Sec. 6):
+    2M points in [-1,1]^3 x [0,1], 40 Gaussians in four dimensions times a sinusoid, N(0,1e-3)
+    noise, ranks 12^4 (R = 20,736) and degree 31; M = 52,000 rows is about 2.5 R."""
+    return make_workload("spacetime_f32", seed=6, n=n, n_gauss=40, grid=grid, rank=rank,
+                         degree=degree, interp_fraction=0.05, n_samples=n_samples,
+                         dtype=np.float32, noise_std=1e-3, lo=(-1.0, -1.0, -1.0, 0.0),
+                         hi=(1.0, 1.0, 1.0, 1.0))
 
 
 def corrector_field(n: int = 600_000) -> Workload:
@@ -208,13 +222,13 @@ def points_only(seed: int, n: int, lo=(-1.0, -1.0, -1.0), hi=(1.0, 1.0, 1.0),
 
 
 def random_model_parts(seed: int, rank, degree, density: float = 0.6, scale: float = 1.0):
-    """A random functional-Tucker model: core (r1,r2,r3) and per-mode coefficient matrices
+    """A random functional-Tucker model: core (r1, .., rd) and per-mode coefficient matrices
     (n_k, r_k) with a random sparsity pattern.  Used where a test needs a model that does
     not come from a fit (for example to plant a field that lies exactly in the model span)."""
     rng = np.random.default_rng(seed)
     core = scale * rng.standard_normal(tuple(rank))
     coefs = []
-    for k in range(3):
+    for k in range(len(rank)):
         n_k = degree[k] + 1
         c = rng.standard_normal((n_k, rank[k])) / np.sqrt(n_k)
         mask = rng.random((n_k, rank[k])) < density

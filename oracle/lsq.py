@@ -1,13 +1,13 @@
 """Core re-estimation by randomized least squares (oracle, test infrastructure).
 
 Sec. 5 rewrites eq. (1) as u~(y) = sum_j alpha_j w_j(y) with w_j = prod_k w^(k)_{j_k} and
-R = r1 r2 r3, and re-estimates the core from the original scattered data by the regression
+R = r1 ... r_d (d = 3, or 4 for the space-time form of Sec. 6), and re-estimates the core from the original scattered data by the regression
 eq. (6): alpha^ = argmin ||u - W alpha||^2, W[q, j] = w_j(y^q).  Algorithm 2 solves it on a
 sketch: rows of W and u are sign-flipped (D), mixed (FFT) and S > R of them are sampled
 uniformly, and step 5 solves the sampled problem exactly.
 
 Readings taken here:
-* the core is vectorised in C order, j = (j1 r2 + j2) r3 + j3;
+* the core is vectorised in C order, j = (j1 r2 + j2) r3 + j3 (and j r4 + j4 for d = 4);
 * the hot path samples M rows of W directly (no mixing).  D alone changes nothing, since
   (DW)^T (DW) = W^T W; the mixed variant is a separate, later row;
 * step 5 is read as min_alpha ||S W alpha - S u||^2 (the printed formula drops alpha) and is
@@ -25,20 +25,24 @@ from .sampler import STREAM_LS, sample_without_replacement
 
 
 def factor_values(model: Model, pts: np.ndarray):
-    """[U_k (m, r_k)]: U_k[q, j] = w^(k)_j(y^q_k) = sum_i C_k[i, j] phi_i(xi^q_k)  (eq. (2))."""
+    """[U_k (m, r_k)] for k = 1..d: U_k[q, j] = w^(k)_j(y^q_k) = sum_i C_k[i, j] phi_i(xi^q_k)
+    (eq. (2)); pts has one column per mode."""
     pts = np.asarray(pts, dtype=np.float64)
     out = []
-    for k in range(3):
+    for k in range(len(model.rank)):
         xi = to_reference(pts[:, k], model.lo[k], model.hi[k])
         out.append(legendre_orthonormal(xi, model.degree[k]) @ model.coefs[k])
     return out
 
 
 def design_rows(U) -> np.ndarray:
-    """A[q, (j1 r2 + j2) r3 + j3] = U1[q, j1] U2[q, j2] U3[q, j3]  (rows of W in eq. (6))."""
-    U1, U2, U3 = U
-    m = U1.shape[0]
-    return np.einsum("qa,qb,qc->qabc", U1, U2, U3).reshape(m, -1)
+    """A[q, j] = prod_k U_k[q, j_k], j = (..((j1 r2 + j2) r3 + j3)..) r_d + j_d: the rows of W in
+    eq. (6), each the Kronecker product of the point's factor rows in mode order."""
+    A = np.asarray(U[0], np.float64)
+    m = A.shape[0]
+    for Uk in U[1:]:
+        A = (A[:, :, None] * np.asarray(Uk, np.float64)[:, None, :]).reshape(m, -1)
+    return A
 
 
 def normal_equations(model: Model, pts: np.ndarray, v: np.ndarray, chunk: int = 4096):
@@ -74,7 +78,7 @@ def sample_rows(seed: int, n: int, m: int) -> np.ndarray:
 
 def refit_core(model: Model, pts: np.ndarray, vals: np.ndarray, n_samples: int, seed: int,
                chunk: int = 4096):
-    """Algorithm 2 with uniform row sampling: returns (alpha (r1, r2, r3), rows, G, h)."""
+    """Algorithm 2 with uniform row sampling: returns (alpha (r1, .., r_d), rows, G, h)."""
     if n_samples <= model.R:
         raise ValueError("Algorithm 2 needs more sampled rows than core entries (S > R)")
     idx = sample_rows(seed, pts.shape[0], n_samples)

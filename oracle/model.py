@@ -1,7 +1,9 @@
 """The functional sparse Tucker model (oracle, test infrastructure).
 
 Eq. (1): u~(y) = sum_{j1,j2,j3} alpha_{j1 j2 j3} w1_{j1}(y1) w2_{j2}(y2) w3_{j3}(y3), and
-eq. (2): w^(k)_j(y) = sum_i C_k[i, j] phi_i(y), with few non-zero C_k[i, j] (Sec. 2).
+eq. (2): w^(k)_j(y) = sum_i C_k[i, j] phi_i(y), with few non-zero C_k[i, j] (Sec. 2).  The
+format is the same for any number of modes d (Sec. 2 states it for d modes); the 4-way form
+carries one more factor w4_{j4}(y4) (the space-time data of Sec. 6).
 
 Storage (Sec. 2): prod r_k core values plus the non-zero expansion coefficients; only the
 values are counted, not the integers that locate them.
@@ -15,11 +17,11 @@ import numpy as np
 
 @dataclass
 class Model:
-    lo: tuple                 # box lower corner (3,)
-    hi: tuple                 # box upper corner (3,)
-    rank: tuple               # (r1, r2, r3)
-    degree: tuple             # (p1, p2, p3); n_k = p_k + 1 basis functions
-    core: np.ndarray          # (r1, r2, r3) float64; flattened in C order j = (j1 r2 + j2) r3 + j3
+    lo: tuple                 # box lower corner (d,)
+    hi: tuple                 # box upper corner (d,)
+    rank: tuple               # (r1, .., rd), d = 3 or 4
+    degree: tuple             # (p1, .., pd); n_k = p_k + 1 basis functions
+    core: np.ndarray          # (r1, .., rd) float64; flattened in C order j = (j1 r2 + j2) r3 + j3 ..
     coefs: list               # [C_k (n_k, r_k) float64, zeros where not in the support]
     info: dict = field(default_factory=dict)
 

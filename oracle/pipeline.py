@@ -24,21 +24,21 @@ def interpolation_subset(seed: int, n: int, fraction: float) -> np.ndarray:
 
 def reference_coords(pts: np.ndarray, lo, hi) -> np.ndarray:
     pts = np.asarray(pts, dtype=np.float64)
-    return np.stack([to_reference(pts[:, k], lo[k], hi[k]) for k in range(3)], axis=1)
+    return np.stack([to_reference(pts[:, k], lo[k], hi[k]) for k in range(len(lo))], axis=1)
 
 
 def compress(pts, vals, lo, hi, grid, rank, degree, interp_fraction, seed,
              idw_k: int = 8, idw_power: float = 2.0) -> Model:
     """Algorithm 1: interpolate a random subset onto the grid, ST-HOSVD at fixed ranks,
     then a sparse Legendre fit of every singular vector.  The returned model carries the
-    ST-HOSVD core alpha_0."""
+    ST-HOSVD core alpha_0.  The number of modes d (3 or 4) is len(grid)."""
     pts = np.asarray(pts, dtype=np.float64)
     vals = np.asarray(vals, dtype=np.float64)
     sub = interpolation_subset(seed, pts.shape[0], interp_fraction)
     xi = reference_coords(pts[sub], lo, hi)
     T = idw_to_grid(xi, vals[sub], grid, k=idw_k, power=idw_power)
     core0, W, sig = st_hosvd(T, rank)
-    coefs = [fit_factor(W[k], grid_nodes(grid[k]), degree[k]) for k in range(3)]
+    coefs = [fit_factor(W[k], grid_nodes(grid[k]), degree[k]) for k in range(len(grid))]
     return Model(tuple(lo), tuple(hi), tuple(rank), tuple(degree), core0, coefs,
                  info={"grid_tensor": T, "factors": W, "sigmas": sig, "subset": sub})
 

@@ -16,39 +16,45 @@ from .model import Model
 from .sthosvd import mode_product
 
 
+def _contract_rows(rows, T) -> np.ndarray:
+    """sum over (a, b, ..) of T[a, b, ..] rows[0][q, a] rows[1][q, b] .. for every q."""
+    idx = "abcd"[:len(rows)]
+    spec = ",".join("q" + c for c in idx) + "," + idx + "->q"
+    return np.einsum(spec, *rows, T, optimize=True)
+
+
 def evaluate(model: Model, pts: np.ndarray, chunk: int = 8192) -> np.ndarray:
-    """u~(y^q) = sum_{j1 j2 j3} alpha_{j1 j2 j3} U1[q,j1] U2[q,j2] U3[q,j3]  (eq. (1))."""
+    """u~(y^q) = sum_{j1 .. jd} alpha_{j1 .. jd} U1[q,j1] .. Ud[q,jd]  (eq. (1), d = 3 or 4)."""
     pts = np.asarray(pts, dtype=np.float64)
     out = np.empty(pts.shape[0], dtype=np.float64)
     core = np.asarray(model.core, np.float64)
     for s in range(0, pts.shape[0], chunk):
-        U1, U2, U3 = factor_values(model, pts[s:s + chunk])
-        out[s:s + chunk] = np.einsum("qa,qb,qc,abc->q", U1, U2, U3, core, optimize=True)
+        out[s:s + chunk] = _contract_rows(factor_values(model, pts[s:s + chunk]), core)
     return out
 
 
 def full_expansion_coefficients(model: Model) -> np.ndarray:
-    """beta (n1, n2, n3) of the tensor-product expansion equal to the Tucker model."""
+    """beta (n1, .., nd) of the tensor-product expansion equal to the Tucker model."""
     beta = np.asarray(model.core, np.float64)
-    for k in range(3):
+    for k in range(len(model.rank)):
         beta = mode_product(beta, model.coefs[k], k)
     return beta
 
 
 def evaluate_full_expansion(model: Model, pts: np.ndarray) -> np.ndarray:
-    """u(y) = sum_{i1 i2 i3} beta_{i1 i2 i3} phi_i1(y1) phi_i2(y2) phi_i3(y3)  (Sec. 2)."""
+    """u(y) = sum_{i1 .. id} beta_{i1 .. id} phi_i1(y1) .. phi_id(yd)  (Sec. 2)."""
     beta = full_expansion_coefficients(model)
     pts = np.asarray(pts, dtype=np.float64)
     P = [legendre_orthonormal(to_reference(pts[:, k], model.lo[k], model.hi[k]), model.degree[k])
-         for k in range(3)]
-    return np.einsum("qa,qb,qc,abc->q", P[0], P[1], P[2], beta, optimize=True)
+         for k in range(len(model.rank))]
+    return _contract_rows(P, beta)
 
 
 def evaluate_on_grid(model: Model, grid) -> np.ndarray:
     """Reconstruction on an equispaced reference grid by mode products (preview form):
-    alpha x_1 (Phi_1 C_1) x_2 (Phi_2 C_2) x_3 (Phi_3 C_3)."""
+    alpha x_1 (Phi_1 C_1) x_2 (Phi_2 C_2) .. x_d (Phi_d C_d)."""
     Y = np.asarray(model.core, np.float64)
-    for k in range(3):
+    for k in range(len(grid)):
         F = legendre_orthonormal(grid_nodes(grid[k]), model.degree[k]) @ model.coefs[k]
         Y = mode_product(Y, F, k)
     return Y
