@@ -25,7 +25,8 @@
  *    fst_model_free) and the small device copy of a model that it uploads on first use.
  *  - Output is bitwise reproducible for identical inputs on the same device: reductions run
  *    in a fixed order and use no floating-point atomics.
- *  - Limits of this version: d = 3, 1 <= r_k <= 32, 0 <= p_k <= 31, n < 2^31 points.
+ *  - Limits of this version: d = 3 (d = 3 or 4 through the d-way calls), 1 <= r_k <= 32,
+ *    0 <= p_k <= 31, n < 2^31 points.
  */
 #ifndef FST_H
 #define FST_H
@@ -312,6 +313,47 @@ int64_t fst_model_paper_bytes(const fst_model* m);
  * *nbytes is the capacity on input and the bytes written on output. */
 fst_status fst_model_save(const fst_model* m, void* buf, size_t* nbytes);
 fst_status fst_model_load(const void* buf, size_t nbytes, fst_model** out);
+
+/* ------------------------------------------------------------------ d-way models (d = 3 or 4) */
+/* Sec. 2 states the functional Tucker format for any number of modes d; Sec. 6 applies it to
+ * data in three space dimensions plus time.  These calls take models with d = 3 or d = 4;
+ * every call above that takes x, y, z (and fst_model_info) takes 3-way models only and
+ * returns FST_E_INVAL for a 4-way one.  fst_model_core, fst_model_coefs (k < d),
+ * fst_model_fit_info, fst_model_paper_bytes, fst_model_save / fst_model_load and
+ * fst_model_free take both.  The core is in C order, j = ((j1 r2 + j2) r3 + j3) r4 + j4. */
+
+/* lo, hi: host double[d]; rank, degree: host int32[d]; core: host FP64 r1 .. rd (C order);
+ * coefs[k]: host FP64 (p_k + 1) x r_k row-major.  FST_E_UNSUPPORTED for d other than 3, 4. */
+fst_status fst_model_from_parts_d(int32_t d, const double* lo, const double* hi, const int32_t* rank,
+                                  const int32_t* degree, const double* core,
+                                  const double* const* coefs, fst_model** out);
+/* d: modes; lo, hi (double[d]), rank, degree (int32[d]), nnz; any may be NULL (pass arrays of
+ * 4 entries when d is not known yet) */
+fst_status fst_model_info_d(const fst_model* m, int32_t* d, double* lo, double* hi, int32_t* rank,
+                            int32_t* degree, int64_t* nnz);
+
+/* Reconstruction at points of interest, eq. (1) with d factors: out[i] = u~(c_1[i], .., c_d[i]).
+ * coords: host array of d device coordinate arrays of n elements of `dtype`; out: device array
+ * of n elements of `dtype`.  Asynchronous on `stream`.  (d = 3 runs the kernel of fst_eval.) */
+fst_status fst_eval_d(const fst_model* m, int32_t dtype, int64_t n, const void* const* coords,
+                      void* out, void* stream);
+
+/* Algorithm 2 (Sec. 5) for a d-way model: M = n_samples rows drawn uniformly without
+ * replacement (stream FST_STREAM_LS of `seed`, sorted), the factor functions of the d modes
+ * evaluated at them (eq. (2)), the design rows A[q, j] = prod_k w^(k)_{j_k}(point q) of eq. (6)
+ * formed in chunks of 16384 rows (device workspace, A^T layout) and contracted into
+ * G = A^T A and h = A^T v on MFMA in the point dtype (FP32 rows: FP32 MFMA with FP64
+ * accumulation across chunks; FP64 rows: FP64 MFMA), then solved by the FP64 Cholesky
+ * factorisation (no refinement, no precision ladder: FST_E_NOT_SPD if the sampled Gram is
+ * not numerically positive definite).  coords: host array of d device coordinate arrays;
+ * v: device values; all of n elements of `dtype`.  R < n_samples <= n, r_k <= p_k + 1.
+ * ws: device workspace >= fst_refit_core_d_workspace_bytes (G alone is R^2 FP64), or NULL to
+ * let the library allocate it.  Synchronises `stream`; *out receives a new model with m's
+ * factors. */
+size_t fst_refit_core_d_workspace_bytes(const fst_model* m, int32_t dtype, int64_t n_samples);
+fst_status fst_refit_core_d(const fst_model* m, int32_t dtype, int64_t n, const void* const* coords,
+                            const void* v, int64_t n_samples, uint64_t seed, void* ws,
+                            size_t ws_bytes, void* stream, fst_model** out);
 
 /* ------------------------------------------------------------------ batched form */
 /* Many field variables on one shared point set (device arrays x, y, z of n points, dtype

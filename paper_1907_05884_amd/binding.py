@@ -99,6 +99,11 @@ _lib_fns = dict(
     fst_sthosvd_eps=(_i32, _vp, _vp, C.c_double, _vp, _i32, _vp, _vp, _vp, _vp),
     fst_sparse_fit=(_i32, _vp, _i32, _i32, _i32, _vp),
     fst_model_from_parts=(_i32, _vp, _vp, _vp, _vp, _vp, _vp, C.POINTER(_vp)),
+    fst_model_from_parts_d=(_i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp, C.POINTER(_vp)),
+    fst_model_info_d=(_i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp),
+    fst_eval_d=(_i32, _vp, _i32, _i64, _vp, _vp, _vp),
+    fst_refit_core_d_workspace_bytes=(C.c_size_t, _vp, _i32, _i64),
+    fst_refit_core_d=(_i32, _vp, _i32, _i64, _vp, _vp, _i64, C.c_uint64, _vp, C.c_size_t, _vp, C.POINTER(_vp)),
     fst_model_free=(None, _vp),
     fst_model_info=(_i32, _vp, _vp, _vp, _vp, _vp, _vp),
     fst_model_core=(_i32, _vp, _vp),
@@ -225,11 +230,17 @@ class Model:
         return self._h
 
     def info(self):
-        lo, hi = (C.c_double * 3)(), (C.c_double * 3)()
-        rank, degree = (C.c_int32 * 3)(), (C.c_int32 * 3)()
-        nnz = C.c_int64()
-        _check(_fn["fst_model_info"](self._h, lo, hi, rank, degree, C.byref(nnz)))
-        return dict(lo=tuple(lo), hi=tuple(hi), rank=tuple(rank), degree=tuple(degree), nnz=nnz.value)
+        lo, hi = (C.c_double * 4)(), (C.c_double * 4)()
+        rank, degree = (C.c_int32 * 4)(), (C.c_int32 * 4)()
+        d, nnz = C.c_int32(), C.c_int64()
+        _check(_fn["fst_model_info_d"](self._h, C.byref(d), lo, hi, rank, degree, C.byref(nnz)))
+        k = d.value
+        return dict(d=k, lo=tuple(lo[:k]), hi=tuple(hi[:k]), rank=tuple(rank[:k]), degree=tuple(degree[:k]),
+                    nnz=nnz.value)
+
+    @property
+    def d(self) -> int:
+        return self.info()["d"]
 
     @property
     def rank(self):
@@ -241,8 +252,7 @@ class Model:
 
     @property
     def R(self) -> int:
-        r = self.rank
-        return r[0] * r[1] * r[2]
+        return int(np.prod(self.rank))
 
     @property
     def core(self) -> np.ndarray:
@@ -271,20 +281,27 @@ class Model:
 
 
 def fst_model_from_parts(lo, hi, rank, degree, core, coefs) -> Model:
+    """A model of d = len(rank) modes (3: fst_model_from_parts, 4: fst_model_from_parts_d)."""
+    d = len(rank)
+    if not (len(lo) == len(hi) == len(degree) == len(coefs) == d):
+        raise ValueError("lo, hi, rank, degree and coefs need one entry per mode")
     lo_a, lo_p = _host(lo, np.float64)
     hi_a, hi_p = _host(hi, np.float64)
     r_a, r_p = _host(rank, np.int32)
     d_a, d_p = _host(degree, np.int32)
     c_a, c_p = _host(core, np.float64)
     cs = [np.ascontiguousarray(c, dtype=np.float64) for c in coefs]
-    for k in range(3):
+    for k in range(d):
         if cs[k].shape != (int(degree[k]) + 1, int(rank[k])):
             raise ValueError("coefficient matrix k must have shape (degree[k] + 1, rank[k])")
     if c_a.size != int(np.prod(rank)):
-        raise ValueError("core must have r1 r2 r3 entries")
-    arr = (C.c_void_p * 3)(*[c.ctypes.data_as(C.c_void_p) for c in cs])
+        raise ValueError("core must have r1 .. rd entries")
+    arr = (C.c_void_p * d)(*[c.ctypes.data_as(C.c_void_p) for c in cs])
     h = C.c_void_p()
-    _check(_fn["fst_model_from_parts"](lo_p, hi_p, r_p, d_p, c_p, arr, C.byref(h)))
+    if d == 3:
+        _check(_fn["fst_model_from_parts"](lo_p, hi_p, r_p, d_p, c_p, arr, C.byref(h)))
+    else:
+        _check(_fn["fst_model_from_parts_d"](d, lo_p, hi_p, r_p, d_p, c_p, arr, C.byref(h)))
     return Model(h)
 
 
@@ -375,6 +392,40 @@ def fst_eval(m: Model, x, y, z, out=None, stream=None):
     _check(_fn["fst_eval"](m.handle, _dtype_code(x), x.numel(), _dev_ptr(x), _dev_ptr(y), _dev_ptr(z),
                            _dev_ptr(out), _stream(stream)))
     return out
+
+
+# ------------------------------------------------------------------------------ d-way calls
+def _coord_list(coords):
+    return (C.c_void_p * len(coords))(*[_dev_ptr(c) for c in coords])
+
+
+def fst_eval_d(m: Model, coords, out=None, stream=None):
+    """Reconstruction of a d-way model at device points given as one array per mode."""
+    torch = _torch()
+    if out is None:
+        out = torch.empty_like(coords[0])
+    _check(_fn["fst_eval_d"](m.handle, _dtype_code(coords[0]), coords[0].numel(), _coord_list(coords),
+                             _dev_ptr(out), _stream(stream)))
+    return out
+
+
+def fst_refit_core_d_workspace_bytes(m: Model, dtype: int, n_samples: int) -> int:
+    b = _fn["fst_refit_core_d_workspace_bytes"](m.handle, int(dtype), int(n_samples))
+    if b == 0:
+        raise FstError(FST_E_INVAL, fst_last_error())
+    return int(b)
+
+
+def fst_refit_core_d(m: Model, coords, v, n_samples: int, seed: int, ws=None, stream=None) -> Model:
+    """Algorithm 2 for a d-way model from materialised design-row chunks and the dense MFMA Gram."""
+    dt = _dtype_code(coords[0])
+    n = coords[0].numel()
+    if ws is None:
+        ws = _workspace(fst_refit_core_d_workspace_bytes(m, dt, n_samples), coords[0].device)
+    h = C.c_void_p()
+    _check(_fn["fst_refit_core_d"](m.handle, dt, n, _coord_list(coords), _dev_ptr(v), int(n_samples), int(seed),
+                                   _dev_ptr(ws), ws.numel(), _stream(stream), C.byref(h)))
+    return Model(h)
 
 
 # ------------------------------------------------------------------------------ batched form

@@ -233,13 +233,6 @@ static size_t refit_bytes_for(const int32_t rank[3], const int32_t degree[3], in
   return refit_layout(tmp->R(), tmp->sum_r(), M, dtype, refine, refit_scratch(tmp.get(), M, refine)).total;
 }
 
-static fst_model* copy_with_core(const fst_model* m, const std::vector<double>& core) {
-  fst_model* out = model_new(m->lo, m->hi, m->rank, m->degree);
-  for (int k = 0; k < 3; ++k) out->coef[k] = m->coef[k];
-  out->core = core;
-  return out;
-}
-
 // Algorithm 2 with mixing: workspace = G, h, alpha, Cholesky scratch, then the mixed rows
 struct MixedRefitLayout {
   size_t G, h, alpha, chol, mix, total;
@@ -265,7 +258,7 @@ static MixedRefitLayout mixed_refit_layout(const fst_model* m, int dtype, int64_
 static fst_model* refit_mixed_impl(const fst_model* m, int dtype, int64_t n, const void* x, const void* y,
                                    const void* z, const void* v, int64_t M, uint64_t seed, void* ws_user,
                                    size_t ws_bytes, void* stream) {
-  check_model(m);
+  check_model3(m);
   check_dtype(dtype);
   const int64_t R = m->R();
   if (n < 1 || n > (int64_t(1) << 23)) fail(FST_E_INVAL, "the mixed refit needs 1 <= n <= 2^23 points");
@@ -298,7 +291,7 @@ static fst_model* refit_mixed_impl(const fst_model* m, int dtype, int64_t n, con
 static fst_model* refit_impl(const fst_model* m, int dtype, int64_t n, const void* x, const void* y,
                              const void* z, const void* v, int64_t M, uint64_t seed, int gram_prec,
                              int refine, void* ws_user, size_t ws_bytes, void* stream) {
-  check_model(m);
+  check_model3(m);
   check_dtype(dtype);
   check_prec(dtype, gram_prec);
   const int64_t R = m->R();
@@ -391,6 +384,79 @@ static fst_model* compress_from_subset(const fst_fit_params* p, const std::vecto
   std::copy(core.begin(), core.begin() + (size_t)rank[0] * rank[1] * rank[2], m->core.begin());
   for (int k = 0; k < 3; ++k) sparse_fit(W[k].data(), p->grid[k], rank[k], p->degree[k], m->coef[k].data());
   return m.release();
+}
+
+// ---------------------------------------------------------------- d-way refit (d = 3 or 4)
+// Algorithm 2 from materialised row chunks: workspace = sampled indices, G, h, alpha,
+// Cholesky scratch, then the rows
+struct DwayRefitLayout {
+  size_t idx, G, h, alpha, chol, rows, total;
+};
+static DwayRefitLayout dway_refit_layout(const fst_model* m, int dtype, int64_t M) {
+  const int64_t R = m->R();
+  DwayRefitLayout L;
+  size_t off = 0;
+  L.idx = off;
+  off += align_up(sizeof(int32_t) * (size_t)M);
+  L.G = off;
+  off += align_up(sizeof(double) * (size_t)R * (size_t)R);
+  L.h = off;
+  off += align_up(sizeof(double) * (size_t)R);
+  L.alpha = off;
+  off += align_up(sizeof(double) * (size_t)R);
+  L.chol = off;
+  off += align_up(cholesky_workspace_bytes(R));
+  L.rows = off;
+  off += dway_workspace_bytes(m, dtype, M);
+  L.total = off;
+  return L;
+}
+
+static void check_coords(const fst_model* m, const void* const* coords) {
+  if (!coords) fail(FST_E_INVAL, "null coordinate list");
+  for (int k = 0; k < m->d; ++k)
+    if (!coords[k]) fail(FST_E_INVAL, "null coordinate array");
+}
+
+static fst_model* refit_d_impl(const fst_model* m, int dtype, int64_t n, const void* const* coords, const void* v,
+                               int64_t M, uint64_t seed, void* ws_user, size_t ws_bytes, void* stream) {
+  check_model(m);
+  check_dtype(dtype);
+  const int64_t R = m->R();
+  if (n < 1 || n >= (int64_t(1) << 31)) fail(FST_E_INVAL, "need 1 <= n < 2^31 points");
+  if (M <= R || M > n) fail(FST_E_INVAL, "Algorithm 2 needs r1 .. rd < n_samples <= n");
+  for (int k = 0; k < m->d; ++k)
+    if (m->rank[k] > m->degree[k] + 1) fail(FST_E_INVAL, "Algorithm 2 needs rank <= degree + 1 in every mode");
+  check_coords(m, coords);
+  if (!v) fail(FST_E_INVAL, "null value array");
+  const DwayRefitLayout L = dway_refit_layout(m, dtype, M);
+  Workspace ws(ws_user, ws_bytes, L.total);
+  char* base = (char*)ws.p;
+  int32_t* d_idx = (int32_t*)(base + L.idx);
+  double* d_G = (double*)(base + L.G);
+  double* d_h = (double*)(base + L.h);
+  double* d_alpha = (double*)(base + L.alpha);
+  // step 4: M rows drawn uniformly without replacement (stream 2), sorted
+  std::vector<int64_t> idx((size_t)M);
+  sample_indices(seed, FST_STREAM_LS, n, M, idx.data());
+  std::vector<int32_t> idx32((size_t)M);
+  for (int64_t i = 0; i < M; ++i) idx32[(size_t)i] = (int32_t)idx[(size_t)i];
+  copy_h2d(d_idx, idx32.data(), sizeof(int32_t) * (size_t)M, stream);
+  // steps 1 and 5
+  dway_normal_equations(m, dtype, coords, v, d_idx, M, base + L.rows, ws.bytes - L.rows, d_G, d_h, stream);
+  const int64_t piv = cholesky(R, d_G, base + L.chol, cholesky_workspace_bytes(R), stream);
+  if (piv != 0)
+    fail(FST_E_NOT_SPD, "d-way refit: Cholesky breakdown at pivot " + std::to_string(piv) +
+                            " (numerically rank-deficient sampled rows)");
+  cholesky_solve(R, d_G, d_h, d_alpha, stream);
+  std::vector<double> alpha((size_t)R);
+  copy_d2h(alpha.data(), d_alpha, sizeof(double) * (size_t)R, stream);
+  for (double t : alpha)
+    if (!std::isfinite(t)) fail(FST_E_NOT_SPD, "d-way refit produced non-finite core values");
+  fst_model* out = copy_with_core(m, alpha);
+  out->fit.gram_prec = dtype == FST_F64 ? FST_GRAM_F64 : FST_GRAM_F32;
+  out->fit.refine_steps = 0;
+  return out;
 }
 
 }  // namespace fst
@@ -508,7 +574,7 @@ fst_status fst_fit(const fst_fit_params* p, int64_t n, const void* x, const void
 size_t fst_refit_workspace_bytes(const fst_model* m, int32_t dtype, int64_t n_samples,
                                  int32_t refine_steps) {
   try {
-    check_model(m);
+    check_model3(m);
     check_dtype(dtype);
     if (n_samples < 1 || refine_steps < 0) fail(FST_E_INVAL, "bad sizes");
     return refit_layout(m->R(), m->sum_r(), n_samples, dtype, refine_steps,
@@ -535,7 +601,7 @@ fst_status fst_eval(const fst_model* m, int32_t dtype, int64_t n, const void* x,
                     const void* z, void* out, void* stream) {
   FST_TRY
   set_last_error("");
-  check_model(m);
+  check_model3(m);
   check_dtype(dtype);
   if (n < 0 || n >= (int64_t(1) << 31)) fail(FST_E_INVAL, "need 0 <= n < 2^31 points");
   if (n == 0) return FST_OK;
@@ -554,7 +620,7 @@ static void check_grid_counts(int64_t n1, int64_t n2, int64_t n3) {
 }
 
 size_t fst_eval_grid_workspace_bytes(const fst_model* m, int32_t dtype, int64_t n1, int64_t n2, int64_t n3) {
-  if (!m || (dtype != FST_F64 && dtype != FST_F32) || n1 < 1 || n2 < 1 || n3 < 1) return 0;
+  if (!m || m->d != 3 || (dtype != FST_F64 && dtype != FST_F32) || n1 < 1 || n2 < 1 || n3 < 1) return 0;
   return eval_grid_workspace_bytes(m, dtype, n1, n2, n3);
 }
 
@@ -562,7 +628,7 @@ fst_status fst_eval_grid(const fst_model* m, int32_t dtype, const void* gx, int6
                          const void* gz, int64_t n3, void* out, void* ws, size_t ws_bytes, void* stream) {
   FST_TRY
   set_last_error("");
-  check_model(m);
+  check_model3(m);
   check_dtype(dtype);
   check_grid_counts(n1, n2, n3);
   if (!gx || !gy || !gz || !out) fail(FST_E_INVAL, "null coordinate or output array");
@@ -587,7 +653,8 @@ fst_status fst_eval_grid(const fst_model* m, int32_t dtype, const void* gx, int6
 }
 
 size_t fst_refit_core_mixed_workspace_bytes(const fst_model* m, int32_t dtype, int64_t n, int64_t n_samples) {
-  if (!m || (dtype != FST_F64 && dtype != FST_F32) || n < 1 || n > (int64_t(1) << 23) || n_samples < 1) return 0;
+  if (!m || m->d != 3 || (dtype != FST_F64 && dtype != FST_F32) || n < 1 || n > (int64_t(1) << 23) || n_samples < 1)
+    return 0;
   return mixed_refit_layout(m, dtype, n, n_samples).total;
 }
 
@@ -612,7 +679,7 @@ fst_status fst_eval_error(const fst_model* m, int32_t dtype, int64_t n, const vo
                           double* sums_out) {
   FST_TRY
   set_last_error("");
-  check_model(m);
+  check_model3(m);
   check_dtype(dtype);
   if (n < 1 || n >= (int64_t(1) << 31)) fail(FST_E_INVAL, "need 1 <= n < 2^31 points");
   if (!x || !y || !z || !v || !sums_out) fail(FST_E_INVAL, "null argument");
@@ -627,7 +694,7 @@ fst_status fst_factor_eval(const fst_model* m, int32_t dtype, int64_t n, const v
                            void* vs, void* stream) {
   FST_TRY
   set_last_error("");
-  check_model(m);
+  check_model3(m);
   check_dtype(dtype);
   if (n < 0 || mrows < 0 || n >= (int64_t(1) << 31)) fail(FST_E_INVAL, "bad sizes");
   if (!idx && mrows > n) fail(FST_E_INVAL, "mrows > n without an index array");
@@ -641,7 +708,7 @@ fst_status fst_factor_eval(const fst_model* m, int32_t dtype, int64_t n, const v
 }
 
 size_t fst_gram_workspace_bytes(const fst_model* m, int64_t mrows) {
-  if (!m || mrows < 0) return 0;
+  if (!m || m->d != 3 || mrows < 0) return 0;
   return gram_workspace_bytes(m, mrows);
 }
 
@@ -649,7 +716,7 @@ fst_status fst_gram(const fst_model* m, int32_t dtype, int64_t mrows, const void
                     int32_t gram_prec, double* G, double* h, void* ws, size_t ws_bytes, void* stream) {
   FST_TRY
   set_last_error("");
-  check_model(m);
+  check_model3(m);
   check_dtype(dtype);
   check_prec(dtype, gram_prec);
   if (mrows < 1) fail(FST_E_INVAL, "need mrows >= 1");
@@ -687,7 +754,7 @@ fst_status fst_cholesky_solve(int64_t R, const double* L, const double* b, doubl
 }
 
 size_t fst_residual_workspace_bytes(const fst_model* m, int64_t mrows) {
-  if (!m || mrows < 0) return 0;
+  if (!m || m->d != 3 || mrows < 0) return 0;
   return residual_workspace_bytes(m, mrows);
 }
 
@@ -696,7 +763,7 @@ fst_status fst_residual(const fst_model* m, int32_t dtype, int64_t n, const void
                         const double* alpha, double* r, void* ws, size_t ws_bytes, void* stream) {
   FST_TRY
   set_last_error("");
-  check_model(m);
+  check_model3(m);
   check_dtype(dtype);
   if (mrows < 1 || n < 1) fail(FST_E_INVAL, "bad sizes");
   if (!x || !y || !z || !v || !idx || !alpha || !r || !ws) fail(FST_E_INVAL, "null argument");
@@ -706,7 +773,7 @@ fst_status fst_residual(const fst_model* m, int32_t dtype, int64_t n, const void
 }
 
 size_t fst_refine_workspace_bytes(const fst_model* m, int64_t mrows) {
-  if (!m || mrows < 0) return 0;
+  if (!m || m->d != 3 || mrows < 0) return 0;
   return align_up(sizeof(double) * (size_t)m->R()) + residual_workspace_bytes(m, mrows);
 }
 
@@ -715,7 +782,7 @@ fst_status fst_refine_step(const fst_model* m, int32_t dtype, int64_t n, const v
                            double* alpha, double* r_out, void* ws, size_t ws_bytes, void* stream) {
   FST_TRY
   set_last_error("");
-  check_model(m);
+  check_model3(m);
   check_dtype(dtype);
   if (mrows < 1 || n < 1) fail(FST_E_INVAL, "bad sizes");
   if (!x || !y || !z || !v || !idx || !L || !alpha || !ws) fail(FST_E_INVAL, "null argument");
@@ -787,15 +854,21 @@ fst_status fst_sparse_fit(const double* W, int32_t I, int32_t r, int32_t p, doub
 fst_status fst_model_from_parts(const double lo[3], const double hi[3], const int32_t rank[3],
                                 const int32_t degree[3], const double* core, const double* const coefs[3],
                                 fst_model** out) {
+  return fst_model_from_parts_d(3, lo, hi, rank, degree, core, coefs, out);
+}
+
+fst_status fst_model_from_parts_d(int32_t d, const double* lo, const double* hi, const int32_t* rank,
+                                  const int32_t* degree, const double* core, const double* const* coefs,
+                                  fst_model** out) {
   FST_TRY
   set_last_error("");
   if (!lo || !hi || !rank || !degree || !core || !coefs || !out) fail(FST_E_INVAL, "null argument");
-  std::unique_ptr<fst_model> m(model_new(lo, hi, rank, degree));
+  std::unique_ptr<fst_model> m(model_new_d(d, lo, hi, rank, degree));
   for (size_t i = 0; i < m->core.size(); ++i) {
     if (!std::isfinite(core[i])) fail(FST_E_INVAL, "non-finite core entry");
     m->core[i] = core[i];
   }
-  for (int k = 0; k < 3; ++k) {
+  for (int k = 0; k < d; ++k) {
     if (!coefs[k]) fail(FST_E_INVAL, "null coefficient matrix");
     for (size_t i = 0; i < m->coef[k].size(); ++i) {
       if (!std::isfinite(coefs[k][i])) fail(FST_E_INVAL, "non-finite coefficient");
@@ -813,7 +886,7 @@ fst_status fst_model_info(const fst_model* m, double* lo, double* hi, int32_t* r
                           int64_t* nnz) {
   FST_TRY
   set_last_error("");
-  check_model(m);
+  check_model3(m);
   for (int k = 0; k < 3; ++k) {
     if (lo) lo[k] = m->lo[k];
     if (hi) hi[k] = m->hi[k];
@@ -826,6 +899,62 @@ fst_status fst_model_info(const fst_model* m, double* lo, double* hi, int32_t* r
       for (double t : m->coef[k]) c += t != 0.0;
     *nnz = c;
   }
+  return FST_OK;
+  FST_CATCH
+}
+
+fst_status fst_model_info_d(const fst_model* m, int32_t* d, double* lo, double* hi, int32_t* rank,
+                            int32_t* degree, int64_t* nnz) {
+  FST_TRY
+  set_last_error("");
+  check_model(m);
+  if (d) *d = m->d;
+  for (int k = 0; k < m->d; ++k) {
+    if (lo) lo[k] = m->lo[k];
+    if (hi) hi[k] = m->hi[k];
+    if (rank) rank[k] = m->rank[k];
+    if (degree) degree[k] = m->degree[k];
+  }
+  if (nnz) {
+    int64_t c = 0;
+    for (int k = 0; k < m->d; ++k)
+      for (double t : m->coef[k]) c += t != 0.0;
+    *nnz = c;
+  }
+  return FST_OK;
+  FST_CATCH
+}
+
+size_t fst_refit_core_d_workspace_bytes(const fst_model* m, int32_t dtype, int64_t n_samples) {
+  if (!m || (dtype != FST_F64 && dtype != FST_F32) || n_samples < 1) return 0;
+  return dway_refit_layout(m, dtype, n_samples).total;
+}
+
+fst_status fst_refit_core_d(const fst_model* m, int32_t dtype, int64_t n, const void* const* coords, const void* v,
+                            int64_t n_samples, uint64_t seed, void* ws, size_t ws_bytes, void* stream,
+                            fst_model** out) {
+  FST_TRY
+  set_last_error("");
+  if (!out) fail(FST_E_INVAL, "null output");
+  *out = refit_d_impl(m, dtype, n, coords, v, n_samples, seed, ws, ws_bytes, stream);
+  return FST_OK;
+  FST_CATCH
+}
+
+fst_status fst_eval_d(const fst_model* m, int32_t dtype, int64_t n, const void* const* coords, void* out,
+                      void* stream) {
+  FST_TRY
+  set_last_error("");
+  check_model(m);
+  check_dtype(dtype);
+  if (n < 0 || n >= (int64_t(1) << 31)) fail(FST_E_INVAL, "need 0 <= n < 2^31 points");
+  if (n == 0) return FST_OK;
+  check_coords(m, coords);
+  if (!out) fail(FST_E_INVAL, "null output array");
+  const void* c4[kMaxModes] = {nullptr, nullptr, nullptr, nullptr};
+  for (int k = 0; k < m->d; ++k) c4[k] = coords[k];
+  const DeviceModel& dm = device_model(m, dtype);
+  launch_eval_d(m, dm, dtype, n, c4, out, stream);
   return FST_OK;
   FST_CATCH
 }
@@ -844,7 +973,7 @@ fst_status fst_model_coefs(const fst_model* m, int32_t k, double* C_out) {
   FST_TRY
   set_last_error("");
   check_model(m);
-  if (k < 0 || k > 2 || !C_out) fail(FST_E_INVAL, "bad mode or null output");
+  if (k < 0 || k >= m->d || !C_out) fail(FST_E_INVAL, "bad mode or null output");
   std::memcpy(C_out, m->coef[k].data(), sizeof(double) * m->coef[k].size());
   return FST_OK;
   FST_CATCH
@@ -866,7 +995,7 @@ fst_status fst_model_fit_info(const fst_model* m, int32_t* gram_prec_used, int64
 int64_t fst_model_paper_bytes(const fst_model* m) {
   if (!m) return -1;
   int64_t nnz = 0;
-  for (int k = 0; k < 3; ++k)
+  for (int k = 0; k < m->d; ++k)
     for (double t : m->coef[k]) nnz += t != 0.0;
   return 8 * (m->R() + nnz);
 }

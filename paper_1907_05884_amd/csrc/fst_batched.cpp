@@ -264,8 +264,10 @@ fst_status fst_eval_graph_create(const fst_model* const* models, int32_t V, int3
   if (n < 1 || n >= (int64_t(1) << 31)) fst::fail(FST_E_INVAL, "bad n");
   std::vector<const fst_model*> ms(models, models + V);
   std::vector<void*> os(outs, outs + V);
-  for (int v = 0; v < V; ++v)
-    if (!ms[(size_t)v] || !os[(size_t)v]) fst::fail(FST_E_INVAL, "null model or output");
+  for (int v = 0; v < V; ++v) {
+    if (!os[(size_t)v]) fst::fail(FST_E_INVAL, "null model or output");
+    fst::check_model3(ms[(size_t)v]);
+  }
   std::unique_ptr<fst_graph> g(new fst_graph());
   g->g = fst::eval_graph_create(ms, dtype, n, x, y, z, os);
   *out = g.release();

@@ -92,7 +92,7 @@ fst_status fst_corrector_train(const fst_model* m, int32_t dtype, int64_t n, con
                                size_t ws_bytes, void* stream, fst_corrector** out) {
   FST_TRY
   fst::set_last_error("");
-  fst::check_model(m);
+  fst::check_model3(m);
   check_train_params(tp);
   if (dtype != FST_F64 && dtype != FST_F32) fst::fail(FST_E_INVAL, "bad dtype");
   if (n < 2 || n >= (int64_t(1) << 31)) fst::fail(FST_E_INVAL, "need 2 <= n < 2^31 training points");

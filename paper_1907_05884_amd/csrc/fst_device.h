@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <cstdint>
 
 #include "fst_internal.h"
@@ -28,6 +29,44 @@ template <> struct MfmaAcc<double> {
   static __device__ inline V mfma(double a, double b, V c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
   static __device__ inline int row(int g, int v) { return g + 4 * v; }
 };
+
+// ------------------------------------------------------------------------------ basis
+// Orthonormal Legendre recurrence phi_{m+1} = a_m t phi_m - b_m phi_{m-1}, phi_0 = 1,
+// phi_1 = sqrt(3) t, from Bonnet's recurrence with phi_m = sqrt(2m+1) P_m:
+//   a_m = sqrt((2m+1)(2m+3)) / (m+1),  b_m = m sqrt(2m+3) / ((m+1) sqrt(2m-1)).
+template <typename T>
+struct Recurrence {
+  T a[kMaxBasis];
+  T b[kMaxBasis];
+};
+template <typename T>
+static inline Recurrence<T> make_recurrence() {
+  Recurrence<T> r;
+  for (int m = 0; m < kMaxBasis; ++m) {
+    double a = std::sqrt((2.0 * m + 1.0) * (2.0 * m + 3.0)) / (m + 1.0);
+    double b = m == 0 ? 0.0 : m * std::sqrt(2.0 * m + 3.0) / ((m + 1.0) * std::sqrt(2.0 * m - 1.0));
+    r.a[m] = (T)a;
+    r.b[m] = (T)b;
+  }
+  return r;
+}
+
+template <typename T>
+struct ModeMap {   // xi = (y - lo) * scale - 1, scale = 2 / (hi - lo)
+  T lo[kMaxModes];
+  T scale[kMaxModes];
+};
+template <typename T>
+static inline ModeMap<T> make_map(const fst_model* m) {
+  ModeMap<T> mm;
+  for (int k = 0; k < kMaxModes; ++k) {
+    mm.lo[k] = (T)m->lo[k];
+    mm.scale[k] = (T)(2.0 / (m->hi[k] - m->lo[k]));
+  }
+  return mm;
+}
+
+static inline int pad8(int r) { return (r + 7) / 8 * 8; }
 
 // lower-triangle tile t -> (bi, bj), bj <= bi, t = bi (bi + 1) / 2 + bj
 __device__ inline void tri_tile(int64_t t, int64_t& bi, int64_t& bj) {

@@ -1,0 +1,343 @@
+// The d-way form of the hot path for gfx950: Algorithm 2 and the reconstruction of eq. (1)
+// for models with d = 4 modes (Sec. 2 states the format for any d; Sec. 6 compresses data in
+// three space dimensions plus time).  The refit also takes 3-way models (r4 = 1).
+//
+//   k_factor_eval  eq. (2) at the M sampled rows for the d modes (fst_kernels.hip)
+//   k_design_rows  rows of W in eq. (6) for a chunk of sampled rows, written transposed:
+//                  A^T[j][q] = U1[q][j1] U2[q][j2] U3[q][j3] U4[q][j4],
+//                  j = ((j1 r2 + j2) r3 + j3) r4 + j4
+//   k_gram_dense   G += A^T A (lower triangle) of the chunk on MFMA, and h += A^T v (fst_mix.hip)
+//   k_eval4        eq. (1) at points of interest
+//
+// Rows are materialised here, unlike in the 3-way Gram, which forms them inside its MFMA
+// loop: a chunk of C = 16384 rows is R C values, written once at HBM speed, against 2 R^2 C
+// flop of Gram work on them, so the write costs about 1% of the contraction at R = 20,736 and
+// the dense Gram (its operands come straight from LDS) runs at the MFMA rate it reaches in the
+// mixed refit.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <string>
+
+#include "fst_device.h"
+#include "fst_internal.h"
+
+namespace fst {
+
+// ------------------------------------------------------------------------------ design rows
+// One thread per row q of the chunk (q < Sp, rows mc .. Sp-1 are zero), one workgroup row per
+// (j1, j2) pair: the product u1 u2 is formed once, the r4 values of U4 are held in registers
+// (RP of them, clamped past r4; RP = 1 and u4 = 1 for a 3-way model) and every (j3, j4)
+// column is a coalesced run of 256 entries of A^T.  The workgroups of pair 0 also write b.
+template <typename T>
+struct DesignArgs {
+  const T* U;      // [sum r][M] factor values of the sampled rows (feature-major)
+  const T* vs;     // [M] sampled values
+  T* At;           // [R][Sp]
+  T* b;            // [Sp]
+  int64_t M, q0, mc, Sp;
+  int32_t r[kMaxModes], off[kMaxModes];
+};
+
+constexpr int DR_THREADS = 256;
+
+template <typename T, int RP>
+__global__ __launch_bounds__(DR_THREADS) void k_design_rows(DesignArgs<T> a) {
+  const int64_t q = (int64_t)blockIdx.x * DR_THREADS + threadIdx.x;
+  if (q >= a.Sp) return;
+  const bool live = q < a.mc;
+  const int64_t col = a.q0 + (live ? q : a.mc - 1);
+  const int pair = (int)blockIdx.y;
+  const int j1 = pair / a.r[1], j2 = pair - j1 * a.r[1];
+  const T* U = a.U;
+  const T p12 = U[(int64_t)(a.off[0] + j1) * a.M + col] * U[(int64_t)(a.off[1] + j2) * a.M + col];
+  const T pm = live ? p12 : T(0);
+  T u4[RP];
+#pragma unroll
+  for (int j4 = 0; j4 < RP; ++j4)
+    u4[j4] = RP == 1 ? T(1) : U[(int64_t)(a.off[3] + min(j4, a.r[3] - 1)) * a.M + col];
+  T* dst = a.At + (int64_t)pair * a.r[2] * a.r[3] * a.Sp + q;
+  for (int j3 = 0; j3 < a.r[2]; ++j3) {
+    const T p = pm * U[(int64_t)(a.off[2] + j3) * a.M + col];
+#pragma unroll
+    for (int j4 = 0; j4 < RP; ++j4)
+      if (j4 < a.r[3]) dst[(int64_t)(j3 * a.r[3] + j4) * a.Sp] = p * u4[j4];
+  }
+  if (pair == 0) a.b[q] = live ? a.vs[col] : T(0);
+}
+
+constexpr int64_t DW_CHUNK = 16384;   // sampled rows per materialised chunk
+static_assert(DW_CHUNK % GD_SP_MULTIPLE == 0, "chunks must be whole Gram chunks");
+
+struct DwayLayout {
+  int64_t Sc;                   // rows of the largest chunk, padded
+  size_t U, vs, At, b, total;   // byte offsets in the workspace
+};
+
+static DwayLayout dway_layout(const fst_model* m, int dtype, int64_t M) {
+  const size_t es = dtype == FST_F64 ? 8 : 4;
+  DwayLayout L;
+  L.Sc = std::min<int64_t>(DW_CHUNK, (M + GD_SP_MULTIPLE - 1) / GD_SP_MULTIPLE * GD_SP_MULTIPLE);
+  size_t off = 0;
+  L.U = off;
+  off += align_up(es * (size_t)m->sum_r() * (size_t)M);
+  L.vs = off;
+  off += align_up(es * (size_t)M);
+  L.At = off;
+  off += align_up(es * (size_t)m->R() * (size_t)L.Sc);
+  L.b = off;
+  off += align_up(es * (size_t)L.Sc);
+  L.total = off;
+  return L;
+}
+
+size_t dway_workspace_bytes(const fst_model* m, int dtype, int64_t M) { return dway_layout(m, dtype, M).total; }
+
+template <typename T, int RP>
+static void design_launch(const DesignArgs<T>& a, void* stream) {
+  const dim3 g((unsigned)((a.Sp + DR_THREADS - 1) / DR_THREADS), (unsigned)(a.r[0] * a.r[1]));
+  hipLaunchKernelGGL((k_design_rows<T, RP>), g, dim3(DR_THREADS), 0, S(stream), a);
+  check_launch("k_design_rows");
+}
+
+template <typename T>
+static void dway_chunks(const fst_model* m, const DwayLayout& L, char* w, int64_t M, double* G, double* h,
+                        void* stream) {
+  const int dtype = sizeof(T) == 8 ? FST_F64 : FST_F32;
+  DesignArgs<T> a;
+  a.U = (const T*)(w + L.U);
+  a.vs = (const T*)(w + L.vs);
+  a.At = (T*)(w + L.At);
+  a.b = (T*)(w + L.b);
+  a.M = M;
+  int off = 0;
+  for (int k = 0; k < kMaxModes; ++k) {
+    a.r[k] = k < m->d ? m->rank[k] : 1;
+    a.off[k] = off;
+    off += k < m->d ? m->rank[k] : 0;
+  }
+  const int rp = m->d == 4 ? pad8(m->rank[3]) : 1;
+  for (int64_t q0 = 0; q0 < M; q0 += L.Sc) {
+    a.q0 = q0;
+    a.mc = std::min<int64_t>(L.Sc, M - q0);
+    a.Sp = (a.mc + GD_SP_MULTIPLE - 1) / GD_SP_MULTIPLE * GD_SP_MULTIPLE;
+    switch (rp) {
+      case 1: design_launch<T, 1>(a, stream); break;
+      case 8: design_launch<T, 8>(a, stream); break;
+      case 16: design_launch<T, 16>(a, stream); break;
+      case 24: design_launch<T, 24>(a, stream); break;
+      default: design_launch<T, 32>(a, stream); break;
+    }
+    dense_normal_equations(dtype, a.At, a.b, m->R(), a.Sp, G, h, q0 > 0, stream);
+  }
+}
+
+void dway_normal_equations(const fst_model* m, int dtype, const void* const* coords, const void* v,
+                           const int32_t* idx, int64_t M, void* ws, size_t ws_bytes, double* G, double* h,
+                           void* stream) {
+  const DwayLayout L = dway_layout(m, dtype, M);
+  if (ws_bytes < L.total) fail(FST_E_NOMEM, "d-way rows: workspace too small");
+  if (m->R() * L.Sc >= (int64_t(1) << 40)) fail(FST_E_UNSUPPORTED, "d-way rows: chunk of A^T too large");
+  if ((int64_t)m->sum_r() * M >= (int64_t(1) << 40)) fail(FST_E_UNSUPPORTED, "d-way rows: too many factor values");
+  char* w = (char*)ws;
+  const DeviceModel& dm = device_model(m, dtype);
+  // Algorithm 2 step 1 at the sampled rows: factor functions of the d modes and the values
+  launch_factor_eval_d(m, dm, dtype, coords, v, idx, M, w + L.U, w + L.vs, stream);
+  // step 5: normal equations of the sampled rows, chunk by chunk
+  if (dtype == FST_F64)
+    dway_chunks<double>(m, L, w, M, G, h, stream);
+  else
+    dway_chunks<float>(m, L, w, M, G, h, stream);
+}
+
+// ------------------------------------------------------------------------------ reconstruction
+// eq. (1) for d = 4: f = sum_{j1 j2} u1[j1] u2[j2] sum_{j3} u3[j3] sum_{j4} alpha[j1 j2 j3 j4] u4[j4].
+// One thread per point.  The basis values of modes 1 and 2 and the factor values u3, u4 (RP of
+// each, zero past r3, r4) stay in registers; u1 and u2 are formed per (j1, j2) pair from the
+// coefficients, read with wave-uniform addresses.  The core is staged in LDS as RP x RP slices
+// per (j1, j2) pair (zero-padded), as many pairs per slice as fit in 64 KB; every thread reads
+// the same LDS word at a time (a broadcast).  The sums run in a fixed order.
+template <typename TIn, typename T>
+struct Eval4Args {
+  const TIn* c[kMaxModes];
+  const T* coefs;   // [kMaxModes][kMaxBasis][kMaxRank]
+  const T* core;    // R, C order
+  TIn* out;
+  int64_t n;
+  int32_t r[kMaxModes];
+  int32_t pair_chunk;
+  ModeMap<T> map;
+  Recurrence<T> rec;
+};
+
+constexpr size_t EVAL4_LDS_BUDGET = 64 * 1024;
+
+template <typename TIn, typename T, int NP, int RP>
+__global__ __launch_bounds__(256) void k_eval4(Eval4Args<TIn, T> a) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* sA = reinterpret_cast<T*>(smem_raw);   // [pair_chunk][RP][RP]
+  const T* __restrict__ C1 = a.coefs;
+  const T* __restrict__ C2 = a.coefs + kMaxBasis * kMaxRank;
+  const T* __restrict__ C3 = a.coefs + 2 * kMaxBasis * kMaxRank;
+  const T* __restrict__ C4 = a.coefs + 3 * kMaxBasis * kMaxRank;
+  const int r2 = a.r[1], r3 = a.r[2], r4 = a.r[3];
+  const int npairs = a.r[0] * r2;
+  const int nchunk = (npairs + a.pair_chunk - 1) / a.pair_chunk;
+  auto load_chunk = [&](int c) {
+    const int p0 = c * a.pair_chunk;
+    const int rows = min(a.pair_chunk, npairs - p0);
+    for (int e = threadIdx.x; e < rows * RP * RP; e += blockDim.x) {
+      const int pp = e / (RP * RP), j3 = (e / RP) % RP, j4 = e % RP;
+      sA[e] = (j3 < r3 && j4 < r4) ? a.core[((int64_t)(p0 + pp) * r3 + j3) * r4 + j4] : T(0);
+    }
+  };
+  if (nchunk == 1) load_chunk(0);
+  __syncthreads();
+
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t nround = (a.n + stride - 1) / stride;
+  for (int64_t rnd = 0; rnd < nround; ++rnd) {
+    const int64_t q = rnd * stride + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool live = q < a.n;
+    const int64_t i = live ? q : 0;
+    T t[kMaxModes];
+#pragma unroll
+    for (int k = 0; k < kMaxModes; ++k) t[k] = ((T)a.c[k][i] - a.map.lo[k]) * a.map.scale[k] - T(1);
+    T phi1[NP], phi2[NP];
+    {
+      T pm1 = T(1), pm = t[0] * a.rec.a[0], rm1 = T(1), rm = t[1] * a.rec.a[0];
+      phi1[0] = T(1);
+      phi2[0] = T(1);
+#pragma unroll
+      for (int m = 1; m < NP; ++m) {
+        phi1[m] = pm;
+        phi2[m] = rm;
+        const T pn = a.rec.a[m] * t[0] * pm - a.rec.b[m] * pm1;
+        pm1 = pm;
+        pm = pn;
+        const T rn = a.rec.a[m] * t[1] * rm - a.rec.b[m] * rm1;
+        rm1 = rm;
+        rm = rn;
+      }
+    }
+    T u3[RP], u4[RP];
+#pragma unroll
+    for (int j = 0; j < RP; ++j) {
+      u3[j] = C3[j];
+      u4[j] = C4[j];
+    }
+    {
+      T pm1 = T(1), pm = t[2] * a.rec.a[0], rm1 = T(1), rm = t[3] * a.rec.a[0];
+#pragma unroll
+      for (int m = 1; m < NP; ++m) {
+#pragma unroll
+        for (int j = 0; j < RP; ++j) {
+          u3[j] += C3[m * kMaxRank + j] * pm;
+          u4[j] += C4[m * kMaxRank + j] * rm;
+        }
+        const T pn = a.rec.a[m] * t[2] * pm - a.rec.b[m] * pm1;
+        pm1 = pm;
+        pm = pn;
+        const T rn = a.rec.a[m] * t[3] * rm - a.rec.b[m] * rm1;
+        rm1 = rm;
+        rm = rn;
+      }
+    }
+    T acc = T(0);
+    for (int c = 0; c < nchunk; ++c) {
+      if (nchunk > 1) {
+        __syncthreads();
+        load_chunk(c);
+        __syncthreads();
+      }
+      const int p0 = c * a.pair_chunk;
+      const int rows = min(a.pair_chunk, npairs - p0);
+      int j1_prev = -1;
+      T u1 = T(0);
+      for (int pp = 0; pp < rows; ++pp) {
+        const int p = p0 + pp, j1 = p / r2, j2 = p - j1 * r2;
+        if (j1 != j1_prev) {   // uniform across the workgroup
+          u1 = T(0);
+#pragma unroll
+          for (int m = 0; m < NP; ++m) u1 += C1[m * kMaxRank + j1] * phi1[m];
+          j1_prev = j1;
+        }
+        T u2 = T(0);
+#pragma unroll
+        for (int m = 0; m < NP; ++m) u2 += C2[m * kMaxRank + j2] * phi2[m];
+        const T* ap = &sA[pp * RP * RP];
+        T s = T(0);
+#pragma unroll
+        for (int j3 = 0; j3 < RP; ++j3) {
+          T w = T(0);
+#pragma unroll
+          for (int j4 = 0; j4 < RP; ++j4) w += ap[j3 * RP + j4] * u4[j4];
+          s += w * u3[j3];
+        }
+        acc += (u1 * u2) * s;
+      }
+    }
+    if (live) a.out[q] = (TIn)acc;
+  }
+}
+
+template <typename TIn, typename T, int NP, int RP>
+static void eval4_launch(Eval4Args<TIn, T>& a, void* stream) {
+  const size_t per_pair = sizeof(T) * RP * RP;
+  const int npairs = a.r[0] * a.r[1];
+  a.pair_chunk = (int)std::min<size_t>((size_t)npairs, std::max<size_t>(1, EVAL4_LDS_BUDGET / per_pair));
+  const size_t lds = per_pair * (size_t)a.pair_chunk;
+  const int64_t blocks = std::min<int64_t>((a.n + 255) / 256, (int64_t)device_cu_count() * 8);
+  if (blocks < 1) return;
+  hipLaunchKernelGGL((k_eval4<TIn, T, NP, RP>), dim3((unsigned)blocks), dim3(256), lds, S(stream), a);
+  check_launch("k_eval4");
+}
+
+template <typename TIn, typename T>
+static void eval4_t(const fst_model* m, const DeviceModel& dm, int64_t n, const void* const* coords, void* out,
+                    void* stream) {
+  Eval4Args<TIn, T> a;
+  for (int k = 0; k < kMaxModes; ++k) {
+    a.c[k] = (const TIn*)coords[k];
+    a.r[k] = m->rank[k];
+  }
+  a.coefs = (const T*)dm.coefs;
+  a.core = (const T*)dm.core;
+  a.out = (TIn*)out;
+  a.n = n;
+  a.map = make_map<T>(m);
+  a.rec = make_recurrence<T>();
+  const int rp = (std::max(m->rank[2], m->rank[3]) + 3) / 4 * 4;
+  const bool np16 = m->degree[0] < 16 && m->degree[1] < 16 && m->degree[2] < 16 && m->degree[3] < 16;
+#define FST_EVAL4_RP(NPV)                                       \
+  switch (rp) {                                                 \
+    case 4: eval4_launch<TIn, T, NPV, 4>(a, stream); break;     \
+    case 8: eval4_launch<TIn, T, NPV, 8>(a, stream); break;     \
+    case 12: eval4_launch<TIn, T, NPV, 12>(a, stream); break;   \
+    case 16: eval4_launch<TIn, T, NPV, 16>(a, stream); break;   \
+    case 20: eval4_launch<TIn, T, NPV, 20>(a, stream); break;   \
+    case 24: eval4_launch<TIn, T, NPV, 24>(a, stream); break;   \
+    case 28: eval4_launch<TIn, T, NPV, 28>(a, stream); break;   \
+    default: eval4_launch<TIn, T, NPV, 32>(a, stream); break;   \
+  }
+  if (np16) {
+    FST_EVAL4_RP(16)
+  } else {
+    FST_EVAL4_RP(32)
+  }
+#undef FST_EVAL4_RP
+}
+
+void launch_eval_d(const fst_model* m, const DeviceModel& dm, int dtype, int64_t n, const void* const* coords,
+                   void* out, void* stream) {
+  if (m->d == 3) {
+    launch_eval(m, dm, dtype, n, coords[0], coords[1], coords[2], nullptr, nullptr, out, stream);
+    return;
+  }
+  if (dtype == FST_F64)
+    eval4_t<double, double>(m, dm, n, coords, out, stream);
+  else
+    eval4_t<float, float>(m, dm, n, coords, out, stream);
+}
+
+}  // namespace fst

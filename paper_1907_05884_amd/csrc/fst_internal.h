@@ -17,6 +17,7 @@ namespace fst {
 
 constexpr int kMaxRank = 32;     // r_k limit of this version
 constexpr int kMaxBasis = 32;    // n_k = p_k + 1 limit of this version
+constexpr int kMaxModes = 4;     // d = 3 (the 3-way calls) or 4 (the d-way calls)
 
 // Error carried from deep inside the library to the C ABI boundary, where it becomes a
 // status code plus a thread-local message.
@@ -28,9 +29,9 @@ struct Error : std::runtime_error {
 void set_last_error(const std::string& msg);
 
 // Device copy of a model for one (device, dtype): coefficient matrices padded to
-// kMaxBasis x kMaxRank per mode, and the core in C order.
+// kMaxBasis x kMaxRank per mode (kMaxModes slots, unused modes zero), and the core in C order.
 struct DeviceModel {
-  void* coefs = nullptr;   // 3 * kMaxBasis * kMaxRank elements of the dtype
+  void* coefs = nullptr;   // kMaxModes * kMaxBasis * kMaxRank elements of the dtype
   void* core = nullptr;    // R elements of the dtype
   void* core64 = nullptr;  // R doubles (for refinement), only for dtype FP64 copy
 };
@@ -50,17 +51,26 @@ struct SolveInfo {
 }  // namespace fst
 
 struct fst_model {
-  double lo[3], hi[3];
-  int32_t rank[3], degree[3];
-  std::vector<double> core;      // r1 r2 r3, C order
-  std::vector<double> coef[3];   // (p_k + 1) x r_k row-major
+  int32_t d = 3;                  // modes; entries k >= d of the arrays below are unused
+  double lo[4] = {0, 0, 0, 0}, hi[4] = {1, 1, 1, 1};
+  int32_t rank[4] = {1, 1, 1, 1}, degree[4] = {0, 0, 0, 0};
+  std::vector<double> core;      // r1 .. rd, C order
+  std::vector<double> coef[4];   // (p_k + 1) x r_k row-major
   fst::SolveInfo fit;             // how the core was solved (models from a refit)
   // lazily uploaded device copies, keyed by (device ordinal, dtype)
   mutable std::mutex mu;
   mutable std::map<std::pair<int, int>, fst::DeviceModel> dev;
   ~fst_model();
-  int64_t R() const { return (int64_t)rank[0] * rank[1] * rank[2]; }
-  int sum_r() const { return rank[0] + rank[1] + rank[2]; }
+  int64_t R() const {
+    int64_t r = 1;
+    for (int k = 0; k < d; ++k) r *= rank[k];
+    return r;
+  }
+  int sum_r() const {
+    int s = 0;
+    for (int k = 0; k < d; ++k) s += rank[k];
+    return s;
+  }
 };
 
 namespace fst {
@@ -85,7 +95,10 @@ int hardware_threads(int requested);
 // ---------------------------------------------------------------- model (fst_model.cpp)
 fst_model* model_new(const double lo[3], const double hi[3], const int32_t rank[3],
                      const int32_t degree[3]);
-void check_model(const fst_model* m);
+fst_model* model_new_d(int d, const double* lo, const double* hi, const int32_t* rank, const int32_t* degree);
+fst_model* copy_with_core(const fst_model* m, const std::vector<double>& core);
+void check_model(const fst_model* m);    // any d
+void check_model3(const fst_model* m);   // the 3-way calls: d = 3 only
 const DeviceModel& device_model(const fst_model* m, int dtype);   // uploads on first use
 
 // ---------------------------------------------------------------- GPU launchers (fst_kernels.hip)
@@ -94,6 +107,9 @@ void check_hip(int err, const char* what);
 void launch_factor_eval(const fst_model* m, const DeviceModel& dm, int dtype, int64_t n,
                         const void* x, const void* y, const void* z, const void* v,
                         const int32_t* idx, int64_t mrows, void* U, void* vs, void* stream);
+// the same for a model of any d: coords holds m->d coordinate arrays
+void launch_factor_eval_d(const fst_model* m, const DeviceModel& dm, int dtype, const void* const* coords,
+                          const void* v, const int32_t* idx, int64_t mrows, void* U, void* vs, void* stream);
 size_t gram_workspace_bytes(const fst_model* m, int64_t mrows);
 void launch_gram(const fst_model* m, int dtype, int64_t mrows, const void* U, const void* vs,
                  int gram_prec, double* G, double* h, void* ws, size_t ws_bytes, void* stream);
@@ -129,6 +145,22 @@ size_t mixed_workspace_bytes(const fst_model* m, int dtype, int64_t n, int64_t n
 void mixed_normal_equations(const fst_model* m, int dtype, int64_t n, const void* x, const void* y, const void* z,
                             const void* v, int64_t nsamp, uint64_t seed, void* ws, size_t ws_bytes, double* G,
                             double* h, void* stream);
+// G = A^T A (lower triangle, FP64) and h = A^T b from materialised rows: At is R x Sp (row j of
+// A^T contiguous), b is Sp long, Sp a multiple of GD_SP_MULTIPLE with rows past the data zero;
+// in the point dtype (FP32: FP32 MFMA folded into FP64; FP64: FP64 MFMA).  accumulate adds to
+// G and h instead of overwriting them.
+constexpr int64_t GD_SP_MULTIPLE = 64;
+void dense_normal_equations(int dtype, const void* At, const void* b, int64_t R, int64_t Sp, double* G, double* h,
+                            bool accumulate, void* stream);
+// d-way form (fst_dway.hip): normal equations of M sampled rows (idx) of a d = 3 or 4 model
+// from materialised row chunks, and the reconstruction for any d (d = 3: launch_eval)
+size_t dway_workspace_bytes(const fst_model* m, int dtype, int64_t M);
+void dway_normal_equations(const fst_model* m, int dtype, const void* const* coords, const void* v,
+                           const int32_t* idx, int64_t M, void* ws, size_t ws_bytes, double* G, double* h,
+                           void* stream);
+void launch_eval_d(const fst_model* m, const DeviceModel& dm, int dtype, int64_t n, const void* const* coords,
+                   void* out, void* stream);
+int device_cu_count();
 size_t eval_grid_workspace_bytes(const fst_model* m, int dtype, int64_t n1, int64_t n2, int64_t n3);
 void eval_grid(const fst_model* m, const DeviceModel& dm, int dtype, const void* gx, int64_t n1, const void* gy,
                int64_t n2, const void* gz, int64_t n3, void* out, void* ws, void* stream);

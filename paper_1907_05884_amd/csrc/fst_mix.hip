@@ -187,14 +187,18 @@ __global__ void k_zero_tail(T* At, T* b, int64_t R, int64_t S, int64_t Sp) {
 // MFMA blocks), KC points of the tile's 128 row-block and 128 column-block rows of A^T staged
 // through double-buffered LDS with 16-byte loads (rows of A^T are Sp long, Sp a multiple of
 // KC, so every chunk is whole).  As in the Khatri-Rao Gram, lane group g takes the points
-// g KC/4 + s, and FP32 accumulation is folded into FP64 registers every chunk.
+// g KC/4 + s, and FP32 accumulation is folded into FP64 registers every chunk.  With
+// accumulate != 0 the tile is added to the G already there (row chunks of a larger A).
 template <typename T> struct DenseKC;
 template <> struct DenseKC<float> { static constexpr int KC = 64; };
 template <> struct DenseKC<double> { static constexpr int KC = 32; };
 constexpr int GD_TILE = 128, GD_THREADS = 1024;
+static_assert(GD_SP_MULTIPLE % DenseKC<float>::KC == 0 && GD_SP_MULTIPLE % DenseKC<double>::KC == 0,
+              "padded row counts must hold whole chunks");
 
 template <typename T>
-__global__ __launch_bounds__(GD_THREADS) void k_gram_dense(const T* At, int64_t R, int64_t Sp, double* G) {
+__global__ __launch_bounds__(GD_THREADS) void k_gram_dense(const T* At, int64_t R, int64_t Sp, double* G,
+                                                          int accumulate) {
   constexpr int KC = DenseKC<T>::KC, KCP = KC + 16 / (int)sizeof(T), VW = 16 / (int)sizeof(T);
   constexpr int PIECES = 2 * GD_TILE * KC / VW / GD_THREADS;   // 16-byte pieces per thread per chunk
   typedef T T4 __attribute__((ext_vector_type(4)));
@@ -290,13 +294,15 @@ __global__ __launch_bounds__(GD_THREADS) void k_gram_dense(const T* At, int64_t 
         const int64_t row = r0 + row0 + x * 16 + MfmaAcc<T>::row(g, v);
         const int64_t col = c0 + col0 + y * 16 + li;
         const double val = kFold ? dacc[kFold ? x : 0][kFold ? y : 0][v] : (double)acc[x][y][v];
-        if (row < R && col <= row) G[row * R + col] = val;
+        if (row < R && col <= row) G[row * R + col] = accumulate ? G[row * R + col] + val : val;
       }
 }
 
-// h[j] = sum_q A^T[j][q] b[q] in FP64, one wave per row, lanes striding over q in a fixed order
+// h[j] = sum_q A^T[j][q] b[q] in FP64 (added to h[j] with accumulate != 0), one wave per row,
+// lanes striding over q in a fixed order
 template <typename T>
-__global__ __launch_bounds__(256) void k_atv_dense(const T* At, const T* b, int64_t R, int64_t Sp, double* h) {
+__global__ __launch_bounds__(256) void k_atv_dense(const T* At, const T* b, int64_t R, int64_t Sp, double* h,
+                                                   int accumulate) {
   const int lane = threadIdx.x & 63;
   const int64_t j = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (j >= R) return;
@@ -305,7 +311,28 @@ __global__ __launch_bounds__(256) void k_atv_dense(const T* At, const T* b, int6
   for (int64_t q = lane; q < Sp; q += 64) s += (double)row[q] * (double)b[q];
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
-  if (lane == 0) h[j] = s;
+  if (lane == 0) h[j] = accumulate ? h[j] + s : s;
+}
+
+void dense_normal_equations(int dtype, const void* At, const void* b, int64_t R, int64_t Sp, double* G, double* h,
+                            bool accumulate, void* stream) {
+  if (Sp % GD_SP_MULTIPLE != 0) fail(FST_E_INVAL, "dense Gram: row count not padded");
+  const int64_t nt = (R + GD_TILE - 1) / GD_TILE;
+  const dim3 gg((unsigned)(nt * (nt + 1) / 2)), ga((unsigned)((R + 3) / 4));
+  if (dtype == FST_F64) {
+    hipLaunchKernelGGL(k_gram_dense<double>, gg, dim3(GD_THREADS), 0, S(stream), (const double*)At, R, Sp, G,
+                       accumulate ? 1 : 0);
+    check_launch("k_gram_dense");
+    hipLaunchKernelGGL(k_atv_dense<double>, ga, dim3(256), 0, S(stream), (const double*)At, (const double*)b, R, Sp,
+                       h, accumulate ? 1 : 0);
+  } else {
+    hipLaunchKernelGGL(k_gram_dense<float>, gg, dim3(GD_THREADS), 0, S(stream), (const float*)At, R, Sp, G,
+                       accumulate ? 1 : 0);
+    check_launch("k_gram_dense");
+    hipLaunchKernelGGL(k_atv_dense<float>, ga, dim3(256), 0, S(stream), (const float*)At, (const float*)b, R, Sp, h,
+                       accumulate ? 1 : 0);
+  }
+  check_launch("k_atv_dense");
 }
 
 // ------------------------------------------------------------------------------ host side
@@ -443,13 +470,7 @@ static void mixed_normal_equations_t(const fst_model* m, const DeviceModel& dm, 
     check_launch("k_zero_tail");
   }
   // step 5: normal equations of the sampled mixed rows
-  const int64_t nt = (R + GD_TILE - 1) / GD_TILE;
-  hipLaunchKernelGGL(k_gram_dense<T>, dim3((unsigned)(nt * (nt + 1) / 2)), dim3(GD_THREADS), 0, S(stream),
-                     (const T*)At, R, L.Sp, G);
-  check_launch("k_gram_dense");
-  hipLaunchKernelGGL(k_atv_dense<T>, dim3((unsigned)((R + 3) / 4)), dim3(256), 0, S(stream), (const T*)At,
-                     (const T*)b, R, L.Sp, h);
-  check_launch("k_atv_dense");
+  dense_normal_equations(dtype, At, b, R, L.Sp, G, h, false, stream);
 }
 
 void mixed_normal_equations(const fst_model* m, int dtype, int64_t n, const void* x, const void* y, const void* z,

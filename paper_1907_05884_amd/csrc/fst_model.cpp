@@ -17,7 +17,12 @@ namespace fst {
 
 fst_model* model_new(const double lo[3], const double hi[3], const int32_t rank[3],
                      const int32_t degree[3]) {
-  for (int k = 0; k < 3; ++k) {
+  return model_new_d(3, lo, hi, rank, degree);
+}
+
+fst_model* model_new_d(int d, const double* lo, const double* hi, const int32_t* rank, const int32_t* degree) {
+  if (d != 3 && d != 4) fail(FST_E_UNSUPPORTED, "model: only d = 3 and d = 4 are supported");
+  for (int k = 0; k < d; ++k) {
     if (!(std::isfinite(lo[k]) && std::isfinite(hi[k]) && hi[k] > lo[k]))
       fail(FST_E_INVAL, "model: need finite lo < hi in every mode");
     if (rank[k] < 1) fail(FST_E_INVAL, "model: ranks must be >= 1");
@@ -26,7 +31,8 @@ fst_model* model_new(const double lo[3], const double hi[3], const int32_t rank[
     if (degree[k] + 1 > kMaxBasis) fail(FST_E_UNSUPPORTED, "model: degree above 31 is not supported");
   }
   fst_model* m = new fst_model();
-  for (int k = 0; k < 3; ++k) {
+  m->d = d;
+  for (int k = 0; k < d; ++k) {
     m->lo[k] = lo[k];
     m->hi[k] = hi[k];
     m->rank[k] = rank[k];
@@ -41,10 +47,22 @@ void check_model(const fst_model* m) {
   if (!m) fail(FST_E_INVAL, "null model");
 }
 
+void check_model3(const fst_model* m) {
+  check_model(m);
+  if (m->d != 3) fail(FST_E_INVAL, "this call takes a 3-way model; 4-way models go through the d-way calls");
+}
+
+fst_model* copy_with_core(const fst_model* m, const std::vector<double>& core) {
+  fst_model* out = model_new_d(m->d, m->lo, m->hi, m->rank, m->degree);
+  for (int k = 0; k < m->d; ++k) out->coef[k] = m->coef[k];
+  out->core = core;
+  return out;
+}
+
 template <class T>
 static void pack_model(const fst_model* m, std::vector<T>& coefs, std::vector<T>& core) {
-  coefs.assign((size_t)3 * kMaxBasis * kMaxRank, T(0));
-  for (int k = 0; k < 3; ++k) {
+  coefs.assign((size_t)kMaxModes * kMaxBasis * kMaxRank, T(0));
+  for (int k = 0; k < m->d; ++k) {
     const int n = m->degree[k] + 1, r = m->rank[k];
     for (int i = 0; i < n; ++i)
       for (int j = 0; j < r; ++j)
@@ -84,7 +102,7 @@ const DeviceModel& device_model(const fst_model* m, int dtype) {
 
 // ------------------------------------------------------------------------------ serialisation
 // Layout (little endian):
-//   "FSTM" | u32 version=1 | u32 d=3 | f64 lo[3] | f64 hi[3] | i32 rank[3] | i32 degree[3]
+//   "FSTM" | u32 version=1 | u32 d (3 or 4) | f64 lo[d] | f64 hi[d] | i32 rank[d] | i32 degree[d]
 //   | f64 core[R] | per mode: i32 nnz, i32 colptr[r+1], u8 row[nnz], f64 val[nnz]
 //   | u64 FNV-1a checksum of all preceding bytes
 namespace {
@@ -118,13 +136,13 @@ std::vector<unsigned char> serialise(const fst_model* m) {
   Writer w;
   w.b.insert(w.b.end(), {'F', 'S', 'T', 'M'});
   w.put<uint32_t>(1);
-  w.put<uint32_t>(3);
-  for (int k = 0; k < 3; ++k) w.put<double>(m->lo[k]);
-  for (int k = 0; k < 3; ++k) w.put<double>(m->hi[k]);
-  for (int k = 0; k < 3; ++k) w.put<int32_t>(m->rank[k]);
-  for (int k = 0; k < 3; ++k) w.put<int32_t>(m->degree[k]);
+  w.put<uint32_t>((uint32_t)m->d);
+  for (int k = 0; k < m->d; ++k) w.put<double>(m->lo[k]);
+  for (int k = 0; k < m->d; ++k) w.put<double>(m->hi[k]);
+  for (int k = 0; k < m->d; ++k) w.put<int32_t>(m->rank[k]);
+  for (int k = 0; k < m->d; ++k) w.put<int32_t>(m->degree[k]);
   for (double c : m->core) w.put<double>(c);
-  for (int k = 0; k < 3; ++k) {
+  for (int k = 0; k < m->d; ++k) {
     const int n = m->degree[k] + 1, r = m->rank[k];
     std::vector<int32_t> colptr(1, 0);
     std::vector<uint8_t> rows;
@@ -185,19 +203,20 @@ fst_status fst_model_load(const void* buf, size_t nbytes, fst_model** out) {
     uint32_t version = r.get<uint32_t>();
     uint32_t d = r.get<uint32_t>();
     if (version != 1) fst::fail(FST_E_FORMAT, "unknown model version");
-    if (d != 3) fst::fail(FST_E_UNSUPPORTED, "only d = 3 models are supported");
-    double lo[3], hi[3];
-    int32_t rank[3], degree[3];
-    for (int k = 0; k < 3; ++k) lo[k] = r.get<double>();
-    for (int k = 0; k < 3; ++k) hi[k] = r.get<double>();
-    for (int k = 0; k < 3; ++k) rank[k] = r.get<int32_t>();
-    for (int k = 0; k < 3; ++k) degree[k] = r.get<int32_t>();
-    for (int k = 0; k < 3; ++k)
+    if (d != 3 && d != 4) fst::fail(FST_E_UNSUPPORTED, "only d = 3 and d = 4 models are supported");
+    double lo[4], hi[4];
+    int32_t rank[4], degree[4];
+    for (uint32_t k = 0; k < d; ++k) lo[k] = r.get<double>();
+    for (uint32_t k = 0; k < d; ++k) hi[k] = r.get<double>();
+    for (uint32_t k = 0; k < d; ++k) rank[k] = r.get<int32_t>();
+    for (uint32_t k = 0; k < d; ++k) degree[k] = r.get<int32_t>();
+    for (uint32_t k = 0; k < d; ++k)
       if (rank[k] < 1 || rank[k] > fst::kMaxRank || degree[k] < 0 || degree[k] + 1 > fst::kMaxBasis)
         fst::fail(FST_E_FORMAT, "model header out of range");
-    m = fst::model_new(lo, hi, rank, degree);
+    m = fst::model_new_d((int)d, lo, hi, rank, degree);
+    if (r.n - r.off < sizeof(double) * m->core.size()) fst::fail(FST_E_FORMAT, "model buffer is truncated");
     for (auto& c : m->core) c = r.get<double>();
-    for (int k = 0; k < 3; ++k) {
+    for (uint32_t k = 0; k < d; ++k) {
       const int n = degree[k] + 1, rk = rank[k];
       int32_t nnz = r.get<int32_t>();
       if (nnz < 0 || nnz > n * rk) fst::fail(FST_E_FORMAT, "bad coefficient count");

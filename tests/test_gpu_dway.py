@@ -1,0 +1,169 @@
+"""GPU parity of the d-way calls (fst_eval_d, fst_refit_core_d) through the C ABI for 4-way
+models (Sec. 2 format with d = 4; the space-time data of Sec. 6) against the oracle
+(``oracle.reconstruct.evaluate``, ``oracle.lsq.refit_core``, pinned on the CPU), and for 3-way
+models against the 3-way calls.
+
+Tolerances (relative L2): FP64 1e-10.  FP32 1e-5 for reconstruction; for the refit, 1e-5 on
+designs with orthonormal factor functions (kappa(G) of order 1-10, so FP32 rows and FP32 MFMA
+with FP64 accumulation stay near 1e-6).
+"""
+import numpy as np
+import pytest
+
+from datagen import random_model_parts
+from oracle.lsq import refit_core
+from oracle.model import Model as OModel
+from oracle.reconstruct import evaluate, rel_l2
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+fst = pytest.importorskip("paper_1907_05884_amd.binding")
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def D(a, dev):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+
+def _models(seed, rank, degree, lo=None, hi=None, orthonormal=False):
+    d = len(rank)
+    lo = lo or (-1.0,) * d
+    hi = hi or (1.0,) * d
+    if orthonormal:
+        rng = np.random.default_rng(seed)
+        core = rng.standard_normal(tuple(rank))
+        coefs = [np.linalg.qr(rng.standard_normal((degree[k] + 1, rank[k])))[0] for k in range(d)]
+    else:
+        core, coefs = random_model_parts(seed, rank, degree)
+    return (OModel(tuple(lo), tuple(hi), tuple(rank), tuple(degree), core, coefs),
+            fst.fst_model_from_parts(lo, hi, rank, degree, core, coefs))
+
+
+def _points(seed, n, lo, hi, dtype):
+    rng = np.random.default_rng(seed)
+    lo, hi = np.asarray(lo, float), np.asarray(hi, float)
+    return (lo + (hi - lo) * rng.random((n, len(lo)))).astype(dtype)
+
+
+# (ranks, degrees, n): ragged ranks and sizes; rank 1; degree 0 in a mode; rank-slice widths
+# 4 .. 32 (the last two modes set the LDS slice); more (j1, j2) pairs than one 64 KB LDS slice
+# holds (8 x 4 pairs of 32 x 30 FP64 entries: four slices)
+EVAL_CASES = [
+    ((3, 2, 4, 2), (5, 3, 6, 4), 3001),
+    ((1, 1, 1, 1), (0, 2, 0, 3), 257),
+    ((5, 6, 7, 9), (11, 17, 9, 20), 1000),
+    ((2, 3, 13, 11), (20, 20, 31, 31), 777),
+    ((8, 4, 32, 30), (31, 7, 31, 31), 600),
+]
+
+
+@pytest.mark.parametrize("rank,degree,n", EVAL_CASES)
+def test_eval_d_four_way_fp64_matches_oracle(dev, rank, degree, n):
+    print(f"eval4 fp64 rank={rank} degree={degree} n={n}", flush=True)
+    lo, hi = (0.0, -2.0, 1.0, 0.0), (4.0, 1.0, 3.0, 10.0)
+    om, gm = _models(sum(rank), rank, degree, lo, hi)
+    pts = _points(n, n, lo, hi, np.float64)
+    out = fst.fst_eval_d(gm, [D(pts[:, k], dev) for k in range(4)])
+    assert rel_l2(out.cpu().numpy(), evaluate(om, pts)) <= 1e-10
+
+
+@pytest.mark.parametrize("rank,degree,n", EVAL_CASES[:4])
+def test_eval_d_four_way_fp32_matches_oracle(dev, rank, degree, n):
+    print(f"eval4 fp32 rank={rank} degree={degree} n={n}", flush=True)
+    lo, hi = (-1.0,) * 4, (1.0,) * 4
+    om, gm = _models(7 + sum(rank), rank, degree, orthonormal=True)
+    pts = _points(n + 1, n, lo, hi, np.float32)
+    out = fst.fst_eval_d(gm, [D(pts[:, k], dev) for k in range(4)])
+    assert rel_l2(out.cpu().numpy(), evaluate(om, pts.astype(np.float64))) <= 1e-5
+
+
+def test_eval_d_many_rounds_and_empty(dev):
+    # more points than one pass of the grid (2048 workgroups x 256 threads), and n = 0
+    rank, degree = (2, 3, 2, 3), (4, 4, 4, 4)
+    om, gm = _models(3, rank, degree, orthonormal=True)
+    n = 600_001
+    pts = _points(5, n, (-1.0,) * 4, (1.0,) * 4, np.float32)
+    out = fst.fst_eval_d(gm, [D(pts[:, k], dev) for k in range(4)])
+    assert rel_l2(out.cpu().numpy(), evaluate(om, pts.astype(np.float64))) <= 1e-5
+    empty = [torch.empty(0, dtype=torch.float32, device=dev) for _ in range(4)]
+    assert fst.fst_eval_d(gm, empty).numel() == 0
+
+
+def test_eval_d_three_way_is_fst_eval(dev):
+    om, gm = _models(4, (5, 4, 6), (9, 8, 7))
+    pts = _points(6, 2000, (-1.0,) * 3, (1.0,) * 3, np.float64)
+    c = [D(pts[:, k], dev) for k in range(3)]
+    a = fst.fst_eval_d(gm, c)
+    b = fst.fst_eval(gm, *c)
+    assert torch.equal(a, b)
+
+
+# refit: multi-chunk (M > 16384 rows, ragged last chunk) and single-chunk cases
+@pytest.mark.parametrize("rank,degree,n,M", [
+    ((3, 2, 4, 2), (5, 3, 6, 4), 60_000, 40_001),
+    ((4, 3, 5, 6), (7, 7, 7, 7), 5_000, 1_500),
+    ((2, 2, 9, 17), (9, 9, 12, 20), 20_000, 4_000),
+])
+def test_refit_d_four_way_fp64_matches_oracle(dev, rank, degree, n, M):
+    print(f"refit4 fp64 rank={rank} n={n} M={M}", flush=True)
+    lo, hi = (0.0, -1.0, 2.0, 0.0), (4.0, 1.0, 3.0, 1.0)
+    om, gm = _models(11, rank, degree, lo, hi, orthonormal=True)
+    pts = _points(12, n, lo, hi, np.float64)
+    vals = evaluate(om, pts) + 0.1 * np.random.default_rng(13).standard_normal(n)
+    alpha_o, _, _, _ = refit_core(om, pts, vals, M, seed=17)
+    out = fst.fst_refit_core_d(gm, [D(pts[:, k], dev) for k in range(4)], D(vals, dev), M, 17)
+    assert out.info()["d"] == 4 and out.core.shape == tuple(rank)
+    assert rel_l2(out.core, alpha_o) <= 1e-10
+    assert out.solve_info()["gram_prec"] == fst.FST_GRAM_F64
+
+
+def test_refit_d_four_way_fp32_matches_oracle(dev):
+    rank, degree, n, M = (4, 5, 3, 6), (9, 8, 7, 10), 50_000, 20_000
+    print(f"refit4 fp32 rank={rank} n={n} M={M}", flush=True)
+    om, gm = _models(21, rank, degree, orthonormal=True)
+    pts = _points(22, n, (-1.0,) * 4, (1.0,) * 4, np.float32)
+    vals = (evaluate(om, pts.astype(np.float64)) + 0.1 * np.random.default_rng(23).standard_normal(n)).astype(
+        np.float32)
+    alpha_o, _, _, _ = refit_core(om, pts.astype(np.float64), vals.astype(np.float64), M, seed=29)
+    out = fst.fst_refit_core_d(gm, [D(pts[:, k], dev) for k in range(4)], D(vals, dev), M, 29)
+    assert rel_l2(out.core, alpha_o) <= 1e-5
+    assert out.solve_info()["gram_prec"] == fst.FST_GRAM_F32
+
+
+def test_refit_d_three_way_matches_the_khatri_rao_refit(dev):
+    rank, degree, n, M = (5, 4, 6), (8, 8, 8), 30_000, 20_000
+    om, gm = _models(31, rank, degree, orthonormal=True)
+    pts = _points(32, n, (-1.0,) * 3, (1.0,) * 3, np.float64)
+    vals = evaluate(om, pts) + 0.05 * np.random.default_rng(33).standard_normal(n)
+    c = [D(pts[:, k], dev) for k in range(3)]
+    v = D(vals, dev)
+    dense = fst.fst_refit_core_d(gm, c, v, M, 5)
+    kr = fst.fst_refit_core(gm, *c, v, M, 5, gram_prec=fst.FST_GRAM_F64)
+    assert rel_l2(dense.core, kr.core) <= 1e-10
+    alpha_o, _, _, _ = refit_core(om, pts, vals, M, seed=5)
+    assert rel_l2(dense.core, alpha_o) <= 1e-10
+
+
+def test_refit_d_rejects_bad_arguments(dev):
+    om, gm = _models(2, (2, 2, 2, 2), (3, 3, 3, 3))
+    pts = _points(3, 500, (-1.0,) * 4, (1.0,) * 4, np.float64)
+    c = [D(pts[:, k], dev) for k in range(4)]
+    v = D(pts[:, 0], dev)
+    for M in (16, 501):   # M <= R, M > n
+        with pytest.raises(fst.FstError) as e:
+            fst.fst_refit_core_d(gm, c, v, M, 1)
+        assert e.value.status == fst.FST_E_INVAL
+    _, g2 = _models(2, (5, 2, 2, 2), (3, 3, 3, 3))   # r_1 > p_1 + 1
+    with pytest.raises(fst.FstError) as e:
+        fst.fst_refit_core_d(g2, c, v, 100, 1)
+    assert e.value.status == fst.FST_E_INVAL
+    # 3-way calls refuse a 4-way model
+    with pytest.raises(fst.FstError) as e:
+        fst.fst_eval(gm, c[0], c[1], c[2])
+    assert e.value.status == fst.FST_E_INVAL

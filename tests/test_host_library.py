@@ -233,3 +233,79 @@ def test_invalid_arguments_are_rejected():
     p.struct_size = 8
     with pytest.raises(fst.FstError):
         fst.fst_fit_workspace_bytes(p, 100)
+
+
+def _model4(seed=1, rank=(3, 2, 4, 2), degree=(5, 3, 6, 4)):
+    core, coefs = datagen.random_model_parts(seed, rank, degree)
+    lo, hi = (0.0, -1.0, 2.0, 0.0), (4.0, 1.0, 3.0, 10.0)
+    return OModel(lo, hi, rank, degree, core, coefs), fst.fst_model_from_parts(lo, hi, rank, degree, core, coefs)
+
+
+def test_four_way_model_parts_info_and_serialisation():
+    om, m = _model4()
+    inf = m.info()
+    assert inf["d"] == 4 and inf["rank"] == om.rank and inf["degree"] == om.degree
+    assert inf["lo"] == om.lo and inf["hi"] == om.hi
+    assert inf["nnz"] == om.nnz() and m.R == om.R
+    np.testing.assert_array_equal(m.core, om.core)
+    for k in range(4):
+        np.testing.assert_array_equal(m.coefs(k), om.coefs[k])
+    assert m.paper_bytes() == om.paper_bytes()
+    blob = fst.fst_model_save(m)
+    m2 = fst.fst_model_load(blob)
+    assert m2.info() == inf
+    np.testing.assert_array_equal(m2.core, om.core)
+    for k in range(4):
+        np.testing.assert_array_equal(m2.coefs(k), om.coefs[k])
+    assert fst.fst_model_save(m2) == blob
+    # a 3-way model built through the d-way constructor is the 3-way model
+    core3, coefs3 = datagen.random_model_parts(2, (3, 4, 2), (5, 4, 6))
+    lo3, hi3 = (-1.0,) * 3, (1.0,) * 3
+    a = fst.fst_model_from_parts(lo3, hi3, (3, 4, 2), (5, 4, 6), core3, coefs3)
+    cs = [np.ascontiguousarray(c) for c in coefs3]
+    arr = (ctypes.c_void_p * 3)(*[c.ctypes.data_as(ctypes.c_void_p) for c in cs])
+    h = ctypes.c_void_p()
+    c3 = np.ascontiguousarray(core3)
+    st = fst._fn["fst_model_from_parts_d"](3, np.asarray(lo3).ctypes.data_as(ctypes.c_void_p),
+                                           np.asarray(hi3).ctypes.data_as(ctypes.c_void_p),
+                                           np.asarray((3, 4, 2), np.int32).ctypes.data_as(ctypes.c_void_p),
+                                           np.asarray((5, 4, 6), np.int32).ctypes.data_as(ctypes.c_void_p),
+                                           c3.ctypes.data_as(ctypes.c_void_p), arr, ctypes.byref(h))
+    assert st == fst.FST_OK
+    b = fst.Model(h)
+    assert fst.fst_model_save(a) == fst.fst_model_save(b)
+    assert b.info()["d"] == 3
+
+
+def test_three_way_calls_reject_four_way_models():
+    om, m = _model4()
+    st = fst._fn["fst_eval"](m.handle, fst.FST_F64, 10, None, None, None, None, None)
+    assert st == fst.FST_E_INVAL and "3-way" in fst.fst_last_error()
+    lo, hi = (ctypes.c_double * 3)(), (ctypes.c_double * 3)()
+    rk, dg = (ctypes.c_int32 * 3)(), (ctypes.c_int32 * 3)()
+    assert fst._fn["fst_model_info"](m.handle, lo, hi, rk, dg, None) == fst.FST_E_INVAL
+    assert fst._fn["fst_refit_workspace_bytes"](m.handle, fst.FST_F32, 1000, 0) == 0
+    assert fst._fn["fst_eval_grid_workspace_bytes"](m.handle, fst.FST_F32, 4, 4, 4) == 0
+    assert fst._fn["fst_gram_workspace_bytes"](m.handle, 1000) == 0
+    assert fst._fn["fst_refit_core_mixed_workspace_bytes"](m.handle, fst.FST_F32, 5000, 1000) == 0
+    # the d-way workspace holds at least the FP64 Gram and the rows of one chunk
+    ws = fst.fst_refit_core_d_workspace_bytes(m, fst.FST_F32, 1000)
+    assert ws >= 8 * om.R * om.R + 4 * om.R * 1024
+    # mode index bounds follow d
+    out = np.empty((7, 2))
+    assert fst._fn["fst_model_coefs"](m.handle, 3, out.ctypes.data_as(ctypes.c_void_p)) == fst.FST_OK
+    assert fst._fn["fst_model_coefs"](m.handle, 4, out.ctypes.data_as(ctypes.c_void_p)) == fst.FST_E_INVAL
+    # only d = 3 and d = 4 exist
+    one = np.ones(5)
+    ip = np.ones(5, np.int32)
+    arr = (ctypes.c_void_p * 5)(*[one.ctypes.data_as(ctypes.c_void_p)] * 5)
+    h = ctypes.c_void_p()
+    st = fst._fn["fst_model_from_parts_d"](5, one.ctypes.data_as(ctypes.c_void_p),
+                                           (one * 2).ctypes.data_as(ctypes.c_void_p),
+                                           ip.ctypes.data_as(ctypes.c_void_p),
+                                           (ip * 0).ctypes.data_as(ctypes.c_void_p),
+                                           one.ctypes.data_as(ctypes.c_void_p), arr, ctypes.byref(h))
+    assert st == fst.FST_E_UNSUPPORTED
+    # the d-way calls reject a null coordinate list before touching the device
+    st = fst._fn["fst_eval_d"](m.handle, fst.FST_F64, 10, None, None, None)
+    assert st == fst.FST_E_INVAL
