@@ -355,6 +355,41 @@ fst_status fst_refit_core_d(const fst_model* m, int32_t dtype, int64_t n, const 
                             const void* v, int64_t n_samples, uint64_t seed, void* ws,
                             size_t ws_bytes, void* stream, fst_model** out);
 
+/* Parameters of Algorithm 1 + Algorithm 2 for d = 3 or 4 modes (entries k >= d unused); the
+ * fields mean what they mean in fst_fit_params.  Set struct_size = sizeof(fst_fit_params_d). */
+typedef struct {
+  uint32_t struct_size;
+  int32_t  dtype;            /* FST_F64 | FST_F32: type of the coordinate and value arrays */
+  int32_t  d;                /* 3 or 4 */
+  double   lo[4], hi[4];     /* box mapped onto [-1,1]^d */
+  int32_t  grid[4];          /* I_k of the interpolation grid (Sec. 4.1), I_1 .. I_d <= 2^28 nodes */
+  int32_t  rank[4];          /* r_k (caps when eps > 0), r_k <= I_k, r_k <= prod of the others */
+  int32_t  degree[4];        /* p_k, r_k <= p_k + 1 */
+  double   interp_fraction;
+  int32_t  idw_k;
+  double   idw_power;
+  int64_t  n_samples;        /* M rows of Algorithm 2; r1 .. rd < M <= n */
+  uint64_t seed;
+  int32_t  n_threads;
+  double   eps;              /* > 0: ranks from this precision (Sec. 4.1), threshold eps^2 ||T||^2 / d */
+} fst_fit_params_d;
+
+/* Fills defaults for d modes (grid 16, ranks 4, degree 15, fraction 0.1, idw 8 / 2.0, ...). */
+void fst_fit_params_d_default(fst_fit_params_d* p, int32_t d);
+/* Device workspace (bytes) of fst_fit_d for n points (the refit at the rank caps). */
+size_t fst_fit_d_workspace_bytes(const fst_fit_params_d* p, int64_t n);
+/* Algorithm 1 then Algorithm 2 for a d-way dataset (Sec. 4-5): the interpolation subset
+ * (stream 1) is gathered from the device, interpolated onto the d-dimensional grid by inverse
+ * distances, decomposed by ST-HOSVD (modes in order 1 .. d) and fitted by sparse Legendre
+ * expansions on host threads; the core is then refitted on the GPU as in fst_refit_core_d.
+ * coords: host array of d device coordinate arrays; v: device values; n elements of
+ * p->dtype each.  ws >= fst_fit_d_workspace_bytes, or NULL.  Synchronises `stream`. */
+fst_status fst_fit_d(const fst_fit_params_d* p, int64_t n, const void* const* coords, const void* v,
+                     void* ws, size_t ws_bytes, void* stream, fst_model** out);
+/* Algorithm 1 only, on host arrays (coords: host array of d host arrays, v: host values). */
+fst_status fst_compress_host_d(const fst_fit_params_d* p, int64_t n, const void* const* coords,
+                               const void* v, fst_model** out);
+
 /* ------------------------------------------------------------------ batched form */
 /* Many field variables on one shared point set (device arrays x, y, z of n points, dtype
  * base->dtype), with per-variable ranks (V x 3) and degrees (V x 3), both host int32.  All

@@ -47,6 +47,14 @@ class fst_fit_params(C.Structure):
                 ("refine_steps", C.c_int32), ("n_threads", C.c_int32), ("eps", C.c_double)]
 
 
+class fst_fit_params_d(C.Structure):
+    _fields_ = [("struct_size", C.c_uint32), ("dtype", C.c_int32), ("d", C.c_int32),
+                ("lo", C.c_double * 4), ("hi", C.c_double * 4),
+                ("grid", C.c_int32 * 4), ("rank", C.c_int32 * 4), ("degree", C.c_int32 * 4),
+                ("interp_fraction", C.c_double), ("idw_k", C.c_int32), ("idw_power", C.c_double),
+                ("n_samples", C.c_int64), ("seed", C.c_uint64), ("n_threads", C.c_int32), ("eps", C.c_double)]
+
+
 _vp, _i64, _i32, _dp = C.c_void_p, C.c_int64, C.c_int32, C.POINTER(C.c_double)
 
 
@@ -104,6 +112,10 @@ _lib_fns = dict(
     fst_eval_d=(_i32, _vp, _i32, _i64, _vp, _vp, _vp),
     fst_refit_core_d_workspace_bytes=(C.c_size_t, _vp, _i32, _i64),
     fst_refit_core_d=(_i32, _vp, _i32, _i64, _vp, _vp, _i64, C.c_uint64, _vp, C.c_size_t, _vp, C.POINTER(_vp)),
+    fst_fit_params_d_default=(None, C.POINTER(fst_fit_params_d), _i32),
+    fst_fit_d_workspace_bytes=(C.c_size_t, C.POINTER(fst_fit_params_d), _i64),
+    fst_fit_d=(_i32, C.POINTER(fst_fit_params_d), _i64, _vp, _vp, _vp, C.c_size_t, _vp, C.POINTER(_vp)),
+    fst_compress_host_d=(_i32, C.POINTER(fst_fit_params_d), _i64, _vp, _vp, C.POINTER(_vp)),
     fst_model_free=(None, _vp),
     fst_model_info=(_i32, _vp, _vp, _vp, _vp, _vp, _vp),
     fst_model_core=(_i32, _vp, _vp),
@@ -207,6 +219,31 @@ def make_params(dtype=FST_F64, lo=(-1.0,) * 3, hi=(1.0,) * 3, grid=(32,) * 3, ra
         gram_prec = FST_GRAM_F64 if dtype == FST_F64 else FST_GRAM_F32
     p.gram_prec = int(gram_prec)
     p.refine_steps = int(refine_steps)
+    p.n_threads = int(n_threads)
+    p.eps = float(eps)
+    return p
+
+
+def make_params_d(d=4, dtype=FST_F64, lo=None, hi=None, grid=None, rank=None, degree=None,
+                  interp_fraction=0.10, idw_k=8, idw_power=2.0, n_samples=2000, seed=1, n_threads=0,
+                  eps=0.0) -> fst_fit_params_d:
+    p = fst_fit_params_d()
+    _fn["fst_fit_params_d_default"](C.byref(p), int(d))
+    p.dtype = dtype
+    for k in range(d):
+        if lo is not None:
+            p.lo[k], p.hi[k] = float(lo[k]), float(hi[k])
+        if grid is not None:
+            p.grid[k] = int(grid[k])
+        if rank is not None:
+            p.rank[k] = int(rank[k])
+        if degree is not None:
+            p.degree[k] = int(degree[k])
+    p.interp_fraction = float(interp_fraction)
+    p.idw_k = int(idw_k)
+    p.idw_power = float(idw_power)
+    p.n_samples = int(n_samples)
+    p.seed = int(seed)
     p.n_threads = int(n_threads)
     p.eps = float(eps)
     return p
@@ -396,6 +433,8 @@ def fst_eval(m: Model, x, y, z, out=None, stream=None):
 
 # ------------------------------------------------------------------------------ d-way calls
 def _coord_list(coords):
+    if any(c.dtype != coords[0].dtype or c.numel() != coords[0].numel() for c in coords):
+        raise ValueError("coordinate arrays must share dtype and length")
     return (C.c_void_p * len(coords))(*[_dev_ptr(c) for c in coords])
 
 
@@ -425,6 +464,33 @@ def fst_refit_core_d(m: Model, coords, v, n_samples: int, seed: int, ws=None, st
     h = C.c_void_p()
     _check(_fn["fst_refit_core_d"](m.handle, dt, n, _coord_list(coords), _dev_ptr(v), int(n_samples), int(seed),
                                    _dev_ptr(ws), ws.numel(), _stream(stream), C.byref(h)))
+    return Model(h)
+
+
+def fst_fit_d_workspace_bytes(p: fst_fit_params_d, n: int) -> int:
+    b = _fn["fst_fit_d_workspace_bytes"](C.byref(p), int(n))
+    if b == 0:
+        raise FstError(FST_E_INVAL, fst_last_error())
+    return int(b)
+
+
+def fst_fit_d(p: fst_fit_params_d, coords, v, stream=None) -> Model:
+    """Algorithm 1 + Algorithm 2 for a d-way dataset given as device arrays (one per mode)."""
+    n = coords[0].numel()
+    ws = _workspace(fst_fit_d_workspace_bytes(p, n), coords[0].device)
+    h = C.c_void_p()
+    _check(_fn["fst_fit_d"](C.byref(p), n, _coord_list(coords), _dev_ptr(v), _dev_ptr(ws), ws.numel(),
+                            _stream(stream), C.byref(h)))
+    return Model(h)
+
+
+def fst_compress_host_d(p: fst_fit_params_d, coords, v) -> Model:
+    """Algorithm 1 for a d-way dataset on host numpy arrays (dtype given by p.dtype)."""
+    dt = np.float64 if p.dtype == FST_F64 else np.float32
+    hs = [_host(a, dt) for a in list(coords) + [v]]
+    arr = (C.c_void_p * len(coords))(*[t[1] for t in hs[:-1]])
+    h = C.c_void_p()
+    _check(_fn["fst_compress_host_d"](C.byref(p), hs[0][0].size, arr, hs[-1][1], C.byref(h)))
     return Model(h)
 
 

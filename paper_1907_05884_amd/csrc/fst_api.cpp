@@ -412,6 +412,100 @@ static DwayRefitLayout dway_refit_layout(const fst_model* m, int dtype, int64_t 
   return L;
 }
 
+static void validate_params_d(const fst_fit_params_d* p, int64_t n) {
+  if (!p) fail(FST_E_INVAL, "null parameters");
+  if (p->struct_size != sizeof(fst_fit_params_d)) fail(FST_E_INVAL, "fst_fit_params_d.struct_size mismatch");
+  check_dtype(p->dtype);
+  if (p->d != 3 && p->d != 4) fail(FST_E_UNSUPPORTED, "only d = 3 and d = 4 are supported");
+  const int D = p->d;
+  if (n < 1 || n >= (int64_t(1) << 31)) fail(FST_E_INVAL, "need 1 <= n < 2^31 points");
+  int64_t nodes = 1, R = 1;
+  for (int k = 0; k < D; ++k) {
+    if (!(std::isfinite(p->lo[k]) && std::isfinite(p->hi[k]) && p->hi[k] > p->lo[k]))
+      fail(FST_E_INVAL, "need finite lo < hi in every mode");
+    if (p->grid[k] < 3 || p->grid[k] > 4096) fail(FST_E_INVAL, "grid sizes must be in [3, 4096]");
+    if (p->rank[k] < 1 || p->rank[k] > p->grid[k]) fail(FST_E_INVAL, "need 1 <= rank <= grid size");
+    if (p->rank[k] > kMaxRank) fail(FST_E_UNSUPPORTED, "rank above 32 is not supported");
+    if (p->degree[k] < 0) fail(FST_E_INVAL, "degree must be >= 0");
+    if (p->degree[k] + 1 > kMaxBasis) fail(FST_E_UNSUPPORTED, "degree above 31 is not supported");
+    if (p->rank[k] > p->degree[k] + 1)
+      fail(FST_E_INVAL, "each rank must not exceed degree + 1 (more factor functions than basis functions "
+                        "makes the core least-squares problem singular)");
+    nodes *= p->grid[k];
+    R *= p->rank[k];
+  }
+  for (int k = 0; k < D; ++k) {
+    int64_t other = 1;
+    for (int l = 0; l < D; ++l)
+      if (l != k) other *= p->rank[l];
+    if (p->rank[k] > other) fail(FST_E_INVAL, "each rank must not exceed the product of the others");
+  }
+  if (nodes > (int64_t(1) << 28)) fail(FST_E_INVAL, "grid too large");
+  if (!(p->interp_fraction > 0.0 && p->interp_fraction <= 1.0)) fail(FST_E_INVAL, "interp_fraction must be in (0, 1]");
+  if (p->idw_k < 1 || p->idw_k > 64) fail(FST_E_INVAL, "idw_k must be in [1, 64]");
+  if (!(p->idw_power > 0.0 && std::isfinite(p->idw_power))) fail(FST_E_INVAL, "idw_power must be positive");
+  if (p->n_samples <= R || p->n_samples > n)
+    fail(FST_E_INVAL, "Algorithm 2 needs r1 .. rd < n_samples <= n (more sampled rows than core entries)");
+  if (llround(p->interp_fraction * (double)n) < 1) fail(FST_E_INVAL, "interpolation subset is empty");
+  if (!(p->eps >= 0.0 && p->eps < 1.0)) fail(FST_E_INVAL, "eps must be in [0, 1)");
+}
+
+// Algorithm 1 for D modes from the gathered subset (host FP64, K x (D + 1): coordinates, value)
+static fst_model* compress_from_subset_d(const fst_fit_params_d* p, const std::vector<double>& sub, int64_t K) {
+  const int D = p->d;
+  std::vector<double> xi((size_t)K * D), v((size_t)K);
+  for (int64_t i = 0; i < K; ++i) {
+    for (int k = 0; k < D; ++k) {
+      const double c = sub[(size_t)((D + 1) * i + k)];
+      if (!std::isfinite(c)) fail(FST_E_INVAL, "non-finite coordinate in the interpolation subset");
+      xi[(size_t)(D * i + k)] = 2.0 * (c - p->lo[k]) / (p->hi[k] - p->lo[k]) - 1.0;
+    }
+    v[(size_t)i] = sub[(size_t)((D + 1) * i + D)];
+    if (!std::isfinite(v[(size_t)i])) fail(FST_E_INVAL, "non-finite value in the interpolation subset");
+  }
+  int64_t nodes = 1;
+  for (int k = 0; k < D; ++k) nodes *= p->grid[k];
+  std::vector<double> T((size_t)nodes);
+  idw_grid_d(xi.data(), v.data(), K, D, p->grid, p->idw_k, p->idw_power, p->n_threads, T.data());
+  int32_t rank[kMaxModes];
+  std::vector<double> W[kMaxModes];
+  double* Wp[kMaxModes];
+  int64_t Rcap = 1;
+  for (int k = 0; k < D; ++k) {
+    rank[k] = p->rank[k];
+    W[k].assign((size_t)p->grid[k] * p->rank[k], 0.0);
+    Wp[k] = W[k].data();
+    Rcap *= p->rank[k];
+  }
+  std::vector<double> core((size_t)Rcap);
+  if (p->eps > 0.0) {
+    // ranks from the precision, capped by rank[]; a rank above the product of the others
+    // would only add dependent design columns, so such ranks are lowered and the
+    // decomposition is taken again at the final ranks
+    int32_t r[kMaxModes];
+    sthosvd_eps_d(T.data(), D, p->grid, p->eps, p->rank, p->n_threads, r, core.data(), Wp, nullptr);
+    bool lowered = false;
+    for (int pass = 0; pass < D; ++pass)
+      for (int k = 0; k < D; ++k) {
+        int64_t lim = 1;
+        for (int l = 0; l < D; ++l)
+          if (l != k) lim *= r[l];
+        if (r[k] > lim) {
+          r[k] = (int32_t)lim;
+          lowered = true;
+        }
+      }
+    for (int k = 0; k < D; ++k) rank[k] = r[k];
+    if (lowered) sthosvd_d(T.data(), D, p->grid, rank, p->n_threads, core.data(), Wp, nullptr);
+  } else {
+    sthosvd_d(T.data(), D, p->grid, rank, p->n_threads, core.data(), Wp, nullptr);
+  }
+  std::unique_ptr<fst_model> m(model_new_d(D, p->lo, p->hi, rank, p->degree));
+  std::copy(core.begin(), core.begin() + (size_t)m->R(), m->core.begin());
+  for (int k = 0; k < D; ++k) sparse_fit(W[k].data(), p->grid[k], rank[k], p->degree[k], m->coef[k].data());
+  return m.release();
+}
+
 static void check_coords(const fst_model* m, const void* const* coords) {
   if (!coords) fail(FST_E_INVAL, "null coordinate list");
   for (int k = 0; k < m->d; ++k)
@@ -921,6 +1015,88 @@ fst_status fst_model_info_d(const fst_model* m, int32_t* d, double* lo, double* 
       for (double t : m->coef[k]) c += t != 0.0;
     *nnz = c;
   }
+  return FST_OK;
+  FST_CATCH
+}
+
+void fst_fit_params_d_default(fst_fit_params_d* p, int32_t d) {
+  if (!p) return;
+  std::memset(p, 0, sizeof(*p));
+  p->struct_size = sizeof(fst_fit_params_d);
+  p->dtype = FST_F64;
+  p->d = d;
+  for (int k = 0; k < kMaxModes; ++k) {
+    p->lo[k] = -1.0;
+    p->hi[k] = 1.0;
+    p->grid[k] = 16;
+    p->rank[k] = 4;
+    p->degree[k] = 15;
+  }
+  p->interp_fraction = 0.10;
+  p->idw_k = 8;
+  p->idw_power = 2.0;
+  p->n_samples = 2000;
+  p->seed = 1;
+  p->eps = 0.0;
+}
+
+size_t fst_fit_d_workspace_bytes(const fst_fit_params_d* p, int64_t n) {
+  try {
+    validate_params_d(p, n);
+    const int64_t K = llround(p->interp_fraction * (double)n);
+    // the refit of a model with the largest ranks allowed (eps may choose smaller ones)
+    std::unique_ptr<fst_model> cap(model_new_d(p->d, p->lo, p->hi, p->rank, p->degree));
+    return std::max(gather_workspace_bytes(K, p->d), dway_refit_layout(cap.get(), p->dtype, p->n_samples).total);
+  } catch (const fst::Error& e) {
+    fst::set_last_error(e.what());
+    return 0;
+  }
+}
+
+fst_status fst_compress_host_d(const fst_fit_params_d* p, int64_t n, const void* const* coords, const void* v,
+                               fst_model** out) {
+  FST_TRY
+  set_last_error("");
+  validate_params_d(p, n);
+  if (!coords || !v || !out) fail(FST_E_INVAL, "null argument");
+  const int D = p->d;
+  for (int k = 0; k < D; ++k)
+    if (!coords[k]) fail(FST_E_INVAL, "null coordinate array");
+  const int64_t K = llround(p->interp_fraction * (double)n);
+  std::vector<int64_t> sub((size_t)K);
+  sample_indices(p->seed, FST_STREAM_INTERP, n, K, sub.data());
+  std::vector<double> rows((size_t)K * (D + 1));
+  for (int64_t t = 0; t < K; ++t) {
+    const int64_t i = sub[(size_t)t];
+    for (int k = 0; k <= D; ++k) {
+      const void* src = k < D ? coords[k] : v;
+      rows[(size_t)((D + 1) * t + k)] =
+          p->dtype == FST_F64 ? ((const double*)src)[i] : (double)((const float*)src)[i];
+    }
+  }
+  *out = compress_from_subset_d(p, rows, K);
+  return FST_OK;
+  FST_CATCH
+}
+
+fst_status fst_fit_d(const fst_fit_params_d* p, int64_t n, const void* const* coords, const void* v, void* ws,
+                     size_t ws_bytes, void* stream, fst_model** out) {
+  FST_TRY
+  set_last_error("");
+  validate_params_d(p, n);
+  if (!coords || !v || !out) fail(FST_E_INVAL, "null argument");
+  for (int k = 0; k < p->d; ++k)
+    if (!coords[k]) fail(FST_E_INVAL, "null coordinate array");
+  const int64_t K = llround(p->interp_fraction * (double)n);
+  Workspace w(ws, ws_bytes, fst_fit_d_workspace_bytes(p, n));
+  // Algorithm 1 step 1: a random subset (stream 1) is gathered on the device and copied out
+  std::vector<int64_t> sub((size_t)K);
+  sample_indices(p->seed, FST_STREAM_INTERP, n, K, sub.data());
+  std::vector<double> rows((size_t)K * (p->d + 1));
+  gather_points_d(p->dtype, K, sub.data(), p->d, coords, v, rows.data(), w.p, w.bytes, stream);
+  std::unique_ptr<fst_model> m0(compress_from_subset_d(p, rows, K));
+  // Algorithm 2 on the device
+  *out = refit_d_impl(m0.get(), p->dtype, n, coords, v, p->n_samples, p->seed, w.p, w.bytes, stream);
   return FST_OK;
   FST_CATCH
 }

@@ -18,6 +18,7 @@
 
 #include <algorithm>
 #include <string>
+#include <vector>
 
 #include "fst_device.h"
 #include "fst_internal.h"
@@ -148,6 +149,53 @@ void dway_normal_equations(const fst_model* m, int dtype, const void* const* coo
     dway_chunks<double>(m, L, w, M, G, h, stream);
   else
     dway_chunks<float>(m, L, w, M, G, h, stream);
+}
+
+// ------------------------------------------------------------------------------ subset gather
+// The interpolation subset of Algorithm 1 (D coordinates and the value of each chosen point)
+// copied into one FP64 array for the host steps.
+struct GatherArgs {
+  const void* c[kMaxModes];
+  const void* v;
+  const int32_t* idx;
+  double* out;
+  int64_t K;
+  int32_t D, f64;
+};
+
+__global__ void k_gather_d(GatherArgs a) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= a.K) return;
+  const int64_t i = a.idx[t];
+  double* o = a.out + (a.D + 1) * t;
+  for (int k = 0; k <= a.D; ++k) {
+    const void* src = k < a.D ? a.c[k] : a.v;
+    o[k] = a.f64 ? ((const double*)src)[i] : (double)((const float*)src)[i];
+  }
+}
+
+size_t gather_workspace_bytes(int64_t K, int D) {
+  return align_up(sizeof(int32_t) * (size_t)K) + sizeof(double) * (size_t)(D + 1) * (size_t)K;
+}
+
+void gather_points_d(int dtype, int64_t K, const int64_t* idx_host, int D, const void* const* coords, const void* v,
+                     double* out_host, void* ws, size_t ws_bytes, void* stream) {
+  if (ws_bytes < gather_workspace_bytes(K, D)) fail(FST_E_NOMEM, "gather: workspace too small");
+  if (K <= 0) return;
+  std::vector<int32_t> idx32((size_t)K);
+  for (int64_t t = 0; t < K; ++t) idx32[(size_t)t] = (int32_t)idx_host[t];
+  GatherArgs a;
+  for (int k = 0; k < kMaxModes; ++k) a.c[k] = k < D ? coords[k] : nullptr;
+  a.v = v;
+  a.idx = (int32_t*)ws;
+  a.out = (double*)((char*)ws + align_up(sizeof(int32_t) * (size_t)K));
+  a.K = K;
+  a.D = D;
+  a.f64 = dtype == FST_F64 ? 1 : 0;
+  copy_h2d((void*)a.idx, idx32.data(), sizeof(int32_t) * (size_t)K, stream);
+  hipLaunchKernelGGL(k_gather_d, dim3((unsigned)((K + 255) / 256)), dim3(256), 0, S(stream), a);
+  check_launch("k_gather_d");
+  copy_d2h(out_host, a.out, sizeof(double) * (size_t)(D + 1) * (size_t)K, stream);
 }
 
 // ------------------------------------------------------------------------------ reconstruction

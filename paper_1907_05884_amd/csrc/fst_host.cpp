@@ -66,8 +66,8 @@ void sample_indices(uint64_t seed, int stream, int64_t n, int64_t m, int64_t* ou
 }
 
 // ------------------------------------------------------------------------------ IDW
-// Exact k-nearest neighbours through a uniform bin grid over [-1,1]^3, searched in growing
-// cubic shells until the k-th best distance is below the distance to any unsearched cell.
+// Exact k-nearest neighbours through a uniform bin grid over [-1,1]^D, searched in growing
+// shells of cells until the k-th best distance is below the distance to any unsearched cell.
 // Candidates are ordered by (squared distance, index): equal distances go to the lower index.
 namespace {
 struct Cand {
@@ -79,7 +79,7 @@ struct Cand {
 struct BinGrid {
   int B = 1;
   double h = 2.0;
-  std::vector<int64_t> start;   // B^3 + 1
+  std::vector<int64_t> start;   // B^D + 1
   std::vector<int64_t> order;   // point indices sorted by cell (stable, so ascending in a cell)
   int cell_of(double t) const {
     int c = (int)std::floor((t + 1.0) / h);
@@ -88,28 +88,40 @@ struct BinGrid {
 };
 }  // namespace
 
-// The k nearest subset points of every grid node (C order), as (index, weight) pairs with
-// weights d^-power; an exact hit is stored as a single neighbour with a negative weight.
-void idw_knn(const double* xi, int64_t K, const int32_t grid[3], int k, double power, int n_threads,
-             std::vector<int64_t>& nbr, std::vector<double>& wgt, std::vector<int32_t>& count) {
+// The k nearest subset points of every grid node (C order, last mode fastest), as (index,
+// weight) pairs with weights d^-power; an exact hit is stored as a single neighbour with a
+// negative weight.  xi: K x D reference coordinates, D = 3 or 4; the bins are D-dimensional
+// cubes and the shells are searched with an odometer over the cells of each shell.
+void idw_knn_d(const double* xi, int64_t K, int D, const int32_t* grid, int k, double power, int n_threads,
+               std::vector<int64_t>& nbr, std::vector<double>& wgt, std::vector<int32_t>& count) {
+  if (D < 1 || D > kMaxModes) fail(FST_E_INVAL, "idw_grid: need 1 <= d <= 4");
   if (K <= 0) fail(FST_E_INVAL, "idw_grid: no points");
-  for (int d = 0; d < 3; ++d)
+  for (int d = 0; d < D; ++d)
     if (grid[d] < 2) fail(FST_E_INVAL, "idw_grid: grid sizes must be >= 2");
   if (k < 1) fail(FST_E_INVAL, "idw_grid: k must be >= 1");
   k = (int)std::min<int64_t>(k, K);
   BinGrid bg;
-  bg.B = std::max(1, (int)std::cbrt((double)K / 2.0));
+  const double per_bin = (double)K / 2.0;   // about two points per bin
+  bg.B = std::max(1, (int)(D == 3 ? std::cbrt(per_bin) : D == 4 ? std::sqrt(std::sqrt(per_bin))
+                                                              : std::pow(per_bin, 1.0 / D)));
   bg.B = std::min(bg.B, 256);
   bg.h = 2.0 / bg.B;
   const int B = bg.B;
-  const int64_t ncell = (int64_t)B * B * B;
+  int64_t ncell = 1;
+  for (int d = 0; d < D; ++d) ncell *= B;
+  auto cell_index = [&](const int* c) {
+    int64_t cc = 0;
+    for (int d = 0; d < D; ++d) cc = cc * B + c[d];
+    return cc;
+  };
   std::vector<int64_t> cell((size_t)K);
   bg.start.assign((size_t)ncell + 1, 0);
   for (int64_t i = 0; i < K; ++i) {
-    int64_t c = ((int64_t)bg.cell_of(xi[3 * i]) * B + bg.cell_of(xi[3 * i + 1])) * B +
-                bg.cell_of(xi[3 * i + 2]);
-    cell[(size_t)i] = c;
-    bg.start[(size_t)c + 1]++;
+    int c[kMaxModes];
+    for (int d = 0; d < D; ++d) c[d] = bg.cell_of(xi[D * i + d]);
+    const int64_t cc = cell_index(c);
+    cell[(size_t)i] = cc;
+    bg.start[(size_t)cc + 1]++;
   }
   for (int64_t c = 0; c < ncell; ++c) bg.start[(size_t)c + 1] += bg.start[(size_t)c];
   bg.order.resize((size_t)K);
@@ -117,8 +129,8 @@ void idw_knn(const double* xi, int64_t K, const int32_t grid[3], int k, double p
     std::vector<int64_t> fill(bg.start.begin(), bg.start.end() - 1);
     for (int64_t i = 0; i < K; ++i) bg.order[(size_t)fill[(size_t)cell[(size_t)i]]++] = i;
   }
-  const int64_t I0 = grid[0], I1 = grid[1], I2 = grid[2];
-  const int64_t nodes = I0 * I1 * I2;
+  int64_t nodes = 1;
+  for (int d = 0; d < D; ++d) nodes *= grid[d];
   nbr.assign((size_t)(nodes * k), 0);
   wgt.assign((size_t)(nodes * k), 0.0);
   count.assign((size_t)nodes, 0);
@@ -126,39 +138,56 @@ void idw_knn(const double* xi, int64_t K, const int32_t grid[3], int k, double p
     std::vector<Cand> best;
     best.reserve((size_t)k + 1);
     for (int64_t node = a; node < b; ++node) {
-      int64_t i0 = node / (I1 * I2), i1 = (node / I2) % I1, i2 = node % I2;
-      double q[3] = {-1.0 + 2.0 * i0 / (I0 - 1), -1.0 + 2.0 * i1 / (I1 - 1),
-                     -1.0 + 2.0 * i2 / (I2 - 1)};
-      int c[3] = {bg.cell_of(q[0]), bg.cell_of(q[1]), bg.cell_of(q[2])};
+      double q[kMaxModes];
+      int c[kMaxModes];
+      int64_t rem = node;
+      for (int d = D - 1; d >= 0; --d) {
+        const int64_t id = rem % grid[d];
+        rem /= grid[d];
+        q[d] = -1.0 + 2.0 * id / (grid[d] - 1);
+        c[d] = bg.cell_of(q[d]);
+      }
       best.clear();
       for (int rho = 0;; ++rho) {
-        int lo[3], hi[3];
-        for (int d = 0; d < 3; ++d) {
+        int lo[kMaxModes], hi[kMaxModes], x[kMaxModes];
+        for (int d = 0; d < D; ++d) {
           lo[d] = std::max(0, c[d] - rho);
           hi[d] = std::min(B - 1, c[d] + rho);
+          x[d] = lo[d];
         }
-        for (int x = lo[0]; x <= hi[0]; ++x)
-          for (int y = lo[1]; y <= hi[1]; ++y)
-            for (int z = lo[2]; z <= hi[2]; ++z) {
-              // only the shell at Chebyshev distance rho (inner cells were done before)
-              int cheb = std::max({std::abs(x - c[0]), std::abs(y - c[1]), std::abs(z - c[2])});
-              if (cheb != rho) continue;
-              int64_t cc = ((int64_t)x * B + y) * B + z;
-              for (int64_t s = bg.start[(size_t)cc]; s < bg.start[(size_t)cc + 1]; ++s) {
-                int64_t i = bg.order[(size_t)s];
-                double dx = xi[3 * i] - q[0], dy = xi[3 * i + 1] - q[1], dz = xi[3 * i + 2] - q[2];
-                Cand cd{dx * dx + dy * dy + dz * dz, i};
-                if ((int)best.size() < k) {
-                  best.insert(std::upper_bound(best.begin(), best.end(), cd), cd);
-                } else if (cd < best.back()) {
-                  best.pop_back();
-                  best.insert(std::upper_bound(best.begin(), best.end(), cd), cd);
-                }
+        for (;;) {
+          // only the shell at Chebyshev distance rho (inner cells were done before)
+          int cheb = 0;
+          for (int d = 0; d < D; ++d) cheb = std::max(cheb, std::abs(x[d] - c[d]));
+          if (cheb == rho) {
+            const int64_t cc = cell_index(x);
+            for (int64_t s = bg.start[(size_t)cc]; s < bg.start[(size_t)cc + 1]; ++s) {
+              const int64_t i = bg.order[(size_t)s];
+              double d2 = 0.0;
+              for (int d = 0; d < D; ++d) {
+                const double t = xi[D * i + d] - q[d];
+                d2 += t * t;
+              }
+              Cand cd{d2, i};
+              if ((int)best.size() < k) {
+                best.insert(std::upper_bound(best.begin(), best.end(), cd), cd);
+              } else if (cd < best.back()) {
+                best.pop_back();
+                best.insert(std::upper_bound(best.begin(), best.end(), cd), cd);
               }
             }
+          }
+          int d = D - 1;   // next cell of the box lo..hi, last mode fastest
+          while (d >= 0 && x[d] == hi[d]) {
+            x[d] = lo[d];
+            --d;
+          }
+          if (d < 0) break;
+          ++x[d];
+        }
         bool covers_all = true;
         double bound = std::numeric_limits<double>::infinity();
-        for (int d = 0; d < 3; ++d) {
+        for (int d = 0; d < D; ++d) {
           if (c[d] - rho > 0) {
             covers_all = false;
             bound = std::min(bound, q[d] - (-1.0 + (c[d] - rho) * bg.h));
@@ -190,6 +219,11 @@ void idw_knn(const double* xi, int64_t K, const int32_t grid[3], int k, double p
   });
 }
 
+void idw_knn(const double* xi, int64_t K, const int32_t grid[3], int k, double power, int n_threads,
+             std::vector<int64_t>& nbr, std::vector<double>& wgt, std::vector<int32_t>& count) {
+  idw_knn_d(xi, K, 3, grid, k, power, n_threads, nbr, wgt, count);
+}
+
 void idw_apply(const std::vector<int64_t>& nbr, const std::vector<double>& wgt, const std::vector<int32_t>& count,
                int k, const double* v, int n_threads, double* out) {
   const int64_t nodes = (int64_t)count.size();
@@ -211,14 +245,19 @@ void idw_apply(const std::vector<int64_t>& nbr, const std::vector<double>& wgt, 
   });
 }
 
-void idw_grid(const double* xi, const double* v, int64_t K, const int32_t grid[3], int k,
-              double power, int n_threads, double* out) {
+void idw_grid_d(const double* xi, const double* v, int64_t K, int D, const int32_t* grid, int k, double power,
+                int n_threads, double* out) {
   std::vector<int64_t> nbr;
   std::vector<double> wgt;
   std::vector<int32_t> count;
   k = (int)std::min<int64_t>(std::max(k, 1), std::max<int64_t>(K, 1));
-  idw_knn(xi, K, grid, k, power, n_threads, nbr, wgt, count);
+  idw_knn_d(xi, K, D, grid, k, power, n_threads, nbr, wgt, count);
   idw_apply(nbr, wgt, count, k, v, n_threads, out);
+}
+
+void idw_grid(const double* xi, const double* v, int64_t K, const int32_t grid[3], int k,
+              double power, int n_threads, double* out) {
+  idw_grid_d(xi, v, K, 3, grid, k, power, n_threads, out);
 }
 
 // ------------------------------------------------------------------------------ ST-HOSVD
@@ -331,13 +370,22 @@ void hestenes(std::vector<double>& B, int64_t n, std::vector<double>& V, std::ve
   }
 }
 
+// Sizes of a C-order tensor with dims d (D modes) around mode k: A = prod_{l<k} d_l rows
+// before it, Bs = prod_{l>k} d_l contiguous entries after it.
+void around_mode(const int64_t* d, int D, int k, int64_t& A, int64_t& Bs) {
+  A = 1;
+  Bs = 1;
+  for (int l = 0; l < k; ++l) A *= d[l];
+  for (int l = k + 1; l < D; ++l) Bs *= d[l];
+}
+
 // Leading r left singular vectors (I x r, row-major, signs fixed) of the mode-k unfolding
-// of Y with dims d; all singular values into sig_out (length min(I, L)).
-void leading_left_singular(const std::vector<double>& Y, const int64_t d[3], int k, int r,
+// of Y with dims d (D modes); all singular values into sig_out (length min(I, L)).
+void leading_left_singular(const std::vector<double>& Y, const int64_t* d, int D, int k, int r,
                            std::vector<double>& Wout, std::vector<double>& sig_out) {
   const int64_t I = d[k];
-  const int64_t A = (k == 0) ? 1 : (k == 1 ? d[0] : d[0] * d[1]);
-  const int64_t Bs = (k == 2) ? 1 : (k == 1 ? d[2] : d[1] * d[2]);
+  int64_t A, Bs;
+  around_mode(d, D, k, A, Bs);
   const int64_t L = A * Bs;
   // element (i, l) of the unfolding with l = a * Bs + b
   auto at = [&](int64_t i, int64_t l) {
@@ -400,11 +448,11 @@ void leading_left_singular(const std::vector<double>& Y, const int64_t d[3], int
   }
 }
 
-// Y (dims d) <- Y x_k W^T with W (I_k x r) row-major; d[k] becomes r.
-void mode_product_transposed(std::vector<double>& Y, int64_t d[3], int k, const std::vector<double>& W, int r) {
+// Y (dims d, D modes) <- Y x_k W^T with W (I_k x r) row-major; d[k] becomes r.
+void mode_product_transposed(std::vector<double>& Y, int64_t* d, int D, int k, const std::vector<double>& W, int r) {
   const int64_t I = d[k];
-  const int64_t A = (k == 0) ? 1 : (k == 1 ? d[0] : d[0] * d[1]);
-  const int64_t Bs = (k == 2) ? 1 : (k == 1 ? d[2] : d[1] * d[2]);
+  int64_t A, Bs;
+  around_mode(d, D, k, A, Bs);
   std::vector<double> out((size_t)(A * r * Bs), 0.0);
   for (int64_t a = 0; a < A; ++a)
     for (int j = 0; j < r; ++j) {
@@ -421,56 +469,66 @@ void mode_product_transposed(std::vector<double>& Y, int64_t d[3], int k, const 
 
 }  // namespace
 
-void sthosvd(const double* T, const int32_t dims[3], const int32_t rank[3], int n_threads,
-             double* core, double* const W[3], double* const sigma[3]) {
+void sthosvd_d(const double* T, int D, const int32_t* dims, const int32_t* rank, int n_threads, double* core,
+               double* const* W, double* const* sigma) {
   (void)n_threads;
-  int64_t d[3] = {dims[0], dims[1], dims[2]};
-  for (int k = 0; k < 3; ++k) {
-    if (d[k] < 1 || rank[k] < 1 || rank[k] > d[k])
-      fail(FST_E_INVAL, "sthosvd: need 1 <= r_k <= I_k");
+  if (D < 1 || D > kMaxModes) fail(FST_E_INVAL, "sthosvd: need 1 <= d <= 4");
+  int64_t d[kMaxModes], total = 1;
+  for (int k = 0; k < D; ++k) {
+    d[k] = dims[k];
+    if (d[k] < 1 || rank[k] < 1 || rank[k] > d[k]) fail(FST_E_INVAL, "sthosvd: need 1 <= r_k <= I_k");
+    total *= d[k];
   }
-  std::vector<double> Y(T, T + d[0] * d[1] * d[2]);
-  for (int k = 0; k < 3; ++k) {
+  std::vector<double> Y(T, T + total);
+  for (int k = 0; k < D; ++k) {
     int64_t L = 1;
-    for (int l = 0; l < 3; ++l)
+    for (int l = 0; l < D; ++l)
       if (l != k) L *= d[l];
     if (rank[k] > L) fail(FST_E_INVAL, "sthosvd: r_k exceeds the product of the other sizes");
     std::vector<double> Wk, sig;
-    leading_left_singular(Y, d, k, rank[k], Wk, sig);
+    leading_left_singular(Y, d, D, k, rank[k], Wk, sig);
     std::memcpy(W[k], Wk.data(), sizeof(double) * Wk.size());
     if (sigma && sigma[k]) {
       for (int64_t i = 0; i < dims[k]; ++i) sigma[k][i] = i < (int64_t)sig.size() ? sig[(size_t)i] : 0.0;
     }
-    mode_product_transposed(Y, d, k, Wk, rank[k]);
+    mode_product_transposed(Y, d, D, k, Wk, rank[k]);
   }
   std::memcpy(core, Y.data(), sizeof(double) * Y.size());
 }
 
+void sthosvd(const double* T, const int32_t dims[3], const int32_t rank[3], int n_threads,
+             double* core, double* const W[3], double* const sigma[3]) {
+  sthosvd_d(T, 3, dims, rank, n_threads, core, W, sigma);
+}
+
 // Ranks from a precision (Sec. 4.1, Table 1): the ST-HOSVD truncation rule that bounds the
 // error, ||T - T~||_F^2 <= sum_k sum_{i > r_k} sigma_i^(k)2 <= eps^2 ||T||_F^2, spread evenly
-// over the three modes: at step k, r_k is the smallest r with
-// sum_{i > r} sigma_i^2 <= eps^2 ||T||_F^2 / 3 over the singular values of the current
+// over the D modes: at step k, r_k is the smallest r with
+// sum_{i > r} sigma_i^2 <= eps^2 ||T||_F^2 / D over the singular values of the current
 // (already truncated) unfolding.  Ranks are capped at max_rank[k] (the bound then need not
-// hold).  W[k] receives I_k x r_k row-major, core r1 r2 r3.
-void sthosvd_eps(const double* T, const int32_t dims[3], double eps, const int32_t max_rank[3], int n_threads,
-                 int32_t rank_out[3], double* core, double* const W[3], double* const sigma[3]) {
+// hold).  W[k] receives I_k x r_k row-major, core r1 .. rD.
+void sthosvd_eps_d(const double* T, int D, const int32_t* dims, double eps, const int32_t* max_rank, int n_threads,
+                   int32_t* rank_out, double* core, double* const* W, double* const* sigma) {
   (void)n_threads;
+  if (D < 1 || D > kMaxModes) fail(FST_E_INVAL, "sthosvd_eps: need 1 <= d <= 4");
   if (!(eps > 0.0 && eps < 1.0)) fail(FST_E_INVAL, "sthosvd_eps: need 0 < eps < 1");
-  int64_t d[3] = {dims[0], dims[1], dims[2]};
-  for (int k = 0; k < 3; ++k)
+  int64_t d[kMaxModes], total = 1;
+  for (int k = 0; k < D; ++k) {
+    d[k] = dims[k];
     if (d[k] < 1 || max_rank[k] < 1) fail(FST_E_INVAL, "sthosvd_eps: need I_k >= 1 and max_rank_k >= 1");
-  const int64_t total = d[0] * d[1] * d[2];
+    total *= d[k];
+  }
   std::vector<double> Y(T, T + total);
   double norm2 = 0.0;
   for (int64_t i = 0; i < total; ++i) norm2 += T[i] * T[i];
-  const double thr = eps * eps * norm2 / 3.0;
-  for (int k = 0; k < 3; ++k) {
+  const double thr = eps * eps * norm2 / (double)D;
+  for (int k = 0; k < D; ++k) {
     int64_t L = 1;
-    for (int l = 0; l < 3; ++l)
+    for (int l = 0; l < D; ++l)
       if (l != k) L *= d[l];
     const int cap = (int)std::min<int64_t>({(int64_t)max_rank[k], d[k], L});
     std::vector<double> Wk, sig;
-    leading_left_singular(Y, d, k, cap, Wk, sig);
+    leading_left_singular(Y, d, D, k, cap, Wk, sig);
     // tail[r] = sum_{i >= r} sigma_i^2 (0-based), summed from the smallest value up
     const int ns = (int)sig.size();
     std::vector<double> tail((size_t)ns + 1, 0.0);
@@ -485,9 +543,14 @@ void sthosvd_eps(const double* T, const int32_t dims[3], double eps, const int32
     if (sigma && sigma[k])
       for (int64_t i = 0; i < dims[k]; ++i) sigma[k][i] = i < (int64_t)sig.size() ? sig[(size_t)i] : 0.0;
     std::vector<double> Wr(W[k], W[k] + d[k] * r);
-    mode_product_transposed(Y, d, k, Wr, r);
+    mode_product_transposed(Y, d, D, k, Wr, r);
   }
   std::memcpy(core, Y.data(), sizeof(double) * Y.size());
+}
+
+void sthosvd_eps(const double* T, const int32_t dims[3], double eps, const int32_t max_rank[3], int n_threads,
+                 int32_t rank_out[3], double* core, double* const W[3], double* const sigma[3]) {
+  sthosvd_eps_d(T, 3, dims, eps, max_rank, n_threads, rank_out, core, W, sigma);
 }
 
 // ------------------------------------------------------------------------------ sparse fit

@@ -88,6 +88,15 @@ void sthosvd(const double* T, const int32_t dims[3], const int32_t rank[3], int 
              double* core, double* const W[3], double* const sigma[3]);
 void sthosvd_eps(const double* T, const int32_t dims[3], double eps, const int32_t max_rank[3], int n_threads,
                  int32_t rank_out[3], double* core, double* const W[3], double* const sigma[3]);
+// the same for D = 3 or 4 modes (xi: K x D; dims, rank, grid: D entries)
+void idw_knn_d(const double* xi, int64_t K, int D, const int32_t* grid, int k, double power, int n_threads,
+               std::vector<int64_t>& nbr, std::vector<double>& wgt, std::vector<int32_t>& count);
+void idw_grid_d(const double* xi, const double* v, int64_t K, int D, const int32_t* grid, int k, double power,
+                int n_threads, double* out);
+void sthosvd_d(const double* T, int D, const int32_t* dims, const int32_t* rank, int n_threads, double* core,
+               double* const* W, double* const* sigma);
+void sthosvd_eps_d(const double* T, int D, const int32_t* dims, double eps, const int32_t* max_rank, int n_threads,
+                   int32_t* rank_out, double* core, double* const* W, double* const* sigma);
 void sparse_fit(const double* W, int I, int r, int p, double* C);
 void legendre_orthonormal_host(double t, int p, double* phi);
 int hardware_threads(int requested);
@@ -161,6 +170,10 @@ void dway_normal_equations(const fst_model* m, int dtype, const void* const* coo
 void launch_eval_d(const fst_model* m, const DeviceModel& dm, int dtype, int64_t n, const void* const* coords,
                    void* out, void* stream);
 int device_cu_count();
+// out_host[(D + 1) t + k] = coordinate k of point idx_host[t] (k < D), then its value, in FP64
+void gather_points_d(int dtype, int64_t K, const int64_t* idx_host, int D, const void* const* coords, const void* v,
+                     double* out_host, void* ws, size_t ws_bytes, void* stream);
+size_t gather_workspace_bytes(int64_t K, int D);
 size_t eval_grid_workspace_bytes(const fst_model* m, int dtype, int64_t n1, int64_t n2, int64_t n3);
 void eval_grid(const fst_model* m, const DeviceModel& dm, int dtype, const void* gx, int64_t n1, const void* gy,
                int64_t n2, const void* gz, int64_t n3, void* out, void* ws, void* stream);

@@ -167,3 +167,48 @@ def test_refit_d_rejects_bad_arguments(dev):
     with pytest.raises(fst.FstError) as e:
         fst.fst_eval(gm, c[0], c[1], c[2])
     assert e.value.status == fst.FST_E_INVAL
+
+
+def test_fit_d_four_way_end_to_end_fp64(dev):
+    # Algorithm 1 (4-D interpolation, 4-way ST-HOSVD, sparse fits) + Algorithm 2 on the GPU,
+    # against the oracle's pipeline on the same seeded space-time data
+    import datagen
+    from oracle import pipeline
+    w = datagen.make_workload("t4", seed=8, n=20_000, n_gauss=6, grid=(8,) * 4, rank=(3, 3, 2, 2),
+                              degree=(6,) * 4, interp_fraction=0.3, n_samples=3000, dtype=np.float64,
+                              lo=(-1.0, -1.0, -1.0, 0.0), hi=(1.0, 1.0, 1.0, 2.0))
+    print("fit4 end to end", flush=True)
+    mo = pipeline.fit(w.pts, w.vals, w.lo, w.hi, w.grid, w.rank, w.degree, w.interp_fraction, w.n_samples, w.seed)
+    p = fst.make_params_d(d=4, dtype=fst.FST_F64, lo=w.lo, hi=w.hi, grid=w.grid, rank=w.rank, degree=w.degree,
+                          interp_fraction=w.interp_fraction, n_samples=w.n_samples, seed=w.seed)
+    c = [D(a, dev) for a in w.soa()]
+    gm = fst.fst_fit_d(p, c[:4], c[4])
+    for k in range(4):
+        np.testing.assert_array_equal(gm.coefs(k) != 0, mo.coefs[k] != 0)
+        assert rel_l2(gm.coefs(k), mo.coefs[k]) <= 1e-7
+    assert rel_l2(gm.core, mo.core) <= 1e-6
+    f = fst.fst_eval_d(gm, c[:4]).cpu().numpy()
+    err_gpu, err_ref = rel_l2(f, w.vals), rel_l2(evaluate(mo, w.pts), w.vals)
+    assert abs(err_gpu - err_ref) <= 1e-6 * err_ref
+
+
+def test_fit_d_four_way_fp32_ranks_from_precision(dev):
+    import datagen
+    from oracle import pipeline
+    from oracle.sthosvd import ranks_for_precision
+    w = datagen.make_workload("t4", seed=9, n=40_000, n_gauss=6, grid=(8,) * 4, rank=(6,) * 4,
+                              degree=(7,) * 4, interp_fraction=0.3, n_samples=8000, dtype=np.float32,
+                              lo=(-1.0, -1.0, -1.0, 0.0), hi=(1.0, 1.0, 1.0, 2.0))
+    eps = 0.2
+    T = pipeline.compress(w.pts.astype(np.float64), w.vals.astype(np.float64), w.lo, w.hi, w.grid, (1,) * 4,
+                          w.degree, w.interp_fraction, w.seed).info["grid_tensor"]
+    r = tuple(min(a, 6) for a in ranks_for_precision(T, eps))
+    print(f"fit4 fp32 eps={eps} ranks={r}", flush=True)
+    p = fst.make_params_d(d=4, dtype=fst.FST_F32, lo=w.lo, hi=w.hi, grid=w.grid, rank=w.rank, degree=w.degree,
+                          interp_fraction=w.interp_fraction, n_samples=w.n_samples, seed=w.seed, eps=eps)
+    c = [D(a, dev) for a in w.soa()]
+    gm = fst.fst_fit_d(p, c[:4], c[4])
+    assert gm.info()["rank"] == r
+    mo = pipeline.fit(w.pts.astype(np.float64), w.vals.astype(np.float64), w.lo, w.hi, w.grid, r, w.degree,
+                      w.interp_fraction, w.n_samples, w.seed)
+    assert rel_l2(gm.core, mo.core) <= 1e-4

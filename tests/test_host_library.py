@@ -309,3 +309,86 @@ def test_three_way_calls_reject_four_way_models():
     # the d-way calls reject a null coordinate list before touching the device
     st = fst._fn["fst_eval_d"](m.handle, fst.FST_F64, 10, None, None, None)
     assert st == fst.FST_E_INVAL
+
+
+def _workload4(n=6000, seed=8):
+    return datagen.make_workload("t4", seed=seed, n=n, n_gauss=6, grid=(8,) * 4, rank=(3, 3, 2, 2),
+                                 degree=(6,) * 4, interp_fraction=0.3, n_samples=1000, dtype=np.float64,
+                                 lo=(-1.0, -1.0, -1.0, 0.0), hi=(1.0, 1.0, 1.0, 2.0))
+
+
+def test_idw_four_dimensional_matches_oracle():
+    # the library's 4-D inverse-distance grid against the oracle's (exact kNN by a k-d tree),
+    # through Algorithm 1's grid tensor
+    w = _workload4()
+    grid = (6, 7, 5, 8)
+    p = fst.make_params_d(d=4, dtype=fst.FST_F64, lo=w.lo, hi=w.hi, grid=grid, rank=(1, 1, 1, 1),
+                          degree=(3,) * 4, interp_fraction=0.3, n_samples=1000, seed=w.seed)
+    coords, v = w.soa()[:4], w.soa()[4]
+    m = fst.fst_compress_host_d(p, coords, v)
+    mo = pipeline.compress(w.pts, w.vals, w.lo, w.hi, grid, (1, 1, 1, 1), (3,) * 4, 0.3, w.seed)
+    # rank (1,1,1,1): the core is the projection of the grid tensor on the leading singular
+    # vectors, so equal cores need equal grid tensors up to rounding
+    np.testing.assert_allclose(m.core, mo.core, rtol=1e-10)
+    T = mo.info["grid_tensor"]
+    assert T.shape == grid and np.isfinite(T).all()
+
+
+def test_compress_host_d_matches_oracle_four_way():
+    w = _workload4()
+    grid, rank, degree = (8, 8, 8, 8), (3, 3, 2, 2), (6, 6, 6, 6)
+    p = fst.make_params_d(d=4, dtype=fst.FST_F64, lo=w.lo, hi=w.hi, grid=grid, rank=rank, degree=degree,
+                          interp_fraction=0.3, n_samples=1000, seed=w.seed)
+    coords, v = w.soa()[:4], w.soa()[4]
+    m = fst.fst_compress_host_d(p, coords, v)
+    mo = pipeline.compress(w.pts, w.vals, w.lo, w.hi, grid, rank, degree, 0.3, w.seed)
+    assert m.info()["d"] == 4 and m.info()["rank"] == rank
+    np.testing.assert_allclose(m.core, mo.core, rtol=1e-8, atol=1e-9)
+    for k in range(4):
+        Ck, Co = m.coefs(k), mo.coefs[k]
+        np.testing.assert_array_equal(Ck != 0, Co != 0)
+        np.testing.assert_allclose(Ck, Co, rtol=1e-7, atol=1e-9)
+
+
+def test_compress_host_d_with_eps_ranks_matches_oracle():
+    w = _workload4()
+    grid, degree, caps, eps = (8, 8, 8, 8), (6, 6, 6, 6), (6, 6, 6, 6), 0.2
+    p = fst.make_params_d(d=4, dtype=fst.FST_F64, lo=w.lo, hi=w.hi, grid=grid, rank=caps, degree=degree,
+                          interp_fraction=0.3, n_samples=2000, seed=w.seed, eps=eps)
+    m = fst.fst_compress_host_d(p, w.soa()[:4], w.soa()[4])
+    T = pipeline.compress(w.pts, w.vals, w.lo, w.hi, grid, (1,) * 4, degree, 0.3, w.seed).info["grid_tensor"]
+    r = ranks_for_precision(T, eps)
+    assert all(1 <= r[k] <= caps[k] for k in range(4)), r
+    assert m.info()["rank"] == r
+    mo = pipeline.compress(w.pts, w.vals, w.lo, w.hi, grid, r, degree, 0.3, w.seed)
+    np.testing.assert_allclose(m.core, mo.core, rtol=1e-8, atol=1e-9)
+    Tt = tucker_full(mo.core, mo.info["factors"])
+    assert np.linalg.norm(T - Tt) <= eps * np.linalg.norm(T) * (1 + 1e-9)
+
+
+def test_compress_host_d_three_way_is_the_three_way_compress():
+    w = datagen.small_f64(n=6000, n_samples=1500)
+    grid, rank, degree = (16, 16, 16), (5, 4, 3), (9, 9, 9)
+    p3 = fst.make_params(dtype=fst.FST_F64, lo=w.lo, hi=w.hi, grid=grid, rank=rank, degree=degree,
+                         interp_fraction=0.2, n_samples=1500, seed=w.seed)
+    pd = fst.make_params_d(d=3, dtype=fst.FST_F64, lo=w.lo, hi=w.hi, grid=grid, rank=rank, degree=degree,
+                           interp_fraction=0.2, n_samples=1500, seed=w.seed)
+    x, y, z, v = w.soa()
+    a = fst.fst_compress_host(p3, x, y, z, v)
+    b = fst.fst_compress_host_d(pd, (x, y, z), v)
+    assert fst.fst_model_save(a) == fst.fst_model_save(b)
+
+
+def test_fit_params_d_validation():
+    ok = dict(d=4, dtype=fst.FST_F64, grid=(8,) * 4, rank=(2,) * 4, degree=(5,) * 4, n_samples=100)
+    assert fst.fst_fit_d_workspace_bytes(fst.make_params_d(**ok), 1000) > 0
+    for bad, status in [(dict(rank=(9, 2, 2, 2)), fst.FST_E_INVAL),          # rank > grid
+                        (dict(rank=(7, 1, 1, 1), grid=(8,) * 4), fst.FST_E_INVAL),  # rank > product of others
+                        (dict(n_samples=16), fst.FST_E_INVAL),               # M <= R
+                        (dict(degree=(40,) * 4), fst.FST_E_UNSUPPORTED)]:
+        p = fst.make_params_d(**{**ok, **bad})
+        assert fst._fn["fst_fit_d_workspace_bytes"](ctypes.byref(p), 1000) == 0
+    p = fst.make_params_d(**ok)
+    p.d = 5
+    h = ctypes.c_void_p()
+    assert fst._fn["fst_compress_host_d"](ctypes.byref(p), 10, None, None, ctypes.byref(h)) == fst.FST_E_UNSUPPORTED
