@@ -297,6 +297,64 @@ def run_batched(args):
     print(json.dumps(result), flush=True)
 
 
+def run_spacetime(dev):
+    """The 4-way (space-time) form: Algorithm 1 on the host threads (untimed), then Algorithm 2
+    (fst_refit_core_d: factor values of the 4 modes, design rows in 16384-row chunks, dense MFMA
+    Gram, FP64 Cholesky) and the 4-way reconstruction (fst_eval_d) timed on the GPU."""
+    import torch
+
+    import datagen
+    import paper_1907_05884_amd.binding as fst
+
+    w = datagen.spacetime_f32()
+    s = w.soa()
+    p = fst.make_params_d(d=4, dtype=fst.FST_F32, lo=w.lo, hi=w.hi, grid=w.grid, rank=w.rank, degree=w.degree,
+                          interp_fraction=w.interp_fraction, n_samples=w.n_samples, seed=w.seed)
+    t = time.perf_counter()
+    m0 = fst.fst_compress_host_d(p, s[:4], s[4])
+    t_host = time.perf_counter() - t
+    c = [torch.from_numpy(a).to(dev) for a in s]
+    N, M, R = w.n, w.n_samples, m0.R
+    ws = torch.empty(fst.fst_refit_core_d_workspace_bytes(m0, fst.FST_F32, M), dtype=torch.uint8, device=dev)
+    refit_s = []
+    gm = None
+    for i in range(3):   # one warm-up call, two timed
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        gm = fst.fst_refit_core_d(m0, c[:4], c[4], M, w.seed, ws=ws)
+        torch.cuda.synchronize()
+        if i:
+            refit_s.append(time.perf_counter() - t0)
+    del ws
+    out = torch.empty(N, dtype=torch.float32, device=dev)
+    stream = torch.cuda.current_stream()
+    eval_ms = []
+    for i in range(4):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        fst.fst_eval_d(gm, c[:4], out=out)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        if i:
+            eval_ms.append(e0.elapsed_time(e1))
+    f = out.cpu().numpy().astype(np.float64)
+    vals = s[4].astype(np.float64)
+    t_refit = float(np.median(refit_s))
+    t_eval = float(np.median(eval_ms)) / 1e3
+    log(f"[bench] space-time: host {t_host:.2f} s, refit {t_refit * 1e3:.1f} ms, eval {t_eval * 1e3:.2f} ms")
+    return {
+        "what": "4-way models (d = 4): Algorithm 1 on host threads, then fst_refit_core_d (FP32 design rows in "
+                "16384-row chunks, dense FP32 MFMA Gram with FP64 accumulation, FP64 Cholesky) and fst_eval_d",
+        "workload": f"spacetime_f32: N={N} FP32 points in [-1,1]^3 x [0,1], 40 4-D Gaussians x sinusoid + "
+                    f"N(0,1e-3) noise; 5% interpolated (IDW-8) to a {w.grid[0]}^4 grid; ranks "
+                    f"{'x'.join(str(r) for r in m0.rank)} (R={R}); degree 31; M={M} sampled rows; reconstruct all N",
+        "host_steps_s": t_host, "refit_ms": t_refit * 1e3, "fitcore_rows_per_s": M / t_refit,
+        "gram_flops": float(M) * R * (R + 1), "cholesky_flops": float(R) ** 3 / 3,
+        "eval_ms": t_eval * 1e3, "reconstructed_points_per_s": N / t_eval,
+        "data_rel_l2": float(np.linalg.norm(f - vals) / np.linalg.norm(vals)),
+        "nnz": m0.info()["nnz"]}
+
+
 def run_copy(args):
     """Calibration of the HBM traffic counters: a plain device-to-device copy of a known
     size (1 GiB read, 1 GiB written per launch).  FETCH_SIZE and WRITE_SIZE of this launch
@@ -329,6 +387,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-spacetime", action="store_true", help="skip the 4-way (space-time) measurement")
     ap.add_argument("--cpu-sample-rows", type=int, default=4096)
     ap.add_argument("--n", type=int, default=2_000_000)
     ap.add_argument("--samples", type=int, default=200_000)
@@ -502,6 +561,8 @@ def main():
         n_pad *= 2
     log(f"[bench] mixed refit: {t_mix * 1e3:.1f} ms, data rel-L2 {np.sqrt(sm_err / sm_v):.4e}")
 
+    spacetime = None if args.no_spacetime else run_spacetime(dev)
+
     avg = {k: float(np.mean(vv)) for k, vv in times.items()}
     t_rows = avg["k1"] + avg["gram"] + avg["atv"]
     design_rows_per_s = M / t_rows
@@ -553,6 +614,7 @@ def main():
             "ms": t_mix * 1e3, "mixed_rows_per_s": M / t_mix, "rows_transformed": n_pad,
             "transform_bytes": float(R + 1) * 2 * n_pad * 4,
             "data_rel_l2": float(np.sqrt(sm_err / sm_v)), "data_rel_l2_unmixed": eps_data},
+        "spacetime": spacetime,
         "roofline": {"kernel": "k_gram<float>" if args.precision == "f32" else f"k_gram_lp<{args.precision}>",
                      "bound": "mfma", "achieved": achieved / 1e12,
                      "peak": peak / 1e12, "unit": "TFLOP/s", "frac": achieved / peak,
