@@ -28,7 +28,7 @@ def reference_coords(pts: np.ndarray, lo, hi) -> np.ndarray:
 
 
 def compress(pts, vals, lo, hi, grid, rank, degree, interp_fraction, seed,
-             idw_k: int = 8, idw_power: float = 2.0) -> Model:
+             idw_k: int = 8, idw_power: float = 2.0, solver: str = "omp") -> Model:
     """Algorithm 1: interpolate a random subset onto the grid, ST-HOSVD at fixed ranks,
     then a sparse Legendre fit of every singular vector.  The returned model carries the
     ST-HOSVD core alpha_0.  The number of modes d (3 or 4) is len(grid)."""
@@ -38,15 +38,15 @@ def compress(pts, vals, lo, hi, grid, rank, degree, interp_fraction, seed,
     xi = reference_coords(pts[sub], lo, hi)
     T = idw_to_grid(xi, vals[sub], grid, k=idw_k, power=idw_power)
     core0, W, sig = st_hosvd(T, rank)
-    coefs = [fit_factor(W[k], grid_nodes(grid[k]), degree[k]) for k in range(len(grid))]
+    coefs = [fit_factor(W[k], grid_nodes(grid[k]), degree[k], solver) for k in range(len(grid))]
     return Model(tuple(lo), tuple(hi), tuple(rank), tuple(degree), core0, coefs,
                  info={"grid_tensor": T, "factors": W, "sigmas": sig, "subset": sub})
 
 
 def fit(pts, vals, lo, hi, grid, rank, degree, interp_fraction, n_samples, seed,
-        idw_k: int = 8, idw_power: float = 2.0) -> Model:
+        idw_k: int = 8, idw_power: float = 2.0, solver: str = "omp") -> Model:
     """Algorithm 1 then Algorithm 2 (uniformly sampled rows, normal equations)."""
-    m = compress(pts, vals, lo, hi, grid, rank, degree, interp_fraction, seed, idw_k, idw_power)
+    m = compress(pts, vals, lo, hi, grid, rank, degree, interp_fraction, seed, idw_k, idw_power, solver)
     alpha, idx, G, h = refit_core(m, np.asarray(pts, np.float64), vals, n_samples, seed)
     out = m.with_core(alpha)
     out.info.update({"core0": m.core, "ls_rows": idx})

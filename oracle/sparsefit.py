@@ -62,12 +62,16 @@ def omp_loo(Phi: np.ndarray, z: np.ndarray, tol: float = 1e-14):
     return np.asarray(support[: best + 1], dtype=np.int64), coefs[best], press
 
 
-def fit_factor(W: np.ndarray, nodes: np.ndarray, p: int) -> np.ndarray:
-    """Sparse coefficient matrix C (p+1, r) with W[:, j] ~ Phi(nodes) @ C[:, j]."""
+def fit_factor(W: np.ndarray, nodes: np.ndarray, p: int, solver: str = "omp") -> np.ndarray:
+    """Sparse coefficient matrix C (p+1, r) with W[:, j] ~ Phi(nodes) @ C[:, j]; solver "omp"
+    (this module) or "lars" (Lasso-LARS path of ``oracle.lars``), both with leave-one-out
+    selection."""
+    from .lars import lars_loo
+    fit = {"omp": omp_loo, "lars": lars_loo}[solver]
     Phi = legendre_orthonormal(nodes, p)
     C = np.zeros((p + 1, W.shape[1]), dtype=np.float64)
     for j in range(W.shape[1]):
-        S, c, _ = omp_loo(Phi, W[:, j])
+        S, c, _ = fit(Phi, W[:, j])
         C[S, j] = c
     return C
 
