@@ -58,6 +58,10 @@ typedef int32_t fst_status;
 #define FST_GRAM_F16  3   /* FP16 rows (scaled), FP16 MFMA, FP32 accumulation folded into FP64 */
 
 /* random streams: state = seed * 256 + stream (SplitMix64) */
+/* sparse solver of the singular-vector fits (Sec. 3, 4.2), both with leave-one-out selection */
+#define FST_SOLVER_OMP  0   /* orthogonal matching pursuit */
+#define FST_SOLVER_LARS 1   /* Lasso-modified least angle regression (the paper's solver) */
+
 #define FST_STREAM_INTERP 1
 #define FST_STREAM_LS     2
 
@@ -82,6 +86,7 @@ typedef struct {
   double   eps;              /* > 0: ST-HOSVD ranks chosen from this compression precision
                                 (Sec. 4.1, Table 1; fst_sthosvd_eps), with rank[] as caps;
                                 0: the fixed ranks rank[] */
+  int32_t  sparse_solver;    /* FST_SOLVER_OMP (default) or FST_SOLVER_LARS (Sec. 3, 4.2) */
 } fst_fit_params;
 
 /* ------------------------------------------------------------------ library */
@@ -279,6 +284,13 @@ fst_status fst_sthosvd_eps(const double* T, const int32_t dims[3], double eps,
  * row-major (zeros off the support). */
 fst_status fst_sparse_fit(const double* W, int32_t I, int32_t r, int32_t p, double* C);
 
+/* The same fit with the Lasso-modified LARS path (Efron et al.) on the unit-norm columns of
+ * the basis matrix instead of OMP: every active set of the path (after each entry or exit) is
+ * refitted by least squares and scored by its leave-one-out error, and the first set with the
+ * smallest error is kept (entry ties to the lowest index; a column that has just left is not
+ * re-admitted in the next step; at most min(p + 1, I - 2) active columns). */
+fst_status fst_sparse_fit_lars(const double* W, int32_t I, int32_t r, int32_t p, double* C);
+
 /* ------------------------------------------------------------------ model */
 
 /* Builds a model from its parts.  lo, hi: host double[3]; rank, degree: host int32[3];
@@ -372,6 +384,7 @@ typedef struct {
   uint64_t seed;
   int32_t  n_threads;
   double   eps;              /* > 0: ranks from this precision (Sec. 4.1), threshold eps^2 ||T||^2 / d */
+  int32_t  sparse_solver;    /* FST_SOLVER_OMP or FST_SOLVER_LARS */
 } fst_fit_params_d;
 
 /* Fills defaults for d modes (grid 16, ranks 4, degree 15, fraction 0.1, idw 8 / 2.0, ...). */

@@ -27,6 +27,7 @@ FST_E_INVAL, FST_E_NOMEM, FST_E_DEVICE, FST_E_NOT_SPD, FST_E_UNSUPPORTED, FST_E_
 FST_F64, FST_F32 = 0, 1
 FST_GRAM_F64, FST_GRAM_F32, FST_GRAM_BF16, FST_GRAM_F16 = 0, 1, 2, 3
 FST_STREAM_INTERP, FST_STREAM_LS = 1, 2
+FST_SOLVER_OMP, FST_SOLVER_LARS = 0, 1
 
 _STATUS_NAMES = {-1: "FST_E_INVAL", -2: "FST_E_NOMEM", -3: "FST_E_DEVICE", -4: "FST_E_NOT_SPD",
                  -5: "FST_E_UNSUPPORTED", -6: "FST_E_FORMAT"}
@@ -44,7 +45,8 @@ class fst_fit_params(C.Structure):
                 ("grid", C.c_int32 * 3), ("rank", C.c_int32 * 3), ("degree", C.c_int32 * 3),
                 ("interp_fraction", C.c_double), ("idw_k", C.c_int32), ("idw_power", C.c_double),
                 ("n_samples", C.c_int64), ("seed", C.c_uint64), ("gram_prec", C.c_int32),
-                ("refine_steps", C.c_int32), ("n_threads", C.c_int32), ("eps", C.c_double)]
+                ("refine_steps", C.c_int32), ("n_threads", C.c_int32), ("eps", C.c_double),
+                ("sparse_solver", C.c_int32)]
 
 
 class fst_fit_params_d(C.Structure):
@@ -52,7 +54,8 @@ class fst_fit_params_d(C.Structure):
                 ("lo", C.c_double * 4), ("hi", C.c_double * 4),
                 ("grid", C.c_int32 * 4), ("rank", C.c_int32 * 4), ("degree", C.c_int32 * 4),
                 ("interp_fraction", C.c_double), ("idw_k", C.c_int32), ("idw_power", C.c_double),
-                ("n_samples", C.c_int64), ("seed", C.c_uint64), ("n_threads", C.c_int32), ("eps", C.c_double)]
+                ("n_samples", C.c_int64), ("seed", C.c_uint64), ("n_threads", C.c_int32), ("eps", C.c_double),
+                ("sparse_solver", C.c_int32)]
 
 
 _vp, _i64, _i32, _dp = C.c_void_p, C.c_int64, C.c_int32, C.POINTER(C.c_double)
@@ -106,6 +109,7 @@ _lib_fns = dict(
     fst_sthosvd=(_i32, _vp, _vp, _vp, _i32, _vp, _vp, _vp),
     fst_sthosvd_eps=(_i32, _vp, _vp, C.c_double, _vp, _i32, _vp, _vp, _vp, _vp),
     fst_sparse_fit=(_i32, _vp, _i32, _i32, _i32, _vp),
+    fst_sparse_fit_lars=(_i32, _vp, _i32, _i32, _i32, _vp),
     fst_model_from_parts=(_i32, _vp, _vp, _vp, _vp, _vp, _vp, C.POINTER(_vp)),
     fst_model_from_parts_d=(_i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp, C.POINTER(_vp)),
     fst_model_info_d=(_i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp),
@@ -203,7 +207,8 @@ def _workspace(nbytes: int, device):
 
 def make_params(dtype=FST_F64, lo=(-1.0,) * 3, hi=(1.0,) * 3, grid=(32,) * 3, rank=(8,) * 3,
                 degree=(15,) * 3, interp_fraction=0.10, idw_k=8, idw_power=2.0, n_samples=2000,
-                seed=1, gram_prec=None, refine_steps=0, n_threads=0, eps=0.0) -> fst_fit_params:
+                seed=1, gram_prec=None, refine_steps=0, n_threads=0, eps=0.0,
+                sparse_solver=FST_SOLVER_OMP) -> fst_fit_params:
     p = fst_fit_params()
     _fn["fst_fit_params_default"](C.byref(p))
     p.dtype = dtype
@@ -221,12 +226,13 @@ def make_params(dtype=FST_F64, lo=(-1.0,) * 3, hi=(1.0,) * 3, grid=(32,) * 3, ra
     p.refine_steps = int(refine_steps)
     p.n_threads = int(n_threads)
     p.eps = float(eps)
+    p.sparse_solver = int(sparse_solver)
     return p
 
 
 def make_params_d(d=4, dtype=FST_F64, lo=None, hi=None, grid=None, rank=None, degree=None,
                   interp_fraction=0.10, idw_k=8, idw_power=2.0, n_samples=2000, seed=1, n_threads=0,
-                  eps=0.0) -> fst_fit_params_d:
+                  eps=0.0, sparse_solver=FST_SOLVER_OMP) -> fst_fit_params_d:
     p = fst_fit_params_d()
     _fn["fst_fit_params_d_default"](C.byref(p), int(d))
     p.dtype = dtype
@@ -246,6 +252,7 @@ def make_params_d(d=4, dtype=FST_F64, lo=None, hi=None, grid=None, rank=None, de
     p.seed = int(seed)
     p.n_threads = int(n_threads)
     p.eps = float(eps)
+    p.sparse_solver = int(sparse_solver)
     return p
 
 
@@ -733,11 +740,12 @@ def fst_sthosvd_eps(T, eps: float, max_rank, n_threads=0):
     return r, core, W, S
 
 
-def fst_sparse_fit(W, p: int) -> np.ndarray:
+def fst_sparse_fit(W, p: int, solver: int = FST_SOLVER_OMP) -> np.ndarray:
     W_a, W_p = _host(W, np.float64)
     I, r = W_a.shape
     out = np.empty((int(p) + 1, r), dtype=np.float64)
-    _check(_fn["fst_sparse_fit"](W_p, int(I), int(r), int(p), out.ctypes.data_as(C.c_void_p)))
+    name = "fst_sparse_fit_lars" if solver == FST_SOLVER_LARS else "fst_sparse_fit"
+    _check(_fn[name](W_p, int(I), int(r), int(p), out.ctypes.data_as(C.c_void_p)))
     return out
 
 

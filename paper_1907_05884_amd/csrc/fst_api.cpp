@@ -77,6 +77,8 @@ static void validate_params(const fst_fit_params* p, int64_t n) {
   if (llround(p->interp_fraction * (double)n) < 1) fail(FST_E_INVAL, "interpolation subset is empty");
   if (p->refine_steps < 0 || p->refine_steps > 100) fail(FST_E_INVAL, "refine_steps must be in [0, 100]");
   if (!(p->eps >= 0.0 && p->eps < 1.0)) fail(FST_E_INVAL, "eps must be in [0, 1)");
+  if (p->sparse_solver != FST_SOLVER_OMP && p->sparse_solver != FST_SOLVER_LARS)
+    fail(FST_E_INVAL, "sparse_solver must be FST_SOLVER_OMP or FST_SOLVER_LARS");
 }
 
 // --------------------------------------------------------------------------- refit layout
@@ -382,7 +384,8 @@ static fst_model* compress_from_subset(const fst_fit_params* p, const std::vecto
   }
   std::unique_ptr<fst_model> m(model_new(p->lo, p->hi, rank, p->degree));
   std::copy(core.begin(), core.begin() + (size_t)rank[0] * rank[1] * rank[2], m->core.begin());
-  for (int k = 0; k < 3; ++k) sparse_fit(W[k].data(), p->grid[k], rank[k], p->degree[k], m->coef[k].data());
+  for (int k = 0; k < 3; ++k)
+    sparse_fit_with(p->sparse_solver, W[k].data(), p->grid[k], rank[k], p->degree[k], m->coef[k].data());
   return m.release();
 }
 
@@ -448,6 +451,8 @@ static void validate_params_d(const fst_fit_params_d* p, int64_t n) {
     fail(FST_E_INVAL, "Algorithm 2 needs r1 .. rd < n_samples <= n (more sampled rows than core entries)");
   if (llround(p->interp_fraction * (double)n) < 1) fail(FST_E_INVAL, "interpolation subset is empty");
   if (!(p->eps >= 0.0 && p->eps < 1.0)) fail(FST_E_INVAL, "eps must be in [0, 1)");
+  if (p->sparse_solver != FST_SOLVER_OMP && p->sparse_solver != FST_SOLVER_LARS)
+    fail(FST_E_INVAL, "sparse_solver must be FST_SOLVER_OMP or FST_SOLVER_LARS");
 }
 
 // Algorithm 1 for D modes from the gathered subset (host FP64, K x (D + 1): coordinates, value)
@@ -502,7 +507,8 @@ static fst_model* compress_from_subset_d(const fst_fit_params_d* p, const std::v
   }
   std::unique_ptr<fst_model> m(model_new_d(D, p->lo, p->hi, rank, p->degree));
   std::copy(core.begin(), core.begin() + (size_t)m->R(), m->core.begin());
-  for (int k = 0; k < D; ++k) sparse_fit(W[k].data(), p->grid[k], rank[k], p->degree[k], m->coef[k].data());
+  for (int k = 0; k < D; ++k)
+    sparse_fit_with(p->sparse_solver, W[k].data(), p->grid[k], rank[k], p->degree[k], m->coef[k].data());
   return m.release();
 }
 
@@ -941,6 +947,15 @@ fst_status fst_sparse_fit(const double* W, int32_t I, int32_t r, int32_t p, doub
   set_last_error("");
   if (!W || !C) fail(FST_E_INVAL, "null argument");
   sparse_fit(W, I, r, p, C);
+  return FST_OK;
+  FST_CATCH
+}
+
+fst_status fst_sparse_fit_lars(const double* W, int32_t I, int32_t r, int32_t p, double* C) {
+  FST_TRY
+  set_last_error("");
+  if (!W || !C) fail(FST_E_INVAL, "null argument");
+  sparse_fit_lars(W, I, r, p, C);
   return FST_OK;
   FST_CATCH
 }

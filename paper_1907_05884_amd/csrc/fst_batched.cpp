@@ -124,7 +124,9 @@ fst_status fst_fit_batched(const fst_fit_params* base, int32_t V, const int32_t*
               Wp[k] = W[k].data();
             }
             fst::sthosvd(T.data(), p.grid, p.rank, 1, m->core.data(), Wp, nullptr);
-            for (int k = 0; k < 3; ++k) fst::sparse_fit(W[k].data(), p.grid[k], p.rank[k], p.degree[k], m->coef[k].data());
+            for (int k = 0; k < 3; ++k)
+              fst::sparse_fit_with(p.sparse_solver, W[k].data(), p.grid[k], p.rank[k], p.degree[k],
+                                   m->coef[k].data());
             m0[(size_t)v] = std::move(m);
           } catch (const std::exception& e) {
             errs[(size_t)v] = e.what();

@@ -619,6 +619,191 @@ void ls_select(const std::vector<double>& Phi, int I, int n, const std::vector<i
 }
 }  // namespace
 
+namespace {
+// Lasso-modified least angle regression (Efron, Hastie, Johnstone, Tibshirani 2004) on the
+// unit-norm columns X (I x n, row-major): the active set after every event of the path, in
+// entry order.  Per step, with s the signs of the active correlations: G = (X_A S)^T (X_A S),
+// A_A = (1^T G^-1 1)^(-1/2), w = A_A G^-1 1, u = X_A S w, a = X^T u; the path moves by the
+// smaller of the first entry of an inactive column (correlation reaching C) and the first
+// sign change of an active coefficient (Lasso modification: that column leaves).  Entry ties
+// go to the lowest index; a column that has just left is not re-admitted in the next step;
+// the path stops at max_active columns, when the correlations vanish, or at its end.
+std::vector<std::vector<int>> lars_active_sets(const std::vector<double>& X, int I, int n, const double* z,
+                                               int max_active) {
+  std::vector<std::vector<int>> sets;
+  std::vector<double> beta((size_t)n, 0.0), mu((size_t)I, 0.0), c((size_t)n), u((size_t)I), a((size_t)n);
+  auto correlations = [&]() {
+    for (int j = 0; j < n; ++j) {
+      double t = 0.0;
+      for (int i = 0; i < I; ++i) t += X[(size_t)i * n + j] * (z[i] - mu[(size_t)i]);
+      c[(size_t)j] = t;
+    }
+  };
+  correlations();
+  int j0 = 0;
+  for (int j = 1; j < n; ++j)
+    if (std::fabs(c[(size_t)j]) > std::fabs(c[(size_t)j0])) j0 = j;
+  const double C0 = n > 0 ? std::fabs(c[(size_t)j0]) : 0.0;
+  if (C0 == 0.0 || max_active < 1) return sets;
+  std::vector<int> A{j0};
+  sets.push_back(A);
+  int barred = -1;
+  for (int it = 0; it < 64 * n; ++it) {
+    correlations();
+    const int k = (int)A.size();
+    double C = 0.0;
+    std::vector<double> sg((size_t)k);
+    for (int q = 0; q < k; ++q) {
+      const double cq = c[(size_t)A[(size_t)q]];
+      sg[(size_t)q] = cq > 0 ? 1.0 : (cq < 0 ? -1.0 : 0.0);
+      C = std::max(C, std::fabs(cq));
+    }
+    if (C <= 1e-14 * C0) break;
+    // G g1 = 1 by Cholesky (G is the Gram of linearly independent signed columns)
+    std::vector<double> L((size_t)k * k, 0.0), g1((size_t)k, 1.0);
+    for (int q = 0; q < k; ++q)
+      for (int t = 0; t <= q; ++t) {
+        double g = 0.0;
+        for (int i = 0; i < I; ++i) g += X[(size_t)i * n + A[(size_t)q]] * X[(size_t)i * n + A[(size_t)t]];
+        g *= sg[(size_t)q] * sg[(size_t)t];
+        for (int l = 0; l < t; ++l) g -= L[(size_t)q * k + l] * L[(size_t)t * k + l];
+        if (q == t) {
+          if (!(g > 0.0)) return sets;   // numerically dependent active columns: end of the path
+          L[(size_t)q * k + q] = std::sqrt(g);
+        } else {
+          L[(size_t)q * k + t] = g / L[(size_t)t * k + t];
+        }
+      }
+    for (int q = 0; q < k; ++q) {
+      double t = g1[(size_t)q];
+      for (int l = 0; l < q; ++l) t -= L[(size_t)q * k + l] * g1[(size_t)l];
+      g1[(size_t)q] = t / L[(size_t)q * k + q];
+    }
+    for (int q = k - 1; q >= 0; --q) {
+      double t = g1[(size_t)q];
+      for (int l = q + 1; l < k; ++l) t -= L[(size_t)l * k + q] * g1[(size_t)l];
+      g1[(size_t)q] = t / L[(size_t)q * k + q];
+    }
+    double sum1 = 0.0;
+    for (double t : g1) sum1 += t;
+    const double AA = 1.0 / std::sqrt(sum1);
+    std::vector<double> w((size_t)k);
+    for (int q = 0; q < k; ++q) w[(size_t)q] = AA * g1[(size_t)q];
+    for (int i = 0; i < I; ++i) {
+      double t = 0.0;
+      for (int q = 0; q < k; ++q) t += X[(size_t)i * n + A[(size_t)q]] * sg[(size_t)q] * w[(size_t)q];
+      u[(size_t)i] = t;
+    }
+    for (int j = 0; j < n; ++j) {
+      double t = 0.0;
+      for (int i = 0; i < I; ++i) t += X[(size_t)i * n + j] * u[(size_t)i];
+      a[(size_t)j] = t;
+    }
+    double gamma_hat = C / AA;
+    int j_hat = -1;
+    for (int j = 0; j < n; ++j) {
+      if (j == barred || std::find(A.begin(), A.end(), j) != A.end()) continue;
+      const double num[2] = {C - c[(size_t)j], C + c[(size_t)j]}, den[2] = {AA - a[(size_t)j], AA + a[(size_t)j]};
+      for (int e = 0; e < 2; ++e) {
+        if (den[e] == 0.0) continue;
+        const double g = num[e] / den[e];
+        if (g > 0.0 && g < gamma_hat) {
+          gamma_hat = g;
+          j_hat = j;
+        }
+      }
+    }
+    double gamma_til = std::numeric_limits<double>::infinity();
+    int k_til = -1;
+    for (int q = 0; q < k; ++q) {
+      const double d = sg[(size_t)q] * w[(size_t)q];
+      if (d == 0.0) continue;
+      const double g = -beta[(size_t)A[(size_t)q]] / d;
+      if (g > 0.0 && g < gamma_til) {
+        gamma_til = g;
+        k_til = q;
+      }
+    }
+    const bool drop = gamma_til < gamma_hat;
+    const double gamma = drop ? gamma_til : gamma_hat;
+    for (int i = 0; i < I; ++i) mu[(size_t)i] += gamma * u[(size_t)i];
+    for (int q = 0; q < k; ++q) beta[(size_t)A[(size_t)q]] += gamma * sg[(size_t)q] * w[(size_t)q];
+    barred = -1;
+    if (drop) {
+      const int j_out = A[(size_t)k_til];
+      beta[(size_t)j_out] = 0.0;
+      A.erase(A.begin() + k_til);
+      barred = j_out;
+      sets.push_back(A);
+      continue;
+    }
+    if (j_hat < 0) {   // end of the path: every correlation reached zero
+      sets.push_back(A);
+      break;
+    }
+    if ((int)A.size() >= max_active) break;
+    A.push_back(j_hat);
+    sets.push_back(A);
+  }
+  return sets;
+}
+}  // namespace
+
+void sparse_fit_lars(const double* W, int I, int r, int p, double* C) {
+  if (I < 3 || r < 1 || p < 0) fail(FST_E_INVAL, "sparse_fit: need I >= 3, r >= 1, p >= 0");
+  const int n = p + 1;
+  std::vector<double> Phi((size_t)I * n), X((size_t)I * n);
+  for (int i = 0; i < I; ++i) legendre_orthonormal_host(-1.0 + 2.0 * i / (I - 1), p, &Phi[(size_t)i * n]);
+  for (int m = 0; m < n; ++m) {
+    double s2 = 0;
+    for (int i = 0; i < I; ++i) s2 += Phi[(size_t)i * n + m] * Phi[(size_t)i * n + m];
+    const double nm = std::sqrt(s2);
+    for (int i = 0; i < I; ++i) X[(size_t)i * n + m] = Phi[(size_t)i * n + m] / nm;
+  }
+  std::fill(C, C + (size_t)n * r, 0.0);
+  std::vector<double> z((size_t)I), res, lev, c;
+  for (int j = 0; j < r; ++j) {
+    for (int i = 0; i < I; ++i) z[(size_t)i] = W[(size_t)i * r + j];
+    double zn = 0;
+    for (double t : z) zn += t * t;
+    zn = std::sqrt(zn);
+    if (zn == 0.0) continue;
+    const std::vector<std::vector<int>> sets = lars_active_sets(X, I, n, z.data(), std::min(n, I - 2));
+    // every active set of the path refitted by least squares and scored by PRESS
+    std::vector<std::vector<double>> coefs;
+    std::vector<double> press;
+    size_t used = 0;
+    for (const std::vector<int>& S : sets) {
+      if (S.empty()) {
+        ++used;
+        press.push_back(std::numeric_limits<double>::infinity());
+        coefs.emplace_back();
+        continue;
+      }
+      ls_select(Phi, I, n, S, z.data(), c, res, lev);
+      double pr = 0.0;
+      for (int i = 0; i < I; ++i) {
+        const double e = res[(size_t)i] / (1.0 - lev[(size_t)i]);
+        pr += e * e;
+      }
+      pr /= I;
+      if (!(pr == pr)) pr = std::numeric_limits<double>::infinity();
+      press.push_back(pr);
+      coefs.push_back(c);
+      ++used;
+      double rn = 0;
+      for (double t2 : res) rn += t2 * t2;
+      if (std::sqrt(rn) <= 1e-14 * zn) break;
+    }
+    if (used == 0) continue;
+    size_t tb = 0;
+    for (size_t t = 1; t < press.size(); ++t)
+      if (press[t] < press[tb]) tb = t;
+    const std::vector<int>& S = sets[tb];
+    for (size_t l = 0; l < S.size(); ++l) C[(size_t)S[l] * r + j] = coefs[tb][l];
+  }
+}
+
 void sparse_fit(const double* W, int I, int r, int p, double* C) {
   if (I < 3 || r < 1 || p < 0) fail(FST_E_INVAL, "sparse_fit: need I >= 3, r >= 1, p >= 0");
   const int n = p + 1;

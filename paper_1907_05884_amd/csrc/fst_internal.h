@@ -98,6 +98,14 @@ void sthosvd_d(const double* T, int D, const int32_t* dims, const int32_t* rank,
 void sthosvd_eps_d(const double* T, int D, const int32_t* dims, double eps, const int32_t* max_rank, int n_threads,
                    int32_t* rank_out, double* core, double* const* W, double* const* sigma);
 void sparse_fit(const double* W, int I, int r, int p, double* C);
+void sparse_fit_lars(const double* W, int I, int r, int p, double* C);
+// the sparse fit of one factor matrix with the chosen solver (FST_SOLVER_*)
+inline void sparse_fit_with(int solver, const double* W, int I, int r, int p, double* C) {
+  if (solver == FST_SOLVER_LARS)
+    sparse_fit_lars(W, I, r, p, C);
+  else
+    sparse_fit(W, I, r, p, C);
+}
 void legendre_orthonormal_host(double t, int p, double* phi);
 int hardware_threads(int requested);
 

@@ -275,6 +275,22 @@ def test_fit_end_to_end_fp64(dev):
     assert abs(err_gpu - err_ref) <= 1e-8 * err_ref + 1e-12
 
 
+def test_fit_end_to_end_lars_fp64(dev):
+    # Algorithm 1 with the paper's sparse solver (Lasso-LARS + leave-one-out), then Algorithm 2
+    w = datagen.small_f64()
+    mo = pipeline.fit(w.pts, w.vals, w.lo, w.hi, w.grid, w.rank, w.degree, w.interp_fraction,
+                      w.n_samples, w.seed, solver="lars")
+    p = fst.make_params(dtype=fst.FST_F64, lo=w.lo, hi=w.hi, grid=w.grid, rank=w.rank, degree=w.degree,
+                        interp_fraction=w.interp_fraction, n_samples=w.n_samples, seed=w.seed,
+                        sparse_solver=fst.FST_SOLVER_LARS)
+    x, y, z, v = [D(a, dev) for a in w.soa()]
+    gm = fst.fst_fit(p, x, y, z, v)
+    for k in range(3):
+        np.testing.assert_array_equal(gm.coefs(k) != 0, mo.coefs[k] != 0)
+        assert rel_l2(gm.coefs(k), mo.coefs[k]) <= 1e-7
+    assert rel_l2(gm.core, mo.core) <= 1e-6
+
+
 def test_fit_with_ranks_from_precision(dev):
     # Algorithm 1 with ranks chosen from eps (Sec. 4.1, Table 1), then Algorithm 2: the ranks
     # the oracle's rule picks on its interpolated grid, and the oracle's fit at those ranks

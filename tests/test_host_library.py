@@ -392,3 +392,60 @@ def test_fit_params_d_validation():
     p.d = 5
     h = ctypes.c_void_p()
     assert fst._fn["fst_compress_host_d"](ctypes.byref(p), 10, None, None, ctypes.byref(h)) == fst.FST_E_UNSUPPORTED
+
+
+def test_sparse_fit_lars_matches_oracle():
+    nodes = interp.grid_nodes(32)
+    rng = np.random.default_rng(1)
+    Phi = legendre_orthonormal(nodes, 15)
+    c = np.zeros((16, 5))
+    c[[0, 3, 7], 0] = [1.0, -0.5, 0.25]
+    c[[2], 1] = [2.0]
+    W = Phi @ c
+    W[:, 2] = np.sin(3 * nodes)
+    W[:, 3] = np.exp(-nodes ** 2) + 1e-3 * rng.standard_normal(32)
+    W[:, 4] = np.tanh(8 * nodes) + 1e-2 * rng.standard_normal(32)
+    ref = sparsefit.fit_factor(W, nodes, 15, solver="lars")
+    got = fst.fst_sparse_fit(W, 15, solver=fst.FST_SOLVER_LARS)
+    np.testing.assert_array_equal(got != 0, ref != 0)      # identical supports
+    np.testing.assert_allclose(got, ref, rtol=1e-9, atol=1e-12)
+    np.testing.assert_allclose(got[:, :2], c[:, :2], atol=1e-12)
+
+
+def test_sparse_fit_lars_on_singular_vectors_matches_oracle():
+    # the factor matrices of Algorithm 1 on the small workload: real singular vectors
+    w = datagen.small_f64(n=6000, n_samples=1500)
+    mo = pipeline.compress(w.pts, w.vals, w.lo, w.hi, (16, 16, 16), (6, 5, 4), (9, 9, 9), 0.2, w.seed)
+    for k in range(3):
+        Wk = mo.info["factors"][k]
+        ref = sparsefit.fit_factor(Wk, interp.grid_nodes(16), 9, solver="lars")
+        got = fst.fst_sparse_fit(Wk, 9, solver=fst.FST_SOLVER_LARS)
+        np.testing.assert_array_equal(got != 0, ref != 0)
+        np.testing.assert_allclose(got, ref, rtol=1e-8, atol=1e-11)
+
+
+def test_compress_host_with_lars_matches_oracle():
+    w = datagen.small_f64(n=6000, n_samples=1500)
+    p = fst.make_params(dtype=fst.FST_F64, lo=w.lo, hi=w.hi, grid=(16, 16, 16), rank=(5, 4, 3),
+                        degree=(9, 9, 9), interp_fraction=0.2, n_samples=1500, seed=w.seed,
+                        sparse_solver=fst.FST_SOLVER_LARS)
+    m = fst.fst_compress_host(p, *w.soa())
+    mo = pipeline.compress(w.pts, w.vals, w.lo, w.hi, (16, 16, 16), (5, 4, 3), (9, 9, 9), 0.2, w.seed,
+                           solver="lars")
+    np.testing.assert_allclose(m.core, mo.core, rtol=1e-8, atol=1e-9)
+    for k in range(3):
+        np.testing.assert_array_equal(m.coefs(k) != 0, mo.coefs[k] != 0)
+        np.testing.assert_allclose(m.coefs(k), mo.coefs[k], rtol=1e-7, atol=1e-9)
+    # the 4-way compress takes the same solver
+    w4 = _workload4()
+    p4 = fst.make_params_d(d=4, dtype=fst.FST_F64, lo=w4.lo, hi=w4.hi, grid=(8,) * 4, rank=(3, 3, 2, 2),
+                           degree=(6,) * 4, interp_fraction=0.3, n_samples=1000, seed=w4.seed,
+                           sparse_solver=fst.FST_SOLVER_LARS)
+    m4 = fst.fst_compress_host_d(p4, w4.soa()[:4], w4.soa()[4])
+    mo4 = pipeline.compress(w4.pts, w4.vals, w4.lo, w4.hi, (8,) * 4, (3, 3, 2, 2), (6,) * 4, 0.3, w4.seed,
+                            solver="lars")
+    for k in range(4):
+        np.testing.assert_array_equal(m4.coefs(k) != 0, mo4.coefs[k] != 0)
+        np.testing.assert_allclose(m4.coefs(k), mo4.coefs[k], rtol=1e-7, atol=1e-9)
+    bad = fst.make_params(sparse_solver=7)
+    assert fst._fn["fst_fit_workspace_bytes"](ctypes.byref(bad), 10000) == 0
