@@ -19,19 +19,21 @@ from __future__ import annotations
 import numpy as np
 import scipy.linalg
 
-from .basis import legendre_orthonormal, to_reference
+from .basis import to_reference
 from .model import Model
 from .sampler import STREAM_LS, sample_without_replacement
+from .wavelets import mode_basis
 
 
 def factor_values(model: Model, pts: np.ndarray):
     """[U_k (m, r_k)] for k = 1..d: U_k[q, j] = w^(k)_j(y^q_k) = sum_i C_k[i, j] phi_i(xi^q_k)
-    (eq. (2)); pts has one column per mode."""
+    (eq. (2)) over the mode's basis (Legendre, plus wavelet details when the model has them);
+    pts has one column per mode."""
     pts = np.asarray(pts, dtype=np.float64)
     out = []
     for k in range(len(model.rank)):
         xi = to_reference(pts[:, k], model.lo[k], model.hi[k])
-        out.append(legendre_orthonormal(xi, model.degree[k]) @ model.coefs[k])
+        out.append(mode_basis(xi, model.degree[k], *model.mode_wavelet(k)) @ model.coefs[k])
     return out
 
 

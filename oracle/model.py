@@ -24,6 +24,12 @@ class Model:
     core: np.ndarray          # (r1, .., rd) float64; flattened in C order j = (j1 r2 + j2) r3 + j3 ..
     coefs: list               # [C_k (n_k, r_k) float64, zeros where not in the support]
     info: dict = field(default_factory=dict)
+    # per mode (s_k, q_k) of a wavelet space W_{s,q} held beside P_p (``oracle.wavelets``):
+    # C_k then has p_k + 1 + (q_k + 1)(2^s_k - 1) rows; () = Legendre only
+    wavelet: tuple = ()
+
+    def mode_wavelet(self, k: int):
+        return tuple(self.wavelet[k]) if self.wavelet else (0, 0)
 
     @property
     def R(self) -> int:
@@ -43,7 +49,7 @@ class Model:
     def with_core(self, core: np.ndarray) -> "Model":
         return Model(self.lo, self.hi, self.rank, self.degree,
                      np.asarray(core, np.float64).reshape(self.rank),
-                     [C.copy() for C in self.coefs], dict(self.info))
+                     [C.copy() for C in self.coefs], dict(self.info), self.wavelet)
 
 
 def to_csc(C: np.ndarray):

@@ -12,7 +12,7 @@ from .interp import grid_nodes, idw_to_grid
 from .lsq import refit_core
 from .model import Model
 from .sampler import STREAM_INTERP, sample_without_replacement
-from .sparsefit import fit_factor
+from .sparsefit import fit_factor, fit_factor_choice
 from .sthosvd import st_hosvd
 
 
@@ -28,7 +28,7 @@ def reference_coords(pts: np.ndarray, lo, hi) -> np.ndarray:
 
 
 def compress(pts, vals, lo, hi, grid, rank, degree, interp_fraction, seed,
-             idw_k: int = 8, idw_power: float = 2.0, solver: str = "omp") -> Model:
+             idw_k: int = 8, idw_power: float = 2.0, solver: str = "omp", wavelet=None) -> Model:
     """Algorithm 1: interpolate a random subset onto the grid, ST-HOSVD at fixed ranks,
     then a sparse Legendre fit of every singular vector.  The returned model carries the
     ST-HOSVD core alpha_0.  The number of modes d (3 or 4) is len(grid)."""
@@ -38,15 +38,22 @@ def compress(pts, vals, lo, hi, grid, rank, degree, interp_fraction, seed,
     xi = reference_coords(pts[sub], lo, hi)
     T = idw_to_grid(xi, vals[sub], grid, k=idw_k, power=idw_power)
     core0, W, sig = st_hosvd(T, rank)
-    coefs = [fit_factor(W[k], grid_nodes(grid[k]), degree[k], solver) for k in range(len(grid))]
+    if wavelet is None:
+        coefs = [fit_factor(W[k], grid_nodes(grid[k]), degree[k], solver) for k in range(len(grid))]
+        wav = ()
+    else:   # wavelet = (s, q): every column chooses between P_p and W_{s,q} (Algorithm 1)
+        s, q = wavelet
+        coefs = [fit_factor_choice(W[k], grid_nodes(grid[k]), degree[k], s, q, solver) for k in range(len(grid))]
+        wav = tuple((s, q) for _ in grid)
     return Model(tuple(lo), tuple(hi), tuple(rank), tuple(degree), core0, coefs,
-                 info={"grid_tensor": T, "factors": W, "sigmas": sig, "subset": sub})
+                 info={"grid_tensor": T, "factors": W, "sigmas": sig, "subset": sub}, wavelet=wav)
 
 
 def fit(pts, vals, lo, hi, grid, rank, degree, interp_fraction, n_samples, seed,
-        idw_k: int = 8, idw_power: float = 2.0, solver: str = "omp") -> Model:
+        idw_k: int = 8, idw_power: float = 2.0, solver: str = "omp", wavelet=None) -> Model:
     """Algorithm 1 then Algorithm 2 (uniformly sampled rows, normal equations)."""
-    m = compress(pts, vals, lo, hi, grid, rank, degree, interp_fraction, seed, idw_k, idw_power, solver)
+    m = compress(pts, vals, lo, hi, grid, rank, degree, interp_fraction, seed, idw_k, idw_power, solver,
+                 wavelet)
     alpha, idx, G, h = refit_core(m, np.asarray(pts, np.float64), vals, n_samples, seed)
     out = m.with_core(alpha)
     out.info.update({"core0": m.core, "ls_rows": idx})

@@ -9,11 +9,12 @@ from __future__ import annotations
 
 import numpy as np
 
-from .basis import legendre_orthonormal, to_reference
+from .basis import to_reference
 from .interp import grid_nodes
 from .lsq import factor_values
 from .model import Model
 from .sthosvd import mode_product
+from .wavelets import mode_basis
 
 
 def _contract_rows(rows, T) -> np.ndarray:
@@ -34,7 +35,8 @@ def evaluate(model: Model, pts: np.ndarray, chunk: int = 8192) -> np.ndarray:
 
 
 def full_expansion_coefficients(model: Model) -> np.ndarray:
-    """beta (n1, .., nd) of the tensor-product expansion equal to the Tucker model."""
+    """beta (n1, .., nd) of the tensor-product expansion equal to the Tucker model (n_k: the size
+    of the mode's basis)."""
     beta = np.asarray(model.core, np.float64)
     for k in range(len(model.rank)):
         beta = mode_product(beta, model.coefs[k], k)
@@ -45,7 +47,7 @@ def evaluate_full_expansion(model: Model, pts: np.ndarray) -> np.ndarray:
     """u(y) = sum_{i1 .. id} beta_{i1 .. id} phi_i1(y1) .. phi_id(yd)  (Sec. 2)."""
     beta = full_expansion_coefficients(model)
     pts = np.asarray(pts, dtype=np.float64)
-    P = [legendre_orthonormal(to_reference(pts[:, k], model.lo[k], model.hi[k]), model.degree[k])
+    P = [mode_basis(to_reference(pts[:, k], model.lo[k], model.hi[k]), model.degree[k], *model.mode_wavelet(k))
          for k in range(len(model.rank))]
     return _contract_rows(P, beta)
 
@@ -55,7 +57,7 @@ def evaluate_on_grid(model: Model, grid) -> np.ndarray:
     alpha x_1 (Phi_1 C_1) x_2 (Phi_2 C_2) .. x_d (Phi_d C_d)."""
     Y = np.asarray(model.core, np.float64)
     for k in range(len(grid)):
-        F = legendre_orthonormal(grid_nodes(grid[k]), model.degree[k]) @ model.coefs[k]
+        F = mode_basis(grid_nodes(grid[k]), model.degree[k], *model.mode_wavelet(k)) @ model.coefs[k]
         Y = mode_product(Y, F, k)
     return Y
 
@@ -67,7 +69,7 @@ def evaluate_tensor_grid(model: Model, gx, gy, gz) -> np.ndarray:
     Y = np.asarray(model.core, np.float64)
     for k, g in enumerate((gx, gy, gz)):
         t = to_reference(np.asarray(g, np.float64), model.lo[k], model.hi[k])
-        Y = mode_product(Y, legendre_orthonormal(t, model.degree[k]) @ model.coefs[k], k)
+        Y = mode_product(Y, mode_basis(t, model.degree[k], *model.mode_wavelet(k)) @ model.coefs[k], k)
     return Y
 
 

@@ -76,6 +76,32 @@ def fit_factor(W: np.ndarray, nodes: np.ndarray, p: int, solver: str = "omp") ->
     return C
 
 
+def fit_factor_choice(W: np.ndarray, nodes: np.ndarray, p: int, s: int, q: int,
+                      solver: str = "omp") -> np.ndarray:
+    """Algorithm 1 steps 5-6: every column is fitted in P_p and in the wavelet space W_{s,q}
+    (``oracle.wavelets``, q <= p) with leave-one-out selection, and the fit with the smaller
+    leave-one-out error is kept (P_p on ties).  Returns C over the mode basis: rows 0..p are
+    phi_0..phi_p, then the (q + 1)(2^s - 1) detail functions."""
+    from .lars import lars_loo
+    from .wavelets import mode_basis, wavelet_columns
+    if not (0 <= q <= p and s >= 1):
+        raise ValueError("need s >= 1 and 0 <= q <= p")
+    fit = {"omp": omp_loo, "lars": lars_loo}[solver]
+    B = mode_basis(nodes, p, s, q)
+    wcols = wavelet_columns(p, s, q)
+    C = np.zeros((B.shape[1], W.shape[1]), dtype=np.float64)
+    for j in range(W.shape[1]):
+        SL, cL, prL = fit(B[:, : p + 1], W[:, j])
+        SW, cW, prW = fit(B[:, wcols], W[:, j])
+        if not prL and not prW:
+            continue
+        if not prW or (prL and min(prL) <= min(prW)):
+            C[SL, j] = cL
+        else:
+            C[wcols[SW], j] = cW
+    return C
+
+
 def press_bruteforce(Phi_S: np.ndarray, z: np.ndarray) -> float:
     """Leave-one-out error by refitting without each node in turn (for pinning PRESS)."""
     I = Phi_S.shape[0]
