@@ -119,11 +119,12 @@ def lars_loo(Phi: np.ndarray, z: np.ndarray, tol: float = 1e-14):
         c, Q = ls_qr(Phi[:, S], z)
         r = z - Phi[:, S] @ c
         h = (Q * Q).sum(axis=1)
-        with np.errstate(divide="ignore"):
+        with np.errstate(divide="ignore", invalid="ignore"):
             loo = r / (1.0 - h)
         supports.append(S)
         coefs.append(c)
-        press.append(float(np.mean(loo * loo)))
+        pr = float(np.mean(loo * loo))
+        press.append(pr if pr == pr else np.inf)     # 0/0 at a node of leverage 1: undefined
         if np.linalg.norm(r) <= tol * znorm:
             break
     best = int(np.argmin(press))

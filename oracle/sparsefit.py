@@ -12,7 +12,8 @@ l0-constrained problem (3), and keeps the leave-one-out model selection:
    and update r = z - Phi_S c_S;
 3. after every step record the leave-one-out (PRESS) error (1/I) sum_i (r_i / (1 - h_ii))^2,
    where h_ii is the leverage of node i, the i-th diagonal entry of the hat matrix
-   Phi_S (Phi_S^T Phi_S)^-1 Phi_S^T;
+   Phi_S (Phi_S^T Phi_S)^-1 Phi_S^T; a support that fits a node of leverage 1 exactly has an
+   undefined leave-one-out error (0/0) and scores +inf;
 4. stop when |S| reaches min(n, I - 2) or ||r|| <= 1e-14 ||z||;
 5. keep the support size with the smallest PRESS (the smaller size on ties).
 """
@@ -52,9 +53,10 @@ def omp_loo(Phi: np.ndarray, z: np.ndarray, tol: float = 1e-14):
         c, Q = ls_qr(Phi[:, support], z)
         r = z - Phi[:, support] @ c
         h = (Q * Q).sum(axis=1)
-        with np.errstate(divide="ignore"):
+        with np.errstate(divide="ignore", invalid="ignore"):
             loo = r / (1.0 - h)
-        press.append(float(np.mean(loo * loo)))
+        pr = float(np.mean(loo * loo))
+        press.append(pr if pr == pr else np.inf)     # 0/0 at a node of leverage 1: undefined
         coefs.append(c)
         if np.linalg.norm(r) <= tol * znorm:
             break
