@@ -87,6 +87,10 @@ typedef struct {
                                 (Sec. 4.1, Table 1; fst_sthosvd_eps), with rank[] as caps;
                                 0: the fixed ranks rank[] */
   int32_t  sparse_solver;    /* FST_SOLVER_OMP (default) or FST_SOLVER_LARS (Sec. 3, 4.2) */
+  int32_t  wavelet_level;    /* s > 0: every singular vector is also fitted in the wavelet space
+                                W_{s,q} and keeps the fit with the smaller leave-one-out error
+                                (Sec. 4.2, Algorithm 1); 0: Legendre only */
+  int32_t  wavelet_degree;   /* q of W_{s,q}: 0 <= q <= min(p_k, 7), (q + 1)(2^s - 1) <= 128 */
 } fst_fit_params;
 
 /* ------------------------------------------------------------------ library */
@@ -291,6 +295,25 @@ fst_status fst_sparse_fit(const double* W, int32_t I, int32_t r, int32_t p, doub
  * re-admitted in the next step; at most min(p + 1, I - 2) active columns). */
 fst_status fst_sparse_fit_lars(const double* W, int32_t I, int32_t r, int32_t p, double* C);
 
+/* ------------------------------------------------------------------ wavelet space (Sec. 4.2)
+ * W_{s,q}: the piecewise polynomials of degree <= q on the 2^s dyadic cells of [-1, 1], with
+ * Alpert's multiwavelet basis (orthonormal under dt/2): the global Legendre functions
+ * phi_0..phi_q and, for each level l < s and cell c < 2^l, the functions
+ * psi_{l,c,m}(t) = 2^(l/2) psi_m(2^l (t + 1) - 2c - 1), m = 0..q.  The mother wavelets psi_m are
+ * polynomials of degree <= q on each half of [-1, 1]; psi_m is the unit function orthogonal to
+ * phi_0..phi_{q+m} and to psi_{m+1}..psi_q, signed so that its largest coefficient on the right
+ * half, in the basis sqrt(2) phi_n(2x - 1), is positive.  A point's cell at level l is
+ * floor((t + 1) 2^(l-1)) clamped to [0, 2^l - 1].  A mode holding both spaces (q <= p) has the
+ * basis phi_0..phi_p followed by the (q + 1)(2^s - 1) detail functions psi_{l,c,m} in the order
+ * (l, c, m); its coefficient matrices have that many rows. */
+
+/* The per-column choice of Algorithm 1: each column of W (host FP64 I x r row-major, sampled at
+ * the I equispaced nodes) is fitted in P_p and in W_{s,q} with the given solver (leave-one-out
+ * selection) and keeps the fit with the smaller leave-one-out error (P_p on ties).
+ * C: host FP64 (p + 1 + (q + 1)(2^s - 1)) x r row-major. */
+fst_status fst_sparse_fit_choice(const double* W, int32_t I, int32_t r, int32_t p, int32_t s,
+                                 int32_t q, int32_t solver, double* C);
+
 /* ------------------------------------------------------------------ model */
 
 /* Builds a model from its parts.  lo, hi: host double[3]; rank, degree: host int32[3];
@@ -299,12 +322,22 @@ fst_status fst_model_from_parts(const double lo[3], const double hi[3], const in
                                 const int32_t degree[3], const double* core,
                                 const double* const coefs[3], fst_model** out);
 void fst_model_free(fst_model* m);
+/* A model whose modes may hold a wavelet space: as fst_model_from_parts_d, with wlevel[k] = s_k
+ * (0: Legendre only) and wdegree[k] = q_k per mode (host int32[d]); coefs[k] has
+ * p_k + 1 + (q_k + 1)(2^s_k - 1) rows. */
+fst_status fst_model_from_parts_wavelet(int32_t d, const double* lo, const double* hi,
+                                        const int32_t* rank, const int32_t* degree,
+                                        const int32_t* wlevel, const int32_t* wdegree,
+                                        const double* core, const double* const* coefs,
+                                        fst_model** out);
+/* wlevel, wdegree: host int32[d] receiving s_k, q_k (0, 0 for Legendre-only modes) */
+fst_status fst_model_wavelets(const fst_model* m, int32_t* wlevel, int32_t* wdegree);
 /* lo, hi (double[3]), rank, degree (int32[3]), nnz: non-zero coefficients; any may be NULL */
 fst_status fst_model_info(const fst_model* m, double* lo, double* hi, int32_t* rank,
                           int32_t* degree, int64_t* nnz);
 /* core_out: host FP64 r1 r2 r3 */
 fst_status fst_model_core(const fst_model* m, double* core_out);
-/* C_out: host FP64 (p_k + 1) x r_k row-major, zeros off the support */
+/* C_out: host FP64 (p_k + 1 + detail functions) x r_k row-major, zeros off the support */
 fst_status fst_model_coefs(const fst_model* m, int32_t k, double* C_out);
 /* How the core of a model from fst_fit, fst_refit_core or fst_fit_batched was solved.
  * Precision ladder: a Gram whose Cholesky breaks down, or whose refinement makes the FP64
@@ -385,6 +418,8 @@ typedef struct {
   int32_t  n_threads;
   double   eps;              /* > 0: ranks from this precision (Sec. 4.1), threshold eps^2 ||T||^2 / d */
   int32_t  sparse_solver;    /* FST_SOLVER_OMP or FST_SOLVER_LARS */
+  int32_t  wavelet_level;    /* as in fst_fit_params */
+  int32_t  wavelet_degree;
 } fst_fit_params_d;
 
 /* Fills defaults for d modes (grid 16, ranks 4, degree 15, fraction 0.1, idw 8 / 2.0, ...). */

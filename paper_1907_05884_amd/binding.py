@@ -46,7 +46,7 @@ class fst_fit_params(C.Structure):
                 ("interp_fraction", C.c_double), ("idw_k", C.c_int32), ("idw_power", C.c_double),
                 ("n_samples", C.c_int64), ("seed", C.c_uint64), ("gram_prec", C.c_int32),
                 ("refine_steps", C.c_int32), ("n_threads", C.c_int32), ("eps", C.c_double),
-                ("sparse_solver", C.c_int32)]
+                ("sparse_solver", C.c_int32), ("wavelet_level", C.c_int32), ("wavelet_degree", C.c_int32)]
 
 
 class fst_fit_params_d(C.Structure):
@@ -55,7 +55,7 @@ class fst_fit_params_d(C.Structure):
                 ("grid", C.c_int32 * 4), ("rank", C.c_int32 * 4), ("degree", C.c_int32 * 4),
                 ("interp_fraction", C.c_double), ("idw_k", C.c_int32), ("idw_power", C.c_double),
                 ("n_samples", C.c_int64), ("seed", C.c_uint64), ("n_threads", C.c_int32), ("eps", C.c_double),
-                ("sparse_solver", C.c_int32)]
+                ("sparse_solver", C.c_int32), ("wavelet_level", C.c_int32), ("wavelet_degree", C.c_int32)]
 
 
 _vp, _i64, _i32, _dp = C.c_void_p, C.c_int64, C.c_int32, C.POINTER(C.c_double)
@@ -110,6 +110,9 @@ _lib_fns = dict(
     fst_sthosvd_eps=(_i32, _vp, _vp, C.c_double, _vp, _i32, _vp, _vp, _vp, _vp),
     fst_sparse_fit=(_i32, _vp, _i32, _i32, _i32, _vp),
     fst_sparse_fit_lars=(_i32, _vp, _i32, _i32, _i32, _vp),
+    fst_sparse_fit_choice=(_i32, _vp, _i32, _i32, _i32, _i32, _i32, _i32, _vp),
+    fst_model_from_parts_wavelet=(_i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, C.POINTER(_vp)),
+    fst_model_wavelets=(_i32, _vp, _vp, _vp),
     fst_model_from_parts=(_i32, _vp, _vp, _vp, _vp, _vp, _vp, C.POINTER(_vp)),
     fst_model_from_parts_d=(_i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp, C.POINTER(_vp)),
     fst_model_info_d=(_i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp),
@@ -208,7 +211,7 @@ def _workspace(nbytes: int, device):
 def make_params(dtype=FST_F64, lo=(-1.0,) * 3, hi=(1.0,) * 3, grid=(32,) * 3, rank=(8,) * 3,
                 degree=(15,) * 3, interp_fraction=0.10, idw_k=8, idw_power=2.0, n_samples=2000,
                 seed=1, gram_prec=None, refine_steps=0, n_threads=0, eps=0.0,
-                sparse_solver=FST_SOLVER_OMP) -> fst_fit_params:
+                sparse_solver=FST_SOLVER_OMP, wavelet=None) -> fst_fit_params:
     p = fst_fit_params()
     _fn["fst_fit_params_default"](C.byref(p))
     p.dtype = dtype
@@ -227,12 +230,14 @@ def make_params(dtype=FST_F64, lo=(-1.0,) * 3, hi=(1.0,) * 3, grid=(32,) * 3, ra
     p.n_threads = int(n_threads)
     p.eps = float(eps)
     p.sparse_solver = int(sparse_solver)
+    if wavelet is not None:
+        p.wavelet_level, p.wavelet_degree = int(wavelet[0]), int(wavelet[1])
     return p
 
 
 def make_params_d(d=4, dtype=FST_F64, lo=None, hi=None, grid=None, rank=None, degree=None,
                   interp_fraction=0.10, idw_k=8, idw_power=2.0, n_samples=2000, seed=1, n_threads=0,
-                  eps=0.0, sparse_solver=FST_SOLVER_OMP) -> fst_fit_params_d:
+                  eps=0.0, sparse_solver=FST_SOLVER_OMP, wavelet=None) -> fst_fit_params_d:
     p = fst_fit_params_d()
     _fn["fst_fit_params_d_default"](C.byref(p), int(d))
     p.dtype = dtype
@@ -253,7 +258,13 @@ def make_params_d(d=4, dtype=FST_F64, lo=None, hi=None, grid=None, rank=None, de
     p.n_threads = int(n_threads)
     p.eps = float(eps)
     p.sparse_solver = int(sparse_solver)
+    if wavelet is not None:
+        p.wavelet_level, p.wavelet_degree = int(wavelet[0]), int(wavelet[1])
     return p
+
+
+def _detail_count(s, q):
+    return (q + 1) * ((1 << s) - 1) if s > 0 else 0
 
 
 # ------------------------------------------------------------------------------ model
@@ -304,9 +315,17 @@ class Model:
         _check(_fn["fst_model_core"](self._h, out.ctypes.data_as(C.c_void_p)))
         return out
 
+    def wavelets(self):
+        """((s_k, q_k) per mode): the wavelet space held beside P_p (0, 0: Legendre only)."""
+        d = self.d
+        wl, wd = (C.c_int32 * 4)(), (C.c_int32 * 4)()
+        _check(_fn["fst_model_wavelets"](self._h, wl, wd))
+        return tuple((wl[k], wd[k]) for k in range(d))
+
     def coefs(self, k: int) -> np.ndarray:
         inf = self.info()
-        out = np.empty((inf["degree"][k] + 1, inf["rank"][k]), dtype=np.float64)
+        s_k, q_k = self.wavelets()[k]
+        out = np.empty((inf["degree"][k] + 1 + _detail_count(s_k, q_k), inf["rank"][k]), dtype=np.float64)
         _check(_fn["fst_model_coefs"](self._h, int(k), out.ctypes.data_as(C.c_void_p)))
         return out
 
@@ -324,8 +343,9 @@ class Model:
         return int(_fn["fst_model_paper_bytes"](self._h))
 
 
-def fst_model_from_parts(lo, hi, rank, degree, core, coefs) -> Model:
-    """A model of d = len(rank) modes (3: fst_model_from_parts, 4: fst_model_from_parts_d)."""
+def fst_model_from_parts(lo, hi, rank, degree, core, coefs, wavelet=None) -> Model:
+    """A model of d = len(rank) modes (3: fst_model_from_parts, 4: fst_model_from_parts_d);
+    wavelet: per-mode (s_k, q_k) of a wavelet space beside P_p (fst_model_from_parts_wavelet)."""
     d = len(rank)
     if not (len(lo) == len(hi) == len(degree) == len(coefs) == d):
         raise ValueError("lo, hi, rank, degree and coefs need one entry per mode")
@@ -335,14 +355,19 @@ def fst_model_from_parts(lo, hi, rank, degree, core, coefs) -> Model:
     d_a, d_p = _host(degree, np.int32)
     c_a, c_p = _host(core, np.float64)
     cs = [np.ascontiguousarray(c, dtype=np.float64) for c in coefs]
+    wav = tuple(wavelet) if wavelet else ((0, 0),) * d
     for k in range(d):
-        if cs[k].shape != (int(degree[k]) + 1, int(rank[k])):
-            raise ValueError("coefficient matrix k must have shape (degree[k] + 1, rank[k])")
+        if cs[k].shape != (int(degree[k]) + 1 + _detail_count(*wav[k]), int(rank[k])):
+            raise ValueError("coefficient matrix k must have shape (rows of mode k's basis, rank[k])")
     if c_a.size != int(np.prod(rank)):
         raise ValueError("core must have r1 .. rd entries")
     arr = (C.c_void_p * d)(*[c.ctypes.data_as(C.c_void_p) for c in cs])
     h = C.c_void_p()
-    if d == 3:
+    if wavelet:
+        wl_a, wl_p = _host([w[0] for w in wav], np.int32)
+        wd_a, wd_p = _host([w[1] for w in wav], np.int32)
+        _check(_fn["fst_model_from_parts_wavelet"](d, lo_p, hi_p, r_p, d_p, wl_p, wd_p, c_p, arr, C.byref(h)))
+    elif d == 3:
         _check(_fn["fst_model_from_parts"](lo_p, hi_p, r_p, d_p, c_p, arr, C.byref(h)))
     else:
         _check(_fn["fst_model_from_parts_d"](d, lo_p, hi_p, r_p, d_p, c_p, arr, C.byref(h)))
@@ -738,6 +763,15 @@ def fst_sthosvd_eps(T, eps: float, max_rank, n_threads=0):
     core = core[:r[0] * r[1] * r[2]].reshape(r)
     W = [W[k][:int(dims[k]) * r[k]].reshape(int(dims[k]), r[k]) for k in range(3)]
     return r, core, W, S
+
+
+def fst_sparse_fit_choice(W, p: int, s: int, q: int, solver: int = FST_SOLVER_OMP) -> np.ndarray:
+    W_a, W_p = _host(W, np.float64)
+    I, r = W_a.shape
+    out = np.empty((int(p) + 1 + _detail_count(int(s), int(q)), r), dtype=np.float64)
+    _check(_fn["fst_sparse_fit_choice"](W_p, int(I), int(r), int(p), int(s), int(q), int(solver),
+                                        out.ctypes.data_as(C.c_void_p)))
+    return out
 
 
 def fst_sparse_fit(W, p: int, solver: int = FST_SOLVER_OMP) -> np.ndarray:

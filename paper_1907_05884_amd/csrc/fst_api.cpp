@@ -45,6 +45,18 @@ static void check_prec(int dtype, int gram_prec) {
 }
 static size_t dsize(int dtype) { return dtype == FST_F64 ? sizeof(double) : sizeof(float); }
 
+static void check_wavelet_params(int s, int q, const int32_t* degree, int D) {
+  if (s == 0) return;
+  if (s < 0 || s > 7) fail(FST_E_INVAL, "wavelet_level must be in [0, 7]");
+  for (int k = 0; k < D; ++k)
+    if (q < 0 || q > std::min(degree[k], kMaxWaveDegree))
+      fail(FST_E_INVAL, "wavelet_degree must be in [0, min(degree, 7)]");
+  if (detail_count(s, q) > kMaxDetail) fail(FST_E_INVAL, "wavelet space too large: (q + 1)(2^s - 1) > 128");
+}
+
+static int D_OF(const fst_fit_params*) { return 3; }
+static int D_OF(const fst_fit_params_d* p) { return p->d; }
+
 static void validate_params(const fst_fit_params* p, int64_t n) {
   if (!p) fail(FST_E_INVAL, "null parameters");
   if (p->struct_size != sizeof(fst_fit_params)) fail(FST_E_INVAL, "fst_fit_params.struct_size mismatch");
@@ -79,6 +91,7 @@ static void validate_params(const fst_fit_params* p, int64_t n) {
   if (!(p->eps >= 0.0 && p->eps < 1.0)) fail(FST_E_INVAL, "eps must be in [0, 1)");
   if (p->sparse_solver != FST_SOLVER_OMP && p->sparse_solver != FST_SOLVER_LARS)
     fail(FST_E_INVAL, "sparse_solver must be FST_SOLVER_OMP or FST_SOLVER_LARS");
+  check_wavelet_params(p->wavelet_level, p->wavelet_degree, p->degree, D_OF(p));
 }
 
 // --------------------------------------------------------------------------- refit layout
@@ -382,10 +395,13 @@ static fst_model* compress_from_subset(const fst_fit_params* p, const std::vecto
   } else {
     sthosvd(T.data(), p->grid, rank, p->n_threads, core.data(), Wp, nullptr);
   }
-  std::unique_ptr<fst_model> m(model_new(p->lo, p->hi, rank, p->degree));
+  const int32_t wl[3] = {p->wavelet_level, p->wavelet_level, p->wavelet_level};
+  const int32_t wd[3] = {p->wavelet_degree, p->wavelet_degree, p->wavelet_degree};
+  std::unique_ptr<fst_model> m(model_new_d(3, p->lo, p->hi, rank, p->degree, wl, wd));
   std::copy(core.begin(), core.begin() + (size_t)rank[0] * rank[1] * rank[2], m->core.begin());
   for (int k = 0; k < 3; ++k)
-    sparse_fit_with(p->sparse_solver, W[k].data(), p->grid[k], rank[k], p->degree[k], m->coef[k].data());
+    sparse_fit_with(p->sparse_solver, W[k].data(), p->grid[k], rank[k], p->degree[k], m->coef[k].data(),
+                    p->wavelet_level, p->wavelet_degree);
   return m.release();
 }
 
@@ -453,6 +469,7 @@ static void validate_params_d(const fst_fit_params_d* p, int64_t n) {
   if (!(p->eps >= 0.0 && p->eps < 1.0)) fail(FST_E_INVAL, "eps must be in [0, 1)");
   if (p->sparse_solver != FST_SOLVER_OMP && p->sparse_solver != FST_SOLVER_LARS)
     fail(FST_E_INVAL, "sparse_solver must be FST_SOLVER_OMP or FST_SOLVER_LARS");
+  check_wavelet_params(p->wavelet_level, p->wavelet_degree, p->degree, D_OF(p));
 }
 
 // Algorithm 1 for D modes from the gathered subset (host FP64, K x (D + 1): coordinates, value)
@@ -505,10 +522,13 @@ static fst_model* compress_from_subset_d(const fst_fit_params_d* p, const std::v
   } else {
     sthosvd_d(T.data(), D, p->grid, rank, p->n_threads, core.data(), Wp, nullptr);
   }
-  std::unique_ptr<fst_model> m(model_new_d(D, p->lo, p->hi, rank, p->degree));
+  const int32_t wl[4] = {p->wavelet_level, p->wavelet_level, p->wavelet_level, p->wavelet_level};
+  const int32_t wd[4] = {p->wavelet_degree, p->wavelet_degree, p->wavelet_degree, p->wavelet_degree};
+  std::unique_ptr<fst_model> m(model_new_d(D, p->lo, p->hi, rank, p->degree, wl, wd));
   std::copy(core.begin(), core.begin() + (size_t)m->R(), m->core.begin());
   for (int k = 0; k < D; ++k)
-    sparse_fit_with(p->sparse_solver, W[k].data(), p->grid[k], rank[k], p->degree[k], m->coef[k].data());
+    sparse_fit_with(p->sparse_solver, W[k].data(), p->grid[k], rank[k], p->degree[k], m->coef[k].data(),
+                    p->wavelet_level, p->wavelet_degree);
   return m.release();
 }
 
@@ -969,10 +989,40 @@ fst_status fst_model_from_parts(const double lo[3], const double hi[3], const in
 fst_status fst_model_from_parts_d(int32_t d, const double* lo, const double* hi, const int32_t* rank,
                                   const int32_t* degree, const double* core, const double* const* coefs,
                                   fst_model** out) {
+  return fst_model_from_parts_wavelet(d, lo, hi, rank, degree, nullptr, nullptr, core, coefs, out);
+}
+
+fst_status fst_model_wavelets(const fst_model* m, int32_t* wlevel, int32_t* wdegree) {
+  FST_TRY
+  set_last_error("");
+  check_model(m);
+  for (int k = 0; k < m->d; ++k) {
+    if (wlevel) wlevel[k] = m->wlevel[k];
+    if (wdegree) wdegree[k] = m->wdegree[k];
+  }
+  return FST_OK;
+  FST_CATCH
+}
+
+fst_status fst_sparse_fit_choice(const double* W, int32_t I, int32_t r, int32_t p, int32_t s, int32_t q,
+                                 int32_t solver, double* C) {
+  FST_TRY
+  set_last_error("");
+  if (!W || !C) fail(FST_E_INVAL, "null argument");
+  if (solver != FST_SOLVER_OMP && solver != FST_SOLVER_LARS) fail(FST_E_INVAL, "unknown solver");
+  sparse_fit_choice(W, I, r, p, s, q, solver, C);
+  return FST_OK;
+  FST_CATCH
+}
+
+fst_status fst_model_from_parts_wavelet(int32_t d, const double* lo, const double* hi, const int32_t* rank,
+                                        const int32_t* degree, const int32_t* wlevel, const int32_t* wdegree,
+                                        const double* core, const double* const* coefs, fst_model** out) {
   FST_TRY
   set_last_error("");
   if (!lo || !hi || !rank || !degree || !core || !coefs || !out) fail(FST_E_INVAL, "null argument");
-  std::unique_ptr<fst_model> m(model_new_d(d, lo, hi, rank, degree));
+  if ((wlevel == nullptr) != (wdegree == nullptr)) fail(FST_E_INVAL, "wlevel and wdegree go together");
+  std::unique_ptr<fst_model> m(model_new_d(d, lo, hi, rank, degree, wlevel, wdegree));
   for (size_t i = 0; i < m->core.size(); ++i) {
     if (!std::isfinite(core[i])) fail(FST_E_INVAL, "non-finite core entry");
     m->core[i] = core[i];

@@ -59,6 +59,8 @@ fst_status fst_fit_batched(const fst_fit_params* base, int32_t V, const int32_t*
   if (V < 1 || V > 4096) fst::fail(FST_E_INVAL, "V must be in [1, 4096]");
   if (base->struct_size == sizeof(fst_fit_params) && base->eps != 0.0)
     fst::fail(FST_E_UNSUPPORTED, "the batched form takes fixed ranks (eps must be 0)");
+  if (base->struct_size == sizeof(fst_fit_params) && base->wavelet_level != 0)
+    fst::fail(FST_E_UNSUPPORTED, "the batched form fits Legendre factors only (wavelet_level must be 0)");
   // every variable must form a valid problem on its own
   std::vector<fst_fit_params> pv((size_t)V, *base);
   for (int v = 0; v < V; ++v) {

@@ -749,118 +749,294 @@ std::vector<std::vector<int>> lars_active_sets(const std::vector<double>& X, int
 }
 }  // namespace
 
-void sparse_fit_lars(const double* W, int I, int r, int p, double* C) {
-  if (I < 3 || r < 1 || p < 0) fail(FST_E_INVAL, "sparse_fit: need I >= 3, r >= 1, p >= 0");
-  const int n = p + 1;
-  std::vector<double> Phi((size_t)I * n), X((size_t)I * n);
-  for (int i = 0; i < I; ++i) legendre_orthonormal_host(-1.0 + 2.0 * i / (I - 1), p, &Phi[(size_t)i * n]);
+namespace {
+// One column's sparse fit: the support and least-squares coefficients of the path step with
+// the smallest PRESS (first on ties), and that PRESS (infinite when nothing was fitted).
+struct ColumnFit {
+  std::vector<int> S;
+  std::vector<double> c;
+  double press = std::numeric_limits<double>::infinity();
+};
+
+// A basis sampled at the nodes: Phi (I x n row-major) and its unit-norm columns X
+struct NodeBasis {
+  int I = 0, n = 0;
+  std::vector<double> Phi, X, colnorm;
+};
+
+NodeBasis node_basis(std::vector<double> Phi, int I, int n) {
+  NodeBasis b;
+  b.I = I;
+  b.n = n;
+  b.Phi = std::move(Phi);
+  b.X.resize((size_t)I * n);
+  b.colnorm.assign((size_t)n, 0.0);
   for (int m = 0; m < n; ++m) {
     double s2 = 0;
-    for (int i = 0; i < I; ++i) s2 += Phi[(size_t)i * n + m] * Phi[(size_t)i * n + m];
-    const double nm = std::sqrt(s2);
-    for (int i = 0; i < I; ++i) X[(size_t)i * n + m] = Phi[(size_t)i * n + m] / nm;
+    for (int i = 0; i < I; ++i) s2 += b.Phi[(size_t)i * n + m] * b.Phi[(size_t)i * n + m];
+    b.colnorm[(size_t)m] = std::sqrt(s2);
+    for (int i = 0; i < I; ++i) b.X[(size_t)i * n + m] = b.Phi[(size_t)i * n + m] / b.colnorm[(size_t)m];
   }
+  return b;
+}
+
+double press_of(const std::vector<double>& res, const std::vector<double>& lev, int I) {
+  double pr = 0.0;
+  for (int i = 0; i < I; ++i) {
+    const double e = res[(size_t)i] / (1.0 - lev[(size_t)i]);
+    pr += e * e;
+  }
+  pr /= I;
+  return pr == pr ? pr : std::numeric_limits<double>::infinity();
+}
+
+// Orthogonal matching pursuit: the column of largest normalised correlation with the residual
+// joins (lowest index on ties), least squares on the support, PRESS after every step.
+ColumnFit omp_column(const NodeBasis& B, const double* z) {
+  const int I = B.I, n = B.n;
+  ColumnFit out;
+  double zn = 0;
+  for (int i = 0; i < I; ++i) zn += z[i] * z[i];
+  zn = std::sqrt(zn);
+  if (zn == 0.0) return out;
+  std::vector<int> S;
+  std::vector<std::vector<double>> coefs;
+  std::vector<double> press, res, lev, c, rcur(z, z + I);
+  const int tmax = std::min(n, I - 2);
+  for (int t = 0; t < tmax; ++t) {
+    int best = -1;
+    double bscore = -1.0;
+    for (int m = 0; m < n; ++m) {
+      if (std::find(S.begin(), S.end(), m) != S.end()) continue;
+      double s = 0;
+      for (int i = 0; i < I; ++i) s += B.Phi[(size_t)i * n + m] * rcur[(size_t)i];
+      const double score = std::fabs(s) / B.colnorm[(size_t)m];
+      if (score > bscore) {
+        bscore = score;
+        best = m;
+      }
+    }
+    S.push_back(best);
+    ls_select(B.Phi, I, n, S, z, c, res, lev);
+    press.push_back(press_of(res, lev, I));
+    coefs.push_back(c);
+    rcur = res;
+    double rn = 0;
+    for (double t2 : res) rn += t2 * t2;
+    if (std::sqrt(rn) <= 1e-14 * zn) break;
+  }
+  if (press.empty()) return out;
+  size_t tb = 0;
+  for (size_t t = 1; t < press.size(); ++t)
+    if (press[t] < press[tb]) tb = t;
+  out.S.assign(S.begin(), S.begin() + (long)tb + 1);
+  out.c = coefs[tb];
+  out.press = press[tb];
+  return out;
+}
+
+// Lasso-LARS path (lars_active_sets on the unit-norm columns), every active set refitted by
+// least squares and scored by PRESS.
+ColumnFit lars_column(const NodeBasis& B, const double* z) {
+  const int I = B.I, n = B.n;
+  ColumnFit out;
+  double zn = 0;
+  for (int i = 0; i < I; ++i) zn += z[i] * z[i];
+  zn = std::sqrt(zn);
+  if (zn == 0.0) return out;
+  const std::vector<std::vector<int>> sets = lars_active_sets(B.X, I, n, z, std::min(n, I - 2));
+  std::vector<std::vector<double>> coefs;
+  std::vector<double> press, res, lev, c;
+  for (const std::vector<int>& S : sets) {
+    if (S.empty()) {
+      press.push_back(std::numeric_limits<double>::infinity());
+      coefs.emplace_back();
+      continue;
+    }
+    ls_select(B.Phi, I, n, S, z, c, res, lev);
+    press.push_back(press_of(res, lev, I));
+    coefs.push_back(c);
+    double rn = 0;
+    for (double t2 : res) rn += t2 * t2;
+    if (std::sqrt(rn) <= 1e-14 * zn) break;
+  }
+  if (press.empty()) return out;
+  size_t tb = 0;
+  for (size_t t = 1; t < press.size(); ++t)
+    if (press[t] < press[tb]) tb = t;
+  out.S = sets[tb];
+  out.c = coefs[tb];
+  out.press = press[tb];
+  return out;
+}
+
+ColumnFit fit_column(int solver, const NodeBasis& B, const double* z) {
+  return solver == FST_SOLVER_LARS ? lars_column(B, z) : omp_column(B, z);
+}
+
+std::vector<double> legendre_at_nodes(int I, int p) {
+  std::vector<double> Phi((size_t)I * (p + 1));
+  for (int i = 0; i < I; ++i) legendre_orthonormal_host(-1.0 + 2.0 * i / (I - 1), p, &Phi[(size_t)i * (p + 1)]);
+  return Phi;
+}
+
+void fit_columns(int solver, const double* W, int I, int r, int p, double* C) {
+  if (I < 3 || r < 1 || p < 0) fail(FST_E_INVAL, "sparse_fit: need I >= 3, r >= 1, p >= 0");
+  const int n = p + 1;
+  const NodeBasis B = node_basis(legendre_at_nodes(I, p), I, n);
   std::fill(C, C + (size_t)n * r, 0.0);
-  std::vector<double> z((size_t)I), res, lev, c;
+  std::vector<double> z((size_t)I);
   for (int j = 0; j < r; ++j) {
     for (int i = 0; i < I; ++i) z[(size_t)i] = W[(size_t)i * r + j];
-    double zn = 0;
-    for (double t : z) zn += t * t;
-    zn = std::sqrt(zn);
-    if (zn == 0.0) continue;
-    const std::vector<std::vector<int>> sets = lars_active_sets(X, I, n, z.data(), std::min(n, I - 2));
-    // every active set of the path refitted by least squares and scored by PRESS
-    std::vector<std::vector<double>> coefs;
-    std::vector<double> press;
-    size_t used = 0;
-    for (const std::vector<int>& S : sets) {
-      if (S.empty()) {
-        ++used;
-        press.push_back(std::numeric_limits<double>::infinity());
-        coefs.emplace_back();
-        continue;
+    const ColumnFit f = fit_column(solver, B, z.data());
+    for (size_t l = 0; l < f.S.size(); ++l) C[(size_t)f.S[l] * r + j] = f.c[l];
+  }
+}
+}  // namespace
+
+void sparse_fit(const double* W, int I, int r, int p, double* C) { fit_columns(FST_SOLVER_OMP, W, I, r, p, C); }
+void sparse_fit_lars(const double* W, int I, int r, int p, double* C) { fit_columns(FST_SOLVER_LARS, W, I, r, p, C); }
+
+// ------------------------------------------------------------------------------ wavelets
+// Gauss-Legendre nodes and weights on [-1, 1] (weights sum to 2): Newton's method on P_n from
+// the usual cosine first guesses, P_n and P_n' from Bonnet's recurrence.
+static void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w) {
+  x.assign((size_t)n, 0.0);
+  w.assign((size_t)n, 0.0);
+  const double pi = 3.14159265358979323846;
+  for (int i = 0; i < n; ++i) {
+    double t = std::cos(pi * (i + 0.75) / (n + 0.5)), dp = 1.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = t;
+      for (int k = 1; k < n; ++k) {
+        const double p2 = ((2.0 * k + 1.0) * t * p1 - k * p0) / (k + 1.0);
+        p0 = p1;
+        p1 = p2;
       }
-      ls_select(Phi, I, n, S, z.data(), c, res, lev);
-      double pr = 0.0;
-      for (int i = 0; i < I; ++i) {
-        const double e = res[(size_t)i] / (1.0 - lev[(size_t)i]);
-        pr += e * e;
-      }
-      pr /= I;
-      if (!(pr == pr)) pr = std::numeric_limits<double>::infinity();
-      press.push_back(pr);
-      coefs.push_back(c);
-      ++used;
-      double rn = 0;
-      for (double t2 : res) rn += t2 * t2;
-      if (std::sqrt(rn) <= 1e-14 * zn) break;
+      const double pn = n == 0 ? 1.0 : p1, pm = n == 0 ? 0.0 : p0;
+      dp = n * (t * pn - pm) / (t * t - 1.0);
+      const double dt = pn / dp;
+      t -= dt;
+      if (std::fabs(dt) <= 1e-16 * std::max(1.0, std::fabs(t))) break;
     }
-    if (used == 0) continue;
-    size_t tb = 0;
-    for (size_t t = 1; t < press.size(); ++t)
-      if (press[t] < press[tb]) tb = t;
-    const std::vector<int>& S = sets[tb];
-    for (size_t l = 0; l < S.size(); ++l) C[(size_t)S[l] * r + j] = coefs[tb][l];
+    {   // derivative at the converged node
+      double p0 = 1.0, p1 = t;
+      for (int k = 1; k < n; ++k) {
+        const double p2 = ((2.0 * k + 1.0) * t * p1 - k * p0) / (k + 1.0);
+        p0 = p1;
+        p1 = p2;
+      }
+      dp = n * (t * p1 - p0) / (t * t - 1.0);
+    }
+    x[(size_t)i] = t;
+    w[(size_t)i] = 2.0 / ((1.0 - t * t) * dp * dp);
   }
 }
 
-void sparse_fit(const double* W, int I, int r, int p, double* C) {
-  if (I < 3 || r < 1 || p < 0) fail(FST_E_INVAL, "sparse_fit: need I >= 3, r >= 1, p >= 0");
-  const int n = p + 1;
-  std::vector<double> Phi((size_t)I * n);
-  for (int i = 0; i < I; ++i) legendre_orthonormal_host(-1.0 + 2.0 * i / (I - 1), p, &Phi[(size_t)i * n]);
-  std::vector<double> colnorm((size_t)n, 0.0);
-  for (int m = 0; m < n; ++m) {
-    double s = 0;
-    for (int i = 0; i < I; ++i) s += Phi[(size_t)i * n + m] * Phi[(size_t)i * n + m];
-    colnorm[(size_t)m] = std::sqrt(s);
+// Mother wavelets psi_0..psi_q of W_{s,q} on [-1, 1]: psi_m(x) = sqrt(2) sum_n H[m][half][n]
+// phi_n(2x + 1) on [-1, 0) (half 0) or phi_n(2x - 1) on [0, 1] (half 1).  In the coordinates of
+// the orthonormal half-cell functions sqrt(2) phi_n(2x -+ 1), psi_m is the unit vector
+// orthogonal to phi_0..phi_{q+m} and to psi_{m+1}..psi_q (found from the top down as the last
+// column of the Q factor of the constraint rows), signed so that its largest right-half
+// coordinate is positive.
+void mother_wavelets_host(int q, double* H) {
+  if (q < 0 || q > kMaxWaveDegree) fail(FST_E_UNSUPPORTED, "wavelet degree out of range");
+  const int nh = q + 1, dim = 2 * nh, nc = 2 * q + 1;
+  std::vector<double> xg, wg;
+  gauss_legendre(2 * q + 2, xg, wg);
+  // M[i][half * nh + n] = <h_{half,n}, phi_i> under dt/2, i = 0..2q
+  std::vector<double> M((size_t)nc * dim, 0.0), h((size_t)nh), g((size_t)2 * q + 1);
+  for (int half = 0; half < 2; ++half)
+    for (size_t k = 0; k < xg.size(); ++k) {
+      const double x = (xg[k] + (half ? 1.0 : -1.0)) / 2.0;
+      legendre_orthonormal_host(xg[k], q, h.data());
+      legendre_orthonormal_host(x, 2 * q, g.data());
+      for (int i = 0; i < nc; ++i)
+        for (int n = 0; n < nh; ++n)
+          M[(size_t)i * dim + half * nh + n] += 0.25 * wg[k] * g[(size_t)i] * std::sqrt(2.0) * h[(size_t)n];
+    }
+  std::vector<std::vector<double>> psi((size_t)nh);
+  for (int m = q; m >= 0; --m) {
+    HouseholderQR qr;   // of A^T, A = the 2q + 1 constraint rows
+    qr.m = dim;
+    qr.n = nc;
+    qr.A.assign((size_t)dim * nc, 0.0);
+    int row = 0;
+    for (int i = 0; i <= q + m; ++i, ++row)
+      for (int c = 0; c < dim; ++c) qr.A[(size_t)row * dim + c] = M[(size_t)i * dim + c];
+    for (int k = m + 1; k <= q; ++k, ++row)
+      for (int c = 0; c < dim; ++c) qr.A[(size_t)row * dim + c] = psi[(size_t)k][(size_t)c];
+    qr.factor();
+    std::vector<double> v((size_t)dim, 0.0);
+    v[(size_t)dim - 1] = 1.0;
+    qr.apply_Q(v.data());
+    int jmax = nh;
+    for (int c = nh + 1; c < dim; ++c)
+      if (std::fabs(v[(size_t)c]) > std::fabs(v[(size_t)jmax])) jmax = c;
+    double nrm = 0.0;
+    for (double t : v) nrm += t * t;
+    nrm = std::sqrt(nrm) * (v[(size_t)jmax] < 0 ? -1.0 : 1.0);
+    for (double& t : v) t /= nrm;
+    psi[(size_t)m] = v;
   }
-  std::fill(C, C + (size_t)n * r, 0.0);
-  std::vector<double> z((size_t)I), res, lev, c;
+  for (int m = 0; m < nh; ++m)
+    for (int c = 0; c < dim; ++c) H[(size_t)m * dim + c] = psi[(size_t)m][(size_t)c];
+}
+
+int detail_count(int s, int q) { return s <= 0 ? 0 : (q + 1) * ((1 << s) - 1); }
+
+// psi_{l,c,m}(t) for every level l < s, in the order (l, c, m), zero off the point's cells
+void detail_values_host(double t, int s, int q, const double* H, double* out) {
+  const int nh = q + 1;
+  std::fill(out, out + detail_count(s, q), 0.0);
+  std::vector<double> ph((size_t)nh);
+  for (int l = 0; l < s; ++l) {
+    const int ncell = 1 << l;
+    const int c = (int)std::min<double>(std::max<double>(std::floor((t + 1.0) * ncell / 2.0), 0.0), ncell - 1);
+    const double x = (t + 1.0) * ncell - 2.0 * c - 1.0;
+    const int half = x >= 0.0 ? 1 : 0;
+    legendre_orthonormal_host(half ? 2.0 * x - 1.0 : 2.0 * x + 1.0, q, ph.data());
+    const double scale = std::sqrt(2.0) * std::pow(2.0, 0.5 * l);
+    for (int m = 0; m < nh; ++m) {
+      double v = 0.0;
+      for (int n = 0; n < nh; ++n) v += H[(size_t)(m * 2 + half) * nh + n] * ph[(size_t)n];
+      out[(size_t)nh * (ncell - 1 + c) + m] = scale * v;
+    }
+  }
+}
+
+// Algorithm 1 steps 5-6 with both spaces: every column is fitted in P_p (rows 0..p of the mode
+// basis) and in W_{s,q} (rows 0..q and the detail rows), and the fit with the smaller
+// leave-one-out error is kept (P_p on ties).  C: (p + 1 + detail_count) x r row-major.
+void sparse_fit_choice(const double* W, int I, int r, int p, int s, int q, int solver, double* C) {
+  if (I < 3 || r < 1 || p < 0) fail(FST_E_INVAL, "sparse_fit: need I >= 3, r >= 1, p >= 0");
+  if (s < 1 || q < 0 || q > p || q > kMaxWaveDegree || detail_count(s, q) > kMaxDetail)
+    fail(FST_E_INVAL, "wavelet space: need s >= 1, 0 <= q <= p, q <= 7 and (q + 1)(2^s - 1) <= 128");
+  const int nd = detail_count(s, q), nrow = p + 1 + nd, nw = q + 1 + nd;
+  std::vector<double> H((size_t)(q + 1) * 2 * (q + 1)), dv((size_t)nd);
+  mother_wavelets_host(q, H.data());
+  std::vector<double> PL = legendre_at_nodes(I, p), PW((size_t)I * nw);
+  for (int i = 0; i < I; ++i) {
+    const double t = -1.0 + 2.0 * i / (I - 1);
+    for (int n = 0; n <= q; ++n) PW[(size_t)i * nw + n] = PL[(size_t)i * (p + 1) + n];
+    detail_values_host(t, s, q, H.data(), dv.data());
+    for (int e = 0; e < nd; ++e) PW[(size_t)i * nw + q + 1 + e] = dv[(size_t)e];
+  }
+  const NodeBasis BL = node_basis(PL, I, p + 1), BW = node_basis(PW, I, nw);
+  std::fill(C, C + (size_t)nrow * r, 0.0);
+  std::vector<double> z((size_t)I);
   for (int j = 0; j < r; ++j) {
     for (int i = 0; i < I; ++i) z[(size_t)i] = W[(size_t)i * r + j];
-    double zn = 0;
-    for (double t : z) zn += t * t;
-    zn = std::sqrt(zn);
-    if (zn == 0.0) continue;
-    std::vector<int> S;
-    std::vector<std::vector<double>> coefs;
-    std::vector<double> press;
-    std::vector<double> rcur = z;
-    const int tmax = std::min(n, I - 2);
-    for (int t = 0; t < tmax; ++t) {
-      int best = -1;
-      double bscore = -1.0;
-      for (int m = 0; m < n; ++m) {
-        if (std::find(S.begin(), S.end(), m) != S.end()) continue;
-        double s = 0;
-        for (int i = 0; i < I; ++i) s += Phi[(size_t)i * n + m] * rcur[(size_t)i];
-        double score = std::fabs(s) / colnorm[(size_t)m];
-        if (score > bscore) {
-          bscore = score;
-          best = m;
-        }
+    const ColumnFit fl = fit_column(solver, BL, z.data()), fw = fit_column(solver, BW, z.data());
+    if (fl.S.empty() && fw.S.empty()) continue;
+    if (!fl.S.empty() && (fw.S.empty() || fl.press <= fw.press)) {
+      for (size_t l = 0; l < fl.S.size(); ++l) C[(size_t)fl.S[l] * r + j] = fl.c[l];
+    } else {
+      for (size_t l = 0; l < fw.S.size(); ++l) {
+        const int col = fw.S[l], rowi = col <= q ? col : p + 1 + (col - q - 1);
+        C[(size_t)rowi * r + j] = fw.c[l];
       }
-      S.push_back(best);
-      ls_select(Phi, I, n, S, z.data(), c, res, lev);
-      double pr = 0.0;
-      for (int i = 0; i < I; ++i) {
-        double e = res[(size_t)i] / (1.0 - lev[(size_t)i]);
-        pr += e * e;
-      }
-      pr /= I;
-      if (!(pr == pr)) pr = std::numeric_limits<double>::infinity();
-      press.push_back(pr);
-      coefs.push_back(c);
-      rcur = res;
-      double rn = 0;
-      for (double t2 : res) rn += t2 * t2;
-      if (std::sqrt(rn) <= 1e-14 * zn) break;
     }
-    size_t tb = 0;
-    for (size_t t = 1; t < press.size(); ++t)
-      if (press[t] < press[tb]) tb = t;
-    for (size_t l = 0; l <= tb; ++l) C[(size_t)S[l] * r + j] = coefs[tb][l];
   }
 }
 

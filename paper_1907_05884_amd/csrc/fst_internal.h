@@ -18,6 +18,9 @@ namespace fst {
 constexpr int kMaxRank = 32;     // r_k limit of this version
 constexpr int kMaxBasis = 32;    // n_k = p_k + 1 limit of this version
 constexpr int kMaxModes = 4;     // d = 3 (the 3-way calls) or 4 (the d-way calls)
+constexpr int kMaxWaveDegree = 7;   // q of a wavelet space W_{s,q}
+constexpr int kMaxDetail = 128;     // (q + 1)(2^s - 1) detail functions per mode at most
+constexpr int kWaveTable = 2 * (kMaxWaveDegree + 1) * (kMaxWaveDegree + 1);   // mother wavelets per mode
 
 // Error carried from deep inside the library to the C ABI boundary, where it becomes a
 // status code plus a thread-local message.
@@ -32,6 +35,8 @@ void set_last_error(const std::string& msg);
 // kMaxBasis x kMaxRank per mode (kMaxModes slots, unused modes zero), and the core in C order.
 struct DeviceModel {
   void* coefs = nullptr;   // kMaxModes * kMaxBasis * kMaxRank elements of the dtype
+  void* detail = nullptr;  // models with wavelets: kMaxModes * kMaxDetail * kMaxRank detail coefficients
+  void* wave = nullptr;    // models with wavelets: kMaxModes * kWaveTable mother-wavelet coefficients
   void* core = nullptr;    // R elements of the dtype
   void* core64 = nullptr;  // R doubles (for refinement), only for dtype FP64 copy
 };
@@ -54,8 +59,10 @@ struct fst_model {
   int32_t d = 3;                  // modes; entries k >= d of the arrays below are unused
   double lo[4] = {0, 0, 0, 0}, hi[4] = {1, 1, 1, 1};
   int32_t rank[4] = {1, 1, 1, 1}, degree[4] = {0, 0, 0, 0};
+  // wavelet space W_{s,q} held beside P_p in mode k (s = wlevel[k] > 0, q = wdegree[k] <= p)
+  int32_t wlevel[4] = {0, 0, 0, 0}, wdegree[4] = {0, 0, 0, 0};
   std::vector<double> core;      // r1 .. rd, C order
-  std::vector<double> coef[4];   // (p_k + 1) x r_k row-major
+  std::vector<double> coef[4];   // rows(k) x r_k row-major: phi_0..phi_p, then the detail functions
   fst::SolveInfo fit;             // how the core was solved (models from a refit)
   // lazily uploaded device copies, keyed by (device ordinal, dtype)
   mutable std::mutex mu;
@@ -70,6 +77,13 @@ struct fst_model {
     int s = 0;
     for (int k = 0; k < d; ++k) s += rank[k];
     return s;
+  }
+  int details(int k) const { return wlevel[k] > 0 ? (wdegree[k] + 1) * ((1 << wlevel[k]) - 1) : 0; }
+  int rows(int k) const { return degree[k] + 1 + details(k); }
+  bool has_wavelets() const {
+    for (int k = 0; k < d; ++k)
+      if (wlevel[k] > 0) return true;
+    return false;
   }
 };
 
@@ -99,9 +113,19 @@ void sthosvd_eps_d(const double* T, int D, const int32_t* dims, double eps, cons
                    int32_t* rank_out, double* core, double* const* W, double* const* sigma);
 void sparse_fit(const double* W, int I, int r, int p, double* C);
 void sparse_fit_lars(const double* W, int I, int r, int p, double* C);
-// the sparse fit of one factor matrix with the chosen solver (FST_SOLVER_*)
-inline void sparse_fit_with(int solver, const double* W, int I, int r, int p, double* C) {
-  if (solver == FST_SOLVER_LARS)
+// wavelet space W_{s,q}: mother wavelets H[(m * 2 + half) * (q + 1) + n], the number of detail
+// functions, their values at t (order (l, c, m)), and the per-column choice between P_p and
+// W_{s,q} (C: (p + 1 + detail_count) x r)
+void mother_wavelets_host(int q, double* H);
+int detail_count(int s, int q);
+void detail_values_host(double t, int s, int q, const double* H, double* out);
+void sparse_fit_choice(const double* W, int I, int r, int p, int s, int q, int solver, double* C);
+// the sparse fit of one factor matrix with the chosen solver (FST_SOLVER_*), and with the
+// choice against W_{s,q} when s > 0
+inline void sparse_fit_with(int solver, const double* W, int I, int r, int p, double* C, int s = 0, int q = 0) {
+  if (s > 0)
+    sparse_fit_choice(W, I, r, p, s, q, solver, C);
+  else if (solver == FST_SOLVER_LARS)
     sparse_fit_lars(W, I, r, p, C);
   else
     sparse_fit(W, I, r, p, C);
@@ -112,7 +136,8 @@ int hardware_threads(int requested);
 // ---------------------------------------------------------------- model (fst_model.cpp)
 fst_model* model_new(const double lo[3], const double hi[3], const int32_t rank[3],
                      const int32_t degree[3]);
-fst_model* model_new_d(int d, const double* lo, const double* hi, const int32_t* rank, const int32_t* degree);
+fst_model* model_new_d(int d, const double* lo, const double* hi, const int32_t* rank, const int32_t* degree,
+                       const int32_t* wlevel = nullptr, const int32_t* wdegree = nullptr);
 fst_model* copy_with_core(const fst_model* m, const std::vector<double>& core);
 void check_model(const fst_model* m);    // any d
 void check_model3(const fst_model* m);   // the 3-way calls: d = 3 only

@@ -1,5 +1,6 @@
 // The functional sparse Tucker model object (eq. (1)-(2)): validation, device copies and a
 // versioned binary serialisation.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 
@@ -10,6 +11,8 @@ fst_model::~fst_model() {
     fst::device_free(kv.second.coefs);
     fst::device_free(kv.second.core);
     fst::device_free(kv.second.core64);
+    fst::device_free(kv.second.detail);
+    fst::device_free(kv.second.wave);
   }
 }
 
@@ -20,8 +23,16 @@ fst_model* model_new(const double lo[3], const double hi[3], const int32_t rank[
   return model_new_d(3, lo, hi, rank, degree);
 }
 
-fst_model* model_new_d(int d, const double* lo, const double* hi, const int32_t* rank, const int32_t* degree) {
+fst_model* model_new_d(int d, const double* lo, const double* hi, const int32_t* rank, const int32_t* degree,
+                       const int32_t* wlevel, const int32_t* wdegree) {
   if (d != 3 && d != 4) fail(FST_E_UNSUPPORTED, "model: only d = 3 and d = 4 are supported");
+  if (wlevel)
+    for (int k = 0; k < d; ++k) {
+      if (wlevel[k] < 0 || wlevel[k] > 7) fail(FST_E_INVAL, "model: wavelet level must be in [0, 7]");
+      if (wlevel[k] > 0 && (!wdegree || wdegree[k] < 0 || wdegree[k] > std::min(degree[k], kMaxWaveDegree) ||
+                            detail_count(wlevel[k], wdegree[k]) > kMaxDetail))
+        fail(FST_E_INVAL, "model: wavelet degree must be in [0, min(p, 7)] with (q + 1)(2^s - 1) <= 128");
+    }
   for (int k = 0; k < d; ++k) {
     if (!(std::isfinite(lo[k]) && std::isfinite(hi[k]) && hi[k] > lo[k]))
       fail(FST_E_INVAL, "model: need finite lo < hi in every mode");
@@ -37,7 +48,9 @@ fst_model* model_new_d(int d, const double* lo, const double* hi, const int32_t*
     m->hi[k] = hi[k];
     m->rank[k] = rank[k];
     m->degree[k] = degree[k];
-    m->coef[k].assign((size_t)(degree[k] + 1) * rank[k], 0.0);
+    m->wlevel[k] = wlevel ? wlevel[k] : 0;
+    m->wdegree[k] = m->wlevel[k] > 0 ? wdegree[k] : 0;
+    m->coef[k].assign((size_t)m->rows(k) * rank[k], 0.0);
   }
   m->core.assign((size_t)m->R(), 0.0);
   return m;
@@ -53,14 +66,15 @@ void check_model3(const fst_model* m) {
 }
 
 fst_model* copy_with_core(const fst_model* m, const std::vector<double>& core) {
-  fst_model* out = model_new_d(m->d, m->lo, m->hi, m->rank, m->degree);
+  fst_model* out = model_new_d(m->d, m->lo, m->hi, m->rank, m->degree, m->wlevel, m->wdegree);
   for (int k = 0; k < m->d; ++k) out->coef[k] = m->coef[k];
   out->core = core;
   return out;
 }
 
 template <class T>
-static void pack_model(const fst_model* m, std::vector<T>& coefs, std::vector<T>& core) {
+static void pack_model(const fst_model* m, std::vector<T>& coefs, std::vector<T>& core, std::vector<T>& detail,
+                       std::vector<T>& wave) {
   coefs.assign((size_t)kMaxModes * kMaxBasis * kMaxRank, T(0));
   for (int k = 0; k < m->d; ++k) {
     const int n = m->degree[k] + 1, r = m->rank[k];
@@ -70,6 +84,33 @@ static void pack_model(const fst_model* m, std::vector<T>& coefs, std::vector<T>
   }
   core.resize(m->core.size());
   for (size_t i = 0; i < core.size(); ++i) core[i] = (T)m->core[i];
+  detail.clear();
+  wave.clear();
+  if (!m->has_wavelets()) return;
+  detail.assign((size_t)kMaxModes * kMaxDetail * kMaxRank, T(0));
+  wave.assign((size_t)kMaxModes * kWaveTable, T(0));
+  for (int k = 0; k < m->d; ++k) {
+    if (m->wlevel[k] == 0) continue;
+    const int n = m->degree[k] + 1, r = m->rank[k], q = m->wdegree[k];
+    for (int e = 0; e < m->details(k); ++e)
+      for (int j = 0; j < r; ++j)
+        detail[(size_t)(k * kMaxDetail + e) * kMaxRank + j] = (T)m->coef[k][(size_t)(n + e) * r + j];
+    // mother wavelets in a fixed stride: [m][half][n] with kMaxWaveDegree + 1 entries per index
+    std::vector<double> H((size_t)2 * (q + 1) * (q + 1));
+    mother_wavelets_host(q, H.data());
+    for (int mm = 0; mm <= q; ++mm)
+      for (int half = 0; half < 2; ++half)
+        for (int nn = 0; nn <= q; ++nn)
+          wave[(size_t)k * kWaveTable + (size_t)((mm * 2 + half) * (kMaxWaveDegree + 1) + nn)] =
+              (T)H[(size_t)(mm * 2 + half) * (q + 1) + nn];
+  }
+}
+
+template <class T>
+static void upload(void*& dst, const std::vector<T>& v) {
+  if (v.empty()) return;
+  dst = device_alloc(v.size() * sizeof(T));
+  copy_h2d(dst, v.data(), v.size() * sizeof(T), nullptr);
 }
 
 const DeviceModel& device_model(const fst_model* m, int dtype) {
@@ -80,19 +121,19 @@ const DeviceModel& device_model(const fst_model* m, int dtype) {
   if (it != m->dev.end()) return it->second;
   DeviceModel dm;
   if (dtype == FST_F64) {
-    std::vector<double> c, a;
-    pack_model(m, c, a);
-    dm.coefs = device_alloc(c.size() * sizeof(double));
-    dm.core = device_alloc(a.size() * sizeof(double));
-    copy_h2d(dm.coefs, c.data(), c.size() * sizeof(double), nullptr);
-    copy_h2d(dm.core, a.data(), a.size() * sizeof(double), nullptr);
+    std::vector<double> c, a, dt, wv;
+    pack_model(m, c, a, dt, wv);
+    upload(dm.coefs, c);
+    upload(dm.core, a);
+    upload(dm.detail, dt);
+    upload(dm.wave, wv);
   } else {
-    std::vector<float> c, a;
-    pack_model(m, c, a);
-    dm.coefs = device_alloc(c.size() * sizeof(float));
-    dm.core = device_alloc(a.size() * sizeof(float));
-    copy_h2d(dm.coefs, c.data(), c.size() * sizeof(float), nullptr);
-    copy_h2d(dm.core, a.data(), a.size() * sizeof(float), nullptr);
+    std::vector<float> c, a, dt, wv;
+    pack_model(m, c, a, dt, wv);
+    upload(dm.coefs, c);
+    upload(dm.core, a);
+    upload(dm.detail, dt);
+    upload(dm.wave, wv);
   }
   stream_sync(nullptr);
   return m->dev.emplace(key, dm).first->second;
@@ -102,7 +143,8 @@ const DeviceModel& device_model(const fst_model* m, int dtype) {
 
 // ------------------------------------------------------------------------------ serialisation
 // Layout (little endian):
-//   "FSTM" | u32 version=1 | u32 d (3 or 4) | f64 lo[d] | f64 hi[d] | i32 rank[d] | i32 degree[d]
+//   "FSTM" | u32 version (1, or 2 with wavelets) | u32 d (3 or 4) | f64 lo[d] | f64 hi[d]
+//   | i32 rank[d] | i32 degree[d] | version 2: i32 wlevel[d], i32 wdegree[d]
 //   | f64 core[R] | per mode: i32 nnz, i32 colptr[r+1], u8 row[nnz], f64 val[nnz]
 //   | u64 FNV-1a checksum of all preceding bytes
 namespace {
@@ -135,15 +177,20 @@ uint64_t fnv1a(const unsigned char* p, size_t n) {
 std::vector<unsigned char> serialise(const fst_model* m) {
   Writer w;
   w.b.insert(w.b.end(), {'F', 'S', 'T', 'M'});
-  w.put<uint32_t>(1);
+  const bool wav = m->has_wavelets();
+  w.put<uint32_t>(wav ? 2 : 1);
   w.put<uint32_t>((uint32_t)m->d);
   for (int k = 0; k < m->d; ++k) w.put<double>(m->lo[k]);
   for (int k = 0; k < m->d; ++k) w.put<double>(m->hi[k]);
   for (int k = 0; k < m->d; ++k) w.put<int32_t>(m->rank[k]);
   for (int k = 0; k < m->d; ++k) w.put<int32_t>(m->degree[k]);
+  if (wav) {
+    for (int k = 0; k < m->d; ++k) w.put<int32_t>(m->wlevel[k]);
+    for (int k = 0; k < m->d; ++k) w.put<int32_t>(m->wdegree[k]);
+  }
   for (double c : m->core) w.put<double>(c);
   for (int k = 0; k < m->d; ++k) {
-    const int n = m->degree[k] + 1, r = m->rank[k];
+    const int n = m->rows(k), r = m->rank[k];
     std::vector<int32_t> colptr(1, 0);
     std::vector<uint8_t> rows;
     std::vector<double> vals;
@@ -202,7 +249,7 @@ fst_status fst_model_load(const void* buf, size_t nbytes, fst_model** out) {
     Reader r{p, nbytes, 4};
     uint32_t version = r.get<uint32_t>();
     uint32_t d = r.get<uint32_t>();
-    if (version != 1) fst::fail(FST_E_FORMAT, "unknown model version");
+    if (version != 1 && version != 2) fst::fail(FST_E_FORMAT, "unknown model version");
     if (d != 3 && d != 4) fst::fail(FST_E_UNSUPPORTED, "only d = 3 and d = 4 models are supported");
     double lo[4], hi[4];
     int32_t rank[4], degree[4];
@@ -213,11 +260,20 @@ fst_status fst_model_load(const void* buf, size_t nbytes, fst_model** out) {
     for (uint32_t k = 0; k < d; ++k)
       if (rank[k] < 1 || rank[k] > fst::kMaxRank || degree[k] < 0 || degree[k] + 1 > fst::kMaxBasis)
         fst::fail(FST_E_FORMAT, "model header out of range");
-    m = fst::model_new_d((int)d, lo, hi, rank, degree);
+    int32_t wl[4] = {0, 0, 0, 0}, wd[4] = {0, 0, 0, 0};
+    if (version == 2) {
+      for (uint32_t k = 0; k < d; ++k) wl[k] = r.get<int32_t>();
+      for (uint32_t k = 0; k < d; ++k) wd[k] = r.get<int32_t>();
+    }
+    try {
+      m = fst::model_new_d((int)d, lo, hi, rank, degree, wl, wd);
+    } catch (const fst::Error&) {
+      fst::fail(FST_E_FORMAT, "model header out of range");
+    }
     if (r.n - r.off < sizeof(double) * m->core.size()) fst::fail(FST_E_FORMAT, "model buffer is truncated");
     for (auto& c : m->core) c = r.get<double>();
     for (uint32_t k = 0; k < d; ++k) {
-      const int n = degree[k] + 1, rk = rank[k];
+      const int n = m->rows((int)k), rk = rank[k];
       int32_t nnz = r.get<int32_t>();
       if (nnz < 0 || nnz > n * rk) fst::fail(FST_E_FORMAT, "bad coefficient count");
       std::vector<int32_t> colptr((size_t)rk + 1);

@@ -449,3 +449,66 @@ def test_compress_host_with_lars_matches_oracle():
         np.testing.assert_allclose(m4.coefs(k), mo4.coefs[k], rtol=1e-7, atol=1e-9)
     bad = fst.make_params(sparse_solver=7)
     assert fst._fn["fst_fit_workspace_bytes"](ctypes.byref(bad), 10000) == 0
+
+
+@pytest.mark.parametrize("solver", ["omp", "lars"])
+@pytest.mark.parametrize("s,q", [(3, 2), (2, 5), (4, 1)])
+def test_sparse_fit_choice_matches_oracle(solver, s, q):
+    nodes = interp.grid_nodes(48)
+    rng = np.random.default_rng(s * 10 + q)
+    # (|t - 0.1| carries noise: exactly piecewise linear, its PRESS path has steps of equal
+    # PRESS to rounding, where either support is a valid answer)
+    W = np.stack([1 + nodes - 0.5 * nodes ** 3, np.where(nodes < 0.25, -1.0, 2.0),
+                  np.exp(-nodes ** 2) + 1e-3 * rng.standard_normal(48),
+                  np.abs(nodes - 0.1) + 1e-3 * rng.standard_normal(48), np.sin(9 * nodes)], axis=1)
+    p = 11
+    ref = sparsefit.fit_factor_choice(W, nodes, p, s, q, solver=solver)
+    code = fst.FST_SOLVER_LARS if solver == "lars" else fst.FST_SOLVER_OMP
+    got = fst.fst_sparse_fit_choice(W, p, s, q, solver=code)
+    np.testing.assert_array_equal(got != 0, ref != 0)
+    np.testing.assert_allclose(got, ref, rtol=1e-8, atol=1e-11)
+    assert np.any(got[p + 1:] != 0)          # some column keeps the wavelet fit
+
+
+def test_compress_host_with_wavelets_matches_oracle():
+    w = datagen.small_f64(n=6000, n_samples=1500)
+    grid, rank, degree, wav = (16, 16, 16), (6, 5, 4), (9, 9, 9), (2, 3)
+    p = fst.make_params(dtype=fst.FST_F64, lo=w.lo, hi=w.hi, grid=grid, rank=rank, degree=degree,
+                        interp_fraction=0.2, n_samples=1500, seed=w.seed, wavelet=wav)
+    m = fst.fst_compress_host(p, *w.soa())
+    mo = pipeline.compress(w.pts, w.vals, w.lo, w.hi, grid, rank, degree, 0.2, w.seed, wavelet=wav)
+    assert m.wavelets() == ((2, 3),) * 3
+    np.testing.assert_allclose(m.core, mo.core, rtol=1e-8, atol=1e-9)
+    for k in range(3):
+        np.testing.assert_array_equal(m.coefs(k) != 0, mo.coefs[k] != 0)
+        np.testing.assert_allclose(m.coefs(k), mo.coefs[k], rtol=1e-7, atol=1e-9)
+    assert m.paper_bytes() == mo.paper_bytes()
+    blob = fst.fst_model_save(m)
+    m2 = fst.fst_model_load(blob)
+    assert m2.wavelets() == m.wavelets() and fst.fst_model_save(m2) == blob
+    for k in range(3):
+        np.testing.assert_array_equal(m2.coefs(k), m.coefs(k))
+    # 4-way data through the d-way compress
+    w4 = _workload4()
+    p4 = fst.make_params_d(d=4, dtype=fst.FST_F64, lo=w4.lo, hi=w4.hi, grid=(8,) * 4, rank=(3, 3, 2, 2),
+                           degree=(6,) * 4, interp_fraction=0.3, n_samples=1000, seed=w4.seed, wavelet=(2, 1))
+    m4 = fst.fst_compress_host_d(p4, w4.soa()[:4], w4.soa()[4])
+    mo4 = pipeline.compress(w4.pts, w4.vals, w4.lo, w4.hi, (8,) * 4, (3, 3, 2, 2), (6,) * 4, 0.3, w4.seed,
+                            wavelet=(2, 1))
+    for k in range(4):
+        np.testing.assert_array_equal(m4.coefs(k) != 0, mo4.coefs[k] != 0)
+        np.testing.assert_allclose(m4.coefs(k), mo4.coefs[k], rtol=1e-7, atol=1e-9)
+
+
+def test_wavelet_parameters_are_validated():
+    for wav in [(8, 0), (2, 12), (7, 1), (-1, 0)]:      # level, degree > p, too many details, level
+        p = fst.make_params(degree=(9, 9, 9), wavelet=wav)
+        assert fst._fn["fst_fit_workspace_bytes"](ctypes.byref(p), 10000) == 0
+    core, coefs = datagen.random_model_parts(1, (2, 2, 2), (4, 4, 4))
+    with pytest.raises(ValueError):
+        fst.fst_model_from_parts((-1.0,) * 3, (1.0,) * 3, (2, 2, 2), (4, 4, 4), core, coefs,
+                                 wavelet=((1, 1),) * 3)     # coefficient rows do not match
+    big = [np.zeros((5 + 2 * 1, 2)), np.zeros((5 + 2 * 1, 2)), np.zeros((5 + 2 * 511, 2))]
+    with pytest.raises(fst.FstError):
+        fst.fst_model_from_parts((-1.0,) * 3, (1.0,) * 3, (2, 2, 2), (4, 4, 4), core, big,
+                                 wavelet=((1, 1), (1, 1), (9, 1)))
