@@ -68,6 +68,64 @@ static inline ModeMap<T> make_map(const fst_model* m) {
 
 static inline int pad8(int r) { return (r + 7) / 8 * 8; }
 
+// Wavelet details of one mode (W_{s,q} beside P_p): for reference coordinate t, calls
+// f(row, value) for the q + 1 functions psi_{l,c,m}(t) of the point's cell c at every level
+// l < s, with row = (q + 1)(2^l - 1 + c) + m the detail row of the coefficient matrix.
+// psi_{l,c,m}(t) = 2^(l/2) psi_m(x), x = 2^l (t + 1) - 2c - 1, c = floor((t + 1) 2^(l-1))
+// clamped to the level's cells; psi_m(x) = sqrt(2) sum_n wave[(m * 2 + half) * 8 + n]
+// phi_n(2x -+ 1) on the half of [-1, 1] that holds x.  Loops run to the largest degree with
+// predicates, so every array index is static.
+template <typename T, typename F>
+__device__ inline void for_each_detail(T t, int s, int q, const T* __restrict__ wave, const Recurrence<T>& rec,
+                                       F&& f) {
+  T scale = T(1.4142135623730951);   // sqrt(2) 2^(l/2) at level l
+  for (int l = 0; l < s; ++l) {
+    const int ncell = 1 << l;
+    T cf = floor((t + T(1)) * T(0.5) * T(ncell));
+    cf = cf < T(0) ? T(0) : (cf > T(ncell - 1) ? T(ncell - 1) : cf);
+    const int c = (int)cf;
+    const T x = (t + T(1)) * T(ncell) - T(2 * c + 1);
+    const int half = x >= T(0) ? 1 : 0;
+    const T y = half ? T(2) * x - T(1) : T(2) * x + T(1);
+    T ph[kMaxWaveDegree + 1];
+    ph[0] = T(1);
+    {
+      T pm1 = T(1), pm = y * rec.a[0];
+#pragma unroll
+      for (int n = 1; n <= kMaxWaveDegree; ++n) {
+        ph[n] = pm;
+        const T pn = rec.a[n] * y * pm - rec.b[n] * pm1;
+        pm1 = pm;
+        pm = pn;
+      }
+    }
+    const int base = (q + 1) * (ncell - 1 + c);
+#pragma unroll
+    for (int m = 0; m <= kMaxWaveDegree; ++m) {
+      if (m > q) break;
+      const T* w = wave + (m * 2 + half) * (kMaxWaveDegree + 1);
+      T v = T(0);
+#pragma unroll
+      for (int n = 0; n <= kMaxWaveDegree; ++n)
+        if (n <= q) v += w[n] * ph[n];
+      f(base + m, scale * v);
+    }
+    scale *= T(1.4142135623730951);
+  }
+}
+
+// u[j] += sum over the point's detail functions of mode k of detail_k[row][j] psi(t), j < RP
+// (detail_k: [kMaxDetail][kMaxRank]); u stays in registers (static indices only)
+template <typename T, int RP>
+__device__ __forceinline__ void add_details(T (&u)[RP], T t, int s, int q, const T* __restrict__ wave,
+                                            const T* __restrict__ detail_k, const Recurrence<T>& rec) {
+  for_each_detail(t, s, q, wave, rec, [&](int row, T v) {
+    const T* dr = detail_k + row * kMaxRank;
+#pragma unroll
+    for (int j = 0; j < RP; ++j) u[j] += dr[j] * v;
+  });
+}
+
 // lower-triangle tile t -> (bi, bj), bj <= bi, t = bi (bi + 1) / 2 + bj
 __device__ inline void tri_tile(int64_t t, int64_t& bi, int64_t& bj) {
   int64_t b = (int64_t)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);

@@ -376,8 +376,160 @@ static void eval4_t(const fst_model* m, const DeviceModel& dm, int64_t n, const 
 #undef FST_EVAL4_RP
 }
 
+// ------------------------------------------------------------------------------ wavelet models
+// eq. (1) for models whose modes hold wavelet details (d = 3 or 4), one thread per point and
+// no cross-thread work: the thread builds the factor values of each mode in its own LDS
+// column (basis values, then the Legendre sums, then the detail sums of the point's cells),
+// keeps the last mode's RP values in registers (rows past r zero) and contracts the core in
+// a fixed order, reading core entries with wave-uniform addresses (indices clamped into the
+// core, where they meet a zero factor value).  With residual != 0 it writes v[idx[q]] - f.
+template <typename TIn, typename T>
+struct EvalWaveArgs {
+  const TIn* c[kMaxModes];
+  const TIn* v;
+  const int32_t* idx;
+  const T* coefs;     // [kMaxModes][kMaxBasis][kMaxRank]
+  const T* detail;    // [kMaxModes][kMaxDetail][kMaxRank]
+  const T* wave;      // [kMaxModes][kWaveTable]
+  const T* core;
+  void* out;          // TIn (eval) or T (residual)
+  int64_t n;
+  int32_t d, residual;
+  int32_t r[kMaxModes], nb[kMaxModes], wl[kMaxModes], wq[kMaxModes], off[kMaxModes];
+  ModeMap<T> map;
+  Recurrence<T> rec;
+};
+
+constexpr int EW_THREADS = 64;
+
+template <typename TIn, typename T, int RP>
+__global__ __launch_bounds__(EW_THREADS) void k_eval_wave(EvalWaveArgs<TIn, T> a) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int st = blockDim.x, me = threadIdx.x;
+  T* sPhi = reinterpret_cast<T*>(smem_raw) + me;     // [kMaxBasis][st]
+  T* sU = reinterpret_cast<T*>(smem_raw) + (size_t)kMaxBasis * st + me;   // [rows][st]
+  const int last = a.d - 1;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < a.n; q += stride) {
+    const int64_t i = a.idx ? (int64_t)a.idx[q] : q;
+    for (int k = 0; k < a.d; ++k) {
+      const T t = ((T)a.c[k][i] - a.map.lo[k]) * a.map.scale[k] - T(1);
+      {
+        T pm1 = T(1), pm = t * a.rec.a[0];
+        sPhi[0] = T(1);
+        for (int m = 1; m < a.nb[k]; ++m) {
+          sPhi[m * st] = pm;
+          const T pn = a.rec.a[m] * t * pm - a.rec.b[m] * pm1;
+          pm1 = pm;
+          pm = pn;
+        }
+      }
+      T* col = sU + (size_t)a.off[k] * st;
+      const T* Ck = a.coefs + (size_t)k * kMaxBasis * kMaxRank;
+      const int rows = k == last ? RP : a.r[k];
+      for (int j = 0; j < rows; ++j) {
+        T u = T(0);
+        if (j < a.r[k])
+          for (int m = 0; m < a.nb[k]; ++m) u += Ck[m * kMaxRank + j] * sPhi[m * st];
+        col[j * st] = u;
+      }
+      if (a.wl[k] > 0) {
+        const T* dk = a.detail + (size_t)k * kMaxDetail * kMaxRank;
+        const int rk = a.r[k];
+        for_each_detail(t, a.wl[k], a.wq[k], a.wave + k * kWaveTable, a.rec, [&](int row, T val) {
+          const T* dr = dk + row * kMaxRank;
+          for (int j = 0; j < rk; ++j) col[j * st] += dr[j] * val;
+        });
+      }
+    }
+    T ul[RP];
+#pragma unroll
+    for (int j = 0; j < RP; ++j) ul[j] = sU[(size_t)(a.off[last] + j) * st];
+    const int rl = a.r[last];
+    // sum over the leading modes (two for d = 3, three for d = 4) of their factor values times
+    // the inner contraction with the last mode
+    const int64_t lead = a.d == 3 ? (int64_t)a.r[0] * a.r[1] : (int64_t)a.r[0] * a.r[1] * a.r[2];
+    T acc = T(0);
+    for (int64_t p = 0; p < lead; ++p) {
+      T w = T(1);
+      int64_t rem = p;
+      for (int k = a.d - 2; k >= 0; --k) {
+        const int jk = (int)(rem % a.r[k]);
+        rem /= a.r[k];
+        w *= sU[(size_t)(a.off[k] + jk) * st];
+      }
+      const T* cp = a.core + p * rl;
+      T s = T(0);
+#pragma unroll
+      for (int j = 0; j < RP; ++j) s += cp[j < rl ? j : rl - 1] * ul[j];
+      acc += w * s;
+    }
+    if (a.residual)
+      reinterpret_cast<T*>(a.out)[q] = (T)a.v[i] - acc;
+    else
+      reinterpret_cast<TIn*>(a.out)[q] = (TIn)acc;
+  }
+}
+
+template <typename TIn, typename T>
+static void eval_wave_t(const fst_model* m, const DeviceModel& dm, int64_t n, const void* const* coords,
+                        const int32_t* idx, const void* v, void* out, bool residual, void* stream) {
+  if (!dm.detail || !dm.wave) fail(FST_E_DEVICE, "reconstruction: wavelet tables missing");
+  EvalWaveArgs<TIn, T> a;
+  a.d = m->d;
+  int off = 0;
+  for (int k = 0; k < kMaxModes; ++k) {
+    const bool live = k < m->d;
+    a.c[k] = live ? (const TIn*)coords[k] : nullptr;
+    a.r[k] = live ? m->rank[k] : 1;
+    a.nb[k] = live ? m->degree[k] + 1 : 0;
+    a.wl[k] = live ? m->wlevel[k] : 0;
+    a.wq[k] = live ? m->wdegree[k] : 0;
+    a.off[k] = off;
+    off += live ? (k == m->d - 1 ? kMaxRank : m->rank[k]) : 0;
+  }
+  a.v = (const TIn*)v;
+  a.idx = idx;
+  a.coefs = (const T*)dm.coefs;
+  a.detail = (const T*)dm.detail;
+  a.wave = (const T*)dm.wave;
+  a.core = (const T*)dm.core;
+  a.out = out;
+  a.n = n;
+  a.residual = residual ? 1 : 0;
+  a.map = make_map<T>(m);
+  a.rec = make_recurrence<T>();
+  const size_t lds = sizeof(T) * (size_t)EW_THREADS * (kMaxBasis + off);
+  const int64_t blocks = std::min<int64_t>((n + EW_THREADS - 1) / EW_THREADS, (int64_t)device_cu_count() * 16);
+  if (blocks < 1) return;
+  const int rp = pad8(m->rank[m->d - 1]);
+  const dim3 g((unsigned)blocks), b(EW_THREADS);
+  switch (rp) {
+    case 8: hipLaunchKernelGGL((k_eval_wave<TIn, T, 8>), g, b, lds, S(stream), a); break;
+    case 16: hipLaunchKernelGGL((k_eval_wave<TIn, T, 16>), g, b, lds, S(stream), a); break;
+    case 24: hipLaunchKernelGGL((k_eval_wave<TIn, T, 24>), g, b, lds, S(stream), a); break;
+    default: hipLaunchKernelGGL((k_eval_wave<TIn, T, 32>), g, b, lds, S(stream), a); break;
+  }
+  check_launch("k_eval_wave");
+}
+
+void launch_eval_wave(const fst_model* m, const DeviceModel& dm, int dtype, int in_dtype, int64_t n,
+                      const void* const* coords, const int32_t* idx, const void* v, void* out, bool residual,
+                      void* stream) {
+  if (dtype == FST_F64 && in_dtype == FST_F64)
+    eval_wave_t<double, double>(m, dm, n, coords, idx, v, out, residual, stream);
+  else if (dtype == FST_F64)
+    eval_wave_t<float, double>(m, dm, n, coords, idx, v, out, residual, stream);
+  else
+    eval_wave_t<float, float>(m, dm, n, coords, idx, v, out, residual, stream);
+}
+
 void launch_eval_d(const fst_model* m, const DeviceModel& dm, int dtype, int64_t n, const void* const* coords,
                    void* out, void* stream) {
+  if (m->has_wavelets()) {
+    launch_eval_wave(m, dm, dtype, dtype, n, coords, nullptr, nullptr, out, false, stream);
+    return;
+  }
   if (m->d == 3) {
     launch_eval(m, dm, dtype, n, coords[0], coords[1], coords[2], nullptr, nullptr, out, stream);
     return;

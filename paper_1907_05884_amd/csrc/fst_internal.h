@@ -203,6 +203,11 @@ void dway_normal_equations(const fst_model* m, int dtype, const void* const* coo
 void launch_eval_d(const fst_model* m, const DeviceModel& dm, int dtype, int64_t n, const void* const* coords,
                    void* out, void* stream);
 int device_cu_count();
+// reconstruction of a model with wavelet factors (d = 3 or 4): arithmetic in dtype, points and
+// values in in_dtype; idx (may be NULL) selects the points; residual: out = v - f in dtype
+void launch_eval_wave(const fst_model* m, const DeviceModel& dm, int dtype, int in_dtype, int64_t n,
+                      const void* const* coords, const int32_t* idx, const void* v, void* out, bool residual,
+                      void* stream);
 // out_host[(D + 1) t + k] = coordinate k of point idx_host[t] (k < D), then its value, in FP64
 void gather_points_d(int dtype, int64_t K, const int64_t* idx_host, int D, const void* const* coords, const void* v,
                      double* out_host, void* ws, size_t ws_bytes, void* stream);
