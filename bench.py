@@ -3,12 +3,13 @@
 
 One step = one pass of the GPU hot path over the large FP32 workload:
   factor functions at the M sampled rows (eq. (2))  ->  Gram G = A^T A on MFMA and
-  h = A^T v (eq. (6), design rows formed on the fly)  ->  FP64 Cholesky + solve
-  (Algorithm 2 step 5)  ->  reconstruction at all N points (eq. (1)).
+  h = A^T v (eq. (6); FP32: design rows materialised transposed, then dense MFMA tiles;
+  16-bit: rows formed on the fly)  ->  FP64 Cholesky + solve (Algorithm 2 step 5)  ->
+  reconstruction at all N points (eq. (1)).
 The host steps of Algorithm 1 (interpolation, ST-HOSVD, sparse fit) run once before the
 timed region and are reported separately, as is the host draw of the sampled rows.
 
-Printed JSON line: value = design rows/s = M / t(factor evaluation + Gram + A^T v),
+Printed JSON line: value = design rows/s = M / t(factor evaluation + design rows + Gram + A^T v),
 plus reconstructed points/s, the roofline of the dominant kernel (the Gram) and the
 FP64 CPU oracle timed on a bounded sample of the same workload.
 
@@ -30,18 +31,28 @@ sys.path.insert(0, ROOT)
 PEAK = {"f32": 157.3e12, "bf16": 2.5e15, "f16": 2.5e15}
 GOLDEN = os.path.join(ROOT, "tests", "golden", "large_f32_reference.npz")
 TRAFFIC = os.path.join(ROOT, "profiles", "traffic_large.json")
-KERNELS_SRC = os.path.join(ROOT, "paper_1907_05884_amd", "csrc", "fst_kernels.hip")
+KERNELS_DIR = os.path.join(ROOT, "paper_1907_05884_amd", "csrc")
+
+
+def kernel_source_hash() -> str:
+    """sha256 prefix over the HIP sources and headers of the library, in name order."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(KERNELS_DIR)):
+        if name.endswith((".hip", ".h")):
+            with open(os.path.join(KERNELS_DIR, name), "rb") as f:
+                h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()[:16]
 
 
 def measured_traffic(precision: str):
     """HBM bytes per launch of the Gram kernel from the committed FETCH_SIZE / WRITE_SIZE
     counters (calibrated against a copy of known size), or None when there are none for this
     precision or the kernel source has changed since they were taken."""
-    import hashlib
     import json as _json
     try:
         t = _json.load(open(TRAFFIC))
-        h = hashlib.sha256(open(KERNELS_SRC, "rb").read()).hexdigest()[:16]
+        h = kernel_source_hash()
     except OSError:
         return None
     name = t.get("gram_kernel", {}).get(precision)
@@ -511,13 +522,18 @@ def main():
     alpha = torch.empty(R, dtype=torch.float64, device=dev)
     out = torch.empty(N, dtype=torch.float32, device=dev)
     gws = torch.empty(max(fst.fst_gram_workspace_bytes(m0, M), 256), dtype=torch.uint8, device=dev)
+    # FP32: the dense route, design rows materialised transposed (R x Sp FP32, 11 GB), then the
+    # dense MFMA Gram; 16-bit Grams form the rows on the fly (Khatri-Rao kernel)
+    dense = args.precision == "f32"
+    Sp = (M + 63) // 64 * 64
+    At = torch.empty((R, Sp), dtype=torch.float32, device=dev) if dense else None
     rws = torch.empty(max(fst.fst_refine_workspace_bytes(m0, M), 256), dtype=torch.uint8, device=dev)
     alpha_steps = []
     coefs = [m0.coefs(k) for k in range(3)]
     lo, hi = m0.info()["lo"], m0.info()["hi"]
     stream = torch.cuda.current_stream()
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(7)]
-    times = {"k1": [], "gram": [], "atv": [], "solve": [], "refine": [], "eval": []}
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(8)]
+    times = {"k1": [], "rows": [], "gram": [], "atv": [], "solve": [], "refine": [], "eval": []}
     gm_fit = None
 
     def step(record):
@@ -525,7 +541,13 @@ def main():
         ev[0].record(stream)
         fst.fst_factor_eval(m0, x, y, z, v, idx, U=U, vs=vs)
         ev[1].record(stream)
-        fst.fst_gram(m0, U, G=G, ws=gws, gram_prec=gram_prec)   # the Gram kernel alone
+        if dense:
+            fst.fst_design_rows(m0, U, Sp=Sp, At=At)             # k_design_rows
+            ev[7].record(stream)
+            fst.fst_gram_rows(At, G=G)                           # the Gram kernel alone
+        else:
+            ev[7].record(stream)
+            fst.fst_gram(m0, U, G=G, ws=gws, gram_prec=gram_prec)   # the Gram kernel alone
         ev[2].record(stream)
         fst.fst_gram(m0, U, vs, h=h, ws=gws, want_G=False)      # A^T v
         ev[3].record(stream)
@@ -547,7 +569,8 @@ def main():
         torch.cuda.synchronize()
         if record:
             times["k1"].append(ev[0].elapsed_time(ev[1]) / 1e3)
-            times["gram"].append(ev[1].elapsed_time(ev[2]) / 1e3)
+            times["rows"].append(ev[1].elapsed_time(ev[7]) / 1e3)
+            times["gram"].append(ev[7].elapsed_time(ev[2]) / 1e3)
             times["atv"].append(ev[2].elapsed_time(ev[3]) / 1e3)
             times["solve"].append(ev[3].elapsed_time(ev[4]) / 1e3)
             times["refine"].append(ev[4].elapsed_time(ev[6]) / 1e3)
@@ -624,12 +647,13 @@ def main():
     wavelet = None if args.no_wavelet else run_wavelet(w, x, y, z, v, stream)
 
     avg = {k: float(np.mean(vv)) for k, vv in times.items()}
-    t_rows = avg["k1"] + avg["gram"] + avg["atv"]
+    t_rows = avg["k1"] + avg["rows"] + avg["gram"] + avg["atv"]
     design_rows_per_s = M / t_rows
     points_per_s = N / avg["eval"]
     fitcore_rows_per_s = M / (t_rows + avg["solve"] + avg["refine"])
     gram_flops = float(M) * R * (R + 1)
     achieved = gram_flops / avg["gram"]
+    rows_bytes = float(R) * Sp * 4 + float(SR) * M * 4     # A^T written, factor values read
     peak = PEAK[args.precision]
     f_all = out.cpu().numpy()
     eps_data = float(np.sqrt(s_err / s_v))
@@ -646,7 +670,8 @@ def main():
         "config": {"workload": f"large_f32: N={N} FP32 points uniform in [-1,1]^3, 40 Gaussians + sinusoid + "
                                f"N(0,1e-3) noise; 5% interpolated (IDW-8) to a 128^3 grid; ranks 24^3 "
                                f"(R={R}); Legendre degree 31; M={M} sampled LS rows; reconstruct all N",
-                   "gram": {"f32": "FP32 MFMA", "bf16": "BF16 MFMA", "f16": "FP16 MFMA (scaled)"}[args.precision]
+                   "gram": {"f32": "design rows materialised (k_design_rows), dense FP32 MFMA (k_gram_dense)",
+                            "bf16": "BF16 MFMA", "f16": "FP16 MFMA (scaled)"}[args.precision]
                            + ", FP32 accumulation folded into FP64", "solve": "FP64 Cholesky",
                    "refine_steps": refine, "model": model_src},
         "reconstructed_points_per_s": points_per_s,
@@ -655,6 +680,10 @@ def main():
         "host_steps_s": t_host, "host_sample_draw_s": t_sample,
         "data_rel_l2": eps_data,
         "other_kernels": {
+            **({"k_design_rows (A^T of the M sampled rows, FP32)": {
+                "bound": "hbm", "achieved": rows_bytes / avg["rows"] / 1e9, "peak": 8000.0, "unit": "GB/s",
+                "frac": rows_bytes / avg["rows"] / 8e12, "ms": avg["rows"] * 1e3,
+                "bytes_per_launch": rows_bytes}} if dense else {}),
             "k_factor_eval (all N points, no gather)": {
                 "bound": "hbm", "achieved": k1_bytes / t_k1_all / 1e9, "peak": 8000.0, "unit": "GB/s",
                 "frac": k1_bytes / t_k1_all / 8e12, "ms": t_k1_all * 1e3,
@@ -676,11 +705,12 @@ def main():
             "data_rel_l2": float(np.sqrt(sm_err / sm_v)), "data_rel_l2_unmixed": eps_data},
         "spacetime": spacetime,
         "wavelet": None if wavelet is None else dict(wavelet, data_rel_l2_legendre=eps_data),
-        "roofline": {"kernel": "k_gram<float>" if args.precision == "f32" else f"k_gram_lp<{args.precision}>",
+        "roofline": {"kernel": "k_gram_dense<float>" if dense else f"k_gram_lp<{args.precision}>",
                      "bound": "mfma", "achieved": achieved / 1e12,
                      "peak": peak / 1e12, "unit": "TFLOP/s", "frac": achieved / peak,
                      "traffic": measured_traffic(args.precision), "flops_per_launch": gram_flops,
-                     "algorithmic_bytes_per_launch": float(SR * M * 4 + R * (R + 1) // 2 * 8)},
+                     "algorithmic_bytes_per_launch": float(R * Sp * 4 + R * (R + 1) // 2 * 8) if dense
+                     else float(SR * M * 4 + R * (R + 1) // 2 * 8)},
     }
     if ref is not None:
         a_ref = ref["alpha"]

@@ -200,14 +200,41 @@ fst_status fst_factor_eval(const fst_model* m, int32_t dtype, int64_t n, const v
 /* Normal equations of the sampled problem (Algorithm 2 step 5, eq. (6)):
  * G = A^T A (lower triangle incl. diagonal written; strictly upper part untouched) and
  * h = A^T vs, with A[q, j] = U1[q, j1] U2[q, j2] U3[q, j3] formed on the fly from U as
- * written by fst_factor_eval (never stored).  U, vs: device, `dtype` (FST_F64 needs
+ * written by fst_factor_eval (stored only by the dense route below, in the workspace).  U, vs: device, `dtype` (FST_F64 needs
  * gram_prec FST_GRAM_F64; FST_F32 takes F32, BF16 or F16).  G: device FP64 R x R
  * row-major, h: device FP64 R; either may be NULL to skip that product (not both).  ws: device workspace >= fst_gram_workspace_bytes.
  * Asynchronous. */
 size_t fst_gram_workspace_bytes(const fst_model* m, int64_t mrows);
+/* Workspace that lets fst_gram form G by its dense route: with FST_GRAM_F32 or FST_GRAM_F64 and
+ * a workspace above fst_gram_workspace_bytes that holds at least 4096 rows of A^T (R x rows
+ * of the row dtype), the design rows are written transposed into it, as many rows at a time
+ * as fit (all of them with this size: R x M x 4 bytes for FP32, 11 GB at R = 13,824,
+ * M = 200,000), and G is formed from them by a dense MFMA Gram (FP32 partial sums folded into
+ * FP64 every 64 rows, as in the other route).  Otherwise G is formed from U directly.
+ * fst_refit_core takes the same route when its workspace exceeds fst_refit_workspace_bytes by
+ * this much. */
+size_t fst_gram_dense_workspace_bytes(const fst_model* m, int32_t dtype, int64_t mrows);
 fst_status fst_gram(const fst_model* m, int32_t dtype, int64_t mrows, const void* U,
                     const void* vs, int32_t gram_prec, double* G, double* h, void* ws,
                     size_t ws_bytes, void* stream);
+
+/* The two steps of the dense route as separate calls, for callers that keep the design rows.
+ * fst_design_rows: the design matrix of Algorithm 2 step 5 (eq. (6)) written transposed,
+ * At[j * Sp + q] = A[q, j] for design column j (C order of the core, j = ((j1 r2 + j2) r3 + j3)
+ * [r4 + j4]) and row q < mrows, zero for mrows <= q < Sp, and b[q] = vs[q] (zero past mrows;
+ * b and vs may be NULL).  A 3-way or 4-way model; U in the layout fst_factor_eval writes
+ * for mrows rows (for a 4-way model mode 4 follows at o_4 = r1 + r2 + r3).  Sp: a multiple of 64, >= mrows >= 1.  U, vs, At, b: device,
+ * `dtype` (FST_F32 or FST_F64); At holds R x Sp entries.
+ * fst_gram_rows: G = At At^T (lower triangle incl. diagonal, FP64; strictly upper part
+ * untouched) by dense MFMA tiles of 128 x 128 (FP32 products accumulated in FP32 over 64 rows,
+ * then folded into FP64; FP64 products in FP64), and h = At b in FP64 with a fixed order; G or
+ * h may be NULL to skip that product.  accumulate != 0 adds to G and h (the sum over chunks of
+ * rows), 0 overwrites them.  Sp: a positive multiple of 64, R x Sp < 2^40.
+ * Both asynchronous; FST_E_INVAL for a bad size or a missing array. */
+fst_status fst_design_rows(const fst_model* m, int32_t dtype, int64_t mrows, const void* U,
+                           const void* vs, int64_t Sp, void* At, void* b, void* stream);
+fst_status fst_gram_rows(int32_t dtype, int64_t R, int64_t Sp, const void* At, const void* b,
+                         double* G, double* h, int32_t accumulate, void* stream);
 
 /* In-place FP64 Cholesky G + shift diag(G) = L L^T of a device R x R row-major matrix
  * (lower triangle read, L written there; the strictly upper triangle of each 64 x 64

@@ -110,6 +110,9 @@ _lib_fns = dict(
     fst_sthosvd_eps=(_i32, _vp, _vp, C.c_double, _vp, _i32, _vp, _vp, _vp, _vp),
     fst_sparse_fit=(_i32, _vp, _i32, _i32, _i32, _vp),
     fst_sparse_fit_lars=(_i32, _vp, _i32, _i32, _i32, _vp),
+    fst_gram_dense_workspace_bytes=(C.c_size_t, _vp, _i32, _i64),
+    fst_design_rows=(_i32, _vp, _i32, _i64, _vp, _vp, _i64, _vp, _vp, _vp),
+    fst_gram_rows=(_i32, _i32, _i64, _i64, _vp, _vp, _vp, _vp, _i32, _vp),
     fst_sparse_fit_choice=(_i32, _vp, _i32, _i32, _i32, _i32, _i32, _i32, _vp),
     fst_model_from_parts_wavelet=(_i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, C.POINTER(_vp)),
     fst_model_wavelets=(_i32, _vp, _vp, _vp),
@@ -639,6 +642,10 @@ def fst_factor_eval(m: Model, x, y, z, v=None, idx=None, mrows=None, U=None, vs=
     return U, vs
 
 
+def fst_gram_dense_workspace_bytes(m: Model, dtype: int, mrows: int) -> int:
+    return int(_fn["fst_gram_dense_workspace_bytes"](m.handle, int(dtype), int(mrows)))
+
+
 def fst_gram_workspace_bytes(m: Model, mrows: int) -> int:
     return int(_fn["fst_gram_workspace_bytes"](m.handle, int(mrows)))
 
@@ -660,6 +667,35 @@ def fst_gram(m: Model, U, vs=None, gram_prec=None, G=None, h=None, ws=None, stre
     _check(_fn["fst_gram"](m.handle, dt, int(mrows), _dev_ptr(U), _dev_ptr(vs), int(gram_prec),
                            _dev_ptr(G) if want_G else None, _dev_ptr(h), _dev_ptr(ws), ws.numel(),
                            _stream(stream)))
+    return G, h
+
+
+def fst_design_rows(m: Model, U, vs=None, Sp=None, At=None, b=None, stream=None):
+    """A^T (R x Sp, rows past U.shape[1] zero) and b of the rows whose factor values U holds."""
+    torch = _torch()
+    mrows = U.shape[1]
+    if Sp is None:
+        Sp = (mrows + 63) // 64 * 64
+    if At is None:
+        At = torch.empty((m.R, Sp), dtype=U.dtype, device=U.device)
+    if b is None and vs is not None:
+        b = torch.empty(Sp, dtype=U.dtype, device=U.device)
+    _check(_fn["fst_design_rows"](m.handle, _dtype_code(U), int(mrows), _dev_ptr(U), _dev_ptr(vs), int(Sp),
+                                  _dev_ptr(At), _dev_ptr(b), _stream(stream)))
+    return At, b
+
+
+def fst_gram_rows(At, b=None, G=None, h=None, want_G=True, accumulate=False, stream=None):
+    """G = At At^T (lower triangle) and h = At b, FP64, from materialised rows."""
+    torch = _torch()
+    R, Sp = At.shape
+    if G is None and want_G:
+        G = torch.zeros((R, R), dtype=torch.float64, device=At.device)
+    if h is None and b is not None:
+        h = torch.empty(R, dtype=torch.float64, device=At.device)
+    _check(_fn["fst_gram_rows"](_dtype_code(At), int(R), int(Sp), _dev_ptr(At), _dev_ptr(b),
+                                _dev_ptr(G) if want_G else None, _dev_ptr(h), 1 if accumulate else 0,
+                                _stream(stream)))
     return G, h
 
 

@@ -832,6 +832,12 @@ size_t fst_gram_workspace_bytes(const fst_model* m, int64_t mrows) {
   return gram_workspace_bytes(m, mrows);
 }
 
+size_t fst_gram_dense_workspace_bytes(const fst_model* m, int32_t dtype, int64_t mrows) {
+  if (!m || m->d != 3 || mrows < 1 || (dtype != FST_F64 && dtype != FST_F32)) return 0;
+  const int64_t all = (mrows + GD_SP_MULTIPLE - 1) / GD_SP_MULTIPLE * GD_SP_MULTIPLE;
+  return gram_workspace_bytes(m, mrows) + dense_rows_bytes(m, dtype, all);
+}
+
 fst_status fst_gram(const fst_model* m, int32_t dtype, int64_t mrows, const void* U, const void* vs,
                     int32_t gram_prec, double* G, double* h, void* ws, size_t ws_bytes, void* stream) {
   FST_TRY
@@ -844,6 +850,33 @@ fst_status fst_gram(const fst_model* m, int32_t dtype, int64_t mrows, const void
   if (h && !vs) fail(FST_E_INVAL, "h requested without vs");
   if ((h || gram_prec == FST_GRAM_F16) && !ws) fail(FST_E_INVAL, "h and FP16 rows need a workspace");
   launch_gram(m, dtype, mrows, U, vs, gram_prec, G, h, ws, ws ? ws_bytes : 0, stream);
+  return FST_OK;
+  FST_CATCH
+}
+
+fst_status fst_design_rows(const fst_model* m, int32_t dtype, int64_t mrows, const void* U, const void* vs,
+                           int64_t Sp, void* At, void* b, void* stream) {
+  FST_TRY
+  set_last_error("");
+  if (!m) fail(FST_E_INVAL, "null model");
+  check_dtype(dtype);
+  if (!U || !At) fail(FST_E_INVAL, "null argument");
+  design_rows(m, dtype, mrows, U, vs, Sp, At, b, stream);
+  return FST_OK;
+  FST_CATCH
+}
+
+fst_status fst_gram_rows(int32_t dtype, int64_t R, int64_t Sp, const void* At, const void* b, double* G, double* h,
+                         int32_t accumulate, void* stream) {
+  FST_TRY
+  set_last_error("");
+  check_dtype(dtype);
+  if (R < 1 || Sp < GD_SP_MULTIPLE || Sp % GD_SP_MULTIPLE != 0)
+    fail(FST_E_INVAL, "need R >= 1 and Sp a positive multiple of 64");
+  if (R * Sp >= (int64_t(1) << 40)) fail(FST_E_UNSUPPORTED, "A^T too large");
+  if (!At || (!G && !h)) fail(FST_E_INVAL, "null argument");
+  if (h && !b) fail(FST_E_INVAL, "h requested without b");
+  dense_normal_equations(dtype, At, b, R, Sp, G, h, accumulate != 0, stream);
   return FST_OK;
   FST_CATCH
 }

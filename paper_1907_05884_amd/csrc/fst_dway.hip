@@ -64,7 +64,7 @@ __global__ __launch_bounds__(DR_THREADS) void k_design_rows(DesignArgs<T> a) {
     for (int j4 = 0; j4 < RP; ++j4)
       if (j4 < a.r[3]) dst[(int64_t)(j3 * a.r[3] + j4) * a.Sp] = p * u4[j4];
   }
-  if (pair == 0) a.b[q] = live ? a.vs[col] : T(0);
+  if (pair == 0 && a.b) a.b[q] = live ? a.vs[col] : T(0);
 }
 
 constexpr int64_t DW_CHUNK = 16384;   // sampled rows per materialised chunk
@@ -102,14 +102,12 @@ static void design_launch(const DesignArgs<T>& a, void* stream) {
 }
 
 template <typename T>
-static void dway_chunks(const fst_model* m, const DwayLayout& L, char* w, int64_t M, double* G, double* h,
-                        void* stream) {
-  const int dtype = sizeof(T) == 8 ? FST_F64 : FST_F32;
+static DesignArgs<T> design_args(const fst_model* m, const T* U, const T* vs, int64_t M, T* At, T* b) {
   DesignArgs<T> a;
-  a.U = (const T*)(w + L.U);
-  a.vs = (const T*)(w + L.vs);
-  a.At = (T*)(w + L.At);
-  a.b = (T*)(w + L.b);
+  a.U = U;
+  a.vs = vs;
+  a.At = At;
+  a.b = b;
   a.M = M;
   int off = 0;
   for (int k = 0; k < kMaxModes; ++k) {
@@ -117,19 +115,66 @@ static void dway_chunks(const fst_model* m, const DwayLayout& L, char* w, int64_
     a.off[k] = off;
     off += k < m->d ? m->rank[k] : 0;
   }
-  const int rp = m->d == 4 ? pad8(m->rank[3]) : 1;
-  for (int64_t q0 = 0; q0 < M; q0 += L.Sc) {
-    a.q0 = q0;
-    a.mc = std::min<int64_t>(L.Sc, M - q0);
-    a.Sp = (a.mc + GD_SP_MULTIPLE - 1) / GD_SP_MULTIPLE * GD_SP_MULTIPLE;
-    switch (rp) {
-      case 1: design_launch<T, 1>(a, stream); break;
-      case 8: design_launch<T, 8>(a, stream); break;
-      case 16: design_launch<T, 16>(a, stream); break;
-      case 24: design_launch<T, 24>(a, stream); break;
-      default: design_launch<T, 32>(a, stream); break;
-    }
-    dense_normal_equations(dtype, a.At, a.b, m->R(), a.Sp, G, h, q0 > 0, stream);
+  return a;
+}
+
+// rows q0 .. q0 + mc - 1 written as columns 0 .. mc - 1 of At (R x Sp), columns mc .. Sp - 1 zero
+template <typename T>
+static void design_chunk(const fst_model* m, DesignArgs<T>& a, int64_t q0, int64_t mc, int64_t Sp, void* stream) {
+  a.q0 = q0;
+  a.mc = mc;
+  a.Sp = Sp;
+  switch (m->d == 4 ? pad8(m->rank[3]) : 1) {
+    case 1: design_launch<T, 1>(a, stream); break;
+    case 8: design_launch<T, 8>(a, stream); break;
+    case 16: design_launch<T, 16>(a, stream); break;
+    case 24: design_launch<T, 24>(a, stream); break;
+    default: design_launch<T, 32>(a, stream); break;
+  }
+}
+
+// G = A^T A and h = A^T v_S (either may be NULL) over M rows given by their factor values,
+// `chunk` rows at a time materialised in At (and b)
+template <typename T>
+static void rows_normal_equations(const fst_model* m, const T* U, const T* vs, int64_t M, T* At, T* b,
+                                  int64_t chunk, double* G, double* h, void* stream) {
+  DesignArgs<T> a = design_args(m, U, vs, M, At, b);
+  for (int64_t q0 = 0; q0 < M; q0 += chunk) {
+    const int64_t mc = std::min<int64_t>(chunk, M - q0);
+    const int64_t Sp = (mc + GD_SP_MULTIPLE - 1) / GD_SP_MULTIPLE * GD_SP_MULTIPLE;
+    design_chunk(m, a, q0, mc, Sp, stream);
+    dense_normal_equations(sizeof(T) == 8 ? FST_F64 : FST_F32, At, b, m->R(), Sp, G, h, q0 > 0, stream);
+  }
+}
+
+size_t dense_rows_bytes(const fst_model* m, int dtype, int64_t chunk) {
+  return align_up((dtype == FST_F64 ? 8 : 4) * (size_t)m->R() * (size_t)chunk);
+}
+
+void dense_gram_from_rows(const fst_model* m, int dtype, int64_t mrows, const void* U, double* G, void* At,
+                          int64_t chunk, void* stream) {
+  if (chunk <= 0 || chunk % GD_SP_MULTIPLE != 0) fail(FST_E_INVAL, "dense Gram: bad chunk");
+  if (m->R() * chunk >= (int64_t(1) << 40)) fail(FST_E_UNSUPPORTED, "dense Gram: chunk of A^T too large");
+  if (dtype == FST_F64)
+    rows_normal_equations<double>(m, (const double*)U, nullptr, mrows, (double*)At, nullptr, chunk, G, nullptr,
+                                  stream);
+  else
+    rows_normal_equations<float>(m, (const float*)U, nullptr, mrows, (float*)At, nullptr, chunk, G, nullptr,
+                                 stream);
+}
+
+void design_rows(const fst_model* m, int dtype, int64_t mrows, const void* U, const void* vs, int64_t Sp, void* At,
+                 void* b, void* stream) {
+  if (Sp < mrows || Sp % GD_SP_MULTIPLE != 0) fail(FST_E_INVAL, "design rows: Sp must be a multiple of 64 >= mrows");
+  if (m->R() * Sp >= (int64_t(1) << 40)) fail(FST_E_UNSUPPORTED, "design rows: A^T too large");
+  if (b && !vs) fail(FST_E_INVAL, "design rows: b needs the sampled values");
+  if (mrows < 1) fail(FST_E_INVAL, "design rows: mrows must be >= 1");
+  if (dtype == FST_F64) {
+    DesignArgs<double> a = design_args(m, (const double*)U, (const double*)vs, mrows, (double*)At, (double*)b);
+    design_chunk(m, a, 0, mrows, Sp, stream);
+  } else {
+    DesignArgs<float> a = design_args(m, (const float*)U, (const float*)vs, mrows, (float*)At, (float*)b);
+    design_chunk(m, a, 0, mrows, Sp, stream);
   }
 }
 
@@ -146,9 +191,11 @@ void dway_normal_equations(const fst_model* m, int dtype, const void* const* coo
   launch_factor_eval_d(m, dm, dtype, coords, v, idx, M, w + L.U, w + L.vs, stream);
   // step 5: normal equations of the sampled rows, chunk by chunk
   if (dtype == FST_F64)
-    dway_chunks<double>(m, L, w, M, G, h, stream);
+    rows_normal_equations<double>(m, (const double*)(w + L.U), (const double*)(w + L.vs), M, (double*)(w + L.At),
+                                  (double*)(w + L.b), L.Sc, G, h, stream);
   else
-    dway_chunks<float>(m, L, w, M, G, h, stream);
+    rows_normal_equations<float>(m, (const float*)(w + L.U), (const float*)(w + L.vs), M, (float*)(w + L.At),
+                                 (float*)(w + L.b), L.Sc, G, h, stream);
 }
 
 // ------------------------------------------------------------------------------ subset gather

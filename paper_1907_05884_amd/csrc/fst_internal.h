@@ -190,8 +190,17 @@ void mixed_normal_equations(const fst_model* m, int dtype, int64_t n, const void
 // G = A^T A (lower triangle, FP64) and h = A^T b from materialised rows: At is R x Sp (row j of
 // A^T contiguous), b is Sp long, Sp a multiple of GD_SP_MULTIPLE with rows past the data zero;
 // in the point dtype (FP32: FP32 MFMA folded into FP64; FP64: FP64 MFMA).  accumulate adds to
-// G and h instead of overwriting them.
+// G and h instead of overwriting them; G or h may be NULL to skip that product.
 constexpr int64_t GD_SP_MULTIPLE = 64;
+// the dense route of the Gram: A^T of mrows rows (factor values U as k_factor_eval writes them)
+// materialised `chunk` rows at a time in At (dense_rows_bytes(chunk) bytes), then k_gram_dense
+// (G = A^T A, lower triangle, accumulated over the chunks)
+size_t dense_rows_bytes(const fst_model* m, int dtype, int64_t chunk);
+void dense_gram_from_rows(const fst_model* m, int dtype, int64_t mrows, const void* U, double* G, void* At,
+                          int64_t chunk, void* stream);
+// A^T (R x Sp) and b (Sp, may be NULL) of mrows rows given by their factor values and values
+void design_rows(const fst_model* m, int dtype, int64_t mrows, const void* U, const void* vs, int64_t Sp, void* At,
+                 void* b, void* stream);
 void dense_normal_equations(int dtype, const void* At, const void* b, int64_t R, int64_t Sp, double* G, double* h,
                             bool accumulate, void* stream);
 // d-way form (fst_dway.hip): normal equations of M sampled rows (idx) of a d = 3 or 4 model

@@ -320,19 +320,28 @@ void dense_normal_equations(int dtype, const void* At, const void* b, int64_t R,
   const int64_t nt = (R + GD_TILE - 1) / GD_TILE;
   const dim3 gg((unsigned)(nt * (nt + 1) / 2)), ga((unsigned)((R + 3) / 4));
   if (dtype == FST_F64) {
-    hipLaunchKernelGGL(k_gram_dense<double>, gg, dim3(GD_THREADS), 0, S(stream), (const double*)At, R, Sp, G,
-                       accumulate ? 1 : 0);
-    check_launch("k_gram_dense");
-    hipLaunchKernelGGL(k_atv_dense<double>, ga, dim3(256), 0, S(stream), (const double*)At, (const double*)b, R, Sp,
-                       h, accumulate ? 1 : 0);
+    if (G) {
+      hipLaunchKernelGGL(k_gram_dense<double>, gg, dim3(GD_THREADS), 0, S(stream), (const double*)At, R, Sp, G,
+                         accumulate ? 1 : 0);
+      check_launch("k_gram_dense");
+    }
+    if (h) {
+      hipLaunchKernelGGL(k_atv_dense<double>, ga, dim3(256), 0, S(stream), (const double*)At, (const double*)b, R,
+                         Sp, h, accumulate ? 1 : 0);
+      check_launch("k_atv_dense");
+    }
   } else {
-    hipLaunchKernelGGL(k_gram_dense<float>, gg, dim3(GD_THREADS), 0, S(stream), (const float*)At, R, Sp, G,
-                       accumulate ? 1 : 0);
-    check_launch("k_gram_dense");
-    hipLaunchKernelGGL(k_atv_dense<float>, ga, dim3(256), 0, S(stream), (const float*)At, (const float*)b, R, Sp, h,
-                       accumulate ? 1 : 0);
+    if (G) {
+      hipLaunchKernelGGL(k_gram_dense<float>, gg, dim3(GD_THREADS), 0, S(stream), (const float*)At, R, Sp, G,
+                         accumulate ? 1 : 0);
+      check_launch("k_gram_dense");
+    }
+    if (h) {
+      hipLaunchKernelGGL(k_atv_dense<float>, ga, dim3(256), 0, S(stream), (const float*)At, (const float*)b, R, Sp,
+                         h, accumulate ? 1 : 0);
+      check_launch("k_atv_dense");
+    }
   }
-  check_launch("k_atv_dense");
 }
 
 // ------------------------------------------------------------------------------ host side

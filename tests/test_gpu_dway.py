@@ -11,7 +11,7 @@ import numpy as np
 import pytest
 
 from datagen import random_model_parts
-from oracle.lsq import refit_core
+from oracle.lsq import design_rows as lsq_design_rows, refit_core
 from oracle.model import Model as OModel
 from oracle.reconstruct import evaluate, rel_l2
 
@@ -212,3 +212,56 @@ def test_fit_d_four_way_fp32_ranks_from_precision(dev):
     mo = pipeline.fit(w.pts.astype(np.float64), w.vals.astype(np.float64), w.lo, w.hi, w.grid, r, w.degree,
                       w.interp_fraction, w.n_samples, w.seed)
     assert rel_l2(gm.core, mo.core) <= 1e-4
+
+
+# ------------------------------------------------------------------------------ dense route calls
+@pytest.mark.parametrize("rank,mrows,Sp", [((3, 2, 4, 2), 1000, 1024), ((5, 6, 7, 9), 777, 832),
+                                           ((4, 3, 5), 130, 192), ((1, 1, 1, 1), 1, 64),
+                                           ((6, 5, 4, 17), 4097, 4160)])
+def test_design_rows_and_gram_rows(dev, rank, mrows, Sp):
+    # the design rows of eq. (6) from arbitrary factor values: the kernel forms the products in
+    # the oracle's order, so FP64 rows are bit-exact; then G and h from the rows in two chunks
+    print(f"design rows rank={rank} mrows={mrows} Sp={Sp}", flush=True)
+    rng = np.random.default_rng(sum(rank) + mrows)
+    Uk = [rng.standard_normal((mrows, r)) for r in rank]
+    vs = rng.standard_normal(mrows)
+    A = lsq_design_rows(Uk)
+    R = A.shape[1]
+    m = _models(3, rank, tuple(r + 1 for r in rank))[1]
+    for dtype in (np.float64, np.float32):
+        U = D(np.concatenate([u.T for u in Uk]).astype(dtype), dev)
+        At, b = fst.fst_design_rows(m, U, D(vs.astype(dtype), dev), Sp=Sp)
+        At_h, b_h = At.cpu().numpy(), b.cpu().numpy()
+        assert At_h.shape == (R, Sp)
+        assert np.all(At_h[:, mrows:] == 0) and np.all(b_h[mrows:] == 0)
+        if dtype == np.float64:
+            np.testing.assert_array_equal(At_h[:, :mrows], A.T)
+        else:
+            A32 = lsq_design_rows([u.astype(np.float32).astype(np.float64) for u in Uk])
+            assert rel_l2(At_h[:, :mrows], A32.T) <= 1e-6
+        np.testing.assert_array_equal(b_h[:mrows], vs.astype(dtype))
+        Ah = At_h[:, :mrows].astype(np.float64)
+        Gr, hr = Ah @ Ah.T, Ah @ b_h[:mrows].astype(np.float64)
+        tol = 1e-12 if dtype == np.float64 else 1e-6
+        G, h = fst.fst_gram_rows(At, b)
+        low = np.tril_indices(R)
+        assert rel_l2(G.cpu().numpy()[low], Gr[low]) <= tol and rel_l2(h.cpu().numpy(), hr) <= tol
+        assert np.all(np.triu(G.cpu().numpy(), 1) == 0)          # strictly upper part untouched
+        if Sp >= 128:   # the same sums over two column chunks of At, the second accumulated
+            c = Sp // 128 * 64
+            G2, h2 = fst.fst_gram_rows(At[:, :c].contiguous(), b[:c].contiguous())
+            fst.fst_gram_rows(At[:, c:].contiguous(), b[c:].contiguous(), G=G2, h=h2, accumulate=True)
+            assert rel_l2(G2.cpu().numpy()[low], Gr[low]) <= tol and rel_l2(h2.cpu().numpy(), hr) <= tol
+
+
+def test_design_and_gram_rows_reject_bad_sizes(dev):
+    m = _models(3, (3, 2, 4), (4, 4, 4))[1]
+    U = torch.zeros((9, 100), dtype=torch.float64, device=dev)
+    for Sp in (96, 64):                      # not a multiple of 64; fewer than mrows
+        with pytest.raises(fst.FstError) as e:
+            fst.fst_design_rows(m, U, Sp=Sp, At=torch.empty((24, 128), dtype=torch.float64, device=dev))
+        assert e.value.status == fst.FST_E_INVAL
+    At = torch.zeros((24, 100), dtype=torch.float64, device=dev)
+    with pytest.raises(fst.FstError) as e:
+        fst.fst_gram_rows(At)
+    assert e.value.status == fst.FST_E_INVAL

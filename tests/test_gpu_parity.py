@@ -130,6 +130,44 @@ def test_gram_is_deterministic(dev):
     assert torch.equal(G1, G2)
 
 
+# dense route of fst_gram: design rows materialised transposed in the workspace, then the
+# dense MFMA Gram; one chunk holding every row, or 4096-row chunks with a ragged last one
+@pytest.mark.parametrize("dtype,tol", [(np.float64, 1e-10), (np.float32, 1e-5)])
+@pytest.mark.parametrize("rank,degree,m", [((5, 7, 3), (9, 12, 6), 777), ((12, 11, 10), (20, 20, 20), 9001)])
+@pytest.mark.parametrize("chunked", [False, True])
+def test_gram_dense_route_parity(dev, dtype, tol, rank, degree, m, chunked):
+    om, gm = _models(31, rank, degree)
+    pts = _pts(32, m, dtype=dtype)
+    x, y, z = _soa(pts, dev)
+    U, _ = fst.fst_factor_eval(gm, x, y, z)
+    code = fst.FST_F64 if dtype == np.float64 else fst.FST_F32
+    base = fst.fst_gram_workspace_bytes(gm, m)
+    full = fst.fst_gram_dense_workspace_bytes(gm, code, m)
+    assert full > base
+    size = base + np.dtype(dtype).itemsize * gm.R * 4096 + 100 if chunked else full
+    ws = torch.empty(size, dtype=torch.uint8, device=dev)
+    G, _ = fst.fst_gram(gm, U, ws=ws)
+    Gk, _ = fst.fst_gram(gm, U)                   # the Khatri-Rao route (minimal workspace)
+    Gr, _ = lsq.normal_equations(om, pts.astype(np.float64), np.zeros(m))
+    low = np.tril_indices(Gr.shape[0])
+    assert rel_l2(H(G)[low], Gr[low]) <= tol
+    assert rel_l2(H(G)[low], H(Gk)[low]) <= tol
+    G2, _ = fst.fst_gram(gm, U, ws=ws)
+    assert torch.equal(G, G2)
+
+
+def test_refit_dense_route_matches_oracle(dev):
+    w, m0 = _small_workload_model()
+    alpha_o, _, _, _ = lsq.refit_core(m0, w.pts, w.vals, w.n_samples, w.seed)
+    gm = fst.fst_model_from_parts(w.lo, w.hi, w.rank, w.degree, m0.core, m0.coefs)
+    x, y, z, v = [D(a, dev) for a in w.soa()]
+    extra = fst.fst_gram_dense_workspace_bytes(gm, fst.FST_F64, w.n_samples)
+    ws = torch.empty(fst.fst_refit_workspace_bytes(gm, fst.FST_F64, w.n_samples) + extra, dtype=torch.uint8,
+                     device=dev)
+    out = fst.fst_refit_core(gm, x, y, z, v, w.n_samples, w.seed, ws=ws)
+    assert rel_l2(out.core, alpha_o) <= 1e-10
+
+
 # ------------------------------------------------------------------------------ Cholesky + solve
 # sizes cover one block, a ragged last block, trailing updates whose last row block is
 # shorter than a tile (R - base not a multiple of 256) and several 256-column panels
