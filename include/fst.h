@@ -223,11 +223,12 @@ fst_status fst_gram(const fst_model* m, int32_t dtype, int64_t mrows, const void
  * At[j * Sp + q] = A[q, j] for design column j (C order of the core, j = ((j1 r2 + j2) r3 + j3)
  * [r4 + j4]) and row q < mrows, zero for mrows <= q < Sp, and b[q] = vs[q] (zero past mrows;
  * b and vs may be NULL).  A 3-way or 4-way model; U in the layout fst_factor_eval writes
- * for mrows rows (for a 4-way model mode 4 follows at o_4 = r1 + r2 + r3).  Sp: a multiple of 64, >= mrows >= 1.  U, vs, At, b: device,
- * `dtype` (FST_F32 or FST_F64); At holds R x Sp entries.
+ * for mrows rows (for a 4-way model mode 4 follows at o_4 = r1 + r2 + r3).  Sp: a multiple
+ * of 64, >= mrows >= 1.  U, vs, At, b: device, `dtype` (FST_F32 or FST_F64); At holds R x Sp
+ * entries.
  * fst_gram_rows: G = At At^T (lower triangle incl. diagonal, FP64; strictly upper part
- * untouched) by dense MFMA tiles of 128 x 128 (FP32 products accumulated in FP32 over 64 rows,
- * then folded into FP64; FP64 products in FP64), and h = At b in FP64 with a fixed order; G or
+ * untouched) by dense MFMA tiles of 128 x 128 (FP32 products accumulated in FP32 over 64
+ * rows, then folded into FP64; FP64 products in FP64), and h = At b in FP64 with a fixed order; G or
  * h may be NULL to skip that product.  accumulate != 0 adds to G and h (the sum over chunks of
  * rows), 0 overwrites them.  Sp: a positive multiple of 64, R x Sp < 2^40.
  * Both asynchronous; FST_E_INVAL for a bad size or a missing array. */

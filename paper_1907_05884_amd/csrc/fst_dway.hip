@@ -42,13 +42,26 @@ struct DesignArgs {
 
 constexpr int DR_THREADS = 256;
 
+// Workgroup order: super-blocks of DR_SUPER row blocks of DR_THREADS rows; inside one, the
+// (j1, j2) pairs, and inside a pair the row blocks.  The factor values of a super-block
+// (sum r x 2048 entries) stay in L2 while all pairs read them, and each design row still
+// receives runs of DR_SUPER x DR_THREADS contiguous entries.  sb0: first super-block of this
+// launch.
+constexpr int64_t DR_SUPER = 8;
+
 template <typename T, int RP>
-__global__ __launch_bounds__(DR_THREADS) void k_design_rows(DesignArgs<T> a) {
-  const int64_t q = (int64_t)blockIdx.x * DR_THREADS + threadIdx.x;
+__global__ __launch_bounds__(DR_THREADS) void k_design_rows(DesignArgs<T> a, int64_t sb0) {
+  const int64_t P = (int64_t)a.r[0] * a.r[1], nb = (a.Sp + DR_THREADS - 1) / DR_THREADS;
+  const int64_t sb = sb0 + (int64_t)blockIdx.x / (P * DR_SUPER), rem = (int64_t)blockIdx.x % (P * DR_SUPER);
+  const int64_t w = min(DR_SUPER, nb - sb * DR_SUPER);
+  if (w <= 0) return;
+  const int64_t pr = rem / w, cb = sb * DR_SUPER + rem % w;
+  if (pr >= P) return;
+  const int64_t q = cb * DR_THREADS + threadIdx.x;
   if (q >= a.Sp) return;
   const bool live = q < a.mc;
   const int64_t col = a.q0 + (live ? q : a.mc - 1);
-  const int pair = (int)blockIdx.y;
+  const int pair = (int)pr;
   const int j1 = pair / a.r[1], j2 = pair - j1 * a.r[1];
   const T* U = a.U;
   const T p12 = U[(int64_t)(a.off[0] + j1) * a.M + col] * U[(int64_t)(a.off[1] + j2) * a.M + col];
@@ -96,9 +109,16 @@ size_t dway_workspace_bytes(const fst_model* m, int dtype, int64_t M) { return d
 
 template <typename T, int RP>
 static void design_launch(const DesignArgs<T>& a, void* stream) {
-  const dim3 g((unsigned)((a.Sp + DR_THREADS - 1) / DR_THREADS), (unsigned)(a.r[0] * a.r[1]));
-  hipLaunchKernelGGL((k_design_rows<T, RP>), g, dim3(DR_THREADS), 0, S(stream), a);
-  check_launch("k_design_rows");
+  const int64_t P = (int64_t)a.r[0] * a.r[1], nb = (a.Sp + DR_THREADS - 1) / DR_THREADS;
+  const int64_t nsb = (nb + DR_SUPER - 1) / DR_SUPER, per = std::max<int64_t>(1, (int64_t(1) << 30) / (P * DR_SUPER));
+  for (int64_t sb0 = 0; sb0 < nsb; sb0 += per) {
+    // the last super-block may hold fewer row blocks: its pairs take P w workgroups, and the
+    // launch's tail of P (DR_SUPER - w) workgroups finds nothing to do
+    const int64_t n = std::min(per, nsb - sb0);
+    hipLaunchKernelGGL((k_design_rows<T, RP>), dim3((unsigned)(n * P * DR_SUPER)), dim3(DR_THREADS), 0, S(stream),
+                       a, sb0);
+    check_launch("k_design_rows");
+  }
 }
 
 template <typename T>
