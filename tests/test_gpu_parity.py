@@ -451,13 +451,27 @@ def test_full_size_against_oracle_reference(dev):
     G, h = fst.fst_gram(gm, U, vs)
     assert rel_l2(H(h), ref["h"]) <= 1e-5
     assert rel_l2(np.diag(H(G)), ref["gram_diag"]) <= 1e-5
-    del G
+    # the dense route as the benchmark times it: A^T of all M rows, then the dense Gram
+    At, _ = fst.fst_design_rows(gm, U, Sp=(w.n_samples + 63) // 64 * 64)
+    Gd, _ = fst.fst_gram_rows(At)
+    del At
+    assert rel_l2(np.diag(H(Gd)), ref["gram_diag"]) <= 1e-5
+    low = torch.tril(torch.ones_like(Gd, dtype=torch.bool))
+    assert (torch.linalg.norm(Gd[low] - G[low]) / torch.linalg.norm(G[low])).item() <= 1e-6
+    del G, Gd, low
     torch.cuda.empty_cache()
     alpha = ref["alpha"]
     # FP32 rows: kappa(G) ~ 6e7 amplifies FP32 rounding in the core; three FP64-residual
     # refinement steps bring it to the oracle's core
     out32 = fst.fst_refit_core(gm, x, y, z, v, w.n_samples, w.seed, refine_steps=3)
     assert rel_l2(out32.core, alpha) <= 1e-6
+    # the same with the workspace of the dense route
+    ws = torch.empty(fst.fst_refit_workspace_bytes(gm, fst.FST_F32, w.n_samples, 3)
+                     + fst.fst_gram_dense_workspace_bytes(gm, fst.FST_F32, w.n_samples), dtype=torch.uint8, device=dev)
+    outd = fst.fst_refit_core(gm, x, y, z, v, w.n_samples, w.seed, refine_steps=3, ws=ws)
+    del ws
+    torch.cuda.empty_cache()
+    assert rel_l2(outd.core, alpha) <= 1e-6
     out16 = fst.fst_refit_core(gm, x, y, z, v, w.n_samples, w.seed, gram_prec=fst.FST_GRAM_F16, refine_steps=9)
     assert rel_l2(out16.core, alpha) <= 1e-6
     # reconstruction at sampled output points, against the oracle's field of its own core
