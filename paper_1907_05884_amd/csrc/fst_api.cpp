@@ -599,6 +599,15 @@ using namespace fst;
     return FST_E_INVAL;                             \
   }
 
+// size queries return 0 (with the message in fst_last_error) instead of a status
+#define FST_SIZE_TRY try {
+#define FST_SIZE_CATCH                              \
+  }                                                 \
+  catch (const std::exception& e) {                 \
+    fst::set_last_error(e.what());                  \
+    return 0;                                       \
+  }
+
 extern "C" {
 
 const char* fst_last_error(void) { return fst::g_last_error.c_str(); }
@@ -634,7 +643,7 @@ size_t fst_fit_workspace_bytes(const fst_fit_params* p, int64_t n) {
     size_t gather = align_up(sizeof(int32_t) * (size_t)K) + sizeof(double) * 4 * (size_t)K;
     size_t refit = refit_bytes_for(p->rank, p->degree, p->n_samples, p->dtype, p->refine_steps);
     return std::max(gather, refit);
-  } catch (const fst::Error& e) {
+  } catch (const std::exception& e) {
     fst::set_last_error(e.what());
     return 0;
   }
@@ -699,7 +708,7 @@ size_t fst_refit_workspace_bytes(const fst_model* m, int32_t dtype, int64_t n_sa
     if (n_samples < 1 || refine_steps < 0) fail(FST_E_INVAL, "bad sizes");
     return refit_layout(m->R(), m->sum_r(), n_samples, dtype, refine_steps,
                         refit_scratch(m, n_samples, refine_steps)).total;
-  } catch (const fst::Error& e) {
+  } catch (const std::exception& e) {
     fst::set_last_error(e.what());
     return 0;
   }
@@ -740,8 +749,10 @@ static void check_grid_counts(int64_t n1, int64_t n2, int64_t n3) {
 }
 
 size_t fst_eval_grid_workspace_bytes(const fst_model* m, int32_t dtype, int64_t n1, int64_t n2, int64_t n3) {
+  FST_SIZE_TRY
   if (!m || m->d != 3 || (dtype != FST_F64 && dtype != FST_F32) || n1 < 1 || n2 < 1 || n3 < 1) return 0;
   return eval_grid_workspace_bytes(m, dtype, n1, n2, n3);
+  FST_SIZE_CATCH
 }
 
 fst_status fst_eval_grid(const fst_model* m, int32_t dtype, const void* gx, int64_t n1, const void* gy, int64_t n2,
@@ -773,9 +784,11 @@ fst_status fst_eval_grid(const fst_model* m, int32_t dtype, const void* gx, int6
 }
 
 size_t fst_refit_core_mixed_workspace_bytes(const fst_model* m, int32_t dtype, int64_t n, int64_t n_samples) {
+  FST_SIZE_TRY
   if (!m || m->d != 3 || (dtype != FST_F64 && dtype != FST_F32) || n < 1 || n > (int64_t(1) << 23) || n_samples < 1)
     return 0;
   return mixed_refit_layout(m, dtype, n, n_samples).total;
+  FST_SIZE_CATCH
 }
 
 fst_status fst_refit_core_mixed(const fst_model* m, int32_t dtype, int64_t n, const void* x, const void* y,
@@ -790,8 +803,10 @@ fst_status fst_refit_core_mixed(const fst_model* m, int32_t dtype, int64_t n, co
 }
 
 size_t fst_eval_error_workspace_bytes(int32_t dtype, int64_t n) {
+  FST_SIZE_TRY
   if ((dtype != FST_F64 && dtype != FST_F32) || n < 0) return 0;
   return eval_error_workspace_bytes(dtype, n);
+  FST_SIZE_CATCH
 }
 
 fst_status fst_eval_error(const fst_model* m, int32_t dtype, int64_t n, const void* x, const void* y,
@@ -828,14 +843,18 @@ fst_status fst_factor_eval(const fst_model* m, int32_t dtype, int64_t n, const v
 }
 
 size_t fst_gram_workspace_bytes(const fst_model* m, int64_t mrows) {
+  FST_SIZE_TRY
   if (!m || m->d != 3 || mrows < 0) return 0;
   return gram_workspace_bytes(m, mrows);
+  FST_SIZE_CATCH
 }
 
 size_t fst_gram_dense_workspace_bytes(const fst_model* m, int32_t dtype, int64_t mrows) {
+  FST_SIZE_TRY
   if (!m || m->d != 3 || mrows < 1 || (dtype != FST_F64 && dtype != FST_F32)) return 0;
   const int64_t all = (mrows + GD_SP_MULTIPLE - 1) / GD_SP_MULTIPLE * GD_SP_MULTIPLE;
   return gram_workspace_bytes(m, mrows) + dense_rows_bytes(m, dtype, all);
+  FST_SIZE_CATCH
 }
 
 fst_status fst_gram(const fst_model* m, int32_t dtype, int64_t mrows, const void* U, const void* vs,
@@ -907,8 +926,10 @@ fst_status fst_cholesky_solve(int64_t R, const double* L, const double* b, doubl
 }
 
 size_t fst_residual_workspace_bytes(const fst_model* m, int64_t mrows) {
+  FST_SIZE_TRY
   if (!m || m->d != 3 || mrows < 0) return 0;
   return residual_workspace_bytes(m, mrows);
+  FST_SIZE_CATCH
 }
 
 fst_status fst_residual(const fst_model* m, int32_t dtype, int64_t n, const void* x, const void* y,
@@ -926,8 +947,10 @@ fst_status fst_residual(const fst_model* m, int32_t dtype, int64_t n, const void
 }
 
 size_t fst_refine_workspace_bytes(const fst_model* m, int64_t mrows) {
+  FST_SIZE_TRY
   if (!m || m->d != 3 || mrows < 0) return 0;
   return align_up(sizeof(double) * (size_t)m->R()) + residual_workspace_bytes(m, mrows);
+  FST_SIZE_CATCH
 }
 
 fst_status fst_refine_step(const fst_model* m, int32_t dtype, int64_t n, const void* x, const void* y,
@@ -1145,7 +1168,7 @@ size_t fst_fit_d_workspace_bytes(const fst_fit_params_d* p, int64_t n) {
     // the refit of a model with the largest ranks allowed (eps may choose smaller ones)
     std::unique_ptr<fst_model> cap(model_new_d(p->d, p->lo, p->hi, p->rank, p->degree));
     return std::max(gather_workspace_bytes(K, p->d), dway_refit_layout(cap.get(), p->dtype, p->n_samples).total);
-  } catch (const fst::Error& e) {
+  } catch (const std::exception& e) {
     fst::set_last_error(e.what());
     return 0;
   }
@@ -1200,8 +1223,10 @@ fst_status fst_fit_d(const fst_fit_params_d* p, int64_t n, const void* const* co
 }
 
 size_t fst_refit_core_d_workspace_bytes(const fst_model* m, int32_t dtype, int64_t n_samples) {
+  FST_SIZE_TRY
   if (!m || (dtype != FST_F64 && dtype != FST_F32) || n_samples < 1) return 0;
   return dway_refit_layout(m, dtype, n_samples).total;
+  FST_SIZE_CATCH
 }
 
 fst_status fst_refit_core_d(const fst_model* m, int32_t dtype, int64_t n, const void* const* coords, const void* v,

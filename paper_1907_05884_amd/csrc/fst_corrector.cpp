@@ -81,7 +81,7 @@ size_t fst_corrector_workspace_bytes(const fst_train_params* tp, int64_t n) {
   try {
     check_train_params(tp);
     return fst::mlp_train_workspace_bytes(tp->batch) + 2 * fst::align_up(sizeof(double) * (size_t)std::max<int64_t>(n, 1));
-  } catch (const fst::Error& e) {
+  } catch (const std::exception& e) {
     fst::set_last_error(e.what());
     return 0;
   }

@@ -512,3 +512,48 @@ def test_wavelet_parameters_are_validated():
     with pytest.raises(fst.FstError):
         fst.fst_model_from_parts((-1.0,) * 3, (1.0,) * 3, (2, 2, 2), (4, 4, 4), core, big,
                                  wavelet=((1, 1), (1, 1), (9, 1)))
+
+
+def test_dense_route_sizes_and_argument_checks():
+    # workspace of the dense Gram route: the A^T v partials plus R x (M rounded up to 64) rows
+    # of the row dtype; 0 for 4-way models, no rows or an unknown dtype.  The argument checks
+    # of fst_design_rows / fst_gram_rows fail before any device work.
+    core, coefs = datagen.random_model_parts(2, (3, 4, 5), (4, 5, 6))
+    m = fst.fst_model_from_parts((0, 0, 0), (1, 1, 1), (3, 4, 5), (4, 5, 6), core, coefs)
+    base = fst.fst_gram_workspace_bytes(m, 1000)
+    for dt, es in ((fst.FST_F32, 4), (fst.FST_F64, 8)):
+        got = fst.fst_gram_dense_workspace_bytes(m, dt, 1000)
+        assert got >= base + es * 60 * 1024 and got < base + es * 60 * 1024 + 512
+    assert fst.fst_gram_dense_workspace_bytes(m, fst.FST_F32, 0) == 0
+    assert fst.fst_gram_dense_workspace_bytes(m, 7, 1000) == 0
+    assert fst.fst_gram_dense_workspace_bytes(_model4()[1], fst.FST_F32, 1000) == 0
+    fake = ctypes.c_void_p(256)             # never dereferenced: every call below is rejected
+    bad_design = [(1000, 1000), (1000, 960), (0, 64)]   # Sp not a multiple of 64; Sp < mrows; no rows
+    for mrows, Sp in bad_design:
+        st = fst._fn["fst_design_rows"](m.handle, fst.FST_F32, mrows, fake, None, Sp, fake, None, None)
+        assert st == fst.FST_E_INVAL, (mrows, Sp)
+    st = fst._fn["fst_design_rows"](m.handle, fst.FST_F32, 100, fake, None, 128, fake, fake, None)
+    assert st == fst.FST_E_INVAL and "values" in fst.fst_last_error()       # b without vs
+    assert fst._fn["fst_design_rows"](None, fst.FST_F32, 100, fake, None, 128, fake, None, None) == fst.FST_E_INVAL
+    for R, Sp in ((0, 64), (60, 0), (60, 100)):
+        assert fst._fn["fst_gram_rows"](fst.FST_F32, R, Sp, fake, None, fake, None, 0, None) == fst.FST_E_INVAL
+    assert fst._fn["fst_gram_rows"](fst.FST_F32, 60, 64, fake, None, None, None, 0, None) == fst.FST_E_INVAL
+    assert fst._fn["fst_gram_rows"](fst.FST_F32, 60, 64, fake, None, None, fake, 0, None) == fst.FST_E_INVAL
+    assert fst._fn["fst_gram_rows"](fst.FST_F32, 1 << 20, 1 << 21, fake, None, fake, None, 0,
+                                    None) == fst.FST_E_UNSUPPORTED
+
+
+def test_size_queries_need_no_device():
+    # every workspace size is a function of the arguments alone (no device query), so it can
+    # be taken on a machine without a GPU and gives the same answer on any one
+    core, coefs = datagen.random_model_parts(3, (6, 5, 4), (8, 8, 8))
+    m = fst.fst_model_from_parts((0, 0, 0), (1, 1, 1), (6, 5, 4), (8, 8, 8), core, coefs)
+    g = fst.fst_gram_workspace_bytes(m, 5000)
+    assert g >= 8 * 120
+    assert fst.fst_refit_workspace_bytes(m, fst.FST_F32, 5000, 0) > g
+    assert fst.fst_refit_workspace_bytes(m, fst.FST_F64, 5000, 3) > g
+    assert fst.fst_refine_workspace_bytes(m, 5000) > g
+    assert fst._fn["fst_residual_workspace_bytes"](m.handle, 5000) > g
+    p = fst.make_params(rank=(6, 5, 4), grid=(8, 8, 8), degree=(8, 8, 8), n_samples=5000)
+    assert fst.fst_fit_workspace_bytes(p, 100000) > 0
+    assert fst._fn["fst_refit_core_mixed_workspace_bytes"](m.handle, fst.FST_F32, 100000, 5000) > 0
