@@ -107,6 +107,73 @@ static DwayLayout dway_layout(const fst_model* m, int dtype, int64_t M) {
 
 size_t dway_workspace_bytes(const fst_model* m, int dtype, int64_t M) { return dway_layout(m, dtype, M).total; }
 
+// 3-way models: each thread forms 16 / sizeof(T) consecutive rows with 16-byte loads of the
+// factor values and 16-byte stores of A^T (same products in the same order as k_design_rows);
+// threads that reach past the chunk's last row take their rows one by one.  Needs U rows and
+// the chunk start aligned to the vector width (M and q0 multiples of it).  Workgroup order as
+// in k_design_rows, with super-blocks of DRV_SUPER blocks of DR_THREADS vectors.
+constexpr int64_t DRV_SUPER = 4;
+
+template <typename T>
+__global__ __launch_bounds__(DR_THREADS) void k_design_rows_vec(DesignArgs<T> a, int64_t sb0) {
+  constexpr int VW = 16 / (int)sizeof(T);
+  typedef T TV __attribute__((ext_vector_type(VW)));
+  const int64_t P = (int64_t)a.r[0] * a.r[1], nb = (a.Sp + DR_THREADS * VW - 1) / (DR_THREADS * VW);
+  const int64_t sb = sb0 + (int64_t)blockIdx.x / (P * DRV_SUPER), rem = (int64_t)blockIdx.x % (P * DRV_SUPER);
+  const int64_t w = min(DRV_SUPER, nb - sb * DRV_SUPER);
+  if (w <= 0) return;
+  const int64_t pr = rem / w, cb = sb * DRV_SUPER + rem % w;
+  if (pr >= P) return;
+  const int64_t q = (cb * DR_THREADS + threadIdx.x) * VW;
+  if (q >= a.Sp) return;
+  const int j1 = (int)(pr / a.r[1]), j2 = (int)(pr - (int64_t)j1 * a.r[1]);
+  const T* U1 = a.U + (int64_t)(a.off[0] + j1) * a.M + a.q0;
+  const T* U2 = a.U + (int64_t)(a.off[1] + j2) * a.M + a.q0;
+  const T* U3 = a.U + (int64_t)a.off[2] * a.M + a.q0;
+  T* dst = a.At + pr * a.r[2] * a.Sp + q;
+  const bool full = q + VW <= a.mc;
+  TV p12;
+  if (full) {
+    p12 = *reinterpret_cast<const TV*>(U1 + q) * *reinterpret_cast<const TV*>(U2 + q);
+  } else {
+#pragma unroll
+    for (int e = 0; e < VW; ++e) {
+      const int64_t c = min(q + e, a.mc - 1);
+      p12[e] = q + e < a.mc ? U1[c] * U2[c] : T(0);
+    }
+  }
+  for (int j3 = 0; j3 < a.r[2]; ++j3) {
+    const T* u3 = U3 + (int64_t)j3 * a.M;
+    TV f;
+    if (full) {
+      f = *reinterpret_cast<const TV*>(u3 + q);
+    } else {
+#pragma unroll
+      for (int e = 0; e < VW; ++e) f[e] = u3[min(q + e, a.mc - 1)];
+    }
+    *reinterpret_cast<TV*>(dst + (int64_t)j3 * a.Sp) = p12 * f;
+  }
+  if (pr == 0 && a.b) {
+    TV bv;
+#pragma unroll
+    for (int e = 0; e < VW; ++e) bv[e] = q + e < a.mc ? a.vs[a.q0 + q + e] : T(0);
+    *reinterpret_cast<TV*>(a.b + q) = bv;
+  }
+}
+
+template <typename T>
+static void design_launch_vec(const DesignArgs<T>& a, void* stream) {
+  constexpr int VW = 16 / (int)sizeof(T);
+  const int64_t P = (int64_t)a.r[0] * a.r[1], nb = (a.Sp + DR_THREADS * VW - 1) / (DR_THREADS * VW);
+  const int64_t nsb = (nb + DRV_SUPER - 1) / DRV_SUPER, per = std::max<int64_t>(1, (int64_t(1) << 30) / (P * DRV_SUPER));
+  for (int64_t sb0 = 0; sb0 < nsb; sb0 += per) {
+    const int64_t n = std::min(per, nsb - sb0);
+    hipLaunchKernelGGL(k_design_rows_vec<T>, dim3((unsigned)(n * P * DRV_SUPER)), dim3(DR_THREADS), 0, S(stream), a,
+                       sb0);
+    check_launch("k_design_rows_vec");
+  }
+}
+
 template <typename T, int RP>
 static void design_launch(const DesignArgs<T>& a, void* stream) {
   const int64_t P = (int64_t)a.r[0] * a.r[1], nb = (a.Sp + DR_THREADS - 1) / DR_THREADS;
@@ -144,6 +211,11 @@ static void design_chunk(const fst_model* m, DesignArgs<T>& a, int64_t q0, int64
   a.q0 = q0;
   a.mc = mc;
   a.Sp = Sp;
+  constexpr int VW = 16 / (int)sizeof(T);
+  if (m->d == 3 && a.M % VW == 0 && q0 % VW == 0) {
+    design_launch_vec(a, stream);
+    return;
+  }
   switch (m->d == 4 ? pad8(m->rank[3]) : 1) {
     case 1: design_launch<T, 1>(a, stream); break;
     case 8: design_launch<T, 8>(a, stream); break;

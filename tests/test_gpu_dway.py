@@ -215,9 +215,12 @@ def test_fit_d_four_way_fp32_ranks_from_precision(dev):
 
 
 # ------------------------------------------------------------------------------ dense route calls
+# 3-way rows whose count is a multiple of 4 take the vector kernel (4 FP32 or 2 FP64 rows per
+# thread), the others the scalar one; both with a padded tail
 @pytest.mark.parametrize("rank,mrows,Sp", [((3, 2, 4, 2), 1000, 1024), ((5, 6, 7, 9), 777, 832),
                                            ((4, 3, 5), 130, 192), ((1, 1, 1, 1), 1, 64),
-                                           ((6, 5, 4, 17), 4097, 4160)])
+                                           ((6, 5, 4, 17), 4097, 4160), ((4, 3, 5), 1000, 1024),
+                                           ((7, 6, 5), 4100, 4160), ((2, 1, 3), 4, 64)])
 def test_design_rows_and_gram_rows(dev, rank, mrows, Sp):
     # the design rows of eq. (6) from arbitrary factor values: the kernel forms the products in
     # the oracle's order, so FP64 rows are bit-exact; then G and h from the rows in two chunks

@@ -133,7 +133,8 @@ def test_gram_is_deterministic(dev):
 # dense route of fst_gram: design rows materialised transposed in the workspace, then the
 # dense MFMA Gram; one chunk holding every row, or 4096-row chunks with a ragged last one
 @pytest.mark.parametrize("dtype,tol", [(np.float64, 1e-10), (np.float32, 1e-5)])
-@pytest.mark.parametrize("rank,degree,m", [((5, 7, 3), (9, 12, 6), 777), ((12, 11, 10), (20, 20, 20), 9001)])
+@pytest.mark.parametrize("rank,degree,m", [((5, 7, 3), (9, 12, 6), 777), ((12, 11, 10), (20, 20, 20), 9001),
+                                           ((12, 11, 10), (20, 20, 20), 9004)])
 @pytest.mark.parametrize("chunked", [False, True])
 def test_gram_dense_route_parity(dev, dtype, tol, rank, degree, m, chunked):
     om, gm = _models(31, rank, degree)
