@@ -459,8 +459,8 @@ def main():
     ap.add_argument("--lr", type=float, default=1e-3, help="corrector: Adam learning rate")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the method shards by points; see the design notes). Run with --gpus 1.", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(the method would shard by points). Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
     if args.workload == "corrector":
         return run_corrector(args)

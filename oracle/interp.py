@@ -2,7 +2,7 @@
 
 Sec. 4.1: a small random subset of the data (about 10%) is interpolated onto an
 equispaced grid I_1 x ... x I_d, and the grid tensor is then Tucker-decomposed.  The paper
-says "linear interpolation"; this build interpolates by inverse distance weighting over
+says "linear interpolation"; this implementation interpolates by inverse distance weighting over
 the k = 8 nearest subset points with power 2, which needs no triangulation of scattered
 3-D data.  Readings taken:
 * grid nodes are equispaced in reference coordinates and include both end points,

@@ -3,8 +3,9 @@
 Sec. 4.2 represents column j of W^(k), sampled at the grid nodes, as a function
 w_j(y) = sum_i c_i phi_i(y) with few non-zero c_i, found by sparsity-regularised least
 squares (Sec. 3, eq. (3)-(5)) with the regularisation chosen by leave-one-out error.  The
-paper uses Lasso-LARS; this build uses orthogonal matching pursuit, a greedy solver of the
-l0-constrained problem (3), and keeps the leave-one-out model selection:
+paper uses Lasso-LARS (``oracle.lars``, solver "lars"); the default solver here is
+orthogonal matching pursuit, a greedy solver of the l0-constrained problem (3), with the same
+leave-one-out model selection:
 
 1. start from the residual r = z and an empty support S;
 2. repeatedly add the column m not in S with the largest normalised correlation
