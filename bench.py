@@ -109,14 +109,34 @@ def cpu_baseline_leg(w, lo, hi, rank, degree, core_gpu, coefs, idx_host, gpu_sam
         # the field of the oracle's own FP64 core: end-to-end rel-L2 of the GPU reconstruction
         f_or = reconstruct.evaluate(om.with_core(core_oracle), pts64[:npts])
         out["field_vs_oracle_core"] = float(np.linalg.norm(gpu_sample["f"][:npts] - f_or) / np.linalg.norm(f_or))
-    cores = 0
+    cores, blas = 0, []
     for info in threadpool_info():
         if info.get("user_api") == "blas":
             cores = max(cores, int(info.get("num_threads", 0)))
+            blas.append(f"{info.get('internal_api')} {info.get('version')}")
+    # the same rows with the BLAS on one thread, on a smaller sample (the first 512 rows)
+    from threadpoolctl import threadpool_limits
+    n1 = min(512, len(rows))
+    with threadpool_limits(limits=1, user_api="blas"):
+        t2 = time.perf_counter()
+        A = lsq.design_rows(lsq.factor_values(om, pts64[rows[:n1]]))
+        G1 = A.T @ A
+        _ = A.T @ v64[rows[:n1]]
+        t_one = time.perf_counter() - t2
+    del A, G1
+    cpu_model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            cpu_model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
+    except OSError:
+        pass
     cpu = {"value": done / t_rows, "unit": "rows/s", "cores": cores or os.cpu_count(), "kind": "oracle",
            "sample": f"{done} of the M sampled rows of this workload (R={R}): FP64 design rows + Gram + A^T v "
                      f"in {t_rows:.1f} s; reconstruction of {npts} points at {npts / t_pts:.3g} points/s",
-           "points_per_s": npts / t_pts}
+           "points_per_s": npts / t_pts,
+           "single_core": {"value": n1 / t_one, "unit": "rows/s", "sample": f"the first {n1} of those rows, "
+                                                                             f"BLAS on one thread"},
+           "host": {"nproc": os.cpu_count(), "cpu_model": cpu_model, "blas": ", ".join(blas)}}
     return cpu, out
 
 
