@@ -211,8 +211,8 @@ size_t fst_gram_workspace_bytes(const fst_model* m, int64_t mrows);
  * as fit (all of them with this size: R x M x 4 bytes for FP32, 11 GB at R = 13,824,
  * M = 200,000), and G is formed from them by a dense MFMA Gram (FP32 partial sums folded into
  * FP64 every 64 rows, as in the other route).  Otherwise G is formed from U directly.
- * fst_refit_core takes the same route when its workspace exceeds fst_refit_workspace_bytes by
- * this much. */
+ * fst_refit_core and fst_fit take the same route when their workspace exceeds
+ * fst_refit_workspace_bytes (fst_fit_workspace_bytes) by this much. */
 size_t fst_gram_dense_workspace_bytes(const fst_model* m, int32_t dtype, int64_t mrows);
 fst_status fst_gram(const fst_model* m, int32_t dtype, int64_t mrows, const void* U,
                     const void* vs, int32_t gram_prec, double* G, double* h, void* ws,
