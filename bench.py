@@ -475,9 +475,8 @@ def main():
                     help="Gram precision: f32 (FP32 MFMA) or the 16-bit form with FP64 refinement")
     ap.add_argument("--refine", type=int, default=None, help="refinement steps (default 0 for f32, 3 otherwise)")
     ap.add_argument("--gram-route", choices=("dense", "khatri-rao"), default="dense",
-                    help="FP32 Gram: design rows materialised + dense MFMA Gram (default), or formed on the fly "
-                         "from the factor values (the route with a minimal workspace); 16-bit Grams always "
-                         "take the latter")
+                    help="Gram: design rows materialised + dense MFMA Gram (default), or formed on the fly "
+                         "from the factor values (the route with a minimal workspace)")
     ap.add_argument("--workload", choices=("large_f32", "corrector", "batched", "copy", "spacetime"),
                     default="large_f32")
     ap.add_argument("--lr", type=float, default=1e-3, help="corrector: Adam learning rate")
@@ -549,8 +548,11 @@ def main():
     # FP32: the dense route, design rows materialised transposed (R x Sp FP32, 11 GB), then the
     # dense MFMA Gram; 16-bit Grams form the rows on the fly (Khatri-Rao kernel)
     dense = args.precision == "f32" and args.gram_route == "dense"
+    dense16 = args.precision != "f32" and args.gram_route == "dense"
     Sp = (M + 63) // 64 * 64
     At = torch.empty((R, Sp), dtype=torch.float32, device=dev) if dense else None
+    if dense16:   # fst_gram takes the 16-bit dense route given room for the 16-bit rows
+        gws = torch.empty(fst.fst_gram_dense_workspace_bytes(m0, fst.FST_F32, M), dtype=torch.uint8, device=dev)
     rws = torch.empty(max(fst.fst_refine_workspace_bytes(m0, M), 256), dtype=torch.uint8, device=dev)
     alpha_steps = []
     coefs = [m0.coefs(k) for k in range(3)]
@@ -696,7 +698,9 @@ def main():
                                f"(R={R}); Legendre degree 31; M={M} sampled LS rows; reconstruct all N",
                    "gram": ("design rows materialised (k_design_rows), dense FP32 MFMA (k_gram_dense)" if dense
                             else {"f32": "FP32 MFMA on rows formed from the factor values (k_gram)",
-                                  "bf16": "BF16 MFMA", "f16": "FP16 MFMA (scaled)"}[args.precision])
+                                  "bf16": "BF16 MFMA", "f16": "FP16 MFMA (scaled)"}[args.precision]
+                            + (", 16-bit design rows materialised (k_design_rows16, k_gram_dense16)" if dense16
+                               else ""))
                            + ", FP32 accumulation folded into FP64", "solve": "FP64 Cholesky",
                    "refine_steps": refine, "model": model_src},
         "reconstructed_points_per_s": points_per_s,
@@ -730,8 +734,9 @@ def main():
             "data_rel_l2": float(np.sqrt(sm_err / sm_v)), "data_rel_l2_unmixed": eps_data},
         "spacetime": spacetime,
         "wavelet": None if wavelet is None else dict(wavelet, data_rel_l2_legendre=eps_data),
-        "roofline": {"kernel": "k_gram_dense<float>" if dense else ("k_gram<float>" if args.precision == "f32"
-                                                                     else f"k_gram_lp<{args.precision}>"),
+        "roofline": {"kernel": "k_gram_dense<float>" if dense else (
+                         f"k_gram_dense16<{args.precision}> with its k_design_rows16 (one fst_gram call)" if dense16
+                         else "k_gram<float>" if args.precision == "f32" else f"k_gram_lp<{args.precision}>"),
                      "bound": "mfma", "achieved": achieved / 1e12,
                      "peak": peak / 1e12, "unit": "TFLOP/s", "frac": achieved / peak,
                      "traffic": measured_traffic(args.precision if dense or args.precision != "f32"

@@ -30,6 +30,22 @@ template <> struct MfmaAcc<double> {
   static __device__ inline int row(int g, int v) { return g + 4 * v; }
 };
 
+// 16-bit operands, MFMA 16x16x32 with FP32 accumulation: lane l supplies 8 consecutive k of
+// row l % 16 (k group l / 16); output layout as MfmaAcc<float> (lane l: D[4 (l / 16) + v][l % 16])
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 halfx8 __attribute__((ext_vector_type(8)));
+typedef float floatx8 __attribute__((ext_vector_type(8)));
+
+template <typename H> struct Mfma16;
+template <> struct Mfma16<__bf16> {
+  typedef bf16x8 V8;
+  static __device__ inline floatx4 mfma(V8 a, V8 b, floatx4 c) { return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0); }
+};
+template <> struct Mfma16<_Float16> {
+  typedef halfx8 V8;
+  static __device__ inline floatx4 mfma(V8 a, V8 b, floatx4 c) { return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0); }
+};
+
 // ------------------------------------------------------------------------------ basis
 // Orthonormal Legendre recurrence phi_{m+1} = a_m t phi_m - b_m phi_{m-1}, phi_0 = 1,
 // phi_1 = sqrt(3) t, from Bonnet's recurrence with phi_m = sqrt(2m+1) P_m:

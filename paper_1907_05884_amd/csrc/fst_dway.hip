@@ -174,6 +174,65 @@ static void design_launch_vec(const DesignArgs<T>& a, void* stream) {
   }
 }
 
+// 16-bit design rows of a 3-way model for the precision form: entry ((u1 u2) scale) u3 formed
+// in FP32 and rounded to H (the scale a power of two, 1 for BF16), as the Khatri-Rao
+// precision-form Gram forms its operands; 8 consecutive rows per thread, one 16-byte store per
+// design column; rows past mc are zero.  Workgroup order as k_design_rows_vec.
+template <typename H>
+__global__ __launch_bounds__(DR_THREADS) void k_design_rows16(DesignArgs<float> a, H* At, float scale, int64_t sb0) {
+  constexpr int VW = 8;
+  typedef H HV __attribute__((ext_vector_type(8)));
+  typedef float F4 __attribute__((ext_vector_type(4)));
+  const int64_t P = (int64_t)a.r[0] * a.r[1], nb = (a.Sp + DR_THREADS * VW - 1) / (DR_THREADS * VW);
+  const int64_t sb = sb0 + (int64_t)blockIdx.x / (P * DRV_SUPER), rem = (int64_t)blockIdx.x % (P * DRV_SUPER);
+  const int64_t w = min(DRV_SUPER, nb - sb * DRV_SUPER);
+  if (w <= 0) return;
+  const int64_t pr = rem / w, cb = sb * DRV_SUPER + rem % w;
+  if (pr >= P) return;
+  const int64_t q = (cb * DR_THREADS + threadIdx.x) * VW;
+  if (q >= a.Sp) return;
+  const int j1 = (int)(pr / a.r[1]), j2 = (int)(pr - (int64_t)j1 * a.r[1]);
+  const float* U1 = a.U + (int64_t)(a.off[0] + j1) * a.M;
+  const float* U2 = a.U + (int64_t)(a.off[1] + j2) * a.M;
+  const float* U3 = a.U + (int64_t)a.off[2] * a.M;
+  const bool vec = q + VW <= a.mc && a.M % 4 == 0;
+  float p12[VW];
+  if (vec) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const F4 x = *reinterpret_cast<const F4*>(U1 + q + 4 * h), y = *reinterpret_cast<const F4*>(U2 + q + 4 * h);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) p12[4 * h + e] = x[e] * y[e] * scale;
+    }
+  } else {
+#pragma unroll
+    for (int e = 0; e < VW; ++e) {
+      const int64_t c = min(q + e, a.mc - 1);
+      p12[e] = q + e < a.mc ? U1[c] * U2[c] * scale : 0.0f;
+    }
+  }
+  H* dst = At + pr * a.r[2] * a.Sp + q;
+  for (int j3 = 0; j3 < a.r[2]; ++j3) {
+    const float* u3 = U3 + (int64_t)j3 * a.M;
+    float f[VW];
+    if (vec) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const F4 z = *reinterpret_cast<const F4*>(u3 + q + 4 * h);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) f[4 * h + e] = z[e];
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < VW; ++e) f[e] = u3[min(q + e, a.mc - 1)];
+    }
+    HV hv;
+#pragma unroll
+    for (int e = 0; e < VW; ++e) hv[e] = (H)(p12[e] * f[e]);
+    *reinterpret_cast<HV*>(dst + (int64_t)j3 * a.Sp) = hv;
+  }
+}
+
 template <typename T, int RP>
 static void design_launch(const DesignArgs<T>& a, void* stream) {
   const int64_t P = (int64_t)a.r[0] * a.r[1], nb = (a.Sp + DR_THREADS - 1) / DR_THREADS;
@@ -267,6 +326,25 @@ void design_rows(const fst_model* m, int dtype, int64_t mrows, const void* U, co
   } else {
     DesignArgs<float> a = design_args(m, (const float*)U, (const float*)vs, mrows, (float*)At, (float*)b);
     design_chunk(m, a, 0, mrows, Sp, stream);
+  }
+}
+
+void design_rows16(const fst_model* m, int gram_prec, int64_t mrows, const float* U, int64_t Sp, void* At, float scale,
+                   void* stream) {
+  if (m->d != 3 || mrows < 1 || Sp < mrows || Sp % 8 != 0) fail(FST_E_INVAL, "16-bit design rows: bad sizes");
+  DesignArgs<float> a = design_args<float>(m, U, nullptr, mrows, nullptr, nullptr);
+  a.q0 = 0;
+  a.mc = mrows;
+  a.Sp = Sp;
+  const int64_t P = (int64_t)a.r[0] * a.r[1], nb = (Sp + DR_THREADS * 8 - 1) / (DR_THREADS * 8);
+  const int64_t nsb = (nb + DRV_SUPER - 1) / DRV_SUPER, per = std::max<int64_t>(1, (int64_t(1) << 30) / (P * DRV_SUPER));
+  for (int64_t sb0 = 0; sb0 < nsb; sb0 += per) {
+    const dim3 g((unsigned)(std::min(per, nsb - sb0) * P * DRV_SUPER));
+    if (gram_prec == FST_GRAM_BF16)
+      hipLaunchKernelGGL(k_design_rows16<__bf16>, g, dim3(DR_THREADS), 0, S(stream), a, (__bf16*)At, scale, sb0);
+    else
+      hipLaunchKernelGGL(k_design_rows16<_Float16>, g, dim3(DR_THREADS), 0, S(stream), a, (_Float16*)At, scale, sb0);
+    check_launch("k_design_rows16");
   }
 }
 

@@ -198,6 +198,12 @@ constexpr int64_t GD_SP_MULTIPLE = 64;
 size_t dense_rows_bytes(const fst_model* m, int dtype, int64_t chunk);
 void dense_gram_from_rows(const fst_model* m, int dtype, int64_t mrows, const void* U, double* G, void* At,
                           int64_t chunk, void* stream);
+// the dense route of the 16-bit Gram (3-way, FP32 factor values): A^T rounded to BF16 or scaled
+// FP16 (R x Sp 16-bit entries, Sp a multiple of GD16_SP_MULTIPLE), then G = sums x unscale
+constexpr int64_t GD16_SP_MULTIPLE = 128;
+void design_rows16(const fst_model* m, int gram_prec, int64_t mrows, const float* U, int64_t Sp, void* At, float scale,
+                   void* stream);
+void dense_gram16(int gram_prec, const void* At, int64_t R, int64_t Sp, double* G, double unscale, void* stream);
 // A^T (R x Sp) and b (Sp, may be NULL) of mrows rows given by their factor values and values
 void design_rows(const fst_model* m, int dtype, int64_t mrows, const void* U, const void* vs, int64_t Sp, void* At,
                  void* b, void* stream);

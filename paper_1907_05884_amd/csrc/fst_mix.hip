@@ -298,6 +298,117 @@ __global__ __launch_bounds__(GD_THREADS) void k_gram_dense(const T* At, int64_t 
       }
 }
 
+// The same Gram from 16-bit rows (BF16, or FP16 already scaled by a power of two): chunks of
+// GD16_KC = 128 points through double-buffered LDS, MFMA 16x16x32 with lane group g taking
+// the points 32 ks + 8 g .. + 7 of step ks, FP32 accumulation folded into FP64 every chunk,
+// G = sums x unscale.  This is the arithmetic of the Khatri-Rao precision-form kernel on the
+// same 16-bit entries.  Sp: a multiple of GD16_KC.
+constexpr int GD16_KC = 128;
+
+template <typename H>
+__global__ __launch_bounds__(GD_THREADS) void k_gram_dense16(const H* At, int64_t R, int64_t Sp, double* G,
+                                                            double unscale, int accumulate) {
+  typedef typename Mfma16<H>::V8 V8;
+  constexpr int KC = GD16_KC, KCP = KC + 8, VW = 8;
+  constexpr int PIECES = 2 * GD_TILE * KC / VW / GD_THREADS;   // 16-byte pieces per thread per chunk
+  __shared__ __align__(16) H sA[2][2 * GD_TILE][KCP];
+  int64_t bi, bj;
+  tri_tile(blockIdx.x, bi, bj);
+  const int64_t r0 = bi * GD_TILE, c0 = bj * GD_TILE;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wr = wave >> 2, wc = wave & 3, li = lane & 15, g = lane >> 4;
+  const int row0 = wr * 32, col0 = wc * 32;
+  const bool active = c0 + col0 <= r0 + row0 + 31;
+  V8 pf[PIECES];
+  auto fetch = [&](int64_t k0) {
+#pragma unroll
+    for (int u = 0; u < PIECES; ++u) {
+      const int e = threadIdx.x + GD_THREADS * u;
+      const int r = e / (KC / VW), pc = e % (KC / VW);
+      const int64_t gr = r < GD_TILE ? r0 + r : c0 + (r - GD_TILE);
+      V8 val = V8{};
+      if (gr < R) val = *reinterpret_cast<const V8*>(&At[gr * Sp + k0 + pc * VW]);
+      pf[u] = val;
+    }
+  };
+  auto stash = [&](int b) {
+#pragma unroll
+    for (int u = 0; u < PIECES; ++u) {
+      const int e = threadIdx.x + GD_THREADS * u;
+      const int r = e / (KC / VW), pc = e % (KC / VW);
+      *reinterpret_cast<V8*>(&sA[b][r][pc * VW]) = pf[u];
+    }
+  };
+  floatx4 acc[2][2];
+  double dacc[2][2][4];
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y) {
+      acc[x][y] = floatx4{0, 0, 0, 0};
+#pragma unroll
+      for (int v = 0; v < 4; ++v) dacc[x][y][v] = 0.0;
+    }
+  const int64_t nch = Sp / KC;
+  fetch(0);
+  stash(0);
+  __syncthreads();
+  for (int64_t ch = 0; ch < nch; ++ch) {
+    const int b = (int)(ch & 1);
+    if (ch + 1 < nch) fetch((ch + 1) * KC);
+    if (active) {
+#pragma unroll
+      for (int ks = 0; ks < KC / 32; ++ks) {
+        const int p = ks * 32 + g * 8;
+        V8 av[2], bv[2];
+#pragma unroll
+        for (int x = 0; x < 2; ++x) av[x] = *reinterpret_cast<const V8*>(&sA[b][row0 + x * 16 + li][p]);
+#pragma unroll
+        for (int y = 0; y < 2; ++y) bv[y] = *reinterpret_cast<const V8*>(&sA[b][GD_TILE + col0 + y * 16 + li][p]);
+#pragma unroll
+        for (int x = 0; x < 2; ++x)
+#pragma unroll
+          for (int y = 0; y < 2; ++y) acc[x][y] = Mfma16<H>::mfma(av[x], bv[y], acc[x][y]);
+      }
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) dacc[x][y][v] += (double)acc[x][y][v];
+          acc[x][y] = floatx4{0, 0, 0, 0};
+        }
+    }
+    if (ch + 1 < nch) stash(b ^ 1);
+    __syncthreads();
+  }
+  if (!active) return;
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t row = r0 + row0 + x * 16 + MfmaAcc<float>::row(g, v);
+        const int64_t col = c0 + col0 + y * 16 + li;
+        const double val = dacc[x][y][v] * unscale;
+        if (row < R && col <= row) G[row * R + col] = accumulate ? G[row * R + col] + val : val;
+      }
+}
+
+void dense_gram16(int gram_prec, const void* At, int64_t R, int64_t Sp, double* G, double unscale, void* stream) {
+  if (Sp % GD16_KC != 0 || Sp <= 0) fail(FST_E_INVAL, "dense 16-bit Gram: row count not padded");
+  const int64_t nt = (R + GD_TILE - 1) / GD_TILE;
+  const dim3 gg((unsigned)(nt * (nt + 1) / 2));
+  if (gram_prec == FST_GRAM_BF16)
+    hipLaunchKernelGGL(k_gram_dense16<__bf16>, gg, dim3(GD_THREADS), 0, S(stream), (const __bf16*)At, R, Sp, G,
+                       unscale, 0);
+  else
+    hipLaunchKernelGGL(k_gram_dense16<_Float16>, gg, dim3(GD_THREADS), 0, S(stream), (const _Float16*)At, R, Sp, G,
+                       unscale, 0);
+  check_launch("k_gram_dense16");
+}
+
 // h[j] = sum_q A^T[j][q] b[q] in FP64 (added to h[j] with accumulate != 0), one wave per row,
 // lanes striding over q in a fixed order
 template <typename T>

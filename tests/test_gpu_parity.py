@@ -157,6 +157,25 @@ def test_gram_dense_route_parity(dev, dtype, tol, rank, degree, m, chunked):
     assert torch.equal(G, G2)
 
 
+# dense route of the 16-bit Gram: the same 16-bit entries ((u1 u2) scale) u3 and the same
+# 16x16x32 MFMA sums per 128-point chunk as the Khatri-Rao precision-form kernel, so the two
+# Grams are equal bit for bit (row counts with and without 16-byte loads, r3 < 8)
+@pytest.mark.parametrize("prec", ["bf16", "f16"])
+@pytest.mark.parametrize("rank,degree,m", [((12, 11, 10), (20, 20, 20), 9004), ((5, 7, 3), (9, 12, 6), 777),
+                                           ((9, 8, 5), (15, 15, 15), 4101)])
+def test_gram_16bit_dense_route_equals_khatri_rao(dev, prec, rank, degree, m):
+    code = {"bf16": fst.FST_GRAM_BF16, "f16": fst.FST_GRAM_F16}[prec]
+    om, gm = _models(33, rank, degree)
+    pts = _pts(34, m, dtype=np.float32)
+    x, y, z = _soa(pts, dev)
+    U, _ = fst.fst_factor_eval(gm, x, y, z)
+    Gk, _ = fst.fst_gram(gm, U, gram_prec=code)
+    ws = torch.empty(fst.fst_gram_dense_workspace_bytes(gm, fst.FST_F32, m), dtype=torch.uint8, device=dev)
+    Gd, _ = fst.fst_gram(gm, U, gram_prec=code, ws=ws)
+    low = torch.tril(torch.ones_like(Gk, dtype=torch.bool))
+    assert torch.equal(Gd[low], Gk[low])
+
+
 def test_refit_dense_route_matches_oracle(dev):
     w, m0 = _small_workload_model()
     alpha_o, _, _, _ = lsq.refit_core(m0, w.pts, w.vals, w.n_samples, w.seed)
@@ -475,6 +494,14 @@ def test_full_size_against_oracle_reference(dev):
     assert rel_l2(outd.core, alpha) <= 1e-6
     out16 = fst.fst_refit_core(gm, x, y, z, v, w.n_samples, w.seed, gram_prec=fst.FST_GRAM_F16, refine_steps=9)
     assert rel_l2(out16.core, alpha) <= 1e-6
+    # the FP16 Gram by the dense route (16-bit rows materialised), then the same refinement
+    ws = torch.empty(fst.fst_refit_workspace_bytes(gm, fst.FST_F32, w.n_samples, 9)
+                     + fst.fst_gram_dense_workspace_bytes(gm, fst.FST_F32, w.n_samples), dtype=torch.uint8, device=dev)
+    out16d = fst.fst_refit_core(gm, x, y, z, v, w.n_samples, w.seed, gram_prec=fst.FST_GRAM_F16, refine_steps=9,
+                                ws=ws)
+    del ws
+    torch.cuda.empty_cache()
+    assert rel_l2(out16d.core, alpha) <= 1e-6
     # reconstruction at sampled output points, against the oracle's field of its own core
     om = OModel(w.lo, w.hi, w.rank, w.degree, alpha.reshape(w.rank), coefs)
     f = H(fst.fst_eval(out32, x, y, z))
