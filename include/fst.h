@@ -210,7 +210,10 @@ size_t fst_gram_workspace_bytes(const fst_model* m, int64_t mrows);
  * of the row dtype), the design rows are written transposed into it, as many rows at a time
  * as fit (all of them with this size: R x M x 4 bytes for FP32, 11 GB at R = 13,824,
  * M = 200,000), and G is formed from them by a dense MFMA Gram (FP32 partial sums folded into
- * FP64 every 64 rows, as in the other route).  Otherwise G is formed from U directly.
+ * FP64 every 64 rows, as in the other route).  With FST_GRAM_BF16 or FST_GRAM_F16 and room for
+ * all rows in 16 bits (R x (M rounded up to 128) x 2 bytes beyond the partials; this size
+ * holds them) the rows are written in BF16 or scaled FP16 and G formed by a dense 16-bit MFMA
+ * Gram, equal bit for bit to the other route's.  Otherwise G is formed from U directly.
  * fst_refit_core and fst_fit take the same route when their workspace exceeds
  * fst_refit_workspace_bytes (fst_fit_workspace_bytes) by this much. */
 size_t fst_gram_dense_workspace_bytes(const fst_model* m, int32_t dtype, int64_t mrows);
