@@ -652,8 +652,9 @@ def fst_gram_workspace_bytes(m: Model, mrows: int) -> int:
 
 def fst_gram(m: Model, U, vs=None, gram_prec=None, G=None, h=None, ws=None, stream=None, want_G=True):
     """G = A^T A (lower triangle) and h = A^T vs, FP64 device tensors (want_G=False: h only).
-    A workspace of fst_gram_dense_workspace_bytes bytes selects the dense route for FP32/FP64
-    Grams (design rows materialised in it, then the dense MFMA Gram)."""
+    A workspace of fst_gram_dense_workspace_bytes bytes selects the dense route (design rows
+    materialised in it, then a dense MFMA Gram; for BF16/FP16 Grams the rows are 16-bit and G
+    equals the other route's bit for bit)."""
     torch = _torch()
     dt = _dtype_code(U)
     if gram_prec is None:
