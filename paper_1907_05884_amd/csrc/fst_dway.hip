@@ -1,19 +1,22 @@
-// The d-way form of the hot path for gfx950: Algorithm 2 and the reconstruction of eq. (1)
-// for models with d = 4 modes (Sec. 2 states the format for any d; Sec. 6 compresses data in
-// three space dimensions plus time).  The refit also takes 3-way models (r4 = 1).
+// Materialised design rows and the d-way form of the hot path for gfx950: Algorithm 2 and the
+// reconstruction of eq. (1) for models with d = 4 modes (Sec. 2 states the format for any d;
+// Sec. 6 compresses data in three space dimensions plus time), and the dense route of the
+// 3-way Gram.  The d-way refit also takes 3-way models (r4 = 1).
 //
-//   k_factor_eval  eq. (2) at the M sampled rows for the d modes (fst_kernels.hip)
-//   k_design_rows  rows of W in eq. (6) for a chunk of sampled rows, written transposed:
-//                  A^T[j][q] = U1[q][j1] U2[q][j2] U3[q][j3] U4[q][j4],
-//                  j = ((j1 r2 + j2) r3 + j3) r4 + j4
-//   k_gram_dense   G += A^T A (lower triangle) of the chunk on MFMA, and h += A^T v (fst_mix.hip)
-//   k_eval4        eq. (1) at points of interest
+//   k_factor_eval      eq. (2) at the M sampled rows for the d modes (fst_kernels.hip)
+//   k_design_rows      rows of W in eq. (6) for a chunk of sampled rows, written transposed:
+//                      A^T[j][q] = U1[q][j1] U2[q][j2] U3[q][j3] U4[q][j4],
+//                      j = ((j1 r2 + j2) r3 + j3) r4 + j4
+//   k_design_rows_vec  the same for 3-way models, 16 / sizeof(T) rows per thread
+//   k_design_rows16    3-way rows in BF16 or scaled FP16 for the precision form
+//   k_gram_dense       G += A^T A (lower triangle) of the chunk on MFMA, and h += A^T v
+//                      (fst_mix.hip; k_gram_dense16 for 16-bit rows)
+//   k_eval4            eq. (1) at points of interest
 //
-// Rows are materialised here, unlike in the 3-way Gram, which forms them inside its MFMA
-// loop: a chunk of C = 16384 rows is R C values, written once at HBM speed, against 2 R^2 C
-// flop of Gram work on them, so the write costs about 1% of the contraction at R = 20,736 and
-// the dense Gram (its operands come straight from LDS) runs at the MFMA rate it reaches in the
-// mixed refit.
+// A chunk of C rows is R C values, written once at HBM speed, against 2 R^2 C flop of Gram
+// work on them, so the write costs about 1% of the contraction at R = 13,824-20,736, and the
+// dense Gram, whose operands come straight from LDS, runs faster than the Khatri-Rao Gram of
+// fst_kernels.hip, which forms the entries inside its MFMA loop.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -26,7 +29,7 @@
 namespace fst {
 
 // ------------------------------------------------------------------------------ design rows
-// One thread per row q of the chunk (q < Sp, rows mc .. Sp-1 are zero), one workgroup row per
+// One thread per row q of the chunk (q < Sp, rows mc .. Sp-1 are zero), each workgroup on one
 // (j1, j2) pair: the product u1 u2 is formed once, the r4 values of U4 are held in registers
 // (RP of them, clamped past r4; RP = 1 and u4 = 1 for a 3-way model) and every (j3, j4)
 // column is a coalesced run of 256 entries of A^T.  The workgroups of pair 0 also write b.
