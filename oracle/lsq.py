@@ -101,6 +101,13 @@ def residual_normal(model: Model, pts: np.ndarray, v: np.ndarray, alpha: np.ndar
 
 
 def leverage_scores(A: np.ndarray) -> np.ndarray:
-    """Squared row norms of the thin left singular factor of A (Sec. 5)."""
-    U, _, _ = np.linalg.svd(A, full_matrices=False)
-    return (U * U).sum(axis=1)
+    """Leverage of every row of A (Sec. 5): the squared row norms of the left singular
+    vectors that span the column space of A, i.e. those whose singular value exceeds
+    max(m, n) * eps * sigma_max.  They lie in [0, 1] and sum to rank(A)."""
+    A = np.asarray(A, np.float64)
+    U, s, _ = np.linalg.svd(A, full_matrices=False)
+    if s.size == 0 or s[0] == 0.0:
+        return np.zeros(A.shape[0])
+    keep = s > max(A.shape) * np.finfo(np.float64).eps * s[0]
+    Uk = U[:, keep]
+    return (Uk * Uk).sum(axis=1)
