@@ -28,7 +28,7 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK = {"f32": 157.3e12, "bf16": 2.5e15, "f16": 2.5e15}
+PEAK = {"f32": 157.3e12, "bf16": 2.5e15, "f16": 2.5e15, "f16x2": 2.5e15, "bf16x3": 2.5e15, "bf16x2": 2.5e15}
 GOLDEN = os.path.join(ROOT, "tests", "golden", "large_f32_reference.npz")
 TRAFFIC = os.path.join(ROOT, "profiles", "traffic_large.json")
 KERNELS_DIR = os.path.join(ROOT, "paper_1907_05884_amd", "csrc")
@@ -471,7 +471,7 @@ def main():
     ap.add_argument("--cpu-sample-rows", type=int, default=4096)
     ap.add_argument("--n", type=int, default=2_000_000)
     ap.add_argument("--samples", type=int, default=200_000)
-    ap.add_argument("--precision", choices=("f32", "bf16", "f16"), default="f32",
+    ap.add_argument("--precision", choices=("f32", "bf16", "f16", "f16x2", "bf16x3", "bf16x2"), default="f32",
                     help="Gram precision: f32 (FP32 MFMA) or the 16-bit form with FP64 refinement")
     ap.add_argument("--refine", type=int, default=None, help="refinement steps (default 0 for f32, 3 otherwise)")
     ap.add_argument("--gram-route", choices=("dense", "khatri-rao"), default="dense",
@@ -529,7 +529,9 @@ def main():
         m0 = fst.fst_model_from_parts(w.lo, w.hi, w.rank, w.degree, ref["core0"], rc)
         model_src = f"oracle host steps (library host steps agree to {host_vs_oracle:.1e} max abs)"
     refine = args.refine if args.refine is not None else (0 if args.precision == "f32" else 3)
-    gram_prec = {"f32": fst.FST_GRAM_F32, "bf16": fst.FST_GRAM_BF16, "f16": fst.FST_GRAM_F16}[args.precision]
+    gram_prec = {"f32": fst.FST_GRAM_F32, "bf16": fst.FST_GRAM_BF16, "f16": fst.FST_GRAM_F16,
+                 "f16x2": fst.FST_GRAM_F16X2, "bf16x3": fst.FST_GRAM_BF16X3,
+                 "bf16x2": fst.FST_GRAM_BF16X2}[args.precision]
     t = time.perf_counter()
     idx_host = fst.fst_sample_indices(w.seed, fst.FST_STREAM_LS, w.n, w.n_samples)
     t_sample = time.perf_counter() - t
@@ -551,7 +553,9 @@ def main():
     dense16 = args.precision != "f32" and args.gram_route == "dense"
     Sp = (M + 63) // 64 * 64
     At = torch.empty((R, Sp), dtype=torch.float32, device=dev) if dense else None
-    if dense16:   # fst_gram takes the 16-bit dense route given room for the 16-bit rows
+    if gram_prec in (fst.FST_GRAM_F16X2, fst.FST_GRAM_BF16X3, fst.FST_GRAM_BF16X2):   # split rows: planes
+        gws = torch.empty(fst.fst_gram_split_workspace_bytes(m0, gram_prec, M), dtype=torch.uint8, device=dev)
+    elif dense16:   # fst_gram takes the 16-bit dense route given room for the 16-bit rows
         gws = torch.empty(fst.fst_gram_dense_workspace_bytes(m0, fst.FST_F32, M), dtype=torch.uint8, device=dev)
     rws = torch.empty(max(fst.fst_refine_workspace_bytes(m0, M), 256), dtype=torch.uint8, device=dev)
     alpha_steps = []
@@ -698,7 +702,13 @@ def main():
                                f"(R={R}); Legendre degree 31; M={M} sampled LS rows; reconstruct all N",
                    "gram": ("design rows materialised (k_design_rows), dense FP32 MFMA (k_gram_dense)" if dense
                             else {"f32": "FP32 MFMA on rows formed from the factor values (k_gram)",
-                                  "bf16": "BF16 MFMA", "f16": "FP16 MFMA (scaled)"}[args.precision]
+                                  "bf16": "BF16 MFMA", "f16": "FP16 MFMA (scaled)",
+                                  "f16x2": "design rows split in two FP16 terms (scaled), 4 FP16 MFMA products "
+                                           "(k_design_rows_split, k_gram_split)",
+                                  "bf16x2": "design rows split in two BF16 terms, 4 BF16 MFMA products "
+                                            "(k_design_rows_split, k_gram_split)",
+                                  "bf16x3": "design rows split in three BF16 terms, 6 BF16 MFMA products "
+                                            "(k_design_rows_split, k_gram_split)"}[args.precision]
                             + (", 16-bit design rows materialised (k_design_rows16, k_gram_dense16)" if dense16
                                else ""))
                            + ", FP32 accumulation folded into FP64", "solve": "FP64 Cholesky",
@@ -735,6 +745,8 @@ def main():
         "spacetime": spacetime,
         "wavelet": None if wavelet is None else dict(wavelet, data_rel_l2_legendre=eps_data),
         "roofline": {"kernel": "k_gram_dense<float>" if dense else (
+                         f"k_gram_split<{args.precision}> with its k_design_rows_split (one fst_gram call)"
+                         if args.precision in ("f16x2", "bf16x3", "bf16x2") else
                          f"k_gram_dense16<{args.precision}> with its k_design_rows16 (one fst_gram call)" if dense16
                          else "k_gram<float>" if args.precision == "f32" else f"k_gram_lp<{args.precision}>"),
                      "bound": "mfma", "achieved": achieved / 1e12,

@@ -56,6 +56,12 @@ typedef int32_t fst_status;
 #define FST_GRAM_F32  1   /* FP32 rows, FP32 MFMA, FP32 partial sums folded into FP64 */
 #define FST_GRAM_BF16 2   /* BF16 rows, BF16 MFMA, FP32 accumulation folded into FP64 */
 #define FST_GRAM_F16  3   /* FP16 rows (scaled), FP16 MFMA, FP32 accumulation folded into FP64 */
+#define FST_GRAM_F16X2  4 /* FP16 rows split in two terms (hi + lo, scaled): four FP16 MFMA
+                              products per entry pair, FP32 sums folded into FP64 */
+#define FST_GRAM_BF16X3 5 /* BF16 rows split in three terms: six BF16 MFMA products per entry
+                              pair, FP32 sums folded into FP64 */
+#define FST_GRAM_BF16X2 6 /* BF16 rows split in two terms: four BF16 MFMA products per entry
+                              pair, FP32 sums folded into FP64 */
 
 /* random streams: state = seed * 256 + stream (SplitMix64) */
 /* sparse solver of the singular-vector fits (Sec. 3, 4.2), both with leave-one-out selection */
@@ -148,8 +154,11 @@ size_t fst_refit_workspace_bytes(const fst_model* m, int32_t dtype, int64_t n_sa
 /* Algorithm 2 (Sec. 5) for a given model's factor functions: re-estimates the core from
  * M = n_samples uniformly sampled rows (stream FST_STREAM_LS of `seed`).  x, y, z, v:
  * device arrays of `dtype`.  ws: device workspace >= fst_refit_workspace_bytes(...), or
- * NULL to let the library allocate it.  Writes the new core into *out (a new model with
- * m's factors).  Synchronises `stream`. */
+ * NULL to let the library allocate it: then it also allocates the room of the dense Gram
+ * route (fst_gram_dense_workspace_bytes or fst_gram_split_workspace_bytes beyond the
+ * minimum) when the device has that much free memory plus 2 GiB.  The split precisions
+ * (FST_GRAM_F16X2, BF16X3, BF16X2) need that room; without it the FP32 Gram is formed.  Writes the new
+ * core into *out (a new model with m's factors).  Synchronises `stream`. */
 fst_status fst_refit_core(const fst_model* m, int32_t dtype, int64_t n, const void* x,
                           const void* y, const void* z, const void* v, int64_t n_samples,
                           uint64_t seed, int32_t gram_prec, int32_t refine_steps, void* ws,
@@ -201,7 +210,7 @@ fst_status fst_factor_eval(const fst_model* m, int32_t dtype, int64_t n, const v
  * G = A^T A (lower triangle incl. diagonal written; strictly upper part untouched) and
  * h = A^T vs, with A[q, j] = U1[q, j1] U2[q, j2] U3[q, j3] formed on the fly from U as
  * written by fst_factor_eval (stored only by the dense route below, in the workspace).  U, vs: device, `dtype` (FST_F64 needs
- * gram_prec FST_GRAM_F64; FST_F32 takes F32, BF16 or F16).  G: device FP64 R x R
+ * gram_prec FST_GRAM_F64; FST_F32 takes F32, BF16, F16 or a split precision).  G: device FP64 R x R
  * row-major, h: device FP64 R; either may be NULL to skip that product (not both).  ws: device workspace >= fst_gram_workspace_bytes.
  * Asynchronous. */
 size_t fst_gram_workspace_bytes(const fst_model* m, int64_t mrows);
@@ -217,6 +226,19 @@ size_t fst_gram_workspace_bytes(const fst_model* m, int64_t mrows);
  * fst_refit_core and fst_fit take the same route when their workspace exceeds
  * fst_refit_workspace_bytes (fst_fit_workspace_bytes) by this much. */
 size_t fst_gram_dense_workspace_bytes(const fst_model* m, int32_t dtype, int64_t mrows);
+/* Workspace for fst_gram with a split precision (FST_GRAM_F16X2, FST_GRAM_BF16X3,
+ * FST_GRAM_BF16X2; FP32 factor values): beyond the A^T v partials, the design rows in 2 or 3
+ * planes of 16-bit terms, each R x (M rounded up to 64) x 2 bytes (11.1 GB for two terms,
+ * 16.6 GB for three at R = 13,824, M = 200,000).  Entry e of A (formed in FP32) is split as
+ * t0 = rnd(e), t1 = rnd(e - t0), t2 = rnd(e - t0 - t1) (FP16: e scaled by a power of two that
+ * keeps it below 2^15, and t1 stored times 2^11 so that it stays a normal number).
+ * G = sum of t_a^T t_b over all a, b for two terms (4 products: the exact Gram of the
+ * two-term representation, 22 significant bits for FP16, 16 for BF16) and over a + b <= 2
+ * for three BF16 terms (6 products, 24 bits); on 16-bit MFMA with FP32 sums folded into FP64
+ * every 512 rows.  fst_gram fails with FST_E_NOMEM when a split precision gets less
+ * workspace; fst_refit_core and fst_fit form the FP32 Gram instead (reported by
+ * fst_model_fit_info).  Returns 0 for a non-split precision or bad arguments. */
+size_t fst_gram_split_workspace_bytes(const fst_model* m, int32_t gram_prec, int64_t mrows);
 fst_status fst_gram(const fst_model* m, int32_t dtype, int64_t mrows, const void* U,
                     const void* vs, int32_t gram_prec, double* G, double* h, void* ws,
                     size_t ws_bytes, void* stream);
@@ -372,9 +394,11 @@ fst_status fst_model_core(const fst_model* m, double* core_out);
 fst_status fst_model_coefs(const fst_model* m, int32_t k, double* C_out);
 /* How the core of a model from fst_fit, fst_refit_core or fst_fit_batched was solved.
  * Precision ladder: a Gram whose Cholesky breaks down, or whose refinement makes the FP64
- * normal-equation residual grow, is formed again from FP32 rows, then from FP64 rows (G and
- * h); the FP64 step skips numerically dependent columns instead of failing.  Refinement
- * undoes a step that does not reduce ||A^T (v - A alpha)|| and stops there.
+ * normal-equation residual grow, or whose refinement stops (a step that does not reduce
+ * the residual, or the last of refine_steps) with ||A^T (v - A alpha)|| / ||A^T v|| above
+ * 1e-8, is formed again from FP32 rows, then from FP64 rows (G and h); the FP64 step skips
+ * numerically dependent columns instead of failing.  Refinement undoes a step that does not
+ * reduce ||A^T (v - A alpha)|| and stops there.
  * gram_prec_used: the Gram precision the core was solved with (-1 for other models);
  * dropped: core entries fixed at zero because their design columns are numerically
  * dependent on earlier ones (the fitted field is unaffected); refine_steps: refinement steps

@@ -26,6 +26,7 @@ FST_OK = 0
 FST_E_INVAL, FST_E_NOMEM, FST_E_DEVICE, FST_E_NOT_SPD, FST_E_UNSUPPORTED, FST_E_FORMAT = -1, -2, -3, -4, -5, -6
 FST_F64, FST_F32 = 0, 1
 FST_GRAM_F64, FST_GRAM_F32, FST_GRAM_BF16, FST_GRAM_F16 = 0, 1, 2, 3
+FST_GRAM_F16X2, FST_GRAM_BF16X3, FST_GRAM_BF16X2 = 4, 5, 6
 FST_STREAM_INTERP, FST_STREAM_LS = 1, 2
 FST_SOLVER_OMP, FST_SOLVER_LARS = 0, 1
 
@@ -111,6 +112,7 @@ _lib_fns = dict(
     fst_sparse_fit=(_i32, _vp, _i32, _i32, _i32, _vp),
     fst_sparse_fit_lars=(_i32, _vp, _i32, _i32, _i32, _vp),
     fst_gram_dense_workspace_bytes=(C.c_size_t, _vp, _i32, _i64),
+    fst_gram_split_workspace_bytes=(C.c_size_t, _vp, _i32, _i64),
     fst_design_rows=(_i32, _vp, _i32, _i64, _vp, _vp, _i64, _vp, _vp, _vp),
     fst_gram_rows=(_i32, _i32, _i64, _i64, _vp, _vp, _vp, _vp, _i32, _vp),
     fst_sparse_fit_choice=(_i32, _vp, _i32, _i32, _i32, _i32, _i32, _i32, _vp),
@@ -400,13 +402,14 @@ def fst_fit_workspace_bytes(p: fst_fit_params, n: int) -> int:
     return int(b)
 
 
-def fst_fit(p: fst_fit_params, x, y, z, v, stream=None) -> Model:
-    """Algorithm 1 + Algorithm 2 on device arrays x, y, z, v (torch, same dtype)."""
+def fst_fit(p: fst_fit_params, x, y, z, v, ws=None, stream=None) -> Model:
+    """Algorithm 1 + Algorithm 2 on device arrays x, y, z, v (torch, same dtype).  With ws
+    None the library allocates its workspace (with room for the dense Gram route when the
+    device has it free)."""
     n = x.numel()
-    ws = _workspace(fst_fit_workspace_bytes(p, n), x.device)
     h = C.c_void_p()
     _check(_fn["fst_fit"](C.byref(p), n, _dev_ptr(x), _dev_ptr(y), _dev_ptr(z), _dev_ptr(v),
-                          _dev_ptr(ws), ws.numel(), _stream(stream), C.byref(h)))
+                          _dev_ptr(ws), ws.numel() if ws is not None else 0, _stream(stream), C.byref(h)))
     return Model(h)
 
 
@@ -428,17 +431,18 @@ def fst_refit_workspace_bytes(m: Model, dtype: int, n_samples: int, refine_steps
 
 def fst_refit_core(m: Model, x, y, z, v, n_samples: int, seed: int, gram_prec=None,
                    refine_steps: int = 0, ws=None, stream=None) -> Model:
-    """Algorithm 2: re-estimates the core of m from n_samples uniformly sampled rows."""
+    """Algorithm 2: re-estimates the core of m from n_samples uniformly sampled rows.  With
+    ws None the library allocates its workspace itself (with room for the dense Gram route
+    when the device has it free)."""
     dt = _dtype_code(x)
     if gram_prec is None:
         gram_prec = FST_GRAM_F64 if dt == FST_F64 else FST_GRAM_F32
     n = x.numel()
-    if ws is None:
-        ws = _workspace(fst_refit_workspace_bytes(m, dt, n_samples, refine_steps), x.device)
     h = C.c_void_p()
     _check(_fn["fst_refit_core"](m.handle, dt, n, _dev_ptr(x), _dev_ptr(y), _dev_ptr(z), _dev_ptr(v),
                                  int(n_samples), int(seed), int(gram_prec), int(refine_steps),
-                                 _dev_ptr(ws), ws.numel(), _stream(stream), C.byref(h)))
+                                 _dev_ptr(ws), ws.numel() if ws is not None else 0, _stream(stream),
+                                 C.byref(h)))
     return Model(h)
 
 
@@ -646,6 +650,10 @@ def fst_gram_dense_workspace_bytes(m: Model, dtype: int, mrows: int) -> int:
     return int(_fn["fst_gram_dense_workspace_bytes"](m.handle, int(dtype), int(mrows)))
 
 
+def fst_gram_split_workspace_bytes(m: Model, gram_prec: int, mrows: int) -> int:
+    return int(_fn["fst_gram_split_workspace_bytes"](m.handle, int(gram_prec), int(mrows)))
+
+
 def fst_gram_workspace_bytes(m: Model, mrows: int) -> int:
     return int(_fn["fst_gram_workspace_bytes"](m.handle, int(mrows)))
 
@@ -654,7 +662,8 @@ def fst_gram(m: Model, U, vs=None, gram_prec=None, G=None, h=None, ws=None, stre
     """G = A^T A (lower triangle) and h = A^T vs, FP64 device tensors (want_G=False: h only).
     A workspace of fst_gram_dense_workspace_bytes bytes selects the dense route (design rows
     materialised in it, then a dense MFMA Gram; for BF16/FP16 Grams the rows are 16-bit and G
-    equals the other route's bit for bit)."""
+    equals the other route's bit for bit).  The split precisions (FST_GRAM_F16X2,
+    FST_GRAM_BF16X3) need fst_gram_split_workspace_bytes and get it when ws is None."""
     torch = _torch()
     dt = _dtype_code(U)
     if gram_prec is None:
@@ -666,7 +675,8 @@ def fst_gram(m: Model, U, vs=None, gram_prec=None, G=None, h=None, ws=None, stre
     if h is None and vs is not None:
         h = torch.empty(R, dtype=torch.float64, device=U.device)
     if ws is None:
-        ws = _workspace(fst_gram_workspace_bytes(m, mrows), U.device)
+        need = fst_gram_split_workspace_bytes(m, gram_prec, mrows) or fst_gram_workspace_bytes(m, mrows)
+        ws = _workspace(need, U.device)
     _check(_fn["fst_gram"](m.handle, dt, int(mrows), _dev_ptr(U), _dev_ptr(vs), int(gram_prec),
                            _dev_ptr(G) if want_G else None, _dev_ptr(h), _dev_ptr(ws), ws.numel(),
                            _stream(stream)))

@@ -40,8 +40,9 @@ static void check_dtype(int dtype) {
 }
 static void check_prec(int dtype, int gram_prec) {
   if (dtype == FST_F64 && gram_prec != FST_GRAM_F64) fail(FST_E_INVAL, "FP64 points need gram_prec FST_GRAM_F64");
-  if (dtype == FST_F32 && gram_prec != FST_GRAM_F32 && gram_prec != FST_GRAM_BF16 && gram_prec != FST_GRAM_F16)
-    fail(FST_E_INVAL, "FP32 points need gram_prec FST_GRAM_F32, FST_GRAM_BF16 or FST_GRAM_F16");
+  if (dtype == FST_F32 && gram_prec != FST_GRAM_F32 && gram_prec != FST_GRAM_BF16 && gram_prec != FST_GRAM_F16 &&
+      split_terms(gram_prec) == 0)
+    fail(FST_E_INVAL, "FP32 points need gram_prec FST_GRAM_F32, BF16, F16, F16X2, BF16X3 or BF16X2");
 }
 static size_t dsize(int dtype) { return dtype == FST_F64 ? sizeof(double) : sizeof(float); }
 
@@ -145,8 +146,9 @@ static double device_norm(const double* d, int64_t R, const std::vector<uint8_t>
 // earlier columns is resolved by FP64 normal equations only well above 2^-52; kept
 // columns closer to that span would give core entries with large, cancelling values.
 constexpr double kDropTol = 1.4901161193847656e-08;
-// A refinement that stops making progress above this relative residual means the factor is
-// too inaccurate for the problem, and the ladder climbs.
+// A refinement that stops making progress, or ends its steps, above this relative residual
+// ||A^T (v - A alpha)|| / ||A^T v|| means the factor is too inaccurate for the problem, and the
+// ladder climbs.
 constexpr double kStallTol = 1e-8;
 
 // Iterative refinement (Algorithm 2 step 5 solved through the factored normal equations,
@@ -176,7 +178,10 @@ static int refine_loop(const fst_model* m, int dtype, int64_t n, const void* x, 
       return (nr > 2.0 * prev || info.rel_residual > kStallTol) ? 1 : 0;
     }
     info.rel_residual = nr / hnorm;
-    if (s == steps || nr == 0.0) return 0;
+    // budget spent: a residual still above kStallTol means the factor's precision was not
+    // enough for this many steps, and the ladder climbs
+    if (s == steps) return info.rel_residual > kStallTol ? 1 : 0;
+    if (nr == 0.0) return 0;
     prev = nr;
     copy_d2d(prev_alpha, alpha, sizeof(double) * (size_t)R, stream);
     cholesky_solve(R, L, r, r, stream);
@@ -214,7 +219,7 @@ SolveInfo solve_core(const fst_model* m, int dtype, int64_t n, const void* x, co
                                 ": non-finite entries in the sampled Gram matrix");
       // precision ladder: 16-bit -> FP32 rows -> FP64 rows (G and h) -> FP64 rows with
       // dependent columns skipped
-      if (level == FST_GRAM_BF16 || level == FST_GRAM_F16) {
+      if (level == FST_GRAM_BF16 || level == FST_GRAM_F16 || split_terms(level) > 0) {
         level = FST_GRAM_F32;
       } else if (level == FST_GRAM_F32) {
         level = FST_GRAM_F64;
@@ -236,7 +241,8 @@ SolveInfo solve_core(const fst_model* m, int dtype, int64_t n, const void* x, co
     const int climb = refine_loop(m, dtype, n, x, y, z, v, idx, M, G, alpha, refine, hnorm, skip, scr, scr_bytes,
                                   stream, info);
     if (!climb || level == FST_GRAM_F64) break;
-    level = (level == FST_GRAM_BF16 || level == FST_GRAM_F16) ? FST_GRAM_F32 : FST_GRAM_F64;
+    level = (level == FST_GRAM_BF16 || level == FST_GRAM_F16 || split_terms(level) > 0) ? FST_GRAM_F32
+                                                                                             : FST_GRAM_F64;
     reform(level);
   }
   return info;
@@ -319,7 +325,14 @@ static fst_model* refit_impl(const fst_model* m, int dtype, int64_t n, const voi
   if (!x || !y || !z || !v) fail(FST_E_INVAL, "null point or value array");
   if (refine < 0 || refine > 100) fail(FST_E_INVAL, "refine_steps must be in [0, 100]");
   const RefitLayout L = refit_layout(R, m->sum_r(), M, dtype, refine, refit_scratch(m, M, refine));
-  Workspace ws(ws_user, ws_bytes, L.total);
+  // without a caller workspace the library allocates one, with room for the dense route of
+  // the Gram (rows materialised) when the device has that much free memory to spare
+  size_t want = L.total;
+  if (!ws_user) {
+    const size_t route = gram_route_bytes(m, dtype, gram_prec, M);
+    if (device_free_bytes() >= L.total + route + (size_t(2) << 30)) want = L.total + route;
+  }
+  Workspace ws(ws_user, ws_user ? ws_bytes : want, want);
   char* base = (char*)ws.p;
   int32_t* d_idx = (int32_t*)(base + L.idx);
   void* d_U = base + L.U;
@@ -340,8 +353,8 @@ static fst_model* refit_impl(const fst_model* m, int dtype, int64_t n, const voi
   // step 1 at the sampled rows (factor functions), then the normal equations of step 5
   const DeviceModel& dm = device_model(m, dtype);
   launch_factor_eval(m, dm, dtype, n, x, y, z, v, d_idx, M, d_U, d_vs, stream);
-  launch_gram(m, dtype, M, d_U, d_vs, gram_prec, d_G, d_h, d_scr, scr_bytes, stream);
-  const SolveInfo si = solve_core(m, dtype, n, x, y, z, v, d_idx, M, d_U, d_vs, gram_prec, refine, d_G, d_h,
+  const int used = launch_gram(m, dtype, M, d_U, d_vs, gram_prec, d_G, d_h, d_scr, scr_bytes, stream);
+  const SolveInfo si = solve_core(m, dtype, n, x, y, z, v, d_idx, M, d_U, d_vs, used, refine, d_G, d_h,
                                   d_alpha, d_scr, scr_bytes, stream);
   std::vector<double> alpha((size_t)R);
   copy_d2h(alpha.data(), d_alpha, sizeof(double) * (size_t)R, stream);
@@ -686,7 +699,10 @@ fst_status fst_fit(const fst_fit_params* p, int64_t n, const void* x, const void
   if (!x || !y || !z || !v || !out) fail(FST_E_INVAL, "null argument");
   const int64_t K = llround(p->interp_fraction * (double)n);
   const size_t need = fst_fit_workspace_bytes(p, n);
-  Workspace w(ws, ws_bytes, need);
+  // without a caller workspace, this one holds the gathered subset only and the refit
+  // allocates its own (with room for the dense Gram route when memory allows)
+  const size_t gather = align_up(sizeof(int32_t) * (size_t)K) + sizeof(double) * 4 * (size_t)K;
+  Workspace w(ws, ws_bytes, ws ? need : gather);
   // Algorithm 1 step 1: a random subset (stream 1) is gathered on the device and copied out
   std::vector<int64_t> sub((size_t)K);
   sample_indices(p->seed, FST_STREAM_INTERP, n, K, sub.data());
@@ -695,7 +711,7 @@ fst_status fst_fit(const fst_fit_params* p, int64_t n, const void* x, const void
   std::unique_ptr<fst_model> m0(compress_from_subset(p, xyzv, K));
   // Algorithm 2 on the device
   *out = refit_impl(m0.get(), p->dtype, n, x, y, z, v, p->n_samples, p->seed, p->gram_prec,
-                    p->refine_steps, w.p, w.bytes, stream);
+                    p->refine_steps, ws ? w.p : nullptr, ws ? w.bytes : 0, stream);
   return FST_OK;
   FST_CATCH
 }
@@ -857,6 +873,13 @@ size_t fst_gram_dense_workspace_bytes(const fst_model* m, int32_t dtype, int64_t
   FST_SIZE_CATCH
 }
 
+size_t fst_gram_split_workspace_bytes(const fst_model* m, int32_t gram_prec, int64_t mrows) {
+  FST_SIZE_TRY
+  if (!m || m->d != 3 || mrows < 1 || split_terms(gram_prec) == 0) return 0;
+  return gram_workspace_bytes(m, mrows) + split_rows_bytes(m, gram_prec, mrows);
+  FST_SIZE_CATCH
+}
+
 fst_status fst_gram(const fst_model* m, int32_t dtype, int64_t mrows, const void* U, const void* vs,
                     int32_t gram_prec, double* G, double* h, void* ws, size_t ws_bytes, void* stream) {
   FST_TRY
@@ -867,8 +890,11 @@ fst_status fst_gram(const fst_model* m, int32_t dtype, int64_t mrows, const void
   if (mrows < 1) fail(FST_E_INVAL, "need mrows >= 1");
   if (!U || (!G && !h)) fail(FST_E_INVAL, "null argument");
   if (h && !vs) fail(FST_E_INVAL, "h requested without vs");
-  if ((h || gram_prec == FST_GRAM_F16) && !ws) fail(FST_E_INVAL, "h and FP16 rows need a workspace");
-  launch_gram(m, dtype, mrows, U, vs, gram_prec, G, h, ws, ws ? ws_bytes : 0, stream);
+  if ((h || gram_prec == FST_GRAM_F16 || split_terms(gram_prec) > 0) && !ws)
+    fail(FST_E_INVAL, "h, FP16 rows and split rows need a workspace");
+  const int used = launch_gram(m, dtype, mrows, U, vs, gram_prec, G, h, ws, ws ? ws_bytes : 0, stream);
+  if (G && used != gram_prec)
+    fail(FST_E_NOMEM, "the split rows of this precision need fst_gram_split_workspace_bytes of workspace");
   return FST_OK;
   FST_CATCH
 }

@@ -1,0 +1,389 @@
+// Split 16-bit Gram of the precision form for gfx950: the normal equations of Algorithm 2
+// step 5 (eq. (6)), G = A^T A, formed on 16-bit MFMA from design rows split into NT 16-bit
+// terms, A = A_0 + A_1 + ... + A_{NT-1}, each term the rounding of what the earlier ones left:
+//
+//   NT = 1  A_0 = rnd(A)                               G ~ A_0^T A_0
+//   NT = 2  FP16, entries scaled by a power of two     G ~ A_0^T A_0 + A_0^T A_1 + A_1^T A_0
+//   NT = 3  BF16                                       G ~ sum over a + b <= 2 of A_a^T A_b
+//
+// Products of terms whose orders add up to NT or more are below the FP32 rounding of the
+// entries and are left out.  FP16 splits carry 22 significant bits and BF16 splits 24, so
+// G is as accurate as a Gram of FP32 rows, at 3 (FP16) or 6 (BF16) 16-bit products per entry
+// pair instead of one FP32 product.
+//
+//   k_design_rows_split  A^T in NT planes, 16-bit, chunk-major: plane[(c R + j) 64 + k] holds
+//                        row 64 c + k of design column j (64-row chunks of one column are
+//                        contiguous, so a Gram tile's chunk is 128 runs of 128 bytes)
+//   k_gram_split         lower-triangle 128 x 128 tiles, four waves of 64 x 64 (4 x 4 MFMA
+//                        16x16x32 blocks), KC rows of the tile's 256 design columns staged per
+//                        chunk through double-buffered LDS; the leading product and the
+//                        others summed in separate FP32 accumulators, folded into FP64 every
+//                        512 rows (16 MFMA additions to the leading sum, as in the FP32 Gram)
+//
+// Tiles are handed out in groups of 4 x 8 (four row blocks, eight column blocks), one group
+// per XCD per round of 256 workgroups, so the 32 workgroups that share an XCD's L2 at a time
+// read 12 blocks of design columns instead of up to 64.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <string>
+
+#include "fst_device.h"
+#include "fst_internal.h"
+
+namespace fst {
+
+constexpr int SR_THREADS = 256, SR_VW = 8;
+constexpr int64_t SR_SUPER = 4;
+
+// FP16 terms after the first are stored scaled by 2^11 (one term's worth of bits), so that a
+// term that is 2^-11 of the entry stays a normal FP16 number instead of a subnormal one; the
+// products that hold such terms are unscaled when they are folded into FP64.  BF16 has FP32's
+// exponent range and needs no such step.
+template <typename H> struct SplitStep;
+template <> struct SplitStep<_Float16> { static constexpr float kStep = 2048.0f; };
+template <> struct SplitStep<__bf16> { static constexpr float kStep = 1.0f; };
+
+struct SplitRowsArgs {
+  const float* U;       // [sum r][M] factor values of the sampled rows (feature-major)
+  void* plane[3];       // NT planes, chunk-major, R x Sp entries each
+  int64_t M, Sp, R;
+  int32_t r1, r2, r3;
+  float scale;          // power of two applied to every entry (FP16 range), 1 for BF16
+};
+
+// entry ((u1 u2) scale) u3 formed in FP32; term t is the rounding of e - (A_0 + .. + A_{t-1})
+// (each subtraction exact in FP32), scaled by kStep^t; 8 consecutive rows per thread, one
+// 16-byte store per term and design column; rows M .. Sp-1 are zero.
+template <typename H, int NT>
+__global__ __launch_bounds__(SR_THREADS) void k_design_rows_split(SplitRowsArgs a, int64_t sb0) {
+  typedef H HV __attribute__((ext_vector_type(8)));
+  typedef float F4 __attribute__((ext_vector_type(4)));
+  const int64_t P = (int64_t)a.r1 * a.r2, nb = (a.Sp + SR_THREADS * SR_VW - 1) / (SR_THREADS * SR_VW);
+  const int64_t sb = sb0 + (int64_t)blockIdx.x / (P * SR_SUPER), rem = (int64_t)blockIdx.x % (P * SR_SUPER);
+  const int64_t w = min(SR_SUPER, nb - sb * SR_SUPER);
+  if (w <= 0) return;
+  const int64_t pr = rem / w, cb = sb * SR_SUPER + rem % w;
+  if (pr >= P) return;
+  const int64_t q = (cb * SR_THREADS + threadIdx.x) * SR_VW;
+  if (q >= a.Sp) return;
+  const int j1 = (int)(pr / a.r2), j2 = (int)(pr - (int64_t)j1 * a.r2);
+  const float* U1 = a.U + (int64_t)j1 * a.M;
+  const float* U2 = a.U + (int64_t)(a.r1 + j2) * a.M;
+  const float* U3 = a.U + (int64_t)(a.r1 + a.r2) * a.M;
+  const bool vec = q + SR_VW <= a.M && a.M % 4 == 0;
+  float p12[SR_VW];
+  if (vec) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const F4 x = *reinterpret_cast<const F4*>(U1 + q + 4 * h), y = *reinterpret_cast<const F4*>(U2 + q + 4 * h);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) p12[4 * h + e] = x[e] * y[e] * a.scale;
+    }
+  } else {
+#pragma unroll
+    for (int e = 0; e < SR_VW; ++e) {
+      const int64_t c = min(q + e, a.M - 1);
+      p12[e] = q + e < a.M ? U1[c] * U2[c] * a.scale : 0.0f;
+    }
+  }
+  // chunk-major offset of (column pr r3, row q); q is a multiple of 8, so the 8 rows share a chunk
+  const int64_t base = ((q >> 6) * a.R + pr * a.r3) * 64 + (q & 63);
+  for (int j3 = 0; j3 < a.r3; ++j3) {
+    const float* u3 = U3 + (int64_t)j3 * a.M;
+    float e[SR_VW];
+    if (vec) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const F4 z = *reinterpret_cast<const F4*>(u3 + q + 4 * h);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) e[4 * h + i] = p12[4 * h + i] * z[i];
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < SR_VW; ++i) e[i] = p12[i] * u3[min(q + i, a.M - 1)];
+    }
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      HV hv;
+#pragma unroll
+      for (int i = 0; i < SR_VW; ++i) {
+        hv[i] = (H)e[i];
+        e[i] = (e[i] - (float)hv[i]) * SplitStep<H>::kStep;
+      }
+      *reinterpret_cast<HV*>(reinterpret_cast<H*>(a.plane[t]) + base + (int64_t)j3 * 64) = hv;
+    }
+  }
+}
+
+constexpr int SG_TILE = 128, SG_LK = 64;
+
+struct SplitGramArgs {
+  const void* plane[3];   // NT planes, chunk-major (SG_LK rows per chunk), R x Sp entries each
+  double* G;              // R x R, lower triangle written
+  int64_t R, Sp;
+  int32_t nt;             // tiles per side
+  int32_t fold;           // chunks between folds of the FP32 sums into FP64
+  double unscale;         // 1 / scale^2
+  int32_t accumulate;
+};
+
+// The products t_a^T t_b summed for each split: (a, b) and the FP32 accumulator they go to.
+// Accumulator 0 holds the leading product alone; the others hold products that are 2^-8 or
+// less of it (their own rounding does not matter) and are multiplied by `unscale` (undoing
+// the 2^11 steps of FP16 terms) when they are folded into FP64.  A product left out must be a
+// cross term of random sign: a left-out square t_a^T t_a is positive semidefinite and would
+// shift the Gram systematically (at 2^-24 of the diagonal, comparable to the smallest
+// eigenvalue of a Gram with condition number 1e7-1e8).
+struct SchemeF16x2 {      // FP16, two terms: the whole square of the two-term representation
+  typedef _Float16 H;
+  static constexpr int NT = 2, N = 4, NACC = 3, KC = 32;
+  static constexpr int a[4] = {0, 0, 1, 1}, b[4] = {0, 1, 0, 1}, c[4] = {0, 1, 1, 2};
+  static constexpr double unscale[3] = {1.0, 1.0 / 2048.0, 1.0 / 4194304.0};
+};
+struct SchemeBF16x2 {     // BF16, two terms: the whole square
+  typedef __bf16 H;
+  static constexpr int NT = 2, N = 4, NACC = 2, KC = 64;
+  static constexpr int a[4] = {0, 0, 1, 1}, b[4] = {0, 1, 0, 1}, c[4] = {0, 1, 1, 1};
+  static constexpr double unscale[2] = {1.0, 1.0};
+};
+struct SchemeBF16x3 {     // BF16, three terms: products of order <= 2 (order-3 cross terms left out)
+  typedef __bf16 H;
+  static constexpr int NT = 3, N = 6, NACC = 2, KC = 32;
+  static constexpr int a[6] = {0, 0, 1, 0, 1, 2}, b[6] = {0, 1, 0, 2, 1, 0}, c[6] = {0, 1, 1, 1, 1, 1};
+  static constexpr double unscale[2] = {1.0, 1.0};
+};
+
+template <class SC, int WR, int WC>
+__global__ __launch_bounds__(64 * WR * WC) void k_gram_split(SplitGramArgs a) {
+  typedef typename SC::H H;
+  constexpr int NT = SC::NT, KC = SC::KC;
+  typedef typename Mfma16<H>::V8 V8;
+  constexpr int THREADS = 64 * WR * WC;
+  constexpr int BX = SG_TILE / WR / 16, BY = SG_TILE / WC / 16;   // 16 x 16 blocks per wave
+  constexpr int ROWS = 2 * SG_TILE;                    // the tile's row block, then its column block
+  constexpr int KCP = KC + 8;                          // padded LDS row (16 bytes)
+  constexpr int PPR = KC / 8;                          // 16-byte pieces per LDS row
+  constexpr int PIECES = NT * ROWS * PPR / THREADS;    // pieces per thread per chunk
+  static_assert(PIECES * THREADS == NT * ROWS * PPR, "chunk must split evenly over the threads");
+  static_assert(SG_LK % KC == 0 && KC % 32 == 0, "chunk must be whole MFMA steps inside a layout chunk");
+  __shared__ __align__(16) H sA[2][NT][ROWS][KCP];
+
+  // tile of this workgroup: round b / 256, group (round, XCD b % 8), slot (b % 256) / 8 of 32
+  const int64_t bid = blockIdx.x;
+  int64_t rest = (bid >> 8) * 8 + (bid & 7);
+  const int slot = (int)((bid & 255) >> 3);
+  const int64_t nt = a.nt;
+  int64_t BI = 0;
+  for (;; ++BI) {
+    if (4 * BI >= nt) return;
+    const int64_t ngr = min(4 * BI + 3, nt - 1) / 8 + 1;   // groups in group row BI
+    if (rest < ngr) break;
+    rest -= ngr;
+  }
+  const int64_t bi = 4 * BI + slot / 8, bj = 8 * rest + slot % 8;
+  if (bi >= nt || bj > bi) return;
+  const int64_t r0 = bi * SG_TILE, c0 = bj * SG_TILE;
+
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wrow = (wave / WC) * BX * 16, wcol = (wave % WC) * BY * 16, li = lane & 15, g = lane >> 4;
+  const bool active = c0 + wcol <= r0 + wrow + BX * 16 - 1;
+
+  V8 pf[PIECES];
+  auto fetch = [&](int64_t k0) {
+    const int64_t lc = k0 / SG_LK, ko = k0 % SG_LK;
+#pragma unroll
+    for (int u = 0; u < PIECES; ++u) {
+      const int e = threadIdx.x + THREADS * u;
+      const int t = e / (ROWS * PPR), r = (e / PPR) % ROWS, pc = e % PPR;
+      const int64_t gr = r < SG_TILE ? r0 + r : c0 + (r - SG_TILE);
+      V8 val = V8{};
+      if (gr < a.R)
+        val = *reinterpret_cast<const V8*>(reinterpret_cast<const H*>(a.plane[t]) + (lc * a.R + gr) * SG_LK + ko +
+                                           pc * 8);
+      pf[u] = val;
+    }
+  };
+  auto stash = [&](int buf) {
+#pragma unroll
+    for (int u = 0; u < PIECES; ++u) {
+      const int e = threadIdx.x + THREADS * u;
+      const int t = e / (ROWS * PPR), r = (e / PPR) % ROWS, pc = e % PPR;
+      *reinterpret_cast<V8*>(&sA[buf][t][r][pc * 8]) = pf[u];
+    }
+  };
+
+  constexpr int NACC = SC::NACC;
+  floatx4 acc[NACC][BX][BY];
+  double dacc[BX][BY][4];
+#pragma unroll
+  for (int x = 0; x < BX; ++x)
+#pragma unroll
+    for (int y = 0; y < BY; ++y) {
+#pragma unroll
+      for (int c = 0; c < NACC; ++c) acc[c][x][y] = floatx4{0, 0, 0, 0};
+#pragma unroll
+      for (int v = 0; v < 4; ++v) dacc[x][y][v] = 0.0;
+    }
+  auto fold = [&]() {
+#pragma unroll
+    for (int x = 0; x < BX; ++x)
+#pragma unroll
+      for (int y = 0; y < BY; ++y) {
+#pragma unroll
+        for (int c = 0; c < NACC; ++c) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+            dacc[x][y][v] += c == 0 ? (double)acc[c][x][y][v] : (double)acc[c][x][y][v] * SC::unscale[c];
+          acc[c][x][y] = floatx4{0, 0, 0, 0};
+        }
+      }
+  };
+
+  const int64_t nch = a.Sp / KC;
+  fetch(0);
+  stash(0);
+  __syncthreads();
+  int since = 0;
+  for (int64_t ch = 0; ch < nch; ++ch) {
+    const int buf = (int)(ch & 1);
+    if (ch + 1 < nch) fetch((ch + 1) * KC);
+    if (active) {
+#pragma unroll
+      for (int ks = 0; ks < KC / 32; ++ks) {
+        const int p = ks * 32 + g * 8;
+        V8 av[NT][BX], bv[NT][BY];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+#pragma unroll
+          for (int x = 0; x < BX; ++x) av[t][x] = *reinterpret_cast<const V8*>(&sA[buf][t][wrow + x * 16 + li][p]);
+#pragma unroll
+          for (int y = 0; y < BY; ++y)
+            bv[t][y] = *reinterpret_cast<const V8*>(&sA[buf][t][SG_TILE + wcol + y * 16 + li][p]);
+        }
+#pragma unroll
+        for (int pp = 0; pp < SC::N; ++pp)
+#pragma unroll
+          for (int x = 0; x < BX; ++x)
+#pragma unroll
+            for (int y = 0; y < BY; ++y)
+              acc[SC::c[pp]][x][y] = Mfma16<H>::mfma(av[SC::a[pp]][x], bv[SC::b[pp]][y], acc[SC::c[pp]][x][y]);
+      }
+      if (++since == a.fold) {
+        fold();
+        since = 0;
+      }
+    }
+    if (ch + 1 < nch) stash(buf ^ 1);
+    __syncthreads();
+  }
+  if (!active) return;
+  fold();
+#pragma unroll
+  for (int x = 0; x < BX; ++x)
+#pragma unroll
+    for (int y = 0; y < BY; ++y)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t row = r0 + wrow + x * 16 + MfmaAcc<float>::row(g, v);
+        const int64_t col = c0 + wcol + y * 16 + li;
+        if (row < a.R && col <= row) {
+          const double val = dacc[x][y][v] * a.unscale;
+          a.G[row * a.R + col] = a.accumulate ? a.G[row * a.R + col] + val : val;
+        }
+      }
+}
+
+int split_terms(int gram_prec) {
+  switch (gram_prec) {
+    case FST_GRAM_F16X2: return 2;
+    case FST_GRAM_BF16X2: return 2;
+    case FST_GRAM_BF16X3: return 3;
+    default: return 0;
+  }
+}
+
+int64_t split_rows_padded(int64_t mrows) { return (mrows + SG_LK - 1) / SG_LK * SG_LK; }
+
+size_t split_rows_bytes(const fst_model* m, int gram_prec, int64_t mrows) {
+  const int nt = split_terms(gram_prec);
+  return (size_t)nt * align_up(2 * (size_t)m->R() * (size_t)split_rows_padded(mrows));
+}
+
+// FP16 terms: every entry scaled into [-2^15, 2^15] (the per-mode maxima give a power of two
+// that brings the entries into [-1, 1]); products of two terms stay below 2^30 and the sums of
+// one fold interval below 2^40, far inside FP32.
+constexpr float kSplitF16Headroom = 32768.0f;
+
+void gram_split(const fst_model* m, int gram_prec, int64_t mrows, const float* U, double* G, void* rows,
+                size_t rows_bytes, void* scratch, void* stream) {
+  const int NT = split_terms(gram_prec);
+  if (NT == 0) fail(FST_E_INVAL, "split Gram: not a split precision");
+  if (m->d != 3 || mrows < 1) fail(FST_E_INVAL, "split Gram: 3-way model and mrows >= 1 needed");
+  if (rows_bytes < split_rows_bytes(m, gram_prec, mrows)) fail(FST_E_NOMEM, "split Gram: row planes do not fit");
+  const int64_t R = m->R(), Sp = split_rows_padded(mrows);
+  if (R * Sp >= (int64_t(1) << 40)) fail(FST_E_UNSUPPORTED, "split Gram: A^T too large");
+  const float scale = gram_prec == FST_GRAM_F16X2 ? f16_row_scale(m, mrows, U, scratch, stream) * kSplitF16Headroom
+                                                  : 1.0f;
+  const size_t pb = align_up(2 * (size_t)R * (size_t)Sp);
+  SplitRowsArgs ra;
+  ra.U = U;
+  for (int t = 0; t < 3; ++t) ra.plane[t] = t < NT ? (char*)rows + t * pb : nullptr;
+  ra.M = mrows;
+  ra.Sp = Sp;
+  ra.R = R;
+  ra.r1 = m->rank[0];
+  ra.r2 = m->rank[1];
+  ra.r3 = m->rank[2];
+  ra.scale = scale;
+  const int64_t P = (int64_t)ra.r1 * ra.r2, nb = (Sp + SR_THREADS * SR_VW - 1) / (SR_THREADS * SR_VW);
+  const int64_t nsb = (nb + SR_SUPER - 1) / SR_SUPER, per = std::max<int64_t>(1, (int64_t(1) << 30) / (P * SR_SUPER));
+  for (int64_t sb0 = 0; sb0 < nsb; sb0 += per) {
+    const dim3 grid((unsigned)(std::min(per, nsb - sb0) * P * SR_SUPER));
+    if (gram_prec == FST_GRAM_F16X2)
+      hipLaunchKernelGGL((k_design_rows_split<_Float16, 2>), grid, dim3(SR_THREADS), 0, S(stream), ra, sb0);
+    else if (gram_prec == FST_GRAM_BF16X2)
+      hipLaunchKernelGGL((k_design_rows_split<__bf16, 2>), grid, dim3(SR_THREADS), 0, S(stream), ra, sb0);
+    else
+      hipLaunchKernelGGL((k_design_rows_split<__bf16, 3>), grid, dim3(SR_THREADS), 0, S(stream), ra, sb0);
+    check_launch("k_design_rows_split");
+  }
+  gram_split_rows(gram_prec, ra.plane, R, Sp, G, 1.0 / ((double)scale * (double)scale), false, stream);
+}
+
+void gram_split_rows(int gram_prec, void* const* plane, int64_t R, int64_t Sp, double* G, double unscale,
+                     bool accumulate, void* stream) {
+  const int NT = split_terms(gram_prec);
+  if (NT == 0) fail(FST_E_INVAL, "split Gram: not a split precision");
+  if (Sp < SG_LK || Sp % SG_LK != 0) fail(FST_E_INVAL, "split Gram: row count must be a multiple of 64");
+  SplitGramArgs ga;
+  for (int t = 0; t < 3; ++t) ga.plane[t] = t < NT ? plane[t] : nullptr;
+  ga.G = G;
+  ga.R = R;
+  ga.Sp = Sp;
+  const int64_t nt = (R + SG_TILE - 1) / SG_TILE;
+  if (nt > (int64_t(1) << 20)) fail(FST_E_UNSUPPORTED, "split Gram: R too large");
+  ga.nt = (int32_t)nt;
+  ga.unscale = unscale;
+  ga.accumulate = accumulate ? 1 : 0;
+  int64_t groups = 0;
+  for (int64_t BI = 0; 4 * BI < nt; ++BI) groups += std::min(4 * BI + 3, nt - 1) / 8 + 1;
+  const int64_t rounds = (groups + 7) / 8;
+  if (rounds * 256 >= (int64_t(1) << 31)) fail(FST_E_UNSUPPORTED, "split Gram: too many tiles");
+  const dim3 grid((unsigned)(rounds * 256));
+  // FP32 sums over 512 rows (16 MFMA accumulations into the leading sum) before each fold
+  if (gram_prec == FST_GRAM_F16X2) {
+    ga.fold = 512 / SchemeF16x2::KC;
+    hipLaunchKernelGGL((k_gram_split<SchemeF16x2, 2, 4>), grid, dim3(512), 0, S(stream), ga);
+  } else if (gram_prec == FST_GRAM_BF16X2) {
+    ga.fold = 512 / SchemeBF16x2::KC;
+    hipLaunchKernelGGL((k_gram_split<SchemeBF16x2, 2, 4>), grid, dim3(512), 0, S(stream), ga);
+  } else {
+    ga.fold = 512 / SchemeBF16x3::KC;
+    hipLaunchKernelGGL((k_gram_split<SchemeBF16x3, 2, 4>), grid, dim3(512), 0, S(stream), ga);
+  }
+  check_launch("k_gram_split");
+}
+
+}  // namespace fst

@@ -153,8 +153,14 @@ void launch_factor_eval(const fst_model* m, const DeviceModel& dm, int dtype, in
 void launch_factor_eval_d(const fst_model* m, const DeviceModel& dm, int dtype, const void* const* coords,
                           const void* v, const int32_t* idx, int64_t mrows, void* U, void* vs, void* stream);
 size_t gram_workspace_bytes(const fst_model* m, int64_t mrows);
-void launch_gram(const fst_model* m, int dtype, int64_t mrows, const void* U, const void* vs,
-                 int gram_prec, double* G, double* h, void* ws, size_t ws_bytes, void* stream);
+// returns the Gram precision used: gram_prec, or FST_GRAM_F32 for a split precision whose row
+// planes do not fit in the workspace
+int launch_gram(const fst_model* m, int dtype, int64_t mrows, const void* U, const void* vs,
+                int gram_prec, double* G, double* h, void* ws, size_t ws_bytes, void* stream);
+// workspace beyond gram_workspace_bytes that lets launch_gram take its dense route at gram_prec
+size_t gram_route_bytes(const fst_model* m, int dtype, int gram_prec, int64_t mrows);
+// free device memory of the current device (bytes)
+size_t device_free_bytes();
 size_t cholesky_workspace_bytes(int64_t R);
 // returns 0 on success, else the 1-based index of the failing pivot
 // FP64 Cholesky in place; returns the first breakdown pivot (1-based) or 0.  A pivot breaks
@@ -204,6 +210,18 @@ constexpr int64_t GD16_SP_MULTIPLE = 128;
 void design_rows16(const fst_model* m, int gram_prec, int64_t mrows, const float* U, int64_t Sp, void* At, float scale,
                    void* stream);
 void dense_gram16(int gram_prec, const void* At, int64_t R, int64_t Sp, double* G, double unscale, void* stream);
+// power of two that brings every 16-bit design-row entry u1 u2 u3 into [-1, 1] (ws: 16 bytes)
+float f16_row_scale(const fst_model* m, int64_t mrows, const float* U, void* ws, void* stream);
+// split 16-bit Gram (fst_gram16.hip): terms per entry of a split precision (0 for the others),
+// padded row count and bytes of the row planes, and G = A^T A from FP32 factor values U
+// (planes written to `rows`; scratch: 16 bytes for the FP16 scale) or from planes already written
+int split_terms(int gram_prec);
+int64_t split_rows_padded(int64_t mrows);
+size_t split_rows_bytes(const fst_model* m, int gram_prec, int64_t mrows);
+void gram_split(const fst_model* m, int gram_prec, int64_t mrows, const float* U, double* G, void* rows,
+                size_t rows_bytes, void* scratch, void* stream);
+void gram_split_rows(int gram_prec, void* const* plane, int64_t R, int64_t Sp, double* G, double unscale,
+                     bool accumulate, void* stream);
 // A^T (R x Sp) and b (Sp, may be NULL) of mrows rows given by their factor values and values
 void design_rows(const fst_model* m, int dtype, int64_t mrows, const void* U, const void* vs, int64_t Sp, void* At,
                  void* b, void* stream);

@@ -10,6 +10,9 @@ Output: tests/golden/large_f32_reference.npz with
   alpha                    FP64 core re-estimated from the M sampled rows
   h                        A^T v over the sampled rows
   gram_diag                diagonal of A^T A
+  gram_rows, gram_cols,    a seeded sample of lower-triangle entries of A^T A (row >= col):
+  gram_vals                  126,976 pairs uniform over the triangle, then the whole 64 x 64
+                             block in the far corner (rows R-64..R-1, columns 0..63)
   eig_min, eig_max         extreme eigenvalues of A^T A
 """
 import os
@@ -38,9 +41,17 @@ def main():
     alpha = lsq.solve_cholesky(G, h)
     ev = np.linalg.eigvalsh(G)
     print(f"solve + eigenvalues done {time.time() - t0:.1f} s, kappa {ev[-1] / ev[0]:.3e}", flush=True)
-    np.savez(os.path.join(HERE, "large_f32_reference.npz"), coefs0=m0.coefs[0], coefs1=m0.coefs[1],
-             coefs2=m0.coefs[2], core0=m0.core, alpha=alpha, h=h, gram_diag=np.diag(G).copy(),
-             eig_min=ev[0], eig_max=ev[-1])
+    R = G.shape[0]
+    rng = np.random.default_rng(20240611)
+    a, b = rng.integers(0, R, 126976), rng.integers(0, R, 126976)
+    rows, cols = np.maximum(a, b), np.minimum(a, b)
+    fr, fc = np.meshgrid(np.arange(R - 64, R), np.arange(64), indexing="ij")
+    rows = np.concatenate([rows, fr.reshape(-1)]).astype(np.int32)
+    cols = np.concatenate([cols, fc.reshape(-1)]).astype(np.int32)
+    np.savez_compressed(os.path.join(HERE, "large_f32_reference.npz"), coefs0=m0.coefs[0], coefs1=m0.coefs[1],
+                        coefs2=m0.coefs[2], core0=m0.core, alpha=alpha, h=h, gram_diag=np.diag(G).copy(),
+                        gram_rows=rows, gram_cols=cols, gram_vals=G[rows, cols],
+                        eig_min=ev[0], eig_max=ev[-1])
 
 
 if __name__ == "__main__":

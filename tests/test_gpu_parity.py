@@ -468,18 +468,35 @@ def test_full_size_against_oracle_reference(dev):
     x, y, z, v = [D(a, dev) for a in w.soa()]
     idx = D(sample_without_replacement(w.seed, STREAM_LS, w.n, w.n_samples).astype(np.int32), dev)
     U, vs = fst.fst_factor_eval(gm, x, y, z, v, idx)
-    G, h = fst.fst_gram(gm, U, vs)
+    # Gram entries against the oracle's: the diagonal and a seeded sample of 131,072
+    # lower-triangle entries (uniform over the triangle, plus the whole 64 x 64 block in the
+    # far corner), each route at the FP32 bar of 1e-5
+    rows, cols = D(ref["gram_rows"].astype(np.int64), dev), D(ref["gram_cols"].astype(np.int64), dev)
+
+    def check_gram(G):
+        assert rel_l2(np.diag(H(G)), ref["gram_diag"]) <= 1e-5
+        gs = H(G[rows, cols])
+        assert rel_l2(gs, ref["gram_vals"]) <= 1e-5
+        corner = slice(len(gs) - 4096, len(gs))
+        assert rel_l2(gs[corner], ref["gram_vals"][corner]) <= 1e-5
+
+    G, h = fst.fst_gram(gm, U, vs)                 # Khatri-Rao route (minimal workspace)
     assert rel_l2(H(h), ref["h"]) <= 1e-5
-    assert rel_l2(np.diag(H(G)), ref["gram_diag"]) <= 1e-5
+    check_gram(G)
+    del G
     # the dense route as the benchmark times it: A^T of all M rows, then the dense Gram
     At, _ = fst.fst_design_rows(gm, U, Sp=(w.n_samples + 63) // 64 * 64)
     Gd, _ = fst.fst_gram_rows(At)
     del At
-    assert rel_l2(np.diag(H(Gd)), ref["gram_diag"]) <= 1e-5
-    low = torch.tril(torch.ones_like(Gd, dtype=torch.bool))
-    assert (torch.linalg.norm(Gd[low] - G[low]) / torch.linalg.norm(G[low])).item() <= 1e-6
-    del G, Gd, low
+    check_gram(Gd)
+    del Gd
     torch.cuda.empty_cache()
+    # the split 16-bit Grams of the precision form
+    for code in (fst.FST_GRAM_F16X2, fst.FST_GRAM_BF16X3):
+        Gs, _ = fst.fst_gram(gm, U, gram_prec=code)
+        check_gram(Gs)
+        del Gs
+        torch.cuda.empty_cache()
     alpha = ref["alpha"]
     # FP32 rows: kappa(G) ~ 6e7 amplifies FP32 rounding in the core; three FP64-residual
     # refinement steps bring it to the oracle's core
@@ -492,6 +509,14 @@ def test_full_size_against_oracle_reference(dev):
     del ws
     torch.cuda.empty_cache()
     assert rel_l2(outd.core, alpha) <= 1e-6
+    # the precision form as configured: split 16-bit Grams and three FP64-residual steps
+    for code in (fst.FST_GRAM_F16X2, fst.FST_GRAM_BF16X3):
+        outs = fst.fst_refit_core(gm, x, y, z, v, w.n_samples, w.seed, gram_prec=code, refine_steps=3)
+        assert outs.solve_info()["gram_prec"] == code
+        assert rel_l2(outs.core, alpha) <= 1e-6
+        del outs
+        torch.cuda.empty_cache()
+    # a single FP16 term needs more steps at this conditioning
     out16 = fst.fst_refit_core(gm, x, y, z, v, w.n_samples, w.seed, gram_prec=fst.FST_GRAM_F16, refine_steps=9)
     assert rel_l2(out16.core, alpha) <= 1e-6
     # the FP16 Gram by the dense route (16-bit rows materialised), then the same refinement
