@@ -440,11 +440,18 @@ def test_refit_16bit_gram_with_refinement_matches_fp64(dev, prec):
         out = fst.fst_refit_core(gm, x, y, z, v, 4000, 9, gram_prec=prec, refine_steps=steps)
         errs.append(rel_l2(out.core, alpha_o))
         info = out.solve_info()
-        assert info["gram_prec"] == prec and info["dropped"] == 0 and info["refine_steps"] <= steps
+        assert info["dropped"] == 0 and info["refine_steps"] <= steps
         res.append(info["rel_residual"])
+        # a refinement whose steps run out above a relative residual of 1e-8 climbs the
+        # precision ladder to FP32 rows; otherwise the core keeps the 16-bit Gram
+        if steps == 0:
+            assert info["gram_prec"] == prec
+        else:
+            assert (info["gram_prec"] == prec and info["rel_residual"] <= 1e-8) or \
+                info["gram_prec"] == fst.FST_GRAM_F32, info
     assert errs[2] <= 1e-6, errs
     assert errs[2] < errs[0], errs
-    assert np.isnan(res[0]) and res[2] < res[1], res
+    assert np.isnan(res[0]) and res[2] <= 1e-8, res
     # many steps: refinement stops once a step no longer reduces the FP64 residual
     out = fst.fst_refit_core(gm, x, y, z, v, 4000, 9, gram_prec=prec, refine_steps=40)
     info = out.solve_info()
