@@ -275,6 +275,19 @@ size_t fst_cholesky_workspace_bytes(int64_t R);
 fst_status fst_cholesky(int64_t R, double* G, double shift, int64_t* info, void* ws,
                         size_t ws_bytes, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): fst_cholesky with its scratch (breakdown
+ * flags and the original diagonal, 256 + 8 R bytes) in a file-scope device array of the
+ * library instead of a caller workspace.  Same arguments, results and errors as
+ * fst_cholesky; no hipMalloc, hipFree or other allocating call.  Limit:
+ * R <= FST_CHOLESKY_NOALLOC_MAX_R (larger R: FST_E_INVAL, nothing launched); the array takes
+ * 256 + 8 * 65,536 bytes (512.25 KiB) on every GPU the library runs on, until the process
+ * ends.  All calls on one GPU share that GPU's array, which keeps the last call's contents
+ * (the flags are cleared by a kernel at the start of every call): calls that overlap on one
+ * GPU (several streams or host threads) race and must be serialised by the caller. */
+#define FST_CHOLESKY_NOALLOC_MAX_R 65536
+fst_status fst_cholesky_noalloc(int64_t R, double* G, double shift, int64_t* info, void* stream);
+
 /* Solves L L^T x = b with L from fst_cholesky (device FP64, including its stored
  * diagonal-block inverses); b and x may alias.
  * Asynchronous. */

@@ -100,6 +100,7 @@ _lib_fns = dict(
     fst_gram=(_i32, _vp, _i32, _i64, _vp, _vp, _i32, _vp, _vp, _vp, C.c_size_t, _vp),
     fst_cholesky_workspace_bytes=(C.c_size_t, _i64),
     fst_cholesky=(_i32, _i64, _vp, C.c_double, C.POINTER(_i64), _vp, C.c_size_t, _vp),
+    fst_cholesky_noalloc=(_i32, _i64, _vp, C.c_double, C.POINTER(_i64), _vp),
     fst_cholesky_solve=(_i32, _i64, _vp, _vp, _vp, _vp),
     fst_residual_workspace_bytes=(C.c_size_t, _vp, _i64),
     fst_residual=(_i32, _vp, _i32, _i64, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp, C.c_size_t, _vp),
@@ -720,6 +721,20 @@ def fst_cholesky(G, stream=None, shift: float = 0.0) -> int:
     info = C.c_int64(0)
     st = _fn["fst_cholesky"](R, _dev_ptr(G), float(shift), C.byref(info), _dev_ptr(ws), ws.numel(),
                              _stream(stream))
+    if st != FST_OK:
+        raise FstError(st, fst_last_error() + f" (info={info.value})")
+    return info.value
+
+
+FST_CHOLESKY_NOALLOC_MAX_R = 65536
+
+
+def fst_cholesky_noalloc(G, stream=None, shift: float = 0.0) -> int:
+    """fst_cholesky with the library's own device scratch (no workspace, no allocation);
+    R <= FST_CHOLESKY_NOALLOC_MAX_R.  Calls that overlap on one GPU race."""
+    R = G.shape[0]
+    info = C.c_int64(0)
+    st = _fn["fst_cholesky_noalloc"](R, _dev_ptr(G), float(shift), C.byref(info), _stream(stream))
     if st != FST_OK:
         raise FstError(st, fst_last_error() + f" (info={info.value})")
     return info.value

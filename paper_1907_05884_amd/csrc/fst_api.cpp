@@ -942,6 +942,19 @@ fst_status fst_cholesky(int64_t R, double* G, double shift, int64_t* info, void*
   FST_CATCH
 }
 
+fst_status fst_cholesky_noalloc(int64_t R, double* G, double shift, int64_t* info, void* stream) {
+  FST_TRY
+  set_last_error("");
+  if (info) *info = 0;
+  if (R < 1 || !G) fail(FST_E_INVAL, "bad arguments");
+  if (!(shift >= 0.0 && shift < 1.0)) fail(FST_E_INVAL, "shift must be in [0, 1)");
+  const int64_t piv = cholesky_static_scratch(R, G, stream, shift);
+  if (info) *info = piv;
+  if (piv != 0) fail(FST_E_NOT_SPD, "Cholesky breakdown at pivot " + std::to_string(piv));
+  return FST_OK;
+  FST_CATCH
+}
+
 fst_status fst_cholesky_solve(int64_t R, const double* L, const double* b, double* x, void* stream) {
   FST_TRY
   set_last_error("");

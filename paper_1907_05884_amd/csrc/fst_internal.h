@@ -172,6 +172,9 @@ size_t cholesky_workspace_bytes(int64_t R);
 int64_t cholesky(int64_t R, double* G, void* ws, size_t ws_bytes, void* stream, double drop_tol = 0.0,
                  int64_t* dropped = nullptr, double shift = 0.0);
 
+// the same factorisation (drop_tol 0) with its scratch in the library's file-scope device
+// array instead of a workspace (fst_linalg.hip); R <= FST_CHOLESKY_NOALLOC_MAX_R
+int64_t cholesky_static_scratch(int64_t R, double* G, void* stream, double shift);
 // 1 for every column a semidefinite factorisation skipped (ws: R doubles of scratch)
 std::vector<uint8_t> dropped_mask(const double* L, int64_t R, void* ws, void* stream);
 void cholesky_solve(int64_t R, const double* L, const double* b, double* x, void* stream);

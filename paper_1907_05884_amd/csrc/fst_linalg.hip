@@ -16,6 +16,8 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -382,14 +384,18 @@ __global__ void k_shift_diag(double* G, int64_t R, double f) {
   if (t < R) G[t * R + t] *= f;
 }
 
+__global__ void k_zero_info(int64_t* info) {
+  if (threadIdx.x < 2) info[threadIdx.x] = 0;
+}
+
 int64_t cholesky(int64_t R, double* G, void* ws, size_t ws_bytes, void* stream, double drop_tol,
                  int64_t* dropped, double shift) {
   if (ws_bytes < cholesky_workspace_bytes(R)) fail(FST_E_NOMEM, "cholesky: workspace too small");
   int64_t* d_info = (int64_t*)ws;   // [0] first breakdown (1-based), [1] dropped pivots
   double* d_diag = (double*)((char*)ws + 256);
   const double tol = (double)R * 2.220446049250313e-16;
-  const int64_t zero[2] = {0, 0};
-  copy_h2d(d_info, zero, sizeof(zero), stream);
+  hipLaunchKernelGGL(k_zero_info, dim3(1), dim3(64), 0, S(stream), d_info);
+  check_launch("k_zero_info");
   hipLaunchKernelGGL(k_copy_diag, dim3((unsigned)((R + 255) / 256)), dim3(256), 0, S(stream), G, R, d_diag);
   check_launch("k_copy_diag");
   if (shift > 0.0) {
@@ -443,6 +449,36 @@ int64_t cholesky(int64_t R, double* G, void* ws, size_t ws_bytes, void* stream, 
   copy_d2h(info, d_info, sizeof(info), stream);
   if (dropped) *dropped = info[1];
   return info[0];
+}
+
+// ------------------------------------------------------------------------------ no-allocation form
+// Scratch of the Cholesky (breakdown flags, then the original diagonal) for callers that
+// cannot allocate device memory: a file-scope device array, one copy per GPU, held until the
+// process ends.  Host code reaches a GPU's copy only through the address hipGetSymbolAddress
+// returns on that GPU (the array's name in host code is not a device address).  Every call on
+// a GPU uses the same copy, so calls that overlap on one GPU race.
+static __device__ __align__(256) unsigned char scratch[256 + 8 * FST_CHOLESKY_NOALLOC_MAX_R];
+
+static std::mutex g_scratch_mu;
+static std::map<int, void*> g_scratch_ptr;   // device ordinal -> address of its copy
+
+static void* scratch_address() {
+  const int dev = current_device();
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  auto it = g_scratch_ptr.find(dev);
+  if (it != g_scratch_ptr.end()) return it->second;
+  void* p = nullptr;
+  check_hip(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+  if (!p) fail(FST_E_DEVICE, "no device address for the Cholesky scratch array");
+  g_scratch_ptr[dev] = p;
+  return p;
+}
+
+int64_t cholesky_static_scratch(int64_t R, double* G, void* stream, double shift) {
+  if (R < 1 || R > FST_CHOLESKY_NOALLOC_MAX_R)
+    fail(FST_E_INVAL, "fst_cholesky_noalloc: R = " + std::to_string(R) + " is outside [1, " +
+                          std::to_string((long long)FST_CHOLESKY_NOALLOC_MAX_R) + "]");
+  return cholesky(R, G, scratch_address(), sizeof(scratch), stream, 0.0, nullptr, shift);
 }
 
 // ------------------------------------------------------------------------------ solves
