@@ -231,7 +231,7 @@ size_t fst_gram_dense_workspace_bytes(const fst_model* m, int32_t dtype, int64_t
  * planes of 16-bit terms, each R x (M rounded up to 64) x 2 bytes (11.1 GB for two terms,
  * 16.6 GB for three at R = 13,824, M = 200,000).  Entry e of A (formed in FP32) is split as
  * t0 = rnd(e), t1 = rnd(e - t0), t2 = rnd(e - t0 - t1) (FP16: e scaled by a power of two that
- * keeps it below 2^15, and t1 stored times 2^11 so that it stays a normal number).
+ * keeps it below 2^15).
  * G = sum of t_a^T t_b over all a, b for two terms (4 products: the exact Gram of the
  * two-term representation, 22 significant bits for FP16, 16 for BF16) and over a + b <= 2
  * for three BF16 terms (6 products, 24 bits); on 16-bit MFMA with FP32 sums folded into FP64

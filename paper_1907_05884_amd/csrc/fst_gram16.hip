@@ -14,11 +14,12 @@
 //   k_design_rows_split  A^T in NT planes, 16-bit, chunk-major: plane[(c R + j) 64 + k] holds
 //                        row 64 c + k of design column j (64-row chunks of one column are
 //                        contiguous, so a Gram tile's chunk is 128 runs of 128 bytes)
-//   k_gram_split         lower-triangle 128 x 128 tiles, four waves of 64 x 64 (4 x 4 MFMA
-//                        16x16x32 blocks), KC rows of the tile's 256 design columns staged per
-//                        chunk through double-buffered LDS; the leading product and the
-//                        others summed in separate FP32 accumulators, folded into FP64 every
-//                        512 rows (16 MFMA additions to the leading sum, as in the FP32 Gram)
+//   k_gram_split         lower-triangle 128 x 128 tiles, sixteen waves of 32 x 32 (2 x 2 MFMA
+//                        16x16x32 blocks); KC rows of the tile's 256 design columns copied
+//                        from HBM straight into double-buffered LDS; the leading product and
+//                        the others summed in separate FP32 accumulators, folded into FP64
+//                        every 512 rows (16 MFMA additions to the leading sum, as in the FP32
+//                        Gram)
 //
 // Tiles are handed out in groups of 4 x 8 (four row blocks, eight column blocks), one group
 // per XCD per round of 256 workgroups, so the 32 workgroups that share an XCD's L2 at a time
@@ -37,14 +38,6 @@ namespace fst {
 constexpr int SR_THREADS = 256, SR_VW = 8;
 constexpr int64_t SR_SUPER = 4;
 
-// FP16 terms after the first are stored scaled by 2^11 (one term's worth of bits), so that a
-// term that is 2^-11 of the entry stays a normal FP16 number instead of a subnormal one; the
-// products that hold such terms are unscaled when they are folded into FP64.  BF16 has FP32's
-// exponent range and needs no such step.
-template <typename H> struct SplitStep;
-template <> struct SplitStep<_Float16> { static constexpr float kStep = 2048.0f; };
-template <> struct SplitStep<__bf16> { static constexpr float kStep = 1.0f; };
-
 struct SplitRowsArgs {
   const float* U;       // [sum r][M] factor values of the sampled rows (feature-major)
   void* plane[3];       // NT planes, chunk-major, R x Sp entries each
@@ -54,8 +47,10 @@ struct SplitRowsArgs {
 };
 
 // entry ((u1 u2) scale) u3 formed in FP32; term t is the rounding of e - (A_0 + .. + A_{t-1})
-// (each subtraction exact in FP32), scaled by kStep^t; 8 consecutive rows per thread, one
-// 16-byte store per term and design column; rows M .. Sp-1 are zero.
+// (each subtraction exact in FP32); 8 consecutive rows per thread, one 16-byte store per term
+// and design column; rows M .. Sp-1 are zero.  With the FP16 scale (entries up to 2^15) the
+// second FP16 term is a normal number for every entry above 2^-3, i.e. within 18 binades of
+// the largest; below that it is subnormal (absolute precision 2^-24, kept by the MFMA).
 template <typename H, int NT>
 __global__ __launch_bounds__(SR_THREADS) void k_design_rows_split(SplitRowsArgs a, int64_t sb0) {
   typedef H HV __attribute__((ext_vector_type(8)));
@@ -110,7 +105,7 @@ __global__ __launch_bounds__(SR_THREADS) void k_design_rows_split(SplitRowsArgs 
 #pragma unroll
       for (int i = 0; i < SR_VW; ++i) {
         hv[i] = (H)e[i];
-        e[i] = (e[i] - (float)hv[i]) * SplitStep<H>::kStep;
+        e[i] -= (float)hv[i];
       }
       *reinterpret_cast<HV*>(reinterpret_cast<H*>(a.plane[t]) + base + (int64_t)j3 * 64) = hv;
     }
@@ -130,45 +125,55 @@ struct SplitGramArgs {
 };
 
 // The products t_a^T t_b summed for each split: (a, b) and the FP32 accumulator they go to.
-// Accumulator 0 holds the leading product alone; the others hold products that are 2^-8 or
-// less of it (their own rounding does not matter) and are multiplied by `unscale` (undoing
-// the 2^11 steps of FP16 terms) when they are folded into FP64.  A product left out must be a
-// cross term of random sign: a left-out square t_a^T t_a is positive semidefinite and would
-// shift the Gram systematically (at 2^-24 of the diagonal, comparable to the smallest
-// eigenvalue of a Gram with condition number 1e7-1e8).
+// Accumulator 0 holds the leading product alone; accumulator 1 the products that are 2^-8 or
+// less of it (their own rounding does not matter); both are folded into FP64.  A product left
+// out must be a cross term of random sign: a left-out square t_a^T t_a is positive
+// semidefinite and would shift the Gram systematically (at 2^-24 of the diagonal for FP16
+// terms, comparable to the smallest eigenvalue of a Gram with condition number 1e7-1e8).
 struct SchemeF16x2 {      // FP16, two terms: the whole square of the two-term representation
   typedef _Float16 H;
-  static constexpr int NT = 2, N = 4, NACC = 3, KC = 32;
-  static constexpr int a[4] = {0, 0, 1, 1}, b[4] = {0, 1, 0, 1}, c[4] = {0, 1, 1, 2};
-  static constexpr double unscale[3] = {1.0, 1.0 / 2048.0, 1.0 / 4194304.0};
+  static constexpr int NT = 2, N = 4, NACC = 2, KC = 64;
+  static constexpr int a[4] = {0, 0, 1, 1}, b[4] = {0, 1, 0, 1}, c[4] = {0, 1, 1, 1};
 };
 struct SchemeBF16x2 {     // BF16, two terms: the whole square
   typedef __bf16 H;
   static constexpr int NT = 2, N = 4, NACC = 2, KC = 64;
   static constexpr int a[4] = {0, 0, 1, 1}, b[4] = {0, 1, 0, 1}, c[4] = {0, 1, 1, 1};
-  static constexpr double unscale[2] = {1.0, 1.0};
 };
 struct SchemeBF16x3 {     // BF16, three terms: products of order <= 2 (order-3 cross terms left out)
   typedef __bf16 H;
   static constexpr int NT = 3, N = 6, NACC = 2, KC = 32;
   static constexpr int a[6] = {0, 0, 1, 0, 1, 2}, b[6] = {0, 1, 0, 2, 1, 0}, c[6] = {0, 1, 1, 1, 1, 1};
-  static constexpr double unscale[2] = {1.0, 1.0};
 };
 
-template <class SC, int WR, int WC>
-__global__ __launch_bounds__(64 * WR * WC) void k_gram_split(SplitGramArgs a) {
+// LDS layout of one staged chunk: [term][256 rows][KC entries] without padding; the 16-byte
+// piece p of row r sits at position p ^ swizzle(r), so that the 16 rows a lane group reads
+// at one piece position fall in distinct banks (for 32 and for 64 banks of 4 bytes).
+template <int PPR> __device__ __forceinline__ int split_swizzle(int r);
+template <> __device__ __forceinline__ int split_swizzle<8>(int r) { return (r ^ (r >> 3)) & 7; }
+template <> __device__ __forceinline__ int split_swizzle<4>(int r) { return ((r >> 1) ^ (r >> 2)) & 3; }
+
+constexpr int SG_THREADS = 1024;   // sixteen waves of 32 x 32 (2 x 2 MFMA blocks of 16 x 16)
+
+// One workgroup per lower-triangle tile.  Each chunk of KC rows of the tile's 256 design
+// columns (its row block, then its column block) is copied from HBM straight into LDS by
+// global_load_lds (1 KB per wave instruction, no register staging), one chunk ahead of the
+// MFMAs, into two buffers that are separate arrays (so the compiler can tell the buffer
+// being filled from the one being read and does not wait for the copy before reading).
+// Rows past R are copied from row R - 1 (real memory); their products land only in entries
+// that are never written.
+template <class SC>
+__global__ __launch_bounds__(SG_THREADS) void k_gram_split(SplitGramArgs a) {
   typedef typename SC::H H;
-  constexpr int NT = SC::NT, KC = SC::KC;
   typedef typename Mfma16<H>::V8 V8;
-  constexpr int THREADS = 64 * WR * WC;
-  constexpr int BX = SG_TILE / WR / 16, BY = SG_TILE / WC / 16;   // 16 x 16 blocks per wave
-  constexpr int ROWS = 2 * SG_TILE;                    // the tile's row block, then its column block
-  constexpr int KCP = KC + 8;                          // padded LDS row (16 bytes)
-  constexpr int PPR = KC / 8;                          // 16-byte pieces per LDS row
-  constexpr int PIECES = NT * ROWS * PPR / THREADS;    // pieces per thread per chunk
-  static_assert(PIECES * THREADS == NT * ROWS * PPR, "chunk must split evenly over the threads");
-  static_assert(SG_LK % KC == 0 && KC % 32 == 0, "chunk must be whole MFMA steps inside a layout chunk");
-  __shared__ __align__(16) H sA[2][NT][ROWS][KCP];
+  constexpr int NT = SC::NT, KC = SC::KC, NACC = SC::NACC;
+  constexpr int PPR = KC / 8;                  // 16-byte pieces per row
+  constexpr int RPI = 64 / PPR;                // rows per 1 KB copy instruction
+  constexpr int INS = NT * 256 / RPI / 16;     // copy instructions per wave per chunk
+  static_assert(INS * RPI * 16 == NT * 256, "a chunk must split evenly over the waves");
+  static_assert(SG_LK % KC == 0 && KC % 32 == 0, "a chunk must be whole MFMA steps inside a layout chunk");
+  __shared__ __align__(16) H bufA[NT][2 * SG_TILE][KC];
+  __shared__ __align__(16) H bufB[NT][2 * SG_TILE][KC];
 
   // tile of this workgroup: round b / 256, group (round, XCD b % 8), slot (b % 256) / 8 of 32
   const int64_t bid = blockIdx.x;
@@ -187,40 +192,38 @@ __global__ __launch_bounds__(64 * WR * WC) void k_gram_split(SplitGramArgs a) {
   const int64_t r0 = bi * SG_TILE, c0 = bj * SG_TILE;
 
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int wrow = (wave / WC) * BX * 16, wcol = (wave % WC) * BY * 16, li = lane & 15, g = lane >> 4;
-  const bool active = c0 + wcol <= r0 + wrow + BX * 16 - 1;
+  const int wrow = (wave >> 2) * 32, wcol = (wave & 3) * 32, li = lane & 15, g = lane >> 4;
+  const bool active = c0 + wcol <= r0 + wrow + 31;
 
-  V8 pf[PIECES];
-  auto fetch = [&](int64_t k0) {
-    const int64_t lc = k0 / SG_LK, ko = k0 % SG_LK;
+  // copy instruction i of this wave: term t, rows RPI q .. RPI q + RPI - 1 of the staged 256;
+  // lane l brings piece (l % PPR) ^ swizzle(row) of row RPI q + l / PPR
+  int64_t src[INS];    // entry offsets within a layout chunk
 #pragma unroll
-    for (int u = 0; u < PIECES; ++u) {
-      const int e = threadIdx.x + THREADS * u;
-      const int t = e / (ROWS * PPR), r = (e / PPR) % ROWS, pc = e % PPR;
-      const int64_t gr = r < SG_TILE ? r0 + r : c0 + (r - SG_TILE);
-      V8 val = V8{};
-      if (gr < a.R)
-        val = *reinterpret_cast<const V8*>(reinterpret_cast<const H*>(a.plane[t]) + (lc * a.R + gr) * SG_LK + ko +
-                                           pc * 8);
-      pf[u] = val;
+  for (int i = 0; i < INS; ++i) {
+    const int blk = wave * INS + i, q = blk % (256 / RPI);
+    const int rl = RPI * q + lane / PPR;
+    const int pc = (lane % PPR) ^ split_swizzle<PPR>(rl);
+    int64_t gr = rl < SG_TILE ? r0 + rl : c0 + (rl - SG_TILE);
+    gr = gr < a.R ? gr : a.R - 1;
+    src[i] = gr * SG_LK + pc * 8;
+  }
+  auto copy = [&](H (*buf)[2 * SG_TILE][KC], int64_t ch) {
+    const int64_t base = (ch * KC / SG_LK) * a.R * SG_LK + (ch * KC) % SG_LK;
+#pragma unroll
+    for (int i = 0; i < INS; ++i) {
+      const int blk = wave * INS + i, t = blk / (256 / RPI), q = blk % (256 / RPI);
+      const H* p = reinterpret_cast<const H*>(a.plane[t]) + base + src[i];
+      __builtin_amdgcn_global_load_lds((const void*)p, (__attribute__((address_space(3))) void*)&buf[t][RPI * q][0],
+                                       16, 0, 0);
     }
   };
-  auto stash = [&](int buf) {
-#pragma unroll
-    for (int u = 0; u < PIECES; ++u) {
-      const int e = threadIdx.x + THREADS * u;
-      const int t = e / (ROWS * PPR), r = (e / PPR) % ROWS, pc = e % PPR;
-      *reinterpret_cast<V8*>(&sA[buf][t][r][pc * 8]) = pf[u];
-    }
-  };
 
-  constexpr int NACC = SC::NACC;
-  floatx4 acc[NACC][BX][BY];
-  double dacc[BX][BY][4];
+  floatx4 acc[NACC][2][2];
+  double dacc[2][2][4];
 #pragma unroll
-  for (int x = 0; x < BX; ++x)
+  for (int x = 0; x < 2; ++x)
 #pragma unroll
-    for (int y = 0; y < BY; ++y) {
+    for (int y = 0; y < 2; ++y) {
 #pragma unroll
       for (int c = 0; c < NACC; ++c) acc[c][x][y] = floatx4{0, 0, 0, 0};
 #pragma unroll
@@ -228,62 +231,66 @@ __global__ __launch_bounds__(64 * WR * WC) void k_gram_split(SplitGramArgs a) {
     }
   auto fold = [&]() {
 #pragma unroll
-    for (int x = 0; x < BX; ++x)
+    for (int x = 0; x < 2; ++x)
 #pragma unroll
-      for (int y = 0; y < BY; ++y) {
+      for (int y = 0; y < 2; ++y)
 #pragma unroll
         for (int c = 0; c < NACC; ++c) {
 #pragma unroll
-          for (int v = 0; v < 4; ++v)
-            dacc[x][y][v] += c == 0 ? (double)acc[c][x][y][v] : (double)acc[c][x][y][v] * SC::unscale[c];
+          for (int v = 0; v < 4; ++v) dacc[x][y][v] += (double)acc[c][x][y][v];
           acc[c][x][y] = floatx4{0, 0, 0, 0};
         }
-      }
+  };
+  auto compute = [&](H (*buf)[2 * SG_TILE][KC]) {
+#pragma unroll
+    for (int ks = 0; ks < KC / 32; ++ks) {
+      const int pc = ks * 4 + g;
+      V8 av[NT][2], bv[NT][2];
+#pragma unroll
+      for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int x = 0; x < 2; ++x) {
+          const int ra = wrow + x * 16 + li, rb = SG_TILE + wcol + x * 16 + li;
+          av[t][x] = *reinterpret_cast<const V8*>(&buf[t][ra][(pc ^ split_swizzle<PPR>(ra)) * 8]);
+          bv[t][x] = *reinterpret_cast<const V8*>(&buf[t][rb][(pc ^ split_swizzle<PPR>(rb)) * 8]);
+        }
+#pragma unroll
+      for (int pp = 0; pp < SC::N; ++pp)
+#pragma unroll
+        for (int x = 0; x < 2; ++x)
+#pragma unroll
+          for (int y = 0; y < 2; ++y)
+            acc[SC::c[pp]][x][y] = Mfma16<H>::mfma(av[SC::a[pp]][x], bv[SC::b[pp]][y], acc[SC::c[pp]][x][y]);
+    }
   };
 
   const int64_t nch = a.Sp / KC;
-  fetch(0);
-  stash(0);
-  __syncthreads();
   int since = 0;
-  for (int64_t ch = 0; ch < nch; ++ch) {
-    const int buf = (int)(ch & 1);
-    if (ch + 1 < nch) fetch((ch + 1) * KC);
+  auto step = [&](H (*cur)[2 * SG_TILE][KC], H (*nxt)[2 * SG_TILE][KC], int64_t ch) {
+    if (ch + 1 < nch) copy(nxt, ch + 1);
     if (active) {
-#pragma unroll
-      for (int ks = 0; ks < KC / 32; ++ks) {
-        const int p = ks * 32 + g * 8;
-        V8 av[NT][BX], bv[NT][BY];
-#pragma unroll
-        for (int t = 0; t < NT; ++t) {
-#pragma unroll
-          for (int x = 0; x < BX; ++x) av[t][x] = *reinterpret_cast<const V8*>(&sA[buf][t][wrow + x * 16 + li][p]);
-#pragma unroll
-          for (int y = 0; y < BY; ++y)
-            bv[t][y] = *reinterpret_cast<const V8*>(&sA[buf][t][SG_TILE + wcol + y * 16 + li][p]);
-        }
-#pragma unroll
-        for (int pp = 0; pp < SC::N; ++pp)
-#pragma unroll
-          for (int x = 0; x < BX; ++x)
-#pragma unroll
-            for (int y = 0; y < BY; ++y)
-              acc[SC::c[pp]][x][y] = Mfma16<H>::mfma(av[SC::a[pp]][x], bv[SC::b[pp]][y], acc[SC::c[pp]][x][y]);
-      }
+      compute(cur);
       if (++since == a.fold) {
         fold();
         since = 0;
       }
     }
-    if (ch + 1 < nch) stash(buf ^ 1);
-    __syncthreads();
+    __builtin_amdgcn_s_waitcnt(0);   // this wave's copies of the next chunk have landed
+    __syncthreads();                 // everyone's, and nobody reads `cur` any more
+  };
+  copy(bufA, 0);
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  for (int64_t ch = 0; ch < nch; ch += 2) {
+    step(bufA, bufB, ch);
+    if (ch + 1 < nch) step(bufB, bufA, ch + 1);
   }
   if (!active) return;
   fold();
 #pragma unroll
-  for (int x = 0; x < BX; ++x)
+  for (int x = 0; x < 2; ++x)
 #pragma unroll
-    for (int y = 0; y < BY; ++y)
+    for (int y = 0; y < 2; ++y)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int64_t row = r0 + wrow + x * 16 + MfmaAcc<float>::row(g, v);
@@ -363,7 +370,7 @@ void gram_split_rows(int gram_prec, void* const* plane, int64_t R, int64_t Sp, d
   ga.R = R;
   ga.Sp = Sp;
   const int64_t nt = (R + SG_TILE - 1) / SG_TILE;
-  if (nt > (int64_t(1) << 20)) fail(FST_E_UNSUPPORTED, "split Gram: R too large");
+  if (nt > (int64_t(1) << 20) || R * SG_LK >= (int64_t(1) << 31)) fail(FST_E_UNSUPPORTED, "split Gram: R too large");
   ga.nt = (int32_t)nt;
   ga.unscale = unscale;
   ga.accumulate = accumulate ? 1 : 0;
@@ -375,13 +382,13 @@ void gram_split_rows(int gram_prec, void* const* plane, int64_t R, int64_t Sp, d
   // FP32 sums over 512 rows (16 MFMA accumulations into the leading sum) before each fold
   if (gram_prec == FST_GRAM_F16X2) {
     ga.fold = 512 / SchemeF16x2::KC;
-    hipLaunchKernelGGL((k_gram_split<SchemeF16x2, 2, 4>), grid, dim3(512), 0, S(stream), ga);
+    hipLaunchKernelGGL((k_gram_split<SchemeF16x2>), grid, dim3(SG_THREADS), 0, S(stream), ga);
   } else if (gram_prec == FST_GRAM_BF16X2) {
     ga.fold = 512 / SchemeBF16x2::KC;
-    hipLaunchKernelGGL((k_gram_split<SchemeBF16x2, 2, 4>), grid, dim3(512), 0, S(stream), ga);
+    hipLaunchKernelGGL((k_gram_split<SchemeBF16x2>), grid, dim3(SG_THREADS), 0, S(stream), ga);
   } else {
     ga.fold = 512 / SchemeBF16x3::KC;
-    hipLaunchKernelGGL((k_gram_split<SchemeBF16x3, 2, 4>), grid, dim3(512), 0, S(stream), ga);
+    hipLaunchKernelGGL((k_gram_split<SchemeBF16x3>), grid, dim3(SG_THREADS), 0, S(stream), ga);
   }
   check_launch("k_gram_split");
 }
