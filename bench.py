@@ -328,6 +328,93 @@ def run_batched(args):
     print(json.dumps(result), flush=True)
 
 
+def precision_leg(fst, torch, dev, args, m0, m_or, ref, x, y, z, v, idx, U, vs, G, h, alpha, rws, stream, w):
+    """The precision form on the large workload: the Gram of design rows split into 16-bit
+    terms (fst_gram: k_design_rows_split + k_gram_split), the FP64 Cholesky and solves and 3
+    FP64-residual refinement steps, timed with HIP events on the library's model; the core
+    after each step against the oracle's FP64 core (the same kernels on the oracle's model);
+    and fst_refit_core as a user calls it (library-allocated workspace), FP32 and split."""
+    R, M = m0.R, w.n_samples
+    steps = 3
+    a_ref = None if ref is None else ref["alpha"]
+    rel = lambda a: None if a_ref is None else float(np.linalg.norm(a - a_ref) / np.linalg.norm(a_ref))
+    out = {}
+    names = {"bf16x2": fst.FST_GRAM_BF16X2, "f16x2": fst.FST_GRAM_F16X2, "bf16x3": fst.FST_GRAM_BF16X3}
+    products = {"bf16x2": 4, "f16x2": 4, "bf16x3": 6}
+    for name, code in names.items():
+        ws = torch.empty(fst.fst_gram_split_workspace_bytes(m0, code, M), dtype=torch.uint8, device=dev)
+        res = {}
+        for mdl, tag, reps in ((m0, "lib", 2), (m_or, "or", 1)):
+            if mdl is None:
+                continue
+            for rep in range(reps):
+                e = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
+                e[0].record(stream)
+                fst.fst_factor_eval(mdl, x, y, z, v, idx, U=U, vs=vs)
+                e[1].record(stream)
+                fst.fst_gram(mdl, U, G=G, ws=ws, gram_prec=code)
+                e[2].record(stream)
+                fst.fst_gram(mdl, U, vs, h=h, ws=ws, want_G=False)
+                e[3].record(stream)
+                fst.fst_cholesky(G)
+                fst.fst_cholesky_solve(G, h, alpha)
+                e[4].record(stream)
+                snaps = [alpha.clone()]
+                for _ in range(steps):
+                    fst.fst_refine_step(mdl, x, y, z, v, idx, G, alpha, ws=rws)
+                    snaps.append(alpha.clone())
+                e[5].record(stream)
+                torch.cuda.synchronize()
+            if tag == "lib":
+                ms = [e[i].elapsed_time(e[i + 1]) for i in range(5)]
+                res["ms"] = {"factor_values": ms[0], "gram_call": ms[1], "atv": ms[2], "cholesky_solve": ms[3],
+                             f"refine_{steps}": ms[4]}
+                res["design_rows_per_s"] = M / ((ms[0] + ms[1] + ms[2]) / 1e3)
+                res["fitcore_rows_per_s"] = M / (sum(ms) / 1e3)
+            else:
+                res["core_rel_l2_vs_oracle_per_refine_step"] = [rel(a.cpu().numpy()) for a in snaps]
+        flops = float(M) * R * (R + 1)
+        t_gram = res["ms"]["gram_call"] / 1e3
+        res["roofline"] = {"kernel": f"k_gram_split<{name}> with its k_design_rows_split (one fst_gram call)",
+                           "bound": "mfma", "achieved": flops / t_gram / 1e12, "peak": 2500.0, "unit": "TFLOP/s",
+                           "frac": flops / t_gram / 2.5e15, "traffic": None, "flops_per_launch": flops,
+                           "mfma_products": products[name],
+                           "executed_16bit_tflops": products[name] * flops / t_gram / 1e12,
+                           "executed_frac": products[name] * flops / t_gram / 2.5e15}
+        out[name] = res
+        del ws
+        torch.cuda.empty_cache()
+        log(f"[bench] precision form {name}: gram call {res['ms']['gram_call']:.1f} ms, fit-core "
+            f"{res['fitcore_rows_per_s']:.3g} rows/s, core per step {res.get('core_rel_l2_vs_oracle_per_refine_step')}")
+    # fst_refit_core as a user calls it: library-allocated workspace (dense route when memory allows)
+    calls = {}
+    for name, code in (("f32", fst.FST_GRAM_F32), ("bf16x2", fst.FST_GRAM_BF16X2)):
+        torch.cuda.empty_cache()
+        t_call = []
+        for rep in range(2):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            gm = fst.fst_refit_core(m0, x, y, z, v, M, w.seed, gram_prec=code, refine_steps=steps)
+            torch.cuda.synchronize()
+            t_call.append(time.perf_counter() - t0)
+        info = gm.solve_info()
+        c = {"ms": t_call[-1] * 1e3, "fitcore_rows_per_s": M / t_call[-1], "solve_info": info,
+             "what": f"fst_refit_core(gram_prec={name}, refine_steps={steps}, ws=NULL) on the library's model, "
+                     f"wall time of the call (sample draw, factor values, Gram, A^T v, Cholesky, solves, refinement)"}
+        if m_or is not None:
+            go = fst.fst_refit_core(m_or, x, y, z, v, M, w.seed, gram_prec=code, refine_steps=steps)
+            c["core_rel_l2_vs_oracle"] = rel(go.core.reshape(-1))
+        calls[name] = c
+        log(f"[bench] fst_refit_core {name}: {c['ms']:.1f} ms, core vs oracle {c.get('core_rel_l2_vs_oracle')}")
+    head = dict(out["bf16x2"])
+    head["what"] = ("precision form: design rows split into two BF16 terms (4 BF16 MFMA products per entry pair, "
+                    "FP32 sums folded into FP64), FP64 Cholesky, 3 FP64-residual refinement steps")
+    head["vs_f32_refit_core_call"] = calls["f32"]["ms"] / calls["bf16x2"]["ms"]
+    head["other_splits"] = {k: out[k] for k in ("f16x2", "bf16x3")}
+    head["refit_core_call"] = calls
+    return head
+
+
 def run_wavelet(w, x, y, z, v, stream):
     """Algorithm 1 with the wavelet space W_{3,5} offered beside P_31 to every singular vector
     (host threads, untimed), then Algorithm 2 (FP32 Gram, FP64 Cholesky, the precision ladder)
@@ -468,6 +555,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-spacetime", action="store_true", help="skip the 4-way (space-time) measurement")
     ap.add_argument("--no-wavelet", action="store_true", help="skip the wavelet-factor measurement")
+    ap.add_argument("--no-precision-form", action="store_true",
+                    help="skip the split 16-bit Gram (precision form) and the fst_refit_core call timings")
     ap.add_argument("--cpu-sample-rows", type=int, default=4096)
     ap.add_argument("--n", type=int, default=2_000_000)
     ap.add_argument("--samples", type=int, default=200_000)
@@ -519,16 +608,16 @@ def main():
     t_host = time.perf_counter() - t
     log(f"[bench] host steps (IDW {w.grid}, ST-HOSVD, OMP): {t_host:.2f} s, nnz={m0.info()['nnz']}")
     ref = None
-    model_src = "library host steps"
+    m_or = None   # the oracle's model: the same kernels run on it for the comparisons with its FP64 core
+    model_src = "library host steps (fst_compress_host)"
     if os.path.exists(GOLDEN) and args.n == 2_000_000 and args.samples == 200_000:
-        # run the GPU path on the oracle's model, so that the core can be compared with the
-        # oracle's FP64 core of the same sampled problem
         ref = np.load(GOLDEN)
         rc = [ref[f"coefs{k}"] for k in range(3)]
         host_vs_oracle = max(float(np.abs(m0.coefs(k) - rc[k]).max()) for k in range(3))
-        m0 = fst.fst_model_from_parts(w.lo, w.hi, w.rank, w.degree, ref["core0"], rc)
-        model_src = f"oracle host steps (library host steps agree to {host_vs_oracle:.1e} max abs)"
-    refine = args.refine if args.refine is not None else (0 if args.precision == "f32" else 3)
+        m_or = fst.fst_model_from_parts(w.lo, w.hi, w.rank, w.degree, ref["core0"], rc)
+        model_src += (f"; its factor coefficients agree with the oracle's to {host_vs_oracle:.1e} max abs, and "
+                      f"every rel-L2 against the oracle's FP64 core runs the same kernels on the oracle's model")
+    refine = args.refine if args.refine is not None else 3
     gram_prec = {"f32": fst.FST_GRAM_F32, "bf16": fst.FST_GRAM_BF16, "f16": fst.FST_GRAM_F16,
                  "f16x2": fst.FST_GRAM_F16X2, "bf16x3": fst.FST_GRAM_BF16X3,
                  "bf16x2": fst.FST_GRAM_BF16X2}[args.precision]
@@ -550,7 +639,7 @@ def main():
     # FP32: the dense route, design rows materialised transposed (R x Sp FP32, 11 GB), then the
     # dense MFMA Gram; 16-bit Grams form the rows on the fly (Khatri-Rao kernel)
     dense = args.precision == "f32" and args.gram_route == "dense"
-    dense16 = args.precision != "f32" and args.gram_route == "dense"
+    dense16 = args.precision in ("bf16", "f16") and args.gram_route == "dense"
     Sp = (M + 63) // 64 * 64
     At = torch.empty((R, Sp), dtype=torch.float32, device=dev) if dense else None
     if gram_prec in (fst.FST_GRAM_F16X2, fst.FST_GRAM_BF16X3, fst.FST_GRAM_BF16X2):   # split rows: planes
@@ -566,32 +655,33 @@ def main():
     times = {"k1": [], "rows": [], "gram": [], "atv": [], "solve": [], "refine": [], "eval": []}
     gm_fit = None
 
-    def step(record):
+    def step(record, mdl=None, snap=False):
         nonlocal gm_fit
+        mdl = m0 if mdl is None else mdl
         ev[0].record(stream)
-        fst.fst_factor_eval(m0, x, y, z, v, idx, U=U, vs=vs)
+        fst.fst_factor_eval(mdl, x, y, z, v, idx, U=U, vs=vs)
         ev[1].record(stream)
         if dense:
-            fst.fst_design_rows(m0, U, Sp=Sp, At=At)             # k_design_rows
+            fst.fst_design_rows(mdl, U, Sp=Sp, At=At)            # k_design_rows
             ev[7].record(stream)
             fst.fst_gram_rows(At, G=G)                           # the Gram kernel alone
         else:
             ev[7].record(stream)
-            fst.fst_gram(m0, U, G=G, ws=gws, gram_prec=gram_prec)   # the Gram kernel alone
+            fst.fst_gram(mdl, U, G=G, ws=gws, gram_prec=gram_prec)   # the Gram kernel alone
         ev[2].record(stream)
-        fst.fst_gram(m0, U, vs, h=h, ws=gws, want_G=False)      # A^T v
+        fst.fst_gram(mdl, U, vs, h=h, ws=gws, want_G=False)     # A^T v
         ev[3].record(stream)
         fst.fst_cholesky(G)
         fst.fst_cholesky_solve(G, h, alpha)
         ev[4].record(stream)
-        snaps = [alpha.clone()] if record else []
+        snaps = [alpha.clone()] if snap else []
         for _ in range(refine):
-            fst.fst_refine_step(m0, x, y, z, v, idx, G, alpha, ws=rws)
-            if record:
+            fst.fst_refine_step(mdl, x, y, z, v, idx, G, alpha, ws=rws)
+            if snap:
                 snaps.append(alpha.clone())
         ev[6].record(stream)
         core = alpha.cpu().numpy()
-        gm_fit = fst.fst_model_from_parts(lo, hi, m0.rank, m0.degree, core, coefs)
+        gm_fit = fst.fst_model_from_parts(lo, hi, mdl.rank, mdl.degree, core, [mdl.coefs(k) for k in range(3)])
         t_ev = torch.cuda.Event(enable_timing=True)
         t_ev.record(stream)
         fst.fst_eval(gm_fit, x, y, z, out)
@@ -604,8 +694,9 @@ def main():
             times["atv"].append(ev[2].elapsed_time(ev[3]) / 1e3)
             times["solve"].append(ev[3].elapsed_time(ev[4]) / 1e3)
             times["refine"].append(ev[4].elapsed_time(ev[6]) / 1e3)
-            alpha_steps[:] = [a_.cpu().numpy() for a_ in snaps]
             times["eval"].append(t_ev.elapsed_time(ev[5]) / 1e3)
+        if snap:
+            alpha_steps[:] = [a_.cpu().numpy() for a_ in snaps]
 
     for i in range(args.warmup):
         step(False)
@@ -618,6 +709,17 @@ def main():
             f"solve {times['solve'][-1] * 1e3:.1f} ms, eval {times['eval'][-1] * 1e3:.2f} ms")
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    gm_lib = gm_fit
+    # accuracy: the same step on the oracle's model, against the oracle's FP64 core (untimed)
+    gm_or_fit = None
+    if m_or is not None:
+        step(False, m_or, snap=True)
+        gm_or_fit = gm_fit
+        gm_fit = gm_lib
+        fst.fst_eval(gm_lib, x, y, z, out)
+        torch.cuda.synchronize()
+    precision_form = precision_leg(fst, torch, dev, args, m0, m_or, ref, x, y, z, v, idx, U, vs, G, h, alpha, rws,
+                                   stream, w) if not args.no_precision_form else None
 
     # factor evaluation at all N points (no gather): the HBM-bound kernel of the path,
     # measured once outside the timed steps; bytes per point = 3 coordinates in + sum r out
@@ -681,6 +783,7 @@ def main():
     design_rows_per_s = M / t_rows
     points_per_s = N / avg["eval"]
     fitcore_rows_per_s = M / (t_rows + avg["solve"] + avg["refine"])
+    fitcore_unrefined = M / (t_rows + avg["solve"])
     gram_flops = float(M) * R * (R + 1)
     achieved = gram_flops / avg["gram"]
     rows_bytes = float(R) * Sp * 4 + float(SR) * M * 4     # A^T written, factor values read
@@ -715,6 +818,8 @@ def main():
                    "refine_steps": refine, "model": model_src},
         "reconstructed_points_per_s": points_per_s,
         "fitcore_rows_per_s": fitcore_rows_per_s,
+        "fitcore_rows_per_s_note": f"with the FP64 Cholesky, the solves and {refine} FP64-residual refinement steps",
+        "fitcore_rows_per_s_unrefined": fitcore_unrefined,
         "breakdown_ms": {k: vv * 1e3 for k, vv in avg.items()},
         "host_steps_s": t_host, "host_sample_draw_s": t_sample,
         "data_rel_l2": eps_data,
@@ -761,6 +866,9 @@ def main():
         result["core_rel_l2_vs_oracle_per_refine_step"] = [
             float(np.linalg.norm(a - a_ref) / np.linalg.norm(a_ref)) for a in alpha_steps]
         result["gram_kappa_oracle"] = float(ref["eig_max"] / ref["eig_min"])
+    if precision_form is not None:
+        result["refit_core_call"] = precision_form.pop("refit_core_call")
+        result["precision_form"] = precision_form
 
     if not args.no_cpu_baseline:
         # GPU results on the oracle's sample, computed outside the timed region
