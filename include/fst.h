@@ -407,11 +407,12 @@ fst_status fst_model_core(const fst_model* m, double* core_out);
 fst_status fst_model_coefs(const fst_model* m, int32_t k, double* C_out);
 /* How the core of a model from fst_fit, fst_refit_core or fst_fit_batched was solved.
  * Precision ladder: a Gram whose Cholesky breaks down, or whose refinement makes the FP64
- * normal-equation residual grow, or whose refinement stops (a step that does not reduce
- * the residual, or the last of refine_steps) with ||A^T (v - A alpha)|| / ||A^T v|| above
- * 1e-8, is formed again from FP32 rows, then from FP64 rows (G and h); the FP64 step skips
- * numerically dependent columns instead of failing.  Refinement undoes a step that does not
- * reduce ||A^T (v - A alpha)|| and stops there.
+ * normal-equation residual grow, or whose refinement ends with ||A^T (v - A alpha)|| / ||A^T v||
+ * above 1e-8, is formed again from FP32 rows (from BF16/FP16 rows), then from FP64 rows (G
+ * and h; split 16-bit rows go there directly); the FP64 step skips numerically dependent
+ * columns instead of failing.  Refinement undoes a step that does not reduce the residual
+ * and stops there; after refine_steps steps a residual above 1e-8 gets further steps while
+ * each one at least halves it, up to 4 x refine_steps in all.
  * gram_prec_used: the Gram precision the core was solved with (-1 for other models);
  * dropped: core entries fixed at zero because their design columns are numerically
  * dependent on earlier ones (the fitted field is unaffected); refine_steps: refinement steps

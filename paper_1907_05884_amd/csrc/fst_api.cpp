@@ -153,8 +153,11 @@ constexpr double kStallTol = 1e-8;
 
 // Iterative refinement (Algorithm 2 step 5 solved through the factored normal equations,
 // corrected with residuals r = A^T (v_S - A alpha) formed from FP64 rows).  Every step must
-// reduce ||r||; a step that does not is undone.  Returns 1 when the residual grew by more
-// than a factor 2 (the factor is too inaccurate for refinement to converge), else 0.
+// reduce ||r||; a step that does not is undone.  After `steps` steps a residual still above
+// kStallTol gets more steps while each step at least halves it (up to 4 steps in all per
+// step asked for).  Returns 1 when the factor is too inaccurate for refinement to reach
+// kStallTol (the residual grew by more than a factor 2, stalled above kStallTol, or the extra
+// steps ran out), else 0.
 static int refine_loop(const fst_model* m, int dtype, int64_t n, const void* x, const void* y, const void* z,
                        const void* v, const int32_t* idx, int64_t M, const double* L, double* alpha, int steps,
                        double hnorm, const std::vector<uint8_t>& skip, void* scr, size_t scr_bytes, void* stream,
@@ -166,7 +169,8 @@ static int refine_loop(const fst_model* m, int dtype, int64_t n, const void* x, 
   char* rest = (char*)scr + 2 * r8;
   const size_t rest_bytes = scr_bytes - 2 * r8;
   double prev = std::numeric_limits<double>::infinity();
-  for (int s = 0; s <= steps; ++s) {
+  const int max_steps = 4 * steps;
+  for (int s = 0; s <= max_steps; ++s) {
     residual(m, dtype, n, x, y, z, v, idx, M, alpha, r, rest, rest_bytes, stream);
     const double nr = device_norm(r, R, skip, stream);
     if (!(nr < prev)) {
@@ -178,10 +182,12 @@ static int refine_loop(const fst_model* m, int dtype, int64_t n, const void* x, 
       return (nr > 2.0 * prev || info.rel_residual > kStallTol) ? 1 : 0;
     }
     info.rel_residual = nr / hnorm;
-    // budget spent: a residual still above kStallTol means the factor's precision was not
-    // enough for this many steps, and the ladder climbs
-    if (s == steps) return info.rel_residual > kStallTol ? 1 : 0;
     if (nr == 0.0) return 0;
+    if (s >= steps) {
+      // the steps asked for are spent: done at kStallTol, else go on only while converging
+      if (info.rel_residual <= kStallTol) return 0;
+      if (s == max_steps || nr > 0.5 * prev) return 1;
+    }
     prev = nr;
     copy_d2d(prev_alpha, alpha, sizeof(double) * (size_t)R, stream);
     cholesky_solve(R, L, r, r, stream);
@@ -191,9 +197,16 @@ static int refine_loop(const fst_model* m, int dtype, int64_t n, const void* x, 
   return 0;
 }
 
+// Relative pivot below which a factorisation of a split 16-bit Gram (FP32-class entries,
+// about 1e-7 of the diagonal) treats a column as dependent on the earlier ones: 2^-16, well
+// above the rounding of the entries, so that a dropped column is within an angle of 4e-3 of
+// the span of the kept ones.
+constexpr double kSplitDropTol = 1.52587890625e-05;
+
 SolveInfo solve_core(const fst_model* m, int dtype, int64_t n, const void* x, const void* y, const void* z,
                      const void* v, const int32_t* idx, int64_t M, const void* U, const void* vs, int gram_prec,
-                     int refine, double* G, double* h, double* alpha, void* scr, size_t scr_bytes, void* stream) {
+                     int refine, double* G, double* h, double* alpha, void* scr, size_t scr_bytes, void* stream,
+                     double* Gsave) {
   if (scr_bytes < solve_scratch_bytes(m, M)) fail(FST_E_NOMEM, "solve: scratch too small");
   const int64_t R = m->R();
   const std::vector<uint8_t> none;
@@ -202,6 +215,16 @@ SolveInfo solve_core(const fst_model* m, int dtype, int64_t n, const void* x, co
   SolveInfo info;
   int level = gram_prec;
   bool semidefinite = false;   // FP64 rows, strict factorisation already broke down
+  // split 16-bit Gram kept in Gsave: when its strict factorisation or refinement fails, it is
+  // factored again with dependent columns (relative pivot below kSplitDropTol) skipped
+  // before the ladder goes to FP64 rows
+  const bool can_resplit = Gsave && split_terms(gram_prec) > 0;
+  bool split_semidefinite = false;
+  if (can_resplit) copy_d2d(Gsave, G, sizeof(double) * (size_t)R * (size_t)R, stream);
+  auto resplit = [&]() {
+    split_semidefinite = true;
+    copy_d2d(G, Gsave, sizeof(double) * (size_t)R * (size_t)R, stream);
+  };
   auto reform = [&](int prec) {
     if (prec == FST_GRAM_F32)
       launch_gram(m, dtype, M, U, vs, FST_GRAM_F32, G, nullptr, scr, scr_bytes, stream);
@@ -212,14 +235,21 @@ SolveInfo solve_core(const fst_model* m, int dtype, int64_t n, const void* x, co
   };
   for (;;) {
     int64_t dropped = 0;
-    const int64_t piv = cholesky(R, G, scr, scr_bytes, stream, semidefinite ? kDropTol : 0.0, &dropped);
+    const double tol = semidefinite ? kDropTol : (split_semidefinite ? kSplitDropTol : 0.0);
+    const int64_t piv = cholesky(R, G, scr, scr_bytes, stream, tol, &dropped);
     if (piv != 0) {
       if (semidefinite)
         fail(FST_E_NOT_SPD, "Cholesky breakdown at pivot " + std::to_string(piv) +
                                 ": non-finite entries in the sampled Gram matrix");
+      if (can_resplit && !split_semidefinite) {
+        resplit();
+        continue;
+      }
       // precision ladder: 16-bit -> FP32 rows -> FP64 rows (G and h) -> FP64 rows with
-      // dependent columns skipped
-      if (level == FST_GRAM_BF16 || level == FST_GRAM_F16 || split_terms(level) > 0) {
+      // dependent columns skipped; split 16-bit rows are FP32-class and go to FP64 rows
+      if (split_terms(level) > 0) {
+        level = FST_GRAM_F64;
+      } else if (level == FST_GRAM_BF16 || level == FST_GRAM_F16) {
         level = FST_GRAM_F32;
       } else if (level == FST_GRAM_F32) {
         level = FST_GRAM_F64;
@@ -241,8 +271,11 @@ SolveInfo solve_core(const fst_model* m, int dtype, int64_t n, const void* x, co
     const int climb = refine_loop(m, dtype, n, x, y, z, v, idx, M, G, alpha, refine, hnorm, skip, scr, scr_bytes,
                                   stream, info);
     if (!climb || level == FST_GRAM_F64) break;
-    level = (level == FST_GRAM_BF16 || level == FST_GRAM_F16 || split_terms(level) > 0) ? FST_GRAM_F32
-                                                                                             : FST_GRAM_F64;
+    if (can_resplit && !split_semidefinite) {
+      resplit();
+      continue;
+    }
+    level = (level == FST_GRAM_BF16 || level == FST_GRAM_F16) ? FST_GRAM_F32 : FST_GRAM_F64;
     reform(level);
   }
   return info;
@@ -354,8 +387,12 @@ static fst_model* refit_impl(const fst_model* m, int dtype, int64_t n, const voi
   const DeviceModel& dm = device_model(m, dtype);
   launch_factor_eval(m, dm, dtype, n, x, y, z, v, d_idx, M, d_U, d_vs, stream);
   const int used = launch_gram(m, dtype, M, d_U, d_vs, gram_prec, d_G, d_h, d_scr, scr_bytes, stream);
+  // a split Gram leaves its row planes' room free: a copy of G goes there (after the solve's scratch)
+  double* Gsave = nullptr;
+  const size_t gbytes = align_up(sizeof(double) * (size_t)R * (size_t)R), sneed = align_up(solve_scratch_bytes(m, M));
+  if (split_terms(used) > 0 && scr_bytes >= sneed + gbytes) Gsave = (double*)((char*)d_scr + sneed);
   const SolveInfo si = solve_core(m, dtype, n, x, y, z, v, d_idx, M, d_U, d_vs, used, refine, d_G, d_h,
-                                  d_alpha, d_scr, scr_bytes, stream);
+                                  d_alpha, d_scr, sneed < scr_bytes && Gsave ? sneed : scr_bytes, stream, Gsave);
   std::vector<double> alpha((size_t)R);
   copy_d2h(alpha.data(), d_alpha, sizeof(double) * (size_t)R, stream);
   for (double t : alpha)

@@ -2,6 +2,7 @@
 // on host threads (the nearest-neighbour search of the interpolation is shared, since every
 // variable uses the same subset); Algorithm 2 runs on the GPU with the Gram of every variable
 // in one persistent launch; reconstructions of all variables can be replayed as one graph.
+#include <algorithm>
 #include <atomic>
 #include <chrono>
 #include <cmath>
@@ -195,7 +196,24 @@ fst_status fst_fit_batched(const fst_fit_params* base, int32_t V, const int32_t*
   DeviceBuffer scr(scr_need);
   fst::stream_sync(stream);
   const double t2 = now_s();
-  fst::launch_gram_batched(mods, Up, Ms, Gp, base->gram_prec, scr.p, stream);
+  if (fst::split_terms(base->gram_prec) > 0) {
+    // split 16-bit rows: the row planes of as many variables as the workspace holds, then one
+    // launch over all their tiles (the workspace takes what the device can spare, at least
+    // the planes of the largest variable)
+    size_t all = 0, largest = 0;
+    for (const fst_model* m : mods) {
+      all += fst::split_rows_bytes(m, base->gram_prec, M);
+      largest = std::max(largest, fst::split_rows_bytes(m, base->gram_prec, M));
+    }
+    const size_t lo = fst::gram_split_batched_min_bytes(mods, base->gram_prec, M);
+    size_t want = lo - largest + all;   // every variable's planes at once
+    const size_t spare = fst::device_free_bytes();
+    if (spare < want + (size_t(8) << 30)) want = std::max(lo, spare > (size_t(8) << 30) ? spare - (size_t(8) << 30) : 0);
+    DeviceBuffer pws(want);
+    fst::gram_split_batched(mods, Up, M, Gp, base->gram_prec, pws.p, want, stream);
+  } else {
+    fst::launch_gram_batched(mods, Up, Ms, Gp, base->gram_prec, scr.p, stream);
+  }
   fst::stream_sync(stream);
   const double t3 = now_s();
   for (int v = 0; v < V; ++v)
@@ -204,24 +222,72 @@ fst_status fst_fit_batched(const fst_fit_params* base, int32_t V, const int32_t*
   fst::stream_sync(stream);
   const double t3b = now_s();
   // Cholesky, solve and refinement of every variable, with the precision ladder (a Gram that
-  // breaks down, or whose refinement diverges, is formed again from more precise rows)
+  // breaks down, or whose refinement stops above its tolerance, is formed again from more
+  // precise rows).  Variables run concurrently on a few streams of their own, largest R first,
+  // so that the latency-bound factorisations of the small systems overlap.
   std::vector<fst::SolveInfo> infos((size_t)V);
-  for (int v = 0; v < V; ++v) {
-    const fst_model* m = mods[(size_t)v];
-    const int64_t R = m->R();
-    double* alpha = (double*)ba[(size_t)v]->p;
-    try {
-      infos[(size_t)v] = fst::solve_core(m, dtype, n, x, y, z, values[v], (const int32_t*)bidx[(size_t)v]->p, M,
-                                         Up[(size_t)v], bvs[(size_t)v]->p, base->gram_prec, base->refine_steps,
-                                         Gp[(size_t)v], (double*)bh[(size_t)v]->p, alpha, scr.p, scr_need, stream);
-    } catch (const fst::Error& e) {
-      throw fst::Error(e.code, "variable " + std::to_string(v) + ": " + e.what());
+  {
+    std::vector<int> order((size_t)V);
+    for (int v = 0; v < V; ++v) order[(size_t)v] = v;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return mods[(size_t)a]->R() > mods[(size_t)b]->R(); });
+    const int nst = std::min(V, 4);
+    const int dev = fst::current_device();
+    std::atomic<int> next(0);
+    std::vector<std::string> errs((size_t)V);
+    std::vector<fst_status> codes((size_t)V, FST_OK);
+    std::vector<std::unique_ptr<DeviceBuffer>> scratch, gsave;
+    int64_t maxR = 0;
+    for (const fst_model* m : mods) maxR = std::max<int64_t>(maxR, m->R());
+    const bool split = fst::split_terms(base->gram_prec) > 0;
+    for (int t = 0; t < nst; ++t) {
+      scratch.emplace_back(new DeviceBuffer(scr_need));
+      if (split) gsave.emplace_back(new DeviceBuffer(sizeof(double) * (size_t)maxR * (size_t)maxR));
     }
-    std::vector<double> core((size_t)R);
-    fst::copy_d2h(core.data(), alpha, sizeof(double) * (size_t)R, stream);
-    for (double t : core)
-      if (!std::isfinite(t)) fst::fail(FST_E_NOT_SPD, "variable " + std::to_string(v) + ": non-finite core");
-    m0[(size_t)v]->core = core;
+    std::vector<std::thread> th;
+    for (int t = 0; t < nst; ++t)
+      th.emplace_back([&, t] {
+        void* st = nullptr;
+        try {
+          fst::set_device(dev);
+          st = fst::stream_create();
+        } catch (const fst::Error& e) {
+          for (int k = next++; k < V; k = next++) {
+            errs[(size_t)order[(size_t)k]] = e.what();
+            codes[(size_t)order[(size_t)k]] = e.code;
+          }
+          return;
+        }
+        for (int k = next++; k < V; k = next++) {
+          const int v = order[(size_t)k];
+          const fst_model* m = mods[(size_t)v];
+          const int64_t R = m->R();
+          double* alpha = (double*)ba[(size_t)v]->p;
+          try {
+            infos[(size_t)v] = fst::solve_core(m, dtype, n, x, y, z, values[v], (const int32_t*)bidx[(size_t)v]->p,
+                                               M, Up[(size_t)v], bvs[(size_t)v]->p, base->gram_prec,
+                                               base->refine_steps, Gp[(size_t)v], (double*)bh[(size_t)v]->p, alpha,
+                                               scratch[(size_t)t]->p, scr_need, st,
+                                               split ? (double*)gsave[(size_t)t]->p : nullptr);
+            std::vector<double> core((size_t)R);
+            fst::copy_d2h(core.data(), alpha, sizeof(double) * (size_t)R, st);
+            for (double c : core)
+              if (!std::isfinite(c)) fst::fail(FST_E_NOT_SPD, "non-finite core");
+            m0[(size_t)v]->core = core;
+          } catch (const fst::Error& e) {
+            errs[(size_t)v] = e.what();
+            codes[(size_t)v] = e.code;
+          } catch (const std::exception& e) {
+            errs[(size_t)v] = e.what();
+            codes[(size_t)v] = FST_E_INVAL;
+          }
+        }
+        fst::stream_sync(st);
+        fst::stream_destroy(st);
+      });
+    for (auto& t : th) t.join();
+    for (int v = 0; v < V; ++v)
+      if (codes[(size_t)v] != FST_OK)
+        throw fst::Error(codes[(size_t)v], "variable " + std::to_string(v) + ": " + errs[(size_t)v]);
   }
   const double t4 = now_s();
   for (int v = 0; v < V; ++v) {

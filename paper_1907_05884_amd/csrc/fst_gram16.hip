@@ -29,6 +29,7 @@
 #include <algorithm>
 #include <cmath>
 #include <string>
+#include <vector>
 
 #include "fst_device.h"
 #include "fst_internal.h"
@@ -115,7 +116,8 @@ __global__ __launch_bounds__(SR_THREADS) void k_design_rows_split(SplitRowsArgs 
 constexpr int SG_TILE = 128, SG_LK = 64;
 
 struct SplitGramArgs {
-  const void* plane[3];   // NT planes, chunk-major (SG_LK rows per chunk), R x Sp entries each
+  const void* plane0;     // NT planes, chunk-major (SG_LK rows per chunk), R x Sp entries each,
+  int64_t plane_stride;   // plane t at plane0 + t plane_stride entries
   double* G;              // R x R, lower triangle written
   int64_t R, Sp;
   int32_t nt;             // tiles per side
@@ -162,8 +164,20 @@ constexpr int SG_THREADS = 1024;   // sixteen waves of 32 x 32 (2 x 2 MFMA block
 // being filled from the one being read and does not wait for the copy before reading).
 // Rows past R are copied from row R - 1 (real memory); their products land only in entries
 // that are never written.
+// One 128 x 128 tile (rows r0.., columns c0..) of G = A^T A from the split planes.
+struct SplitTile {
+  const void* plane0;
+  int64_t plane_stride;
+  double* G;
+  int64_t R, Sp, r0, c0;
+  int32_t fold, accumulate;
+  double unscale;
+};
+
 template <class SC>
-__global__ __launch_bounds__(SG_THREADS) void k_gram_split(SplitGramArgs a) {
+__device__ __forceinline__ void split_tile(const SplitTile& a,
+                                           typename SC::H (*bufA)[2 * SG_TILE][SC::KC],
+                                           typename SC::H (*bufB)[2 * SG_TILE][SC::KC]) {
   typedef typename SC::H H;
   typedef typename Mfma16<H>::V8 V8;
   constexpr int NT = SC::NT, KC = SC::KC, NACC = SC::NACC;
@@ -172,25 +186,7 @@ __global__ __launch_bounds__(SG_THREADS) void k_gram_split(SplitGramArgs a) {
   constexpr int INS = NT * 256 / RPI / 16;     // copy instructions per wave per chunk
   static_assert(INS * RPI * 16 == NT * 256, "a chunk must split evenly over the waves");
   static_assert(SG_LK % KC == 0 && KC % 32 == 0, "a chunk must be whole MFMA steps inside a layout chunk");
-  __shared__ __align__(16) H bufA[NT][2 * SG_TILE][KC];
-  __shared__ __align__(16) H bufB[NT][2 * SG_TILE][KC];
-
-  // tile of this workgroup: round b / 256, group (round, XCD b % 8), slot (b % 256) / 8 of 32
-  const int64_t bid = blockIdx.x;
-  int64_t rest = (bid >> 8) * 8 + (bid & 7);
-  const int slot = (int)((bid & 255) >> 3);
-  const int64_t nt = a.nt;
-  int64_t BI = 0;
-  for (;; ++BI) {
-    if (4 * BI >= nt) return;
-    const int64_t ngr = min(4 * BI + 3, nt - 1) / 8 + 1;   // groups in group row BI
-    if (rest < ngr) break;
-    rest -= ngr;
-  }
-  const int64_t bi = 4 * BI + slot / 8, bj = 8 * rest + slot % 8;
-  if (bi >= nt || bj > bi) return;
-  const int64_t r0 = bi * SG_TILE, c0 = bj * SG_TILE;
-
+  const int64_t r0 = a.r0, c0 = a.c0;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wrow = (wave >> 2) * 32, wcol = (wave & 3) * 32, li = lane & 15, g = lane >> 4;
   const bool active = c0 + wcol <= r0 + wrow + 31;
@@ -212,7 +208,7 @@ __global__ __launch_bounds__(SG_THREADS) void k_gram_split(SplitGramArgs a) {
 #pragma unroll
     for (int i = 0; i < INS; ++i) {
       const int blk = wave * INS + i, t = blk / (256 / RPI), q = blk % (256 / RPI);
-      const H* p = reinterpret_cast<const H*>(a.plane[t]) + base + src[i];
+      const H* p = reinterpret_cast<const H*>(a.plane0) + t * a.plane_stride + base + src[i];
       __builtin_amdgcn_global_load_lds((const void*)p, (__attribute__((address_space(3))) void*)&buf[t][RPI * q][0],
                                        16, 0, 0);
     }
@@ -302,6 +298,78 @@ __global__ __launch_bounds__(SG_THREADS) void k_gram_split(SplitGramArgs a) {
       }
 }
 
+
+template <class SC>
+__global__ __launch_bounds__(SG_THREADS) void k_gram_split(SplitGramArgs a) {
+  __shared__ __align__(16) typename SC::H bufA[SC::NT][2 * SG_TILE][SC::KC];
+  __shared__ __align__(16) typename SC::H bufB[SC::NT][2 * SG_TILE][SC::KC];
+  // tile of this workgroup: round b / 256, group (round, XCD b % 8), slot (b % 256) / 8 of 32
+  const int64_t bid = blockIdx.x;
+  int64_t rest = (bid >> 8) * 8 + (bid & 7);
+  const int slot = (int)((bid & 255) >> 3);
+  const int64_t nt = a.nt;
+  int64_t BI = 0;
+  for (;; ++BI) {
+    if (4 * BI >= nt) return;
+    const int64_t ngr = min(4 * BI + 3, nt - 1) / 8 + 1;   // groups in group row BI
+    if (rest < ngr) break;
+    rest -= ngr;
+  }
+  const int64_t bi = 4 * BI + slot / 8, bj = 8 * rest + slot % 8;
+  if (bi >= nt || bj > bi) return;
+  SplitTile t;
+  t.plane0 = a.plane0;
+  t.plane_stride = a.plane_stride;
+  t.G = a.G;
+  t.R = a.R;
+  t.Sp = a.Sp;
+  t.r0 = bi * SG_TILE;
+  t.c0 = bj * SG_TILE;
+  t.fold = a.fold;
+  t.accumulate = a.accumulate;
+  t.unscale = a.unscale;
+  split_tile<SC>(t, bufA, bufB);
+}
+
+// Several variables in one launch: workgroup b takes global tile b of a list in which each
+// variable's lower-triangle tiles follow the previous variable's (tile0 ascending, larger
+// variables first so that the small ones fill the end of the launch).
+struct SplitVar {
+  const void* plane0;
+  int64_t plane_stride;
+  double* G;
+  int64_t R, Sp, tile0;
+  double unscale;
+};
+
+template <class SC>
+__global__ __launch_bounds__(SG_THREADS) void k_gram_split_batched(const SplitVar* __restrict__ vars, int nvars,
+                                                                   int32_t fold) {
+  __shared__ __align__(16) typename SC::H bufA[SC::NT][2 * SG_TILE][SC::KC];
+  __shared__ __align__(16) typename SC::H bufB[SC::NT][2 * SG_TILE][SC::KC];
+  const int64_t tt = blockIdx.x;
+  int lo = 0, hi = nvars - 1;   // last variable with tile0 <= tt
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) / 2;
+    if (vars[mid].tile0 <= tt) lo = mid; else hi = mid - 1;
+  }
+  const SplitVar& v = vars[lo];
+  int64_t bi, bj;
+  tri_tile(tt - v.tile0, bi, bj);
+  SplitTile t;
+  t.plane0 = v.plane0;
+  t.plane_stride = v.plane_stride;
+  t.G = v.G;
+  t.R = v.R;
+  t.Sp = v.Sp;
+  t.r0 = bi * SG_TILE;
+  t.c0 = bj * SG_TILE;
+  t.fold = fold;
+  t.accumulate = 0;
+  t.unscale = v.unscale;
+  split_tile<SC>(t, bufA, bufB);
+}
+
 int split_terms(int gram_prec) {
   switch (gram_prec) {
     case FST_GRAM_F16X2: return 2;
@@ -323,20 +391,15 @@ size_t split_rows_bytes(const fst_model* m, int gram_prec, int64_t mrows) {
 // one fold interval below 2^40, far inside FP32.
 constexpr float kSplitF16Headroom = 32768.0f;
 
-void gram_split(const fst_model* m, int gram_prec, int64_t mrows, const float* U, double* G, void* rows,
-                size_t rows_bytes, void* scratch, void* stream) {
+// the row planes of one variable (FP16: scaled by `scale`) into `rows`
+static void split_rows(const fst_model* m, int gram_prec, int64_t mrows, const float* U, void* rows, float scale,
+                       void* plane_out[3], void* stream) {
   const int NT = split_terms(gram_prec);
-  if (NT == 0) fail(FST_E_INVAL, "split Gram: not a split precision");
-  if (m->d != 3 || mrows < 1) fail(FST_E_INVAL, "split Gram: 3-way model and mrows >= 1 needed");
-  if (rows_bytes < split_rows_bytes(m, gram_prec, mrows)) fail(FST_E_NOMEM, "split Gram: row planes do not fit");
   const int64_t R = m->R(), Sp = split_rows_padded(mrows);
-  if (R * Sp >= (int64_t(1) << 40)) fail(FST_E_UNSUPPORTED, "split Gram: A^T too large");
-  const float scale = gram_prec == FST_GRAM_F16X2 ? f16_row_scale(m, mrows, U, scratch, stream) * kSplitF16Headroom
-                                                  : 1.0f;
   const size_t pb = align_up(2 * (size_t)R * (size_t)Sp);
   SplitRowsArgs ra;
   ra.U = U;
-  for (int t = 0; t < 3; ++t) ra.plane[t] = t < NT ? (char*)rows + t * pb : nullptr;
+  for (int t = 0; t < 3; ++t) ra.plane[t] = plane_out[t] = t < NT ? (char*)rows + t * pb : nullptr;
   ra.M = mrows;
   ra.Sp = Sp;
   ra.R = R;
@@ -356,7 +419,99 @@ void gram_split(const fst_model* m, int gram_prec, int64_t mrows, const float* U
       hipLaunchKernelGGL((k_design_rows_split<__bf16, 3>), grid, dim3(SR_THREADS), 0, S(stream), ra, sb0);
     check_launch("k_design_rows_split");
   }
-  gram_split_rows(gram_prec, ra.plane, R, Sp, G, 1.0 / ((double)scale * (double)scale), false, stream);
+}
+
+static void check_split(const fst_model* m, int gram_prec, int64_t mrows) {
+  if (split_terms(gram_prec) == 0) fail(FST_E_INVAL, "split Gram: not a split precision");
+  if (m->d != 3 || mrows < 1) fail(FST_E_INVAL, "split Gram: 3-way model and mrows >= 1 needed");
+  if (m->R() * split_rows_padded(mrows) >= (int64_t(1) << 40)) fail(FST_E_UNSUPPORTED, "split Gram: A^T too large");
+  if (m->R() * SG_LK >= (int64_t(1) << 31)) fail(FST_E_UNSUPPORTED, "split Gram: R too large");
+}
+
+static float split_scale(const fst_model* m, int gram_prec, int64_t mrows, const float* U, void* scratch,
+                         void* stream) {
+  return gram_prec == FST_GRAM_F16X2 ? f16_row_scale(m, mrows, U, scratch, stream) * kSplitF16Headroom : 1.0f;
+}
+
+void gram_split(const fst_model* m, int gram_prec, int64_t mrows, const float* U, double* G, void* rows,
+                size_t rows_bytes, void* scratch, void* stream) {
+  check_split(m, gram_prec, mrows);
+  if (rows_bytes < split_rows_bytes(m, gram_prec, mrows)) fail(FST_E_NOMEM, "split Gram: row planes do not fit");
+  const float scale = split_scale(m, gram_prec, mrows, U, scratch, stream);
+  void* plane[3];
+  split_rows(m, gram_prec, mrows, U, rows, scale, plane, stream);
+  gram_split_rows(gram_prec, plane, m->R(), split_rows_padded(mrows), G, 1.0 / ((double)scale * (double)scale),
+                  false, stream);
+}
+
+template <class SC>
+static void launch_split_batched(const SplitVar* vars, int nvars, int64_t tiles, void* stream) {
+  hipLaunchKernelGGL((k_gram_split_batched<SC>), dim3((unsigned)tiles), dim3(SG_THREADS), 0, S(stream), vars, nvars,
+                     (int32_t)(512 / SC::KC));
+  check_launch("k_gram_split_batched");
+}
+
+size_t gram_split_batched_min_bytes(const std::vector<const fst_model*>& models, int gram_prec, int64_t mrows) {
+  size_t mx = 0;
+  for (const fst_model* m : models) mx = std::max(mx, split_rows_bytes(m, gram_prec, mrows));
+  return 4096 + align_up(sizeof(SplitVar) * models.size()) + mx;
+}
+
+// Gram matrices of several variables: row planes of as many variables as fit in the
+// workspace (largest R first), then one launch over all their tiles; repeated until every
+// variable is done.  ws: 4096 bytes of scratch, the variable table, then the planes.
+void gram_split_batched(const std::vector<const fst_model*>& models, const std::vector<const void*>& U,
+                        int64_t mrows, const std::vector<double*>& G, int gram_prec, void* ws, size_t ws_bytes,
+                        void* stream) {
+  const size_t nv = models.size();
+  for (const fst_model* m : models) check_split(m, gram_prec, mrows);
+  if (ws_bytes < gram_split_batched_min_bytes(models, gram_prec, mrows))
+    fail(FST_E_NOMEM, "batched split Gram: workspace too small");
+  const size_t tab = align_up(sizeof(SplitVar) * nv);
+  SplitVar* d_vars = (SplitVar*)((char*)ws + 4096);
+  char* planes = (char*)ws + 4096 + tab;
+  const size_t budget = ws_bytes - 4096 - tab;
+  std::vector<size_t> order(nv);
+  for (size_t i = 0; i < nv; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return models[a]->R() > models[b]->R(); });
+  const int64_t Sp = split_rows_padded(mrows);
+  size_t i0 = 0;
+  while (i0 < nv) {
+    std::vector<SplitVar> vars;
+    size_t used = 0;
+    int64_t tiles = 0;
+    size_t i = i0;
+    for (; i < nv; ++i) {
+      const fst_model* m = models[order[i]];
+      const size_t need = split_rows_bytes(m, gram_prec, mrows);
+      if (used + need > budget) break;
+      const float scale = split_scale(m, gram_prec, mrows, (const float*)U[order[i]], ws, stream);
+      void* plane[3];
+      split_rows(m, gram_prec, mrows, (const float*)U[order[i]], planes + used, scale, plane, stream);
+      SplitVar v;
+      v.plane0 = plane[0];
+      v.plane_stride = (int64_t)(((char*)plane[1] - (char*)plane[0]) / 2);
+      v.G = G[order[i]];
+      v.R = m->R();
+      v.Sp = Sp;
+      v.tile0 = tiles;
+      v.unscale = 1.0 / ((double)scale * (double)scale);
+      const int64_t nt = (v.R + SG_TILE - 1) / SG_TILE;
+      tiles += nt * (nt + 1) / 2;
+      vars.push_back(v);
+      used += need;
+    }
+    if (tiles >= (int64_t(1) << 31)) fail(FST_E_UNSUPPORTED, "batched split Gram: too many tiles");
+    copy_h2d(d_vars, vars.data(), sizeof(SplitVar) * vars.size(), stream);
+    if (gram_prec == FST_GRAM_F16X2)
+      launch_split_batched<SchemeF16x2>(d_vars, (int)vars.size(), tiles, stream);
+    else if (gram_prec == FST_GRAM_BF16X2)
+      launch_split_batched<SchemeBF16x2>(d_vars, (int)vars.size(), tiles, stream);
+    else
+      launch_split_batched<SchemeBF16x3>(d_vars, (int)vars.size(), tiles, stream);
+    stream_sync(stream);   // the planes and the table are reused by the next group
+    i0 = i;
+  }
 }
 
 void gram_split_rows(int gram_prec, void* const* plane, int64_t R, int64_t Sp, double* G, double unscale,
@@ -365,7 +520,11 @@ void gram_split_rows(int gram_prec, void* const* plane, int64_t R, int64_t Sp, d
   if (NT == 0) fail(FST_E_INVAL, "split Gram: not a split precision");
   if (Sp < SG_LK || Sp % SG_LK != 0) fail(FST_E_INVAL, "split Gram: row count must be a multiple of 64");
   SplitGramArgs ga;
-  for (int t = 0; t < 3; ++t) ga.plane[t] = t < NT ? plane[t] : nullptr;
+  ga.plane0 = plane[0];
+  ga.plane_stride = (int64_t)(((char*)plane[1] - (char*)plane[0]) / 2);
+  for (int t = 1; t < NT; ++t)
+    if ((char*)plane[t] - (char*)plane[0] != (ptrdiff_t)(2 * t * ga.plane_stride))
+      fail(FST_E_INVAL, "split Gram: planes must be equally spaced");
   ga.G = G;
   ga.R = R;
   ga.Sp = Sp;

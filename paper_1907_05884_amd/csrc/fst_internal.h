@@ -225,6 +225,12 @@ void gram_split(const fst_model* m, int gram_prec, int64_t mrows, const float* U
                 size_t rows_bytes, void* scratch, void* stream);
 void gram_split_rows(int gram_prec, void* const* plane, int64_t R, int64_t Sp, double* G, double unscale,
                      bool accumulate, void* stream);
+// Gram matrices of several variables (same mrows) from their FP32 factor values, in as few
+// launches as the workspace allows (at least gram_split_batched_min_bytes)
+size_t gram_split_batched_min_bytes(const std::vector<const fst_model*>& models, int gram_prec, int64_t mrows);
+void gram_split_batched(const std::vector<const fst_model*>& models, const std::vector<const void*>& U,
+                        int64_t mrows, const std::vector<double*>& G, int gram_prec, void* ws, size_t ws_bytes,
+                        void* stream);
 // A^T (R x Sp) and b (Sp, may be NULL) of mrows rows given by their factor values and values
 void design_rows(const fst_model* m, int dtype, int64_t mrows, const void* U, const void* vs, int64_t Sp, void* At,
                  void* b, void* stream);
@@ -256,9 +262,12 @@ void eval_error(const fst_model* m, int dtype, int64_t n, const void* x, const v
 size_t solve_scratch_bytes(const fst_model* m, int64_t M);
 // Cholesky + solve + refinement of one sampled system with the precision ladder (fst_api.cpp).
 // On entry G holds the Gram at gram_prec and h = A^T v from the rows U, vs.
+// Gsave (may be NULL): room for a copy of G (R x R doubles), used with a split gram_prec to
+// factor the same Gram again with dependent columns skipped before climbing to FP64 rows.
 SolveInfo solve_core(const fst_model* m, int dtype, int64_t n, const void* x, const void* y, const void* z,
                      const void* v, const int32_t* idx, int64_t M, const void* U, const void* vs, int gram_prec,
-                     int refine, double* G, double* h, double* alpha, void* scr, size_t scr_bytes, void* stream);
+                     int refine, double* G, double* h, double* alpha, void* scr, size_t scr_bytes, void* stream,
+                     double* Gsave = nullptr);
 size_t gram_f64_rows_workspace_bytes(const fst_model* m, int64_t mrows);
 void gram_from_f64_rows(const fst_model* m, int dtype, int64_t n, const void* x, const void* y,
                         const void* z, const void* v, const int32_t* idx, int64_t mrows, double* G,
@@ -272,6 +281,9 @@ void gather_points(int dtype, int64_t K, const int64_t* idx_host, const void* x,
                    size_t ws_bytes, void* stream);
 void device_axpy(int64_t n, double a, const double* x, double* y, void* stream);
 void stream_sync(void* stream);
+void set_device(int dev);
+void* stream_create();            // a non-blocking stream of default priority on the current device
+void stream_destroy(void* stream);
 void* device_alloc(size_t bytes);
 void device_free(void* p);
 void copy_h2d(void* dst, const void* src, size_t bytes, void* stream);

@@ -194,3 +194,32 @@ def test_batched_errors(small64, dev):
     x, y, z = case.xyz
     with pytest.raises(fst.FstError):
         fst.EvalGraph(models, x[:0], y[:0], z[:0], [torch.empty(0, dtype=x.dtype, device=dev)] * len(models))
+
+
+def test_batched_split_gram_three_steps_matches_oracle(dev):
+    """The batched precision form: BF16 x 2 split Grams of all variables (row planes written,
+    then one launch over every variable's tiles), concurrent FP64 Cholesky solves and three
+    FP64-residual refinement steps.  Every variable's core matches the oracle's FP64 core of
+    its own sampled problem to 1e-6, the smallest and the largest R included, and equals the
+    per-variable entry point (the same tile arithmetic)."""
+    wl = datagen.batched(n_vars=6, n=120_000, grid=(24, 24, 24), rmin=4, rmax=12, pmin=11, pmax=19)
+    case = Case(wl, dev, np.float32)
+    code = fst.FST_GRAM_BF16X2
+    base = _params(wl, fst.FST_F32, wl.ranks[0], wl.degrees[0], code, 3)
+    models, t, used = fst.fst_fit_batched(base, wl.ranks, wl.degrees, *case.xyz, case.dv)
+    assert np.all(used == code), used
+    Rs = [int(np.prod(r)) for r in wl.ranks]
+    print("R per variable", Rs)
+    for v in range(len(models)):
+        om = _omodel(wl, models[v])
+        alpha, *_ = lsq.refit_core(om, case.pts.astype(np.float64), case.vals[v].astype(np.float64),
+                                   wl.n_samples, wl.seed + v)
+        err = rel_l2(models[v].core.reshape(-1), alpha.reshape(-1))
+        print(f"variable {v} R={Rs[v]}: core rel-L2 {err:.3e}, fit {models[v].solve_info()}")
+        assert err <= 1e-6, (v, Rs[v], err)
+    for v in (int(np.argmin(Rs)), int(np.argmax(Rs))):
+        pv = _params(wl, fst.FST_F32, wl.ranks[v], wl.degrees[v], code, 3)
+        host = fst.fst_compress_host(pv, *[np.ascontiguousarray(case.pts[:, k]) for k in range(3)], case.vals[v])
+        ref = fst.fst_refit_core(host, *case.xyz, case.dv[v], wl.n_samples, wl.seed + v, gram_prec=code,
+                                 refine_steps=3)
+        assert rel_l2(models[v].core, ref.core) <= 1e-12, v

@@ -440,9 +440,10 @@ def test_refit_16bit_gram_with_refinement_matches_fp64(dev, prec):
         out = fst.fst_refit_core(gm, x, y, z, v, 4000, 9, gram_prec=prec, refine_steps=steps)
         errs.append(rel_l2(out.core, alpha_o))
         info = out.solve_info()
-        assert info["dropped"] == 0 and info["refine_steps"] <= steps
+        assert info["dropped"] == 0 and info["refine_steps"] <= 4 * steps
         res.append(info["rel_residual"])
-        # a refinement whose steps run out above a relative residual of 1e-8 climbs the
+        # a refinement that ends above a relative residual of 1e-8 (after the steps asked for,
+        # and further steps while each halves the residual, at most 4 x steps) climbs the
         # precision ladder to FP32 rows; otherwise the core keeps the 16-bit Gram
         if steps == 0:
             assert info["gram_prec"] == prec
