@@ -181,6 +181,11 @@ void cholesky_solve(int64_t R, const double* L, const double* b, double* x, void
 void launch_eval(const fst_model* m, const DeviceModel& dm, int dtype, int64_t n,
                  const void* x, const void* y, const void* z, const int32_t* idx,
                  const void* v, void* out, void* stream);
+// FP32 reconstruction with the core contraction on MFMA (fst_eval_mfma.hip): 3-way Legendre
+// models whose core fits the kernel's LDS layout; out = f, or v[idx] - f with residual
+bool eval_mfma_applies(const fst_model* m);
+void launch_eval_mfma(const fst_model* m, const DeviceModel& dm, int64_t n, const float* x, const float* y,
+                      const float* z, const int32_t* idx, const float* v, float* out, bool residual, void* stream);
 size_t residual_workspace_bytes(const fst_model* m, int64_t mrows);
 void residual(const fst_model* m, int dtype, int64_t n, const void* x, const void* y,
               const void* z, const void* v, const int32_t* idx, int64_t mrows,

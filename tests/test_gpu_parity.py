@@ -245,6 +245,8 @@ def test_cholesky_reports_non_spd_pivot(dev):
     (np.float32, (24, 24, 24), (31, 31, 31), 100003, 1e-5),
     (np.float32, (32, 32, 32), (31, 31, 31), 5000, 1e-5),
     (np.float32, (4, 20, 9), (15, 31, 22), 777, 1e-5),
+    (np.float32, (7, 5, 11), (12, 9, 20), 4999, 1e-5),     # r2 < 16, r3 not a multiple of 4
+    (np.float32, (30, 3, 2), (31, 4, 2), 2500, 1e-5),      # r1 r2 = 90: a partial 16-column block
     (np.float32, (1, 1, 1), (0, 0, 0), 1, 1e-6),
 ])
 def test_eval_parity(dev, dtype, rank, degree, n, tol):
