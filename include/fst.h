@@ -147,6 +147,26 @@ fst_status fst_refit_core_mixed(const fst_model* m, int32_t dtype, int64_t n, co
                                 uint64_t seed, void* ws, size_t ws_bytes, void* stream,
                                 fst_model** out);
 
+/* The S sampled rows of the mixed problem of Algorithm 2 (steps 2-4: sign flips D, the
+ * normalised Walsh-Hadamard transform over N = max(4096, 2^ceil(log2 n)) rows, S rows drawn
+ * uniformly without replacement with stream FST_STREAM_LS of `seed`) for diagnostics such as
+ * leverage scores (Sec. 5, Sec. 6 Fig. 4): At (device, dtype, R x Sp with Sp = S rounded up to
+ * 64; row j holds design column j of the sampled mixed rows, zero past S) and b (device,
+ * dtype, Sp; may be NULL): the mixed values.  S = N keeps every mixed row.  Same inputs and
+ * workspace as fst_refit_core_mixed (fst_refit_core_mixed_workspace_bytes).  Asynchronous. */
+fst_status fst_mixed_rows(const fst_model* m, int32_t dtype, int64_t n, const void* x,
+                          const void* y, const void* z, const void* v, int64_t n_samples,
+                          uint64_t seed, void* At, void* b, void* ws, size_t ws_bytes,
+                          void* stream);
+
+/* Leverage scores of rows (Sec. 5: the squared row norms of the left singular vectors of a
+ * full-column-rank design, equal to l_q = a_q^T (A^T A)^-1 a_q): out[q] = ||y||^2 with L y = a_q
+ * for the rows q < mrows of At (device FP64, R x Sp, row j = design column j), L from
+ * fst_cholesky of A^T A (device FP64 R x R; columns it skipped count zero).  1 <= R <= 8192,
+ * mrows <= Sp.  out: device FP64 mrows.  Asynchronous. */
+fst_status fst_leverage(int64_t R, int64_t Sp, int64_t mrows, const double* At,
+                        const double* L, double* out, void* stream);
+
 /* Device workspace (bytes) of fst_refit_core for a model, point dtype, M and refinement. */
 size_t fst_refit_workspace_bytes(const fst_model* m, int32_t dtype, int64_t n_samples,
                                  int32_t refine_steps);

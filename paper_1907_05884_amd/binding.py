@@ -101,6 +101,8 @@ _lib_fns = dict(
     fst_cholesky_workspace_bytes=(C.c_size_t, _i64),
     fst_cholesky=(_i32, _i64, _vp, C.c_double, C.POINTER(_i64), _vp, C.c_size_t, _vp),
     fst_cholesky_noalloc=(_i32, _i64, _vp, C.c_double, C.POINTER(_i64), _vp),
+    fst_mixed_rows=(_i32, _vp, _i32, _i64, _vp, _vp, _vp, _vp, _i64, C.c_uint64, _vp, _vp, _vp, C.c_size_t, _vp),
+    fst_leverage=(_i32, _i64, _i64, _i64, _vp, _vp, _vp, _vp),
     fst_cholesky_solve=(_i32, _i64, _vp, _vp, _vp, _vp),
     fst_residual_workspace_bytes=(C.c_size_t, _vp, _i64),
     fst_residual=(_i32, _vp, _i32, _i64, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp, C.c_size_t, _vp),
@@ -459,6 +461,33 @@ def fst_refit_core_mixed(m: Model, x, y, z, v, n_samples: int, seed: int, ws=Non
                                        int(n_samples), int(seed), _dev_ptr(ws), ws.numel(), _stream(stream),
                                        C.byref(h)))
     return Model(h)
+
+
+def fst_mixed_rows(m: Model, x, y, z, v, n_samples: int, seed: int, ws=None, stream=None):
+    """The sampled mixed rows of Algorithm 2 (sign flips, Walsh-Hadamard transform, uniform
+    sample): (At (R x Sp), b (Sp)) device tensors of the points' dtype, zero past n_samples."""
+    torch = _torch()
+    dt = _dtype_code(x)
+    n = x.numel()
+    Sp = (int(n_samples) + 63) // 64 * 64
+    At = torch.empty((m.R, Sp), dtype=x.dtype, device=x.device)
+    b = torch.empty(Sp, dtype=x.dtype, device=x.device)
+    if ws is None:
+        ws = _workspace(int(_fn["fst_refit_core_mixed_workspace_bytes"](m.handle, dt, n, int(n_samples))), x.device)
+    _check(_fn["fst_mixed_rows"](m.handle, dt, n, _dev_ptr(x), _dev_ptr(y), _dev_ptr(z), _dev_ptr(v), int(n_samples),
+                                 int(seed), _dev_ptr(At), _dev_ptr(b), _dev_ptr(ws), ws.numel(), _stream(stream)))
+    return At, b
+
+
+def fst_leverage(At, L, mrows=None, out=None, stream=None):
+    """Leverage of the rows of At (FP64 R x Sp) given L from fst_cholesky of At At^T."""
+    torch = _torch()
+    R, Sp = At.shape
+    mrows = Sp if mrows is None else int(mrows)
+    if out is None:
+        out = torch.empty(mrows, dtype=torch.float64, device=At.device)
+    _check(_fn["fst_leverage"](int(R), int(Sp), mrows, _dev_ptr(At), _dev_ptr(L), _dev_ptr(out), _stream(stream)))
+    return out
 
 
 def fst_eval(m: Model, x, y, z, out=None, stream=None):

@@ -855,6 +855,33 @@ fst_status fst_refit_core_mixed(const fst_model* m, int32_t dtype, int64_t n, co
   FST_CATCH
 }
 
+fst_status fst_mixed_rows(const fst_model* m, int32_t dtype, int64_t n, const void* x, const void* y,
+                          const void* z, const void* v, int64_t n_samples, uint64_t seed, void* At, void* b,
+                          void* ws, size_t ws_bytes, void* stream) {
+  FST_TRY
+  set_last_error("");
+  check_model3(m);
+  check_dtype(dtype);
+  if (n < 1 || n > (int64_t(1) << 23)) fail(FST_E_INVAL, "mixed rows: need 1 <= n <= 2^23 points");
+  if (n_samples < 1 || n_samples > mixed_length(n)) fail(FST_E_INVAL, "mixed rows: need 1 <= n_samples <= N");
+  if (!x || !y || !z || !v || !At || !ws) fail(FST_E_INVAL, "null argument");
+  const size_t need = mixed_workspace_bytes(m, dtype, n, n_samples);
+  if (ws_bytes < need) fail(FST_E_NOMEM, "mixed rows: workspace too small");
+  mixed_rows(m, dtype, n, x, y, z, v, n_samples, seed, ws, ws_bytes, At, b, stream);
+  return FST_OK;
+  FST_CATCH
+}
+
+fst_status fst_leverage(int64_t R, int64_t Sp, int64_t mrows, const double* At, const double* L, double* out,
+                        void* stream) {
+  FST_TRY
+  set_last_error("");
+  if (!At || !L || (!out && mrows > 0)) fail(FST_E_INVAL, "null argument");
+  leverage(R, Sp, mrows, At, L, out, stream);
+  return FST_OK;
+  FST_CATCH
+}
+
 size_t fst_eval_error_workspace_bytes(int32_t dtype, int64_t n) {
   FST_SIZE_TRY
   if ((dtype != FST_F64 && dtype != FST_F32) || n < 0) return 0;

@@ -197,6 +197,11 @@ size_t eval_error_workspace_bytes(int dtype, int64_t n);
 // mixed least-squares rows (Algorithm 2 steps 2-4): normal equations of S sampled rows of
 // F D W and F D u into G (lower triangle) and h
 int64_t mixed_length(int64_t n);
+// the S sampled mixed rows themselves: A^T (R x Sp, Sp = S rounded up to 64, zero past S) and b
+void mixed_rows(const fst_model* m, int dtype, int64_t n, const void* x, const void* y, const void* z, const void* v,
+                int64_t nsamp, uint64_t seed, void* ws, size_t ws_bytes, void* At, void* b, void* stream);
+// leverage of the rows of A^T (R x Sp, FP64) given the Cholesky factor L of A^T A
+void leverage(int64_t R, int64_t Sp, int64_t mrows, const double* At, const double* L, double* out, void* stream);
 size_t mixed_workspace_bytes(const fst_model* m, int dtype, int64_t n, int64_t nsamp);
 void mixed_normal_equations(const fst_model* m, int dtype, int64_t n, const void* x, const void* y, const void* z,
                             const void* v, int64_t nsamp, uint64_t seed, void* ws, size_t ws_bytes, double* G,

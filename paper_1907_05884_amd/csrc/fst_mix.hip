@@ -589,8 +589,17 @@ static void mixed_normal_equations_t(const fst_model* m, const DeviceModel& dm, 
                        L.Sp);
     check_launch("k_zero_tail");
   }
-  // step 5: normal equations of the sampled mixed rows
-  dense_normal_equations(dtype, At, b, R, L.Sp, G, h, false, stream);
+  // step 5: normal equations of the sampled mixed rows (the rows alone when G and h are NULL)
+  if (G || h) dense_normal_equations(dtype, At, b, R, L.Sp, G, h, false, stream);
+}
+
+void mixed_rows(const fst_model* m, int dtype, int64_t n, const void* x, const void* y, const void* z, const void* v,
+                int64_t nsamp, uint64_t seed, void* ws, size_t ws_bytes, void* At, void* b, void* stream) {
+  const MixLayout L = mix_layout(m, dtype, n, nsamp);
+  mixed_normal_equations(m, dtype, n, x, y, z, v, nsamp, seed, ws, ws_bytes, nullptr, nullptr, stream);
+  const size_t es = dtype == FST_F64 ? 8 : 4;
+  if (At) copy_d2d(At, (char*)ws + L.At, es * (size_t)m->R() * (size_t)L.Sp, stream);
+  if (b) copy_d2d(b, (char*)ws + L.b, es * (size_t)L.Sp, stream);
 }
 
 void mixed_normal_equations(const fst_model* m, int dtype, int64_t n, const void* x, const void* y, const void* z,
@@ -605,6 +614,47 @@ void mixed_normal_equations(const fst_model* m, int dtype, int64_t n, const void
     mixed_normal_equations_t<double>(m, dm, n, x, y, z, v, nsamp, seed, ws, G, h, stream);
   else
     mixed_normal_equations_t<float>(m, dm, n, x, y, z, v, nsamp, seed, ws, G, h, stream);
+}
+
+// ------------------------------------------------------------------------------ leverage
+// Leverage of sampled rows (Sec. 5): l_q = a_q^T (A^T A)^-1 a_q = ||y||^2 with L y = a_q, L the
+// Cholesky factor of A^T A (fst_cholesky storage; a skipped column has L_jj = +inf, so y_j = 0).
+// One wave per row: forward substitution, each step a wave-wide dot product over the solved
+// entries, kept in LDS.
+constexpr int LV_MAX_WAVES = 4;
+constexpr size_t LV_LDS_BYTES = 65536;
+__global__ __launch_bounds__(64 * LV_MAX_WAVES) void k_leverage(int64_t R, int64_t Sp, int64_t mrows,
+                                                                const double* At, const double* L, double* out) {
+  extern __shared__ double lv_y[];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, waves = blockDim.x >> 6;
+  const int64_t q = (int64_t)blockIdx.x * waves + wave;
+  if (q >= mrows) return;
+  double* y = lv_y + (int64_t)wave * R;
+  double ss = 0.0;
+  for (int64_t j = 0; j < R; ++j) {
+    const double* Lj = L + j * R;
+    double part = 0.0;
+    for (int64_t k = lane; k < j; k += 64) part += Lj[k] * y[k];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o, 64);
+    const double yj = (At[j * Sp + q] - part) / Lj[j];
+    if (lane == 0) y[j] = yj;
+    ss += yj * yj;
+    __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0): the LDS store is done before the next reads
+    __builtin_amdgcn_wave_barrier();
+  }
+  if (lane == 0) out[q] = ss;
+}
+
+void leverage(int64_t R, int64_t Sp, int64_t mrows, const double* At, const double* L, double* out, void* stream) {
+  if (R < 1 || R > 8192 || mrows < 0 || Sp < mrows) fail(FST_E_INVAL, "leverage: need 1 <= R <= 8192, mrows <= Sp");
+  if (mrows == 0) return;
+  int waves = (int)(LV_LDS_BYTES / (sizeof(double) * (size_t)R));
+  waves = waves > LV_MAX_WAVES ? LV_MAX_WAVES : waves;
+  const int64_t blocks = (mrows + waves - 1) / waves;
+  hipLaunchKernelGGL(k_leverage, dim3((unsigned)blocks), dim3(64 * waves), sizeof(double) * waves * (size_t)R,
+                     S(stream), R, Sp, mrows, At, L, out);
+  check_launch("k_leverage");
 }
 
 }  // namespace fst
