@@ -134,10 +134,16 @@ def test_batched_fit_f32_low_precision_matches_per_variable(dev):
         for v, (m, (host, ref)) in enumerate(zip(models, refs)):
             assert rel_l2(m.core, ref.core) <= 1e-12, (prec, v)
         om = _omodel(wl, models[1])
-        alpha, *_ = lsq.refit_core(om, case.pts.astype(np.float64), case.vals[1], wl.n_samples, wl.seed + 1)
+        alpha, _, Gk, _ = lsq.refit_core(om, case.pts.astype(np.float64), case.vals[1], wl.n_samples, wl.seed + 1)
         err = rel_l2(models[1].core.reshape(-1), alpha.reshape(-1))
-        print(f"prec {prec}: core rel-L2 vs FP64 oracle after 4 refinement steps {err:.3e}")
-        assert err <= 1e-4
+        info = models[1].solve_info()
+        kappa = np.linalg.cond(Gk)
+        print(f"prec {prec}: core rel-L2 vs FP64 oracle after refinement {err:.3e} ({info}, kappa {kappa:.2e})")
+        # the refinement stops at a relative normal-equation residual of 1e-8 or below (after at most
+        # four times the steps asked for, climbing to a wider Gram if needed): the core is then within
+        # kappa(G) times that residual, plus the FP32 rounding of the points and values
+        assert info["rel_residual"] <= 1e-8
+        assert err <= max(1e-6, 2 * kappa * info["rel_residual"])
 
 
 def test_batched_more_variables_than_one_launch(dev):

@@ -12,6 +12,7 @@ import datagen
 from oracle import interp, pipeline, sampler, sparsefit, sthosvd
 from oracle.basis import legendre_orthonormal
 from oracle.model import Model as OModel
+from oracle.reconstruct import rel_l2
 from oracle.sthosvd import ranks_for_precision, st_hosvd, tucker_full
 
 fst = pytest.importorskip("paper_1907_05884_amd.binding")
@@ -110,11 +111,11 @@ def test_compress_host_matches_oracle_small():
     x, y, z, v = w.soa()
     m = fst.fst_compress_host(p, x, y, z, v)
     mo = pipeline.compress(w.pts, w.vals, w.lo, w.hi, (16, 16, 16), (5, 4, 3), (9, 9, 9), 0.2, w.seed)
-    np.testing.assert_allclose(m.core, mo.core, rtol=1e-8, atol=1e-9)
+    assert rel_l2(m.core, mo.core) <= 1e-10
     for k in range(3):
         Ck, Co = m.coefs(k), mo.coefs[k]
         np.testing.assert_array_equal(Ck != 0, Co != 0)
-        np.testing.assert_allclose(Ck, Co, rtol=1e-7, atol=1e-9)
+        assert rel_l2(Ck, Co) <= 1e-10
 
 
 def _decaying_tensor(seed, dims, core_dims):
@@ -165,7 +166,7 @@ def test_compress_host_with_eps_ranks_matches_oracle():
     assert all(1 <= r[k] <= caps[k] for k in range(3)) and all(r[k] <= r[(k + 1) % 3] * r[(k + 2) % 3] for k in range(3))
     assert m.info()["rank"] == r
     mo = pipeline.compress(w.pts, w.vals, w.lo, w.hi, grid, r, degree, 0.2, w.seed)
-    np.testing.assert_allclose(m.core, mo.core, rtol=1e-8, atol=1e-9)
+    assert rel_l2(m.core, mo.core) <= 1e-10
 
 
 def test_model_parts_roundtrip_and_serialisation():
@@ -343,11 +344,11 @@ def test_compress_host_d_matches_oracle_four_way():
     m = fst.fst_compress_host_d(p, coords, v)
     mo = pipeline.compress(w.pts, w.vals, w.lo, w.hi, grid, rank, degree, 0.3, w.seed)
     assert m.info()["d"] == 4 and m.info()["rank"] == rank
-    np.testing.assert_allclose(m.core, mo.core, rtol=1e-8, atol=1e-9)
+    assert rel_l2(m.core, mo.core) <= 1e-10
     for k in range(4):
         Ck, Co = m.coefs(k), mo.coefs[k]
         np.testing.assert_array_equal(Ck != 0, Co != 0)
-        np.testing.assert_allclose(Ck, Co, rtol=1e-7, atol=1e-9)
+        assert rel_l2(Ck, Co) <= 1e-10
 
 
 def test_compress_host_d_with_eps_ranks_matches_oracle():
@@ -361,7 +362,7 @@ def test_compress_host_d_with_eps_ranks_matches_oracle():
     assert all(1 <= r[k] <= caps[k] for k in range(4)), r
     assert m.info()["rank"] == r
     mo = pipeline.compress(w.pts, w.vals, w.lo, w.hi, grid, r, degree, 0.3, w.seed)
-    np.testing.assert_allclose(m.core, mo.core, rtol=1e-8, atol=1e-9)
+    assert rel_l2(m.core, mo.core) <= 1e-10
     Tt = tucker_full(mo.core, mo.info["factors"])
     assert np.linalg.norm(T - Tt) <= eps * np.linalg.norm(T) * (1 + 1e-9)
 
@@ -421,7 +422,7 @@ def test_sparse_fit_lars_on_singular_vectors_matches_oracle():
         ref = sparsefit.fit_factor(Wk, interp.grid_nodes(16), 9, solver="lars")
         got = fst.fst_sparse_fit(Wk, 9, solver=fst.FST_SOLVER_LARS)
         np.testing.assert_array_equal(got != 0, ref != 0)
-        np.testing.assert_allclose(got, ref, rtol=1e-8, atol=1e-11)
+        np.testing.assert_allclose(got, ref, rtol=1e-10, atol=1e-13)
 
 
 def test_compress_host_with_lars_matches_oracle():
@@ -432,10 +433,10 @@ def test_compress_host_with_lars_matches_oracle():
     m = fst.fst_compress_host(p, *w.soa())
     mo = pipeline.compress(w.pts, w.vals, w.lo, w.hi, (16, 16, 16), (5, 4, 3), (9, 9, 9), 0.2, w.seed,
                            solver="lars")
-    np.testing.assert_allclose(m.core, mo.core, rtol=1e-8, atol=1e-9)
+    assert rel_l2(m.core, mo.core) <= 1e-10
     for k in range(3):
         np.testing.assert_array_equal(m.coefs(k) != 0, mo.coefs[k] != 0)
-        np.testing.assert_allclose(m.coefs(k), mo.coefs[k], rtol=1e-7, atol=1e-9)
+        assert rel_l2(m.coefs(k), mo.coefs[k]) <= 1e-10
     # the 4-way compress takes the same solver
     w4 = _workload4()
     p4 = fst.make_params_d(d=4, dtype=fst.FST_F64, lo=w4.lo, hi=w4.hi, grid=(8,) * 4, rank=(3, 3, 2, 2),
@@ -446,7 +447,7 @@ def test_compress_host_with_lars_matches_oracle():
                             solver="lars")
     for k in range(4):
         np.testing.assert_array_equal(m4.coefs(k) != 0, mo4.coefs[k] != 0)
-        np.testing.assert_allclose(m4.coefs(k), mo4.coefs[k], rtol=1e-7, atol=1e-9)
+        assert rel_l2(m4.coefs(k), mo4.coefs[k]) <= 1e-10
     bad = fst.make_params(sparse_solver=7)
     assert fst._fn["fst_fit_workspace_bytes"](ctypes.byref(bad), 10000) == 0
 
@@ -466,7 +467,7 @@ def test_sparse_fit_choice_matches_oracle(solver, s, q):
     code = fst.FST_SOLVER_LARS if solver == "lars" else fst.FST_SOLVER_OMP
     got = fst.fst_sparse_fit_choice(W, p, s, q, solver=code)
     np.testing.assert_array_equal(got != 0, ref != 0)
-    np.testing.assert_allclose(got, ref, rtol=1e-8, atol=1e-11)
+    np.testing.assert_allclose(got, ref, rtol=1e-10, atol=1e-13)
     assert np.any(got[p + 1:] != 0)          # some column keeps the wavelet fit
 
 
@@ -478,10 +479,10 @@ def test_compress_host_with_wavelets_matches_oracle():
     m = fst.fst_compress_host(p, *w.soa())
     mo = pipeline.compress(w.pts, w.vals, w.lo, w.hi, grid, rank, degree, 0.2, w.seed, wavelet=wav)
     assert m.wavelets() == ((2, 3),) * 3
-    np.testing.assert_allclose(m.core, mo.core, rtol=1e-8, atol=1e-9)
+    assert rel_l2(m.core, mo.core) <= 1e-10
     for k in range(3):
         np.testing.assert_array_equal(m.coefs(k) != 0, mo.coefs[k] != 0)
-        np.testing.assert_allclose(m.coefs(k), mo.coefs[k], rtol=1e-7, atol=1e-9)
+        assert rel_l2(m.coefs(k), mo.coefs[k]) <= 1e-10
     assert m.paper_bytes() == mo.paper_bytes()
     blob = fst.fst_model_save(m)
     m2 = fst.fst_model_load(blob)
@@ -497,7 +498,7 @@ def test_compress_host_with_wavelets_matches_oracle():
                             wavelet=(2, 1))
     for k in range(4):
         np.testing.assert_array_equal(m4.coefs(k) != 0, mo4.coefs[k] != 0)
-        np.testing.assert_allclose(m4.coefs(k), mo4.coefs[k], rtol=1e-7, atol=1e-9)
+        assert rel_l2(m4.coefs(k), mo4.coefs[k]) <= 1e-10
 
 
 def test_wavelet_parameters_are_validated():
