@@ -18,7 +18,8 @@ LIB = os.path.join(PKG, "libfst.so")
 ARCH = os.environ.get("FST_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["fst_api.cpp", "fst_model.cpp", "fst_host.cpp", "fst_corrector.cpp", "fst_batched.cpp",
-           "fst_kernels.hip", "fst_linalg.hip", "fst_grid.hip", "fst_mix.hip", "fst_dway.hip", "fst_mlp.hip", "fst_gram16.hip", "fst_eval_mfma.hip"]
+           "fst_kernels.hip", "fst_linalg.hip", "fst_grid.hip", "fst_mix.hip", "fst_dway.hip", "fst_mlp.hip", "fst_gram16.hip", "fst_eval_mfma.hip",
+           "fst_factor_mfma.hip"]
 
 COMMON = ["-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-function",
           "-I" + os.path.join(ROOT, "include")]

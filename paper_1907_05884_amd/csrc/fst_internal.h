@@ -150,6 +150,10 @@ void launch_factor_eval(const fst_model* m, const DeviceModel& dm, int dtype, in
                         const void* x, const void* y, const void* z, const void* v,
                         const int32_t* idx, int64_t mrows, void* U, void* vs, void* stream);
 // the same for a model of any d: coords holds m->d coordinate arrays
+// FP32 Legendre models (d = 3 or 4): eq. (2) with the contraction on MFMA
+bool factor_eval_mfma_applies(const fst_model* m, int64_t mrows);
+void launch_factor_eval_mfma(const fst_model* m, const DeviceModel& dm, const void* const* coords, const void* v,
+                             const int32_t* idx, int64_t mrows, void* U, void* vs, void* stream);
 void launch_factor_eval_d(const fst_model* m, const DeviceModel& dm, int dtype, const void* const* coords,
                           const void* v, const int32_t* idx, int64_t mrows, void* U, void* vs, void* stream);
 size_t gram_workspace_bytes(const fst_model* m, int64_t mrows);
