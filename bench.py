@@ -396,9 +396,16 @@ def precision_leg(fst, torch, dev, args, m0, m_or, ref, x, y, z, v, idx, U, vs, 
         torch.cuda.empty_cache()
         log(f"[bench] precision form {name}: gram call {res['ms']['gram_call']:.1f} ms, fit-core "
             f"{res['fitcore_rows_per_s']:.3g} rows/s, core per step {res.get('core_rel_l2_vs_oracle_per_refine_step')}")
+    # the headline split: the fastest whose core is within 1e-6 of the oracle's after the
+    # refinement steps (all three are reported)
+    def final_err(name):
+        e = out[name].get("core_rel_l2_vs_oracle_per_refine_step")
+        return e[-1] if e else float("inf")
+    ok = [k for k in out if final_err(k) <= 1e-6]
+    pick = max(ok, key=lambda k: out[k]["fitcore_rows_per_s"]) if ok else min(out, key=final_err)
     # fst_refit_core as a user calls it: library-allocated workspace (dense route when memory allows)
     calls = {}
-    for name, code in (("f32", fst.FST_GRAM_F32), ("bf16x2", fst.FST_GRAM_BF16X2)):
+    for name, code in (("f32", fst.FST_GRAM_F32), (pick, names[pick])):
         torch.cuda.empty_cache()
         t_call = []
         for rep in range(2):
@@ -416,11 +423,16 @@ def precision_leg(fst, torch, dev, args, m0, m_or, ref, x, y, z, v, idx, U, vs, 
             c["core_rel_l2_vs_oracle"] = rel(go.core.reshape(-1))
         calls[name] = c
         log(f"[bench] fst_refit_core {name}: {c['ms']:.1f} ms, core vs oracle {c.get('core_rel_l2_vs_oracle')}")
-    head = dict(out["bf16x2"])
-    head["what"] = ("precision form: design rows split into two BF16 terms (4 BF16 MFMA products per entry pair, "
-                    "FP32 sums folded into FP64), FP64 Cholesky, 3 FP64-residual refinement steps")
-    head["vs_f32_refit_core_call"] = calls["f32"]["ms"] / calls["bf16x2"]["ms"]
-    head["other_splits"] = {k: out[k] for k in ("f16x2", "bf16x3")}
+    terms = {"bf16x2": "two BF16 terms (4 BF16 MFMA products per entry pair)",
+             "f16x2": "two scaled FP16 terms (4 FP16 MFMA products per entry pair)",
+             "bf16x3": "three BF16 terms (6 BF16 MFMA products per entry pair)"}
+    head = dict(out[pick])
+    head["split"] = pick
+    head["what"] = (f"precision form: design rows split into {terms[pick]}, FP32 sums folded into FP64, FP64 "
+                    f"Cholesky, {steps} FP64-residual refinement steps; the fastest split whose core is within "
+                    f"1e-6 of the FP64 oracle's after those steps")
+    head["vs_f32_refit_core_call"] = calls["f32"]["ms"] / calls[pick]["ms"]
+    head["other_splits"] = {k: out[k] for k in out if k != pick}
     head["refit_core_call"] = calls
     return head
 
@@ -572,7 +584,7 @@ def main():
     ap.add_argument("--samples", type=int, default=200_000)
     ap.add_argument("--precision", choices=("f32", "bf16", "f16", "f16x2", "bf16x3", "bf16x2"), default="f32",
                     help="Gram precision: f32 (FP32 MFMA) or the 16-bit form with FP64 refinement")
-    ap.add_argument("--refine", type=int, default=None, help="refinement steps (default 0 for f32, 3 otherwise)")
+    ap.add_argument("--refine", type=int, default=None, help="FP64-residual refinement steps (default 3)")
     ap.add_argument("--gram-route", choices=("dense", "khatri-rao"), default="dense",
                     help="Gram: design rows materialised + dense MFMA Gram (default), or formed on the fly "
                          "from the factor values (the route with a minimal workspace)")
