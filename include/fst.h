@@ -308,6 +308,30 @@ fst_status fst_cholesky(int64_t R, double* G, double shift, int64_t* info, void*
 #define FST_CHOLESKY_NOALLOC_MAX_R 65536
 fst_status fst_cholesky_noalloc(int64_t R, double* G, double shift, int64_t* info, void* stream);
 
+/* Algorithm 2 step 5 from given normal equations: the FP64 Cholesky of G, the solve for the
+ * core, and refine_steps FP64-residual refinement steps on the sampled rows, with the
+ * precision ladder of fst_model_fit_info (a Gram that breaks down or stalls above 1e-8 is
+ * formed again from FP32 rows, then FP64 rows, then with dependent columns skipped; a split
+ * Gram is first factored again with dependent columns skipped).  The calls fst_refit_core
+ * makes after its Gram, for callers that form the Gram themselves.
+ * x, y, z, v: device points and values (dtype, n); idx: device int32 mrows sampled row
+ * indices in [0, n) (as fst_sample_indices draws them; not checked on the device); U, vs: their factor values and values as
+ * fst_factor_eval writes them (read when the ladder forms the Gram again); gram_prec: the
+ * precision G was formed at.  G: device FP64 R x R, on entry the lower triangle of A^T A,
+ * on return the Cholesky factor (fst_cholesky layout) of the Gram actually used; h: device
+ * FP64 R, A^T v on entry (formed again from FP64 rows when the ladder reaches them); alpha:
+ * device FP64 R, the core (C order).  gram_prec_used, dropped, steps_kept, rel_residual: as
+ * fst_model_fit_info; any may be NULL.  ws >= fst_solve_core_workspace_bytes(m, mrows,
+ * gram_prec) (FST_E_NOMEM below).  r1 r2 r3 < mrows <= n; 0 <= refine_steps <= 100.
+ * Synchronises `stream`. */
+size_t fst_solve_core_workspace_bytes(const fst_model* m, int64_t mrows, int32_t gram_prec);
+fst_status fst_solve_core(const fst_model* m, int32_t dtype, int64_t n, const void* x,
+                          const void* y, const void* z, const void* v, const int32_t* idx,
+                          int64_t mrows, const void* U, const void* vs, int32_t gram_prec,
+                          int32_t refine_steps, double* G, double* h, double* alpha,
+                          int32_t* gram_prec_used, int64_t* dropped, int32_t* steps_kept,
+                          double* rel_residual, void* ws, size_t ws_bytes, void* stream);
+
 /* Solves L L^T x = b with L from fst_cholesky (device FP64, including its stored
  * diagonal-block inverses); b and x may alias.
  * Asynchronous. */
@@ -425,6 +449,15 @@ fst_status fst_model_info(const fst_model* m, double* lo, double* hi, int32_t* r
 fst_status fst_model_core(const fst_model* m, double* core_out);
 /* C_out: host FP64 (p_k + 1 + detail functions) x r_k row-major, zeros off the support */
 fst_status fst_model_coefs(const fst_model* m, int32_t k, double* C_out);
+/* Factor k in the compressed-column form the sparse fit produces (Sec. 3: the coefficients
+ * of each factor function on its selected basis functions, eq. (2)): column j (factor
+ * function j of mode k) holds rowidx[colptr[j] .. colptr[j+1]) (basis function indices,
+ * ascending: Legendre degree i for i <= p_k, then the wavelet functions) with values vals[..]
+ * (host FP64).  colptr: host int32[r_k + 1]; rowidx: host int32[nnz]; vals: host
+ * double[nnz]; *nnz: number of non-zeros.  Any output may be NULL (call with only nnz to size
+ * the arrays).  Explicit zeros of the dense form are not stored. */
+fst_status fst_model_factor(const fst_model* m, int32_t k, int32_t* colptr, int32_t* rowidx,
+                            double* vals, int64_t* nnz);
 /* How the core of a model from fst_fit, fst_refit_core or fst_fit_batched was solved.
  * Precision ladder: a Gram whose Cholesky breaks down, or whose refinement makes the FP64
  * normal-equation residual grow, or whose refinement ends with ||A^T (v - A alpha)|| / ||A^T v||

@@ -101,6 +101,10 @@ _lib_fns = dict(
     fst_cholesky_workspace_bytes=(C.c_size_t, _i64),
     fst_cholesky=(_i32, _i64, _vp, C.c_double, C.POINTER(_i64), _vp, C.c_size_t, _vp),
     fst_cholesky_noalloc=(_i32, _i64, _vp, C.c_double, C.POINTER(_i64), _vp),
+    fst_solve_core_workspace_bytes=(C.c_size_t, _vp, _i64, _i32),
+    fst_solve_core=(_i32, _vp, _i32, _i64, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp, _i32, _i32, _vp, _vp, _vp,
+                    C.POINTER(_i32), C.POINTER(_i64), C.POINTER(_i32), C.POINTER(C.c_double), _vp, C.c_size_t, _vp),
+    fst_model_factor=(_i32, _vp, _i32, _vp, _vp, _vp, C.POINTER(_i64)),
     fst_mixed_rows=(_i32, _vp, _i32, _i64, _vp, _vp, _vp, _vp, _i64, C.c_uint64, _vp, _vp, _vp, C.c_size_t, _vp),
     fst_leverage=(_i32, _i64, _i64, _i64, _vp, _vp, _vp, _vp),
     fst_cholesky_solve=(_i32, _i64, _vp, _vp, _vp, _vp),
@@ -461,6 +465,42 @@ def fst_refit_core_mixed(m: Model, x, y, z, v, n_samples: int, seed: int, ws=Non
                                        int(n_samples), int(seed), _dev_ptr(ws), ws.numel(), _stream(stream),
                                        C.byref(h)))
     return Model(h)
+
+
+def fst_solve_core(m: Model, x, y, z, v, idx, U, vs, G, h, gram_prec=None, refine_steps: int = 3, ws=None,
+                   stream=None):
+    """Algorithm 2 step 5 from the caller's normal equations (G overwritten by its Cholesky
+    factor): returns (alpha device FP64 tensor, info dict as Model.solve_info)."""
+    torch = _torch()
+    dt = _dtype_code(x)
+    if gram_prec is None:
+        gram_prec = FST_GRAM_F64 if dt == FST_F64 else FST_GRAM_F32
+    mrows = idx.numel()
+    if ws is None:
+        ws = _workspace(int(_fn["fst_solve_core_workspace_bytes"](m.handle, int(mrows), int(gram_prec))), x.device)
+    alpha = torch.empty(m.R, dtype=torch.float64, device=x.device)
+    prec, dropped, steps, res = _i32(), _i64(), _i32(), C.c_double()
+    _check(_fn["fst_solve_core"](m.handle, dt, x.numel(), _dev_ptr(x), _dev_ptr(y), _dev_ptr(z), _dev_ptr(v),
+                                 _dev_ptr(idx), int(mrows), _dev_ptr(U), _dev_ptr(vs), int(gram_prec),
+                                 int(refine_steps), _dev_ptr(G), _dev_ptr(h), _dev_ptr(alpha), C.byref(prec),
+                                 C.byref(dropped), C.byref(steps), C.byref(res), _dev_ptr(ws), ws.numel(),
+                                 _stream(stream)))
+    return alpha, dict(gram_prec=prec.value, dropped=dropped.value, refine_steps=steps.value,
+                       rel_residual=res.value)
+
+
+def fst_model_factor(m: Model, k: int):
+    """Factor k as compressed columns: (colptr int32[r_k + 1], rowidx int32[nnz], vals float64[nnz])."""
+    nnz = _i64()
+    _check(_fn["fst_model_factor"](m.handle, int(k), None, None, None, C.byref(nnz)))
+    r = m.info()["rank"][k]
+    colptr = np.empty(r + 1, np.int32)
+    rowidx = np.empty(max(nnz.value, 1), np.int32)
+    vals = np.empty(max(nnz.value, 1), np.float64)
+    _check(_fn["fst_model_factor"](m.handle, int(k), colptr.ctypes.data_as(C.c_void_p),
+                                   rowidx.ctypes.data_as(C.c_void_p), vals.ctypes.data_as(C.c_void_p),
+                                   C.byref(nnz)))
+    return colptr, rowidx[:nnz.value], vals[:nnz.value]
 
 
 def fst_mixed_rows(m: Model, x, y, z, v, n_samples: int, seed: int, ws=None, stream=None):

@@ -779,6 +779,46 @@ fst_status fst_refit_core(const fst_model* m, int32_t dtype, int64_t n, const vo
   FST_CATCH
 }
 
+size_t fst_solve_core_workspace_bytes(const fst_model* m, int64_t mrows, int32_t gram_prec) {
+  FST_SIZE_TRY
+  if (!m || m->d != 3 || mrows < 1) return 0;
+  const int64_t R = m->R();
+  size_t bytes = align_up(solve_scratch_bytes(m, mrows));
+  if (split_terms(gram_prec) > 0) bytes += align_up(sizeof(double) * (size_t)R * (size_t)R);
+  return bytes;
+  FST_SIZE_CATCH
+}
+
+fst_status fst_solve_core(const fst_model* m, int32_t dtype, int64_t n, const void* x, const void* y,
+                          const void* z, const void* v, const int32_t* idx, int64_t mrows, const void* U,
+                          const void* vs, int32_t gram_prec, int32_t refine_steps, double* G, double* h,
+                          double* alpha, int32_t* gram_prec_used, int64_t* dropped, int32_t* steps_kept,
+                          double* rel_residual, void* ws, size_t ws_bytes, void* stream) {
+  FST_TRY
+  set_last_error("");
+  check_model3(m);
+  check_dtype(dtype);
+  check_prec(dtype, gram_prec);
+  const int64_t R = m->R();
+  if (n < 1 || n >= (int64_t(1) << 31)) fail(FST_E_INVAL, "need 1 <= n < 2^31 points");
+  if (mrows <= R || mrows > n) fail(FST_E_INVAL, "Algorithm 2 needs r1 r2 r3 < mrows <= n");
+  if (refine_steps < 0 || refine_steps > 100) fail(FST_E_INVAL, "refine_steps must be in [0, 100]");
+  if (!x || !y || !z || !v || !idx || !U || !vs || !G || !h || !alpha || !ws)
+    fail(FST_E_INVAL, "null argument");
+  const size_t sneed = align_up(solve_scratch_bytes(m, mrows));
+  const size_t need = fst_solve_core_workspace_bytes(m, mrows, gram_prec);
+  if (ws_bytes < need) fail(FST_E_NOMEM, "solve: workspace smaller than fst_solve_core_workspace_bytes");
+  double* Gsave = split_terms(gram_prec) > 0 ? (double*)((char*)ws + sneed) : nullptr;
+  const SolveInfo si = solve_core(m, dtype, n, x, y, z, v, idx, mrows, U, vs, gram_prec, refine_steps, G, h, alpha,
+                                  ws, sneed, stream, Gsave);
+  if (gram_prec_used) *gram_prec_used = si.gram_prec;
+  if (dropped) *dropped = si.dropped;
+  if (steps_kept) *steps_kept = si.refine_steps;
+  if (rel_residual) *rel_residual = si.rel_residual;
+  return FST_OK;
+  FST_CATCH
+}
+
 fst_status fst_eval(const fst_model* m, int32_t dtype, int64_t n, const void* x, const void* y,
                     const void* z, void* out, void* stream) {
   FST_TRY
@@ -1377,6 +1417,31 @@ fst_status fst_model_coefs(const fst_model* m, int32_t k, double* C_out) {
   check_model(m);
   if (k < 0 || k >= m->d || !C_out) fail(FST_E_INVAL, "bad mode or null output");
   std::memcpy(C_out, m->coef[k].data(), sizeof(double) * m->coef[k].size());
+  return FST_OK;
+  FST_CATCH
+}
+
+fst_status fst_model_factor(const fst_model* m, int32_t k, int32_t* colptr, int32_t* rowidx, double* vals,
+                            int64_t* nnz) {
+  FST_TRY
+  set_last_error("");
+  check_model(m);
+  if (k < 0 || k >= m->d) fail(FST_E_INVAL, "bad mode");
+  const int rows = m->rows(k), r = m->rank[k];
+  const std::vector<double>& C = m->coef[k];
+  int64_t count = 0;
+  for (int j = 0; j < r; ++j) {
+    if (colptr) colptr[j] = (int32_t)count;
+    for (int i = 0; i < rows; ++i) {
+      const double c = C[(size_t)i * r + j];
+      if (c == 0.0) continue;
+      if (rowidx) rowidx[count] = i;
+      if (vals) vals[count] = c;
+      ++count;
+    }
+  }
+  if (colptr) colptr[r] = (int32_t)count;
+  if (nnz) *nnz = count;
   return FST_OK;
   FST_CATCH
 }

@@ -558,3 +558,28 @@ def test_size_queries_need_no_device():
     p = fst.make_params(rank=(6, 5, 4), grid=(8, 8, 8), degree=(8, 8, 8), n_samples=5000)
     assert fst.fst_fit_workspace_bytes(p, 100000) > 0
     assert fst._fn["fst_refit_core_mixed_workspace_bytes"](m.handle, fst.FST_F32, 100000, 5000) > 0
+
+
+def test_model_factor_compressed_columns():
+    # the sparse factors of a host compress (Legendre + wavelets) as compressed columns: the
+    # same non-zeros as the dense form, rows ascending in every column, counts that add up
+    w = datagen.small_f64(n=6000, n_samples=1500)
+    p = fst.make_params(dtype=fst.FST_F64, lo=w.lo, hi=w.hi, grid=(16, 16, 16), rank=(6, 5, 4), degree=(9, 9, 9),
+                        interp_fraction=0.2, n_samples=1500, seed=w.seed, wavelet=(2, 3))
+    m = fst.fst_compress_host(p, *w.soa())
+    total = 0
+    for k in range(3):
+        C = m.coefs(k)
+        colptr, rowidx, vals = fst.fst_model_factor(m, k)
+        assert colptr[0] == 0 and np.all(np.diff(colptr) >= 0) and colptr[-1] == rowidx.size == vals.size
+        dense = np.zeros_like(C)
+        for j in range(C.shape[1]):
+            rows = rowidx[colptr[j]:colptr[j + 1]]
+            assert np.all(np.diff(rows) > 0) and np.all((rows >= 0) & (rows < C.shape[0]))
+            dense[rows, j] = vals[colptr[j]:colptr[j + 1]]
+        np.testing.assert_array_equal(dense, C)
+        assert np.count_nonzero(vals) == vals.size == np.count_nonzero(C)
+        total += vals.size
+    assert total == m.info()["nnz"]
+    with pytest.raises(fst.FstError):
+        fst.fst_model_factor(m, 3)
