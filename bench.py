@@ -45,20 +45,32 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(precision: str):
-    """HBM bytes per launch of the Gram kernel from the committed FETCH_SIZE / WRITE_SIZE
-    counters (calibrated against a copy of known size), or None when there are none for this
-    precision or the kernel source has changed since they were taken."""
+def measured_kernel_bytes(names):
+    """HBM bytes per launch of the named kernels (summed) from the committed FETCH_SIZE /
+    WRITE_SIZE counters (calibrated against a copy of known size), or None when a kernel has no
+    counters or the kernel sources have changed since they were taken."""
     import json as _json
     try:
         t = _json.load(open(TRAFFIC))
         h = kernel_source_hash()
     except OSError:
         return None
-    name = t.get("gram_kernel", {}).get(precision)
-    if h != t.get("source_sha256_prefix") or name not in t.get("kernels", {}):
+    names = [names] if isinstance(names, str) else list(names or [])
+    if h != t.get("source_sha256_prefix") or not names or any(n not in t.get("kernels", {}) for n in names):
         return None
-    return float(t["kernels"][name]["bytes"])
+    return float(sum(t["kernels"][n]["bytes"] for n in names))
+
+
+def measured_traffic(precision: str):
+    """HBM bytes per launch of the Gram of this precision (the kernels of one fst_gram call)."""
+    import json as _json
+    try:
+        t = _json.load(open(TRAFFIC))
+    except OSError:
+        return None
+    return measured_kernel_bytes(t.get("gram_kernel", {}).get(precision))
+
+
 METRIC = "LS design rows/s + reconstructed points/s at stated rel-L2 vs FP64 oracle"
 
 
@@ -387,7 +399,8 @@ def precision_leg(fst, torch, dev, args, m0, m_or, ref, x, y, z, v, idx, U, vs, 
         t_gram = res["ms"]["gram_call"] / 1e3
         res["roofline"] = {"kernel": f"k_gram_split<{name}> with its k_design_rows_split (one fst_gram call)",
                            "bound": "mfma", "achieved": flops / t_gram / 1e12, "peak": 2500.0, "unit": "TFLOP/s",
-                           "frac": flops / t_gram / 2.5e15, "traffic": None, "flops_per_launch": flops,
+                           "frac": flops / t_gram / 2.5e15, "traffic": measured_traffic(name),
+                           "flops_per_launch": flops,
                            "mfma_products": products[name],
                            "executed_16bit_tflops": products[name] * flops / t_gram / 1e12,
                            "executed_frac": products[name] * flops / t_gram / 2.5e15}
@@ -849,16 +862,19 @@ def main():
             **({"k_design_rows (A^T of the M sampled rows, FP32)": {
                 "bound": "hbm", "achieved": rows_bytes / avg["rows"] / 1e9, "peak": 8000.0, "unit": "GB/s",
                 "frac": rows_bytes / avg["rows"] / 8e12, "ms": avg["rows"] * 1e3,
-                "bytes_per_launch": rows_bytes}} if dense else {}),
+                "bytes_per_launch": rows_bytes, "traffic": measured_kernel_bytes("k_design_rows_vec<float>")}}
+               if dense else {}),
             "k_factor_eval (all N points, no gather)": {
                 "bound": "hbm", "achieved": k1_bytes / t_k1_all / 1e9, "peak": 8000.0, "unit": "GB/s",
                 "frac": k1_bytes / t_k1_all / 8e12, "ms": t_k1_all * 1e3,
-                "bytes_per_launch": k1_bytes},
+                "bytes_per_launch": k1_bytes,
+                "traffic": measured_kernel_bytes("k_factor_eval_mfma<float, 3, 2, 8, true> [all N]")},
             "k_eval (reconstruction)": {
                 "bound": "alu", "achieved": eval_flops / avg["eval"] / 1e12, "peak": 157.3, "unit": "TFLOP/s",
                 "frac": eval_flops / avg["eval"] / 157.3e12, "flops_per_launch": eval_flops,
-                "note": "FP32 vector peak; packed FP32 is disabled by the build rules, so 78.6 TFLOP/s is the "
-                        "attainable scalar-FMA ceiling"},
+                "traffic": measured_kernel_bytes("k_eval_mfma<32, 24>"),
+                "note": "k_eval_mfma: the core contraction (2R flop per point) on FP32 MFMA, the basis, factor "
+                        "values and weighted reduction on the VALU; peak = FP32 MFMA and vector peak"},
             "grid preview 512^3 FP32 (fst_eval_grid: k_factor_eval + 3 x k_mode_product)": {
                 "bound": "hbm", "achieved": grid_bytes / t_grid / 1e9, "peak": 8000.0, "unit": "GB/s",
                 "frac": grid_bytes / t_grid / 8e12, "ms": t_grid * 1e3, "bytes_per_launch": grid_bytes,

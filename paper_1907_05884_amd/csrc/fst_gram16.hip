@@ -2,14 +2,15 @@
 // step 5 (eq. (6)), G = A^T A, formed on 16-bit MFMA from design rows split into NT 16-bit
 // terms, A = A_0 + A_1 + ... + A_{NT-1}, each term the rounding of what the earlier ones left:
 //
-//   NT = 1  A_0 = rnd(A)                               G ~ A_0^T A_0
-//   NT = 2  FP16, entries scaled by a power of two     G ~ A_0^T A_0 + A_0^T A_1 + A_1^T A_0
-//   NT = 3  BF16                                       G ~ sum over a + b <= 2 of A_a^T A_b
+//   FP16 x 2  entries scaled by a power of two     G ~ (A_0 + A_1)^T (A_0 + A_1), 4 products
+//   BF16 x 2                                       G ~ (A_0 + A_1)^T (A_0 + A_1), 4 products
+//   BF16 x 3                                       G ~ sum over a + b <= 2 of A_a^T A_b, 6 products
 //
-// Products of terms whose orders add up to NT or more are below the FP32 rounding of the
-// entries and are left out.  FP16 splits carry 22 significant bits and BF16 splits 24, so
-// G is as accurate as a Gram of FP32 rows, at 3 (FP16) or 6 (BF16) 16-bit products per entry
-// pair instead of one FP32 product.
+// The two-term forms keep the whole square, so G is the Gram of the split rows (positive
+// semidefinite); leaving out A_1^T A_1 would bias the diagonal by about 2^-24 of each entry,
+// as large as the smallest eigenvalues of ill-conditioned systems, and slow the refinement
+// that follows.  In the three-term form the products left out are below the FP32 rounding of
+// the entries.  FP16 x 2 carries 22 significant bits, BF16 x 2 16 and BF16 x 3 24.
 //
 //   k_design_rows_split  A^T in NT planes, 16-bit, chunk-major: plane[(c R + j) 64 + k] holds
 //                        row 64 c + k of design column j (64-row chunks of one column are
