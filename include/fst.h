@@ -645,6 +645,12 @@ size_t fst_mlp_grad_workspace_bytes(int32_t batch);
 fst_status fst_mlp_grad(const fst_corrector* c, int32_t dtype, int64_t n, const void* x, const void* y,
                         const void* z, const float* target, const int32_t* idx, int32_t batch,
                         float* grad_out, void* ws, size_t ws_bytes, void* stream);
+/* The same gradient with the 64 x 64 layer in FP32 from the FP32 master weights, activations
+ * not rounded to BF16: the reference mode of the training kernel (the BF16 MFMA layer is the
+ * one fst_corrector_train uses).  Same arguments, workspace and errors as fst_mlp_grad. */
+fst_status fst_mlp_grad_fp32(const fst_corrector* c, int32_t dtype, int64_t n, const void* x,
+                             const void* y, const void* z, const float* target, const int32_t* idx,
+                             int32_t batch, float* grad_out, void* ws, size_t ws_bytes, void* stream);
 
 #ifdef __cplusplus
 }

@@ -160,6 +160,7 @@ _lib_fns = dict(
     fst_eval_corrected=(_i32, _vp, _vp, _i32, _i64, _vp, _vp, _vp, _vp, _vp),
     fst_mlp_grad_workspace_bytes=(C.c_size_t, _i32),
     fst_mlp_grad=(_i32, _vp, _i32, _i64, _vp, _vp, _vp, _vp, _vp, _i32, _vp, _vp, C.c_size_t, _vp),
+    fst_mlp_grad_fp32=(_i32, _vp, _i32, _i64, _vp, _vp, _vp, _vp, _vp, _i32, _vp, _vp, C.c_size_t, _vp),
 )
 _fn = {name: _proto(name, spec[0], *spec[1:]) for name, spec in _lib_fns.items()}
 EXPORTED_SYMBOLS = tuple(_lib_fns)
@@ -1009,13 +1010,14 @@ def fst_eval_corrected(m: Model, c, x, y, z, out=None, stream=None):
     return out
 
 
-def fst_mlp_grad(c: Corrector, x, y, z, target, idx, stream=None):
-    """Gradients (4481) and the batch's sum of squared errors, as a device float tensor."""
+def fst_mlp_grad(c: Corrector, x, y, z, target, idx, stream=None, fp32=False):
+    """Gradients (4481) and the batch's sum of squared errors, as a device float tensor
+    (fp32: the reference mode with the 64 x 64 layer in FP32, fst_mlp_grad_fp32)."""
     torch = _torch()
     batch = idx.numel()
     ws = _workspace(int(_fn["fst_mlp_grad_workspace_bytes"](batch)), x.device)
     g = torch.empty(MLP_PARAMS + 1, dtype=torch.float32, device=x.device)
-    _check(_fn["fst_mlp_grad"](c.handle, _dtype_code(x), x.numel(), _dev_ptr(x), _dev_ptr(y), _dev_ptr(z),
+    _check(_fn["fst_mlp_grad_fp32" if fp32 else "fst_mlp_grad"](c.handle, _dtype_code(x), x.numel(), _dev_ptr(x), _dev_ptr(y), _dev_ptr(z),
                                _dev_ptr(target), _dev_ptr(idx), batch, _dev_ptr(g), _dev_ptr(ws), ws.numel(),
                                _stream(stream)))
     return g

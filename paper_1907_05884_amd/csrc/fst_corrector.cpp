@@ -213,9 +213,9 @@ fst_status fst_eval_corrected(const fst_model* m, const fst_corrector* c, int32_
   return fst_corrector_apply(c, dtype, n, x, y, z, out, stream);
 }
 
-fst_status fst_mlp_grad(const fst_corrector* c, int32_t dtype, int64_t n, const void* x, const void* y, const void* z,
-                        const float* target, const int32_t* idx, int32_t batch, float* grad_out, void* ws,
-                        size_t ws_bytes, void* stream) {
+static fst_status mlp_grad_impl(const fst_corrector* c, int32_t dtype, int64_t n, const void* x, const void* y,
+                                const void* z, const float* target, const int32_t* idx, int32_t batch,
+                                float* grad_out, void* ws, size_t ws_bytes, void* stream, bool fp32) {
   FST_TRY
   fst::set_last_error("");
   if (!c) fst::fail(FST_E_INVAL, "null corrector");
@@ -224,10 +224,23 @@ fst_status fst_mlp_grad(const fst_corrector* c, int32_t dtype, int64_t n, const 
   if (!x || !y || !z || !target || !idx || !grad_out || !ws) fst::fail(FST_E_INVAL, "null argument");
   std::vector<float> P = c->P;
   fst::MlpAdam opt;
+  opt.fp32 = fp32;
   fst::mlp_train(dtype, c->lo, c->hi, n, x, y, z, target, idx, batch, 0, 0, 0, opt, P, grad_out, nullptr, ws,
                  ws_bytes, stream);
   return FST_OK;
   FST_CATCH
+}
+
+fst_status fst_mlp_grad(const fst_corrector* c, int32_t dtype, int64_t n, const void* x, const void* y, const void* z,
+                        const float* target, const int32_t* idx, int32_t batch, float* grad_out, void* ws,
+                        size_t ws_bytes, void* stream) {
+  return mlp_grad_impl(c, dtype, n, x, y, z, target, idx, batch, grad_out, ws, ws_bytes, stream, false);
+}
+
+fst_status fst_mlp_grad_fp32(const fst_corrector* c, int32_t dtype, int64_t n, const void* x, const void* y,
+                             const void* z, const float* target, const int32_t* idx, int32_t batch,
+                             float* grad_out, void* ws, size_t ws_bytes, void* stream) {
+  return mlp_grad_impl(c, dtype, n, x, y, z, target, idx, batch, grad_out, ws, ws_bytes, stream, true);
 }
 
 size_t fst_mlp_grad_workspace_bytes(int32_t batch) { return fst::mlp_train_workspace_bytes(batch); }

@@ -17,6 +17,7 @@ constexpr int kMlpParams = 4481;
 
 struct MlpAdam {
   double lr = 1e-3, beta1 = 0.9, beta2 = 0.999, eps = 1e-8;
+  bool fp32 = false;   // the 64 x 64 layer in FP32 (reference mode) instead of BF16 MFMA
 };
 
 struct CorrectorDeviceCache {

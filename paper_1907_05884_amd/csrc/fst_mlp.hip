@@ -62,7 +62,10 @@ struct MlpTrainArgs {
   float* partial;          // [gridDim.x][RS]
 };
 
-template <typename TIn>
+// F32: the 64 x 64 layer in FP32 on the VALU from the FP32 master weights, activations kept in
+// FP32 (the reference mode of the kernel, for checking the gradients against an FP64 oracle
+// without the BF16 roundings); otherwise BF16 operands on MFMA as described above.
+template <typename TIn, bool F32>
 __global__ __launch_bounds__(256) void k_mlp_fwdbwd(MlpTrainArgs<TIn> a) {
   __shared__ float sP[kMlpParams];
   __shared__ __align__(16) __bf16 sW2[H][H + 8];
@@ -104,21 +107,37 @@ __global__ __launch_bounds__(256) void k_mlp_fwdbwd(MlpTrainArgs<TIn> a) {
     for (int kb = 0; kb < 2; ++kb) {
       int h = kb * 32 + g * 8 + j;
       float z1 = W1[h * 3 + 0] * xi[0] + W1[h * 3 + 1] * xi[1] + W1[h * 3 + 2] * xi[2] + b1[h];
-      __bf16 hb = (__bf16)silu(z1);
-      if (kb == 0) B0[j] = hb; else B1[j] = hb;
-      sa1[p][h] = (float)hb;
+      if (F32) {
+        sa1[p][h] = silu(z1);
+      } else {
+        __bf16 hb = (__bf16)silu(z1);
+        if (kb == 0) B0[j] = hb; else B1[j] = hb;
+        sa1[p][h] = (float)hb;
+      }
     }
   }
-  // layer 2 on MFMA, then the output layer
+  if (F32) __syncthreads();   // every hidden value of the point before layer 2 reads them
+  const float* W2f = sP + kOffW2;   // [o][i], FP32 master weights
+  // layer 2 (MFMA, or FP32 on the VALU), then the output layer
   float s2d[4][4];
   float ypart = 0.f;
 #pragma unroll
   for (int ob = 0; ob < 4; ++ob) {
-    bf16x8 A0 = *reinterpret_cast<const bf16x8*>(&sW2[ob * 16 + li][g * 8]);
-    bf16x8 A1 = *reinterpret_cast<const bf16x8*>(&sW2[ob * 16 + li][32 + g * 8]);
     floatx4 acc = floatx4{0, 0, 0, 0};
-    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A0, B0, acc, 0, 0, 0);
-    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A1, B1, acc, 0, 0, 0);
+    if (F32) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int o = ob * 16 + 4 * g + v;
+        float s = 0.f;
+        for (int i = 0; i < H; ++i) s += W2f[o * H + i] * sa1[p][i];
+        acc[v] = s;
+      }
+    } else {
+      bf16x8 A0 = *reinterpret_cast<const bf16x8*>(&sW2[ob * 16 + li][g * 8]);
+      bf16x8 A1 = *reinterpret_cast<const bf16x8*>(&sW2[ob * 16 + li][32 + g * 8]);
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A0, B0, acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A1, B1, acc, 0, 0, 0);
+    }
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       int o = ob * 16 + 4 * g + v;
@@ -146,20 +165,32 @@ __global__ __launch_bounds__(256) void k_mlp_fwdbwd(MlpTrainArgs<TIn> a) {
       sdz2[p][o] = dy * W3[o] * s2d[ob][v];
     }
   __syncthreads();
-  // input gradient of layer 2 on MFMA: da1[i][p] = sum_o W2[o][i] dz2[o][p]
+  // input gradient of layer 2 (MFMA, or FP32 on the VALU): da1[i][p] = sum_o W2[o][i] dz2[o][p]
   bf16x8 D0, D1;
+  if (!F32) {
 #pragma unroll
-  for (int j = 0; j < 8; ++j) {
-    D0[j] = (__bf16)sdz2[p][g * 8 + j];
-    D1[j] = (__bf16)sdz2[p][32 + g * 8 + j];
+    for (int j = 0; j < 8; ++j) {
+      D0[j] = (__bf16)sdz2[p][g * 8 + j];
+      D1[j] = (__bf16)sdz2[p][32 + g * 8 + j];
+    }
   }
 #pragma unroll
   for (int ib = 0; ib < 4; ++ib) {
-    bf16x8 A0 = *reinterpret_cast<const bf16x8*>(&sW2T[ib * 16 + li][g * 8]);
-    bf16x8 A1 = *reinterpret_cast<const bf16x8*>(&sW2T[ib * 16 + li][32 + g * 8]);
     floatx4 acc = floatx4{0, 0, 0, 0};
-    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A0, D0, acc, 0, 0, 0);
-    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A1, D1, acc, 0, 0, 0);
+    if (F32) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = ib * 16 + 4 * g + v;
+        float s = 0.f;
+        for (int o = 0; o < H; ++o) s += W2f[o * H + i] * sdz2[p][o];
+        acc[v] = s;
+      }
+    } else {
+      bf16x8 A0 = *reinterpret_cast<const bf16x8*>(&sW2T[ib * 16 + li][g * 8]);
+      bf16x8 A1 = *reinterpret_cast<const bf16x8*>(&sW2T[ib * 16 + li][32 + g * 8]);
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A0, D0, acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A1, D1, acc, 0, 0, 0);
+    }
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       int h = ib * 16 + 4 * g + v;
@@ -370,6 +401,7 @@ static void train_t(const double lo[3], const double hi[3], int64_t n, const voi
                     int64_t steps, uint64_t seed, const MlpAdam& opt, std::vector<float>& P, float* grad_out_dev,
                     std::vector<float>* losses, void* ws, size_t ws_bytes, void* stream) {
   if (ws_bytes < mlp_train_workspace_bytes(batch)) fail(FST_E_NOMEM, "corrector: workspace too small");
+  const bool f32 = opt.fp32;
   const int nwg = (batch + PTS - 1) / PTS;
   char* base = (char*)ws;
   float* partial = (float*)base;
@@ -425,7 +457,10 @@ static void train_t(const double lo[3], const double hi[3], int64_t n, const voi
   if (losses) losses->clear();
   for (int64_t s = 0; s < nsteps; ++s) {
     ta.step = first_step + s;
-    hipLaunchKernelGGL((k_mlp_fwdbwd<TIn>), dim3((unsigned)nwg), dim3(256), 0, Sm(stream), ta);
+    if (f32)
+      hipLaunchKernelGGL((k_mlp_fwdbwd<TIn, true>), dim3((unsigned)nwg), dim3(256), 0, Sm(stream), ta);
+    else
+      hipLaunchKernelGGL((k_mlp_fwdbwd<TIn, false>), dim3((unsigned)nwg), dim3(256), 0, Sm(stream), ta);
     check_launch_m("k_mlp_fwdbwd");
     aa.update = steps > 0 ? 1 : 0;
     aa.grad_out = steps > 0 ? nullptr : grad_out_dev;

@@ -4,7 +4,9 @@ Tolerances: the 64 x 64 layer runs on BF16 MFMA (weights and activations rounded
 unit roundoff 2^-8, FP32 accumulation).  The oracle is given the same BF16-rounded W2, so the
 remaining differences come from rounding the hidden activations and the layer-2 error
 signal: per-tensor relative L2 errors are bounded by a few unit roundoffs, stated below as
-2e-2 for the first layer (two rounded products away from the loss) and 1e-2 elsewhere."""
+2e-2 for the first layer (two rounded products away from the loss) and 1e-2 elsewhere.  The
+kernel's FP32 reference mode (fst_mlp_grad_fp32: the 64 x 64 layer in FP32, nothing rounded
+to BF16) matches the oracle's gradients to 1e-5 per tensor."""
 import numpy as np
 import pytest
 
@@ -141,3 +143,32 @@ def test_adam_steps_match_oracle(dev):
     assert big.sum() > 100
     assert rel_l2(d_gpu[big], d_ref[big]) <= 0.1
     assert sd == pytest.approx(e.std(), rel=1e-4)
+
+
+def test_gradients_fp32_mode_match_oracle(dev):
+    # the reference mode of the training kernel (64 x 64 layer in FP32, no BF16 rounding of W2 or
+    # of the activations) against the FP64 oracle: FP32 arithmetic throughout, per-point terms
+    # summed over 64-point tiles and then over the tiles in FP32, so each gradient entry carries
+    # a few units of 2^-24 of the sum of its terms' magnitudes
+    rng = np.random.default_rng(13)
+    p = mlp.init_params(13)
+    for k in p:
+        p[k] = p[k] + 0.05 * rng.standard_normal(p[k].shape)
+    flat = mlp.flatten(p).astype(np.float32)
+    lo, hi = (0.0, 0.0, 0.0), (4.0, 1.0, 1.0)
+    n, B = 5000, 700
+    pts = (np.asarray(lo) + (np.asarray(hi) - np.asarray(lo)) * rng.random((n, 3))).astype(np.float32)
+    t = rng.standard_normal(n).astype(np.float32)
+    idx = rng.integers(0, n, B).astype(np.int32)
+    c = fst.fst_corrector_from_params(lo, hi, flat, 1.0)
+    x, y, z = [D(pts[:, k], dev) for k in range(3)]
+    g = fst.fst_mlp_grad(c, x, y, z, D(t, dev), D(idx, dev), fp32=True).cpu().numpy().astype(np.float64)
+    xi = 2.0 * (pts[idx].astype(np.float64) - np.asarray(lo)) / (np.asarray(hi) - np.asarray(lo)) - 1.0
+    loss, gr = mlp.loss_and_grads(mlp.unflatten(flat.astype(np.float64)), xi, t[idx].astype(np.float64))
+    ref = mlp.flatten(gr)
+    for name, (a, b) in {"W1": (0, 192), "b1": (192, 256), "W2": (256, 4352), "b2": (4352, 4416),
+                         "W3": (4416, 4480), "b3": (4480, 4481)}.items():
+        err = rel_l2(g[a:b], ref[a:b])
+        print(f"fp32 mode {name}: rel-L2 {err:.2e}", flush=True)
+        assert err <= 1e-5, name
+    assert g[4481] / B == pytest.approx(loss, rel=1e-5)
