@@ -110,7 +110,10 @@ __global__ __launch_bounds__(FM_THREADS) __attribute__((amdgpu_waves_per_eu(4)))
   __shared__ float sC[D][4 * KS][32];
   __shared__ float sPark[FM_WAVES][FM_PARK][D][64];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, li = lane & 15, g = lane >> 4;
-  for (int e = threadIdx.x; e < D * 4 * KS * 32; e += FM_THREADS) {
+  static_assert(D * 4 * KS * 32 % FM_THREADS == 0, "staging loop");
+#pragma unroll   // all loads issued before the first wait
+  for (int e0 = 0; e0 < D * 4 * KS * 32; e0 += FM_THREADS) {
+    const int e = e0 + threadIdx.x;
     const int k = e / (4 * KS * 32), m = (e / 32) % (4 * KS), j = e % 32;
     sC[k][m][j ^ (16 * ((m >> 1) & 1))] =
         (m < a.nb[k] && j < a.rank[k]) ? (float)(fm_scale_table[m] * a.coefs[(k * kMaxBasis + m) * kMaxRank + j]) : 0.0f;
