@@ -22,13 +22,22 @@
 //                        every 512 rows (16 MFMA additions to the leading sum, as in the FP32
 //                        Gram)
 //
-// Tiles are handed out in groups of 4 x 8 (four row blocks, eight column blocks), one group
-// per XCD per round of 256 workgroups, so the 32 workgroups that share an XCD's L2 at a time
-// read 12 blocks of design columns instead of up to 64.
+// Tiles are handed out in groups of GR x (32 / GR) (GR row blocks, 32 / GR column blocks), one
+// group per XCD per round of 256 workgroups, so the 32 workgroups that share an XCD's L2 at a
+// time read GR + 32 / GR blocks of design columns instead of up to 64 (12 for 4 x 8).  The
+// group shape, and for the batched launch the choice between these groups and plain triangle
+// order, is picked per shape by a small autotuner: every candidate computes the same G bit for
+// bit (only the tile-to-workgroup order differs), so the first call of a shape times each
+// candidate on the caller's data and keeps the fastest, in memory and, when the environment
+// names a file in FST_TUNE_FILE, in that JSON object keyed by shape for later processes.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -300,24 +309,38 @@ __device__ __forceinline__ void split_tile(const SplitTile& a,
 }
 
 
-template <class SC>
-__global__ __launch_bounds__(SG_THREADS) void k_gram_split(SplitGramArgs a) {
-  __shared__ __align__(16) typename SC::H bufA[SC::NT][2 * SG_TILE][SC::KC];
-  __shared__ __align__(16) typename SC::H bufB[SC::NT][2 * SG_TILE][SC::KC];
-  // tile of this workgroup: round b / 256, group (round, XCD b % 8), slot (b % 256) / 8 of 32
-  const int64_t bid = blockIdx.x;
-  int64_t rest = (bid >> 8) * 8 + (bid & 7);
-  const int slot = (int)((bid & 255) >> 3);
-  const int64_t nt = a.nt;
+// Workgroup slot `local` (counted from a multiple of 256) -> lower-triangle tile (bi, bj) of an
+// nt x nt tile grid in GR x (32 / GR) groups: round local / 256, XCD local % 8, slot
+// (local % 256) / 8 of the group's 32.  False for slots past the triangle.
+__device__ __forceinline__ bool group_tile(int64_t local, int64_t nt, int GR, int64_t& bi, int64_t& bj) {
+  const int GC = 32 / GR;
+  int64_t rest = (local >> 8) * 8 + (local & 7);
+  const int slot = (int)((local & 255) >> 3);
   int64_t BI = 0;
   for (;; ++BI) {
-    if (4 * BI >= nt) return;
-    const int64_t ngr = min(4 * BI + 3, nt - 1) / 8 + 1;   // groups in group row BI
+    if (GR * BI >= nt) return false;
+    const int64_t ngr = min(GR * BI + GR - 1, nt - 1) / GC + 1;   // groups in group row BI
     if (rest < ngr) break;
     rest -= ngr;
   }
-  const int64_t bi = 4 * BI + slot / 8, bj = 8 * rest + slot % 8;
-  if (bi >= nt || bj > bi) return;
+  bi = GR * BI + slot / GC;
+  bj = GC * rest + slot % GC;
+  return bi < nt && bj <= bi;
+}
+// workgroup slots of that order: 256 per round of eight groups
+static int64_t group_slots(int64_t nt, int GR) {
+  const int GC = 32 / GR;
+  int64_t groups = 0;
+  for (int64_t BI = 0; GR * BI < nt; ++BI) groups += std::min(GR * BI + GR - 1, nt - 1) / GC + 1;
+  return (groups + 7) / 8 * 256;
+}
+
+template <class SC, int GR>
+__global__ __launch_bounds__(SG_THREADS) void k_gram_split(SplitGramArgs a) {
+  __shared__ __align__(16) typename SC::H bufA[SC::NT][2 * SG_TILE][SC::KC];
+  __shared__ __align__(16) typename SC::H bufB[SC::NT][2 * SG_TILE][SC::KC];
+  int64_t bi, bj;
+  if (!group_tile(blockIdx.x, a.nt, GR, bi, bj)) return;
   SplitTile t;
   t.plane0 = a.plane0;
   t.plane_stride = a.plane_stride;
@@ -332,9 +355,6 @@ __global__ __launch_bounds__(SG_THREADS) void k_gram_split(SplitGramArgs a) {
   split_tile<SC>(t, bufA, bufB);
 }
 
-// Several variables in one launch: workgroup b takes global tile b of a list in which each
-// variable's lower-triangle tiles follow the previous variable's (tile0 ascending, larger
-// variables first so that the small ones fill the end of the launch).
 struct SplitVar {
   const void* plane0;
   int64_t plane_stride;
@@ -343,7 +363,9 @@ struct SplitVar {
   double unscale;
 };
 
-template <class SC>
+// GR = 0: each variable's tiles in triangle order; GR > 0: in the groups above, each variable's
+// slots starting at a multiple of 256 (tile0), so the slot's XCD is that of the workgroup
+template <class SC, int GR>
 __global__ __launch_bounds__(SG_THREADS) void k_gram_split_batched(const SplitVar* __restrict__ vars, int nvars,
                                                                    int32_t fold) {
   __shared__ __align__(16) typename SC::H bufA[SC::NT][2 * SG_TILE][SC::KC];
@@ -356,7 +378,12 @@ __global__ __launch_bounds__(SG_THREADS) void k_gram_split_batched(const SplitVa
   }
   const SplitVar& v = vars[lo];
   int64_t bi, bj;
-  tri_tile(tt - v.tile0, bi, bj);
+  if (GR == 0) {
+    tri_tile(tt - v.tile0, bi, bj);
+  } else {
+    const int64_t nt = (v.R + SG_TILE - 1) / SG_TILE;
+    if (!group_tile(tt - v.tile0, nt, GR, bi, bj)) return;
+  }
   SplitTile t;
   t.plane0 = v.plane0;
   t.plane_stride = v.plane_stride;
@@ -369,6 +396,135 @@ __global__ __launch_bounds__(SG_THREADS) void k_gram_split_batched(const SplitVa
   t.accumulate = 0;
   t.unscale = v.unscale;
   split_tile<SC>(t, bufA, bufB);
+}
+
+// ------------------------------------------------------------------------------ tile-order autotuner
+// Candidates: single Gram, groups of 2 x 16, 4 x 8, 8 x 4 (index 0, 1, 2); batched Gram, triangle
+// order or groups of 4 x 8 (index 0, 1).  Keys: kind, precision, tile-grid size (log2 buckets
+// for the batched launch), padded row count bucket, architecture.
+static const int kSingleGR[3] = {2, 4, 8};
+static const int kBatchedGR[2] = {0, 4};
+struct SplitTuner {
+  std::mutex mu;
+  bool loaded = false;
+  std::string path;   // the file the choices were loaded from ("" for none)
+  std::map<std::string, int> best;
+};
+static SplitTuner& tuner() {
+  static SplitTuner t;
+  return t;
+}
+static const char* tune_file() {
+  const char* f = std::getenv("FST_TUNE_FILE");
+  return (f && *f) ? f : nullptr;
+}
+// the file is a flat JSON object {"key": index, ...} written by tuner_store
+static void tuner_load_locked(SplitTuner& t) {
+  const char* path = tune_file();
+  const std::string cur = path ? path : "";
+  if (t.loaded && cur == t.path) return;
+  // first use, or FST_TUNE_FILE names another file now: start from that file's choices
+  t.loaded = true;
+  t.path = cur;
+  t.best.clear();
+  if (!path) return;
+  FILE* f = std::fopen(path, "rb");
+  if (!f) return;
+  std::string txt;
+  char buf[4096];
+  size_t got;
+  while ((got = std::fread(buf, 1, sizeof(buf), f)) > 0) txt.append(buf, got);
+  std::fclose(f);
+  size_t pos = 0;
+  for (;;) {
+    const size_t k0 = txt.find('"', pos);
+    if (k0 == std::string::npos) break;
+    const size_t k1 = txt.find('"', k0 + 1);
+    if (k1 == std::string::npos) break;
+    const size_t colon = txt.find(':', k1);
+    if (colon == std::string::npos) break;
+    char* end = nullptr;
+    const long val = std::strtol(txt.c_str() + colon + 1, &end, 10);
+    if (end == txt.c_str() + colon + 1) break;
+    t.best[txt.substr(k0 + 1, k1 - k0 - 1)] = (int)val;
+    pos = (size_t)(end - txt.c_str());
+  }
+}
+static void tuner_save_locked(const SplitTuner& t) {
+  const char* path = tune_file();
+  if (!path) return;
+  const std::string tmp = std::string(path) + ".tmp";
+  FILE* f = std::fopen(tmp.c_str(), "wb");
+  if (!f) return;
+  std::fputs("{\n", f);
+  size_t i = 0;
+  for (const auto& kv : t.best)
+    std::fprintf(f, "  \"%s\": %d%s\n", kv.first.c_str(), kv.second, ++i < t.best.size() ? "," : "");
+  std::fputs("}\n", f);
+  std::fclose(f);
+  std::rename(tmp.c_str(), path);
+}
+static int tuner_lookup(const std::string& key) {
+  SplitTuner& t = tuner();
+  std::lock_guard<std::mutex> lk(t.mu);
+  tuner_load_locked(t);
+  auto it = t.best.find(key);
+  return it == t.best.end() ? -1 : it->second;
+}
+static void tuner_store(const std::string& key, int v) {
+  SplitTuner& t = tuner();
+  std::lock_guard<std::mutex> lk(t.mu);
+  tuner_load_locked(t);
+  t.best[key] = v;
+  tuner_save_locked(t);
+}
+static std::string arch_name() {
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, current_device()) != hipSuccess) return "gfx";
+  std::string a = prop.gcnArchName;
+  const size_t c = a.find(':');
+  return c == std::string::npos ? a : a.substr(0, c);
+}
+static int log2_bucket(int64_t x) {
+  int b = 0;
+  while ((int64_t(1) << (b + 1)) <= x) ++b;
+  return b;
+}
+// may the tuner time candidates on this stream (not while a graph is being captured)
+static bool can_time(void* stream) {
+  hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(S(stream), &st) != hipSuccess) return false;
+  return st == hipStreamCaptureStatusNone;
+}
+// runs candidate `run(i)` for i < n once each, timed with events on the stream; returns the fastest
+template <class F>
+static int time_candidates(int n, F run, void* stream) {
+  hipEvent_t e0, e1;
+  check_hip(hipEventCreate(&e0), "hipEventCreate");
+  check_hip(hipEventCreate(&e1), "hipEventCreate");
+  int best = 0;
+  float best_ms = 0.0f;
+  for (int i = 0; i < n; ++i) {
+    check_hip(hipEventRecord(e0, S(stream)), "hipEventRecord");
+    run(i);
+    check_hip(hipEventRecord(e1, S(stream)), "hipEventRecord");
+    check_hip(hipEventSynchronize(e1), "hipEventSynchronize");
+    float ms = 0.0f;
+    check_hip(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+    if (i == 0 || ms < best_ms) {
+      best = i;
+      best_ms = ms;
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  return best;
+}
+
+static std::string split_key(int batched, int gram_prec, int64_t tiles_or_nt, int64_t Sp) {
+  return std::string(batched ? "split_batched" : "split") + ":" + std::to_string(gram_prec) + ":" +
+         (batched ? "tiles2^" + std::to_string(log2_bucket(tiles_or_nt)) : "nt" + std::to_string(tiles_or_nt)) +
+         ":rows2^" + std::to_string(log2_bucket(Sp)) + ":" + arch_name();
 }
 
 int split_terms(int gram_prec) {
@@ -446,10 +602,23 @@ void gram_split(const fst_model* m, int gram_prec, int64_t mrows, const float* U
 }
 
 template <class SC>
-static void launch_split_batched(const SplitVar* vars, int nvars, int64_t tiles, void* stream) {
-  hipLaunchKernelGGL((k_gram_split_batched<SC>), dim3((unsigned)tiles), dim3(SG_THREADS), 0, S(stream), vars, nvars,
-                     (int32_t)(512 / SC::KC));
+static void launch_split_batched(const SplitVar* vars, int nvars, int64_t slots, int order, void* stream) {
+  const dim3 grid((unsigned)slots), block(SG_THREADS);
+  const int32_t fold = 512 / SC::KC;
+  if (kBatchedGR[order] == 0)
+    hipLaunchKernelGGL((k_gram_split_batched<SC, 0>), grid, block, 0, S(stream), vars, nvars, fold);
+  else
+    hipLaunchKernelGGL((k_gram_split_batched<SC, 4>), grid, block, 0, S(stream), vars, nvars, fold);
   check_launch("k_gram_split_batched");
+}
+static void launch_split_batched_prec(int gram_prec, const SplitVar* vars, int nvars, int64_t slots, int order,
+                                      void* stream) {
+  if (gram_prec == FST_GRAM_F16X2)
+    launch_split_batched<SchemeF16x2>(vars, nvars, slots, order, stream);
+  else if (gram_prec == FST_GRAM_BF16X2)
+    launch_split_batched<SchemeBF16x2>(vars, nvars, slots, order, stream);
+  else
+    launch_split_batched<SchemeBF16x3>(vars, nvars, slots, order, stream);
 }
 
 size_t gram_split_batched_min_bytes(const std::vector<const fst_model*>& models, int gram_prec, int64_t mrows) {
@@ -495,24 +664,53 @@ void gram_split_batched(const std::vector<const fst_model*>& models, const std::
       v.G = G[order[i]];
       v.R = m->R();
       v.Sp = Sp;
-      v.tile0 = tiles;
+      v.tile0 = 0;
       v.unscale = 1.0 / ((double)scale * (double)scale);
       const int64_t nt = (v.R + SG_TILE - 1) / SG_TILE;
       tiles += nt * (nt + 1) / 2;
       vars.push_back(v);
       used += need;
     }
-    if (tiles >= (int64_t(1) << 31)) fail(FST_E_UNSUPPORTED, "batched split Gram: too many tiles");
-    copy_h2d(d_vars, vars.data(), sizeof(SplitVar) * vars.size(), stream);
-    if (gram_prec == FST_GRAM_F16X2)
-      launch_split_batched<SchemeF16x2>(d_vars, (int)vars.size(), tiles, stream);
-    else if (gram_prec == FST_GRAM_BF16X2)
-      launch_split_batched<SchemeBF16x2>(d_vars, (int)vars.size(), tiles, stream);
-    else
-      launch_split_batched<SchemeBF16x3>(d_vars, (int)vars.size(), tiles, stream);
+    // the variables' first workgroup slots for tile order `o` (group orders start each variable
+    // at a multiple of 256), uploaded; returns the launch size
+    auto table = [&](int o) {
+      int64_t slots = 0;
+      for (SplitVar& v : vars) {
+        const int64_t nt = (v.R + SG_TILE - 1) / SG_TILE;
+        v.tile0 = slots;
+        slots += kBatchedGR[o] == 0 ? nt * (nt + 1) / 2 : group_slots(nt, kBatchedGR[o]);
+      }
+      if (slots >= (int64_t(1) << 31)) fail(FST_E_UNSUPPORTED, "batched split Gram: too many tiles");
+      copy_h2d(d_vars, vars.data(), sizeof(SplitVar) * vars.size(), stream);
+      return slots;
+    };
+    auto run = [&](int o) {
+      const int64_t slots = table(o);
+      launch_split_batched_prec(gram_prec, d_vars, (int)vars.size(), slots, o, stream);
+    };
+    const std::string key = split_key(1, gram_prec, tiles, Sp);
+    const int known = tuner_lookup(key);
+    if (known >= 0 && known < 2) {
+      run(known);
+    } else if (can_time(stream)) {
+      // every candidate writes the same G bit for bit, so the last one timed leaves the result
+      tuner_store(key, time_candidates(2, run, stream));
+    } else {
+      run(1);
+    }
     stream_sync(stream);   // the planes and the table are reused by the next group
     i0 = i;
   }
+}
+
+template <class SC>
+static void launch_split_single(int GR, dim3 grid, const SplitGramArgs& ga, void* stream) {
+  if (GR == 2)
+    hipLaunchKernelGGL((k_gram_split<SC, 2>), grid, dim3(SG_THREADS), 0, S(stream), ga);
+  else if (GR == 4)
+    hipLaunchKernelGGL((k_gram_split<SC, 4>), grid, dim3(SG_THREADS), 0, S(stream), ga);
+  else
+    hipLaunchKernelGGL((k_gram_split<SC, 8>), grid, dim3(SG_THREADS), 0, S(stream), ga);
 }
 
 void gram_split_rows(int gram_prec, void* const* plane, int64_t R, int64_t Sp, double* G, double unscale,
@@ -534,21 +732,26 @@ void gram_split_rows(int gram_prec, void* const* plane, int64_t R, int64_t Sp, d
   ga.nt = (int32_t)nt;
   ga.unscale = unscale;
   ga.accumulate = accumulate ? 1 : 0;
-  int64_t groups = 0;
-  for (int64_t BI = 0; 4 * BI < nt; ++BI) groups += std::min(4 * BI + 3, nt - 1) / 8 + 1;
-  const int64_t rounds = (groups + 7) / 8;
-  if (rounds * 256 >= (int64_t(1) << 31)) fail(FST_E_UNSUPPORTED, "split Gram: too many tiles");
-  const dim3 grid((unsigned)(rounds * 256));
   // FP32 sums over 512 rows (16 MFMA accumulations into the leading sum) before each fold
-  if (gram_prec == FST_GRAM_F16X2) {
-    ga.fold = 512 / SchemeF16x2::KC;
-    hipLaunchKernelGGL((k_gram_split<SchemeF16x2>), grid, dim3(SG_THREADS), 0, S(stream), ga);
-  } else if (gram_prec == FST_GRAM_BF16X2) {
-    ga.fold = 512 / SchemeBF16x2::KC;
-    hipLaunchKernelGGL((k_gram_split<SchemeBF16x2>), grid, dim3(SG_THREADS), 0, S(stream), ga);
+  ga.fold = 512 / (NT == 3 ? SchemeBF16x3::KC : SchemeF16x2::KC);
+  auto run = [&](int c) {
+    const int GR = kSingleGR[c];
+    const int64_t slots = group_slots(nt, GR);
+    if (slots >= (int64_t(1) << 31)) fail(FST_E_UNSUPPORTED, "split Gram: too many tiles");
+    const dim3 grid((unsigned)slots);
+    if (gram_prec == FST_GRAM_F16X2) launch_split_single<SchemeF16x2>(GR, grid, ga, stream);
+    else if (gram_prec == FST_GRAM_BF16X2) launch_split_single<SchemeBF16x2>(GR, grid, ga, stream);
+    else launch_split_single<SchemeBF16x3>(GR, grid, ga, stream);
+  };
+  const std::string key = split_key(0, gram_prec, nt, Sp);
+  const int known = tuner_lookup(key);
+  if (known >= 0 && known < 3) {
+    run(known);
+  } else if (!accumulate && can_time(stream)) {
+    // every candidate writes the same G bit for bit, so the last one timed leaves the result
+    tuner_store(key, time_candidates(3, run, stream));
   } else {
-    ga.fold = 512 / SchemeBF16x3::KC;
-    hipLaunchKernelGGL((k_gram_split<SchemeBF16x3>), grid, dim3(SG_THREADS), 0, S(stream), ga);
+    run(1);
   }
   check_launch("k_gram_split");
 }

@@ -109,3 +109,31 @@ def test_refit_split_gram_three_steps_matches_fp64(dev, name, code):
         errs.append(rel_l2(out.core, alpha_o))
     assert errs[0] <= 1e-4, errs
     assert errs[1] <= 1e-6, errs
+
+
+@pytest.mark.parametrize("name,code", SPLITS)
+def test_tile_order_autotuner(dev, name, code, tmp_path, monkeypatch):
+    # the split Gram's tile-group shape is picked per shape by timing the candidates on the first
+    # call; with FST_TUNE_FILE the choice is kept in that JSON object.  Every candidate must give
+    # the same G bit for bit: forcing each one through the file checks it.
+    import json
+    om, gm, pts = _case(41, (9, 10, 7), (11, 11, 11), 5000)    # R = 630: 5 x 5 tiles
+    U, _ = fst.fst_factor_eval(gm, *[D(pts[:, k], dev) for k in range(3)])
+    path = tmp_path / "tune.json"
+    monkeypatch.setenv("FST_TUNE_FILE", str(path))
+    G1, _ = fst.fst_gram(gm, U, gram_prec=code)        # tunes and records
+    G2, _ = fst.fst_gram(gm, U, gram_prec=code)        # takes the recorded choice
+    torch.cuda.synchronize()
+    tab = json.loads(path.read_text())
+    keys = [k for k in tab if k.startswith(f"split:{code}:nt5:")]
+    assert len(keys) == 1 and tab[keys[0]] in (0, 1, 2), tab
+    assert torch.equal(torch.tril(G1), torch.tril(G2))
+    for choice in (0, 1, 2):
+        tab[keys[0]] = choice
+        path.write_text(json.dumps(tab))
+        monkeypatch.setenv("FST_TUNE_FILE", str(tmp_path / "other.json"))
+        fst.fst_gram(gm, U, gram_prec=code)            # a call under another file ...
+        monkeypatch.setenv("FST_TUNE_FILE", str(path))
+        Gc, _ = fst.fst_gram(gm, U, gram_prec=code)    # ... makes this one reload the edited file
+        torch.cuda.synchronize()
+        assert torch.equal(torch.tril(Gc), torch.tril(G1)), choice
