@@ -400,10 +400,13 @@ __global__ __launch_bounds__(SG_THREADS) void k_gram_split_batched(const SplitVa
 
 // ------------------------------------------------------------------------------ tile-order autotuner
 // Candidates: single Gram, groups of 2 x 16, 4 x 8, 8 x 4 (index 0, 1, 2); batched Gram, triangle
-// order or groups of 4 x 8 (index 0, 1).  Keys: kind, precision, tile-grid size (log2 buckets
-// for the batched launch), padded row count bucket, architecture.
+// order or groups of 4 x 8, 8 x 4 (index 0, 1, 2).  Untimed calls (under graph capture, or
+// accumulating into G) take 8 x 4, the fastest on a 13824-column Gram of 200k rows.  Keys: kind,
+// precision, tile-grid size (log2 buckets for the batched launch), padded row count bucket,
+// architecture.
 static const int kSingleGR[3] = {2, 4, 8};
-static const int kBatchedGR[2] = {0, 4};
+static const int kBatchedGR[3] = {0, 4, 8};
+constexpr int kDefaultGR = 2;   // index of 8 x 4 in both tables
 struct SplitTuner {
   std::mutex mu;
   bool loaded = false;
@@ -607,8 +610,10 @@ static void launch_split_batched(const SplitVar* vars, int nvars, int64_t slots,
   const int32_t fold = 512 / SC::KC;
   if (kBatchedGR[order] == 0)
     hipLaunchKernelGGL((k_gram_split_batched<SC, 0>), grid, block, 0, S(stream), vars, nvars, fold);
-  else
+  else if (kBatchedGR[order] == 4)
     hipLaunchKernelGGL((k_gram_split_batched<SC, 4>), grid, block, 0, S(stream), vars, nvars, fold);
+  else
+    hipLaunchKernelGGL((k_gram_split_batched<SC, 8>), grid, block, 0, S(stream), vars, nvars, fold);
   check_launch("k_gram_split_batched");
 }
 static void launch_split_batched_prec(int gram_prec, const SplitVar* vars, int nvars, int64_t slots, int order,
@@ -690,13 +695,13 @@ void gram_split_batched(const std::vector<const fst_model*>& models, const std::
     };
     const std::string key = split_key(1, gram_prec, tiles, Sp);
     const int known = tuner_lookup(key);
-    if (known >= 0 && known < 2) {
+    if (known >= 0 && known < 3) {
       run(known);
     } else if (can_time(stream)) {
       // every candidate writes the same G bit for bit, so the last one timed leaves the result
-      tuner_store(key, time_candidates(2, run, stream));
+      tuner_store(key, time_candidates(3, run, stream));
     } else {
-      run(1);
+      run(kDefaultGR);
     }
     stream_sync(stream);   // the planes and the table are reused by the next group
     i0 = i;
@@ -751,7 +756,7 @@ void gram_split_rows(int gram_prec, void* const* plane, int64_t R, int64_t Sp, d
     // every candidate writes the same G bit for bit, so the last one timed leaves the result
     tuner_store(key, time_candidates(3, run, stream));
   } else {
-    run(1);
+    run(kDefaultGR);
   }
   check_launch("k_gram_split");
 }

@@ -229,3 +229,30 @@ def test_batched_split_gram_three_steps_matches_oracle(dev):
         ref = fst.fst_refit_core(host, *case.xyz, case.dv[v], wl.n_samples, wl.seed + v, gram_prec=code,
                                  refine_steps=3)
         assert rel_l2(models[v].core, ref.core) <= 1e-12, v
+
+
+def test_batched_split_gram_tile_orders_agree(dev, tmp_path, monkeypatch):
+    """The batched split Gram's tile order (triangle order, 4 x 8 or 8 x 4 groups) is picked by
+    timing on first use and kept in the JSON file FST_TUNE_FILE names; forcing each order through
+    that file gives the same cores (the Grams agree bit for bit)."""
+    import json
+    wl = datagen.batched(n_vars=4, n=60_000, grid=(16, 16, 16), rmin=4, rmax=12, pmin=11, pmax=19)
+    case = Case(wl, dev, np.float32)
+    code = fst.FST_GRAM_BF16X2
+    base = _params(wl, fst.FST_F32, wl.ranks[0], wl.degrees[0], code, 3)
+    path = tmp_path / "tune.json"
+    monkeypatch.setenv("FST_TUNE_FILE", str(path))
+    first, *_ = fst.fst_fit_batched(base, wl.ranks, wl.degrees, *case.xyz, case.dv)
+    tab = json.loads(path.read_text())
+    keys = [k for k in tab if k.startswith(f"split_batched:{code}:")]
+    assert keys and all(tab[k] in (0, 1, 2) for k in keys), tab
+    for choice in (0, 1, 2):
+        for k in keys:
+            tab[k] = choice
+        path.write_text(json.dumps(tab))
+        monkeypatch.setenv("FST_TUNE_FILE", str(tmp_path / "other.json"))
+        fst.fst_fit_batched(base, wl.ranks[:1], wl.degrees[:1], *case.xyz, case.dv[:1])   # another file ...
+        monkeypatch.setenv("FST_TUNE_FILE", str(path))                                    # ... then reload
+        models, *_ = fst.fst_fit_batched(base, wl.ranks, wl.degrees, *case.xyz, case.dv)
+        for v in range(len(models)):
+            assert rel_l2(models[v].core, first[v].core) <= 1e-12, (choice, v)
