@@ -7,19 +7,28 @@
 // FP32 accumulation): 2 R flop per point, the bulk of the work.  The weighted reduction over
 // (j1, j2), 3 r1 r2 flop per point, runs on the VALU from the MFMA accumulators.
 //
-// Layout (per workgroup of four waves, each wave one 64-point tile per round):
-//   LDS alpha   [r1 r2 padded to 16][r3s]   the core with j3 fastest, r3s = r3 rounded up to
-//                                           4 and to 2 mod 4 (16 consecutive rows read at one
-//                                           column fall in distinct bank pairs)
-//   LDS U3      [64 points][r3s]            factor values of mode 3 (MFMA A operand)
-//   LDS U1T/U2T [r1 | r2][68]               modes 1 and 2, points contiguous (float4 reads)
-// Phase 1: each lane evaluates the Legendre basis and the three factor functions of one
-// point (eq. (2); coefficients staged in LDS, read as broadcasts) and writes them to the tables.
-// Phase 2: for every 16 columns (j1 j2) of T, K = r3 / 4 MFMA steps per 16-point block, then
-// f += u1 u2 T in registers; a 16-lane butterfly sums each point's 16 column partials.
+// Each wave takes one 64-point tile per round; lane l evaluates point l of a tile.
+//   phase 1 (VALU): the factor functions of eq. (2) at the lane's point, the three modes advanced
+//     together one degree per step by the monic Legendre recurrence p_{m+1} = t p_m - beta_m
+//     p_{m-1} (the normalisation c_m of phi_m = c_m p_m is folded into the staged coefficients,
+//     which every lane reads from LDS at the same address);
+//   phase 2 (MFMA): T of the tile, 16 columns (j1 j2) per block, then f += u1 u2 T.
+// The LDS holds one workgroup per CU, so a SIMD runs one wave; the two phases overlap inside
+// the wave instead: the loop over T's column blocks carries the degree steps of the NEXT
+// tile's phase 1 (SB steps per two blocks), so the VALU works while the matrix core runs.
+// U3 reaches the MFMA A operand without LDS: a 4 x 4 transpose of 16-lane blocks
+// (v_permlane16_swap, v_permlane32_swap) turns lane l's u3[4s .. 4s+3] into the operands of
+// the four 16-point blocks.  u1 and u2 go to per-wave LDS tables (points contiguous, float4
+// reads), and a per-column table gives each column's rows of them.
+//
+// LDS: coefficients [3][kMaxBasis][kMaxRank] (scaled by c_m); alpha [r1 r2 padded to 16][r3s]
+// with j3 fastest (r3s = r3 rounded up to 4 and to 2 mod 4, so 16 consecutive rows read at
+// one column fall in distinct bank pairs); the column table [r1 r2 padded]; per wave
+// u1 [r1][68] and u2 [r2][68].
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 
 #include "fst_device.h"
 #include "fst_internal.h"
@@ -36,9 +45,10 @@ struct EvalMfmaArgs {
   const float* core;    // R, C order
   float* out;
   int64_t n, ntiles;
-  int32_t r1, r2, r3, r3s, r12p, residual, rounds;
+  int32_t r1, r2, r3, r3s, r12p, residual, rounds, nst;
   ModeMap<float> map;
-  Recurrence<float> rec;
+  float beta[kMaxBasis];     // beta_m of the monic recurrence (beta_0 = 0)
+  double cscale[kMaxBasis];  // c_m
 };
 
 static inline int em_r3s(int r3) {
@@ -50,127 +60,183 @@ constexpr int EM_CSIZE = 3 * kMaxBasis * kMaxRank;   // coefficient matrices, st
 
 static size_t em_lds_bytes(int r1, int r2, int r3) {
   const size_t r3s = (size_t)em_r3s(r3), r12p = ((size_t)r1 * r2 + 15) / 16 * 16;
-  return sizeof(float) * (EM_CSIZE + r12p * r3s + EM_WAVES * (64 * r3s + (size_t)(r1 + r2) * EM_TSTRIDE));
+  return sizeof(float) * (EM_CSIZE + r12p * r3s + (size_t)EM_WAVES * (r1 + r2) * EM_TSTRIDE) + 8 * r12p;
 }
 
-template <int NP, int RP>
-__global__ __launch_bounds__(EM_THREADS) void k_eval_mfma(EvalMfmaArgs a) {
+// RP: ranks padded to 8 (KS = RP / 4 MFMA k-steps and the factor values held per mode);
+// SB: degree steps of the next tile per two column blocks.
+template <int RP, int SB>
+__global__ __launch_bounds__(EM_THREADS) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_eval_mfma(
+    EvalMfmaArgs a) {
+  constexpr int KS = RP / 4;
   extern __shared__ __align__(16) float em_smem[];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, li = lane & 15, g = lane >> 4;
-  const int r1 = a.r1, r2 = a.r2, r3 = a.r3, r3s = a.r3s;
-  float* sC = em_smem;                                            // [3][kMaxBasis][kMaxRank]
-  float* sAlpha = sC + EM_CSIZE;                                  // [r12p][r3s]
-  float* sW = sAlpha + (size_t)a.r12p * r3s + (size_t)wave * (64 * r3s + (r1 + r2) * EM_TSTRIDE);
-  float* sU3 = sW;                                                 // [64][r3s]
-  float* sU1 = sW + 64 * r3s;                                      // [r1][68]
-  float* sU2 = sU1 + r1 * EM_TSTRIDE;                              // [r2][68]
-  const int R12 = r1 * r2;
+  const int r1 = a.r1, r2 = a.r2, r3 = a.r3, r3s = a.r3s, R12 = r1 * r2, nbs = a.r12p / 16, nst = a.nst;
+  float* sC = em_smem;                                           // [3][kMaxBasis][kMaxRank]
+  float* sAlpha = sC + EM_CSIZE;                                 // [r12p][r3s]
+  int2* sCol = reinterpret_cast<int2*>(sAlpha + (size_t)a.r12p * r3s);   // [r12p]
+  float* sU1 = reinterpret_cast<float*>(sCol + a.r12p) + (size_t)wave * (r1 + r2) * EM_TSTRIDE;   // [r1][68]
+  float* sU2 = sU1 + r1 * EM_TSTRIDE;                                                              // [r2][68]
   for (int e = threadIdx.x; e < a.r12p * r3s; e += EM_THREADS) {
     const int c = e / r3s, j3 = e - c * r3s;
     sAlpha[e] = (c < R12 && j3 < r3) ? a.core[(int64_t)c * r3 + j3] : 0.0f;
   }
-  for (int e = threadIdx.x; e < EM_CSIZE; e += EM_THREADS) sC[e] = a.coefs[e];
-  const int KS = (r3 + 3) / 4;
+  for (int e = threadIdx.x; e < EM_CSIZE; e += EM_THREADS)
+    sC[e] = (float)(a.cscale[(e / kMaxRank) % kMaxBasis] * (double)a.coefs[e]);
+  // columns past r1 r2 point at row 0 of both tables (finite values; their alpha rows are zero)
+  for (int c = threadIdx.x; c < a.r12p; c += EM_THREADS)
+    sCol[c] = c < R12 ? make_int2((c / r2) * EM_TSTRIDE, (c % r2) * EM_TSTRIDE) : make_int2(0, 0);
   __syncthreads();
 
-  for (int rnd = 0; rnd < a.rounds; ++rnd) {
-    const int64_t tile = ((int64_t)rnd * gridDim.x + blockIdx.x) * EM_WAVES + wave;
-    // ---- phase 1: this lane's point
-    {
-      int64_t q = tile * 64 + lane;
-      q = q < a.n ? q : a.n - 1;
-      q = q < 0 ? 0 : q;
-      const int64_t i = a.idx ? (int64_t)a.idx[q] : q;
-      // one mode at a time: basis values, then the factor values (coefficients by scalar loads)
+  // ---- phase 1 state: the lane's point of the tile being evaluated
+  float tt[3], pm[3], pm1[3], u[3][RP];
+  auto start = [&](const float (&c)[3]) {
 #pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        const float c = k == 0 ? a.x[i] : (k == 1 ? a.y[i] : a.z[i]);
-        const float t = (c - a.map.lo[k]) * a.map.scale[k] - 1.0f;
-        const float* Ck = sC + k * kMaxBasis * kMaxRank;   // same address in every lane: broadcast reads
-        float u[RP];
+    for (int k = 0; k < 3; ++k) {
+      tt[k] = (c[k] - a.map.lo[k]) * a.map.scale[k] - 1.0f;
+      pm[k] = 1.0f;
+      pm1[k] = 0.0f;
 #pragma unroll
-        for (int j = 0; j < RP; ++j) u[j] = Ck[j];
-        float pm1 = 1.0f, pm = t * a.rec.a[0];
-#pragma unroll 2
-        for (int m = 1; m < NP; ++m) {
-#pragma unroll
-          for (int j = 0; j < RP; ++j) u[j] += Ck[m * kMaxRank + j] * pm;
-          const float pn = a.rec.a[m] * t * pm - a.rec.b[m] * pm1;
-          pm1 = pm;
-          pm = pn;
-        }
-        if (k == 0) {
-#pragma unroll
-          for (int j = 0; j < RP; ++j)
-            if (j < r1) sU1[j * EM_TSTRIDE + lane] = u[j];
-        } else if (k == 1) {
-#pragma unroll
-          for (int j = 0; j < RP; ++j)
-            if (j < r2) sU2[j * EM_TSTRIDE + lane] = u[j];
-        } else {
-#pragma unroll
-          for (int j = 0; j < RP; ++j)
-            if (j < r3s) sU3[lane * r3s + j] = j < r3 ? u[j] : 0.0f;
-        }
-      }
-      for (int j = RP; j < r3s; ++j) sU3[lane * r3s + j] = 0.0f;
+      for (int j = 0; j < RP; ++j) u[k][j] = 0.0f;
     }
-    __syncthreads();
-    // ---- phase 2: T = U3 alpha^T on MFMA, 16 columns at a time, reduced with u1 u2
-    float av[4][RP / 4];
+  };
+  auto step = [&](int m) {   // degree m of all three modes
+    const float* cm = sC + m * kMaxRank;
+    const float bm = a.beta[m];
 #pragma unroll
-    for (int mb = 0; mb < 4; ++mb)
+    for (int k = 0; k < 3; ++k)
 #pragma unroll
-      for (int s = 0; s < RP / 4; ++s) av[mb][s] = s < KS ? sU3[(16 * mb + li) * r3s + 4 * s + g] : 0.0f;
-    float f[4][4];
+      for (int j = 0; j < RP; ++j) u[k][j] = fmaf(cm[k * kMaxBasis * kMaxRank + j], pm[k], u[k][j]);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const float pn = fmaf(tt[k], pm[k], -bm * pm1[k]);
+      pm1[k] = pm[k];
+      pm[k] = pn;
+    }
+  };
+  // coordinates of the lane's point in the wave's tile of round rnd (clamped into the input)
+  auto load_coords = [&](int rnd, float (&c)[3]) {
+    const int64_t tile = ((int64_t)rnd * gridDim.x + blockIdx.x) * EM_WAVES + wave;
+    const int64_t q = std::min<int64_t>(tile * 64 + lane, a.n - 1);
+    const int64_t i = a.idx ? (int64_t)a.idx[q] : q;
+    c[0] = a.x[i];
+    c[1] = a.y[i];
+    c[2] = a.z[i];
+  };
+  // ---- phase 2 state: A operands of the tile being contracted, the f partials
+  float av[4][KS];
+  // end of a tile's phase 1: u1, u2 to the wave's tables, u3 transposed into the A operands
+  // (lane group mb of register i holds u3[4 s + i] of points 16 mb + li; afterwards register mb of
+  // lane group i holds it, as the A operand of point block mb wants)
+  auto finish = [&]() {
+    __builtin_amdgcn_s_waitcnt(0xC07F);   // earlier reads of the tables done (lgkmcnt(0))
+#pragma unroll
+    for (int j = 0; j < RP; ++j) {
+      if (j < r1) sU1[j * EM_TSTRIDE + lane] = u[0][j];
+      if (j < r2) sU2[j * EM_TSTRIDE + lane] = u[1][j];
+    }
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+      uint32_t x[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) x[i] = __builtin_bit_cast(uint32_t, u[2][4 * s + i]);
+      auto p0 = __builtin_amdgcn_permlane16_swap(x[0], x[1], false, false);
+      auto p1 = __builtin_amdgcn_permlane16_swap(x[2], x[3], false, false);
+      auto q0 = __builtin_amdgcn_permlane32_swap(p0[0], p1[0], false, false);
+      auto q1 = __builtin_amdgcn_permlane32_swap(p0[1], p1[1], false, false);
+      av[0][s] = __builtin_bit_cast(float, (uint32_t)q0[0]);
+      av[2][s] = __builtin_bit_cast(float, (uint32_t)q0[1]);
+      av[1][s] = __builtin_bit_cast(float, (uint32_t)q1[0]);
+      av[3][s] = __builtin_bit_cast(float, (uint32_t)q1[1]);
+    }
+    __builtin_amdgcn_s_waitcnt(0xC07F);   // the tables written before they are read
+    __builtin_amdgcn_wave_barrier();
+  };
+  const int ks3 = (r3 + 3) / 4 - 1;   // last k-step with alpha columns (av is zero past r3)
+  auto block = [&](int nb, floatx4 (&acc)[4]) {
+    const float* bp = sAlpha + (nb * 16 + li) * r3s + g;
+    float b[KS];
+#pragma unroll
+    for (int s = 0; s < KS; ++s) b[s] = bp[4 * std::min(s, ks3)];
+#pragma unroll
+    for (int s = 0; s < KS; ++s)
+#pragma unroll
+      for (int mb = 0; mb < 4; ++mb)
+        acc[mb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[mb][s], b[s], s == 0 ? floatx4{0, 0, 0, 0} : acc[mb], 0, 0, 0);
+  };
+  // scheduling of one block with the VALU work beside it: each MFMA followed by VALU and LDS
+  // reads of the independent work (hints to the instruction scheduler, no effect on results)
+  auto interleave = [&]() {
+#pragma unroll
+    for (int i = 0; i < 4 * KS; ++i) {
+      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);   // MFMA
+      __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);   // LDS read
+      __builtin_amdgcn_sched_group_barrier(0x002, 4, 0);   // VALU
+    }
+  };
+  float f[4][4];
+  auto reduce = [&](const floatx4 (&acc)[4], int nb) {
+    const int2 off = sCol[nb * 16 + li];
+    const float* w1 = sU1 + off.x + 4 * g;
+    const float* w2 = sU2 + off.y + 4 * g;
+#pragma unroll
+    for (int mb = 0; mb < 4; ++mb) {
+      const floatx4 x1 = *reinterpret_cast<const floatx4*>(w1 + 16 * mb);
+      const floatx4 x2 = *reinterpret_cast<const floatx4*>(w2 + 16 * mb);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) f[mb][v] = fmaf(x1[v] * x2[v], acc[mb][v], f[mb][v]);
+    }
+  };
+
+  // prologue: phase 1 of the wave's first tile on its own
+  float cn[3];
+  load_coords(0, cn);
+  start(cn);
+  for (int m = 0; m < nst; ++m) step(m);
+  finish();
+  load_coords(1, cn);
+  // column-block pairs that carry SB degree steps each (the steps left over run after them)
+  const int npair = std::min((nbs - 1) / 2, nst / SB);
+  for (int rnd = 0; rnd < a.rounds; ++rnd) {
+    start(cn);                  // phase 1 of the next tile
+    load_coords(rnd + 2, cn);   // coordinates of the tile after it
 #pragma unroll
     for (int mb = 0; mb < 4; ++mb)
 #pragma unroll
       for (int v = 0; v < 4; ++v) f[mb][v] = 0.0f;
-    // T blocks of 16 columns on MFMA, two in flight: the MFMAs of block nb + 1 are issued before
-    // the VALU reduction of block nb reads its accumulators
-    auto block = [&](int nb, floatx4 (&acc)[4]) {
-#pragma unroll
-      for (int mb = 0; mb < 4; ++mb) acc[mb] = floatx4{0, 0, 0, 0};
-      const float* bp = sAlpha + (nb * 16 + li) * r3s + g;
-#pragma unroll
-      for (int s = 0; s < RP / 4; ++s) {
-        if (s < KS) {
-          const float b = bp[4 * s];
-#pragma unroll
-          for (int mb = 0; mb < 4; ++mb) acc[mb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[mb][s], b, acc[mb], 0, 0, 0);
-        }
-      }
-    };
-    int j1 = li / r2, j2 = li - (li / r2) * r2;
-    auto reduce = [&](const floatx4 (&acc)[4]) {
-      if (j1 < r1) {
-        const float* w1 = sU1 + j1 * EM_TSTRIDE + 4 * g;
-        const float* w2 = sU2 + j2 * EM_TSTRIDE + 4 * g;
-#pragma unroll
-        for (int mb = 0; mb < 4; ++mb) {
-          const floatx4 x1 = *reinterpret_cast<const floatx4*>(w1 + 16 * mb);
-          const floatx4 x2 = *reinterpret_cast<const floatx4*>(w2 + 16 * mb);
-#pragma unroll
-          for (int v = 0; v < 4; ++v) f[mb][v] += x1[v] * x2[v] * acc[mb][v];
-        }
-      }
-      j2 += 16;
-      while (j2 >= r2) {
-        j2 -= r2;
-        ++j1;
-      }
-    };
-    const int nbs = a.r12p / 16;
     floatx4 accA[4], accB[4];
     block(0, accA);
-    for (int nb = 0; nb < nbs; nb += 2) {
-      if (nb + 1 < nbs) block(nb + 1, accB);
-      reduce(accA);
-      if (nb + 1 >= nbs) break;
-      if (nb + 2 < nbs) block(nb + 2, accA);
-      reduce(accB);
+    int nb = 0, m = 0;
+    // two column blocks and SB degree steps per iteration: straight-line code, so the
+    // scheduler can interleave the steps' VALU work with the blocks' MFMAs
+    for (int it = 0; it < npair; ++it) {
+      block(nb + 1, accB);
+      reduce(accA, nb);
+#pragma unroll
+      for (int s = 0; s < (SB + 1) / 2; ++s) step(m + s);
+      interleave();
+      block(nb + 2, accA);
+#pragma unroll
+      for (int s = (SB + 1) / 2; s < SB; ++s) step(m + s);
+      reduce(accB, nb + 1);
+      interleave();
+      nb += 2;
+      m += SB;
     }
+    for (; nb + 2 < nbs; nb += 2) {   // blocks left over (accA holds block nb)
+      block(nb + 1, accB);
+      reduce(accA, nb);
+      block(nb + 2, accA);
+      reduce(accB, nb + 1);
+    }
+    if (nb + 1 < nbs) {
+      block(nb + 1, accB);
+      reduce(accA, nb);
+      reduce(accB, nb + 1);
+    } else {
+      reduce(accA, nb);
+    }
+    for (; m < nst; ++m) step(m);   // degree steps left over
     // the 16 lanes of a lane group hold partial sums of the same points over different columns
 #pragma unroll
     for (int mb = 0; mb < 4; ++mb)
@@ -183,23 +249,24 @@ __global__ __launch_bounds__(EM_THREADS) void k_eval_mfma(EvalMfmaArgs a) {
         s += __shfl_xor(s, 8, 64);
         f[mb][v] = s;
       }
-    if (li == 0) {
+    // lanes li < 4 of lane group g store points 16 mb + 4 g + li: 16 consecutive points per mb
+    const int64_t tile = ((int64_t)rnd * gridDim.x + blockIdx.x) * EM_WAVES + wave;
+    if (li < 4) {
 #pragma unroll
-      for (int mb = 0; mb < 4; ++mb)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int64_t q = tile * 64 + 16 * mb + 4 * g + v;
-          if (q < a.n) {
-            if (a.residual) {
-              const int64_t i = a.idx ? (int64_t)a.idx[q] : q;
-              a.out[q] = a.v[i] - f[mb][v];
-            } else {
-              a.out[q] = f[mb][v];
-            }
+      for (int mb = 0; mb < 4; ++mb) {
+        const float val = li == 0 ? f[mb][0] : (li == 1 ? f[mb][1] : (li == 2 ? f[mb][2] : f[mb][3]));
+        const int64_t q = tile * 64 + 16 * mb + 4 * g + li;
+        if (q < a.n) {
+          if (a.residual) {
+            const int64_t i = a.idx ? (int64_t)a.idx[q] : q;
+            a.out[q] = a.v[i] - val;
+          } else {
+            a.out[q] = val;
           }
         }
+      }
     }
-    __syncthreads();
+    finish();   // the next tile's tables and A operands
   }
 }
 
@@ -210,10 +277,19 @@ bool eval_mfma_applies(const fst_model* m) {
   return em_lds_bytes(m->rank[0], m->rank[1], m->rank[2]) <= EM_LDS_LIMIT;
 }
 
-template <int NP, int RP>
+template <int RP, int SB>
 static void em_launch(const EvalMfmaArgs& a, size_t lds, int blocks, void* stream) {
-  hipLaunchKernelGGL((k_eval_mfma<NP, RP>), dim3((unsigned)blocks), dim3(EM_THREADS), lds, S(stream), a);
+  hipLaunchKernelGGL((k_eval_mfma<RP, SB>), dim3((unsigned)blocks), dim3(EM_THREADS), lds, S(stream), a);
   check_launch("k_eval_mfma");
+}
+template <int RP>
+static void em_launch_sb(const EvalMfmaArgs& a, int sb, size_t lds, int blocks, void* stream) {
+  switch (sb) {
+    case 1: em_launch<RP, 1>(a, lds, blocks, stream); break;
+    case 2: em_launch<RP, 2>(a, lds, blocks, stream); break;
+    case 4: em_launch<RP, 4>(a, lds, blocks, stream); break;
+    default: em_launch<RP, 8>(a, lds, blocks, stream); break;
+  }
 }
 
 void launch_eval_mfma(const fst_model* m, const DeviceModel& dm, int64_t n, const float* x, const float* y,
@@ -238,30 +314,35 @@ void launch_eval_mfma(const fst_model* m, const DeviceModel& dm, int64_t n, cons
   a.r12p = (a.r1 * a.r2 + 15) / 16 * 16;
   a.residual = residual ? 1 : 0;
   a.map = make_map<float>(m);
-  a.rec = make_recurrence<float>();
+  a.nst = 1;
+  for (int k = 0; k < 3; ++k) a.nst = std::max(a.nst, m->degree[k] + 1);
+  // monic Legendre recurrence: phi_{m+1} = A_m t phi_m - B_m phi_{m-1} with phi_m = c_m p_m,
+  // c_0 = 1, c_{m+1} = A_m c_m gives p_{m+1} = t p_m - beta_m p_{m-1}, beta_m = B_m / (A_m A_{m-1})
+  {
+    auto A = [](int k) { return std::sqrt((2.0 * k + 1.0) * (2.0 * k + 3.0)) / (k + 1.0); };
+    auto B = [](int k) { return k == 0 ? 0.0 : k * std::sqrt(2.0 * k + 3.0) / ((k + 1.0) * std::sqrt(2.0 * k - 1.0)); };
+    double c = 1.0;
+    for (int k = 0; k < kMaxBasis; ++k) {
+      a.cscale[k] = c;
+      a.beta[k] = k == 0 ? 0.0f : (float)(B(k) / (A(k) * A(k - 1)));
+      c *= A(k);
+    }
+  }
   const size_t lds = em_lds_bytes(a.r1, a.r2, a.r3);
   const int64_t per_block = EM_WAVES;
   const int blocks = (int)std::min<int64_t>((a.ntiles + per_block - 1) / per_block, (int64_t)device_cu_count());
   a.rounds = (int)((a.ntiles + (int64_t)blocks * per_block - 1) / ((int64_t)blocks * per_block));
+  // degree steps per pair of column blocks: the power of two nearest to steps / pairs
+  const int pairs = std::max(1, (a.r12p / 16 - 1) / 2);
+  const double ratio = (double)a.nst / pairs;
+  const int sb = ratio < 1.5 ? 1 : (ratio < 3.0 ? 2 : (ratio < 6.0 ? 4 : 8));
   const int rp = pad8(std::max(std::max(a.r1, a.r2), a.r3));
-  const bool np16 = m->degree[0] < 16 && m->degree[1] < 16 && m->degree[2] < 16;
-#define FST_EM_CASE(NPV, RPV) em_launch<NPV, RPV>(a, lds, blocks, stream)
-  if (np16) {
-    switch (rp) {
-      case 8: FST_EM_CASE(16, 8); break;
-      case 16: FST_EM_CASE(16, 16); break;
-      case 24: FST_EM_CASE(16, 24); break;
-      default: FST_EM_CASE(16, 32); break;
-    }
-  } else {
-    switch (rp) {
-      case 8: FST_EM_CASE(32, 8); break;
-      case 16: FST_EM_CASE(32, 16); break;
-      case 24: FST_EM_CASE(32, 24); break;
-      default: FST_EM_CASE(32, 32); break;
-    }
+  switch (rp) {
+    case 8: em_launch_sb<8>(a, sb, lds, blocks, stream); break;
+    case 16: em_launch_sb<16>(a, sb, lds, blocks, stream); break;
+    case 24: em_launch_sb<24>(a, sb, lds, blocks, stream); break;
+    default: em_launch_sb<32>(a, sb, lds, blocks, stream); break;
   }
-#undef FST_EM_CASE
 }
 
 }  // namespace fst
