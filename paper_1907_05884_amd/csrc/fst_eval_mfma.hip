@@ -15,7 +15,7 @@
 //   phase 2 (MFMA): T of the tile, 16 columns (j1 j2) per block, then f += u1 u2 T.
 // The LDS holds one workgroup per CU, so a SIMD runs one wave; the two phases overlap inside
 // the wave instead: the loop over T's column blocks carries the degree steps of the NEXT
-// tile's phase 1 (SB steps per two blocks), so the VALU works while the matrix core runs.
+// tile's phase 1 (SPH degree steps per block), so the VALU works while the matrix core runs.
 // U3 reaches the MFMA A operand without LDS: a 4 x 4 transpose of 16-lane blocks
 // (v_permlane16_swap, v_permlane32_swap) turns lane l's u3[4s .. 4s+3] into the operands of
 // the four 16-point blocks.  u1 and u2 go to per-wave LDS tables (points contiguous, float4
@@ -29,6 +29,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 
 #include "fst_device.h"
 #include "fst_internal.h"
@@ -60,12 +61,12 @@ constexpr int EM_CSIZE = 3 * kMaxBasis * kMaxRank;   // coefficient matrices, st
 
 static size_t em_lds_bytes(int r1, int r2, int r3) {
   const size_t r3s = (size_t)em_r3s(r3), r12p = ((size_t)r1 * r2 + 15) / 16 * 16;
-  return sizeof(float) * (EM_CSIZE + r12p * r3s + (size_t)EM_WAVES * (r1 + r2) * EM_TSTRIDE) + 8 * r12p;
+  return sizeof(float) * (EM_CSIZE + kMaxBasis + r12p * r3s + (size_t)EM_WAVES * (r1 + r2) * EM_TSTRIDE) + 8 * r12p;
 }
 
 // RP: ranks padded to 8 (KS = RP / 4 MFMA k-steps and the factor values held per mode);
-// SB: degree steps of the next tile per two column blocks.
-template <int RP, int SB>
+// SPH: degree steps of the next tile per column block.
+template <int RP, int SPH>
 __global__ __launch_bounds__(EM_THREADS) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_eval_mfma(
     EvalMfmaArgs a) {
   constexpr int KS = RP / 4;
@@ -73,7 +74,8 @@ __global__ __launch_bounds__(EM_THREADS) __attribute__((amdgpu_waves_per_eu(1, 1
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, li = lane & 15, g = lane >> 4;
   const int r1 = a.r1, r2 = a.r2, r3 = a.r3, r3s = a.r3s, R12 = r1 * r2, nbs = a.r12p / 16, nst = a.nst;
   float* sC = em_smem;                                           // [3][kMaxBasis][kMaxRank]
-  float* sAlpha = sC + EM_CSIZE;                                 // [r12p][r3s]
+  float* sBeta = sC + EM_CSIZE;                                  // [kMaxBasis]
+  float* sAlpha = sBeta + kMaxBasis;                             // [r12p][r3s]
   int2* sCol = reinterpret_cast<int2*>(sAlpha + (size_t)a.r12p * r3s);   // [r12p]
   float* sU1 = reinterpret_cast<float*>(sCol + a.r12p) + (size_t)wave * (r1 + r2) * EM_TSTRIDE;   // [r1][68]
   float* sU2 = sU1 + r1 * EM_TSTRIDE;                                                              // [r2][68]
@@ -83,6 +85,7 @@ __global__ __launch_bounds__(EM_THREADS) __attribute__((amdgpu_waves_per_eu(1, 1
   }
   for (int e = threadIdx.x; e < EM_CSIZE; e += EM_THREADS)
     sC[e] = (float)(a.cscale[(e / kMaxRank) % kMaxBasis] * (double)a.coefs[e]);
+  if (threadIdx.x < kMaxBasis) sBeta[threadIdx.x] = a.beta[threadIdx.x];
   // columns past r1 r2 point at row 0 of both tables (finite values; their alpha rows are zero)
   for (int c = threadIdx.x; c < a.r12p; c += EM_THREADS)
     sCol[c] = c < R12 ? make_int2((c / r2) * EM_TSTRIDE, (c % r2) * EM_TSTRIDE) : make_int2(0, 0);
@@ -100,19 +103,33 @@ __global__ __launch_bounds__(EM_THREADS) __attribute__((amdgpu_waves_per_eu(1, 1
       for (int j = 0; j < RP; ++j) u[k][j] = 0.0f;
     }
   };
-  auto step = [&](int m) {   // degree m of all three modes
+  // degree m of all three modes: the coefficient rows (and beta_m) are read first, then used
+  typedef floatx4 CoefRows[3][RP / 4];
+  auto loadc = [&](int m, CoefRows& c, float& bm) {
     const float* cm = sC + m * kMaxRank;
-    const float bm = a.beta[m];
 #pragma unroll
     for (int k = 0; k < 3; ++k)
 #pragma unroll
-      for (int j = 0; j < RP; ++j) u[k][j] = fmaf(cm[k * kMaxBasis * kMaxRank + j], pm[k], u[k][j]);
+      for (int q = 0; q < RP / 4; ++q) c[k][q] = *reinterpret_cast<const floatx4*>(cm + k * kMaxBasis * kMaxRank + 4 * q);
+    bm = sBeta[m];
+  };
+  auto stepc = [&](const CoefRows& c, float bm) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+      for (int j = 0; j < RP; ++j) u[k][j] = fmaf(c[k][j / 4][j % 4], pm[k], u[k][j]);
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       const float pn = fmaf(tt[k], pm[k], -bm * pm1[k]);
       pm1[k] = pm[k];
       pm[k] = pn;
     }
+  };
+  CoefRows cr;
+  float crb;
+  auto step = [&](int m) {
+    loadc(m, cr, crb);
+    stepc(cr, crb);
   };
   // coordinates of the lane's point in the wave's tile of round rnd (clamped into the input)
   auto load_coords = [&](int rnd, float (&c)[3]) {
@@ -153,38 +170,49 @@ __global__ __launch_bounds__(EM_THREADS) __attribute__((amdgpu_waves_per_eu(1, 1
     __builtin_amdgcn_wave_barrier();
   };
   const int ks3 = (r3 + 3) / 4 - 1;   // last k-step with alpha columns (av is zero past r3)
-  auto block = [&](int nb, floatx4 (&acc)[4]) {
-    const float* bp = sAlpha + (nb * 16 + li) * r3s + g;
-    float b[KS];
+  // LDS reads of column block nb (clamped into the blocks): B operands, the column's rows of
+  // the u1 and u2 tables, and the products u1 u2 of the lane's 16 points
+  auto loadb = [&](int nb, float (&b)[KS]) {
+    const float* bp = sAlpha + (std::min(nb, nbs - 1) * 16 + li) * r3s + g;
 #pragma unroll
     for (int s = 0; s < KS; ++s) b[s] = bp[4 * std::min(s, ks3)];
+  };
+  auto loadcol = [&](int nb) { return sCol[std::min(nb, nbs - 1) * 16 + li]; };
+  auto loadx = [&](int2 off, floatx4 (&x1)[4], floatx4 (&x2)[4]) {
+    const float* w1 = sU1 + off.x + 4 * g;
+    const float* w2 = sU2 + off.y + 4 * g;
+#pragma unroll
+    for (int mb = 0; mb < 4; ++mb) {
+      x1[mb] = *reinterpret_cast<const floatx4*>(w1 + 16 * mb);
+      x2[mb] = *reinterpret_cast<const floatx4*>(w2 + 16 * mb);
+    }
+  };
+  auto product = [&](const floatx4 (&x1)[4], const floatx4 (&x2)[4], floatx4 (&w)[4]) {
+#pragma unroll
+    for (int mb = 0; mb < 4; ++mb) w[mb] = x1[mb] * x2[mb];
+  };
+  auto mfma = [&](const float (&b)[KS], floatx4 (&acc)[4]) {
 #pragma unroll
     for (int s = 0; s < KS; ++s)
 #pragma unroll
       for (int mb = 0; mb < 4; ++mb)
         acc[mb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[mb][s], b[s], s == 0 ? floatx4{0, 0, 0, 0} : acc[mb], 0, 0, 0);
   };
-  // scheduling of one block with the VALU work beside it: each MFMA followed by VALU and LDS
-  // reads of the independent work (hints to the instruction scheduler, no effect on results)
-  auto interleave = [&]() {
+  float f[4][4];
+  auto reduce = [&](const floatx4 (&acc)[4], const floatx4 (&w)[4]) {
+#pragma unroll
+    for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) f[mb][v] = fmaf(w[mb][v], acc[mb][v], f[mb][v]);
+  };
+  // one half-iteration as the scheduler should order it: its LDS reads first, then each MFMA
+  // followed by a share of the VALU work (hints only: no effect on the results)
+  auto schedule = [&]() {
+    __builtin_amdgcn_sched_group_barrier(0x100, 40, 0);   // LDS reads
 #pragma unroll
     for (int i = 0; i < 4 * KS; ++i) {
       __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);   // MFMA
-      __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);   // LDS read
-      __builtin_amdgcn_sched_group_barrier(0x002, 4, 0);   // VALU
-    }
-  };
-  float f[4][4];
-  auto reduce = [&](const floatx4 (&acc)[4], int nb) {
-    const int2 off = sCol[nb * 16 + li];
-    const float* w1 = sU1 + off.x + 4 * g;
-    const float* w2 = sU2 + off.y + 4 * g;
-#pragma unroll
-    for (int mb = 0; mb < 4; ++mb) {
-      const floatx4 x1 = *reinterpret_cast<const floatx4*>(w1 + 16 * mb);
-      const floatx4 x2 = *reinterpret_cast<const floatx4*>(w2 + 16 * mb);
-#pragma unroll
-      for (int v = 0; v < 4; ++v) f[mb][v] = fmaf(x1[v] * x2[v], acc[mb][v], f[mb][v]);
+      __builtin_amdgcn_sched_group_barrier(0x002, 6, 0);   // VALU
     }
   };
 
@@ -195,8 +223,9 @@ __global__ __launch_bounds__(EM_THREADS) __attribute__((amdgpu_waves_per_eu(1, 1
   for (int m = 0; m < nst; ++m) step(m);
   finish();
   load_coords(1, cn);
-  // column-block pairs that carry SB degree steps each (the steps left over run after them)
-  const int npair = std::min((nbs - 1) / 2, nst / SB);
+  // the column blocks go in pairs; the first npair_s pairs carry 2 SPH degree steps of the
+  // next tile, the steps left over run after the blocks
+  const int nit = (nbs - 1) / 2, nit_s = std::min(nit, nst / (2 * SPH));
   for (int rnd = 0; rnd < a.rounds; ++rnd) {
     start(cn);                  // phase 1 of the next tile
     load_coords(rnd + 2, cn);   // coordinates of the tile after it
@@ -204,37 +233,63 @@ __global__ __launch_bounds__(EM_THREADS) __attribute__((amdgpu_waves_per_eu(1, 1
     for (int mb = 0; mb < 4; ++mb)
 #pragma unroll
       for (int v = 0; v < 4; ++v) f[mb][v] = 0.0f;
-    floatx4 accA[4], accB[4];
-    block(0, accA);
+    // pipeline state at the top of an iteration (nb even): accA = block nb issued, wA its
+    // products; bB and colB of block nb + 1 read
+    floatx4 accA[4], accB[4], x1[4], x2[4], wA[4], wB[4];
+    float bA[KS], bB[KS];
+    int2 colA = loadcol(0), colB;
+    loadb(0, bA);
+    loadx(colA, x1, x2);
+    product(x1, x2, wA);
+    colB = loadcol(1);
+    loadb(1, bB);
+    mfma(bA, accA);
     int nb = 0, m = 0;
-    // two column blocks and SB degree steps per iteration: straight-line code, so the
-    // scheduler can interleave the steps' VALU work with the blocks' MFMAs
-    for (int it = 0; it < npair; ++it) {
-      block(nb + 1, accB);
-      reduce(accA, nb);
+    auto iteration = [&](auto with_steps) {
+      // block nb + 1 into accB; reads for blocks nb + 1 (u1 u2) and nb + 2 (B, column)
+      loadx(colB, x1, x2);
+      loadb(nb + 2, bA);
+      colA = loadcol(nb + 2);
+      if (decltype(with_steps)::value) loadc(m, cr, crb);
+      mfma(bB, accB);
+      reduce(accA, wA);
+      if (decltype(with_steps)::value) {
+        stepc(cr, crb);
 #pragma unroll
-      for (int s = 0; s < (SB + 1) / 2; ++s) step(m + s);
-      interleave();
-      block(nb + 2, accA);
+        for (int s = 1; s < SPH; ++s) step(m + s);
+      }
+      product(x1, x2, wB);
+      schedule();
+      __builtin_amdgcn_sched_barrier(0);
+      // block nb + 2 into accA; reads for blocks nb + 2 (u1 u2) and nb + 3 (B, column)
+      loadx(colA, x1, x2);
+      loadb(nb + 3, bB);
+      colB = loadcol(nb + 3);
+      if (decltype(with_steps)::value) loadc(m + SPH, cr, crb);
+      mfma(bA, accA);
+      reduce(accB, wB);
+      if (decltype(with_steps)::value) {
+        stepc(cr, crb);
 #pragma unroll
-      for (int s = (SB + 1) / 2; s < SB; ++s) step(m + s);
-      reduce(accB, nb + 1);
-      interleave();
+        for (int s = 1; s < SPH; ++s) step(m + SPH + s);
+      }
+      product(x1, x2, wA);
+      schedule();
+      __builtin_amdgcn_sched_barrier(0);
       nb += 2;
-      m += SB;
-    }
-    for (; nb + 2 < nbs; nb += 2) {   // blocks left over (accA holds block nb)
-      block(nb + 1, accB);
-      reduce(accA, nb);
-      block(nb + 2, accA);
-      reduce(accB, nb + 1);
-    }
-    if (nb + 1 < nbs) {
-      block(nb + 1, accB);
-      reduce(accA, nb);
-      reduce(accB, nb + 1);
+      if (decltype(with_steps)::value) m += 2 * SPH;
+    };
+    int it = 0;
+    for (; it < nit_s; ++it) iteration(std::true_type{});
+    for (; it < nit; ++it) iteration(std::false_type{});
+    if (nb + 1 < nbs) {   // one block left over
+      loadx(colB, x1, x2);
+      product(x1, x2, wB);
+      mfma(bB, accB);
+      reduce(accA, wA);
+      reduce(accB, wB);
     } else {
-      reduce(accA, nb);
+      reduce(accA, wA);
     }
     for (; m < nst; ++m) step(m);   // degree steps left over
     // the 16 lanes of a lane group hold partial sums of the same points over different columns
@@ -277,19 +332,16 @@ bool eval_mfma_applies(const fst_model* m) {
   return em_lds_bytes(m->rank[0], m->rank[1], m->rank[2]) <= EM_LDS_LIMIT;
 }
 
-template <int RP, int SB>
+template <int RP, int SPH>
 static void em_launch(const EvalMfmaArgs& a, size_t lds, int blocks, void* stream) {
-  hipLaunchKernelGGL((k_eval_mfma<RP, SB>), dim3((unsigned)blocks), dim3(EM_THREADS), lds, S(stream), a);
+  hipLaunchKernelGGL((k_eval_mfma<RP, SPH>), dim3((unsigned)blocks), dim3(EM_THREADS), lds, S(stream), a);
   check_launch("k_eval_mfma");
 }
 template <int RP>
 static void em_launch_sb(const EvalMfmaArgs& a, int sb, size_t lds, int blocks, void* stream) {
-  switch (sb) {
-    case 1: em_launch<RP, 1>(a, lds, blocks, stream); break;
-    case 2: em_launch<RP, 2>(a, lds, blocks, stream); break;
-    case 4: em_launch<RP, 4>(a, lds, blocks, stream); break;
-    default: em_launch<RP, 8>(a, lds, blocks, stream); break;
-  }
+  if (RP == 32 || sb == 1) em_launch<RP, 1>(a, lds, blocks, stream);
+  else if (sb == 2) em_launch<RP, 2>(a, lds, blocks, stream);
+  else em_launch<RP, 4>(a, lds, blocks, stream);
 }
 
 void launch_eval_mfma(const fst_model* m, const DeviceModel& dm, int64_t n, const float* x, const float* y,
@@ -332,11 +384,13 @@ void launch_eval_mfma(const fst_model* m, const DeviceModel& dm, int64_t n, cons
   const int64_t per_block = EM_WAVES;
   const int blocks = (int)std::min<int64_t>((a.ntiles + per_block - 1) / per_block, (int64_t)device_cu_count());
   a.rounds = (int)((a.ntiles + (int64_t)blocks * per_block - 1) / ((int64_t)blocks * per_block));
-  // degree steps per pair of column blocks: the power of two nearest to steps / pairs
-  const int pairs = std::max(1, (a.r12p / 16 - 1) / 2);
-  const double ratio = (double)a.nst / pairs;
-  const int sb = ratio < 1.5 ? 1 : (ratio < 3.0 ? 2 : (ratio < 6.0 ? 4 : 8));
+  // degree steps per column block (pairs of blocks after the first carry them): 1, 2 or 4,
+  // the nearest to steps / blocks
+  const int carriers = std::max(1, (a.r12p / 16 - 1) / 2 * 2);
+  const double ratio = (double)a.nst / carriers;
   const int rp = pad8(std::max(std::max(a.r1, a.r2), a.r3));
+  // (at RP = 32 more steps per block do not fit the registers)
+  const int sb = rp == 32 || ratio < 1.5 ? 1 : (ratio < 3.0 ? 2 : 4);
   switch (rp) {
     case 8: em_launch_sb<8>(a, sb, lds, blocks, stream); break;
     case 16: em_launch_sb<16>(a, sb, lds, blocks, stream); break;
