@@ -3,9 +3,16 @@
 //   f(x_q) = sum_{j1, j2} u1[q, j1] u2[q, j2] T[q, (j1 j2)],   T = U3 alpha^T,
 //   U3[q, j3] = u3_{j3}(x_q),  alpha^T[j3, (j1 j2)] = alpha[j1, j2, j3]
 //
-// For a tile of 64 points, T (64 x r1 r2) is a GEMM with K = r3 on MFMA 16x16x4 (FP32 in,
-// FP32 accumulation): 2 R flop per point, the bulk of the work.  The weighted reduction over
-// (j1, j2), 3 r1 r2 flop per point, runs on the VALU from the MFMA accumulators.
+// For a tile of 64 points, T (64 x r1 r2) is a GEMM with K = r3 <= 32: 2 R flop per point, the
+// bulk of the work, on MFMA 16x16x32 FP16 with FP32 accumulation over operands split in two
+// FP16 terms each (x = hi + lo, 22 significant bits): hi*hi + hi*lo + lo*hi per product (the
+// dropped lo*lo is below 2^-22 of it), so T is as accurate as an FP32 product while taking a
+// third of the matrix-core time of FP32 MFMA 16x16x4, and (unlike FP32 MFMA on this chip) the
+// 16-bit MFMAs run alongside the wave's VALU work.  Scaling by powers of two keeps the terms in
+// FP16 range: alpha by one factor per workgroup (its largest entry to [2^14, 2^15)), u3 by one
+// factor per point (its largest value likewise); both are undone in the u1 table, exactly.
+// The weighted reduction over (j1, j2), 3 r1 r2 flop per point, runs on the VALU from the MFMA
+// accumulators.
 //
 // Each wave takes one 64-point tile per round; lane l evaluates point l of a tile.
 //   phase 1 (VALU): the factor functions of eq. (2) at the lane's point, the three modes advanced
@@ -16,15 +23,18 @@
 // The LDS holds one workgroup per CU, so a SIMD runs one wave; the two phases overlap inside
 // the wave instead: the loop over T's column blocks carries the degree steps of the NEXT
 // tile's phase 1 (SPH degree steps per block), so the VALU works while the matrix core runs.
-// U3 reaches the MFMA A operand without LDS: a 4 x 4 transpose of 16-lane blocks
-// (v_permlane16_swap, v_permlane32_swap) turns lane l's u3[4s .. 4s+3] into the operands of
-// the four 16-point blocks.  u1 and u2 go to per-wave LDS tables (points contiguous, float4
-// reads), and a per-column table gives each column's rows of them.
+// U3 reaches the MFMA A operand without LDS: lane l holds the 16 FP16 pairs of u3 (each term)
+// of point l; for each of the four pairs of a lane group's k-slot, a 4 x 4 transpose of
+// 16-lane blocks (v_permlane16_swap, v_permlane32_swap) hands lane group g of point block mb
+// the pairs 4 g .. 4 g + 3 of the points 16 mb + li, i.e. u3[8 g .. 8 g + 7], which is the
+// k-slot g of the A operand; B takes alpha[column][8 g .. 8 g + 7] in the same slot.  u1 and u2
+// go to per-wave LDS tables (points contiguous, float4 reads), and a per-column table gives
+// each column's rows of them.
 //
-// LDS: coefficients [3][kMaxBasis][kMaxRank] (scaled by c_m); alpha [r1 r2 padded to 16][r3s]
-// with j3 fastest (r3s = r3 rounded up to 4 and to 2 mod 4, so 16 consecutive rows read at
-// one column fall in distinct bank pairs); the column table [r1 r2 padded]; per wave
-// u1 [r1][68] and u2 [r2][68].
+// LDS: coefficients [3][kMaxBasis][kMaxRank] (scaled by c_m); beta [kMaxBasis]; alpha as two
+// FP16 planes [2][r1 r2 padded to 16][40] with j3 fastest (80-byte rows: the 16-byte reads of
+// 16 consecutive rows fall in distinct banks); the column table [r1 r2 padded]; four floats for
+// the workgroup's maximum; per wave u1 [r1][68] and u2 [r2][68].
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -36,7 +46,9 @@
 
 namespace fst {
 
-constexpr int EM_WAVES = 4, EM_THREADS = 64 * EM_WAVES, EM_TSTRIDE = 68;
+constexpr int EM_WAVES = 4, EM_THREADS = 64 * EM_WAVES, EM_TSTRIDE = 68, EM_APAD = 40;
+// power-of-two scale exponents are kept within +-60, so the unscale 2^-(xa + xq) is a normal float
+constexpr int EM_XMAX = 60;
 constexpr size_t EM_LDS_LIMIT = 160 * 1024;
 
 struct EvalMfmaArgs {
@@ -46,42 +58,55 @@ struct EvalMfmaArgs {
   const float* core;    // R, C order
   float* out;
   int64_t n, ntiles;
-  int32_t r1, r2, r3, r3s, r12p, residual, rounds, nst;
+  int32_t r1, r2, r3, r12p, residual, rounds, nst;
   ModeMap<float> map;
   float beta[kMaxBasis];     // beta_m of the monic recurrence (beta_0 = 0)
   double cscale[kMaxBasis];  // c_m
 };
 
-static inline int em_r3s(int r3) {
-  int s = (r3 + 3) / 4 * 4;
-  return s % 4 == 2 ? s : s + 2;
+constexpr int EM_CSIZE = 3 * kMaxBasis * kMaxRank;
+typedef _Float16 half2v __attribute__((ext_vector_type(2)));
+typedef uint32_t uint32x4 __attribute__((ext_vector_type(4)));   // coefficient matrices, staged once per workgroup
+
+static size_t em_lds_bytes(int r1, int r2) {
+  const size_t r12p = ((size_t)r1 * r2 + 15) / 16 * 16;
+  return sizeof(float) * (EM_CSIZE + kMaxBasis + EM_WAVES + (size_t)EM_WAVES * (r1 + r2) * EM_TSTRIDE) +
+         2 * sizeof(_Float16) * r12p * EM_APAD + 8 * r12p;
 }
 
-constexpr int EM_CSIZE = 3 * kMaxBasis * kMaxRank;   // coefficient matrices, staged once per workgroup
-
-static size_t em_lds_bytes(int r1, int r2, int r3) {
-  const size_t r3s = (size_t)em_r3s(r3), r12p = ((size_t)r1 * r2 + 15) / 16 * 16;
-  return sizeof(float) * (EM_CSIZE + kMaxBasis + r12p * r3s + (size_t)EM_WAVES * (r1 + r2) * EM_TSTRIDE) + 8 * r12p;
-}
-
-// RP: ranks padded to 8 (KS = RP / 4 MFMA k-steps and the factor values held per mode);
-// SPH: degree steps of the next tile per column block.
+// RP: ranks padded to 8 (the factor values held per mode); SPH: degree steps of the next
+// tile per column block.
 template <int RP, int SPH>
 __global__ __launch_bounds__(EM_THREADS) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_eval_mfma(
     EvalMfmaArgs a) {
-  constexpr int KS = RP / 4;
+  constexpr int NW = RP / 2;   // FP16 pairs of u3 per point and term
   extern __shared__ __align__(16) float em_smem[];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, li = lane & 15, g = lane >> 4;
-  const int r1 = a.r1, r2 = a.r2, r3 = a.r3, r3s = a.r3s, R12 = r1 * r2, nbs = a.r12p / 16, nst = a.nst;
-  float* sC = em_smem;                                           // [3][kMaxBasis][kMaxRank]
-  float* sBeta = sC + EM_CSIZE;                                  // [kMaxBasis]
-  float* sAlpha = sBeta + kMaxBasis;                             // [r12p][r3s]
-  int2* sCol = reinterpret_cast<int2*>(sAlpha + (size_t)a.r12p * r3s);   // [r12p]
-  float* sU1 = reinterpret_cast<float*>(sCol + a.r12p) + (size_t)wave * (r1 + r2) * EM_TSTRIDE;   // [r1][68]
-  float* sU2 = sU1 + r1 * EM_TSTRIDE;                                                              // [r2][68]
-  for (int e = threadIdx.x; e < a.r12p * r3s; e += EM_THREADS) {
-    const int c = e / r3s, j3 = e - c * r3s;
-    sAlpha[e] = (c < R12 && j3 < r3) ? a.core[(int64_t)c * r3 + j3] : 0.0f;
+  const int r1 = a.r1, r2 = a.r2, r3 = a.r3, R12 = r1 * r2, nbs = a.r12p / 16, nst = a.nst;
+  const int plane = a.r12p * EM_APAD;
+  float* sC = em_smem;                                                  // [3][kMaxBasis][kMaxRank]
+  float* sBeta = sC + EM_CSIZE;                                         // [kMaxBasis]
+  _Float16* sA16 = reinterpret_cast<_Float16*>(sBeta + kMaxBasis);      // [2][r12p][EM_APAD]
+  int2* sCol = reinterpret_cast<int2*>(sA16 + 2 * plane);               // [r12p]
+  float* sRed = reinterpret_cast<float*>(sCol + a.r12p);                // [EM_WAVES]
+  float* sU1 = sRed + EM_WAVES + (size_t)wave * (r1 + r2) * EM_TSTRIDE;  // [r1][68]
+  float* sU2 = sU1 + r1 * EM_TSTRIDE;                                   // [r2][68]
+  // the scale of alpha: its largest magnitude to [2^14, 2^15)
+  float amax = 0.0f;
+  for (int e = threadIdx.x; e < R12 * r3; e += EM_THREADS) amax = fmaxf(amax, fabsf(a.core[e]));
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) amax = fmaxf(amax, __shfl_xor(amax, o, 64));
+  if (lane == 0) sRed[wave] = amax;
+  __syncthreads();
+  amax = fmaxf(fmaxf(sRed[0], sRed[1]), fmaxf(sRed[2], sRed[3]));
+  const int xa = std::min(EM_XMAX, std::max(-EM_XMAX, 15 - __builtin_amdgcn_frexp_expf(amax)));
+  const float sa = ldexpf(1.0f, xa);
+  for (int e = threadIdx.x; e < plane; e += EM_THREADS) {
+    const int c = e / EM_APAD, j3 = e - c * EM_APAD;
+    const float x = (c < R12 && j3 < r3) ? a.core[(int64_t)c * r3 + j3] * sa : 0.0f;
+    const _Float16 hi = (_Float16)x;
+    sA16[e] = hi;
+    sA16[plane + e] = (_Float16)(x - (float)hi);
   }
   for (int e = threadIdx.x; e < EM_CSIZE; e += EM_THREADS)
     sC[e] = (float)(a.cscale[(e / kMaxRank) % kMaxBasis] * (double)a.coefs[e]);
@@ -140,42 +165,69 @@ __global__ __launch_bounds__(EM_THREADS) __attribute__((amdgpu_waves_per_eu(1, 1
     c[1] = a.y[i];
     c[2] = a.z[i];
   };
-  // ---- phase 2 state: A operands of the tile being contracted, the f partials
-  float av[4][KS];
-  // end of a tile's phase 1: u1, u2 to the wave's tables, u3 transposed into the A operands
-  // (lane group mb of register i holds u3[4 s + i] of points 16 mb + li; afterwards register mb of
-  // lane group i holds it, as the A operand of point block mb wants)
+  // ---- phase 2 state: A operands of the tile being contracted (point block mb; hi, lo terms)
+  halfx8 ah[4], al[4];
+  // end of a tile's phase 1: u1 (with the unscale of both factors) and u2 to the wave's tables;
+  // u3 scaled, split in two FP16 terms and transposed into the A operands
   auto finish = [&]() {
+    float mq = 0.0f;
+#pragma unroll
+    for (int j = 0; j < RP; ++j) mq = fmaxf(mq, fabsf(u[2][j]));
+    const int xq = std::min(EM_XMAX, std::max(-EM_XMAX, 15 - __builtin_amdgcn_frexp_expf(mq)));
+    const float sq = ldexpf(1.0f, xq), unscale = ldexpf(1.0f, -(xa + xq));
     __builtin_amdgcn_s_waitcnt(0xC07F);   // earlier reads of the tables done (lgkmcnt(0))
 #pragma unroll
     for (int j = 0; j < RP; ++j) {
-      if (j < r1) sU1[j * EM_TSTRIDE + lane] = u[0][j];
+      if (j < r1) sU1[j * EM_TSTRIDE + lane] = u[0][j] * unscale;
       if (j < r2) sU2[j * EM_TSTRIDE + lane] = u[1][j];
     }
+    uint32_t wh[16], wl[16];   // FP16 pairs (2 w, 2 w + 1) of each term; zero past RP
 #pragma unroll
-    for (int s = 0; s < KS; ++s) {
-      uint32_t x[4];
+    for (int w = 0; w < 16; ++w) {
+      if (w < NW) {
+        const float x0 = u[2][2 * w] * sq, x1 = u[2][2 * w + 1] * sq;
+        const _Float16 h0 = (_Float16)x0, h1 = (_Float16)x1;
+        const _Float16 l0 = (_Float16)(x0 - (float)h0), l1 = (_Float16)(x1 - (float)h1);
+        wh[w] = __builtin_bit_cast(uint32_t, half2v{h0, h1});
+        wl[w] = __builtin_bit_cast(uint32_t, half2v{l0, l1});
+      } else {
+        wh[w] = 0u;
+        wl[w] = 0u;
+      }
+    }
+    uint32x4 th[4], tl[4];   // [point block mb] words 0..3 of the k-slot of this lane group
+    auto transpose = [&](const uint32_t (&wd)[16], uint32x4 (&t)[4]) {
 #pragma unroll
-      for (int i = 0; i < 4; ++i) x[i] = __builtin_bit_cast(uint32_t, u[2][4 * s + i]);
-      auto p0 = __builtin_amdgcn_permlane16_swap(x[0], x[1], false, false);
-      auto p1 = __builtin_amdgcn_permlane16_swap(x[2], x[3], false, false);
-      auto q0 = __builtin_amdgcn_permlane32_swap(p0[0], p1[0], false, false);
-      auto q1 = __builtin_amdgcn_permlane32_swap(p0[1], p1[1], false, false);
-      av[0][s] = __builtin_bit_cast(float, (uint32_t)q0[0]);
-      av[2][s] = __builtin_bit_cast(float, (uint32_t)q0[1]);
-      av[1][s] = __builtin_bit_cast(float, (uint32_t)q1[0]);
-      av[3][s] = __builtin_bit_cast(float, (uint32_t)q1[1]);
+      for (int w = 0; w < 4; ++w) {
+        // lane group mb holds pair 4 g' + w of its points in register g'; afterwards lane group g
+        // holds pair 4 g + w of the points of block mb in register mb
+        auto p0 = __builtin_amdgcn_permlane16_swap(wd[w], wd[4 + w], false, false);
+        auto p1 = __builtin_amdgcn_permlane16_swap(wd[8 + w], wd[12 + w], false, false);
+        auto q0 = __builtin_amdgcn_permlane32_swap(p0[0], p1[0], false, false);
+        auto q1 = __builtin_amdgcn_permlane32_swap(p0[1], p1[1], false, false);
+        t[0][w] = q0[0];
+        t[2][w] = q0[1];
+        t[1][w] = q1[0];
+        t[3][w] = q1[1];
+      }
+    };
+    transpose(wh, th);
+    transpose(wl, tl);
+#pragma unroll
+    for (int mb = 0; mb < 4; ++mb) {
+      ah[mb] = __builtin_bit_cast(halfx8, th[mb]);
+      al[mb] = __builtin_bit_cast(halfx8, tl[mb]);
     }
     __builtin_amdgcn_s_waitcnt(0xC07F);   // the tables written before they are read
     __builtin_amdgcn_wave_barrier();
   };
-  const int ks3 = (r3 + 3) / 4 - 1;   // last k-step with alpha columns (av is zero past r3)
-  // LDS reads of column block nb (clamped into the blocks): B operands, the column's rows of
-  // the u1 and u2 tables, and the products u1 u2 of the lane's 16 points
-  auto loadb = [&](int nb, float (&b)[KS]) {
-    const float* bp = sAlpha + (std::min(nb, nbs - 1) * 16 + li) * r3s + g;
-#pragma unroll
-    for (int s = 0; s < KS; ++s) b[s] = bp[4 * std::min(s, ks3)];
+  // LDS reads of column block nb (clamped into the blocks): B operands (k-slot g of column
+  // 16 nb + li, both terms), the column's rows of the u1 and u2 tables, and the products u1 u2
+  // of the lane's 16 points
+  auto loadb = [&](int nb, halfx8 (&b)[2]) {
+    const _Float16* bp = sA16 + (std::min(nb, nbs - 1) * 16 + li) * EM_APAD + 8 * g;
+    b[0] = *reinterpret_cast<const halfx8*>(bp);
+    b[1] = *reinterpret_cast<const halfx8*>(bp + plane);
   };
   auto loadcol = [&](int nb) { return sCol[std::min(nb, nbs - 1) * 16 + li]; };
   auto loadx = [&](int2 off, floatx4 (&x1)[4], floatx4 (&x2)[4]) {
@@ -191,12 +243,13 @@ __global__ __launch_bounds__(EM_THREADS) __attribute__((amdgpu_waves_per_eu(1, 1
 #pragma unroll
     for (int mb = 0; mb < 4; ++mb) w[mb] = x1[mb] * x2[mb];
   };
-  auto mfma = [&](const float (&b)[KS], floatx4 (&acc)[4]) {
+  auto mfma = [&](const halfx8 (&b)[2], floatx4 (&acc)[4]) {
 #pragma unroll
-    for (int s = 0; s < KS; ++s)
-#pragma unroll
-      for (int mb = 0; mb < 4; ++mb)
-        acc[mb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[mb][s], b[s], s == 0 ? floatx4{0, 0, 0, 0} : acc[mb], 0, 0, 0);
+    for (int mb = 0; mb < 4; ++mb) {
+      acc[mb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[mb], b[0], floatx4{0, 0, 0, 0}, 0, 0, 0);
+      acc[mb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[mb], b[1], acc[mb], 0, 0, 0);
+      acc[mb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al[mb], b[0], acc[mb], 0, 0, 0);
+    }
   };
   float f[4][4];
   auto reduce = [&](const floatx4 (&acc)[4], const floatx4 (&w)[4]) {
@@ -210,9 +263,9 @@ __global__ __launch_bounds__(EM_THREADS) __attribute__((amdgpu_waves_per_eu(1, 1
   auto schedule = [&]() {
     __builtin_amdgcn_sched_group_barrier(0x100, 40, 0);   // LDS reads
 #pragma unroll
-    for (int i = 0; i < 4 * KS; ++i) {
+    for (int i = 0; i < 12; ++i) {
       __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);   // MFMA
-      __builtin_amdgcn_sched_group_barrier(0x002, 6, 0);   // VALU
+      __builtin_amdgcn_sched_group_barrier(0x002, 10, 0);  // VALU
     }
   };
 
@@ -236,7 +289,7 @@ __global__ __launch_bounds__(EM_THREADS) __attribute__((amdgpu_waves_per_eu(1, 1
     // pipeline state at the top of an iteration (nb even): accA = block nb issued, wA its
     // products; bB and colB of block nb + 1 read
     floatx4 accA[4], accB[4], x1[4], x2[4], wA[4], wB[4];
-    float bA[KS], bB[KS];
+    halfx8 bA[2], bB[2];
     int2 colA = loadcol(0), colB;
     loadb(0, bA);
     loadx(colA, x1, x2);
@@ -329,7 +382,7 @@ bool eval_mfma_applies(const fst_model* m) {
   if (m->d != 3 || m->has_wavelets()) return false;
   for (int k = 0; k < 3; ++k)
     if (m->rank[k] > kMaxRank || m->degree[k] + 1 > kMaxBasis) return false;
-  return em_lds_bytes(m->rank[0], m->rank[1], m->rank[2]) <= EM_LDS_LIMIT;
+  return em_lds_bytes(m->rank[0], m->rank[1]) <= EM_LDS_LIMIT;
 }
 
 template <int RP, int SPH>
@@ -362,7 +415,6 @@ void launch_eval_mfma(const fst_model* m, const DeviceModel& dm, int64_t n, cons
   a.r1 = m->rank[0];
   a.r2 = m->rank[1];
   a.r3 = m->rank[2];
-  a.r3s = em_r3s(a.r3);
   a.r12p = (a.r1 * a.r2 + 15) / 16 * 16;
   a.residual = residual ? 1 : 0;
   a.map = make_map<float>(m);
@@ -380,7 +432,7 @@ void launch_eval_mfma(const fst_model* m, const DeviceModel& dm, int64_t n, cons
       c *= A(k);
     }
   }
-  const size_t lds = em_lds_bytes(a.r1, a.r2, a.r3);
+  const size_t lds = em_lds_bytes(a.r1, a.r2);
   const int64_t per_block = EM_WAVES;
   const int blocks = (int)std::min<int64_t>((a.ntiles + per_block - 1) / per_block, (int64_t)device_cu_count());
   a.rounds = (int)((a.ntiles + (int64_t)blocks * per_block - 1) / ((int64_t)blocks * per_block));
