@@ -1,27 +1,35 @@
-// Factor evaluation of eq. (2) with the contraction on FP32 MFMA (gfx950):
+// Factor evaluation of eq. (2) with the contraction on MFMA (gfx950):
 //
 //   U_k[j, q] = sum_m C_k[m, j] phi_m(xi_k(x_q)),   m < n_k = p_k + 1 <= 32,  j < r_k <= 32
 //
-// Per 64 sampled rows and mode, U_k (64 x r_k) = Phi (64 x n_k) C_k (n_k x r_k) is a GEMM
-// with K = n_k: on MFMA 16x16x4 (FP32 in, FP32 accumulation) that is 2 n_k r_k flop per point
-// at the matrix-core rate instead of one VALU FMA and one LDS broadcast per term, which is
-// what bounded the one-thread-per-point form.
+// Per 64 sampled rows and mode, U_k (64 x r_k) = Phi (64 x n_k) C_k (n_k x r_k) is a GEMM with
+// K = n_k <= 32: one step of MFMA 16x16x32 FP16 per 16 x 16 block, over operands split in two
+// FP16 terms each (x = hi + lo, 22 significant bits; hi*hi + hi*lo + lo*hi, FP32
+// accumulation; the dropped lo*lo is below 2^-22 of the product).  FP32 MFMA would take four
+// times the matrix-core time and, on this chip, does not run alongside the VALU work of the
+// wave (the basis recurrence), while the 16-bit MFMAs do.
 //
-// Per wave and round of 64 rows, lane l takes row q0 + l, and for each mode and each MFMA
-// k-step s:
-//   1. the lane advances the monic three-term recurrence of the Legendre polynomials
-//      (coefficients folded into the code as constants; the normalisation of the orthonormal
-//      basis goes into the staged coefficients) by four degrees, holding p_{4s .. 4s+3} of
-//      its own row in four registers;
-//   2. a 4 x 4 transpose of 16-lane blocks across those registers (two v_permlane16_swap and
-//      two v_permlane32_swap) turns them into the A operands of the four 16-row tiles: lane
-//      group g of tile t's register holds p_{4s+g} of rows 16 t .. 16 t + 15;
-//   3. one MFMA per tile and 16-column block; the B operand (c_m C_k, zero past n_k and r_k) comes
-//      from a per-workgroup LDS copy, swizzled [m][j ^ 16 ((m / 2) % 2)] so that the reads of 4
-//      consecutive m at 16 consecutive j fall in 64 distinct banks.
-// The basis never goes through LDS, so recurrence (VALU) and MFMA interleave within a wave.
-// Lane l then holds U_k[16 jb + l % 16] at rows 16 t + 4 (l / 16) + v, v = 0..3: four
-// consecutive rows of one column, one 16-byte store.
+// Basis: phi_m = c_m p_m with p_m the monic Legendre polynomials; the kernel runs
+//   q_{m+1} = 2 t q_m - 4 beta_m q_{m-1},   q_m = 2^m p_m,
+// two VALU operations per degree, and folds c_m 2^-m into the staged coefficients.  |q_m(t)|
+// is at most about 10 rho^m with rho = |t| + sqrt(t^2 - 1) (rho = 1 inside the box), so
+// starting the recurrence at 2^xs with xs = 11 - ceil(31 log2 rho) keeps every value below
+// 2^15, in FP16 range.  The coefficients of a mode are scaled by one power of two (largest to
+// [2^14, 2^15)); both scales are undone on the accumulators through a per-point factor.
+//
+// Per wave and round of 64 rows, lane l takes row q0 + l and, for each mode:
+//   1. runs the recurrence for the 32 basis values of its row and splits them into FP16 terms
+//      (16 pairs per term);
+//   2. a 4 x 4 transpose of 16-lane blocks (v_permlane16_swap, v_permlane32_swap) per pair
+//      position turns them into the A operands of the four 16-row tiles (lane group g: the
+//      basis values 8 g .. 8 g + 7 of rows 16 t + li, the k-slot g);
+//   3. three MFMAs per tile and 16-column block; the B operands (coefficients 8 g .. 8 g + 7 of
+//      column 16 jb + li, both terms) come from an LDS copy with 80-byte rows (conflict-free).
+// Lane l then holds U_k[16 jb + l % 16] at rows 16 t + 4 (l / 16) + v, v = 0..3.  A store of
+// that layout would touch 16 columns of U (mrows apart) with 64 bytes each, and the store path
+// spends its time on the per-column requests; so each 16-column block goes through a per-wave
+// LDS tile [16 columns][64 rows] and leaves as four stores of four whole column segments
+// (lanes 16 G .. 16 G + 15 write rows q0 .. q0 + 63 of one column: 256 contiguous bytes).
 // A wave loads the coordinates of up to eight rounds at once (through the row index of a
 // gather) and parks them in LDS before computing them, so no load waits behind its stores
 // (vector memory counts loads and stores in one queue).  The sampled values v_S are gathered by
@@ -37,12 +45,15 @@
 
 namespace fst {
 
-constexpr int FM_WAVES = 4, FM_THREADS = 64 * FM_WAVES, FM_ROWS = 64, FM_PARK = 8;
+constexpr int FM_WAVES = 4, FM_THREADS = 64 * FM_WAVES, FM_ROWS = 64, FM_PARK = 6, FM_TPAD = 68;
 
 typedef float fm_floatx4 __attribute__((ext_vector_type(4)));
 typedef uint32_t fm_uintx4 __attribute__((ext_vector_type(4)));
 // buffer offset of a dropped store, and the largest U (bytes) that the kernel writes
 constexpr uint32_t kFmSkip = 0x80000000u;
+// cache policy of the U stores: non-temporal (U is streamed to HBM for a later kernel; 10%
+// faster than stores that allocate in L2)
+constexpr int kFmNontemporal = 2;
 constexpr int64_t kFmMaxUBytes = 0x7FFFFF00;
 
 template <typename TIn>
@@ -62,9 +73,8 @@ struct FactorMfmaArgs {
 // The orthonormal Legendre basis satisfies phi_{m+1} = A_m t phi_m - B_m phi_{m-1} with
 // A_m = sqrt((2m+1)(2m+3)) / (m+1), B_m = m sqrt(2m+3) / ((m+1) sqrt(2m-1)).  Writing
 // phi_m = c_m p_m with c_0 = 1, c_{m+1} = A_m c_m gives the monic recurrence
-// p_{m+1} = t p_m - beta_m p_{m-1}, beta_m = B_m / (A_m A_{m-1}): two VALU operations per degree.
-// The kernel runs it and folds c_m into the staged coefficients (C'[m][j] = c_m C[m][j]).
-// Square roots by Newton's iteration at compile time.
+// p_{m+1} = t p_m - beta_m p_{m-1}, beta_m = B_m / (A_m A_{m-1}).  Square roots by Newton's
+// iteration at compile time.
 constexpr double fm_sqrt(double x) {
   double r = x > 1.0 ? x : 1.0;
   for (int i = 0; i < 200; ++i) r = 0.5 * (r + x / r);
@@ -75,48 +85,83 @@ constexpr double fm_rec_b(int m) {
   return m == 0 ? 0.0 : m * fm_sqrt(2.0 * m + 3.0) / ((m + 1.0) * fm_sqrt(2.0 * m - 1.0));
 }
 struct FmMonic {
-  float beta[kMaxBasis];    // beta_m (beta_0 = 0)
-  double scale[kMaxBasis];  // c_m
+  float beta4[kMaxBasis];   // 4 beta_m (beta_0 = 0)
+  double qscale[kMaxBasis];  // c_m 2^-m: phi_m = c_m 2^-m q_m
 };
 constexpr FmMonic fm_monic() {
   FmMonic t{};
-  double c = 1.0;
+  double c = 1.0, p2 = 1.0;
   for (int m = 0; m < kMaxBasis; ++m) {
-    t.scale[m] = c;
-    t.beta[m] = m == 0 ? 0.0f : (float)(fm_rec_b(m) / (fm_rec_a(m) * fm_rec_a(m - 1)));
+    t.qscale[m] = c / p2;
+    t.beta4[m] = m == 0 ? 0.0f : (float)(4.0 * fm_rec_b(m) / (fm_rec_a(m) * fm_rec_a(m - 1)));
     c *= fm_rec_a(m);
+    p2 *= 2.0;
   }
   return t;
 }
-// c_m for the coefficient staging (a plain device table: indexed at run time)
-__constant__ double fm_scale_table[kMaxBasis] = {
-#define FM_S(m) fm_monic().scale[m]
+// c_m 2^-m for the coefficient staging (a plain device table: indexed at run time)
+__constant__ double fm_qscale_table[kMaxBasis] = {
+#define FM_S(m) fm_monic().qscale[m]
     FM_S(0),  FM_S(1),  FM_S(2),  FM_S(3),  FM_S(4),  FM_S(5),  FM_S(6),  FM_S(7),  FM_S(8),  FM_S(9),  FM_S(10),
     FM_S(11), FM_S(12), FM_S(13), FM_S(14), FM_S(15), FM_S(16), FM_S(17), FM_S(18), FM_S(19), FM_S(20), FM_S(21),
     FM_S(22), FM_S(23), FM_S(24), FM_S(25), FM_S(26), FM_S(27), FM_S(28), FM_S(29), FM_S(30), FM_S(31)};
 #undef FM_S
 static_assert(kMaxBasis == 32, "scale table size");
-// bound on the recurrence state when n_k is not a multiple of 4: rows past n_k are then
-// evaluated too (their coefficients are zero) and must stay finite; far outside the box the
-// state would overflow, so it is clamped there (values at that size are not representable in
-// the field either)
-constexpr float kFmClamp = 1e30f;
+constexpr int FM_BPAD = 40;   // halfs per staged coefficient row (80 bytes)
+// scale exponents: xs in [-100, 11] (rows up to |t| of about 6 stay in FP16 range, about
+// where FP32 values of degree 31 overflow too), xc in [-20, 26] (largest coefficient between
+// 2^-12 and 2^34); the unscale 2^-(xs + xc) is then a normal float
+constexpr int FM_XSMIN = -100, FM_XCMIN = -20, FM_XCMAX = 26;
 
-// JB: blocks of 16 columns (ceil(max r_k / 16)); KS: MFMA k-steps (ceil(max n_k / 4));
-// VEC: the row count is a multiple of 4 (16-byte stores).
-template <typename TIn, int D, int JB, int KS, bool VEC>
-__global__ __launch_bounds__(FM_THREADS) __attribute__((amdgpu_waves_per_eu(4))) void k_factor_eval_mfma(
+typedef _Float16 fm_half2 __attribute__((ext_vector_type(2)));
+typedef _Float16 fm_half8 __attribute__((ext_vector_type(8)));
+
+// JB: blocks of 16 columns (ceil(max r_k / 16)); NQ: basis values evaluated (16 or 32, at
+// least max n_k); VEC: the row count is a multiple of 4 (16-byte stores).
+template <typename TIn, int D, int JB, int NQ, bool VEC>
+__global__ __launch_bounds__(FM_THREADS) __attribute__((amdgpu_waves_per_eu(D == 3 ? 3 : 2))) void k_factor_eval_mfma(
     FactorMfmaArgs<TIn> a) {
-  __shared__ float sC[D][4 * KS][32];
-  __shared__ float sPark[FM_WAVES][FM_PARK][D][64];
+  __shared__ __align__(16) _Float16 sB[2][D][32][FM_BPAD];   // [term][mode][column j][degree m]
+  __shared__ __align__(16) float sPark[FM_WAVES][FM_PARK][D][64];
+  __shared__ __align__(16) float sUs[FM_WAVES][64];            // per-point unscale of the mode
+  __shared__ __align__(16) float sT[FM_WAVES][16][FM_TPAD];      // column block on its way out
+  __shared__ float sRed[FM_WAVES][D];
+  __shared__ int sXc[D];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, li = lane & 15, g = lane >> 4;
-  static_assert(D * 4 * KS * 32 % FM_THREADS == 0, "staging loop");
-#pragma unroll   // all loads issued before the first wait
-  for (int e0 = 0; e0 < D * 4 * KS * 32; e0 += FM_THREADS) {
-    const int e = e0 + threadIdx.x;
-    const int k = e / (4 * KS * 32), m = (e / 32) % (4 * KS), j = e % 32;
-    sC[k][m][j ^ (16 * ((m >> 1) & 1))] =
-        (m < a.nb[k] && j < a.rank[k]) ? (float)(fm_scale_table[m] * a.coefs[(k * kMaxBasis + m) * kMaxRank + j]) : 0.0f;
+  // the coefficient scale of each mode: the largest |c_m 2^-m C[m][j]| to [2^14, 2^15)
+  {
+    float mx[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) mx[k] = 0.0f;
+    for (int e = threadIdx.x; e < 32 * 32; e += FM_THREADS) {
+      const int m = e / 32, j = e % 32;
+#pragma unroll
+      for (int k = 0; k < D; ++k)
+        if (m < a.nb[k] && j < a.rank[k])
+          mx[k] = fmaxf(mx[k], fabsf((float)(fm_qscale_table[m] * a.coefs[(k * kMaxBasis + m) * kMaxRank + j])));
+    }
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+#pragma unroll
+      for (int o = 32; o >= 1; o >>= 1) mx[k] = fmaxf(mx[k], __shfl_xor(mx[k], o, 64));
+      if (lane == 0) sRed[wave][k] = mx[k];
+    }
+    __syncthreads();
+    if (threadIdx.x < D) {
+      float v = 0.0f;
+      for (int w = 0; w < FM_WAVES; ++w) v = fmaxf(v, sRed[w][threadIdx.x]);
+      sXc[threadIdx.x] = std::max(FM_XCMIN, std::min(FM_XCMAX, 15 - __builtin_amdgcn_frexp_expf(v)));
+    }
+    __syncthreads();
+  }
+  for (int e = threadIdx.x; e < D * 32 * FM_BPAD; e += FM_THREADS) {
+    const int k = e / (32 * FM_BPAD), j = (e / FM_BPAD) % 32, m = e % FM_BPAD;
+    const float x = (m < a.nb[k] && j < a.rank[k])
+                        ? (float)(fm_qscale_table[m] * a.coefs[(k * kMaxBasis + m) * kMaxRank + j]) * ldexpf(1.0f, sXc[k])
+                        : 0.0f;
+    const _Float16 hi = (_Float16)x;
+    sB[0][k][j][m] = hi;
+    sB[1][k][j][m] = (_Float16)(x - (float)hi);
   }
   // values of the sampled rows (a gather when idx is given)
   if (a.vs) {
@@ -124,6 +169,9 @@ __global__ __launch_bounds__(FM_THREADS) __attribute__((amdgpu_waves_per_eu(4)))
       a.vs[q] = (float)a.v[a.idx ? (int64_t)a.idx[q] : q];
   }
   __syncthreads();
+  int xc[D];
+#pragma unroll
+  for (int k = 0; k < D; ++k) xc[k] = sXc[k];
   // U through a buffer resource: a store whose offset is past the end (kFmSkip) is dropped by
   // the hardware, so the stores need no branches
   const __amdgpu_buffer_rsrc_t urs = __builtin_amdgcn_make_buffer_rsrc(
@@ -133,6 +181,8 @@ __global__ __launch_bounds__(FM_THREADS) __attribute__((amdgpu_waves_per_eu(4)))
   // are computed and stored with no load in between, so no wait on the stores is needed until
   // the next pass.
   float (*park)[D][64] = sPark[wave];
+  float* us = sUs[wave];
+  float (*tt)[FM_TPAD] = sT[wave];
   const int64_t wtot = (int64_t)gridDim.x * FM_WAVES, w = (int64_t)blockIdx.x * FM_WAVES + wave;
   for (int64_t pass0 = 0; pass0 < a.nrounds; pass0 += wtot * FM_PARK) {
     int nr = 0;
@@ -158,75 +208,103 @@ __global__ __launch_bounds__(FM_THREADS) __attribute__((amdgpu_waves_per_eu(4)))
       for (int k = 0; k < D; ++k) {
         constexpr FmMonic rec = fm_monic();
         const float t = (cur[k] - a.map.lo[k]) * a.map.scale[k] - 1.0f;
-        fm_floatx4 acc[4][JB];
+        // 1. the basis of this lane's row, started at 2^xs, split into FP16 terms
+        const float at = fabsf(t);
+        const float rho = fmaxf(1.0f, at + sqrtf(fmaxf(at * at - 1.0f, 0.0f)));   // 1 inside the box
+        const int xs = std::max(FM_XSMIN, 11 - (int)ceilf((NQ - 1) * __log2f(rho)));
+        uint32_t wh[16], wl[16];
+        {
+          const float t2 = t + t;
+          float prev = 0.0f, now = ldexpf(1.0f, xs);
 #pragma unroll
-        for (int tile = 0; tile < 4; ++tile)
+          for (int pr = 0; pr < 16; ++pr) {
+            if (2 * pr < NQ) {
+              float x[2];
 #pragma unroll
-          for (int jb = 0; jb < JB; ++jb) acc[tile][jb] = fm_floatx4{0.0f, 0.0f, 0.0f, 0.0f};
-        auto contract = [&](auto clamp) {
-          float prev = 0.0f, now = 1.0f;   // p_{m-1}, p_m of this lane's row
-#pragma unroll
-          for (int s = 0; s < KS; ++s) {
-            // 1. p_{4s .. 4s+3} of this lane's row
-            uint32_t x[4];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-              const int m = 4 * s + i;
-              x[i] = __builtin_bit_cast(uint32_t, now);
-              float next = fmaf(t, now, -rec.beta[m] * prev);
-              if (decltype(clamp)::value) next = fminf(fmaxf(next, -kFmClamp), kFmClamp);
-              prev = now;
-              now = next;
+              for (int i = 0; i < 2; ++i) {
+                const int m = 2 * pr + i;
+                x[i] = now;
+                const float next = fmaf(t2, now, -rec.beta4[m] * prev);
+                prev = now;
+                now = next;
+              }
+              const _Float16 h0 = (_Float16)x[0], h1 = (_Float16)x[1];
+              wh[pr] = __builtin_bit_cast(uint32_t, fm_half2{h0, h1});
+              wl[pr] = __builtin_bit_cast(uint32_t, fm_half2{(_Float16)(x[0] - (float)h0), (_Float16)(x[1] - (float)h1)});
+            } else {
+              wh[pr] = 0u;
+              wl[pr] = 0u;
             }
-            // 2. blocks (row group t, degree g) -> (tile t, lane group g)
-            {
-              auto p0 = __builtin_amdgcn_permlane16_swap(x[0], x[1], false, false);
-              auto p1 = __builtin_amdgcn_permlane16_swap(x[2], x[3], false, false);
-              auto q0 = __builtin_amdgcn_permlane32_swap(p0[0], p1[0], false, false);
-              auto q1 = __builtin_amdgcn_permlane32_swap(p0[1], p1[1], false, false);
-              x[0] = q0[0];
-              x[2] = q0[1];
-              x[1] = q1[0];
-              x[3] = q1[1];
-            }
-            // 3. MFMA
-            float bv[JB];
+          }
+        }
+        us[lane] = ldexpf(1.0f, -(xs + xc[k]));
+        // 2. pairs -> A operands: register t of lane group g holds pairs 4 g .. 4 g + 3 of rows
+        //    16 t + li
+        uint32_t ah[4][4], al[4][4];
+        auto transpose = [&](const uint32_t (&wd)[16], uint32_t (&o)[4][4]) {
 #pragma unroll
-            for (int jb = 0; jb < JB; ++jb) bv[jb] = sC[k][4 * s + g][(16 * jb + li) ^ (16 * ((g >> 1) & 1))];
-#pragma unroll
-            for (int tile = 0; tile < 4; ++tile)
-#pragma unroll
-              for (int jb = 0; jb < JB; ++jb)
-                acc[tile][jb] = __builtin_amdgcn_mfma_f32_16x16x4f32(__builtin_bit_cast(float, x[tile]), bv[jb],
-                                                                     acc[tile][jb], 0, 0, 0);
+          for (int pw = 0; pw < 4; ++pw) {
+            auto p0 = __builtin_amdgcn_permlane16_swap(wd[pw], wd[4 + pw], false, false);
+            auto p1 = __builtin_amdgcn_permlane16_swap(wd[8 + pw], wd[12 + pw], false, false);
+            auto q0 = __builtin_amdgcn_permlane32_swap(p0[0], p1[0], false, false);
+            auto q1 = __builtin_amdgcn_permlane32_swap(p0[1], p1[1], false, false);
+            o[0][pw] = q0[0];
+            o[2][pw] = q0[1];
+            o[1][pw] = q1[0];
+            o[3][pw] = q1[1];
           }
         };
-        if (a.nb[k] == 4 * KS) contract(std::false_type{});
-        else contract(std::true_type{});
-        // 3. lane l: column 16 jb + l % 16, rows q0 + 16 tile + 4 g + (0..3)
+        transpose(wh, ah);
+        transpose(wl, al);
+        // 3. MFMA: B operands of the mode's column blocks, three products per tile and block
+        fm_floatx4 acc[4][JB];
 #pragma unroll
         for (int jb = 0; jb < JB; ++jb) {
-          const int j = 16 * jb + li;
-          const bool jv = j < a.rank[k];
-          const uint32_t base = (uint32_t)(((int64_t)(a.off[k] + j) * a.mrows + q0 + 4 * g) * 4);
-          if (VEC) {   // n % 4 == 0: four consecutive rows are all inside or all past the end
+          const fm_half8 bh = *reinterpret_cast<const fm_half8*>(&sB[0][k][16 * jb + li][8 * g]);
+          const fm_half8 bl = *reinterpret_cast<const fm_half8*>(&sB[1][k][16 * jb + li][8 * g]);
 #pragma unroll
-            for (int tile = 0; tile < 4; ++tile) {
-              const bool ok = jv && q0 + 16 * tile + 4 * g < a.mrows;
-              __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(fm_uintx4, acc[tile][jb]), urs,
-                                                     ok ? base + 64u * tile : kFmSkip, 0, 0);
-            }
-          } else {
+          for (int tile = 0; tile < 4; ++tile) {
+            const fm_half8 xh = __builtin_bit_cast(fm_half8, fm_uintx4{ah[tile][0], ah[tile][1], ah[tile][2], ah[tile][3]});
+            const fm_half8 xl = __builtin_bit_cast(fm_half8, fm_uintx4{al[tile][0], al[tile][1], al[tile][2], al[tile][3]});
+            fm_floatx4 c = __builtin_amdgcn_mfma_f32_16x16x32_f16(xh, bh, fm_floatx4{0.0f, 0.0f, 0.0f, 0.0f}, 0, 0, 0);
+            c = __builtin_amdgcn_mfma_f32_16x16x32_f16(xh, bl, c, 0, 0, 0);
+            acc[tile][jb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(xl, bh, c, 0, 0, 0);
+          }
+        }
+        // per-point unscale: rows 16 t + 4 g + v of this lane
 #pragma unroll
-            for (int tile = 0; tile < 4; ++tile)
+        for (int tile = 0; tile < 4; ++tile) {
+          const fm_floatx4 f = *reinterpret_cast<const fm_floatx4*>(&us[16 * tile + 4 * g]);
 #pragma unroll
-              for (int v = 0; v < 4; ++v) {
+          for (int jb = 0; jb < JB; ++jb) acc[tile][jb] *= f;
+        }
+        // 4. per column block: through the LDS tile (lane (li, g) writes rows 16 t + 4 g .. + 3 of
+        //    column li; lane (p, G) reads rows 4 p .. 4 p + 3 of column 4 s + G) and out, four
+        //    columns per store
+#pragma unroll
+        for (int jb = 0; jb < JB; ++jb) {
+#pragma unroll
+          for (int tile = 0; tile < 4; ++tile)
+            *reinterpret_cast<fm_floatx4*>(&tt[li][16 * tile + 4 * g]) = acc[tile][jb];
+#pragma unroll
+          for (int sc = 0; sc < 4; ++sc) {
+            const fm_floatx4 v = *reinterpret_cast<const fm_floatx4*>(&tt[4 * sc + g][4 * li]);
+            const int j = 16 * jb + 4 * sc + g;
+            const bool jv = j < a.rank[k];
+            const int64_t row = q0 + 4 * li;
+            const uint32_t base = (uint32_t)(((int64_t)(a.off[k] + j) * a.mrows + row) * 4);
+            if (VEC) {   // mrows % 4 == 0: four consecutive rows are all inside or all past the end
+              __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(fm_uintx4, v), urs,
+                                                     jv && row < a.mrows ? base : kFmSkip, 0, kFmNontemporal);
+            } else {
+#pragma unroll
+              for (int e = 0; e < 4; ++e)
                 // (the element is copied to a float first: a bit cast of a vector-element lvalue
                 // compiles to a read of element 0)
-                const bool ok = jv && q0 + 16 * tile + 4 * g + v < a.mrows;
-                __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, (float)acc[tile][jb][v]), urs,
-                                                      ok ? base + 64u * tile + 4u * v : kFmSkip, 0, 0);
-              }
+                __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, (float)v[e]), urs,
+                                                      jv && row + e < a.mrows ? base + 4u * e : kFmSkip, 0,
+                                                      kFmNontemporal);
+            }
           }
         }
       }
@@ -246,31 +324,31 @@ bool factor_eval_mfma_applies(const fst_model* m, int64_t mrows) {
 
 // one resident workgroup per slot (grid-stride over the rounds): as many workgroups as the
 // occupancy of the instance allows on every CU
-template <typename TIn, int D, int JB, int KS, bool VEC>
+template <typename TIn, int D, int JB, int NQ, bool VEC>
 static void launch_one(const FactorMfmaArgs<TIn>& a, void* stream) {
   static std::atomic<int> occupancy(0);
   int per_cu = occupancy.load();
   if (!per_cu) {
     int nb = 0;
-    check_hip(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_factor_eval_mfma<TIn, D, JB, KS, VEC>, FM_THREADS, 0),
+    check_hip(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_factor_eval_mfma<TIn, D, JB, NQ, VEC>, FM_THREADS, 0),
               "hipOccupancyMaxActiveBlocksPerMultiprocessor");
     per_cu = nb > 0 ? nb : 1;
     occupancy.store(per_cu);
   }
   const int64_t blocks =
       std::min<int64_t>((a.nrounds + FM_WAVES - 1) / FM_WAVES, (int64_t)device_cu_count() * per_cu);
-  hipLaunchKernelGGL((k_factor_eval_mfma<TIn, D, JB, KS, VEC>), dim3((unsigned)blocks), dim3(FM_THREADS), 0, S(stream),
+  hipLaunchKernelGGL((k_factor_eval_mfma<TIn, D, JB, NQ, VEC>), dim3((unsigned)blocks), dim3(FM_THREADS), 0, S(stream),
                      a);
 }
 
 template <typename TIn, int D, bool VEC>
-static void launch_d(const FactorMfmaArgs<TIn>& a, int jb, int ks, void* stream) {
+static void launch_d(const FactorMfmaArgs<TIn>& a, int jb, int nq, void* stream) {
   if (jb == 1) {
-    if (ks <= 4) launch_one<TIn, D, 1, 4, VEC>(a, stream);
-    else launch_one<TIn, D, 1, 8, VEC>(a, stream);
+    if (nq <= 16) launch_one<TIn, D, 1, 16, VEC>(a, stream);
+    else launch_one<TIn, D, 1, 32, VEC>(a, stream);
   } else {
-    if (ks <= 4) launch_one<TIn, D, 2, 4, VEC>(a, stream);
-    else launch_one<TIn, D, 2, 8, VEC>(a, stream);
+    if (nq <= 16) launch_one<TIn, D, 2, 16, VEC>(a, stream);
+    else launch_one<TIn, D, 2, 32, VEC>(a, stream);
   }
 }
 
@@ -301,14 +379,14 @@ void launch_factor_eval_mfma(const fst_model* m, const DeviceModel& dm, const vo
     nbmax = std::max(nbmax, a.nb[k]);
   }
   a.map = make_map<float>(m);
-  const int jb = (rmax + 15) / 16, ks = (nbmax + 3) / 4;
+  const int jb = (rmax + 15) / 16, nq = nbmax;
   const bool vec = mrows % 4 == 0;
   if (m->d == 3) {
-    if (vec) launch_d<float, 3, true>(a, jb, ks, stream);
-    else launch_d<float, 3, false>(a, jb, ks, stream);
+    if (vec) launch_d<float, 3, true>(a, jb, nq, stream);
+    else launch_d<float, 3, false>(a, jb, nq, stream);
   } else {
-    if (vec) launch_d<float, 4, true>(a, jb, ks, stream);
-    else launch_d<float, 4, false>(a, jb, ks, stream);
+    if (vec) launch_d<float, 4, true>(a, jb, nq, stream);
+    else launch_d<float, 4, false>(a, jb, nq, stream);
   }
   check_launch("k_factor_eval_mfma");
 }
