@@ -13,8 +13,8 @@
 //   q_{m+1} = 2 t q_m - 4 beta_m q_{m-1},   q_m = 2^m p_m,
 // two VALU operations per degree, and folds c_m 2^-m into the staged coefficients.  |q_m(t)|
 // is at most about 10 rho^m with rho = |t| + sqrt(t^2 - 1) (rho = 1 inside the box), so
-// starting the recurrence at 2^xs with xs = 11 - ceil(31 log2 rho) keeps every value below
-// 2^15, in FP16 range.  The coefficients of a mode are scaled by one power of two (largest to
+// starting the recurrence at 2^xs with xs = 11 - ceil((n_k - 1) log2 rho) keeps every value the
+// mode uses below 2^15, in FP16 range (values past n_k are replaced by zeros).  The coefficients of a mode are scaled by one power of two (largest to
 // [2^14, 2^15)); both scales are undone on the accumulators through a per-point factor.
 //
 // Per wave and round of 64 rows, lane l takes row q0 + l and, for each mode:
@@ -208,12 +208,15 @@ __global__ __launch_bounds__(FM_THREADS) __attribute__((amdgpu_waves_per_eu(D ==
       for (int k = 0; k < D; ++k) {
         constexpr FmMonic rec = fm_monic();
         const float t = (cur[k] - a.map.lo[k]) * a.map.scale[k] - 1.0f;
-        // 1. the basis of this lane's row, started at 2^xs, split into FP16 terms
+        // 1. the basis of this lane's row, started at 2^xs, split into FP16 terms.  The scale is
+        //    set by the mode's own degree n_k - 1; a mode with n_k < NQ runs the recurrence on
+        //    (it may leave FP16 range there) but keeps zeros past n_k
+        const int nbk = a.nb[k];
         const float at = fabsf(t);
         const float rho = fmaxf(1.0f, at + sqrtf(fmaxf(at * at - 1.0f, 0.0f)));   // 1 inside the box
-        const int xs = std::max(FM_XSMIN, 11 - (int)ceilf((NQ - 1) * __log2f(rho)));
+        const int xs = std::max(FM_XSMIN, 11 - (int)ceilf((float)(nbk - 1) * __log2f(rho)));
         uint32_t wh[16], wl[16];
-        {
+        auto basis = [&](auto full) {
           const float t2 = t + t;
           float prev = 0.0f, now = ldexpf(1.0f, xs);
 #pragma unroll
@@ -223,7 +226,7 @@ __global__ __launch_bounds__(FM_THREADS) __attribute__((amdgpu_waves_per_eu(D ==
 #pragma unroll
               for (int i = 0; i < 2; ++i) {
                 const int m = 2 * pr + i;
-                x[i] = now;
+                x[i] = decltype(full)::value || m < nbk ? now : 0.0f;
                 const float next = fmaf(t2, now, -rec.beta4[m] * prev);
                 prev = now;
                 now = next;
@@ -236,7 +239,9 @@ __global__ __launch_bounds__(FM_THREADS) __attribute__((amdgpu_waves_per_eu(D ==
               wl[pr] = 0u;
             }
           }
-        }
+        };
+        if (nbk == NQ) basis(std::true_type{});
+        else basis(std::false_type{});
         us[lane] = ldexpf(1.0f, -(xs + xc[k]));
         // 2. pairs -> A operands: register t of lane group g holds pairs 4 g .. 4 g + 3 of rows
         //    16 t + li

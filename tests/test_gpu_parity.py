@@ -546,3 +546,52 @@ def test_full_size_against_oracle_reference(dev):
     pick = np.random.default_rng(0).choice(w.n, 20000, replace=False)
     fr = reconstruct.evaluate(om, w.pts[pick].astype(np.float64))
     assert rel_l2(f[pick], fr) <= 1e-5
+
+
+# ------------------------------------------------------------------------------ outside the box
+def _per_point_rel(a, b):
+    """max over points of ||a_q - b_q|| / ||b_q|| (rows are points)."""
+    num = np.linalg.norm(a - b, axis=1)
+    den = np.linalg.norm(b, axis=1)
+    return float(np.max(num / np.where(den > 0, den, 1.0)))
+
+
+@pytest.mark.parametrize("rank,degree", [((24, 24, 24), (31, 31, 31)), ((16, 8, 5), (15, 7, 31))])
+def test_factor_eval_outside_the_box(dev, rank, degree):
+    """FP32 factor values at points up to three half-widths from the box centre (|t| <= 3): the
+    basis grows like (|t| + sqrt(t^2 - 1))^m there, and the kernel scales each point's basis by
+    its own power of two to keep its 16-bit terms in range.  The values match the oracle's to
+    1e-5 (relative L2 over all points, whose size the farthest points set), and every point's
+    values to 5e-5 relative to that point's own magnitude: a wrong scale for one point would
+    show as an O(1) error there, while FP32 alone leaves t rounded by about 1e-6 at |t| <= 3,
+    which the degree-31 basis amplifies up to m / sqrt(t^2 - 1) (about 1.1e-5 measured)."""
+    om, gm = _models(5, rank, degree, lo=(0, 0, 0), hi=(4, 1, 1))
+    pts = _pts(6, 6001, (-4, -1, -1), (8, 2, 2), np.float32)     # t in [-3, 3] in every mode
+    x, y, z = _soa(pts, dev)
+    U, _ = fst.fst_factor_eval(gm, x, y, z)
+    ref = lsq.factor_values(om, pts.astype(np.float64))
+    Uh = H(U)
+    off = 0
+    for k in range(3):
+        got = Uh[off:off + rank[k]].T.astype(np.float64)
+        assert rel_l2(got, ref[k]) <= 1e-5, k
+        assert _per_point_rel(got, ref[k]) <= 5e-5, k
+        off += rank[k]
+
+
+def test_eval_outside_the_box(dev):
+    """FP32 reconstruction (eq. (1)) at points up to two half-widths out (|t| <= 2), where the
+    factor values of a degree-15 model grow by up to 1e8: within 1e-5 of the oracle's field
+    over the points inside the box and over those outside it."""
+    rank, degree = (8, 12, 6), (15, 11, 13)
+    om, gm = _models(7, rank, degree, lo=(0, 0, 0), hi=(4, 1, 1))
+    pts = _pts(8, 20000, (-2, -0.5, -0.5), (6, 1.5, 1.5), np.float32)   # t in [-2, 2]
+    x, y, z = _soa(pts, dev)
+    out = torch.empty_like(x)
+    fst.fst_eval(gm, x, y, z, out)
+    f = H(out).astype(np.float64)
+    ref = reconstruct.evaluate(om, pts.astype(np.float64))
+    inside = np.all((pts >= (0, 0, 0)) & (pts <= (4, 1, 1)), axis=1)
+    assert inside.sum() > 1000 and (~inside).sum() > 1000
+    assert rel_l2(f[inside], ref[inside]) <= 1e-5
+    assert rel_l2(f[~inside], ref[~inside]) <= 1e-5
