@@ -319,6 +319,7 @@ def run_batched(args):
         a_ref = a_ref.reshape(-1)
         rel = lambda a: float(np.linalg.norm(a.reshape(-1) - a_ref) / np.linalg.norm(a_ref))
         errs[f"var{int(k)} (R={Rs[k]})"] = {"batched": rel(m.core), "plain_fp32": rel(plain[k].core)}
+    cpu = None if args.no_cpu_baseline else batched_cpu_baseline(wl, models, Rs, M)
     result = {
         "metric": METRIC, "value": V * M / t_rows, "unit": "rows/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": float(np.sum(ph) + tg) * 1e3, "higher_is_better": True,
@@ -351,8 +352,43 @@ def run_batched(args):
                      "bound": "mfma", "achieved": gram_flops / ph[2] / 1e12,
                      "peak": PEAK[prec] / 1e12, "unit": "TFLOP/s", "frac": gram_flops / ph[2] / PEAK[prec],
                      "traffic": None, "flops_per_launch": gram_flops},
+        "cpu_baseline": cpu,
     }
     print(json.dumps(result), flush=True)
+
+
+def batched_cpu_baseline(wl, models, Rs, M, n_rows=1024):
+    """The oracle's rate for the batched workload's design rows, Gram and A^T v, extrapolated:
+    timed on n_rows sampled rows of the median-R and the largest-R variable, the per-row cost
+    fitted as a R^2 (the Gram dominates it) and summed over every variable at M rows."""
+    from threadpoolctl import threadpool_info
+
+    from oracle import lsq
+    from oracle.model import Model as OModel
+    order = np.argsort(Rs)
+    picks = sorted({int(order[len(order) // 2]), int(order[-1])})
+    rows = np.sort(np.random.default_rng(0).choice(wl.pts.shape[0], n_rows, replace=False))
+    pts = wl.pts[rows].astype(np.float64)
+    samples = []
+    for k in picks:
+        m = models[k]
+        om = OModel(tuple(wl.lo), tuple(wl.hi), tuple(m.rank), tuple(m.degree), m.core, [m.coefs(j) for j in range(3)])
+        t0 = time.perf_counter()
+        A = lsq.design_rows(lsq.factor_values(om, pts))
+        G = A.T @ A
+        h = A.T @ wl.vals[k][rows].astype(np.float64)
+        dt = time.perf_counter() - t0
+        del A, G, h
+        samples.append((Rs[k], dt / n_rows))
+    a = sum(c * R ** 2 for R, c in samples) / sum(float(R) ** 4 for R, c in samples)
+    total = float(M) * sum(a * float(R) ** 2 for R in Rs)
+    cores = max([int(i.get("num_threads", 0)) for i in threadpool_info() if i.get("user_api") == "blas"] + [0])
+    log(f"[batched] oracle leg: {' '.join(f'R={R}: {c * 1e3:.2f} ms/row' for R, c in samples)}")
+    return {"value": len(Rs) * M / total, "unit": "rows/s", "cores": cores, "kind": "oracle",
+            "sample": f"extrapolated: the oracle's FP64 design rows + Gram + A^T v timed on {n_rows} sampled rows "
+                      f"of the variables with R = {', '.join(str(R) for R, _ in samples)}, per-row cost fitted as "
+                      f"a R^2 and summed over the {len(Rs)} variables at M = {M} rows each",
+            "per_row_s": {str(R): c for R, c in samples}}
 
 
 def precision_leg(fst, torch, dev, args, m0, m_or, ref, x, y, z, v, idx, U, vs, G, h, alpha, rws, stream, w):
