@@ -4,7 +4,8 @@
 //
 // Per 64 sampled rows and mode, U_k (64 x r_k) = Phi (64 x n_k) C_k (n_k x r_k) is a GEMM with
 // K = n_k <= 32: one step of MFMA 16x16x32 FP16 per 16 x 16 block, over operands split in two
-// FP16 terms each (x = hi + lo, 22 significant bits; hi*hi + hi*lo + lo*hi, FP32
+// FP16 terms each (x = hi + lo, 22 significant bits; for the basis hi is x truncated to 11
+// significant bits, so that hi and lo = x - hi are exact; hi*hi + hi*lo + lo*hi, FP32
 // accumulation; the dropped lo*lo is below 2^-22 of the product).  FP32 MFMA would take four
 // times the matrix-core time and, on this chip, does not run alongside the VALU work of the
 // wave (the basis recurrence), while the 16-bit MFMAs do.
@@ -14,7 +15,8 @@
 // two VALU operations per degree, and folds c_m 2^-m into the staged coefficients.  |q_m(t)|
 // is at most about 10 rho^m with rho = |t| + sqrt(t^2 - 1) (rho = 1 inside the box), so
 // starting the recurrence at 2^xs with xs = 11 - ceil((n_k - 1) log2 rho) keeps every value the
-// mode uses below 2^15, in FP16 range (values past n_k are replaced by zeros).  The coefficients of a mode are scaled by one power of two (largest to
+// mode uses below 2^15, in FP16 range (values past n_k, whose coefficients are zero, are
+// clamped into it).  The coefficients of a mode are scaled by one power of two (largest to
 // [2^14, 2^15)); both scales are undone on the accumulators through a per-point factor.
 //
 // Per wave and round of 64 rows, lane l takes row q0 + l and, for each mode:
@@ -210,7 +212,8 @@ __global__ __launch_bounds__(FM_THREADS) __attribute__((amdgpu_waves_per_eu(D ==
         const float t = (cur[k] - a.map.lo[k]) * a.map.scale[k] - 1.0f;
         // 1. the basis of this lane's row, started at 2^xs, split into FP16 terms.  The scale is
         //    set by the mode's own degree n_k - 1; a mode with n_k < NQ runs the recurrence on
-        //    (it may leave FP16 range there) but keeps zeros past n_k
+        //    past n_k, where it may leave FP16 range: those values are clamped into it (their
+        //    coefficients are zero)
         const int nbk = a.nb[k];
         const float at = fabsf(t);
         const float rho = fmaxf(1.0f, at + sqrtf(fmaxf(at * at - 1.0f, 0.0f)));   // 1 inside the box
@@ -226,14 +229,17 @@ __global__ __launch_bounds__(FM_THREADS) __attribute__((amdgpu_waves_per_eu(D ==
 #pragma unroll
               for (int i = 0; i < 2; ++i) {
                 const int m = 2 * pr + i;
-                x[i] = decltype(full)::value || m < nbk ? now : 0.0f;
+                // past n_k the coefficients are zero; the value only has to stay finite in FP16
+                x[i] = decltype(full)::value ? now : __builtin_amdgcn_fmed3f(now, -65504.0f, 65504.0f);
                 const float next = fmaf(t2, now, -rec.beta4[m] * prev);
                 prev = now;
                 now = next;
               }
-              const _Float16 h0 = (_Float16)x[0], h1 = (_Float16)x[1];
-              wh[pr] = __builtin_bit_cast(uint32_t, fm_half2{h0, h1});
-              wl[pr] = __builtin_bit_cast(uint32_t, fm_half2{(_Float16)(x[0] - (float)h0), (_Float16)(x[1] - (float)h1)});
+              // hi: x with its low 13 mantissa bits cleared (exact in FP16), lo = x - hi (exact)
+              const float h0 = __builtin_bit_cast(float, __builtin_bit_cast(uint32_t, x[0]) & 0xFFFFE000u);
+              const float h1 = __builtin_bit_cast(float, __builtin_bit_cast(uint32_t, x[1]) & 0xFFFFE000u);
+              wh[pr] = __builtin_bit_cast(uint32_t, fm_half2{(_Float16)h0, (_Float16)h1});
+              wl[pr] = __builtin_bit_cast(uint32_t, fm_half2{(_Float16)(x[0] - h0), (_Float16)(x[1] - h1)});
             } else {
               wh[pr] = 0u;
               wl[pr] = 0u;
