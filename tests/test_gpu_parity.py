@@ -59,6 +59,8 @@ def _soa(p, dev):
     (np.float64, (8, 8, 8), (15, 15, 15), 20000, 2000, 1e-10),
     (np.float32, (24, 24, 24), (31, 31, 31), 50001, 20011, 1e-5),
     (np.float32, (32, 4, 17), (31, 15, 20), 9000, 9000, 1e-5),
+    (np.float32, (16, 12, 9), (15, 9, 12), 7001, 5003, 1e-5),      # 16 basis values, one column block
+    (np.float32, (5, 7, 3), (9, 12, 6), 4097, 4097, 1e-5),
 ])
 def test_factor_eval_parity(dev, dtype, rank, degree, n, m, tol):
     om, gm = _models(1, rank, degree, lo=(0, 0, 0), hi=(4, 1, 1))
@@ -248,6 +250,11 @@ def test_cholesky_reports_non_spd_pivot(dev):
     (np.float32, (7, 5, 11), (12, 9, 20), 4999, 1e-5),     # r2 < 16, r3 not a multiple of 4
     (np.float32, (30, 3, 2), (31, 4, 2), 2500, 1e-5),      # r1 r2 = 90: a partial 16-column block
     (np.float32, (1, 1, 1), (0, 0, 0), 1, 1e-6),
+    # instances of the MFMA kernel by padded rank and degree steps per column block
+    (np.float32, (16, 16, 16), (31, 31, 31), 30001, 1e-5),   # ranks padded to 16, 2 steps per block
+    (np.float32, (12, 20, 17), (25, 31, 19), 20011, 1e-5),   # ranks padded to 24, 2 steps per block
+    (np.float32, (8, 8, 8), (15, 15, 15), 20001, 1e-5),      # ranks padded to 8, 4 steps per block
+    (np.float32, (32, 16, 8), (31, 20, 11), 9001, 1e-5),     # ranks padded to 32, 1 step per block
 ])
 def test_eval_parity(dev, dtype, rank, degree, n, tol):
     om, gm = _models(11, rank, degree, lo=(0, 0, 0), hi=(4, 1, 1))
