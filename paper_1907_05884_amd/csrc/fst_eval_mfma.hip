@@ -1,40 +1,34 @@
-// Reconstruction of eq. (1) with the core contraction on FP32 MFMA (gfx950):
+// Reconstruction of eq. (1) on MFMA (gfx950):
 //
 //   f(x_q) = sum_{j1, j2} u1[q, j1] u2[q, j2] T[q, (j1 j2)],   T = U3 alpha^T,
 //   U3[q, j3] = u3_{j3}(x_q),  alpha^T[j3, (j1 j2)] = alpha[j1, j2, j3]
 //
-// For a tile of 64 points, T (64 x r1 r2) is a GEMM with K = r3 <= 32: 2 R flop per point, the
-// bulk of the work, on MFMA 16x16x32 FP16 with FP32 accumulation over operands split in two
-// FP16 terms each (x = hi + lo, 22 significant bits): hi*hi + hi*lo + lo*hi per product (the
-// dropped lo*lo is below 2^-22 of it), so T is as accurate as an FP32 product while taking a
-// third of the matrix-core time of FP32 MFMA 16x16x4, and (unlike FP32 MFMA on this chip) the
-// 16-bit MFMAs run alongside the wave's VALU work.  Scaling by powers of two keeps the terms in
-// FP16 range: alpha by one factor per workgroup (its largest entry to [2^14, 2^15)), u3 by one
-// factor per point (its largest value likewise); both are undone in the u1 table, exactly.
-// The weighted reduction over (j1, j2), 3 r1 r2 flop per point, runs on the VALU from the MFMA
-// accumulators.
+// Both contractions with K <= 32 run on MFMA 16x16x32 FP16 with FP32 accumulation over
+// operands split in two FP16 terms each (x = hi + lo, 22 significant bits; hi*hi + hi*lo +
+// lo*hi, the dropped lo*lo is below 2^-22 of the product): the factor functions of eq. (2)
+// (basis against coefficients, per mode) and T (u3 against the core).  FP32 MFMA would take
+// three to four times the matrix-core time and, on this chip, does not run alongside the VALU
+// work of the wave, while the 16-bit MFMAs do.  Powers of two keep every term in FP16 range:
+// the basis of a point from its growth bound (the factor-value kernel's scaled monic
+// recurrence, q_m = 2^m p_m), the coefficients per mode and the core per workgroup (largest
+// entry to [2^14, 2^15)), u3 per point (its largest value likewise).  All of them are undone
+// at once, exactly, by one per-point exponent applied to the u1 table with ldexp.
 //
-// Each wave takes one 64-point tile per round; lane l evaluates point l of a tile.
-//   phase 1 (VALU): the factor functions of eq. (2) at the lane's point, the three modes advanced
-//     together one degree per step by the monic Legendre recurrence p_{m+1} = t p_m - beta_m
-//     p_{m-1} (the normalisation c_m of phi_m = c_m p_m is folded into the staged coefficients,
-//     which every lane reads from LDS at the same address);
-//   phase 2 (MFMA): T of the tile, 16 columns (j1 j2) per block, then f += u1 u2 T.
-// The LDS holds one workgroup per CU, so a SIMD runs one wave; the two phases overlap inside
-// the wave instead: the loop over T's column blocks carries the degree steps of the NEXT
-// tile's phase 1 (SPH degree steps per block), so the VALU works while the matrix core runs.
-// U3 reaches the MFMA A operand without LDS: lane l holds the 16 FP16 pairs of u3 (each term)
-// of point l; for each of the four pairs of a lane group's k-slot, a 4 x 4 transpose of
-// 16-lane blocks (v_permlane16_swap, v_permlane32_swap) hands lane group g of point block mb
-// the pairs 4 g .. 4 g + 3 of the points 16 mb + li, i.e. u3[8 g .. 8 g + 7], which is the
-// k-slot g of the A operand; B takes alpha[column][8 g .. 8 g + 7] in the same slot.  u1 and u2
-// go to per-wave LDS tables (points contiguous, float4 reads), and a per-column table gives
-// each column's rows of them.
+// Each wave takes one 64-point tile per round; the LDS holds one workgroup per CU.
+//   phase 1 (lane l: point l): per mode, the 32 basis values, split and transposed into the
+//     A operands of the four 16-point blocks (v_permlane16_swap, v_permlane32_swap), then
+//     three MFMAs per block and 16-column block of ranks; u3 goes through a per-wave LDS tile
+//     [point][j3] and comes back in the A-operand layout of phase 2 (lane group g: u3[8 g ..
+//     8 g + 7] of a point), where it is scaled and split; u1 (unscaled) and u2 are written to
+//     per-wave tables [j][point];
+//   phase 2: T of the tile, 16 columns (j1 j2) per block on MFMA, then f += u1 u2 T from the
+//     accumulators, with the LDS reads of the next blocks issued half a block pair ahead.
 //
-// LDS: coefficients [3][kMaxBasis][kMaxRank] (scaled by c_m); beta [kMaxBasis]; alpha as two
-// FP16 planes [2][r1 r2 padded to 16][40] with j3 fastest (80-byte rows: the 16-byte reads of
-// 16 consecutive rows fall in distinct banks); the column table [r1 r2 padded]; four floats for
-// the workgroup's maximum; per wave u1 [r1][68] and u2 [r2][68].
+// LDS: coefficients as two FP16 planes [2][3][RP][40]; four scale exponents; alpha as two FP16
+// planes [2][r1 r2 padded to 16][40] (80-byte rows: the 16-byte reads of 16 consecutive rows
+// fall in distinct banks); the column table [r1 r2 padded] of (j1, j2) table offsets; four
+// floats for the workgroup's maximum; per wave the point exponents [2][64] and a region that
+// holds the u3 tile [64][36] and then the tables u1 [r1][68], u2 [r2][68].
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -46,9 +40,11 @@
 
 namespace fst {
 
-constexpr int EM_WAVES = 4, EM_THREADS = 64 * EM_WAVES, EM_TSTRIDE = 68, EM_APAD = 40;
-// power-of-two scale exponents are kept within +-60, so the unscale 2^-(xa + xq) is a normal float
-constexpr int EM_XMAX = 60;
+constexpr int EM_WAVES = 4, EM_THREADS = 64 * EM_WAVES, EM_TSTRIDE = 68, EM_APAD = 40, EM_CPAD = 40, EM_SPAD = 36;
+// scale exponents: point basis in [-100, 11] (rows up to |t| of about 6 stay in range),
+// coefficients in [-20, 26], core and u3 in [-60, 60]; the per-point exponent is applied with
+// ldexp, so their sum needs no range of its own
+constexpr int EM_XSMIN = -100, EM_XCMIN = -20, EM_XCMAX = 26, EM_XMAX = 60;
 constexpr size_t EM_LDS_LIMIT = 160 * 1024;
 
 struct EvalMfmaArgs {
@@ -58,104 +54,129 @@ struct EvalMfmaArgs {
   const float* core;    // R, C order
   float* out;
   int64_t n, ntiles;
-  int32_t r1, r2, r3, r12p, residual, rounds, nst;
+  int32_t r1, r2, r3, r12p, residual, rounds;
+  int32_t nb[3];              // n_k = degree + 1
   ModeMap<float> map;
-  float beta[kMaxBasis];     // beta_m of the monic recurrence (beta_0 = 0)
-  double cscale[kMaxBasis];  // c_m
+  float beta4[kMaxBasis];     // 4 beta_m of the monic recurrence (beta_0 = 0)
+  double qscale[kMaxBasis];   // c_m 2^-m: phi_m = c_m 2^-m q_m
 };
 
-constexpr int EM_CSIZE = 3 * kMaxBasis * kMaxRank;
 typedef _Float16 half2v __attribute__((ext_vector_type(2)));
-typedef uint32_t uint32x4 __attribute__((ext_vector_type(4)));   // coefficient matrices, staged once per workgroup
+typedef uint32_t uint32x4 __attribute__((ext_vector_type(4)));
+typedef int int4v __attribute__((ext_vector_type(4)));
 
-static size_t em_lds_bytes(int r1, int r2) {
-  const size_t r12p = ((size_t)r1 * r2 + 15) / 16 * 16;
-  return sizeof(float) * (EM_CSIZE + kMaxBasis + EM_WAVES + (size_t)EM_WAVES * (r1 + r2) * EM_TSTRIDE) +
-         2 * sizeof(_Float16) * r12p * EM_APAD + 8 * r12p;
+static inline int em_rp(int r1, int r2, int r3) { return pad8(std::max(std::max(r1, r2), r3)); }
+__host__ __device__ inline size_t em_wave_bytes(int r1, int r2) {
+  const size_t tables = (size_t)(r1 + r2) * EM_TSTRIDE * 4, stage = (size_t)64 * EM_SPAD * 4;
+  return 512 + (tables > stage ? tables : stage);
+}
+static size_t em_lds_bytes(int r1, int r2, int r3) {
+  const size_t r12p = ((size_t)r1 * r2 + 15) / 16 * 16, rp = (size_t)em_rp(r1, r2, r3);
+  return 480 * rp + 16 + 160 * r12p + 8 * r12p + 16 + EM_WAVES * em_wave_bytes(r1, r2);
 }
 
-// RP: ranks padded to 8 (the factor values held per mode); SPH: degree steps of the next
-// tile per column block.
-template <int RP, int SPH>
+// hi: x with its low 13 mantissa bits cleared (exact in FP16 in range), lo = x - hi (exact)
+__device__ __forceinline__ void em_split2(float x0, float x1, uint32_t& hi, uint32_t& lo) {
+  const float h0 = __builtin_bit_cast(float, __builtin_bit_cast(uint32_t, x0) & 0xFFFFE000u);
+  const float h1 = __builtin_bit_cast(float, __builtin_bit_cast(uint32_t, x1) & 0xFFFFE000u);
+  hi = __builtin_bit_cast(uint32_t, half2v{(_Float16)h0, (_Float16)h1});
+  lo = __builtin_bit_cast(uint32_t, half2v{(_Float16)(x0 - h0), (_Float16)(x1 - h1)});
+}
+
+// RP: ranks padded to 8 (JB = 16-column blocks of the factor products)
+template <int RP>
 __global__ __launch_bounds__(EM_THREADS) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_eval_mfma(
     EvalMfmaArgs a) {
-  constexpr int NW = RP / 2;   // FP16 pairs of u3 per point and term
+  constexpr int JB = (RP + 15) / 16;
   extern __shared__ __align__(16) float em_smem[];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, li = lane & 15, g = lane >> 4;
-  const int r1 = a.r1, r2 = a.r2, r3 = a.r3, R12 = r1 * r2, nbs = a.r12p / 16, nst = a.nst;
+  const int r1 = a.r1, r2 = a.r2, r3 = a.r3, R12 = r1 * r2, nbs = a.r12p / 16;
+  char* base = reinterpret_cast<char*>(em_smem);
+  _Float16* sCB = reinterpret_cast<_Float16*>(base);                       // [2][3][RP][EM_CPAD]
+  int* sXc = reinterpret_cast<int*>(base + 480 * RP);                       // [4]
+  _Float16* sA16 = reinterpret_cast<_Float16*>(base + 480 * RP + 16);       // [2][r12p][EM_APAD]
   const int plane = a.r12p * EM_APAD;
-  float* sC = em_smem;                                                  // [3][kMaxBasis][kMaxRank]
-  float* sBeta = sC + EM_CSIZE;                                         // [kMaxBasis]
-  _Float16* sA16 = reinterpret_cast<_Float16*>(sBeta + kMaxBasis);      // [2][r12p][EM_APAD]
-  int2* sCol = reinterpret_cast<int2*>(sA16 + 2 * plane);               // [r12p]
-  float* sRed = reinterpret_cast<float*>(sCol + a.r12p);                // [EM_WAVES]
-  float* sU1 = sRed + EM_WAVES + (size_t)wave * (r1 + r2) * EM_TSTRIDE;  // [r1][68]
-  float* sU2 = sU1 + r1 * EM_TSTRIDE;                                   // [r2][68]
-  // the scale of alpha: its largest magnitude to [2^14, 2^15)
-  float amax = 0.0f;
-  for (int e = threadIdx.x; e < R12 * r3; e += EM_THREADS) amax = fmaxf(amax, fabsf(a.core[e]));
+  int2* sCol = reinterpret_cast<int2*>(sA16 + 2 * plane);                   // [r12p]
+  float* sRed = reinterpret_cast<float*>(sCol + a.r12p);                    // [EM_WAVES]
+  char* wb = reinterpret_cast<char*>(sRed + EM_WAVES) + (size_t)wave * em_wave_bytes(r1, r2);
+  int* sE = reinterpret_cast<int*>(wb);          // [64] per-point exponent of the u1 table
+  int* sQ = sE + 64;                              // [64] per-point scale exponent of u3
+  float* sU1 = reinterpret_cast<float*>(wb + 512);   // [r1][68]
+  float* sU2 = sU1 + r1 * EM_TSTRIDE;                  // [r2][68]
+  float* sStage = sU1;                                  // [64][36], before the tables are written
+
+  // ---- staging: the scales of the core and of the coefficients (largest entry to [2^14, 2^15))
+  {
+    float amax = 0.0f, cmax[3] = {0.0f, 0.0f, 0.0f};
+    for (int e = threadIdx.x; e < R12 * r3; e += EM_THREADS) amax = fmaxf(amax, fabsf(a.core[e]));
+    for (int e = threadIdx.x; e < kMaxBasis * kMaxRank; e += EM_THREADS) {
+      const int m = e / kMaxRank, j = e % kMaxRank;
 #pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) amax = fmaxf(amax, __shfl_xor(amax, o, 64));
-  if (lane == 0) sRed[wave] = amax;
-  __syncthreads();
-  amax = fmaxf(fmaxf(sRed[0], sRed[1]), fmaxf(sRed[2], sRed[3]));
-  const int xa = std::min(EM_XMAX, std::max(-EM_XMAX, 15 - __builtin_amdgcn_frexp_expf(amax)));
-  const float sa = ldexpf(1.0f, xa);
-  for (int e = threadIdx.x; e < plane; e += EM_THREADS) {
-    const int c = e / EM_APAD, j3 = e - c * EM_APAD;
-    const float x = (c < R12 && j3 < r3) ? a.core[(int64_t)c * r3 + j3] * sa : 0.0f;
-    const _Float16 hi = (_Float16)x;
-    sA16[e] = hi;
-    sA16[plane + e] = (_Float16)(x - (float)hi);
+      for (int k = 0; k < 3; ++k) {
+        const int rk = k == 0 ? r1 : (k == 1 ? r2 : r3);
+        if (m < a.nb[k] && j < rk)
+          cmax[k] = fmaxf(cmax[k], fabsf((float)(a.qscale[m] * a.coefs[(k * kMaxBasis + m) * kMaxRank + j])));
+      }
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+      amax = fmaxf(amax, __shfl_xor(amax, o, 64));
+#pragma unroll
+      for (int k = 0; k < 3; ++k) cmax[k] = fmaxf(cmax[k], __shfl_xor(cmax[k], o, 64));
+    }
+    if (lane == 0) {
+      sRed[wave] = amax;
+      // coefficient maxima of this wave, combined below through the scale slots
+      sXc[wave < 3 ? wave : 3] = 0;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      float v = 0.0f;
+      for (int w = 0; w < EM_WAVES; ++w) v = fmaxf(v, sRed[w]);
+      sXc[3] = std::min(EM_XMAX, std::max(-EM_XMAX, 15 - __builtin_amdgcn_frexp_expf(v)));
+    }
+    __syncthreads();
+    // per-mode coefficient maxima: each wave's lane 0 posts its three maxima in turn
+    for (int k = 0; k < 3; ++k) {
+      if (lane == 0) sRed[wave] = cmax[k];
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        float v = 0.0f;
+        for (int w = 0; w < EM_WAVES; ++w) v = fmaxf(v, sRed[w]);
+        sXc[k] = std::max(EM_XCMIN, std::min(EM_XCMAX, 15 - __builtin_amdgcn_frexp_expf(v)));
+      }
+      __syncthreads();
+    }
   }
-  for (int e = threadIdx.x; e < EM_CSIZE; e += EM_THREADS)
-    sC[e] = (float)(a.cscale[(e / kMaxRank) % kMaxBasis] * (double)a.coefs[e]);
-  if (threadIdx.x < kMaxBasis) sBeta[threadIdx.x] = a.beta[threadIdx.x];
-  // columns past r1 r2 point at row 0 of both tables (finite values; their alpha rows are zero)
-  for (int c = threadIdx.x; c < a.r12p; c += EM_THREADS)
-    sCol[c] = c < R12 ? make_int2((c / r2) * EM_TSTRIDE, (c % r2) * EM_TSTRIDE) : make_int2(0, 0);
+  const int xa = sXc[3];
+  int xc[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) xc[k] = sXc[k];
+  {
+    const float sa = ldexpf(1.0f, xa);
+    for (int e = threadIdx.x; e < plane; e += EM_THREADS) {
+      const int c = e / EM_APAD, j3 = e - c * EM_APAD;
+      const float x = (c < R12 && j3 < r3) ? a.core[(int64_t)c * r3 + j3] * sa : 0.0f;
+      const _Float16 hi = (_Float16)x;
+      sA16[e] = hi;
+      sA16[plane + e] = (_Float16)(x - (float)hi);
+    }
+    for (int e = threadIdx.x; e < 3 * RP * EM_CPAD; e += EM_THREADS) {
+      const int k = e / (RP * EM_CPAD), j = (e / EM_CPAD) % RP, m = e % EM_CPAD;
+      const int rk = k == 0 ? r1 : (k == 1 ? r2 : r3);
+      const float x = (m < a.nb[k] && j < rk)
+                          ? (float)(a.qscale[m] * a.coefs[(k * kMaxBasis + m) * kMaxRank + j]) * ldexpf(1.0f, xc[k])
+                          : 0.0f;
+      const _Float16 hi = (_Float16)x;
+      sCB[e] = hi;
+      sCB[3 * RP * EM_CPAD + e] = (_Float16)(x - (float)hi);
+    }
+    // columns past r1 r2 point at row 0 of both tables (finite values; their alpha rows are zero)
+    for (int c = threadIdx.x; c < a.r12p; c += EM_THREADS)
+      sCol[c] = c < R12 ? make_int2((c / r2) * EM_TSTRIDE, (c % r2) * EM_TSTRIDE) : make_int2(0, 0);
+  }
   __syncthreads();
 
-  // ---- phase 1 state: the lane's point of the tile being evaluated
-  float tt[3], pm[3], pm1[3], u[3][RP];
-  auto start = [&](const float (&c)[3]) {
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      tt[k] = (c[k] - a.map.lo[k]) * a.map.scale[k] - 1.0f;
-      pm[k] = 1.0f;
-      pm1[k] = 0.0f;
-#pragma unroll
-      for (int j = 0; j < RP; ++j) u[k][j] = 0.0f;
-    }
-  };
-  // degree m of all three modes: the coefficient rows (and beta_m) are read first, then used
-  typedef floatx4 CoefRows[3][RP / 4];
-  auto loadc = [&](int m, CoefRows& c, float& bm) {
-    const float* cm = sC + m * kMaxRank;
-#pragma unroll
-    for (int k = 0; k < 3; ++k)
-#pragma unroll
-      for (int q = 0; q < RP / 4; ++q) c[k][q] = *reinterpret_cast<const floatx4*>(cm + k * kMaxBasis * kMaxRank + 4 * q);
-    bm = sBeta[m];
-  };
-  auto stepc = [&](const CoefRows& c, float bm) {
-#pragma unroll
-    for (int k = 0; k < 3; ++k)
-#pragma unroll
-      for (int j = 0; j < RP; ++j) u[k][j] = fmaf(c[k][j / 4][j % 4], pm[k], u[k][j]);
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      const float pn = fmaf(tt[k], pm[k], -bm * pm1[k]);
-      pm1[k] = pm[k];
-      pm[k] = pn;
-    }
-  };
-  CoefRows cr;
-  float crb;
-  auto step = [&](int m) {
-    loadc(m, cr, crb);
-    stepc(cr, crb);
-  };
   // coordinates of the lane's point in the wave's tile of round rnd (clamped into the input)
   auto load_coords = [&](int rnd, float (&c)[3]) {
     const int64_t tile = ((int64_t)rnd * gridDim.x + blockIdx.x) * EM_WAVES + wave;
@@ -165,65 +186,137 @@ __global__ __launch_bounds__(EM_THREADS) __attribute__((amdgpu_waves_per_eu(1, 1
     c[1] = a.y[i];
     c[2] = a.z[i];
   };
-  // ---- phase 2 state: A operands of the tile being contracted (point block mb; hi, lo terms)
+  // 4 x 4 transpose of 16-lane blocks for each of the four pairs of a k-slot: register t of
+  // lane group g then holds pairs 4 g .. 4 g + 3 of points 16 t + li
+  auto transpose = [&](const uint32_t (&wd)[16], uint32_t (&o)[4][4]) {
+#pragma unroll
+    for (int pw = 0; pw < 4; ++pw) {
+      auto p0 = __builtin_amdgcn_permlane16_swap(wd[pw], wd[4 + pw], false, false);
+      auto p1 = __builtin_amdgcn_permlane16_swap(wd[8 + pw], wd[12 + pw], false, false);
+      auto q0 = __builtin_amdgcn_permlane32_swap(p0[0], p1[0], false, false);
+      auto q1 = __builtin_amdgcn_permlane32_swap(p0[1], p1[1], false, false);
+      o[0][pw] = q0[0];
+      o[2][pw] = q0[1];
+      o[1][pw] = q1[0];
+      o[3][pw] = q1[1];
+    }
+  };
+
+  // ---- phase 2 operands of the tile being contracted (point block mb; hi, lo terms)
   halfx8 ah[4], al[4];
-  // end of a tile's phase 1: u1 (with the unscale of both factors) and u2 to the wave's tables;
-  // u3 scaled, split in two FP16 terms and transposed into the A operands
-  auto finish = [&]() {
-    float mq = 0.0f;
+  // phase 1 of the tile whose point coordinates the lane holds in c: factor values on MFMA,
+  // then the tables and the A operands
+  auto phase1 = [&](const float (&c)[3]) {
+    floatx4 U[3][4][JB];
+    int esum = xa;
 #pragma unroll
-    for (int j = 0; j < RP; ++j) mq = fmaxf(mq, fabsf(u[2][j]));
-    const int xq = std::min(EM_XMAX, std::max(-EM_XMAX, 15 - __builtin_amdgcn_frexp_expf(mq)));
-    const float sq = ldexpf(1.0f, xq), unscale = ldexpf(1.0f, -(xa + xq));
-    __builtin_amdgcn_s_waitcnt(0xC07F);   // earlier reads of the tables done (lgkmcnt(0))
+    for (int k = 0; k < 3; ++k) {
+      const float t = (c[k] - a.map.lo[k]) * a.map.scale[k] - 1.0f;
+      const int nbk = a.nb[k];
+      const float at = fabsf(t);
+      const float rho = fmaxf(1.0f, at + sqrtf(fmaxf(at * at - 1.0f, 0.0f)));   // 1 inside the box
+      const int xs = std::max(EM_XSMIN, 11 - (int)ceilf((float)(nbk - 1) * __log2f(rho)));
+      esum += xs + xc[k];
+      uint32_t wh[16], wl[16];
+      {
+        const float t2 = t + t;
+        float prev = 0.0f, now = ldexpf(1.0f, xs);
 #pragma unroll
-    for (int j = 0; j < RP; ++j) {
-      if (j < r1) sU1[j * EM_TSTRIDE + lane] = u[0][j] * unscale;
-      if (j < r2) sU2[j * EM_TSTRIDE + lane] = u[1][j];
-    }
-    uint32_t wh[16], wl[16];   // FP16 pairs (2 w, 2 w + 1) of each term; zero past RP
+        for (int pr = 0; pr < 16; ++pr) {
+          float x[2];
 #pragma unroll
-    for (int w = 0; w < 16; ++w) {
-      if (w < NW) {
-        const float x0 = u[2][2 * w] * sq, x1 = u[2][2 * w + 1] * sq;
-        const _Float16 h0 = (_Float16)x0, h1 = (_Float16)x1;
-        const _Float16 l0 = (_Float16)(x0 - (float)h0), l1 = (_Float16)(x1 - (float)h1);
-        wh[w] = __builtin_bit_cast(uint32_t, half2v{h0, h1});
-        wl[w] = __builtin_bit_cast(uint32_t, half2v{l0, l1});
-      } else {
-        wh[w] = 0u;
-        wl[w] = 0u;
+          for (int i = 0; i < 2; ++i) {
+            const int m = 2 * pr + i;
+            // past n_k the coefficients are zero: the value only has to stay finite in FP16
+            x[i] = __builtin_amdgcn_fmed3f(now, -65504.0f, 65504.0f);
+            const float next = fmaf(t2, now, -a.beta4[m] * prev);
+            prev = now;
+            now = next;
+          }
+          em_split2(x[0], x[1], wh[pr], wl[pr]);
+        }
+      }
+      uint32_t th[4][4], tl[4][4];
+      transpose(wh, th);
+      transpose(wl, tl);
+#pragma unroll
+      for (int jb = 0; jb < JB; ++jb) {
+        const int row = std::min(16 * jb + li, RP - 1);   // columns past RP are never used
+        const _Float16* bp = sCB + ((size_t)k * RP + row) * EM_CPAD + 8 * g;
+        const halfx8 bh = *reinterpret_cast<const halfx8*>(bp);
+        const halfx8 bl = *reinterpret_cast<const halfx8*>(bp + 3 * RP * EM_CPAD);
+#pragma unroll
+        for (int t4 = 0; t4 < 4; ++t4) {
+          const halfx8 xh = __builtin_bit_cast(halfx8, uint32x4{th[t4][0], th[t4][1], th[t4][2], th[t4][3]});
+          const halfx8 xl = __builtin_bit_cast(halfx8, uint32x4{tl[t4][0], tl[t4][1], tl[t4][2], tl[t4][3]});
+          floatx4 acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(xh, bh, floatx4{0.0f, 0.0f, 0.0f, 0.0f}, 0, 0, 0);
+          acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(xh, bl, acc, 0, 0, 0);
+          U[k][t4][jb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(xl, bh, acc, 0, 0, 0);
+        }
       }
     }
-    uint32x4 th[4], tl[4];   // [point block mb] words 0..3 of the k-slot of this lane group
-    auto transpose = [&](const uint32_t (&wd)[16], uint32x4 (&t)[4]) {
+    // lane (li, g) holds U_k[points 16 t + 4 g + v][ranks 16 jb + li]
+    __builtin_amdgcn_s_waitcnt(0xC07F);   // earlier reads of the wave's region done (lgkmcnt(0))
+    // u3 to the stage [point][j3] (zeros from RP on), back as the A operands of phase 2
 #pragma unroll
-      for (int w = 0; w < 4; ++w) {
-        // lane group mb holds pair 4 g' + w of its points in register g'; afterwards lane group g
-        // holds pair 4 g + w of the points of block mb in register mb
-        auto p0 = __builtin_amdgcn_permlane16_swap(wd[w], wd[4 + w], false, false);
-        auto p1 = __builtin_amdgcn_permlane16_swap(wd[8 + w], wd[12 + w], false, false);
-        auto q0 = __builtin_amdgcn_permlane32_swap(p0[0], p1[0], false, false);
-        auto q1 = __builtin_amdgcn_permlane32_swap(p0[1], p1[1], false, false);
-        t[0][w] = q0[0];
-        t[2][w] = q0[1];
-        t[1][w] = q1[0];
-        t[3][w] = q1[1];
-      }
-    };
-    transpose(wh, th);
-    transpose(wl, tl);
+    for (int t4 = 0; t4 < 4; ++t4)
+#pragma unroll
+      for (int jb = 0; jb < JB; ++jb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          sStage[(16 * t4 + 4 * g + v) * EM_SPAD + 16 * jb + li] = 16 * jb + li < RP ? U[2][t4][jb][v] : 0.0f;
+    __builtin_amdgcn_s_waitcnt(0xC07F);
+    __builtin_amdgcn_wave_barrier();
 #pragma unroll
     for (int mb = 0; mb < 4; ++mb) {
-      ah[mb] = __builtin_bit_cast(halfx8, th[mb]);
-      al[mb] = __builtin_bit_cast(halfx8, tl[mb]);
+      const float* sp = sStage + (16 * mb + li) * EM_SPAD + 8 * g;
+      floatx4 p0 = *reinterpret_cast<const floatx4*>(sp), p1 = *reinterpret_cast<const floatx4*>(sp + 4);
+      if (8 * g >= 16 * JB) {   // k-slots past the ranks of the factor products
+        p0 = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+        p1 = p0;
+      }
+      float mq = 0.0f;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) mq = fmaxf(mq, fmaxf(fabsf(p0[e]), fabsf(p1[e])));
+      mq = fmaxf(mq, __shfl_xor(mq, 16, 64));
+      mq = fmaxf(mq, __shfl_xor(mq, 32, 64));
+      const int xq = std::min(EM_XMAX, std::max(-EM_XMAX, 15 - __builtin_amdgcn_frexp_expf(mq)));
+      const float sq = ldexpf(1.0f, xq);
+      uint32_t hw[4], lw[4];
+      em_split2(p0[0] * sq, p0[1] * sq, hw[0], lw[0]);
+      em_split2(p0[2] * sq, p0[3] * sq, hw[1], lw[1]);
+      em_split2(p1[0] * sq, p1[1] * sq, hw[2], lw[2]);
+      em_split2(p1[2] * sq, p1[3] * sq, hw[3], lw[3]);
+      ah[mb] = __builtin_bit_cast(halfx8, uint32x4{hw[0], hw[1], hw[2], hw[3]});
+      al[mb] = __builtin_bit_cast(halfx8, uint32x4{lw[0], lw[1], lw[2], lw[3]});
+      if (g == 0) sQ[16 * mb + li] = xq;
+    }
+    __builtin_amdgcn_s_waitcnt(0xC07F);
+    __builtin_amdgcn_wave_barrier();
+    sE[lane] = esum + sQ[lane];   // every scale of this point, undone on its u1 values
+    __builtin_amdgcn_s_waitcnt(0xC07F);
+    __builtin_amdgcn_wave_barrier();
+    // u1 (scaled back by the point exponents) and u2 to the tables, over the stage
+#pragma unroll
+    for (int t4 = 0; t4 < 4; ++t4) {
+      const int4v E = *reinterpret_cast<const int4v*>(&sE[16 * t4 + 4 * g]);
+#pragma unroll
+      for (int jb = 0; jb < JB; ++jb) {
+        const int col = 16 * jb + li;
+        if (col < r1)
+          *reinterpret_cast<floatx4*>(&sU1[col * EM_TSTRIDE + 16 * t4 + 4 * g]) =
+              floatx4{ldexpf(U[0][t4][jb][0], -E[0]), ldexpf(U[0][t4][jb][1], -E[1]), ldexpf(U[0][t4][jb][2], -E[2]),
+                      ldexpf(U[0][t4][jb][3], -E[3])};
+        if (col < r2) *reinterpret_cast<floatx4*>(&sU2[col * EM_TSTRIDE + 16 * t4 + 4 * g]) = U[1][t4][jb];
+      }
     }
     __builtin_amdgcn_s_waitcnt(0xC07F);   // the tables written before they are read
     __builtin_amdgcn_wave_barrier();
   };
-  // LDS reads of column block nb (clamped into the blocks): B operands (k-slot g of column
-  // 16 nb + li, both terms), the column's rows of the u1 and u2 tables, and the products u1 u2
-  // of the lane's 16 points
+
+  // ---- phase 2: LDS reads of column block nb (clamped into the blocks): B operands (k-slot g
+  // of column 16 nb + li, both terms), the column's rows of the u1 and u2 tables, and the
+  // products u1 u2 of the lane's 16 points
   auto loadb = [&](int nb, halfx8 (&b)[2]) {
     const _Float16* bp = sA16 + (std::min(nb, nbs - 1) * 16 + li) * EM_APAD + 8 * g;
     b[0] = *reinterpret_cast<const halfx8*>(bp);
@@ -258,30 +351,13 @@ __global__ __launch_bounds__(EM_THREADS) __attribute__((amdgpu_waves_per_eu(1, 1
 #pragma unroll
       for (int v = 0; v < 4; ++v) f[mb][v] = fmaf(w[mb][v], acc[mb][v], f[mb][v]);
   };
-  // one half-iteration as the scheduler should order it: its LDS reads first, then each MFMA
-  // followed by a share of the VALU work (hints only: no effect on the results)
-  auto schedule = [&]() {
-    __builtin_amdgcn_sched_group_barrier(0x100, 40, 0);   // LDS reads
-#pragma unroll
-    for (int i = 0; i < 12; ++i) {
-      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);   // MFMA
-      __builtin_amdgcn_sched_group_barrier(0x002, 10, 0);  // VALU
-    }
-  };
 
-  // prologue: phase 1 of the wave's first tile on its own
   float cn[3];
   load_coords(0, cn);
-  start(cn);
-  for (int m = 0; m < nst; ++m) step(m);
-  finish();
-  load_coords(1, cn);
-  // the column blocks go in pairs; the first npair_s pairs carry 2 SPH degree steps of the
-  // next tile, the steps left over run after the blocks
-  const int nit = (nbs - 1) / 2, nit_s = std::min(nit, nst / (2 * SPH));
+  const int nit = (nbs - 1) / 2;
   for (int rnd = 0; rnd < a.rounds; ++rnd) {
-    start(cn);                  // phase 1 of the next tile
-    load_coords(rnd + 2, cn);   // coordinates of the tile after it
+    phase1(cn);
+    load_coords(rnd + 1, cn);   // the next tile's coordinates, used by the next round
 #pragma unroll
     for (int mb = 0; mb < 4; ++mb)
 #pragma unroll
@@ -297,44 +373,24 @@ __global__ __launch_bounds__(EM_THREADS) __attribute__((amdgpu_waves_per_eu(1, 1
     colB = loadcol(1);
     loadb(1, bB);
     mfma(bA, accA);
-    int nb = 0, m = 0;
-    auto iteration = [&](auto with_steps) {
+    int nb = 0;
+    for (int it = 0; it < nit; ++it) {
       // block nb + 1 into accB; reads for blocks nb + 1 (u1 u2) and nb + 2 (B, column)
       loadx(colB, x1, x2);
       loadb(nb + 2, bA);
       colA = loadcol(nb + 2);
-      if (decltype(with_steps)::value) loadc(m, cr, crb);
       mfma(bB, accB);
       reduce(accA, wA);
-      if (decltype(with_steps)::value) {
-        stepc(cr, crb);
-#pragma unroll
-        for (int s = 1; s < SPH; ++s) step(m + s);
-      }
       product(x1, x2, wB);
-      schedule();
-      __builtin_amdgcn_sched_barrier(0);
       // block nb + 2 into accA; reads for blocks nb + 2 (u1 u2) and nb + 3 (B, column)
       loadx(colA, x1, x2);
       loadb(nb + 3, bB);
       colB = loadcol(nb + 3);
-      if (decltype(with_steps)::value) loadc(m + SPH, cr, crb);
       mfma(bA, accA);
       reduce(accB, wB);
-      if (decltype(with_steps)::value) {
-        stepc(cr, crb);
-#pragma unroll
-        for (int s = 1; s < SPH; ++s) step(m + SPH + s);
-      }
       product(x1, x2, wA);
-      schedule();
-      __builtin_amdgcn_sched_barrier(0);
       nb += 2;
-      if (decltype(with_steps)::value) m += 2 * SPH;
-    };
-    int it = 0;
-    for (; it < nit_s; ++it) iteration(std::true_type{});
-    for (; it < nit; ++it) iteration(std::false_type{});
+    }
     if (nb + 1 < nbs) {   // one block left over
       loadx(colB, x1, x2);
       product(x1, x2, wB);
@@ -344,7 +400,6 @@ __global__ __launch_bounds__(EM_THREADS) __attribute__((amdgpu_waves_per_eu(1, 1
     } else {
       reduce(accA, wA);
     }
-    for (; m < nst; ++m) step(m);   // degree steps left over
     // the 16 lanes of a lane group hold partial sums of the same points over different columns
 #pragma unroll
     for (int mb = 0; mb < 4; ++mb)
@@ -374,7 +429,6 @@ __global__ __launch_bounds__(EM_THREADS) __attribute__((amdgpu_waves_per_eu(1, 1
         }
       }
     }
-    finish();   // the next tile's tables and A operands
   }
 }
 
@@ -382,19 +436,13 @@ bool eval_mfma_applies(const fst_model* m) {
   if (m->d != 3 || m->has_wavelets()) return false;
   for (int k = 0; k < 3; ++k)
     if (m->rank[k] > kMaxRank || m->degree[k] + 1 > kMaxBasis) return false;
-  return em_lds_bytes(m->rank[0], m->rank[1]) <= EM_LDS_LIMIT;
+  return em_lds_bytes(m->rank[0], m->rank[1], m->rank[2]) <= EM_LDS_LIMIT;
 }
 
-template <int RP, int SPH>
-static void em_launch(const EvalMfmaArgs& a, size_t lds, int blocks, void* stream) {
-  hipLaunchKernelGGL((k_eval_mfma<RP, SPH>), dim3((unsigned)blocks), dim3(EM_THREADS), lds, S(stream), a);
-  check_launch("k_eval_mfma");
-}
 template <int RP>
-static void em_launch_sb(const EvalMfmaArgs& a, int sb, size_t lds, int blocks, void* stream) {
-  if (RP == 32 || sb == 1) em_launch<RP, 1>(a, lds, blocks, stream);
-  else if (sb == 2) em_launch<RP, 2>(a, lds, blocks, stream);
-  else em_launch<RP, 4>(a, lds, blocks, stream);
+static void em_launch(const EvalMfmaArgs& a, size_t lds, int blocks, void* stream) {
+  hipLaunchKernelGGL((k_eval_mfma<RP>), dim3((unsigned)blocks), dim3(EM_THREADS), lds, S(stream), a);
+  check_launch("k_eval_mfma");
 }
 
 void launch_eval_mfma(const fst_model* m, const DeviceModel& dm, int64_t n, const float* x, const float* y,
@@ -418,36 +466,30 @@ void launch_eval_mfma(const fst_model* m, const DeviceModel& dm, int64_t n, cons
   a.r12p = (a.r1 * a.r2 + 15) / 16 * 16;
   a.residual = residual ? 1 : 0;
   a.map = make_map<float>(m);
-  a.nst = 1;
-  for (int k = 0; k < 3; ++k) a.nst = std::max(a.nst, m->degree[k] + 1);
+  for (int k = 0; k < 3; ++k) a.nb[k] = m->degree[k] + 1;
   // monic Legendre recurrence: phi_{m+1} = A_m t phi_m - B_m phi_{m-1} with phi_m = c_m p_m,
-  // c_0 = 1, c_{m+1} = A_m c_m gives p_{m+1} = t p_m - beta_m p_{m-1}, beta_m = B_m / (A_m A_{m-1})
+  // c_0 = 1, c_{m+1} = A_m c_m gives p_{m+1} = t p_m - beta_m p_{m-1}, beta_m = B_m / (A_m A_{m-1});
+  // the kernel runs q_m = 2^m p_m: q_{m+1} = 2 t q_m - 4 beta_m q_{m-1}
   {
     auto A = [](int k) { return std::sqrt((2.0 * k + 1.0) * (2.0 * k + 3.0)) / (k + 1.0); };
     auto B = [](int k) { return k == 0 ? 0.0 : k * std::sqrt(2.0 * k + 3.0) / ((k + 1.0) * std::sqrt(2.0 * k - 1.0)); };
-    double c = 1.0;
+    double c = 1.0, p2 = 1.0;
     for (int k = 0; k < kMaxBasis; ++k) {
-      a.cscale[k] = c;
-      a.beta[k] = k == 0 ? 0.0f : (float)(B(k) / (A(k) * A(k - 1)));
+      a.qscale[k] = c / p2;
+      a.beta4[k] = k == 0 ? 0.0f : (float)(4.0 * B(k) / (A(k) * A(k - 1)));
       c *= A(k);
+      p2 *= 2.0;
     }
   }
-  const size_t lds = em_lds_bytes(a.r1, a.r2);
+  const size_t lds = em_lds_bytes(a.r1, a.r2, a.r3);
   const int64_t per_block = EM_WAVES;
   const int blocks = (int)std::min<int64_t>((a.ntiles + per_block - 1) / per_block, (int64_t)device_cu_count());
   a.rounds = (int)((a.ntiles + (int64_t)blocks * per_block - 1) / ((int64_t)blocks * per_block));
-  // degree steps per column block (pairs of blocks after the first carry them): 1, 2 or 4,
-  // the nearest to steps / blocks
-  const int carriers = std::max(1, (a.r12p / 16 - 1) / 2 * 2);
-  const double ratio = (double)a.nst / carriers;
-  const int rp = pad8(std::max(std::max(a.r1, a.r2), a.r3));
-  // (at RP = 32 more steps per block do not fit the registers)
-  const int sb = rp == 32 || ratio < 1.5 ? 1 : (ratio < 3.0 ? 2 : 4);
-  switch (rp) {
-    case 8: em_launch_sb<8>(a, sb, lds, blocks, stream); break;
-    case 16: em_launch_sb<16>(a, sb, lds, blocks, stream); break;
-    case 24: em_launch_sb<24>(a, sb, lds, blocks, stream); break;
-    default: em_launch_sb<32>(a, sb, lds, blocks, stream); break;
+  switch (em_rp(a.r1, a.r2, a.r3)) {
+    case 8: em_launch<8>(a, lds, blocks, stream); break;
+    case 16: em_launch<16>(a, lds, blocks, stream); break;
+    case 24: em_launch<24>(a, lds, blocks, stream); break;
+    default: em_launch<32>(a, lds, blocks, stream); break;
   }
 }
 
