@@ -26,9 +26,12 @@ COMMON = ["-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-function",
 # Device code: gfx950 only; packed FP32 instructions are disabled on purpose (the compiler
 # would otherwise form v_pk_* FP32 ops from scalar code).
 HIPFLAGS = ["--offload-arch=" + ARCH, "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
-# The one-wave diagonal-block factorisation keeps a 64-entry row in registers, which needs
-# its doubly nested 64-step loops unrolled completely (beyond the default pragma limit).
-FILE_FLAGS = {"fst_linalg.hip": ["-mllvm", "-pragma-unroll-threshold=1000000"]}
+# Per-file device flags.  fst_linalg.hip: the one-wave diagonal-block factorisation keeps a
+# 64-entry row in registers, which needs its doubly nested 64-step loops unrolled completely
+# (beyond the default pragma limit).  fst_eval_mfma.hip: MFMA results in ordinary VGPRs (in
+# the default accumulator registers each would cost a copy before the VALU reduction reads it).
+FILE_FLAGS = {"fst_linalg.hip": ["-mllvm", "-pragma-unroll-threshold=1000000"],
+              "fst_eval_mfma.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
 
 
 def _hipcc() -> str:

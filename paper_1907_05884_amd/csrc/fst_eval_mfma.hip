@@ -17,10 +17,11 @@
 // Each wave takes one 64-point tile per round; the LDS holds one workgroup per CU.
 //   phase 1 (lane l: point l): per mode, the 32 basis values, split and transposed into the
 //     A operands of the four 16-point blocks (v_permlane16_swap, v_permlane32_swap), then
-//     three MFMAs per block and 16-column block of ranks; u3 goes through a per-wave LDS tile
-//     [point][j3] and comes back in the A-operand layout of phase 2 (lane group g: u3[8 g ..
-//     8 g + 7] of a point), where it is scaled and split; u1 (unscaled) and u2 are written to
-//     per-wave tables [j][point];
+//     three MFMAs per block and 16-column block of ranks.  Mode 3 first: u3 goes through a
+//     per-wave LDS tile [point][j3] and comes back in the A-operand layout of phase 2 (lane
+//     group g: u3[8 g .. 8 g + 7] of a point), where it is scaled and split, which completes
+//     the point's exponent; then u1 (unscaled by it) and u2 go to per-wave tables [j][point],
+//     each as soon as it is formed;
 //   phase 2: T of the tile, 16 columns (j1 j2) per block on MFMA, then f += u1 u2 T from the
 //     accumulators, with the LDS reads of the next blocks issued half a block pair ahead.
 //
@@ -204,23 +205,28 @@ __global__ __launch_bounds__(EM_THREADS) __attribute__((amdgpu_waves_per_eu(1, 1
 
   // ---- phase 2 operands of the tile being contracted (point block mb; hi, lo terms)
   halfx8 ah[4], al[4];
-  // phase 1 of the tile whose point coordinates the lane holds in c: factor values on MFMA,
-  // then the tables and the A operands
+  // phase 1 of the tile whose point coordinates the lane holds in c.  Mode 3 first: its factor
+  // values go through the stage into the A operands of phase 2 and fix the point's u3 scale,
+  // which completes the per-point exponent; then modes 1 and 2, each written to its table as
+  // soon as it is formed (one mode's products live at a time)
   auto phase1 = [&](const float (&c)[3]) {
-    floatx4 U[3][4][JB];
+    float tk[3];
+    int xs[3];
     int esum = xa;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      const float t = (c[k] - a.map.lo[k]) * a.map.scale[k] - 1.0f;
-      const int nbk = a.nb[k];
-      const float at = fabsf(t);
+      tk[k] = (c[k] - a.map.lo[k]) * a.map.scale[k] - 1.0f;
+      const float at = fabsf(tk[k]);
       const float rho = fmaxf(1.0f, at + sqrtf(fmaxf(at * at - 1.0f, 0.0f)));   // 1 inside the box
-      const int xs = std::max(EM_XSMIN, 11 - (int)ceilf((float)(nbk - 1) * __log2f(rho)));
-      esum += xs + xc[k];
+      xs[k] = std::max(EM_XSMIN, 11 - (int)ceilf((float)(a.nb[k] - 1) * __log2f(rho)));
+      esum += xs[k] + xc[k];
+    }
+    // the factor values of mode k on MFMA: lane (li, g) gets U_k[points 16 t + 4 g + v][ranks 16 jb + li]
+    auto factor = [&](int k, floatx4 (&U)[4][JB]) {
       uint32_t wh[16], wl[16];
       {
-        const float t2 = t + t;
-        float prev = 0.0f, now = ldexpf(1.0f, xs);
+        const float t2 = tk[k] + tk[k];
+        float prev = 0.0f, now = ldexpf(1.0f, xs[k]);
 #pragma unroll
         for (int pr = 0; pr < 16; ++pr) {
           float x[2];
@@ -251,20 +257,23 @@ __global__ __launch_bounds__(EM_THREADS) __attribute__((amdgpu_waves_per_eu(1, 1
           const halfx8 xl = __builtin_bit_cast(halfx8, uint32x4{tl[t4][0], tl[t4][1], tl[t4][2], tl[t4][3]});
           floatx4 acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(xh, bh, floatx4{0.0f, 0.0f, 0.0f, 0.0f}, 0, 0, 0);
           acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(xh, bl, acc, 0, 0, 0);
-          U[k][t4][jb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(xl, bh, acc, 0, 0, 0);
+          U[t4][jb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(xl, bh, acc, 0, 0, 0);
         }
       }
+    };
+    {
+      floatx4 U[4][JB];
+      factor(2, U);
+      __builtin_amdgcn_s_waitcnt(0xC07F);   // earlier reads of the wave's region done (lgkmcnt(0))
+      // u3 to the stage [point][j3] (zeros from RP on), back as the A operands of phase 2
+#pragma unroll
+      for (int t4 = 0; t4 < 4; ++t4)
+#pragma unroll
+        for (int jb = 0; jb < JB; ++jb)
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+            sStage[(16 * t4 + 4 * g + v) * EM_SPAD + 16 * jb + li] = 16 * jb + li < RP ? U[t4][jb][v] : 0.0f;
     }
-    // lane (li, g) holds U_k[points 16 t + 4 g + v][ranks 16 jb + li]
-    __builtin_amdgcn_s_waitcnt(0xC07F);   // earlier reads of the wave's region done (lgkmcnt(0))
-    // u3 to the stage [point][j3] (zeros from RP on), back as the A operands of phase 2
-#pragma unroll
-    for (int t4 = 0; t4 < 4; ++t4)
-#pragma unroll
-      for (int jb = 0; jb < JB; ++jb)
-#pragma unroll
-        for (int v = 0; v < 4; ++v)
-          sStage[(16 * t4 + 4 * g + v) * EM_SPAD + 16 * jb + li] = 16 * jb + li < RP ? U[2][t4][jb][v] : 0.0f;
     __builtin_amdgcn_s_waitcnt(0xC07F);
     __builtin_amdgcn_wave_barrier();
 #pragma unroll
@@ -296,19 +305,33 @@ __global__ __launch_bounds__(EM_THREADS) __attribute__((amdgpu_waves_per_eu(1, 1
     sE[lane] = esum + sQ[lane];   // every scale of this point, undone on its u1 values
     __builtin_amdgcn_s_waitcnt(0xC07F);
     __builtin_amdgcn_wave_barrier();
-    // u1 (scaled back by the point exponents) and u2 to the tables, over the stage
+    // u1 (scaled back by the point exponents), then u2, to the tables over the stage
+    {
+      floatx4 U[4][JB];
+      factor(0, U);
 #pragma unroll
-    for (int t4 = 0; t4 < 4; ++t4) {
-      const int4v E = *reinterpret_cast<const int4v*>(&sE[16 * t4 + 4 * g]);
+      for (int t4 = 0; t4 < 4; ++t4) {
+        const int4v E = *reinterpret_cast<const int4v*>(&sE[16 * t4 + 4 * g]);
 #pragma unroll
-      for (int jb = 0; jb < JB; ++jb) {
-        const int col = 16 * jb + li;
-        if (col < r1)
-          *reinterpret_cast<floatx4*>(&sU1[col * EM_TSTRIDE + 16 * t4 + 4 * g]) =
-              floatx4{ldexpf(U[0][t4][jb][0], -E[0]), ldexpf(U[0][t4][jb][1], -E[1]), ldexpf(U[0][t4][jb][2], -E[2]),
-                      ldexpf(U[0][t4][jb][3], -E[3])};
-        if (col < r2) *reinterpret_cast<floatx4*>(&sU2[col * EM_TSTRIDE + 16 * t4 + 4 * g]) = U[1][t4][jb];
+        for (int jb = 0; jb < JB; ++jb) {
+          const int col = 16 * jb + li;
+          if (col < r1)
+            *reinterpret_cast<floatx4*>(&sU1[col * EM_TSTRIDE + 16 * t4 + 4 * g]) =
+                floatx4{ldexpf(U[t4][jb][0], -E[0]), ldexpf(U[t4][jb][1], -E[1]), ldexpf(U[t4][jb][2], -E[2]),
+                        ldexpf(U[t4][jb][3], -E[3])};
+        }
       }
+    }
+    {
+      floatx4 U[4][JB];
+      factor(1, U);
+#pragma unroll
+      for (int t4 = 0; t4 < 4; ++t4)
+#pragma unroll
+        for (int jb = 0; jb < JB; ++jb) {
+          const int col = 16 * jb + li;
+          if (col < r2) *reinterpret_cast<floatx4*>(&sU2[col * EM_TSTRIDE + 16 * t4 + 4 * g]) = U[t4][jb];
+        }
     }
     __builtin_amdgcn_s_waitcnt(0xC07F);   // the tables written before they are read
     __builtin_amdgcn_wave_barrier();
