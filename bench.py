@@ -916,11 +916,12 @@ def main():
             "k_eval (reconstruction)": {
                 "bound": "alu", "achieved": eval_flops / avg["eval"] / 1e12, "peak": 157.3, "unit": "TFLOP/s",
                 "frac": eval_flops / avg["eval"] / 157.3e12, "flops_per_launch": eval_flops,
-                "traffic": measured_kernel_bytes("k_eval_mfma<24, 1>"),
-                "note": "k_eval_mfma: the core contraction (2R flop per point) on MFMA 16x16x32 FP16 over "
-                        "two-term FP16 splits of u3 and alpha (hi*hi + hi*lo + lo*hi, FP32 accumulation, "
-                        "22-bit operands: FP32 accuracy), the basis, factor values and weighted reduction on "
-                        "the VALU; peak = the FP32 MFMA and vector peak, a conservative roof"},
+                "traffic": measured_kernel_bytes("k_eval_mfma<24>"),
+                "note": "k_eval_mfma: the factor functions (basis times coefficients) and the core "
+                        "contraction (2R flop per point) on MFMA 16x16x32 FP16 over two-term FP16 splits "
+                        "(hi*hi + hi*lo + lo*hi, FP32 accumulation, 22-bit operands: FP32 accuracy), the "
+                        "basis recurrence and the weighted reduction on the VALU; peak = the FP32 MFMA and "
+                        "vector peak, a conservative roof"},
             "grid preview 512^3 FP32 (fst_eval_grid: k_factor_eval + 3 x k_mode_product)": {
                 "bound": "hbm", "achieved": grid_bytes / t_grid / 1e9, "peak": 8000.0, "unit": "GB/s",
                 "frac": grid_bytes / t_grid / 8e12, "ms": t_grid * 1e3, "bytes_per_launch": grid_bytes,
