@@ -8,11 +8,14 @@
 // lo*hi, the dropped lo*lo is below 2^-22 of the product): the factor functions of eq. (2)
 // (basis against coefficients, per mode) and T (u3 against the core).  FP32 MFMA would take
 // three to four times the matrix-core time and, on this chip, does not run alongside the VALU
-// work of the wave, while the 16-bit MFMAs do.  Powers of two keep every term in FP16 range:
-// the basis of a point from its growth bound (the factor-value kernel's scaled monic
-// recurrence, q_m = 2^m p_m), the coefficients per mode and the core per workgroup (largest
-// entry to [2^14, 2^15)), u3 per point (its largest value likewise).  All of them are undone
-// at once, exactly, by one per-point exponent applied to the u1 table with ldexp.
+// work of the wave, while the 16-bit MFMAs do.  The factor functions are evaluated in the
+// Chebyshev basis, with the coefficients converted when the model is placed on the device
+// (T_{i+1} = 2 t T_i - T_{i-1}: one VALU operation per degree; the polynomials are the same).
+// Powers of two keep every term in FP16 range: the basis of a point from its growth bound
+// (|T_i(t)| <= rho^i), the coefficients per mode (applied with the conversion) and the core
+// per workgroup (largest entry to [2^14, 2^15)), u3 per point (its largest value likewise).
+// All of them are undone at once, exactly, by one per-point exponent applied to the u1 table
+// with ldexp.
 //
 // Each wave takes one 64-point tile per round; the LDS holds one workgroup per CU.
 //   phase 1 (lane l: point l): per mode, the 32 basis values, split and transposed into the
@@ -42,7 +45,7 @@
 namespace fst {
 
 constexpr int EM_WAVES = 4, EM_THREADS = 64 * EM_WAVES, EM_TSTRIDE = 68, EM_APAD = 40, EM_CPAD = 40, EM_SPAD = 36;
-// scale exponents: point basis in [-100, 11] (rows up to |t| of about 6 stay in range),
+// scale exponents: point basis in [-100, 14] (rows up to |t| of about 6 stay in range),
 // coefficients in [-20, 26], core and u3 in [-60, 60]; the per-point exponent is applied with
 // ldexp, so their sum needs no range of its own
 constexpr int EM_XSMIN = -100, EM_XCMIN = -20, EM_XCMAX = 26, EM_XMAX = 60;
@@ -51,15 +54,17 @@ constexpr size_t EM_LDS_LIMIT = 160 * 1024;
 struct EvalMfmaArgs {
   const float *x, *y, *z, *v;
   const int32_t* idx;
-  const float* coefs;   // [3][kMaxBasis][kMaxRank]
+  const float* coefs;   // Chebyshev coefficients D 2^xc, [3][kMaxBasis][kMaxRank]
   const float* core;    // R, C order
   float* out;
   int64_t n, ntiles;
   int32_t r1, r2, r3, r12p, residual, rounds;
   int32_t nb[3];              // n_k = degree + 1
+  int32_t xc[3];              // the coefficients' scale exponents
+  // -1, passed at run time: the compiler then forms lo = x - hi as one mixed-precision FMA
+  // (v_fma_mix, hi read as FP16) instead of a conversion back to FP32 and a subtraction
+  float minus_one;
   ModeMap<float> map;
-  float beta4[kMaxBasis];     // 4 beta_m of the monic recurrence (beta_0 = 0)
-  double qscale[kMaxBasis];   // c_m 2^-m: phi_m = c_m 2^-m q_m
 };
 
 typedef _Float16 half2v __attribute__((ext_vector_type(2)));
@@ -76,12 +81,12 @@ static size_t em_lds_bytes(int r1, int r2, int r3) {
   return 480 * rp + 16 + 160 * r12p + 8 * r12p + 16 + EM_WAVES * em_wave_bytes(r1, r2);
 }
 
-// hi: x with its low 13 mantissa bits cleared (exact in FP16 in range), lo = x - hi (exact)
-__device__ __forceinline__ void em_split2(float x0, float x1, uint32_t& hi, uint32_t& lo) {
-  const float h0 = __builtin_bit_cast(float, __builtin_bit_cast(uint32_t, x0) & 0xFFFFE000u);
-  const float h1 = __builtin_bit_cast(float, __builtin_bit_cast(uint32_t, x1) & 0xFFFFE000u);
-  hi = __builtin_bit_cast(uint32_t, half2v{(_Float16)h0, (_Float16)h1});
-  lo = __builtin_bit_cast(uint32_t, half2v{(_Float16)(x0 - h0), (_Float16)(x1 - h1)});
+// hi = x rounded to FP16, lo = x - hi (exact in FP32) rounded to FP16; m1 = -1
+__device__ __forceinline__ void em_split2(float x0, float x1, float m1, uint32_t& hi, uint32_t& lo) {
+  const half2v h = {(_Float16)x0, (_Float16)x1};
+  hi = __builtin_bit_cast(uint32_t, h);
+  lo = __builtin_bit_cast(uint32_t, half2v{(_Float16)__builtin_fmaf((float)h[0], m1, x0),
+                                           (_Float16)__builtin_fmaf((float)h[1], m1, x1)});
 }
 
 // RP: ranks padded to 8 (JB = 16-column blocks of the factor products)
@@ -106,30 +111,14 @@ __global__ __launch_bounds__(EM_THREADS) __attribute__((amdgpu_waves_per_eu(1, 1
   float* sU2 = sU1 + r1 * EM_TSTRIDE;                  // [r2][68]
   float* sStage = sU1;                                  // [64][36], before the tables are written
 
-  // ---- staging: the scales of the core and of the coefficients (largest entry to [2^14, 2^15))
+  // ---- staging: the scale of the core (largest entry to [2^14, 2^15)); the coefficients come
+  // scaled
   {
-    float amax = 0.0f, cmax[3] = {0.0f, 0.0f, 0.0f};
+    float amax = 0.0f;
     for (int e = threadIdx.x; e < R12 * r3; e += EM_THREADS) amax = fmaxf(amax, fabsf(a.core[e]));
-    for (int e = threadIdx.x; e < kMaxBasis * kMaxRank; e += EM_THREADS) {
-      const int m = e / kMaxRank, j = e % kMaxRank;
 #pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        const int rk = k == 0 ? r1 : (k == 1 ? r2 : r3);
-        if (m < a.nb[k] && j < rk)
-          cmax[k] = fmaxf(cmax[k], fabsf((float)(a.qscale[m] * a.coefs[(k * kMaxBasis + m) * kMaxRank + j])));
-      }
-    }
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) {
-      amax = fmaxf(amax, __shfl_xor(amax, o, 64));
-#pragma unroll
-      for (int k = 0; k < 3; ++k) cmax[k] = fmaxf(cmax[k], __shfl_xor(cmax[k], o, 64));
-    }
-    if (lane == 0) {
-      sRed[wave] = amax;
-      // coefficient maxima of this wave, combined below through the scale slots
-      sXc[wave < 3 ? wave : 3] = 0;
-    }
+    for (int o = 32; o >= 1; o >>= 1) amax = fmaxf(amax, __shfl_xor(amax, o, 64));
+    if (lane == 0) sRed[wave] = amax;
     __syncthreads();
     if (threadIdx.x == 0) {
       float v = 0.0f;
@@ -137,22 +126,12 @@ __global__ __launch_bounds__(EM_THREADS) __attribute__((amdgpu_waves_per_eu(1, 1
       sXc[3] = std::min(EM_XMAX, std::max(-EM_XMAX, 15 - __builtin_amdgcn_frexp_expf(v)));
     }
     __syncthreads();
-    // per-mode coefficient maxima: each wave's lane 0 posts its three maxima in turn
-    for (int k = 0; k < 3; ++k) {
-      if (lane == 0) sRed[wave] = cmax[k];
-      __syncthreads();
-      if (threadIdx.x == 0) {
-        float v = 0.0f;
-        for (int w = 0; w < EM_WAVES; ++w) v = fmaxf(v, sRed[w]);
-        sXc[k] = std::max(EM_XCMIN, std::min(EM_XCMAX, 15 - __builtin_amdgcn_frexp_expf(v)));
-      }
-      __syncthreads();
-    }
   }
   const int xa = sXc[3];
   int xc[3];
 #pragma unroll
-  for (int k = 0; k < 3; ++k) xc[k] = sXc[k];
+  for (int k = 0; k < 3; ++k) xc[k] = a.xc[k];
+  const float m1 = a.minus_one;
   {
     const float sa = ldexpf(1.0f, xa);
     for (int e = threadIdx.x; e < plane; e += EM_THREADS) {
@@ -165,9 +144,7 @@ __global__ __launch_bounds__(EM_THREADS) __attribute__((amdgpu_waves_per_eu(1, 1
     for (int e = threadIdx.x; e < 3 * RP * EM_CPAD; e += EM_THREADS) {
       const int k = e / (RP * EM_CPAD), j = (e / EM_CPAD) % RP, m = e % EM_CPAD;
       const int rk = k == 0 ? r1 : (k == 1 ? r2 : r3);
-      const float x = (m < a.nb[k] && j < rk)
-                          ? (float)(a.qscale[m] * a.coefs[(k * kMaxBasis + m) * kMaxRank + j]) * ldexpf(1.0f, xc[k])
-                          : 0.0f;
+      const float x = (m < a.nb[k] && j < rk) ? a.coefs[(k * kMaxBasis + m) * kMaxRank + j] : 0.0f;
       const _Float16 hi = (_Float16)x;
       sCB[e] = hi;
       sCB[3 * RP * EM_CPAD + e] = (_Float16)(x - (float)hi);
@@ -218,7 +195,7 @@ __global__ __launch_bounds__(EM_THREADS) __attribute__((amdgpu_waves_per_eu(1, 1
       tk[k] = (c[k] - a.map.lo[k]) * a.map.scale[k] - 1.0f;
       const float at = fabsf(tk[k]);
       const float rho = fmaxf(1.0f, at + sqrtf(fmaxf(at * at - 1.0f, 0.0f)));   // 1 inside the box
-      xs[k] = std::max(EM_XSMIN, 11 - (int)ceilf((float)(a.nb[k] - 1) * __log2f(rho)));
+      xs[k] = std::max(EM_XSMIN, 14 - (int)ceilf((float)(a.nb[k] - 1) * __log2f(rho)));
       esum += xs[k] + xc[k];
     }
     // the factor values of mode k on MFMA: lane (li, g) gets U_k[points 16 t + 4 g + v][ranks 16 jb + li]
@@ -235,11 +212,11 @@ __global__ __launch_bounds__(EM_THREADS) __attribute__((amdgpu_waves_per_eu(1, 1
             const int m = 2 * pr + i;
             // past n_k the coefficients are zero: the value only has to stay finite in FP16
             x[i] = __builtin_amdgcn_fmed3f(now, -65504.0f, 65504.0f);
-            const float next = fmaf(t2, now, -a.beta4[m] * prev);
+            const float next = m == 0 ? tk[k] * now : fmaf(t2, now, -prev);
             prev = now;
             now = next;
           }
-          em_split2(x[0], x[1], wh[pr], wl[pr]);
+          em_split2(x[0], x[1], m1, wh[pr], wl[pr]);
         }
       }
       uint32_t th[4][4], tl[4][4];
@@ -292,10 +269,10 @@ __global__ __launch_bounds__(EM_THREADS) __attribute__((amdgpu_waves_per_eu(1, 1
       const int xq = std::min(EM_XMAX, std::max(-EM_XMAX, 15 - __builtin_amdgcn_frexp_expf(mq)));
       const float sq = ldexpf(1.0f, xq);
       uint32_t hw[4], lw[4];
-      em_split2(p0[0] * sq, p0[1] * sq, hw[0], lw[0]);
-      em_split2(p0[2] * sq, p0[3] * sq, hw[1], lw[1]);
-      em_split2(p1[0] * sq, p1[1] * sq, hw[2], lw[2]);
-      em_split2(p1[2] * sq, p1[3] * sq, hw[3], lw[3]);
+      em_split2(p0[0] * sq, p0[1] * sq, m1, hw[0], lw[0]);
+      em_split2(p0[2] * sq, p0[3] * sq, m1, hw[1], lw[1]);
+      em_split2(p1[0] * sq, p1[1] * sq, m1, hw[2], lw[2]);
+      em_split2(p1[2] * sq, p1[3] * sq, m1, hw[3], lw[3]);
       ah[mb] = __builtin_bit_cast(halfx8, uint32x4{hw[0], hw[1], hw[2], hw[3]});
       al[mb] = __builtin_bit_cast(halfx8, uint32x4{lw[0], lw[1], lw[2], lw[3]});
       if (g == 0) sQ[16 * mb + li] = xq;
@@ -478,7 +455,8 @@ void launch_eval_mfma(const fst_model* m, const DeviceModel& dm, int64_t n, cons
   a.z = z;
   a.v = v;
   a.idx = idx;
-  a.coefs = (const float*)dm.coefs;
+  if (!dm.cheb) fail(FST_E_UNSUPPORTED, "MFMA reconstruction: no Chebyshev coefficients on the device");
+  a.coefs = (const float*)dm.cheb;
   a.core = (const float*)dm.core;
   a.out = out;
   a.n = n;
@@ -490,20 +468,8 @@ void launch_eval_mfma(const fst_model* m, const DeviceModel& dm, int64_t n, cons
   a.residual = residual ? 1 : 0;
   a.map = make_map<float>(m);
   for (int k = 0; k < 3; ++k) a.nb[k] = m->degree[k] + 1;
-  // monic Legendre recurrence: phi_{m+1} = A_m t phi_m - B_m phi_{m-1} with phi_m = c_m p_m,
-  // c_0 = 1, c_{m+1} = A_m c_m gives p_{m+1} = t p_m - beta_m p_{m-1}, beta_m = B_m / (A_m A_{m-1});
-  // the kernel runs q_m = 2^m p_m: q_{m+1} = 2 t q_m - 4 beta_m q_{m-1}
-  {
-    auto A = [](int k) { return std::sqrt((2.0 * k + 1.0) * (2.0 * k + 3.0)) / (k + 1.0); };
-    auto B = [](int k) { return k == 0 ? 0.0 : k * std::sqrt(2.0 * k + 3.0) / ((k + 1.0) * std::sqrt(2.0 * k - 1.0)); };
-    double c = 1.0, p2 = 1.0;
-    for (int k = 0; k < kMaxBasis; ++k) {
-      a.qscale[k] = c / p2;
-      a.beta4[k] = k == 0 ? 0.0f : (float)(4.0 * B(k) / (A(k) * A(k - 1)));
-      c *= A(k);
-      p2 *= 2.0;
-    }
-  }
+  for (int k = 0; k < 3; ++k) a.xc[k] = dm.cheb_xc[k];
+  a.minus_one = -1.0f;
   const size_t lds = em_lds_bytes(a.r1, a.r2, a.r3);
   const int64_t per_block = EM_WAVES;
   const int blocks = (int)std::min<int64_t>((a.ntiles + per_block - 1) / per_block, (int64_t)device_cu_count());

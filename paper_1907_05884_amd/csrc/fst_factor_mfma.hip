@@ -4,20 +4,23 @@
 //
 // Per 64 sampled rows and mode, U_k (64 x r_k) = Phi (64 x n_k) C_k (n_k x r_k) is a GEMM with
 // K = n_k <= 32: one step of MFMA 16x16x32 FP16 per 16 x 16 block, over operands split in two
-// FP16 terms each (x = hi + lo, 22 significant bits; for the basis hi is x truncated to 11
-// significant bits, so that hi and lo = x - hi are exact; hi*hi + hi*lo + lo*hi, FP32
-// accumulation; the dropped lo*lo is below 2^-22 of the product).  FP32 MFMA would take four
-// times the matrix-core time and, on this chip, does not run alongside the VALU work of the
-// wave (the basis recurrence), while the 16-bit MFMAs do.
+// FP16 terms each (x = hi + lo: hi = x rounded to FP16, lo = x - hi exact in FP32 and rounded
+// to FP16, 22 significant bits; hi*hi + hi*lo + lo*hi, FP32 accumulation; the dropped lo*lo is
+// below 2^-22 of the product).  FP32 MFMA would take four times the matrix-core time and, on
+// this chip, does not run alongside the VALU work of the wave (the basis recurrence), while
+// the 16-bit MFMAs do.
 //
-// Basis: phi_m = c_m p_m with p_m the monic Legendre polynomials; the kernel runs
-//   q_{m+1} = 2 t q_m - 4 beta_m q_{m-1},   q_m = 2^m p_m,
-// two VALU operations per degree, and folds c_m 2^-m into the staged coefficients.  |q_m(t)|
-// is at most about 10 rho^m with rho = |t| + sqrt(t^2 - 1) (rho = 1 inside the box), so
-// starting the recurrence at 2^xs with xs = 11 - ceil((n_k - 1) log2 rho) keeps every value the
-// mode uses below 2^15, in FP16 range (values past n_k, whose coefficients are zero, are
-// clamped into it).  The coefficients of a mode are scaled by one power of two (largest to
-// [2^14, 2^15)); both scales are undone on the accumulators through a per-point factor.
+// Basis: a factor function of eq. (2) is a polynomial of degree n_k - 1; the kernel evaluates
+// it in the Chebyshev basis, sum_m C[m, j] phi_m = sum_i D[i, j] T_i, with D formed in FP64
+// when the model is placed on the device (phi_m = sqrt(2m+1) P_m = sum_i L[m, i] T_i,
+// D = L^T C; sum_i |D_i| <= sum_m sqrt(2m+1) |C_m|, so the Chebyshev form is no worse
+// conditioned than the Legendre one).  T_{i+1} = 2 t T_i - T_{i-1} is one VALU operation per
+// degree (the Legendre recurrence takes two).  |T_i(t)| <= rho^i with
+// rho = |t| + sqrt(t^2 - 1) (rho = 1 inside the box), so starting the recurrence at 2^xs with
+// xs = 14 - ceil((n_k - 1) log2 rho) keeps every value the mode uses below 2^15, in FP16
+// range (values past n_k, whose coefficients are zero, are clamped into it).  The
+// coefficients of a mode come scaled by one power of two (largest to [2^14, 2^15), applied
+// with D); both scales are undone on the accumulators through a per-point factor.
 //
 // Per wave and round of 64 rows, lane l takes row q0 + l and, for each mode:
 //   1. runs the recurrence for the 32 basis values of its row and splits them into FP16 terms
@@ -63,54 +66,21 @@ struct FactorMfmaArgs {
   const TIn* c[kMaxModes];
   const TIn* v;
   const int32_t* idx;
-  const float* coefs;   // [kMaxModes][kMaxBasis][kMaxRank]
+  const float* coefs;   // Chebyshev coefficients D 2^xc, [kMaxModes][kMaxBasis][kMaxRank]
   float* U;
   float* vs;
   int64_t mrows, nrounds, ubytes;
   int32_t d;
   int32_t rank[kMaxModes], nb[kMaxModes], off[kMaxModes];
+  int32_t xc[kMaxModes];   // the coefficients' scale exponents
+  // -1, passed at run time: the compiler then forms lo = x - hi as one mixed-precision FMA
+  // (v_fma_mix_f32, hi read as FP16) instead of a conversion back to FP32 and a subtraction
+  float minus_one;
   ModeMap<float> map;
 };
 
-// The orthonormal Legendre basis satisfies phi_{m+1} = A_m t phi_m - B_m phi_{m-1} with
-// A_m = sqrt((2m+1)(2m+3)) / (m+1), B_m = m sqrt(2m+3) / ((m+1) sqrt(2m-1)).  Writing
-// phi_m = c_m p_m with c_0 = 1, c_{m+1} = A_m c_m gives the monic recurrence
-// p_{m+1} = t p_m - beta_m p_{m-1}, beta_m = B_m / (A_m A_{m-1}).  Square roots by Newton's
-// iteration at compile time.
-constexpr double fm_sqrt(double x) {
-  double r = x > 1.0 ? x : 1.0;
-  for (int i = 0; i < 200; ++i) r = 0.5 * (r + x / r);
-  return r;
-}
-constexpr double fm_rec_a(int m) { return fm_sqrt((2.0 * m + 1.0) * (2.0 * m + 3.0)) / (m + 1.0); }
-constexpr double fm_rec_b(int m) {
-  return m == 0 ? 0.0 : m * fm_sqrt(2.0 * m + 3.0) / ((m + 1.0) * fm_sqrt(2.0 * m - 1.0));
-}
-struct FmMonic {
-  float beta4[kMaxBasis];   // 4 beta_m (beta_0 = 0)
-  double qscale[kMaxBasis];  // c_m 2^-m: phi_m = c_m 2^-m q_m
-};
-constexpr FmMonic fm_monic() {
-  FmMonic t{};
-  double c = 1.0, p2 = 1.0;
-  for (int m = 0; m < kMaxBasis; ++m) {
-    t.qscale[m] = c / p2;
-    t.beta4[m] = m == 0 ? 0.0f : (float)(4.0 * fm_rec_b(m) / (fm_rec_a(m) * fm_rec_a(m - 1)));
-    c *= fm_rec_a(m);
-    p2 *= 2.0;
-  }
-  return t;
-}
-// c_m 2^-m for the coefficient staging (a plain device table: indexed at run time)
-__constant__ double fm_qscale_table[kMaxBasis] = {
-#define FM_S(m) fm_monic().qscale[m]
-    FM_S(0),  FM_S(1),  FM_S(2),  FM_S(3),  FM_S(4),  FM_S(5),  FM_S(6),  FM_S(7),  FM_S(8),  FM_S(9),  FM_S(10),
-    FM_S(11), FM_S(12), FM_S(13), FM_S(14), FM_S(15), FM_S(16), FM_S(17), FM_S(18), FM_S(19), FM_S(20), FM_S(21),
-    FM_S(22), FM_S(23), FM_S(24), FM_S(25), FM_S(26), FM_S(27), FM_S(28), FM_S(29), FM_S(30), FM_S(31)};
-#undef FM_S
-static_assert(kMaxBasis == 32, "scale table size");
 constexpr int FM_BPAD = 40;   // halfs per staged coefficient row (80 bytes)
-// scale exponents: xs in [-100, 11] (rows up to |t| of about 6 stay in FP16 range, about
+// scale exponents: xs in [-100, 14] (rows up to |t| of about 6 stay in FP16 range, about
 // where FP32 values of degree 31 overflow too), xc in [-20, 26] (largest coefficient between
 // 2^-12 and 2^34); the unscale 2^-(xs + xc) is then a normal float
 constexpr int FM_XSMIN = -100, FM_XCMIN = -20, FM_XCMAX = 26;
@@ -127,40 +97,10 @@ __global__ __launch_bounds__(FM_THREADS) __attribute__((amdgpu_waves_per_eu(D ==
   __shared__ __align__(16) float sPark[FM_WAVES][FM_PARK][D][64];
   __shared__ __align__(16) float sUs[FM_WAVES][64];            // per-point unscale of the mode
   __shared__ __align__(16) float sT[FM_WAVES][16][FM_TPAD];      // column block on its way out
-  __shared__ float sRed[FM_WAVES][D];
-  __shared__ int sXc[D];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, li = lane & 15, g = lane >> 4;
-  // the coefficient scale of each mode: the largest |c_m 2^-m C[m][j]| to [2^14, 2^15)
-  {
-    float mx[D];
-#pragma unroll
-    for (int k = 0; k < D; ++k) mx[k] = 0.0f;
-    for (int e = threadIdx.x; e < 32 * 32; e += FM_THREADS) {
-      const int m = e / 32, j = e % 32;
-#pragma unroll
-      for (int k = 0; k < D; ++k)
-        if (m < a.nb[k] && j < a.rank[k])
-          mx[k] = fmaxf(mx[k], fabsf((float)(fm_qscale_table[m] * a.coefs[(k * kMaxBasis + m) * kMaxRank + j])));
-    }
-#pragma unroll
-    for (int k = 0; k < D; ++k) {
-#pragma unroll
-      for (int o = 32; o >= 1; o >>= 1) mx[k] = fmaxf(mx[k], __shfl_xor(mx[k], o, 64));
-      if (lane == 0) sRed[wave][k] = mx[k];
-    }
-    __syncthreads();
-    if (threadIdx.x < D) {
-      float v = 0.0f;
-      for (int w = 0; w < FM_WAVES; ++w) v = fmaxf(v, sRed[w][threadIdx.x]);
-      sXc[threadIdx.x] = std::max(FM_XCMIN, std::min(FM_XCMAX, 15 - __builtin_amdgcn_frexp_expf(v)));
-    }
-    __syncthreads();
-  }
   for (int e = threadIdx.x; e < D * 32 * FM_BPAD; e += FM_THREADS) {
     const int k = e / (32 * FM_BPAD), j = (e / FM_BPAD) % 32, m = e % FM_BPAD;
-    const float x = (m < a.nb[k] && j < a.rank[k])
-                        ? (float)(fm_qscale_table[m] * a.coefs[(k * kMaxBasis + m) * kMaxRank + j]) * ldexpf(1.0f, sXc[k])
-                        : 0.0f;
+    const float x = (m < a.nb[k] && j < a.rank[k]) ? a.coefs[(k * kMaxBasis + m) * kMaxRank + j] : 0.0f;
     const _Float16 hi = (_Float16)x;
     sB[0][k][j][m] = hi;
     sB[1][k][j][m] = (_Float16)(x - (float)hi);
@@ -173,25 +113,25 @@ __global__ __launch_bounds__(FM_THREADS) __attribute__((amdgpu_waves_per_eu(D ==
   __syncthreads();
   int xc[D];
 #pragma unroll
-  for (int k = 0; k < D; ++k) xc[k] = sXc[k];
+  for (int k = 0; k < D; ++k) xc[k] = a.xc[k];
   // U through a buffer resource: a store whose offset is past the end (kFmSkip) is dropped by
   // the hardware, so the stores need no branches
   const __amdgpu_buffer_rsrc_t urs = __builtin_amdgcn_make_buffer_rsrc(
       (void*)a.U, (short)0, (int)(uint32_t)(a.ubytes), 0x00020000);
   // Each wave takes up to FM_PARK rounds per pass (rounds w, w + W, .. of the pass, W = all
   // waves of the grid): their coordinates are loaded first and parked in LDS, then the rounds
-  // are computed and stored with no load in between, so no wait on the stores is needed until
-  // the next pass.
+  // are computed and stored with no load in between (loads and stores share one counter of
+  // outstanding requests, so a load after stores waits for them).
   float (*park)[D][64] = sPark[wave];
   float* us = sUs[wave];
   float (*tt)[FM_TPAD] = sT[wave];
   const int64_t wtot = (int64_t)gridDim.x * FM_WAVES, w = (int64_t)blockIdx.x * FM_WAVES + wave;
-  for (int64_t pass0 = 0; pass0 < a.nrounds; pass0 += wtot * FM_PARK) {
+  for (int64_t pass0 = w; pass0 < a.nrounds; pass0 += wtot * FM_PARK) {
     int nr = 0;
     uint32_t rows[FM_PARK];
 #pragma unroll
     for (int i = 0; i < FM_PARK; ++i) {   // rows past the end read the last row (never stored)
-      const int64_t r = pass0 + w + i * wtot;
+      const int64_t r = pass0 + wtot * i;
       const int64_t q = min(r * FM_ROWS + lane, a.mrows - 1);
       rows[i] = a.idx ? (uint32_t)a.idx[q] : (uint32_t)q;
       nr += r < a.nrounds ? 1 : 0;
@@ -201,14 +141,13 @@ __global__ __launch_bounds__(FM_THREADS) __attribute__((amdgpu_waves_per_eu(D ==
 #pragma unroll
       for (int k = 0; k < D; ++k) park[i][k][lane] = (float)a.c[k][rows[i]];
     for (int i = 0; i < nr; ++i) {
-      const int64_t r = pass0 + w + i * wtot;
+      const int64_t r = pass0 + wtot * i;
       float cur[D];
 #pragma unroll
       for (int k = 0; k < D; ++k) cur[k] = park[i][k][lane];
       const int64_t q0 = r * FM_ROWS;
 #pragma unroll
       for (int k = 0; k < D; ++k) {
-        constexpr FmMonic rec = fm_monic();
         const float t = (cur[k] - a.map.lo[k]) * a.map.scale[k] - 1.0f;
         // 1. the basis of this lane's row, started at 2^xs, split into FP16 terms.  The scale is
         //    set by the mode's own degree n_k - 1; a mode with n_k < NQ runs the recurrence on
@@ -217,11 +156,12 @@ __global__ __launch_bounds__(FM_THREADS) __attribute__((amdgpu_waves_per_eu(D ==
         const int nbk = a.nb[k];
         const float at = fabsf(t);
         const float rho = fmaxf(1.0f, at + sqrtf(fmaxf(at * at - 1.0f, 0.0f)));   // 1 inside the box
-        const int xs = std::max(FM_XSMIN, 11 - (int)ceilf((float)(nbk - 1) * __log2f(rho)));
+        const int xs = std::max(FM_XSMIN, 14 - (int)ceilf((float)(nbk - 1) * __log2f(rho)));
         uint32_t wh[16], wl[16];
         auto basis = [&](auto full) {
           const float t2 = t + t;
           float prev = 0.0f, now = ldexpf(1.0f, xs);
+          const float m1 = a.minus_one;
 #pragma unroll
           for (int pr = 0; pr < 16; ++pr) {
             if (2 * pr < NQ) {
@@ -231,15 +171,15 @@ __global__ __launch_bounds__(FM_THREADS) __attribute__((amdgpu_waves_per_eu(D ==
                 const int m = 2 * pr + i;
                 // past n_k the coefficients are zero; the value only has to stay finite in FP16
                 x[i] = decltype(full)::value ? now : __builtin_amdgcn_fmed3f(now, -65504.0f, 65504.0f);
-                const float next = fmaf(t2, now, -rec.beta4[m] * prev);
+                const float next = m == 0 ? t * now : fmaf(t2, now, -prev);
                 prev = now;
                 now = next;
               }
-              // hi: x with its low 13 mantissa bits cleared (exact in FP16), lo = x - hi (exact)
-              const float h0 = __builtin_bit_cast(float, __builtin_bit_cast(uint32_t, x[0]) & 0xFFFFE000u);
-              const float h1 = __builtin_bit_cast(float, __builtin_bit_cast(uint32_t, x[1]) & 0xFFFFE000u);
-              wh[pr] = __builtin_bit_cast(uint32_t, fm_half2{(_Float16)h0, (_Float16)h1});
-              wl[pr] = __builtin_bit_cast(uint32_t, fm_half2{(_Float16)(x[0] - h0), (_Float16)(x[1] - h1)});
+              // hi = x rounded to FP16, lo = x - hi (exact in FP32), then rounded to FP16
+              const fm_half2 h = {(_Float16)x[0], (_Float16)x[1]};
+              wh[pr] = __builtin_bit_cast(uint32_t, h);
+              wl[pr] = __builtin_bit_cast(uint32_t, fm_half2{(_Float16)__builtin_fmaf((float)h[0], m1, x[0]),
+                                                             (_Float16)__builtin_fmaf((float)h[1], m1, x[1])});
             } else {
               wh[pr] = 0u;
               wl[pr] = 0u;
@@ -333,8 +273,7 @@ bool factor_eval_mfma_applies(const fst_model* m, int64_t mrows) {
   return true;
 }
 
-// one resident workgroup per slot (grid-stride over the rounds): as many workgroups as the
-// occupancy of the instance allows on every CU
+// a persistent grid: as many workgroups as the occupancy of the instance allows on every CU
 template <typename TIn, int D, int JB, int NQ, bool VEC>
 static void launch_one(const FactorMfmaArgs<TIn>& a, void* stream) {
   static std::atomic<int> occupancy(0);
@@ -370,7 +309,8 @@ void launch_factor_eval_mfma(const fst_model* m, const DeviceModel& dm, const vo
   FactorMfmaArgs<float> a;
   a.v = (const float*)v;
   a.idx = idx;
-  a.coefs = (const float*)dm.coefs;
+  if (!dm.cheb) fail(FST_E_UNSUPPORTED, "factor evaluation on MFMA: no Chebyshev coefficients on the device");
+  a.coefs = (const float*)dm.cheb;
   a.U = (float*)U;
   a.vs = (float*)vs;
   a.mrows = mrows;
@@ -390,6 +330,8 @@ void launch_factor_eval_mfma(const fst_model* m, const DeviceModel& dm, const vo
     nbmax = std::max(nbmax, a.nb[k]);
   }
   a.map = make_map<float>(m);
+  a.minus_one = -1.0f;
+  for (int k = 0; k < kMaxModes; ++k) a.xc[k] = dm.cheb_xc[k];
   const int jb = (rmax + 15) / 16, nq = nbmax;
   const bool vec = mrows % 4 == 0;
   if (m->d == 3) {

@@ -35,6 +35,12 @@ void set_last_error(const std::string& msg);
 // kMaxBasis x kMaxRank per mode (kMaxModes slots, unused modes zero), and the core in C order.
 struct DeviceModel {
   void* coefs = nullptr;   // kMaxModes * kMaxBasis * kMaxRank elements of the dtype
+  // FP32 models without wavelets: the factor functions in the Chebyshev basis (same layout,
+  // D[i][j] = sum_m L[m][i] C[m][j] for phi_m = sum_i L[m][i] T_i, formed in FP64)
+  void* cheb = nullptr;
+  // each mode's scale exponent xc of cheb: the stored values are D 2^xc, the largest |D| of
+  // the mode brought to [2^14, 2^15) (xc clamped to [-20, 26])
+  int32_t cheb_xc[kMaxModes] = {0, 0, 0, 0};
   void* detail = nullptr;  // models with wavelets: kMaxModes * kMaxDetail * kMaxRank detail coefficients
   void* wave = nullptr;    // models with wavelets: kMaxModes * kWaveTable mother-wavelet coefficients
   void* core = nullptr;    // R elements of the dtype

@@ -9,6 +9,7 @@
 fst_model::~fst_model() {
   for (auto& kv : dev) {
     fst::device_free(kv.second.coefs);
+    fst::device_free(kv.second.cheb);
     fst::device_free(kv.second.core);
     fst::device_free(kv.second.core64);
     fst::device_free(kv.second.detail);
@@ -106,6 +107,49 @@ static void pack_model(const fst_model* m, std::vector<T>& coefs, std::vector<T>
   }
 }
 
+// The factor functions of eq. (2) in the Chebyshev basis: phi_m = sqrt(2m+1) P_m =
+// sum_i L[m][i] T_i, with P_m = sum_i a[m][i] T_i from (m+1) P_{m+1} = (2m+1) t P_m - m P_{m-1}
+// and t T_0 = T_1, t T_i = (T_{i+1} + T_{i-1}) / 2; the coefficients of mode k become
+// D[i][j] = sum_m L[m][i] C[m][j] (FP64, rounded once to FP32).  The row sums of L are
+// phi_m(1) = sqrt(2m+1) with all entries >= 0, so sum_i |D[i][j]| <= sum_m sqrt(2m+1) |C[m][j]|.
+// Each mode is then scaled by 2^xc[k] (exact), its largest |D| to [2^14, 2^15), for the FP16
+// operands of the factor kernel.
+static void pack_chebyshev(const fst_model* m, std::vector<float>& cheb, int32_t* xc) {
+  double a[kMaxBasis][kMaxBasis] = {};
+  a[0][0] = 1.0;
+  a[1][1] = 1.0;
+  for (int n = 1; n + 1 < kMaxBasis; ++n) {
+    double tp[kMaxBasis + 1] = {};   // t P_n
+    tp[1] += a[n][0];
+    for (int i = 1; i <= n; ++i) {
+      tp[i + 1] += 0.5 * a[n][i];
+      tp[i - 1] += 0.5 * a[n][i];
+    }
+    for (int i = 0; i <= n + 1; ++i) a[n + 1][i] = ((2.0 * n + 1.0) * tp[i] - n * a[n - 1][i]) / (n + 1.0);
+  }
+  cheb.assign((size_t)kMaxModes * kMaxBasis * kMaxRank, 0.0f);
+  for (int k = 0; k < m->d; ++k) {
+    const int n = m->degree[k] + 1, r = m->rank[k];
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < r; ++j) {
+        double sum = 0.0;
+        for (int mm = i; mm < n; mm += 2) sum += std::sqrt(2.0 * mm + 1.0) * a[mm][i] * m->coef[k][(size_t)mm * r + j];
+        cheb[(size_t)(k * kMaxBasis + i) * kMaxRank + j] = (float)sum;
+      }
+    float mx = 0.0f;
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < r; ++j) mx = std::max(mx, std::fabs(cheb[(size_t)(k * kMaxBasis + i) * kMaxRank + j]));
+    int e = 0;
+    std::frexp(mx, &e);
+    xc[k] = std::max(-20, std::min(26, 15 - e));
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < r; ++j) {
+        float& c = cheb[(size_t)(k * kMaxBasis + i) * kMaxRank + j];
+        c = std::ldexp(c, xc[k]);
+      }
+  }
+}
+
 template <class T>
 static void upload(void*& dst, const std::vector<T>& v) {
   if (v.empty()) return;
@@ -134,6 +178,11 @@ const DeviceModel& device_model(const fst_model* m, int dtype) {
     upload(dm.core, a);
     upload(dm.detail, dt);
     upload(dm.wave, wv);
+    if (!m->has_wavelets()) {
+      std::vector<float> ch;
+      pack_chebyshev(m, ch, dm.cheb_xc);
+      upload(dm.cheb, ch);
+    }
   }
   stream_sync(nullptr);
   return m->dev.emplace(key, dm).first->second;
