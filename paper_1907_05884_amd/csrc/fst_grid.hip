@@ -34,11 +34,14 @@ __global__ void k_grid_axes(const T* gx, int64_t n1, const T* gy, int64_t n2, co
 }
 
 // O[b][i][c] = sum_{k < K} A[i][k] B[b][k][c] for i < n, c < C, b < gridDim.z, with
-// arbitrary strides for A, c contiguous in B and O.  One thread per column c holds the K
-// values B[b][k][c] in registers; the workgroup stages MP_ROWS rows of A in LDS (zero beyond
-// K) and writes MP_ROWS output rows, each a coalesced run of 256 columns.  The sum over k
-// runs in a fixed order.  B rows k >= K are read clamped to row K - 1 (finite values that
-// meet a zero in A), so every load is unconditional.
+// arbitrary strides for A, c contiguous in B and O.  One thread per column c (VEC: per four
+// columns) holds the K values B[b][k][c] in registers; the workgroup stages MP_ROWS rows of A
+// in LDS (zero beyond K) and writes MP_ROWS output rows, each a coalesced run of 256 (VEC:
+// 1024) columns.  The sum over k runs in a fixed order.  B rows k >= K are read clamped to row
+// K - 1 (finite values that meet a zero in A), so every load is unconditional.  VEC (FP32,
+// 16-byte aligned rows) writes 16 bytes per lane with non-temporal stores: the last product
+// streams the whole grid to HBM, and per-lane 4-byte stores leave the store path, not HBM,
+// as the limit.
 constexpr int MP_ROWS = 32, MP_THREADS = 256;
 template <typename T>
 struct ModeArgs {
@@ -52,7 +55,8 @@ struct ModeArgs {
   int32_t K;
 };
 
-template <typename T, int KP>
+typedef float mp_float4 __attribute__((ext_vector_type(4)));
+template <typename T, int KP, bool VEC>
 __global__ __launch_bounds__(MP_THREADS) void k_mode_product(ModeArgs<T> a) {
   __shared__ T sA[MP_ROWS][KP];
   const int64_t b = blockIdx.z, i0 = (int64_t)blockIdx.y * MP_ROWS;
@@ -62,19 +66,52 @@ __global__ __launch_bounds__(MP_THREADS) void k_mode_product(ModeArgs<T> a) {
     sA[r][k] = (r < nr && k < a.K) ? a.A[(i0 + r) * a.sa_i + k * a.sa_k] : T(0);
   }
   __syncthreads();
-  const int64_t c = (int64_t)blockIdx.x * MP_THREADS + threadIdx.x;
-  if (c >= a.C) return;
-  const T* Bp = a.B + b * a.sb_b + c;
-  T bv[KP];
+  if constexpr (VEC) {
+    const int64_t c = 4 * ((int64_t)blockIdx.x * MP_THREADS + threadIdx.x);   // C % 4 == 0
+    if (c >= a.C) return;
+    const float* Bp = a.B + b * a.sb_b + c;
+    mp_float4 bv[KP];
 #pragma unroll
-  for (int k = 0; k < KP; ++k) bv[k] = Bp[(int64_t)(k < a.K ? k : a.K - 1) * a.sb_k];
-  T* Op = a.O + b * a.so_b + i0 * a.so_i + c;
-  for (int r = 0; r < nr; ++r) {
-    T acc = T(0);
+    for (int k = 0; k < KP; ++k) bv[k] = *reinterpret_cast<const mp_float4*>(Bp + (int64_t)(k < a.K ? k : a.K - 1) * a.sb_k);
+    float* Op = a.O + b * a.so_b + i0 * a.so_i + c;
+    for (int r = 0; r < nr; ++r) {
+      mp_float4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-    for (int k = 0; k < KP; ++k) acc += sA[r][k] * bv[k];
-    Op[r * a.so_i] = acc;
+      for (int k = 0; k < KP; ++k) acc += sA[r][k] * bv[k];
+      __builtin_nontemporal_store(acc, reinterpret_cast<mp_float4*>(Op + r * a.so_i));
+    }
+  } else {
+    const int64_t c = (int64_t)blockIdx.x * MP_THREADS + threadIdx.x;
+    if (c >= a.C) return;
+    const T* Bp = a.B + b * a.sb_b + c;
+    T bv[KP];
+#pragma unroll
+    for (int k = 0; k < KP; ++k) bv[k] = Bp[(int64_t)(k < a.K ? k : a.K - 1) * a.sb_k];
+    T* Op = a.O + b * a.so_b + i0 * a.so_i + c;
+    for (int r = 0; r < nr; ++r) {
+      T acc = T(0);
+#pragma unroll
+      for (int k = 0; k < KP; ++k) acc += sA[r][k] * bv[k];
+      Op[r * a.so_i] = acc;
+    }
   }
+}
+
+template <typename T, int KP>
+static void mp_launch(const ModeArgs<T>& a, int64_t batch, void* stream) {
+  const int64_t gy = (a.n + MP_ROWS - 1) / MP_ROWS;
+  const auto aligned = [](const void* p) { return ((uintptr_t)p & 15) == 0; };
+  const bool vec = sizeof(T) == 4 && a.C % 4 == 0 && a.sb_b % 4 == 0 && a.sb_k % 4 == 0 && a.so_b % 4 == 0 &&
+                   a.so_i % 4 == 0 && aligned(a.B) && aligned(a.O);
+  const int64_t per_block = vec ? 4 * MP_THREADS : MP_THREADS;
+  const dim3 g((unsigned)((a.C + per_block - 1) / per_block), (unsigned)gy, (unsigned)batch);
+  if constexpr (sizeof(T) == 4) {
+    if (vec) {
+      hipLaunchKernelGGL((k_mode_product<T, KP, true>), g, dim3(MP_THREADS), 0, S(stream), a);
+      return;
+    }
+  }
+  hipLaunchKernelGGL((k_mode_product<T, KP, false>), g, dim3(MP_THREADS), 0, S(stream), a);
 }
 
 template <typename T>
@@ -84,13 +121,12 @@ static void mode_product(const ModeArgs<T>& a, int64_t batch, void* stream) {
   const int64_t gy = (a.n + MP_ROWS - 1) / MP_ROWS;
   if (gy > 65535 || batch > 65535 || (a.C + MP_THREADS - 1) / MP_THREADS > 0x7fffffff)
     fail(FST_E_UNSUPPORTED, "mode product: grid too large");
-  const dim3 g((unsigned)((a.C + MP_THREADS - 1) / MP_THREADS), (unsigned)gy, (unsigned)batch);
   const int kp = (a.K + 7) / 8 * 8;
   switch (kp) {
-    case 8: hipLaunchKernelGGL((k_mode_product<T, 8>), g, dim3(MP_THREADS), 0, S(stream), a); break;
-    case 16: hipLaunchKernelGGL((k_mode_product<T, 16>), g, dim3(MP_THREADS), 0, S(stream), a); break;
-    case 24: hipLaunchKernelGGL((k_mode_product<T, 24>), g, dim3(MP_THREADS), 0, S(stream), a); break;
-    default: hipLaunchKernelGGL((k_mode_product<T, 32>), g, dim3(MP_THREADS), 0, S(stream), a); break;
+    case 8: mp_launch<T, 8>(a, batch, stream); break;
+    case 16: mp_launch<T, 16>(a, batch, stream); break;
+    case 24: mp_launch<T, 24>(a, batch, stream); break;
+    default: mp_launch<T, 32>(a, batch, stream); break;
   }
   check_launch("k_mode_product");
 }
