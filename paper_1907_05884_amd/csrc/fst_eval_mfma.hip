@@ -28,11 +28,12 @@
 //   phase 2: T of the tile, 16 columns (j1 j2) per block on MFMA, then f += u1 u2 T from the
 //     accumulators, with the LDS reads of the next blocks issued half a block pair ahead.
 //
-// LDS: coefficients as two FP16 planes [2][3][RP][40]; four scale exponents; alpha as two FP16
-// planes [2][r1 r2 padded to 16][40] (80-byte rows: the 16-byte reads of 16 consecutive rows
-// fall in distinct banks); the column table [r1 r2 padded] of (j1, j2) table offsets; four
-// floats for the workgroup's maximum; per wave the point exponents [2][64] and a region that
-// holds the u3 tile [64][36] and then the tables u1 [r1][68], u2 [r2][68].
+// LDS: coefficients as two FP16 planes [2][3][RP][40]; 16 bytes for the core's scale
+// exponent; alpha as two FP16 planes [2][r1 r2 padded to 16][40] (80-byte rows: the 16-byte
+// reads of 16 consecutive rows fall in distinct banks); the column table [r1 r2 padded] of
+// (j1, j2) table offsets; four floats for the workgroup's maximum; per wave the point
+// exponents [2][64] and a region that holds the u3 tile [64][36] and then the tables
+// u1 [r1][68], u2 [r2][68].
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -99,7 +100,7 @@ __global__ __launch_bounds__(EM_THREADS) __attribute__((amdgpu_waves_per_eu(1, 1
   const int r1 = a.r1, r2 = a.r2, r3 = a.r3, R12 = r1 * r2, nbs = a.r12p / 16;
   char* base = reinterpret_cast<char*>(em_smem);
   _Float16* sCB = reinterpret_cast<_Float16*>(base);                       // [2][3][RP][EM_CPAD]
-  int* sXc = reinterpret_cast<int*>(base + 480 * RP);                       // [4]
+  int* sXa = reinterpret_cast<int*>(base + 480 * RP);                       // [4], [0]: the core's scale
   _Float16* sA16 = reinterpret_cast<_Float16*>(base + 480 * RP + 16);       // [2][r12p][EM_APAD]
   const int plane = a.r12p * EM_APAD;
   int2* sCol = reinterpret_cast<int2*>(sA16 + 2 * plane);                   // [r12p]
@@ -123,11 +124,11 @@ __global__ __launch_bounds__(EM_THREADS) __attribute__((amdgpu_waves_per_eu(1, 1
     if (threadIdx.x == 0) {
       float v = 0.0f;
       for (int w = 0; w < EM_WAVES; ++w) v = fmaxf(v, sRed[w]);
-      sXc[3] = std::min(EM_XMAX, std::max(-EM_XMAX, 15 - __builtin_amdgcn_frexp_expf(v)));
+      sXa[0] = std::min(EM_XMAX, std::max(-EM_XMAX, 15 - __builtin_amdgcn_frexp_expf(v)));
     }
     __syncthreads();
   }
-  const int xa = sXc[3];
+  const int xa = sXa[0];
   int xc[3];
 #pragma unroll
   for (int k = 0; k < 3; ++k) xc[k] = a.xc[k];
