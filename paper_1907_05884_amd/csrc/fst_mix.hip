@@ -526,8 +526,12 @@ static void mixed_normal_equations_t(const fst_model* m, const DeviceModel& dm, 
   const int64_t R = m->R(), N = L.N;
 
   // Algorithm 2 step 4 over the N mixed rows: S rows uniformly without replacement (stream
-  // 2), listed per second-pass workgroup as (LDS element, sample position)
+  // 2), listed per second-pass workgroup as (LDS element, sample position).  The normal
+  // equations do not depend on the order of the rows, so when they are formed here the rows
+  // of a workgroup take consecutive positions (its writes are coalesced); the rows handed to
+  // the caller keep the order of the draw.
   {
+    const bool grouped = G || h;
     std::vector<int64_t> idx((size_t)nsamp);
     sample_indices(seed, FST_STREAM_LS, N, nsamp, idx.data());
     const int nblk = MX_B1 / L.L;
@@ -540,7 +544,7 @@ static void mixed_normal_equations_t(const fst_model* m, const DeviceModel& dm, 
       const int64_t e = (i / MX_B1) * L.L + (i % MX_B1 - (int64_t)bk * L.L);
       const int32_t t = off[(size_t)bk] + fill[(size_t)bk]++;
       list[(size_t)(2 * t)] = (int32_t)e;
-      list[(size_t)(2 * t + 1)] = (int32_t)q;
+      list[(size_t)(2 * t + 1)] = grouped ? t : (int32_t)q;
     }
     copy_h2d(sel, list.data(), sizeof(int32_t) * list.size(), stream);
     copy_h2d(sel_off, off.data(), sizeof(int32_t) * off.size(), stream);
