@@ -23,6 +23,7 @@
 #include <algorithm>
 #include <cmath>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "fst_device.h"
@@ -148,16 +149,37 @@ __global__ __launch_bounds__(MX_THREADS) void k_mix_hi(MixArgs<T> a) {
   // L and 2^H are powers of two: every index below is shifts and masks
   for (int e = threadIdx.x; e < E; e += MX_THREADS) s[e] = col[(int64_t)(e >> lgL) * MX_B1 + l0 + (e & (L - 1))];
   __syncthreads();
-  for (int lh = 0; lh < a.H; ++lh) {
-    const int h = 1 << lh;
-    for (int p = threadIdx.x; p < E / 2; p += MX_THREADS) {
+  // the H cross-block stages (they commute) up to three at a time: a thread takes the 2^NB
+  // elements of a group (blocks k = base + m 2^lh, m < 2^NB, one offset l), applies NB stages
+  // in registers and writes them back, so each pass reads and writes the column once
+  auto pass = [&](int lh, auto nbits) {
+    constexpr int NB = decltype(nbits)::value, G = 1 << NB;
+    const int lo = (1 << lh) - 1;
+    for (int p = threadIdx.x; p < (E >> NB); p += MX_THREADS) {
       const int pk = p >> lgL, l = p & (L - 1);
-      const int k0 = ((pk >> lh) << (lh + 1)) | (pk & (h - 1)), k1 = k0 + h;
-      const T x = s[k0 * L + l], y = s[k1 * L + l];
-      s[k0 * L + l] = x + y;
-      s[k1 * L + l] = x - y;
+      const int base = ((pk >> lh) << (lh + NB)) | (pk & lo);
+      T w[G];
+#pragma unroll
+      for (int m = 0; m < G; ++m) w[m] = s[(base + (m << lh)) * L + l];
+#pragma unroll
+      for (int sb = 0; sb < NB; ++sb)
+#pragma unroll
+        for (int m = 0; m < G; ++m)
+          if (!(m & (1 << sb))) {
+            const T x = w[m], y = w[m | (1 << sb)];
+            w[m] = x + y;
+            w[m | (1 << sb)] = x - y;
+          }
+#pragma unroll
+      for (int m = 0; m < G; ++m) s[(base + (m << lh)) * L + l] = w[m];
     }
     __syncthreads();
+  };
+  for (int lh = 0; lh < a.H; lh += 3) {
+    const int nb = a.H - lh < 3 ? a.H - lh : 3;
+    if (nb == 3) pass(lh, std::integral_constant<int, 3>{});
+    else if (nb == 2) pass(lh, std::integral_constant<int, 2>{});
+    else pass(lh, std::integral_constant<int, 1>{});
   }
   const int beg = a.sel_off[blockIdx.x], end = a.sel_off[blockIdx.x + 1];
   for (int q = beg + threadIdx.x; q < end; q += MX_THREADS) {
