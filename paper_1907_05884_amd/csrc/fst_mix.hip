@@ -7,10 +7,11 @@
 //   k_mix_lo     the r3 design columns of one (j1, j2) pair (Khatri-Rao products of three
 //                factor rows, times the sign of each row) in blocks of 4096 rows: the signed
 //                product u1 u2 is formed once per row and each column multiplies it by its u3;
-//                the 12 butterfly stages inside a block, 4 in registers and 8 through LDS
-//   k_mix_hi     the remaining stages across blocks (strides 4096 .. N/2) through LDS, the
-//                1/sqrt(N) scale, and a scatter of the sampled rows into A^T from a list of
-//                the samples that fall into the workgroup's rows
+//                the 12 butterfly stages inside a block, 4 in registers and 8 through LDS (in
+//                passes of up to three stages, each a register butterfly of 8 elements)
+//   k_mix_hi     the remaining stages across blocks (strides 4096 .. N/2) through LDS (up to
+//                three per pass, as above), the 1/sqrt(N) scale, and a scatter of the sampled
+//                rows into A^T from a list of the samples that fall into the workgroup's rows
 //   k_gram_dense G = A^T A (lower triangle) from the materialised sampled rows, MFMA
 //   k_atv_dense  h = A^T b
 //
@@ -115,19 +116,35 @@ __global__ __launch_bounds__(MX_THREADS) void k_mix_lo(MixArgs<T> a) {
 #pragma unroll
     for (int k = 0; k < 16; ++k) s[t + 256 * k] = w[k];
     __syncthreads();
-    // strides 1 .. 128 (bits 0 .. 7): 2048 disjoint pairs per stage, 8 per thread
+    // strides 1 .. 128 (bits 0 .. 7), in passes of three, three and two stages: a thread takes
+    // the 2^NB elements base + m 2^lh of a group, applies NB stages in registers and writes
+    // them back
+    auto pass = [&](auto lhc, auto nbits) {
+      constexpr int LH = decltype(lhc)::value, NB = decltype(nbits)::value, G = 1 << NB;
 #pragma unroll
-    for (int lh = 0; lh < 8; ++lh) {
+      for (int q = 0; q < (MX_B1 >> NB) / MX_THREADS; ++q) {
+        const int p = t + MX_THREADS * q;
+        const int base = ((p >> LH) << (LH + NB)) | (p & ((1 << LH) - 1));
+        T v[G];
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const int p = t + 256 * q;
-        const int i0 = ((p >> lh) << (lh + 1)) | (p & ((1 << lh) - 1)), i1 = i0 + (1 << lh);
-        const T x = s[i0], y = s[i1];
-        s[i0] = x + y;
-        s[i1] = x - y;
+        for (int m = 0; m < G; ++m) v[m] = s[base + (m << LH)];
+#pragma unroll
+        for (int sb = 0; sb < NB; ++sb)
+#pragma unroll
+          for (int m = 0; m < G; ++m)
+            if (!(m & (1 << sb))) {
+              const T x = v[m], y = v[m | (1 << sb)];
+              v[m] = x + y;
+              v[m | (1 << sb)] = x - y;
+            }
+#pragma unroll
+        for (int m = 0; m < G; ++m) s[base + (m << LH)] = v[m];
       }
       __syncthreads();
-    }
+    };
+    pass(std::integral_constant<int, 0>{}, std::integral_constant<int, 3>{});
+    pass(std::integral_constant<int, 3>{}, std::integral_constant<int, 3>{});
+    pass(std::integral_constant<int, 6>{}, std::integral_constant<int, 2>{});
     T* out = a.buf + ((int64_t)blockIdx.y * ncol + jj) * a.N + base;
 #pragma unroll
     for (int k = 0; k < 16; ++k) out[t + 256 * k] = s[t + 256 * k];
