@@ -51,7 +51,9 @@ def _axes(seed, shape, dtype):
 
 
 # shapes: ragged counts (not multiples of the 256-column or 32-row blocks), 2-D slices along
-# each axis, a single point; ranks: not multiples of 8 (padded contraction), and the maximum
+# each axis, a single point; ranks: not multiples of 8 (padded contraction), and the maximum.
+# FP32 column counts that are multiples of 4 take the four-column (16-byte store) path of the
+# mode products: (45, 12, 68) has 68 and 816 columns, ragged against its 1024-column blocks
 @pytest.mark.parametrize("dtype,rank,degree,shape,tol", [
     (np.float64, (7, 12, 5), (9, 14, 6), (37, 1, 53), 1e-10),
     (np.float64, (32, 32, 32), (31, 31, 31), (64, 65, 33), 1e-10),
@@ -59,6 +61,7 @@ def _axes(seed, shape, dtype):
     (np.float64, (16, 1, 9), (20, 3, 11), (300, 2, 1), 1e-10),
     (np.float32, (24, 24, 24), (31, 31, 31), (130, 70, 257), 1e-5),
     (np.float32, (9, 17, 31), (12, 20, 31), (1, 300, 299), 1e-5),
+    (np.float32, (5, 11, 24), (8, 15, 29), (45, 12, 68), 1e-5),
 ])
 def test_grid_matches_oracle(dev, dtype, rank, degree, shape, tol):
     print(f"grid {shape} rank {rank} {np.dtype(dtype).name}", flush=True)
