@@ -52,10 +52,12 @@ def _data(seed, n, om, dtype):
     return pts, vals
 
 
-# n = 3000: N = 4096 (one block, second pass only scatters); n = 70000: N = 131072, five
-# cross-block stages; ranks not multiples of 8
+# n = 3000: N = 4096 (one block, second pass only scatters); n = 40000: N = 65536, four
+# cross-block stages (register passes of three and one); n = 70000: N = 131072, five (three and
+# two); ranks not multiples of 8
 @pytest.mark.parametrize("n,rank,degree,S", [
     (3000, (4, 5, 3), (7, 7, 7), 1500),
+    (40000, (5, 4, 6), (8, 7, 9), 2500),
     (70000, (6, 5, 4), (9, 8, 7), 3000),
 ])
 def test_mixed_refit_fp64_matches_oracle(dev, n, rank, degree, S):
